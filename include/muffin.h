@@ -1,0 +1,149 @@
+/*
+ * muffin.h - C ABI of the MI355X (gfx950) MUFFIN primal-dual reconstruction library.
+ *
+ * MUFFIN recovers a sky cube X = [x_1 ... x_L] (L channels of N x N pixels) from dirty images
+ * y_l = H_l x_l + n_l, where H_l is convolution by the PSF of channel l (Sec. 2, eq. (model)),
+ * by minimising (eq. (reg) with the prior of eq. (RegAll))
+ *
+ *   sum_l w_l/2 ||y_l - H_l x_l||^2 + 1_{R+}(X) + mu_s sum_l ||W_s x_l||_1 + mu_lambda sum_n ||W_lambda x^n||_1
+ *
+ * with W_s the isotropic undecimated wavelet transform (IUWT, B3-spline a trous, periodic) and
+ * W_lambda the orthonormal cosine transform (DCT-II) of each pixel spectrum, through the
+ * primal-dual iteration of Algorithm 1 (Sec. 3).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns MUFFIN_OK (0) or a negative MUFFIN_E* code; none aborts or throws.
+ *    muffin_last_error() gives a message for the last failure on the calling thread.
+ *  - Arrays are FP32, C-contiguous, channel-major:
+ *      cube    [L][N][N]           (X, dirty image, PSF, V, gradients)
+ *      U       [L][J+1][N][N]      (planes w_1..w_J, then the coarse plane c_J, of each channel)
+ *    V holds the cosine coefficients of each pixel spectrum, coefficient index first.
+ *  - "on_device" arguments: nonzero means the pointer is device memory on the context's device,
+ *    zero means host memory.  The library never takes ownership of caller memory: it copies
+ *    what it needs into its own buffers.
+ *  - A context is bound to one HIP stream given at creation (NULL = the null stream).  Work is
+ *    enqueued on a private stream of the library that is ordered after all prior work of the
+ *    caller's stream; the caller's stream is made to wait for the library's work before each call
+ *    returns, so device outputs are safe to use on the caller's stream.  Calls returning host
+ *    values (objective, get_* to host) synchronise.  A context is not thread-safe; distinct
+ *    contexts are independent.
+ */
+#ifndef MUFFIN_H
+#define MUFFIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MUFFIN_OK 0
+#define MUFFIN_EINVAL (-1)     /* bad argument: size, pointer, parameter out of range */
+#define MUFFIN_ENOMEM (-2)     /* device or host allocation failed */
+#define MUFFIN_EHIP (-3)       /* a HIP runtime call failed */
+#define MUFFIN_ENONFINITE (-4) /* NaN or Inf in an input, or the objective became non-finite */
+#define MUFFIN_ESTEP (-5)      /* (tau, sigma, rho) violate the convergence condition */
+#define MUFFIN_ESTATE (-6)     /* checkpoint blob does not match the context */
+
+typedef struct muffin_ctx muffin_ctx;
+
+/* Problem and algorithm parameters (Sec. 2 eqs. (reg), (RegAll); Sec. 3, Algorithm 1). */
+typedef struct {
+  int32_t N;                /* image side; N = 2^a or 3 * 2^a with 8 <= N <= 1024 */
+  int32_t L;                /* channels, 1 <= L <= 512 */
+  int32_t J;                /* IUWT detail scales, 1 <= J <= 6; W_s yields J+1 planes */
+  int32_t iuwt_gen;         /* 1 or 2: first or second generation IUWT (the paper uses 2, Sec. 4) */
+  int32_t penalize_coarse;  /* 1: the coarse plane is part of W_s's l1 term; 0: it is not */
+  int32_t reserved;
+  double mu_s;              /* spatial weight mu_s >= 0 (eq. (RegAll)) */
+  double mu_lambda;         /* spectral weight mu_lambda >= 0 (eq. (RegAll)) */
+  double tau;               /* primal step; <= 0 selects 0.99 / (beta/2 + sigma ||K||^2) */
+  double sigma;             /* dual step > 0 */
+  double rho;               /* relaxation, 0 < rho < delta (see muffin_info) */
+  const float* chan_weight; /* host [L] weights w_l = 1/sigma_l^2 (eq. (reg)), or NULL for all 1 */
+} muffin_params;
+
+/* Create a context: copy the dirty cube y [L][N][N] and the PSF cube [L][N][N] (origin of each PSF
+ * at pixel (N/2, N/2)), precompute the transfer functions H_l, b_l = w_l H_l^dagger y_l, the
+ * Lipschitz constant beta = max_l w_l ||H_l||^2 and ||K||^2 = mu_s^2 ||W_s||^2 + mu_lambda^2 (FP64),
+ * choose tau if needed, and initialise X = U = V = 0 (Algorithm 1, "Initialize").
+ * Errors: EINVAL (sizes, NULL pointers, parameters), ENONFINITE (NaN/Inf in dirty or psf),
+ * ESTEP (convergence condition violated), ENOMEM, EHIP.  *out is NULL on error. */
+int muffin_init(muffin_ctx** out, const muffin_params* p, const float* dirty, const float* psf,
+                int inputs_on_device, void* hip_stream);
+
+/* Run n_iter >= 0 iterations of Algorithm 1 (gradient, primal proximal step, spatial and spectral
+ * dual steps, relaxation).  Iterations after the first call replay a captured HIP graph. */
+int muffin_step(muffin_ctx* ctx, int32_t n_iter);
+
+/* Iterate until a stopping rule holds (Algorithm 1, "until stopping criterion"): every
+ * check_every iterations the objective f is evaluated; with f_ref finite the run stops at the
+ * first check where (f - f_ref)/|f_ref| <= tol, otherwise when the relative change of f between
+ * two checks is <= tol.  Stops after max_iter iterations at most.  iters_done / f_final may be
+ * NULL.  Returns ENONFINITE if f becomes non-finite. */
+int muffin_solve(muffin_ctx* ctx, int32_t max_iter, int32_t check_every, double tol, double f_ref,
+                 int32_t* iters_done, double* f_final);
+
+/* Objective of eq. (reg) + eq. (RegAll) at the current X, reduced in FP64:
+ * out[0] total, out[1] data term sum_l w_l/2 ||y_l - H_l x_l||^2, out[2] mu_s-weighted spatial l1,
+ * out[3] mu_lambda-weighted spectral l1.  Synchronises. */
+int muffin_objective(muffin_ctx* ctx, double out[4]);
+
+/* Scalars of the context: out[0] tau, [1] sigma, [2] rho, [3] beta, [4] ||K||^2, [5] ||W_s||^2,
+ * [6] delta (rho must lie in (0, delta)), [7] iterations done. */
+int muffin_info(muffin_ctx* ctx, double out[8]);
+
+/* Replace X by max(x0, 0) (a warm start) and reset U = V = 0.  x0 is [L][N][N]. */
+int muffin_set_x(muffin_ctx* ctx, const float* x0, int on_device);
+/* Copy X, U or V out of the context (sizes [L][N][N], [L][J+1][N][N], [L][N][N]). */
+int muffin_get_x(muffin_ctx* ctx, float* x, int on_device);
+int muffin_get_u(muffin_ctx* ctx, float* u, int on_device);
+int muffin_get_v(muffin_ctx* ctx, float* v, int on_device);
+
+/* Checkpoint: a host blob holding a header (sizes, parameters, iteration count) and X, U, V.
+ * muffin_state_size gives its size in bytes.  muffin_set_state rejects a blob written by a
+ * context of other sizes or parameters with ESTATE.  Restoring and continuing reproduces an
+ * uninterrupted run bit for bit. */
+int muffin_state_size(muffin_ctx* ctx, size_t* bytes);
+int muffin_get_state(muffin_ctx* ctx, void* blob, size_t bytes);
+int muffin_set_state(muffin_ctx* ctx, const void* blob, size_t bytes);
+
+/* Single operators on device arrays, for per-operator parity checks.  in/out are device
+ * pointers on the context's device with the sizes given per operator:
+ *   MUFFIN_OP_H        cube -> cube       H_l x_l (Sec. 2, eq. (model))
+ *   MUFFIN_OP_HT       cube -> cube       H_l^dagger y_l
+ *   MUFFIN_OP_GRAD     cube -> cube       w_l H_l^dagger (H_l x_l - y_l) (Algorithm 1, eq. (grad))
+ *   MUFFIN_OP_IUWT     cube -> U          W_s x_l per channel
+ *   MUFFIN_OP_IUWT_ADJ U -> cube          W_s^dagger u_l per channel (eq. (adjointspat) without mu_s)
+ *   MUFFIN_OP_DCT      cube -> cube       X W_lambda (cosine coefficients of each pixel spectrum)
+ *   MUFFIN_OP_IDCT     cube -> cube       V W_lambda^dagger
+ * The context's state is not changed.  EINVAL for an unknown op. */
+#define MUFFIN_OP_H 1
+#define MUFFIN_OP_HT 2
+#define MUFFIN_OP_GRAD 3
+#define MUFFIN_OP_IUWT 4
+#define MUFFIN_OP_IUWT_ADJ 5
+#define MUFFIN_OP_DCT 6
+#define MUFFIN_OP_IDCT 7
+int muffin_apply_op(muffin_ctx* ctx, int op, const float* in, float* out);
+
+/* Time n_iter iterations with HIP events on the library's stream, without graph replay, and
+ * report the average device milliseconds per iteration of each kernel family:
+ *   ms[0] whole iteration, [1] spatial adjoint (IUWT^dagger), [2] gradient FFT passes,
+ *   [3] fused spectral kernel, [4] spatial analysis and dual update, [5..7] reserved (0).
+ * The iterations advance the state like muffin_step. */
+int muffin_profile(muffin_ctx* ctx, int32_t n_iter, double ms[8]);
+
+/* Time n_iter iterations (graph replay) with HIP events on the library's stream: *ms is the
+ * total device time.  Advances the state like muffin_step. */
+int muffin_step_timed(muffin_ctx* ctx, int32_t n_iter, double* ms);
+
+void muffin_free(muffin_ctx* ctx);
+const char* muffin_strerror(int code);
+const char* muffin_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MUFFIN_H */

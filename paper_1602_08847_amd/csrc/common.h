@@ -1,0 +1,137 @@
+// Internal declarations shared by the HIP translation units of libmuffin.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "muffin.h"
+
+namespace mf {
+
+void set_error(const std::string& msg);
+
+#define MF_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::mf::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+      return MUFFIN_EHIP;                                                         \
+    }                                                                             \
+  } while (0)
+
+#define MF_TRY(expr)             \
+  do {                           \
+    int rc_ = (expr);            \
+    if (rc_ != MUFFIN_OK) return rc_; \
+  } while (0)
+
+// ------------------------------------------------------------------ complex helpers
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// ------------------------------------------------------------------ FFT geometry
+// Column blocking of the half spectrum: CB columns of N/2+1 per block, pitch = ncb * CB.
+struct FftGeom {
+  int N = 0;
+  int CB = 8;       // columns per block in the column pass
+  int ncb = 0;      // column blocks
+  int pitch = 0;    // complex entries per spectrum row (>= N/2 + 1)
+};
+bool fft_supported(int N);
+FftGeom fft_geom(int N);
+// Twiddle table exp(-2 pi i m / N), m = 0..N-1, built in FP64 on the host.
+std::vector<float2> fft_twiddles(int N);
+
+// Row pass, real -> half spectrum.  x: [nch][N][N] (channel stride N*N), S: [nch][N][pitch].
+// With shift, the input is read with an (N/2, N/2) circular shift (ifftshift of a centred PSF).
+int launch_rows_r2c(const float* x, float2* S, int nch, const FftGeom& g, const float2* tw,
+                    bool shift, hipStream_t st);
+
+enum ColMode { COL_FWD = 0, COL_REAL = 1, COL_CPLX = 2, COL_CPLX_CONJ = 3 };
+// Column pass over the half spectrum: forward FFT along rows, then (mode != COL_FWD) multiply by
+// M (real [nch][pitch][N] or complex [nch][pitch][N], transposed) times scale, then inverse FFT.
+// For COL_FWD the forward result is written transposed to outT ([nch][pitch][N]) instead of S.
+int launch_cols(float2* S, int nch, const FftGeom& g, const float2* tw, int mode, const float* Mr,
+                const float2* Mc, float scale, float2* outT, hipStream_t st);
+
+enum RowEpi { EPI_STORE = 0, EPI_GRAD = 1, EPI_RESID = 2 };
+// Row pass, half spectrum -> real, with an epilogue per pixel (g = inverse transform):
+//   EPI_STORE: out = g
+//   EPI_GRAD : out = g - b + s_scale * s      (s may be NULL)
+//   EPI_RESID: partial[block] = sum over the block of 0.5 * w_l * (g - y)^2   (FP64)
+int launch_rows_c2r(const float2* S, int nch, const FftGeom& g, const float2* tw, int epi,
+                    float* out, const float* b, const float* s, float s_scale, const float* y,
+                    const float* chan_w, double* partial, int* nblocks_out, hipStream_t st);
+
+// ------------------------------------------------------------------ IUWT (a trous)
+// Pointer + channel stride (in floats) of one plane per channel.
+struct PlaneRef {
+  const float* p = nullptr;
+  long long cs = 0;
+};
+struct PlaneOut {
+  float* p = nullptr;
+  long long cs = 0;
+};
+enum AtrousMode {
+  AT_SMOOTH = 0,     // out = H_j(A)
+  AT_SUBADD = 1,     // out = E + H_j(A - B)
+  AT_DETAIL = 2,     // w = E - H_j(A);  out(u) = rho*sat(u + coef*w) + (1-rho)*u  (in place on out)
+  AT_DETAIL_ABS = 3  // partial[block] = sum |E - H_j(A)|
+};
+int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out,
+                  float coef, float rho, double* partial, int* nblocks_out, hipStream_t st);
+enum PointMode {
+  PT_DETAIL1 = 0,  // w = E - A; u update (first-generation detail, no smoothing)
+  PT_COARSE = 1,   // w = A; u update
+  PT_ABS_DIFF = 2, // partial = sum |E - A|
+  PT_ABS = 3,      // partial = sum |A|
+  PT_COPY = 4,     // out = coef * A
+  PT_SUB = 5       // out = E - A
+};
+int launch_pointwise(int mode, int N, int nch, PlaneRef A, PlaneRef E, PlaneOut out, float coef,
+                     float rho, double* partial, int* nblocks_out, hipStream_t st);
+
+// ------------------------------------------------------------------ spectral (per pixel)
+struct SpectralArgs {
+  float* X;
+  const float* Q;
+  float* V;
+  float* D;
+  const float* W;   // [L][L] W[l][k] = s_k cos(pi (2l+1) k / 2L)
+  const float* WT;  // [L][L] transpose
+  long long npix;   // N*N
+  int L;
+  float tau, mu_l, smu_l, rho;
+};
+int launch_spectral_step(const SpectralArgs& a, hipStream_t st);
+// out = X W_lambda (inverse = false) or X W_lambda^dagger (inverse = true), per pixel.
+int launch_dct(const float* in, float* out, const float* Wmat, long long npix, int L, hipStream_t st);
+// partial[block] = sum |X W_lambda| over the block's pixels.
+int launch_dct_abs(const float* in, const float* WT, long long npix, int L, double* partial,
+                   int* nblocks_out, hipStream_t st);
+
+// ------------------------------------------------------------------ reductions (FP64)
+// dst[slot] (+)= sum(partial[0..n)) in a fixed order.
+int launch_reduce_sum(const double* partial, int n, double* dst, int accumulate, hipStream_t st);
+// dst = max over a float array (times scale) in FP64.
+int launch_reduce_max(const float* x, long long n, double scale, double* partial, double* dst,
+                      hipStream_t st);
+// dst = max over the N x N frequency grid of sum_k omega_k |g_k|^2 (IUWT frame symbol).
+int launch_frame_bound(int N, int J, int gen, double omega_coarse, double* partial, double* dst,
+                       hipStream_t st);
+// Scan for non-finite values; dst[0] += count (as double).
+int launch_count_nonfinite(const float* x, long long n, double* partial, double* dst,
+                           hipStream_t st);
+constexpr int kMaxPartials = 1 << 20;
+
+}  // namespace mf

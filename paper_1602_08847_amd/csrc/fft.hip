@@ -1,0 +1,670 @@
+// Real 2-D FFT convolution passes for the data term (Algorithm 1, eq. (grad)).
+//
+// A channel's gradient H^dagger H x is C2R(P . R2C(x)) with P = w |H(k)|^2 / N^2, computed in
+// three passes over an [N][pitch] half spectrum:
+//   1. rows:    two real rows packed as one complex row, one N-point complex FFT, then split;
+//   2. columns: CB columns per workgroup, N-point forward FFT, pointwise multiply, inverse FFT;
+//   3. rows:    Hermitian completion of two rows, inverse FFT, real/imaginary parts are the rows,
+//               fused epilogue (gradient, plain store, or FP64 residual energy).
+// Every 1-D transform is a self-sorting (Stockham) decimation-in-time FFT held in LDS: at each
+// stage of radix R over a span Ns (product of the earlier radices), butterfly b reads the R
+// inputs b + r N/R, multiplies input r by w^(r k), k = b mod Ns, w = exp(-2 pi i / (Ns R)),
+// takes an R-point DFT in registers and writes output r to (b / Ns) Ns R + k + r Ns.
+#include "common.h"
+
+#include <cmath>
+
+namespace mf {
+
+// ------------------------------------------------------------------ radix plans
+template <int N>
+struct Plan;
+#define MF_PLAN(n, nst_, r0, r1, r2, rmax)                             \
+  template <>                                                          \
+  struct Plan<n> {                                                     \
+    static constexpr int nst = nst_;                                   \
+    static constexpr int rad[3] = {r0, r1, r2};                        \
+    static constexpr int T = n / rmax; /* threads per transform */     \
+  };
+MF_PLAN(8, 1, 8, 1, 1, 8)
+MF_PLAN(16, 1, 16, 1, 1, 16)
+MF_PLAN(32, 2, 8, 4, 1, 8)
+MF_PLAN(64, 2, 8, 8, 1, 8)
+MF_PLAN(128, 2, 16, 8, 1, 16)
+MF_PLAN(256, 2, 16, 16, 1, 16)
+MF_PLAN(512, 3, 8, 8, 8, 8)
+MF_PLAN(1024, 3, 16, 16, 4, 16)
+MF_PLAN(12, 2, 4, 3, 1, 4)
+MF_PLAN(24, 2, 8, 3, 1, 8)
+MF_PLAN(48, 2, 16, 3, 1, 16)
+MF_PLAN(96, 3, 8, 4, 3, 8)
+MF_PLAN(192, 3, 8, 8, 3, 8)
+MF_PLAN(384, 3, 16, 8, 3, 16)
+MF_PLAN(768, 3, 16, 16, 3, 16)
+#undef MF_PLAN
+
+template <int N>
+constexpr int span_before(int s) {
+  int p = 1;
+  for (int i = 0; i < s; ++i) p *= Plan<N>::rad[i];
+  return p;
+}
+
+// LDS addressing: one padding slot every 16 complex entries breaks power-of-two strides;
+// the per-transform stride is odd so that transforms side by side fall in different banks.
+__host__ __device__ constexpr int lpad(int i) { return i + (i >> 4); }
+template <int N>
+constexpr int lstride() {
+  int s = lpad(N - 1) + 1;
+  return (s & 1) ? s : s + 1;
+}
+
+// ------------------------------------------------------------------ butterflies
+// Multiply by -i (forward) or +i (inverse).
+template <bool INV>
+__device__ __forceinline__ float2 rot90(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+  float2 t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2* v) {
+  const float c = -0.5f;
+  const float s = 0.86602540378443864676f;  // sqrt(3)/2
+  float2 t = cadd(v[1], v[2]);
+  float2 d = csub(v[1], v[2]);
+  float2 m = make_float2(v[0].x + c * t.x, v[0].y + c * t.y);
+  // (-/+ i) s d
+  float2 r = rot90<INV>(d);
+  v[0] = cadd(v[0], t);
+  v[1] = make_float2(m.x + s * r.x, m.y + s * r.y);
+  v[2] = make_float2(m.x - s * r.x, m.y - s * r.y);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  float2 t2 = cadd(a1, a3), t3 = rot90<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* v) {
+  // even/odd split: E = DFT4(v0,v2,v4,v6), O = DFT4(v1,v3,v5,v7); y_k = E_k + w8^k O_k
+  dft4<INV>(v[0], v[2], v[4], v[6]);
+  dft4<INV>(v[1], v[3], v[5], v[7]);
+  const float h = 0.70710678118654752440f;
+  float2 o1 = v[3], o2 = v[5], o3 = v[7];
+  // w8 = (h, -h) forward, (h, h) inverse
+  o1 = INV ? make_float2(h * (o1.x - o1.y), h * (o1.x + o1.y)) : make_float2(h * (o1.x + o1.y), h * (o1.y - o1.x));
+  o2 = rot90<INV>(o2);
+  o3 = INV ? make_float2(-h * (o3.x + o3.y), h * (o3.x - o3.y)) : make_float2(h * (o3.y - o3.x), -h * (o3.x + o3.y));
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1];
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft16(float2* v) {
+  // n = 4 n1 + n2, k = k1 + 4 k2: inner 4-point DFTs over n1, twiddle w16^(n2 k1), outer over n2.
+  float2 b[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    float2 a0 = v[n2], a1 = v[4 + n2], a2 = v[8 + n2], a3 = v[12 + n2];
+    dft4<INV>(a0, a1, a2, a3);
+    b[n2][0] = a0;
+    b[n2][1] = a1;
+    b[n2][2] = a2;
+    b[n2][3] = a3;
+  }
+  const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
+  const float sg = INV ? 1.f : -1.f;
+  // w16^m for m = n2 * k1, m in {1,2,3,4,6,9}
+  const float2 w1 = make_float2(c1, sg * s1), w2 = make_float2(h, sg * h), w3 = make_float2(s1, sg * c1);
+  const float2 w6 = make_float2(-h, sg * h), w9 = make_float2(-c1, -sg * s1);
+  b[1][1] = cmul(b[1][1], w1);
+  b[1][2] = cmul(b[1][2], w2);
+  b[1][3] = cmul(b[1][3], w3);
+  b[2][1] = cmul(b[2][1], w2);
+  b[2][2] = rot90<INV>(b[2][2]);
+  b[2][3] = cmul(b[2][3], w6);
+  b[3][1] = cmul(b[3][1], w3);
+  b[3][2] = cmul(b[3][2], w6);
+  b[3][3] = cmul(b[3][3], w9);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 a0 = b[0][k1], a1 = b[1][k1], a2 = b[2][k1], a3 = b[3][k1];
+    dft4<INV>(a0, a1, a2, a3);
+    v[k1] = a0;
+    v[k1 + 4] = a1;
+    v[k1 + 8] = a2;
+    v[k1 + 12] = a3;
+  }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dftR(float2* v) {
+  if constexpr (R == 2) dft2<INV>(v[0], v[1]);
+  else if constexpr (R == 3) dft3<INV>(v);
+  else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 8) dft8<INV>(v);
+  else if constexpr (R == 16) dft16<INV>(v);
+}
+
+// ------------------------------------------------------------------ LDS Stockham transform
+// One N-point transform of buf (LDS, lpad addressing) by T cooperating threads, t in [0, T).
+// All threads of the workgroup must call it (it synchronises the workgroup).
+template <int N, bool INV, int S = 0>
+__device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const float2* __restrict__ tw) {
+  if constexpr (S < Plan<N>::nst) {
+    constexpr int T = Plan<N>::T;
+    constexpr int R = Plan<N>::rad[S];
+    constexpr int Ns = span_before<N>(S);
+    constexpr int NB = N / R;
+    constexpr int PER = (NB + T - 1) / T;
+    constexpr int TWS = N / (Ns * R);  // twiddle table stride
+    float2 v[PER][R];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = t + i * T;
+      if (active && (PER * T == NB || b < NB)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[i][r] = buf[lpad(b + r * NB)];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = t + i * T;
+      if (active && (PER * T == NB || b < NB)) {
+        const int k = b % Ns;
+        if constexpr (Ns > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            float2 w = tw[r * k * TWS];
+            if (INV) w.y = -w.y;
+            v[i][r] = cmul(v[i][r], w);
+          }
+        }
+        dftR<R, INV>(v[i]);
+        const int base = (b / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[lpad(base + r * Ns)] = v[i][r];
+      }
+    }
+    __syncthreads();
+    fft_lds<N, INV, S + 1>(buf, t, active, tw);
+  }
+}
+
+// ------------------------------------------------------------------ pass 1: rows, real -> half spectrum
+template <int N>
+__global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, float2* __restrict__ S,
+                                                  int pitch, long long npairs, const float2* __restrict__ tw,
+                                                  int shift) {
+  constexpr int T = Plan<N>::T;
+  constexpr int FPB = (256 / T) > 0 ? (256 / T) : 1;
+  constexpr int LS = lstride<N>();
+  __shared__ float2 lds[FPB * LS];
+  const int f = threadIdx.x / T, t = threadIdx.x % T;
+  const long long pair = (long long)blockIdx.x * FPB + f;
+  const bool active = (f < FPB) && (pair < npairs);
+  float2* buf = lds + (f < FPB ? f : 0) * LS;
+  long long ch = 0;
+  int r0 = 0;
+  if (active) {
+    ch = pair / (N / 2);
+    r0 = 2 * (int)(pair % (N / 2));
+    const float* xc = x + ch * (long long)N * N;
+    int ra = r0, rb = r0 + 1;
+    if (shift) {
+      ra = (ra + N / 2) % N;
+      rb = (rb + N / 2) % N;
+    }
+    const float* pa = xc + (long long)ra * N;
+    const float* pb = xc + (long long)rb * N;
+    for (int i = t; i < N; i += T) {
+      const int c = shift ? (i + N / 2) % N : i;
+      buf[lpad(i)] = make_float2(pa[c], pb[c]);
+    }
+  }
+  __syncthreads();
+  fft_lds<N, false>(buf, t, active, tw);
+  if (active) {
+    float2* sa = S + (ch * N + r0) * (long long)pitch;
+    float2* sb = sa + pitch;
+    for (int k = t; k <= N / 2; k += T) {
+      const float2 zk = buf[lpad(k)];
+      const float2 zm = cconj(buf[lpad((N - k) % N)]);
+      // A = (Z_k + conj Z_{N-k}) / 2,  B = (Z_k - conj Z_{N-k}) / (2i)
+      const float2 a = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+      const float2 d = csub(zk, zm);
+      const float2 bb = make_float2(0.5f * d.y, -0.5f * d.x);
+      sa[k] = a;
+      sb[k] = bb;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ pass 2: columns
+template <int N>
+constexpr int col_block() {
+  constexpr int T = Plan<N>::T;
+  constexpr int cb = 512 / T;
+  return cb < 8 ? 8 : (cb > 32 ? 32 : cb);
+}
+
+template <int N, int MODE>
+__global__ void __launch_bounds__(512) k_cols(float2* __restrict__ S, int pitch, int ncb,
+                                              const float2* __restrict__ tw, const float* __restrict__ Mr,
+                                              const float2* __restrict__ Mc, float scale,
+                                              float2* __restrict__ outT) {
+  constexpr int T = Plan<N>::T;
+  constexpr int CB = col_block<N>();
+  constexpr int LS = lstride<N>();
+  extern __shared__ float2 lds[];
+  const int ch = blockIdx.x / ncb;
+  const int c0 = (blockIdx.x % ncb) * CB;
+  const int nthr = CB * T;
+  float2* Sc = S + (long long)ch * N * pitch;
+  for (int idx = threadIdx.x; idx < N * CB; idx += nthr) {
+    const int r = idx / CB, c = idx % CB;
+    lds[c * LS + lpad(r)] = Sc[(long long)r * pitch + c0 + c];
+  }
+  __syncthreads();
+  const int f = threadIdx.x / T, t = threadIdx.x % T;
+  float2* buf = lds + f * LS;
+  fft_lds<N, false>(buf, t, true, tw);
+  const long long mrow = ((long long)ch * pitch + c0 + f) * N;  // transposed multiplier row
+  if constexpr (MODE == COL_FWD) {
+    for (int r = t; r < N; r += T) outT[mrow + r] = buf[lpad(r)];
+    return;
+  } else {
+    for (int r = t; r < N; r += T) {
+      float2 v = buf[lpad(r)];
+      if constexpr (MODE == COL_REAL) {
+        v = cscale(v, Mr[mrow + r] * scale);
+      } else {
+        float2 m = Mc[mrow + r];
+        if (MODE == COL_CPLX_CONJ) m.y = -m.y;
+        v = cscale(cmul(v, m), scale);
+      }
+      buf[lpad(r)] = v;
+    }
+    // fft_lds begins with reads of this thread group's own entries only after a barrier
+    __syncthreads();
+    fft_lds<N, true>(buf, t, true, tw);
+    for (int idx = threadIdx.x; idx < N * CB; idx += nthr) {
+      const int r = idx / CB, c = idx % CB;
+      Sc[(long long)r * pitch + c0 + c] = lds[c * LS + lpad(r)];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ pass 3: rows, half spectrum -> real
+__device__ __forceinline__ double block_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double red[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += red[i];
+  }
+  return s;
+}
+
+template <int N, int EPI>
+__global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, int pitch, long long npairs,
+                                                  const float2* __restrict__ tw, float* __restrict__ out,
+                                                  const float* __restrict__ b, const float* __restrict__ s,
+                                                  float s_scale, const float* __restrict__ y,
+                                                  const float* __restrict__ chan_w, double* __restrict__ partial) {
+  constexpr int T = Plan<N>::T;
+  constexpr int FPB = (256 / T) > 0 ? (256 / T) : 1;
+  constexpr int LS = lstride<N>();
+  __shared__ float2 lds[FPB * LS];
+  const int f = threadIdx.x / T, t = threadIdx.x % T;
+  const long long pair = (long long)blockIdx.x * FPB + f;
+  const bool active = (f < FPB) && (pair < npairs);
+  float2* buf = lds + (f < FPB ? f : 0) * LS;
+  long long ch = 0;
+  int r0 = 0;
+  if (active) {
+    ch = pair / (N / 2);
+    r0 = 2 * (int)(pair % (N / 2));
+    const float2* sa = S + (ch * N + r0) * (long long)pitch;
+    const float2* sb = sa + pitch;
+    for (int k = t; k < N; k += T) {
+      float2 a, bb;
+      if (k <= N / 2) {
+        a = sa[k];
+        bb = sb[k];
+        if (k == 0 || k == N / 2) {
+          a.y = 0.f;
+          bb.y = 0.f;
+        }
+      } else {
+        a = cconj(sa[N - k]);
+        bb = cconj(sb[N - k]);
+      }
+      // Z = A + i B
+      buf[lpad(k)] = make_float2(a.x - bb.y, a.y + bb.x);
+    }
+  }
+  __syncthreads();
+  fft_lds<N, true>(buf, t, active, tw);
+  double acc = 0.0;
+  if (active) {
+    const long long o0 = (ch * N + r0) * (long long)N;
+    const long long o1 = o0 + N;
+    for (int n = t; n < N; n += T) {
+      const float2 z = buf[lpad(n)];
+      if constexpr (EPI == EPI_STORE) {
+        out[o0 + n] = z.x;
+        out[o1 + n] = z.y;
+      } else if constexpr (EPI == EPI_GRAD) {
+        float g0 = z.x - b[o0 + n], g1 = z.y - b[o1 + n];
+        if (s) {
+          g0 += s_scale * s[o0 + n];
+          g1 += s_scale * s[o1 + n];
+        }
+        out[o0 + n] = g0;
+        out[o1 + n] = g1;
+      } else {
+        const double r0d = (double)z.x - (double)y[o0 + n];
+        const double r1d = (double)z.y - (double)y[o1 + n];
+        acc += r0d * r0d + r1d * r1d;
+      }
+    }
+    if constexpr (EPI == EPI_RESID) acc *= 0.5 * (chan_w ? (double)chan_w[ch] : 1.0);
+  }
+  if constexpr (EPI == EPI_RESID) {
+    const double tot = block_sum_d(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+  }
+}
+
+// ------------------------------------------------------------------ host side
+bool fft_supported(int N) {
+  switch (N) {
+    case 8: case 16: case 32: case 64: case 128: case 256: case 512: case 1024:
+    case 12: case 24: case 48: case 96: case 192: case 384: case 768:
+      return true;
+    default:
+      return false;
+  }
+}
+
+template <int N>
+static FftGeom geom_of() {
+  FftGeom g;
+  g.N = N;
+  g.CB = col_block<N>();
+  g.ncb = (N / 2 + 1 + g.CB - 1) / g.CB;
+  g.pitch = g.ncb * g.CB;
+  return g;
+}
+
+FftGeom fft_geom(int N) {
+  switch (N) {
+#define MF_G(n) case n: return geom_of<n>();
+    MF_G(8) MF_G(16) MF_G(32) MF_G(64) MF_G(128) MF_G(256) MF_G(512) MF_G(1024)
+    MF_G(12) MF_G(24) MF_G(48) MF_G(96) MF_G(192) MF_G(384) MF_G(768)
+#undef MF_G
+    default: return FftGeom{};
+  }
+}
+
+std::vector<float2> fft_twiddles(int N) {
+  std::vector<float2> tw(N);
+  for (int m = 0; m < N; ++m) {
+    const double a = -2.0 * M_PI * (double)m / (double)N;
+    tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  return tw;
+}
+
+template <int N>
+static int rows_r2c_n(const float* x, float2* S, int nch, const FftGeom& g, const float2* tw, bool shift,
+                      hipStream_t st) {
+  constexpr int T = Plan<N>::T;
+  constexpr int FPB = (256 / T) > 0 ? (256 / T) : 1;
+  const long long npairs = (long long)nch * (N / 2);
+  const long long nblk = (npairs + FPB - 1) / FPB;
+  hipLaunchKernelGGL(k_rows_r2c<N>, dim3((unsigned)nblk), dim3(FPB * T), 0, st, x, S, g.pitch, npairs, tw,
+                     shift ? 1 : 0);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+template <int N>
+static int cols_n(float2* S, int nch, const FftGeom& g, const float2* tw, int mode, const float* Mr,
+                  const float2* Mc, float scale, float2* outT, hipStream_t st) {
+  constexpr int T = Plan<N>::T;
+  constexpr int CB = col_block<N>();
+  constexpr int LS = lstride<N>();
+  const size_t shm = sizeof(float2) * CB * LS;
+  const dim3 grid((unsigned)(nch * g.ncb)), block(CB * T);
+  switch (mode) {
+    case COL_FWD:
+      hipLaunchKernelGGL((k_cols<N, COL_FWD>), grid, block, shm, st, S, g.pitch, g.ncb, tw, Mr, Mc, scale, outT);
+      break;
+    case COL_REAL:
+      hipLaunchKernelGGL((k_cols<N, COL_REAL>), grid, block, shm, st, S, g.pitch, g.ncb, tw, Mr, Mc, scale, outT);
+      break;
+    case COL_CPLX:
+      hipLaunchKernelGGL((k_cols<N, COL_CPLX>), grid, block, shm, st, S, g.pitch, g.ncb, tw, Mr, Mc, scale, outT);
+      break;
+    case COL_CPLX_CONJ:
+      hipLaunchKernelGGL((k_cols<N, COL_CPLX_CONJ>), grid, block, shm, st, S, g.pitch, g.ncb, tw, Mr, Mc, scale,
+                         outT);
+      break;
+    default:
+      set_error("launch_cols: bad mode");
+      return MUFFIN_EINVAL;
+  }
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+template <int N>
+static int rows_c2r_n(const float2* S, int nch, const FftGeom& g, const float2* tw, int epi, float* out,
+                      const float* b, const float* s, float s_scale, const float* y, const float* chan_w,
+                      double* partial, int* nblocks_out, hipStream_t st) {
+  constexpr int T = Plan<N>::T;
+  constexpr int FPB = (256 / T) > 0 ? (256 / T) : 1;
+  const long long npairs = (long long)nch * (N / 2);
+  const long long nblk = (npairs + FPB - 1) / FPB;
+  if (nblocks_out) *nblocks_out = (int)nblk;
+  if (epi == EPI_RESID && nblk > kMaxPartials) {
+    set_error("rows_c2r: too many blocks for the partial-sum buffer");
+    return MUFFIN_EINVAL;
+  }
+  const dim3 grid((unsigned)nblk), block(FPB * T);
+  switch (epi) {
+    case EPI_STORE:
+      hipLaunchKernelGGL((k_rows_c2r<N, EPI_STORE>), grid, block, 0, st, S, g.pitch, npairs, tw, out, b, s, s_scale,
+                         y, chan_w, partial);
+      break;
+    case EPI_GRAD:
+      hipLaunchKernelGGL((k_rows_c2r<N, EPI_GRAD>), grid, block, 0, st, S, g.pitch, npairs, tw, out, b, s, s_scale,
+                         y, chan_w, partial);
+      break;
+    case EPI_RESID:
+      hipLaunchKernelGGL((k_rows_c2r<N, EPI_RESID>), grid, block, 0, st, S, g.pitch, npairs, tw, out, b, s, s_scale,
+                         y, chan_w, partial);
+      break;
+    default:
+      set_error("rows_c2r: bad epilogue");
+      return MUFFIN_EINVAL;
+  }
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+#define MF_DISPATCH(N, call) \
+  switch (N) {               \
+    case 8: return call<8>;  \
+    case 16: return call<16>; \
+    case 32: return call<32>; \
+    case 64: return call<64>; \
+    case 128: return call<128>; \
+    case 256: return call<256>; \
+    case 512: return call<512>; \
+    case 1024: return call<1024>; \
+    case 12: return call<12>; \
+    case 24: return call<24>; \
+    case 48: return call<48>; \
+    case 96: return call<96>; \
+    case 192: return call<192>; \
+    case 384: return call<384>; \
+    case 768: return call<768>; \
+    default: set_error("unsupported FFT size"); return MUFFIN_EINVAL; \
+  }
+
+int launch_rows_r2c(const float* x, float2* S, int nch, const FftGeom& g, const float2* tw, bool shift,
+                    hipStream_t st) {
+#define CALL(n) rows_r2c_n<n>(x, S, nch, g, tw, shift, st)
+  switch (g.N) {
+    case 8: return CALL(8);
+    case 16: return CALL(16);
+    case 32: return CALL(32);
+    case 64: return CALL(64);
+    case 128: return CALL(128);
+    case 256: return CALL(256);
+    case 512: return CALL(512);
+    case 1024: return CALL(1024);
+    case 12: return CALL(12);
+    case 24: return CALL(24);
+    case 48: return CALL(48);
+    case 96: return CALL(96);
+    case 192: return CALL(192);
+    case 384: return CALL(384);
+    case 768: return CALL(768);
+    default: set_error("unsupported FFT size"); return MUFFIN_EINVAL;
+  }
+#undef CALL
+}
+
+int launch_cols(float2* S, int nch, const FftGeom& g, const float2* tw, int mode, const float* Mr,
+                const float2* Mc, float scale, float2* outT, hipStream_t st) {
+#define CALL(n) cols_n<n>(S, nch, g, tw, mode, Mr, Mc, scale, outT, st)
+  switch (g.N) {
+    case 8: return CALL(8);
+    case 16: return CALL(16);
+    case 32: return CALL(32);
+    case 64: return CALL(64);
+    case 128: return CALL(128);
+    case 256: return CALL(256);
+    case 512: return CALL(512);
+    case 1024: return CALL(1024);
+    case 12: return CALL(12);
+    case 24: return CALL(24);
+    case 48: return CALL(48);
+    case 96: return CALL(96);
+    case 192: return CALL(192);
+    case 384: return CALL(384);
+    case 768: return CALL(768);
+    default: set_error("unsupported FFT size"); return MUFFIN_EINVAL;
+  }
+#undef CALL
+}
+
+int launch_rows_c2r(const float2* S, int nch, const FftGeom& g, const float2* tw, int epi, float* out,
+                    const float* b, const float* s, float s_scale, const float* y, const float* chan_w,
+                    double* partial, int* nblocks_out, hipStream_t st) {
+#define CALL(n) rows_c2r_n<n>(S, nch, g, tw, epi, out, b, s, s_scale, y, chan_w, partial, nblocks_out, st)
+  switch (g.N) {
+    case 8: return CALL(8);
+    case 16: return CALL(16);
+    case 32: return CALL(32);
+    case 64: return CALL(64);
+    case 128: return CALL(128);
+    case 256: return CALL(256);
+    case 512: return CALL(512);
+    case 1024: return CALL(1024);
+    case 12: return CALL(12);
+    case 24: return CALL(24);
+    case 48: return CALL(48);
+    case 96: return CALL(96);
+    case 192: return CALL(192);
+    case 384: return CALL(384);
+    case 768: return CALL(768);
+    default: set_error("unsupported FFT size"); return MUFFIN_EINVAL;
+  }
+#undef CALL
+}
+#undef MF_DISPATCH
+
+template <int N>
+static int attrs_n() {
+  constexpr int shm = (int)(sizeof(float2) * col_block<N>() * lstride<N>());
+  MF_HIP(hipFuncSetAttribute((const void*)k_cols<N, COL_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_cols<N, COL_REAL>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_cols<N, COL_CPLX>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_cols<N, COL_CPLX_CONJ>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  return MUFFIN_OK;
+}
+
+int fft_init_attrs(int N) {
+  switch (N) {
+    case 8: return attrs_n<8>();
+    case 16: return attrs_n<16>();
+    case 32: return attrs_n<32>();
+    case 64: return attrs_n<64>();
+    case 128: return attrs_n<128>();
+    case 256: return attrs_n<256>();
+    case 512: return attrs_n<512>();
+    case 1024: return attrs_n<1024>();
+    case 12: return attrs_n<12>();
+    case 24: return attrs_n<24>();
+    case 48: return attrs_n<48>();
+    case 96: return attrs_n<96>();
+    case 192: return attrs_n<192>();
+    case 384: return attrs_n<384>();
+    case 768: return attrs_n<768>();
+    default: set_error("unsupported FFT size"); return MUFFIN_EINVAL;
+  }
+}
+
+// P = w_l |H|^2 * scale on the transposed half spectrum.
+__global__ void __launch_bounds__(256) k_power_spectrum(const float2* __restrict__ H, float* __restrict__ P,
+                                                        const float* __restrict__ w, long long per_ch, float scale) {
+  const int ch = blockIdx.y;
+  const float s = scale * (w ? w[ch] : 1.f);
+  const long long o = (long long)ch * per_ch;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < per_ch; i += (long long)gridDim.x * 256) {
+    const float2 h = H[o + i];
+    P[o + i] = s * (h.x * h.x + h.y * h.y);
+  }
+}
+
+int launch_power_spectrum(const float2* Hhat_T, float* P_T, const float* chan_w, long long per_ch, int nch,
+                          float scale, hipStream_t st) {
+  long long nb = (per_ch + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  hipLaunchKernelGGL(k_power_spectrum, dim3((unsigned)nb, (unsigned)nch), dim3(256), 0, st, Hhat_T, P_T, chan_w,
+                     per_ch, scale);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+}  // namespace mf

@@ -1,0 +1,222 @@
+"""Python binding of libmuffin (C ABI in include/muffin.h): argument marshalling only.
+
+Every computation runs in the HIP library.  Device arrays are torch tensors on the GPU (float32,
+contiguous); their ``data_ptr()`` and torch's current stream are handed to the library.  If the
+library is missing, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmuffin.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libmuffin.so not built at {LIB_PATH}; run __graft_entry__.build()")
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ESTEP, ESTATE = 0, -1, -2, -3, -4, -5, -6
+OP_H, OP_HT, OP_GRAD, OP_IUWT, OP_IUWT_ADJ, OP_DCT, OP_IDCT = 1, 2, 3, 4, 5, 6, 7
+
+EXPORTS = [
+    "muffin_init", "muffin_step", "muffin_solve", "muffin_objective", "muffin_info",
+    "muffin_set_x", "muffin_get_x", "muffin_get_u", "muffin_get_v", "muffin_state_size",
+    "muffin_get_state", "muffin_set_state", "muffin_apply_op", "muffin_profile",
+    "muffin_step_timed", "muffin_free", "muffin_strerror", "muffin_last_error",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int32), ("L", ctypes.c_int32), ("J", ctypes.c_int32),
+        ("iuwt_gen", ctypes.c_int32), ("penalize_coarse", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("mu_s", ctypes.c_double), ("mu_lambda", ctypes.c_double),
+        ("tau", ctypes.c_double), ("sigma", ctypes.c_double), ("rho", ctypes.c_double),
+        ("chan_weight", ctypes.POINTER(ctypes.c_float)),
+    ]
+
+
+_vp, _i32, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+_lib.muffin_init.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(Params), _vp, _vp, ctypes.c_int, _vp]
+_lib.muffin_step.argtypes = [_vp, _i32]
+_lib.muffin_solve.argtypes = [_vp, _i32, _i32, _dbl, _dbl, ctypes.POINTER(_i32), ctypes.POINTER(_dbl)]
+_lib.muffin_objective.argtypes = [_vp, ctypes.POINTER(_dbl)]
+_lib.muffin_info.argtypes = [_vp, ctypes.POINTER(_dbl)]
+for _n in ("muffin_set_x", "muffin_get_x", "muffin_get_u", "muffin_get_v"):
+    getattr(_lib, _n).argtypes = [_vp, _vp, ctypes.c_int]
+_lib.muffin_state_size.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+_lib.muffin_get_state.argtypes = [_vp, _vp, ctypes.c_size_t]
+_lib.muffin_set_state.argtypes = [_vp, _vp, ctypes.c_size_t]
+_lib.muffin_apply_op.argtypes = [_vp, ctypes.c_int, _vp, _vp]
+_lib.muffin_profile.argtypes = [_vp, _i32, ctypes.POINTER(_dbl)]
+_lib.muffin_step_timed.argtypes = [_vp, _i32, ctypes.POINTER(_dbl)]
+_lib.muffin_free.argtypes = [_vp]
+_lib.muffin_free.restype = None
+_lib.muffin_strerror.argtypes = [ctypes.c_int]
+_lib.muffin_strerror.restype = ctypes.c_char_p
+_lib.muffin_last_error.argtypes = []
+_lib.muffin_last_error.restype = ctypes.c_char_p
+
+
+class MuffinError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.muffin_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_lib.muffin_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise MuffinError(rc, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, shape, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{what} must be contiguous float32")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Muffin:
+    """One reconstruction context (one cube) on the current GPU."""
+
+    def __init__(self, dirty, psf, J: int, mu_s: float, mu_lambda: float, iuwt_gen: int = 2,
+                 penalize_coarse: bool = True, tau: float = 0.0, sigma: float = 1.0,
+                 rho: float = 1.0, chan_weight=None):
+        torch = _torch()
+        dirty = torch.as_tensor(dirty, dtype=torch.float32).cuda().contiguous()
+        psf = torch.as_tensor(psf, dtype=torch.float32).cuda().contiguous()
+        L, N, N2 = dirty.shape
+        if N != N2 or tuple(psf.shape) != (L, N, N):
+            raise ValueError("dirty and psf must both be [L][N][N]")
+        self.N, self.L, self.J = N, L, J
+        self._cw = None
+        p = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=int(bool(penalize_coarse)),
+                   reserved=0, mu_s=mu_s, mu_lambda=mu_lambda, tau=tau, sigma=sigma, rho=rho)
+        if chan_weight is not None:
+            self._cw = np.ascontiguousarray(chan_weight, dtype=np.float32)
+            if self._cw.shape != (L,):
+                raise ValueError("chan_weight must have shape (L,)")
+            p.chan_weight = self._cw.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        h = ctypes.c_void_p()
+        _check(_lib.muffin_init(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(dirty.data_ptr()),
+                                ctypes.c_void_p(psf.data_ptr()), 1, _stream_handle()), "muffin_init")
+        self._h = h
+
+    # ------------------------------------------------------------------ lifecycle
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.muffin_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ------------------------------------------------------------------ iteration
+    def step(self, n: int = 1):
+        _check(_lib.muffin_step(self._h, n), "muffin_step")
+
+    def step_timed(self, n: int) -> float:
+        ms = ctypes.c_double()
+        _check(_lib.muffin_step_timed(self._h, n, ctypes.byref(ms)), "muffin_step_timed")
+        return ms.value
+
+    def profile(self, n: int) -> np.ndarray:
+        out = (ctypes.c_double * 8)()
+        _check(_lib.muffin_profile(self._h, n, out), "muffin_profile")
+        return np.array(out[:])
+
+    def solve(self, max_iter: int, check_every: int = 10, tol: float = 1e-4, f_ref: float = math.nan):
+        it, f = _i32(), _dbl()
+        _check(_lib.muffin_solve(self._h, max_iter, check_every, tol, f_ref, ctypes.byref(it),
+                                 ctypes.byref(f)), "muffin_solve")
+        return it.value, f.value
+
+    def objective(self) -> np.ndarray:
+        out = (ctypes.c_double * 4)()
+        _check(_lib.muffin_objective(self._h, out), "muffin_objective")
+        return np.array(out[:])
+
+    def info(self) -> dict:
+        out = (ctypes.c_double * 8)()
+        _check(_lib.muffin_info(self._h, out), "muffin_info")
+        keys = ["tau", "sigma", "rho", "beta", "K2", "Ws2", "delta", "iter"]
+        return dict(zip(keys, out[:]))
+
+    # ------------------------------------------------------------------ state
+    def set_x(self, x0):
+        torch = _torch()
+        x0 = torch.as_tensor(x0, dtype=torch.float32).cuda().contiguous()
+        _check(_lib.muffin_set_x(self._h, _dev_ptr(x0, (self.L, self.N, self.N), "x0"), 1), "muffin_set_x")
+        torch.cuda.current_stream().synchronize()
+
+    def _get(self, fn, shape):
+        torch = _torch()
+        out = torch.empty(shape, dtype=torch.float32, device="cuda")
+        _check(fn(self._h, ctypes.c_void_p(out.data_ptr()), 1), fn.__name__)
+        return out
+
+    def get_x(self):
+        return self._get(_lib.muffin_get_x, (self.L, self.N, self.N))
+
+    def get_u(self):
+        return self._get(_lib.muffin_get_u, (self.L, self.J + 1, self.N, self.N))
+
+    def get_v(self):
+        return self._get(_lib.muffin_get_v, (self.L, self.N, self.N))
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        _check(_lib.muffin_state_size(self._h, ctypes.byref(n)), "muffin_state_size")
+        buf = ctypes.create_string_buffer(n.value)
+        _check(_lib.muffin_get_state(self._h, buf, n.value), "muffin_get_state")
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(_lib.muffin_set_state(self._h, buf, len(blob)), "muffin_set_state")
+
+    # ------------------------------------------------------------------ single operators
+    def apply_op(self, op: int, x):
+        torch = _torch()
+        L, N, J = self.L, self.N, self.J
+        cube, ucube = (L, N, N), (L, J + 1, N, N)
+        in_shape = ucube if op == OP_IUWT_ADJ else cube
+        out_shape = ucube if op == OP_IUWT else cube
+        x = torch.as_tensor(x, dtype=torch.float32).cuda().contiguous()
+        out = torch.empty(out_shape, dtype=torch.float32, device="cuda")
+        _check(_lib.muffin_apply_op(self._h, op, _dev_ptr(x, in_shape, "in"),
+                                    _dev_ptr(out, out_shape, "out")), "muffin_apply_op")
+        return out
+
+
+def last_error() -> str:
+    return _lib.muffin_last_error().decode(errors="replace")
