@@ -47,6 +47,7 @@ struct muffin_ctx {
   float2* Hhat_T = nullptr;
   float* P_T = nullptr;
   float2* tw = nullptr;
+  float2 *twL = nullptr, *csL = nullptr;
   float *W = nullptr, *WT = nullptr;
   float* chan_w = nullptr;
   double* partial = nullptr;
@@ -125,15 +126,22 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omeg
   }
   for (int j = J - 1; j >= 0; --j) {
     const float* uj = Ubase + (long long)j * np;
-    const float* sub = uj;
-    if (c->gen == 2) {
-      MF_TRY(launch_atrous(AT_SMOOTH, c->N, c->L, j, pref(uj, ucs), PlaneRef{}, PlaneRef{}, pout(c->cT, np), 0.f,
-                           1.f, nullptr, nullptr, c->st));
-      sub = c->cT;
-    }
     float* dst = bufs[nb];
-    MF_TRY(launch_atrous(AT_SUBADD, c->N, c->L, j, pref(a, acs), pref(sub, c->gen == 2 ? np : ucs),
-                         pref(uj, ucs), pout(dst, np), 0.f, 1.f, nullptr, nullptr, c->st));
+    if (c->gen == 2 && atrous_double_fits(c->N, j, nullptr, nullptr)) {
+      MF_TRY(launch_atrous(DB_ADJOINT, c->N, c->L, j, pref(uj, ucs), pref(a, acs), PlaneRef{}, pout(dst, np),
+                           PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
+    } else {
+      const float* sub = uj;
+      long long scs = ucs;
+      if (c->gen == 2) {
+        MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(uj, ucs), PlaneRef{}, PlaneRef{}, pout(c->cT, np),
+                             PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
+        sub = c->cT;
+        scs = np;
+      }
+      MF_TRY(launch_atrous(SM_SUBADD, c->N, c->L, j, pref(a, acs), pref(sub, scs), pref(uj, ucs), pout(dst, np),
+                           PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
+    }
     a = dst;
     acs = np;
     nb ^= 1;
@@ -152,15 +160,19 @@ int enqueue_dual_update(muffin_ctx* c, const float* in) {
   float* bufs[2] = {c->cA, c->cB};
   for (int j = 0; j < J; ++j) {
     float* nxt = bufs[j & 1];
-    MF_TRY(launch_atrous(AT_SMOOTH, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np), 0.f, 1.f,
-                         nullptr, nullptr, c->st));
     float* uj = c->U + (long long)j * np;
-    if (c->gen == 2)
-      MF_TRY(launch_atrous(AT_DETAIL, c->N, c->L, j, pref(nxt, np), PlaneRef{}, pref(cur, np), pout(uj, ucs), coef,
-                           rho, nullptr, nullptr, c->st));
-    else
-      MF_TRY(launch_pointwise(PT_DETAIL1, c->N, c->L, pref(nxt, np), pref(cur, np), pout(uj, ucs), coef, rho,
-                              nullptr, nullptr, c->st));
+    if (c->gen == 1) {
+      MF_TRY(launch_atrous(SM_DETAIL1, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                           pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
+    } else if (atrous_double_fits(c->N, j, nullptr, nullptr)) {
+      MF_TRY(launch_atrous(DB_ANALYSIS, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                           pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
+    } else {
+      MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np),
+                           PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
+      MF_TRY(launch_atrous(SM_DETAIL, c->N, c->L, j, pref(nxt, np), PlaneRef{}, pref(cur, np), pout(uj, ucs),
+                           PlaneOut{}, coef, rho, nullptr, nullptr, c->st));
+    }
     cur = nxt;
   }
   MF_TRY(launch_pointwise(PT_COARSE, c->N, c->L, pref(cur, np), PlaneRef{}, pout(c->U + (long long)J * np, ucs),
@@ -184,8 +196,11 @@ int enqueue_spectral(muffin_ctx* c) {
   a.D = c->D;
   a.W = c->W;
   a.WT = c->WT;
+  a.twL = c->twL;
+  a.csL = c->csL;
   a.npix = c->npix;
   a.L = c->L;
+  a.use_fft = spectral_has_fft(c->L) ? 1 : 0;
   a.tau = (float)c->tau;
   a.mu_l = (float)c->p.mu_lambda;
   a.smu_l = (float)(c->sigma * c->p.mu_lambda);
@@ -223,11 +238,11 @@ int enqueue_objective(muffin_ctx* c) {
   float* bufs[2] = {c->cA, c->cB};
   for (int j = 0; j < c->J; ++j) {
     float* nxt = bufs[j & 1];
-    MF_TRY(launch_atrous(AT_SMOOTH, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np), 0.f, 1.f,
-                         nullptr, nullptr, c->st));
+    MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np),
+                         PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
     if (c->gen == 2)
-      MF_TRY(launch_atrous(AT_DETAIL_ABS, c->N, c->L, j, pref(nxt, np), PlaneRef{}, pref(cur, np), PlaneOut{}, 0.f,
-                           1.f, c->partial, &nb, c->st));
+      MF_TRY(launch_atrous(SM_DETAIL_ABS, c->N, c->L, j, pref(nxt, np), PlaneRef{}, pref(cur, np), PlaneOut{},
+                           PlaneOut{}, 0.f, 1.f, c->partial, &nb, c->st));
     else
       MF_TRY(launch_pointwise(PT_ABS_DIFF, c->N, c->L, pref(nxt, np), pref(cur, np), PlaneOut{}, 0.f, 1.f,
                               c->partial, &nb, c->st));
@@ -250,7 +265,7 @@ void destroy(muffin_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   void* bufs[] = {c->X, c->U, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT, c->S, c->Hhat_T, c->P_T,
-                  c->tw, c->W, c->WT, c->chan_w, c->partial, c->dres};
+                  c->tw, c->twL, c->csL, c->W, c->WT, c->chan_w, c->partial, c->dres};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   hipEvent_t evs[] = {c->ev_in, c->ev_out, c->e0, c->e1, c->ph[0], c->ph[1], c->ph[2], c->ph[3], c->ph[4]};
@@ -311,6 +326,8 @@ int init_impl(muffin_ctx* c, const muffin_params* p, const float* dirty, const f
   MF_TRY(dalloc(&c->Hhat_T, spec));
   MF_TRY(dalloc(&c->P_T, spec));
   MF_TRY(dalloc(&c->tw, c->N));
+  MF_TRY(dalloc(&c->twL, c->L));
+  MF_TRY(dalloc(&c->csL, c->L));
   MF_TRY(dalloc(&c->W, (long long)c->L * c->L));
   MF_TRY(dalloc(&c->WT, (long long)c->L * c->L));
   MF_TRY(dalloc(&c->partial, kMaxPartials));
@@ -328,6 +345,14 @@ int init_impl(muffin_ctx* c, const muffin_params* p, const float* dirty, const f
   {
     auto tw = fft_twiddles(c->N);
     MF_HIP(hipMemcpyAsync(c->tw, tw.data(), sizeof(float2) * c->N, hipMemcpyHostToDevice, st));
+    auto twl = fft_twiddles(c->L);
+    std::vector<float2> cs(c->L);
+    for (int k = 0; k < c->L; ++k) {
+      const double th = M_PI * k / (2.0 * c->L);
+      cs[k] = make_float2((float)std::cos(th), (float)std::sin(th));
+    }
+    MF_HIP(hipMemcpyAsync(c->twL, twl.data(), sizeof(float2) * c->L, hipMemcpyHostToDevice, st));
+    MF_HIP(hipMemcpyAsync(c->csL, cs.data(), sizeof(float2) * c->L, hipMemcpyHostToDevice, st));
     std::vector<float> W((size_t)c->L * c->L), WT((size_t)c->L * c->L);
     for (int l = 0; l < c->L; ++l)
       for (int k = 0; k < c->L; ++k) {
@@ -648,13 +673,13 @@ int muffin_apply_op(muffin_ctx* c, int op, const float* in, float* out) {
       float* bufs[2] = {c->cA, c->cB};
       for (int j = 0; j < c->J; ++j) {
         float* nxt = bufs[j & 1];
-        MF_TRY(launch_atrous(AT_SMOOTH, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np), 0.f,
-                             1.f, nullptr, nullptr, c->st));
+        MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np),
+                             PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
         float* wj = out + (long long)j * np;
         if (c->gen == 2) {
           // w = c_j - H_j c_{j+1}: smooth c_{j+1} into the output plane, then subtract
-          MF_TRY(launch_atrous(AT_SMOOTH, c->N, c->L, j, pref(nxt, np), PlaneRef{}, PlaneRef{}, pout(c->cT, np), 0.f,
-                               1.f, nullptr, nullptr, c->st));
+          MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(nxt, np), PlaneRef{}, PlaneRef{}, pout(c->cT, np),
+                               PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
           MF_TRY(launch_pointwise(PT_SUB, c->N, c->L, pref(c->cT, np), pref(cur, np), pout(wj, ucs), 0.f, 1.f,
                                   nullptr, nullptr, c->st));
         } else {

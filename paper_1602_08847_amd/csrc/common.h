@@ -83,13 +83,18 @@ struct PlaneOut {
   long long cs = 0;
 };
 enum AtrousMode {
-  AT_SMOOTH = 0,     // out = H_j(A)
-  AT_SUBADD = 1,     // out = E + H_j(A - B)
-  AT_DETAIL = 2,     // w = E - H_j(A);  out(u) = rho*sat(u + coef*w) + (1-rho)*u  (in place on out)
-  AT_DETAIL_ABS = 3  // partial[block] = sum |E - H_j(A)|
+  SM_SMOOTH = 0,      // out = H_j(A)
+  SM_SUBADD = 1,      // out = E + H_j(A - B)
+  SM_DETAIL = 2,      // w = E - H_j(A);  u(out) <- rho*sat(u + coef*w) + (1-rho)*u
+  SM_DETAIL_ABS = 3,  // partial[block] = sum |E - H_j(A)|
+  SM_DETAIL1 = 4,     // out2 = H_j(A); w = A - H_j(A); u(out) update  (first generation)
+  DB_ANALYSIS = 5,    // out2 = c' = H_j(A); w = A - H_j(c'); u(out) update  (second generation)
+  DB_ADJOINT = 6      // out = A + H_j(B - H_j(A))  (A = u_j, B = a; second generation Horner step)
 };
+// true if the double-smoothing kernels fit in LDS at scale j for image side N
+bool atrous_double_fits(int N, int j, int* TX, int* TY);
 int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out,
-                  float coef, float rho, double* partial, int* nblocks_out, hipStream_t st);
+                  PlaneOut out2, float coef, float rho, double* partial, int* nblocks_out, hipStream_t st);
 enum PointMode {
   PT_DETAIL1 = 0,  // w = E - A; u update (first-generation detail, no smoothing)
   PT_COARSE = 1,   // w = A; u update
@@ -109,10 +114,14 @@ struct SpectralArgs {
   float* D;
   const float* W;   // [L][L] W[l][k] = s_k cos(pi (2l+1) k / 2L)
   const float* WT;  // [L][L] transpose
-  long long npix;   // N*N
+  const float2* twL;  // FFT twiddles exp(-2 pi i m / L)
+  const float2* csL;  // exp(i pi k / 2L)
+  long long npix;     // N*N
   int L;
+  int use_fft;        // 1: FFT-based cosine transforms (L has an FFT plan), 0: cosine table
   float tau, mu_l, smu_l, rho;
 };
+bool spectral_has_fft(int L);
 int launch_spectral_step(const SpectralArgs& a, hipStream_t st);
 // out = X W_lambda (inverse = false) or X W_lambda^dagger (inverse = true), per pixel.
 int launch_dct(const float* in, float* out, const float* Wmat, long long npix, int L, hipStream_t st);

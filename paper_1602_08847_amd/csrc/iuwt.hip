@@ -1,21 +1,19 @@
 // Isotropic undecimated wavelet transform (B3-spline a trous, periodic boundary) building blocks.
 //
-// H_j is the separable smoothing by [1, 4, 6, 4, 1] / 16 with taps 2^j apart along each axis.
-// A workgroup owns a TX x TY output tile of one channel; it loads the tile plus a halo of 2^(j+1)
-// pixels on every side (wrapped periodically) into LDS, filters the columns into a second LDS
-// buffer, filters the rows, and applies one of the fused epilogues:
-//   AT_SMOOTH      out = H_j A                           (analysis: c_{j+1} = H_j c_j)
-//   AT_SUBADD      out = E + H_j (A - B)                 (adjoint Horner step, both generations)
-//   AT_DETAIL      w = E - H_j A, u <- rho sat(u + coef w) + (1 - rho) u   (gen-2 detail + dual step)
-//   AT_DETAIL_ABS  partial = sum |E - H_j A|             (objective, FP64)
+// H_j is the separable smoothing by [1, 4, 6, 4, 1] / 16 with taps s = 2^j apart along each axis.
+// Every kernel is the band kernel below with a fused epilogue:
+//   SM_SMOOTH      out = H_j A                           (c_{j+1} = H_j c_j)
+//   SM_SUBADD      out = E + H_j (A - B)                 (adjoint Horner step)
+//   SM_DETAIL      w = E - H_j A, u <- rho sat(u + coef w) + (1 - rho) u     (second generation)
+//   SM_DETAIL_ABS  partial = sum |E - H_j A|             (objective, FP64)
+//   SM_DETAIL1     out2 = H_j A and u update with w = A - H_j A              (first generation)
+//   DB_ANALYSIS    c' = H_j c (written to out2), w = c - H_j c', u update     (second generation)
+//   DB_ADJOINT     out = u + H_j (a - H_j u)  (A = u, B = a)                  (second generation)
+// Workgroups are ordered so that each XCD (blocks b, b + 8, ...) walks a contiguous range of
+// bands, keeping neighbouring bands' edge rows in its own L2.
 #include "common.h"
 
 namespace mf {
-
-__device__ __forceinline__ int wrapi(int v, int N) {
-  v %= N;
-  return v < 0 ? v + N : v;
-}
 
 __device__ __forceinline__ float satf(float u) { return fminf(1.f, fmaxf(-1.f, u)); }
 
@@ -35,113 +33,243 @@ __device__ __forceinline__ double block_sum_atrous(double v) {
 
 struct AtrousArgs {
   PlaneRef A, B, E;
-  PlaneOut out;
+  PlaneOut out, out2;
   int N, j, TX, TY;
-  int tiles_x, tiles_y;
+  int tiles_x, tiles_per_ch, nblocks;
+  int small;  // halo may exceed N: wrap with a full modulo
   float coef, rho;
   double* partial;
 };
 
-template <int MODE>
-__global__ void __launch_bounds__(256) k_atrous(AtrousArgs a) {
+// XCD-aware block order: block b runs on XCD b % 8; XCD x gets a contiguous range of tiles.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = b & 7, i = b >> 3;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
+__device__ __forceinline__ int wrap_idx(int v, int N, int small) {
+  if (small) {
+    v %= N;
+    return v < 0 ? v + N : v;
+  }
+  return v < 0 ? v + N : (v >= N ? v - N : v);
+}
+
+__device__ __forceinline__ float b3(float c0, float c1, float c2, float c3, float c4) {
+  return 0.0625f * (c0 + c4) + 0.25f * (c1 + c3) + 0.375f * c2;
+}
+
+// Band kernel: one workgroup of N threads owns rows [y0, y0 + TY) of one channel, thread x owns
+// column x.  Rows are visited residue class by residue class modulo s, so the vertical 5-tap
+// filter is a sliding window of five registers fed by one coalesced row load per step.  KR
+// vertical results at a time go through LDS for the horizontal taps (x +- s, x +- 2s, periodic).
+// Double-smoothing modes chain a second window over the first stage's output in the same class,
+// two steps behind, which extends the first stage by 2s rows on each side of the band.
+template <int MODE, int KR>
+__global__ void __launch_bounds__(1024) k_band(AtrousArgs a) {
+  constexpr bool DBL = (MODE == DB_ANALYSIS || MODE == DB_ADJOINT);
   extern __shared__ float sm[];
-  const int N = a.N;
-  const int s = 1 << a.j;      // tap spacing
-  const int h = 2 * s;         // halo
-  const int TX = a.TX, TY = a.TY;
-  const int W = TX + 2 * h, Hh = TY + 2 * h;
-  float* in = sm;              // [Hh][W]
-  float* mid = sm + Hh * W;    // [TY][W]
-  const int tile = blockIdx.x;
-  const int ch = blockIdx.y;
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  const int x0 = tx * TX, y0 = ty * TY;
-  const float* A = a.A.p + ch * a.A.cs;
-  const float* B = (MODE == AT_SUBADD) ? a.B.p + ch * a.B.cs : nullptr;
-  for (int idx = threadIdx.x; idx < Hh * W; idx += blockDim.x) {
-    const int yy = idx / W, xx = idx - yy * W;
-    const long long g = (long long)wrapi(y0 - h + yy, N) * N + wrapi(x0 - h + xx, N);
+  const int N = a.N, s = 1 << a.j, x = threadIdx.x, TY = a.TY;
+  const int small = a.small;
+  float* buf1 = sm;                            // [2][KR][N] single stage, [KR][N] double
+  float* buf2 = sm + (DBL ? KR : 2 * KR) * N;  // [KR][N]
+  const int b = xcd_remap(blockIdx.x, a.nblocks);
+  const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
+  const int y0 = band * TY;
+  const int E1 = DBL ? 2 * s : 0;
+  const float* __restrict__ A = a.A.p + ch * a.A.cs;
+  const float* __restrict__ B = (MODE == SM_SUBADD || MODE == DB_ADJOINT) ? a.B.p + ch * a.B.cs : nullptr;
+  const int xm2 = wrap_idx(x - 2 * s, N, 1), xm1 = wrap_idx(x - s, N, 1);
+  const int xp1 = wrap_idx(x + s, N, 1), xp2 = wrap_idx(x + 2 * s, N, 1);
+  auto loadA = [&](int y) -> float {
+    const long long g = (long long)wrap_idx(y, N, small) * N + x;
     float v = A[g];
-    if (MODE == AT_SUBADD) v -= B[g];
-    in[idx] = v;
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < TY * W; idx += blockDim.x) {
-    const int yy = idx / W, xx = idx - yy * W;
-    const float* c = in + yy * W + xx;  // taps at rows yy + {0, s, 2s, 3s, 4s}
-    mid[idx] = 0.0625f * (c[0] + c[4 * s * W]) + 0.25f * (c[s * W] + c[3 * s * W]) + 0.375f * c[2 * s * W];
-  }
-  __syncthreads();
+    if (MODE == SM_SUBADD) v -= B[g];
+    return v;
+  };
   double acc = 0.0;
-  for (int idx = threadIdx.x; idx < TY * TX; idx += blockDim.x) {
-    const int yy = idx / TX, xx = idx - yy * TX;
-    const float* c = mid + yy * W + xx;
-    const float v = 0.0625f * (c[0] + c[4 * s]) + 0.25f * (c[s] + c[3 * s]) + 0.375f * c[2 * s];
-    const long long g = (long long)(y0 + yy) * N + (x0 + xx);
-    if constexpr (MODE == AT_SMOOTH) {
-      a.out.p[ch * a.out.cs + g] = v;
-    } else if constexpr (MODE == AT_SUBADD) {
-      a.out.p[ch * a.out.cs + g] = a.E.p[ch * a.E.cs + g] + v;
-    } else if constexpr (MODE == AT_DETAIL) {
-      const float w = a.E.p[ch * a.E.cs + g] - v;
-      float* up = a.out.p + ch * a.out.cs + g;
-      const float u = *up;
-      *up = a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u;
-    } else {
-      acc += fabs((double)a.E.p[ch * a.E.cs + g] - (double)v);
+  int round = 0;
+  for (int r = 0; r < s; ++r) {
+    const int first = y0 + r - E1;                 // first stage-1 output row of this class
+    const int M1 = (TY + 2 * E1 - r + s - 1) / s;  // stage-1 steps: first + m s < y0 + TY + E1
+    if (M1 <= 0) continue;
+    float w0 = loadA(first - 2 * s), w1 = loadA(first - s), w2 = loadA(first), w3 = loadA(first + s);
+    float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+    for (int m0 = 0; m0 < M1; m0 += KR) {
+      float pv[KR], cen1[KR], cen2[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const int m = m0 + kk;
+        pv[kk] = 0.f;
+        cen1[kk] = 0.f;
+        cen2[kk] = 0.f;
+        if (m < M1) {
+          const float w4 = loadA(first + m * s + 2 * s);
+          pv[kk] = b3(w0, w1, w2, w3, w4);
+          cen1[kk] = w2;
+          cen2[kk] = w0;
+          w0 = w1;
+          w1 = w2;
+          w2 = w3;
+          w3 = w4;
+        }
+      }
+      float* L1 = buf1 + (DBL ? 0 : (round & 1) * KR * N);
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) L1[kk * N + x] = pv[kk];
+      __syncthreads();
+      float P[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const float* row = L1 + kk * N;
+        P[kk] = b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]);
+      }
+      if constexpr (!DBL) {
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) {
+          const int m = m0 + kk;
+          if (m >= M1) continue;
+          const long long g = (long long)(first + m * s) * N + x;  // inside the band, no wrap
+          const float v = P[kk];
+          if constexpr (MODE == SM_SMOOTH) {
+            a.out.p[ch * a.out.cs + g] = v;
+          } else if constexpr (MODE == SM_SUBADD) {
+            a.out.p[ch * a.out.cs + g] = a.E.p[ch * a.E.cs + g] + v;
+          } else if constexpr (MODE == SM_DETAIL || MODE == SM_DETAIL1) {
+            const float e = (MODE == SM_DETAIL) ? a.E.p[ch * a.E.cs + g] : cen1[kk];
+            const float w = e - v;
+            float* up = a.out.p + ch * a.out.cs + g;
+            const float u = *up;
+            *up = a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u;
+            if (MODE == SM_DETAIL1) a.out2.p[ch * a.out2.cs + g] = v;
+          } else {
+            acc += fabs((double)a.E.p[ch * a.E.cs + g] - (double)v);
+          }
+        }
+      } else {
+        float rv[KR];
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) {
+          const int m = m0 + kk;
+          rv[kk] = 0.f;
+          if (m < M1) {
+            const int y = first + m * s;
+            float qin = P[kk];
+            if constexpr (MODE == DB_ADJOINT) {
+              qin = B[(long long)wrap_idx(y, N, small) * N + x] - qin;
+            } else {
+              if (y >= y0 && y < y0 + TY) a.out2.p[ch * a.out2.cs + (long long)y * N + x] = qin;
+            }
+            if (m >= 4) rv[kk] = b3(q0, q1, q2, q3, qin);
+            q0 = q1;
+            q1 = q2;
+            q2 = q3;
+            q3 = qin;
+          }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) buf2[kk * N + x] = rv[kk];
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KR; ++kk) {
+          const int m = m0 + kk;
+          if (m >= M1 || m < 4) continue;
+          const float* row = buf2 + kk * N;
+          const float R = b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]);
+          const long long g = (long long)(first + m * s - 2 * s) * N + x;  // stage-2 row, inside the band
+          if constexpr (MODE == DB_ADJOINT) {
+            a.out.p[ch * a.out.cs + g] = cen2[kk] + R;
+          } else {
+            const float w = cen2[kk] - R;
+            float* up = a.out.p + ch * a.out.cs + g;
+            const float u = *up;
+            *up = a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u;
+          }
+        }
+      }
+      ++round;
     }
   }
-  if constexpr (MODE == AT_DETAIL_ABS) {
+  if constexpr (MODE == SM_DETAIL_ABS) {
     const double tot = block_sum_atrous(acc);
-    if (threadIdx.x == 0) a.partial[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = tot;
   }
 }
 
-static void tile_shape(int N, int j, int& TX, int& TY) {
-  // widest row tile that divides N (coalesced rows), height chosen to bound LDS
-  TX = 64;
-  while (N % TX) TX >>= 1;
-  const int h = 2 << j;
-  TY = 32;
-  while (TY > 4 && (size_t)((TY + 2 * h) * (TX + 2 * h) + TY * (TX + 2 * h)) * 4 > 96 * 1024) TY >>= 1;
+constexpr int kKR = 8;
+
+static int band_rows(int N, int j) {
+  // about 32 s rows per band (band edges cost 4s or 8s extra row loads per class), at least 64
+  int target = 32 << j;
+  if (target < 64) target = 64;
+  int TY = 1;
+  while (TY * 2 <= target && TY * 2 <= N) TY *= 2;
   while (N % TY) TY >>= 1;
+  return TY;
 }
 
-int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out, float coef,
-                  float rho, double* partial, int* nblocks_out, hipStream_t st) {
+bool atrous_double_fits(int N, int j, int* TXo, int* TYo) {
+  if (TXo) *TXo = N;
+  if (TYo) *TYo = band_rows(N, j);
+  return true;
+}
+
+int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out, PlaneOut out2,
+                  float coef, float rho, double* partial, int* nblocks_out, hipStream_t st) {
   AtrousArgs a;
   a.A = A;
   a.B = B;
   a.E = E;
   a.out = out;
+  a.out2 = out2;
   a.N = N;
   a.j = j;
-  tile_shape(N, j, a.TX, a.TY);
-  a.tiles_x = N / a.TX;
-  a.tiles_y = N / a.TY;
   a.coef = coef;
   a.rho = rho;
   a.partial = partial;
-  const int h = 2 << j;
-  const size_t shm = sizeof(float) * ((size_t)(a.TY + 2 * h) * (a.TX + 2 * h) + (size_t)a.TY * (a.TX + 2 * h));
-  if (shm > 144 * 1024) {
-    set_error("atrous: scale too coarse for the LDS tile");
-    return MUFFIN_EINVAL;
-  }
-  const dim3 grid((unsigned)(a.tiles_x * a.tiles_y), (unsigned)nch);
-  if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y);
-  if (mode == AT_DETAIL_ABS && (long long)grid.x * grid.y > kMaxPartials) {
+  const bool dbl = (mode == DB_ANALYSIS || mode == DB_ADJOINT);
+  if (N > 1024) return set_error("atrous: N > 1024"), MUFFIN_EINVAL;
+  a.TX = N;
+  a.TY = band_rows(N, j);
+  a.tiles_x = 1;
+  a.tiles_per_ch = N / a.TY;
+  const long long nb = (long long)a.tiles_per_ch * nch;
+  if (nb > 0x7fffffffLL) return set_error("atrous: grid too large"), MUFFIN_EINVAL;
+  if (nblocks_out) *nblocks_out = (int)nb;
+  if (mode == SM_DETAIL_ABS && nb > kMaxPartials) {
     set_error("atrous: too many blocks for the partial-sum buffer");
     return MUFFIN_EINVAL;
   }
+  a.nblocks = (int)nb;
+  const int s = 1 << j;
+  a.small = (dbl ? 4 * s : 2 * s) + a.TY >= N ? 1 : 0;  // row indices may leave [-N, 2N)
+  const size_t shm = sizeof(float) * (size_t)2 * kKR * N;
+  const dim3 grid((unsigned)nb), block((unsigned)N);
   switch (mode) {
-    case AT_SMOOTH: hipLaunchKernelGGL(k_atrous<AT_SMOOTH>, grid, dim3(256), shm, st, a); break;
-    case AT_SUBADD: hipLaunchKernelGGL(k_atrous<AT_SUBADD>, grid, dim3(256), shm, st, a); break;
-    case AT_DETAIL: hipLaunchKernelGGL(k_atrous<AT_DETAIL>, grid, dim3(256), shm, st, a); break;
-    case AT_DETAIL_ABS: hipLaunchKernelGGL(k_atrous<AT_DETAIL_ABS>, grid, dim3(256), shm, st, a); break;
+    case SM_SMOOTH: hipLaunchKernelGGL((k_band<SM_SMOOTH, kKR>), grid, block, shm, st, a); break;
+    case SM_SUBADD: hipLaunchKernelGGL((k_band<SM_SUBADD, kKR>), grid, block, shm, st, a); break;
+    case SM_DETAIL: hipLaunchKernelGGL((k_band<SM_DETAIL, kKR>), grid, block, shm, st, a); break;
+    case SM_DETAIL_ABS: hipLaunchKernelGGL((k_band<SM_DETAIL_ABS, kKR>), grid, block, shm, st, a); break;
+    case SM_DETAIL1: hipLaunchKernelGGL((k_band<SM_DETAIL1, kKR>), grid, block, shm, st, a); break;
+    case DB_ANALYSIS: hipLaunchKernelGGL((k_band<DB_ANALYSIS, kKR>), grid, block, shm, st, a); break;
+    case DB_ADJOINT: hipLaunchKernelGGL((k_band<DB_ADJOINT, kKR>), grid, block, shm, st, a); break;
     default: set_error("atrous: bad mode"); return MUFFIN_EINVAL;
   }
   MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+int atrous_init_attrs() {
+  const int shm = (int)(sizeof(float) * 2 * kKR * 1024);
+  MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_SMOOTH, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_SUBADD, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_DETAIL, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_DETAIL_ABS, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_DETAIL1, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ANALYSIS, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ADJOINT, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   return MUFFIN_OK;
 }
 
@@ -209,15 +337,6 @@ int launch_pointwise(int mode, int N, int nch, PlaneRef A, PlaneRef E, PlaneOut 
     default: set_error("pointwise: bad mode"); return MUFFIN_EINVAL;
   }
   MF_HIP(hipGetLastError());
-  return MUFFIN_OK;
-}
-
-int atrous_init_attrs() {
-  const int shm = 144 * 1024;  // leaves room for the static LDS of the reduction variants
-  MF_HIP(hipFuncSetAttribute((const void*)k_atrous<AT_SMOOTH>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
-  MF_HIP(hipFuncSetAttribute((const void*)k_atrous<AT_SUBADD>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
-  MF_HIP(hipFuncSetAttribute((const void*)k_atrous<AT_DETAIL>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
-  MF_HIP(hipFuncSetAttribute((const void*)k_atrous<AT_DETAIL_ABS>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   return MUFFIN_OK;
 }
 

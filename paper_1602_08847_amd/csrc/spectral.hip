@@ -4,11 +4,13 @@
 //   d   = 2 x~ - x
 //   V   <- rho sat(V + sigma mu_l d W) + (1 - rho) V      (spectral dual step, DCT-II)
 //   x   <- rho x~ + (1 - rho) x
-// A workgroup owns 32 pixels across all L channels: it stages their V spectra and their d spectra
-// in LDS ([L][32] each), reads x and q once, and writes x, d and V once.  The length-L cosine
-// transforms are dense products with a cosine table, each thread accumulating four outputs so
-// every LDS read feeds four FMAs.
-#include "common.h"
+// A workgroup owns a run of pixels across all L channels; it reads x, q and V once and writes x, d
+// and V once.  When L has an FFT plan the two cosine transforms go through an L-point complex
+// FFT in LDS (reordering of the spectrum into even samples followed by reversed odd samples,
+// then a quarter-sample phase factor, Makhoul 1980), two pixels packed per transform as real and
+// imaginary parts.  Other L use dense products with a cosine table, each thread accumulating
+// four outputs so every LDS read feeds four FMAs.
+#include "fft_core.h"
 
 namespace mf {
 
@@ -86,7 +88,147 @@ __global__ void __launch_bounds__(256) k_spectral_step(SpectralArgs a) {
   }
 }
 
+
+// ------------------------------------------------------------------ FFT-based fused step
+// Orthonormal DCT-II of a length-L spectrum x: v = (x_0, x_2, ..., x_{L-2}, x_{L-1}, ..., x_3, x_1),
+// X_k = s_k Re(exp(-i pi k / 2L) FFT(v)_k).  Its inverse: Y_k = s_k h_k X_k (h_0 = 1, h_k = 1/2),
+// V_k = exp(i pi k / 2L) (Y_k - i Y_{L-k}) (Y_L = 0), v = unnormalised inverse FFT of V, and x is
+// read back from v with the same reordering.
+template <int L>
+struct SpecGeom {
+  static constexpr int T = Plan<L>::T;
+  static constexpr int NF = (256 / T) > 0 ? (256 / T) : 1;  // transforms (pixel pairs) per block
+  static constexpr int PXB = 2 * NF;                        // pixels per block
+  static constexpr int LS = lstride<L>();
+  static constexpr size_t shm = sizeof(float) * L * PXB + sizeof(float2) * NF * LS;
+};
+
+__device__ __forceinline__ int dct_slot(int l, int L) { return (l & 1) ? L - 1 - (l >> 1) : (l >> 1); }
+
+template <int L>
+__global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
+  using G = SpecGeom<L>;
+  constexpr int T = G::T, NF = G::NF, PXB = G::PXB, LS = G::LS;
+  constexpr int NT = NF * T;
+  extern __shared__ float sm[];
+  float* Vs = sm;                                   // [L][PXB] dual spectra
+  float2* buf = reinterpret_cast<float2*>(sm + L * PXB);  // [NF][LS] transforms
+  const long long npix = a.npix;
+  const long long pix0 = (long long)blockIdx.x * PXB;
+  for (int idx = threadIdx.x; idx < L * PXB; idx += NT) {
+    const int l = idx / PXB, p = idx - l * PXB;
+    const long long q = pix0 + p;
+    Vs[idx] = (q < npix) ? a.V[(long long)l * npix + q] : 0.f;
+  }
+  __syncthreads();
+  const int f = threadIdx.x / T, t = threadIdx.x - f * T;
+  float2* fb = buf + f * LS;
+  {
+    // t = mu_l * DCT-III(V): build the spectra of pixels 2f and 2f+1 packed as one complex array
+    const float c0 = a.mu_l * sqrtf(1.f / L), c1 = a.mu_l * rsqrtf(2.f * L);
+    const float* va = Vs + 2 * f;
+    for (int k = t; k < L; k += T) {
+      const float sk = k ? c1 : c0;
+      const float ya = va[k * PXB] * sk, yb = va[k * PXB + 1] * sk;
+      const float ra = k ? va[(L - k) * PXB] * c1 : 0.f, rb = k ? va[(L - k) * PXB + 1] * c1 : 0.f;
+      const float2 e = a.csL[k];
+      const float2 Va = make_float2(ya * e.x + ra * e.y, ya * e.y - ra * e.x);
+      const float2 Vb = make_float2(yb * e.x + rb * e.y, yb * e.y - rb * e.x);
+      fb[lpad(k)] = make_float2(Va.x - Vb.y, Va.y + Vb.x);
+    }
+  }
+  __syncthreads();
+  fft_lds<L, true>(fb, t, true, a.twL);
+  // primal step per (channel, pixel); d goes back into the same slot for the forward transform
+  for (int idx = threadIdx.x; idx < L * PXB; idx += NT) {
+    const int l = idx / PXB, p = idx - l * PXB;
+    const long long q = pix0 + p;
+    float* slot = reinterpret_cast<float*>(buf + (p >> 1) * LS + lpad(dct_slot(l, L))) + (p & 1);
+    const float tv = *slot;
+    float d = 0.f;
+    if (q < npix) {
+      const long long o = (long long)l * npix + q;
+      const float x = a.X[o];
+      const float xt = fmaxf(x - a.tau * (a.Q[o] + tv), 0.f);
+      d = 2.f * xt - x;
+      a.D[o] = d;
+      a.X[o] = a.rho * xt + (1.f - a.rho) * x;
+    }
+    *slot = d;
+  }
+  __syncthreads();
+  fft_lds<L, false>(fb, t, true, a.twL);
+  // spectral dual step per (coefficient, pixel)
+  const float s0 = a.smu_l * sqrtf(1.f / L), s1 = a.smu_l * sqrtf(2.f / L);
+  for (int idx = threadIdx.x; idx < L * PXB; idx += NT) {
+    const int k = idx / PXB, p = idx - k * PXB;
+    const long long q = pix0 + p;
+    const float2* fp = buf + (p >> 1) * LS;
+    const float2 zk = fp[lpad(k)];
+    const float2 zm = cconj(fp[lpad(k ? L - k : 0)]);
+    float2 v;
+    if ((p & 1) == 0) {
+      v = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+    } else {
+      v = make_float2(0.5f * (zk.y - zm.y), -0.5f * (zk.x - zm.x));
+    }
+    const float2 e = a.csL[k];
+    const float c = (v.x * e.x + v.y * e.y) * (k ? s1 : s0);
+    if (q < npix) {
+      const float vo = Vs[k * PXB + p];
+      a.V[(long long)k * npix + q] = a.rho * satf_s(vo + c) + (1.f - a.rho) * vo;
+    }
+  }
+}
+
+template <int L>
+static int spectral_fft_n(const SpectralArgs& a, hipStream_t st) {
+  using G = SpecGeom<L>;
+  const long long nblk = (a.npix + G::PXB - 1) / G::PXB;
+  hipLaunchKernelGGL(k_spectral_fft<L>, dim3((unsigned)nblk), dim3(G::NF * G::T), G::shm, st, a);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+template <int L>
+static int spectral_fft_attr() {
+  MF_HIP(hipFuncSetAttribute((const void*)k_spectral_fft<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)SpecGeom<L>::shm));
+  return MUFFIN_OK;
+}
+
+bool spectral_has_fft(int L) {
+  switch (L) {
+    case 8: case 16: case 32: case 64: case 128: case 256: case 512:
+    case 12: case 24: case 48: case 96: case 192: case 384:
+      return true;
+    default:
+      return false;
+  }
+}
+
+#define MF_SPEC_DISPATCH(L, fn, ...)        \
+  switch (L) {                              \
+    case 8: return fn<8>(__VA_ARGS__);      \
+    case 16: return fn<16>(__VA_ARGS__);    \
+    case 32: return fn<32>(__VA_ARGS__);    \
+    case 64: return fn<64>(__VA_ARGS__);    \
+    case 128: return fn<128>(__VA_ARGS__);  \
+    case 256: return fn<256>(__VA_ARGS__);  \
+    case 512: return fn<512>(__VA_ARGS__);  \
+    case 12: return fn<12>(__VA_ARGS__);    \
+    case 24: return fn<24>(__VA_ARGS__);    \
+    case 48: return fn<48>(__VA_ARGS__);    \
+    case 96: return fn<96>(__VA_ARGS__);    \
+    case 192: return fn<192>(__VA_ARGS__);  \
+    case 384: return fn<384>(__VA_ARGS__);  \
+    default: break;                         \
+  }
+
 int launch_spectral_step(const SpectralArgs& a, hipStream_t st) {
+  if (a.use_fft) {
+    MF_SPEC_DISPATCH(a.L, spectral_fft_n, a, st)
+  }
   const size_t shm = sizeof(float) * 2 * (size_t)a.L * PX;
   const long long nblk = (a.npix + PX - 1) / PX;
   hipLaunchKernelGGL(k_spectral_step, dim3((unsigned)nblk), dim3(256), shm, st, a);
@@ -163,11 +305,19 @@ int launch_dct_abs(const float* in, const float* WT, long long npix, int L, doub
   return MUFFIN_OK;
 }
 
-int spectral_init_attrs(int L) {
+int spectral_direct_attrs(int L) {
   const int shm = (int)(sizeof(float) * 2 * (size_t)L * PX);
   MF_HIP(hipFuncSetAttribute((const void*)k_spectral_step, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_pix_matvec<false>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_pix_matvec<true>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  return MUFFIN_OK;
+}
+
+int spectral_init_attrs(int L) {
+  MF_TRY(spectral_direct_attrs(L));
+  if (spectral_has_fft(L)) {
+    MF_SPEC_DISPATCH(L, spectral_fft_attr)
+  }
   return MUFFIN_OK;
 }
 

@@ -69,9 +69,10 @@ def test_closed_form_positive_part(lib):
     Y = f32(np.random.default_rng(6).normal(size=(3, 16, 16)))
     with lib.Muffin(Y, delta_psf(3, 16), J=2, mu_s=0.0, mu_lambda=0.0) as m:
         m.step(1500)
-        # tau = 1.98 makes x <- -0.98 x + 1.98 y a 0.98-contraction: its FP32 fixed point sits
-        # within about 1.98 / 0.02 = 100 ulp (1.2e-5 relative) of (y)_+
-        np.testing.assert_allclose(m.get_x().cpu().numpy(), np.maximum(Y, 0), rtol=3e-5, atol=1e-6)
+        # tau = 1.98 makes x <- -0.98 x + 1.98 y a 0.98-contraction, which amplifies the FFT
+        # rounding of H^T H x (about 1e-7 max|x|, spread over every pixel) by 1.98 / 0.02 = 100
+        np.testing.assert_allclose(m.get_x().cpu().numpy(), np.maximum(Y, 0), rtol=0,
+                                   atol=3e-5 * np.abs(Y).max())
 
 
 def test_closed_form_single_channel_soft_threshold(lib):
