@@ -41,6 +41,9 @@ struct muffin_ctx {
   hipStream_t user = nullptr, st = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, e0 = nullptr, e1 = nullptr;
   hipEvent_t ph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t kev[16] = {};  // per-launch timing marks (profiling only)
+  double kms_an = 0, kms_ad = 0;  // summed per-launch times of the last profiled iteration
+  int kn_an = 0, kn_ad = 0;
   float *X = nullptr, *U = nullptr, *V = nullptr, *D = nullptr, *Q = nullptr, *B = nullptr, *Y = nullptr;
   float *cA = nullptr, *cB = nullptr, *cT = nullptr;
   float2* S = nullptr;
@@ -110,7 +113,8 @@ int validate(const muffin_params* p) {
 
 // ---------------------------------------------------------------- phases
 // Spatial adjoint of omega-weighted U; returns the buffer holding a = W_s^dagger (omega u).
-int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omega_c, const float** result) {
+int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omega_c, const float** result,
+                    bool timed = false) {
   const int J = c->J;
   const long long np = c->npix;
   const float* a = Ubase + (long long)J * np;  // coarse plane
@@ -128,8 +132,10 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omeg
     const float* uj = Ubase + (long long)j * np;
     float* dst = bufs[nb];
     if (c->gen == 2 && atrous_double_fits(c->N, j, nullptr, nullptr)) {
+      if (timed) MF_HIP(hipEventRecord(c->kev[2 * j], c->st));
       MF_TRY(launch_atrous(DB_ADJOINT, c->N, c->L, j, pref(uj, ucs), pref(a, acs), PlaneRef{}, pout(dst, np),
                            PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
+      if (timed) MF_HIP(hipEventRecord(c->kev[2 * j + 1], c->st));
     } else {
       const float* sub = uj;
       long long scs = ucs;
@@ -151,7 +157,7 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omeg
 }
 
 // Analysis of the channel images in (stride np) fused with the spatial dual step on U.
-int enqueue_dual_update(muffin_ctx* c, const float* in) {
+int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
   const int J = c->J;
   const long long np = c->npix, ucs = (long long)(J + 1) * np;
   const float coef = (float)(c->sigma * c->p.mu_s);
@@ -165,8 +171,10 @@ int enqueue_dual_update(muffin_ctx* c, const float* in) {
       MF_TRY(launch_atrous(SM_DETAIL1, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
                            pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
     } else if (atrous_double_fits(c->N, j, nullptr, nullptr)) {
+      if (timed) MF_HIP(hipEventRecord(c->kev[2 * j], c->st));
       MF_TRY(launch_atrous(DB_ANALYSIS, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
                            pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
+      if (timed) MF_HIP(hipEventRecord(c->kev[2 * j + 1], c->st));
     } else {
       MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np),
                            PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
@@ -208,17 +216,19 @@ int enqueue_spectral(muffin_ctx* c) {
   return launch_spectral_step(a, c->st);
 }
 
-int enqueue_iteration(muffin_ctx* c, hipEvent_t* marks) {
+// With marks, phase boundaries are recorded in marks[0..4] and, for the second-generation
+// transform, each scale's fused adjoint (marks pass 1) or analysis launch is bracketed in kev.
+int enqueue_iteration(muffin_ctx* c, hipEvent_t* marks, int timed_family = 0) {
   const long long ucs = (long long)(c->J + 1) * c->npix;
   if (marks) MF_HIP(hipEventRecord(marks[0], c->st));
   const float* s = nullptr;
-  MF_TRY(enqueue_adjoint(c, c->U, ucs, c->omega_c, &s));
+  MF_TRY(enqueue_adjoint(c, c->U, ucs, c->omega_c, &s, timed_family == 1));
   if (marks) MF_HIP(hipEventRecord(marks[1], c->st));
   MF_TRY(enqueue_gradient(c, c->X, c->Q, s, (float)c->p.mu_s));
   if (marks) MF_HIP(hipEventRecord(marks[2], c->st));
   MF_TRY(enqueue_spectral(c));
   if (marks) MF_HIP(hipEventRecord(marks[3], c->st));
-  MF_TRY(enqueue_dual_update(c, c->D));
+  MF_TRY(enqueue_dual_update(c, c->D, timed_family == 2));
   if (marks) MF_HIP(hipEventRecord(marks[4], c->st));
   return MUFFIN_OK;
 }
@@ -271,6 +281,8 @@ void destroy(muffin_ctx* c) {
   hipEvent_t evs[] = {c->ev_in, c->ev_out, c->e0, c->e1, c->ph[0], c->ph[1], c->ph[2], c->ph[3], c->ph[4]};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->kev)
+    if (e) (void)hipEventDestroy(e);
   if (c->st) (void)hipStreamDestroy(c->st);
   delete c;
 }
@@ -306,6 +318,7 @@ int init_impl(muffin_ctx* c, const muffin_params* p, const float* dirty, const f
   for (hipEvent_t* e : {&c->ev_in, &c->ev_out}) MF_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   for (hipEvent_t* e : {&c->e0, &c->e1, &c->ph[0], &c->ph[1], &c->ph[2], &c->ph[3], &c->ph[4]})
     MF_HIP(hipEventCreate(e));
+  for (auto& e : c->kev) MF_HIP(hipEventCreate(&e));
   MF_TRY(fft_init_attrs(c->N));
   MF_TRY(atrous_init_attrs());
   MF_TRY(spectral_init_attrs(c->L));
@@ -504,8 +517,11 @@ int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[8]) {
   if (!c || !ms || n_iter < 1) return set_error("bad arguments"), MUFFIN_EINVAL;
   for (int i = 0; i < 8; ++i) ms[i] = 0;
   StreamScope scope(c);
+  int n_ad = 0, n_an = 0;
   for (int it = 0; it < n_iter; ++it) {
-    MF_TRY(enqueue_iteration(c, c->ph));
+    // alternate which kernel family is bracketed so the marks do not pile up in one iteration
+    const int fam = 1 + (it & 1);
+    MF_TRY(enqueue_iteration(c, c->ph, c->gen == 2 ? fam : 0));
     MF_HIP(hipEventSynchronize(c->ph[4]));
     float t[4];
     for (int k = 0; k < 4; ++k) MF_HIP(hipEventElapsedTime(&t[k], c->ph[k], c->ph[k + 1]));
@@ -513,7 +529,23 @@ int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[8]) {
       ms[k + 1] += t[k] / n_iter;
       ms[0] += t[k] / n_iter;
     }
+    if (c->gen == 2) {
+      for (int j = 0; j < c->J; ++j) {
+        if (!atrous_double_fits(c->N, j, nullptr, nullptr)) continue;
+        float tk = 0.f;
+        MF_HIP(hipEventElapsedTime(&tk, c->kev[2 * j], c->kev[2 * j + 1]));
+        if (fam == 1) {
+          ms[6] += tk;
+          ++n_ad;
+        } else {
+          ms[5] += tk;
+          ++n_an;
+        }
+      }
+    }
   }
+  if (n_an) ms[5] /= n_an;
+  if (n_ad) ms[6] /= n_ad;
   c->iter += n_iter;
   return MUFFIN_OK;
 }

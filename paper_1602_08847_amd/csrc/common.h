@@ -29,6 +29,15 @@ void set_error(const std::string& msg);
     if (rc_ != MUFFIN_OK) return rc_; \
   } while (0)
 
+// Workgroup barrier ordering LDS only: unlike __syncthreads() it does not wait for this wave's
+// outstanding global loads and stores, so prefetched rows stay in flight across it.  Use it only
+// where the data exchanged through the barrier lives in LDS.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------------ complex helpers
 __host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, f
       buf[lpad(i)] = make_float2(pa[c], pb[c]);
     }
   }
-  __syncthreads();
+  lds_barrier();
   fft_lds<N, false>(buf, t, active, tw);
   if (active) {
     float2* sa = S + (ch * N + r0) * (long long)pitch;
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(512) k_cols(float2* __restrict__ S, int pitch,
     const int r = idx / CB, c = idx % CB;
     lds[c * LS + lpad(r)] = Sc[(long long)r * pitch + c0 + c];
   }
-  __syncthreads();
+  lds_barrier();
   const int f = threadIdx.x / T, t = threadIdx.x % T;
   float2* buf = lds + f * LS;
   fft_lds<N, false>(buf, t, true, tw);
@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(512) k_cols(float2* __restrict__ S, int pitch,
       buf[lpad(r)] = v;
     }
     // fft_lds begins with reads of this thread group's own entries only after a barrier
-    __syncthreads();
+    lds_barrier();
     fft_lds<N, true>(buf, t, true, tw);
     for (int idx = threadIdx.x; idx < N * CB; idx += nthr) {
       const int r = idx / CB, c = idx % CB;
@@ -123,7 +123,7 @@ __device__ __forceinline__ double block_sum_d(double v) {
   __shared__ double red[16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (lane == 0) red[w] = v;
-  __syncthreads();
+  lds_barrier();
   double s = 0.0;
   if (threadIdx.x == 0) {
     const int nw = (blockDim.x + 63) >> 6;
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
       buf[lpad(k)] = make_float2(a.x - bb.y, a.y + bb.x);
     }
   }
-  __syncthreads();
+  lds_barrier();
   fft_lds<N, true>(buf, t, active, tw);
   double acc = 0.0;
   if (active) {

@@ -180,7 +180,7 @@ __device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const f
         for (int r = 0; r < R; ++r) v[i][r] = buf[lpad(b + r * NB)];
       }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int b = t + i * T;
@@ -200,7 +200,7 @@ __device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const f
         for (int r = 0; r < R; ++r) buf[lpad(base + r * Ns)] = v[i][r];
       }
     }
-    __syncthreads();
+    lds_barrier();
     fft_lds<N, INV, S + 1>(buf, t, active, tw);
   }
 }

@@ -62,10 +62,18 @@ __device__ __forceinline__ float b3(float c0, float c1, float c2, float c3, floa
 
 // Band kernel: one workgroup of N threads owns rows [y0, y0 + TY) of one channel, thread x owns
 // column x.  Rows are visited residue class by residue class modulo s, so the vertical 5-tap
-// filter is a sliding window of five registers fed by one coalesced row load per step.  KR
-// vertical results at a time go through LDS for the horizontal taps (x +- s, x +- 2s, periodic).
-// Double-smoothing modes chain a second window over the first stage's output in the same class,
-// two steps behind, which extends the first stage by 2s rows on each side of the band.
+// filter is a sliding window of five registers fed by one coalesced row load per step (the first
+// four steps of a class only fill the window).  Steps are grouped in rounds of KR; the KR vertical
+// results of a round go through LDS for the horizontal taps (x +- s, x +- 2s, periodic).  Every
+// global load of the next round (input rows and epilogue operands) is issued before the current
+// round is computed, so memory latency overlaps the LDS passes and barriers.  Double-smoothing
+// modes chain a second window over the first stage's output in the same class, two steps behind,
+// which extends the first stage by 2s rows on each side of the band.
+template <int KR>
+struct BandPre {
+  float a[KR], b[KR], e[KR], u[KR];
+};
+
 template <int MODE, int KR>
 __global__ void __launch_bounds__(1024) k_band(AtrousArgs a) {
   constexpr bool DBL = (MODE == DB_ANALYSIS || MODE == DB_ADJOINT);
@@ -80,116 +88,154 @@ __global__ void __launch_bounds__(1024) k_band(AtrousArgs a) {
   const int E1 = DBL ? 2 * s : 0;
   const float* __restrict__ A = a.A.p + ch * a.A.cs;
   const float* __restrict__ B = (MODE == SM_SUBADD || MODE == DB_ADJOINT) ? a.B.p + ch * a.B.cs : nullptr;
+  const float* __restrict__ E =
+      (MODE == SM_SUBADD || MODE == SM_DETAIL || MODE == SM_DETAIL_ABS) ? a.E.p + ch * a.E.cs : nullptr;
+  float* __restrict__ O = a.out.p ? a.out.p + ch * a.out.cs : nullptr;
+  float* __restrict__ O2 = a.out2.p ? a.out2.p + ch * a.out2.cs : nullptr;
   const int xm2 = wrap_idx(x - 2 * s, N, 1), xm1 = wrap_idx(x - s, N, 1);
   const int xp1 = wrap_idx(x + s, N, 1), xp2 = wrap_idx(x + 2 * s, N, 1);
-  auto loadA = [&](int y) -> float {
-    const long long g = (long long)wrap_idx(y, N, small) * N + x;
-    float v = A[g];
-    if (MODE == SM_SUBADD) v -= B[g];
-    return v;
+  // class r: stage-1 outputs at rows first(r) + m s, m < M1(r); load steps t = m + 4
+  auto nsteps = [&](int r) -> int {
+    const int M1 = (TY + 2 * E1 - r + s - 1) / s;
+    return M1 > 0 ? M1 + 4 : 0;
+  };
+  auto load_round = [&](BandPre<KR>& P, int r, int t0) {
+    const int first = y0 + r - E1, ns = nsteps(r);
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) {
+      const int t = t0 + kk;
+      if (t < ns) {
+        // step t brings row y_m + 2s (m = t - 4) into the window
+        const long long g = (long long)wrap_idx(first + (t - 2) * s, N, small) * N + x;
+        P.a[kk] = A[g];
+        if constexpr (MODE == SM_SUBADD) P.b[kk] = B[g];
+        const int m = t - 4;
+        if (m >= 0) {
+          const int y = first + m * s;
+          if constexpr (MODE == SM_SUBADD || MODE == SM_DETAIL || MODE == SM_DETAIL_ABS)
+            P.e[kk] = E[(long long)y * N + x];
+          if constexpr (MODE == SM_DETAIL || MODE == SM_DETAIL1) P.u[kk] = O[(long long)y * N + x];
+          if constexpr (MODE == DB_ADJOINT) P.e[kk] = B[(long long)wrap_idx(y, N, small) * N + x];
+          if constexpr (MODE == DB_ANALYSIS)
+            if (m >= 4) P.u[kk] = O[(long long)(y - 2 * s) * N + x];
+        }
+      }
+    }
   };
   double acc = 0.0;
   int round = 0;
-  for (int r = 0; r < s; ++r) {
-    const int first = y0 + r - E1;                 // first stage-1 output row of this class
-    const int M1 = (TY + 2 * E1 - r + s - 1) / s;  // stage-1 steps: first + m s < y0 + TY + E1
-    if (M1 <= 0) continue;
-    float w0 = loadA(first - 2 * s), w1 = loadA(first - s), w2 = loadA(first), w3 = loadA(first + s);
-    float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
-    for (int m0 = 0; m0 < M1; m0 += KR) {
-      float pv[KR], cen1[KR], cen2[KR];
+  int r = 0;
+  while (r < s && nsteps(r) == 0) ++r;
+  int t0 = 0;
+  BandPre<KR> cur, nxt;
+  if (r < s) load_round(cur, r, t0);
+  float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
+  float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+  while (r < s) {
+    const int ns = nsteps(r), first = y0 + r - E1;
+    int rn = r, tn = t0 + KR;
+    if (tn >= ns) {
+      rn = r + 1;
+      tn = 0;
+      while (rn < s && nsteps(rn) == 0) ++rn;
+    }
+    if (rn < s) load_round(nxt, rn, tn);
+    float pv[KR], cen1[KR], cen2[KR];
 #pragma unroll
-      for (int kk = 0; kk < KR; ++kk) {
-        const int m = m0 + kk;
-        pv[kk] = 0.f;
-        cen1[kk] = 0.f;
-        cen2[kk] = 0.f;
-        if (m < M1) {
-          const float w4 = loadA(first + m * s + 2 * s);
+    for (int kk = 0; kk < KR; ++kk) {
+      const int t = t0 + kk;
+      pv[kk] = 0.f;
+      cen1[kk] = 0.f;
+      cen2[kk] = 0.f;
+      if (t < ns) {
+        float w4 = cur.a[kk];
+        if constexpr (MODE == SM_SUBADD) w4 -= cur.b[kk];
+        if (t >= 4) {
           pv[kk] = b3(w0, w1, w2, w3, w4);
           cen1[kk] = w2;
           cen2[kk] = w0;
-          w0 = w1;
-          w1 = w2;
-          w2 = w3;
-          w3 = w4;
         }
+        w0 = w1;
+        w1 = w2;
+        w2 = w3;
+        w3 = w4;
       }
-      float* L1 = buf1 + (DBL ? 0 : (round & 1) * KR * N);
+    }
+    float* L1 = buf1 + (DBL ? 0 : (round & 1) * KR * N);
 #pragma unroll
-      for (int kk = 0; kk < KR; ++kk) L1[kk * N + x] = pv[kk];
-      __syncthreads();
-      float P[KR];
+    for (int kk = 0; kk < KR; ++kk) L1[kk * N + x] = pv[kk];
+    lds_barrier();
+    float P[KR];
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) {
+      const float* row = L1 + kk * N;
+      P[kk] = b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]);
+    }
+    if constexpr (!DBL) {
 #pragma unroll
       for (int kk = 0; kk < KR; ++kk) {
-        const float* row = L1 + kk * N;
-        P[kk] = b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]);
+        const int m = t0 + kk - 4;
+        if (m < 0 || t0 + kk >= ns) continue;
+        const long long g = (long long)(first + m * s) * N + x;  // inside the band
+        const float v = P[kk];
+        if constexpr (MODE == SM_SMOOTH) {
+          O[g] = v;
+        } else if constexpr (MODE == SM_SUBADD) {
+          O[g] = cur.e[kk] + v;
+        } else if constexpr (MODE == SM_DETAIL || MODE == SM_DETAIL1) {
+          const float e = (MODE == SM_DETAIL) ? cur.e[kk] : cen1[kk];
+          const float w = e - v;
+          const float u = cur.u[kk];
+          O[g] = a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u;
+          if (MODE == SM_DETAIL1) O2[g] = v;
+        } else {
+          acc += fabs((double)cur.e[kk] - (double)v);
+        }
       }
-      if constexpr (!DBL) {
+    } else {
+      float rv[KR];
 #pragma unroll
-        for (int kk = 0; kk < KR; ++kk) {
-          const int m = m0 + kk;
-          if (m >= M1) continue;
-          const long long g = (long long)(first + m * s) * N + x;  // inside the band, no wrap
-          const float v = P[kk];
-          if constexpr (MODE == SM_SMOOTH) {
-            a.out.p[ch * a.out.cs + g] = v;
-          } else if constexpr (MODE == SM_SUBADD) {
-            a.out.p[ch * a.out.cs + g] = a.E.p[ch * a.E.cs + g] + v;
-          } else if constexpr (MODE == SM_DETAIL || MODE == SM_DETAIL1) {
-            const float e = (MODE == SM_DETAIL) ? a.E.p[ch * a.E.cs + g] : cen1[kk];
-            const float w = e - v;
-            float* up = a.out.p + ch * a.out.cs + g;
-            const float u = *up;
-            *up = a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u;
-            if (MODE == SM_DETAIL1) a.out2.p[ch * a.out2.cs + g] = v;
-          } else {
-            acc += fabs((double)a.E.p[ch * a.E.cs + g] - (double)v);
-          }
-        }
-      } else {
-        float rv[KR];
-#pragma unroll
-        for (int kk = 0; kk < KR; ++kk) {
-          const int m = m0 + kk;
-          rv[kk] = 0.f;
-          if (m < M1) {
-            const int y = first + m * s;
-            float qin = P[kk];
-            if constexpr (MODE == DB_ADJOINT) {
-              qin = B[(long long)wrap_idx(y, N, small) * N + x] - qin;
-            } else {
-              if (y >= y0 && y < y0 + TY) a.out2.p[ch * a.out2.cs + (long long)y * N + x] = qin;
-            }
-            if (m >= 4) rv[kk] = b3(q0, q1, q2, q3, qin);
-            q0 = q1;
-            q1 = q2;
-            q2 = q3;
-            q3 = qin;
-          }
-        }
-#pragma unroll
-        for (int kk = 0; kk < KR; ++kk) buf2[kk * N + x] = rv[kk];
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < KR; ++kk) {
-          const int m = m0 + kk;
-          if (m >= M1 || m < 4) continue;
-          const float* row = buf2 + kk * N;
-          const float R = b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]);
-          const long long g = (long long)(first + m * s - 2 * s) * N + x;  // stage-2 row, inside the band
+      for (int kk = 0; kk < KR; ++kk) {
+        const int m = t0 + kk - 4;
+        rv[kk] = 0.f;
+        if (m >= 0 && t0 + kk < ns) {
+          const int y = first + m * s;
+          float qin = P[kk];
           if constexpr (MODE == DB_ADJOINT) {
-            a.out.p[ch * a.out.cs + g] = cen2[kk] + R;
+            qin = cur.e[kk] - qin;
           } else {
-            const float w = cen2[kk] - R;
-            float* up = a.out.p + ch * a.out.cs + g;
-            const float u = *up;
-            *up = a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u;
+            if (y >= y0 && y < y0 + TY) O2[(long long)y * N + x] = qin;
           }
+          if (m >= 4) rv[kk] = b3(q0, q1, q2, q3, qin);
+          q0 = q1;
+          q1 = q2;
+          q2 = q3;
+          q3 = qin;
         }
       }
-      ++round;
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) buf2[kk * N + x] = rv[kk];
+      lds_barrier();
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const int m = t0 + kk - 4;
+        if (m < 4 || t0 + kk >= ns) continue;
+        const float* row = buf2 + kk * N;
+        const float R = b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]);
+        const long long g = (long long)(first + m * s - 2 * s) * N + x;  // stage-2 row, inside the band
+        if constexpr (MODE == DB_ADJOINT) {
+          O[g] = cen2[kk] + R;
+        } else {
+          const float w = cen2[kk] - R;
+          const float u = cur.u[kk];
+          O[g] = a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u;
+        }
+      }
     }
+    ++round;
+    cur = nxt;
+    r = rn;
+    t0 = tn;
   }
   if constexpr (MODE == SM_DETAIL_ABS) {
     const double tot = block_sum_atrous(acc);
@@ -197,7 +243,8 @@ __global__ void __launch_bounds__(1024) k_band(AtrousArgs a) {
   }
 }
 
-constexpr int kKR = 8;
+constexpr int kKR = 8;   // rows per round, single-smoothing modes
+constexpr int kKR2 = 4;  // rows per round, double-smoothing modes (keeps them within 128 VGPRs)
 
 static int band_rows(int N, int j) {
   // about 32 s rows per band (band edges cost 4s or 8s extra row loads per class), at least 64
@@ -252,8 +299,8 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
     case SM_DETAIL: hipLaunchKernelGGL((k_band<SM_DETAIL, kKR>), grid, block, shm, st, a); break;
     case SM_DETAIL_ABS: hipLaunchKernelGGL((k_band<SM_DETAIL_ABS, kKR>), grid, block, shm, st, a); break;
     case SM_DETAIL1: hipLaunchKernelGGL((k_band<SM_DETAIL1, kKR>), grid, block, shm, st, a); break;
-    case DB_ANALYSIS: hipLaunchKernelGGL((k_band<DB_ANALYSIS, kKR>), grid, block, shm, st, a); break;
-    case DB_ADJOINT: hipLaunchKernelGGL((k_band<DB_ADJOINT, kKR>), grid, block, shm, st, a); break;
+    case DB_ANALYSIS: hipLaunchKernelGGL((k_band<DB_ANALYSIS, kKR2>), grid, block, shm, st, a); break;
+    case DB_ADJOINT: hipLaunchKernelGGL((k_band<DB_ADJOINT, kKR2>), grid, block, shm, st, a); break;
     default: set_error("atrous: bad mode"); return MUFFIN_EINVAL;
   }
   MF_HIP(hipGetLastError());
@@ -268,8 +315,8 @@ int atrous_init_attrs() {
   MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_DETAIL_ABS, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_DETAIL1, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
-  MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ANALYSIS, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
-  MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ADJOINT, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ANALYSIS, kKR2>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ADJOINT, kKR2>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   return MUFFIN_OK;
 }
 

@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(256) k_spectral_step(SpectralArgs a) {
     const long long q = pix0 + pp;
     Vs[idx] = (q < a.npix) ? a.V[(long long)l * a.npix + q] : 0.f;
   }
-  __syncthreads();
+  lds_barrier();
   // primal step, channel rows l = g + 8 i (four per pass)
   for (int lb = g; lb < L; lb += 32) {
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_spectral_step(SpectralArgs a) {
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
   // spectral dual step, coefficient rows k = g + 8 i
   for (int kb = g; kb < L; kb += 32) {
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     const long long q = pix0 + p;
     Vs[idx] = (q < npix) ? a.V[(long long)l * npix + q] : 0.f;
   }
-  __syncthreads();
+  lds_barrier();
   const int f = threadIdx.x / T, t = threadIdx.x - f * T;
   float2* fb = buf + f * LS;
   {
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
       fb[lpad(k)] = make_float2(Va.x - Vb.y, Va.y + Vb.x);
     }
   }
-  __syncthreads();
+  lds_barrier();
   fft_lds<L, true>(fb, t, true, a.twL);
   // primal step per (channel, pixel); d goes back into the same slot for the forward transform
   for (int idx = threadIdx.x; idx < L * PXB; idx += NT) {
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     }
     *slot = d;
   }
-  __syncthreads();
+  lds_barrier();
   fft_lds<L, false>(fb, t, true, a.twL);
   // spectral dual step per (coefficient, pixel)
   const float s0 = a.smu_l * sqrtf(1.f / L), s1 = a.smu_l * sqrtf(2.f / L);
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(256) k_pix_matvec(const float* __restrict__ in
     const long long q = pix0 + pp;
     Is[idx] = (q < npix) ? in[(long long)l * npix + q] : 0.f;
   }
-  __syncthreads();
+  lds_barrier();
   double acc_abs = 0.0;
   for (int ib = g; ib < L; ib += 32) {
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(256) k_pix_matvec(const float* __restrict__ in
     for (int off = 32; off > 0; off >>= 1) acc_abs += __shfl_down(acc_abs, off, 64);
     __shared__ double red[4];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc_abs;
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
   }
 }
