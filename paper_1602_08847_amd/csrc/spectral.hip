@@ -99,8 +99,13 @@ struct SpecGeom {
   static constexpr int T = Plan<L>::T;
   static constexpr int NF = (256 / T) > 0 ? (256 / T) : 1;  // transforms (pixel pairs) per block
   static constexpr int PXB = 2 * NF;                        // pixels per block
+  static constexpr int VS = PXB + 1;  // odd row stride of the staged dual spectra: column reads
+                                      // (one coefficient per lane) fall in distinct banks
+  // odd transform stride: the per-pixel steps read one entry of each of 16 transforms at once
   static constexpr int LS = lstride<L>();
-  static constexpr size_t shm = sizeof(float) * L * PXB + sizeof(float2) * NF * LS;
+  static constexpr int NT = NF * T;                       // threads per block
+  static constexpr int PER = (L * PXB + NT - 1) / NT;     // (channel, pixel) elements per thread
+  static constexpr size_t shm = sizeof(float) * ((L * VS + 1) & ~1) + sizeof(float2) * NF * LS;
 };
 
 __device__ __forceinline__ int dct_slot(int l, int L) { return (l & 1) ? L - 1 - (l >> 1) : (l >> 1); }
@@ -111,14 +116,37 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   constexpr int T = G::T, NF = G::NF, PXB = G::PXB, LS = G::LS;
   constexpr int NT = NF * T;
   extern __shared__ float sm[];
-  float* Vs = sm;                                   // [L][PXB] dual spectra
-  float2* buf = reinterpret_cast<float2*>(sm + L * PXB);  // [NF][LS] transforms
+  constexpr int VS = G::VS;
+  float* Vs = sm;                                                   // [L][VS] dual spectra
+  float2* buf = reinterpret_cast<float2*>(sm + ((L * VS + 1) & ~1));  // [NF][LS] transforms
   const long long npix = a.npix;
   const long long pix0 = (long long)blockIdx.x * PXB;
-  for (int idx = threadIdx.x; idx < L * PXB; idx += NT) {
-    const int l = idx / PXB, p = idx - l * PXB;
-    const long long q = pix0 + p;
-    Vs[idx] = (q < npix) ? a.V[(long long)l * npix + q] : 0.f;
+  // every global read of the block is issued here: V (staged through LDS for the transform-major
+  // reads of the inverse transform, and kept for the dual step), x and q (for the primal step)
+  constexpr int PER = G::PER;
+  float vreg[PER], xreg[PER], qreg[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int idx = threadIdx.x + i * NT;
+    vreg[i] = xreg[i] = qreg[i] = 0.f;
+    if (idx < L * PXB) {
+      const int l = idx / PXB, p = idx - l * PXB;
+      const long long q = pix0 + p;
+      if (q < npix) {
+        const long long o = (long long)l * npix + q;
+        vreg[i] = a.V[o];
+        xreg[i] = a.X[o];
+        qreg[i] = a.Q[o];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int idx = threadIdx.x + i * NT;
+    if (idx < L * PXB) {
+      const int l = idx / PXB, p = idx - l * PXB;
+      Vs[l * VS + p] = vreg[i];
+    }
   }
   lds_barrier();
   const int f = threadIdx.x / T, t = threadIdx.x - f * T;
@@ -129,8 +157,8 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     const float* va = Vs + 2 * f;
     for (int k = t; k < L; k += T) {
       const float sk = k ? c1 : c0;
-      const float ya = va[k * PXB] * sk, yb = va[k * PXB + 1] * sk;
-      const float ra = k ? va[(L - k) * PXB] * c1 : 0.f, rb = k ? va[(L - k) * PXB + 1] * c1 : 0.f;
+      const float ya = va[k * VS] * sk, yb = va[k * VS + 1] * sk;
+      const float ra = k ? va[(L - k) * VS] * c1 : 0.f, rb = k ? va[(L - k) * VS + 1] * c1 : 0.f;
       const float2 e = a.csL[k];
       const float2 Va = make_float2(ya * e.x + ra * e.y, ya * e.y - ra * e.x);
       const float2 Vb = make_float2(yb * e.x + rb * e.y, yb * e.y - rb * e.x);
@@ -140,7 +168,10 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   lds_barrier();
   fft_lds<L, true>(fb, t, true, a.twL);
   // primal step per (channel, pixel); d goes back into the same slot for the forward transform
-  for (int idx = threadIdx.x; idx < L * PXB; idx += NT) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int idx = threadIdx.x + i * NT;
+    if (idx >= L * PXB) continue;
     const int l = idx / PXB, p = idx - l * PXB;
     const long long q = pix0 + p;
     float* slot = reinterpret_cast<float*>(buf + (p >> 1) * LS + lpad(dct_slot(l, L))) + (p & 1);
@@ -148,8 +179,8 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     float d = 0.f;
     if (q < npix) {
       const long long o = (long long)l * npix + q;
-      const float x = a.X[o];
-      const float xt = fmaxf(x - a.tau * (a.Q[o] + tv), 0.f);
+      const float x = xreg[i];
+      const float xt = fmaxf(x - a.tau * (qreg[i] + tv), 0.f);
       d = 2.f * xt - x;
       a.D[o] = d;
       a.X[o] = a.rho * xt + (1.f - a.rho) * x;
@@ -160,7 +191,10 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   fft_lds<L, false>(fb, t, true, a.twL);
   // spectral dual step per (coefficient, pixel)
   const float s0 = a.smu_l * sqrtf(1.f / L), s1 = a.smu_l * sqrtf(2.f / L);
-  for (int idx = threadIdx.x; idx < L * PXB; idx += NT) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int idx = threadIdx.x + i * NT;
+    if (idx >= L * PXB) continue;
     const int k = idx / PXB, p = idx - k * PXB;
     const long long q = pix0 + p;
     const float2* fp = buf + (p >> 1) * LS;
@@ -175,7 +209,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     const float2 e = a.csL[k];
     const float c = (v.x * e.x + v.y * e.y) * (k ? s1 : s0);
     if (q < npix) {
-      const float vo = Vs[k * PXB + p];
+      const float vo = vreg[i];
       a.V[(long long)k * npix + q] = a.rho * satf_s(vo + c) + (1.f - a.rho) * vo;
     }
   }
