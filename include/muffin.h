@@ -142,6 +142,46 @@ int muffin_profile(muffin_ctx* ctx, int32_t n_iter, double ms[8]);
  * total device time.  Advances the state like muffin_step. */
 int muffin_step_timed(muffin_ctx* ctx, int32_t n_iter, double* ms);
 
+/* ---------------------------------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method): a CNN that maps a dirty channel image,
+ * normalised by the sum of its PSF, to an estimate of the reconstructed image; the primal-dual
+ * iteration refines from max(estimate, 0).  Four 3x3 convolutions 1 -> 32 -> 32 -> 32 -> 1 with
+ * circular padding, bias, ReLU after the first three; BF16 weights and activations (rounded to
+ * nearest even), FP32 accumulation; MSE loss and Adam (beta 0.9 / 0.999, eps 1e-8) on FP32 master
+ * weights.  Parameters are one FP32 vector in the order w1[32][1][3][3], b1[32], w2[32][32][3][3],
+ * b2[32], w3[32][32][3][3], b3[32], w4[1][32][3][3], b4[1] (19105 values); tap [a][e] reads the
+ * input at offset (a - 1, e - 1).  Image batches are device FP32 arrays [B][N][N] with N a multiple
+ * of 32.  A network object is bound to a HIP stream like a context and is not thread-safe.
+ * --------------------------------------------------------------------------------------------- */
+typedef struct muffin_cnn muffin_cnn;
+/* Create with He-normal weights drawn from a counter-based generator seeded by seed; features
+ * must be 32. */
+int muffin_cnn_create(muffin_cnn** out, int32_t features, uint64_t seed, void* hip_stream);
+int muffin_cnn_param_count(muffin_cnn* net, int32_t* n);
+/* Copy the FP32 parameter vector to or from host memory (n must equal the count); set_params
+ * also resets the Adam moments. */
+int muffin_cnn_get_params(muffin_cnn* net, float* params, int32_t n);
+int muffin_cnn_set_params(muffin_cnn* net, const float* params, int32_t n);
+/* out = network output (before the positive-part projection) for B images. */
+int muffin_cnn_predict(muffin_cnn* net, const float* in, float* out, int32_t B, int32_t N);
+/* Mean squared error against target and its gradient (host [count], may be NULL), no update. */
+int muffin_cnn_loss_grad(muffin_cnn* net, const float* in, const float* target, int32_t B, int32_t N,
+                         double* loss, float* grad);
+/* One Adam step of learning rate lr on the mean squared error; *loss (may be NULL) is the loss
+ * before the step. */
+int muffin_cnn_train_step(muffin_cnn* net, const float* in, const float* target, int32_t B, int32_t N,
+                          float lr, double* loss);
+/* Single layer (1..4), for parity checks.  x: device FP32 [B][Cin][N][N], rounded to BF16 inside.
+ * op 0: out = pre-activation z [B][Cout][N][N] (bias added).  op 1: given dz [B][Cout][N][N]
+ * (rounded to BF16 inside), out = input gradient [B][Cin][N][N] without activation mask (zeros
+ * for layer 1) and dparams (host) = weight then bias gradients of the layer. */
+int muffin_cnn_layer(muffin_cnn* net, int32_t layer, int32_t op, const float* x, const float* dz,
+                     float* out, float* dparams, int32_t B, int32_t N);
+void muffin_cnn_free(muffin_cnn* net);
+/* Warm start: X = max(CNN(y_l / sum psf_l), 0) channel by channel, U = V = 0.  N must be a
+ * multiple of 32. */
+int muffin_warm_start(muffin_ctx* ctx, muffin_cnn* net);
+
 void muffin_free(muffin_ctx* ctx);
 const char* muffin_strerror(int code);
 const char* muffin_last_error(void);

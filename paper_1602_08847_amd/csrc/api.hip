@@ -27,6 +27,7 @@ int launch_power_spectrum(const float2* Hhat_T, float* P_T, const float* chan_w,
                           float scale, hipStream_t st);
 int launch_clamp_pos(float* x, long long n, hipStream_t st);
 int launch_scale_channels(float* x, const float* chan_w, long long npix, int nch, hipStream_t st);
+int cnn_warm_input(const float* Y, const float2* Hhat_T, int pitchN, float* out, int N, int L, hipStream_t st);
 }  // namespace mf
 
 using namespace mf;
@@ -680,6 +681,21 @@ int muffin_set_state(muffin_ctx* c, const void* blob, size_t bytes) {
   MF_TRY(copy_in(c->U, f + c->cube, c->cube * (c->J + 1), 0, c->st));
   MF_TRY(copy_in(c->V, f + c->cube * (c->J + 2), c->cube, 0, c->st));
   c->iter = h.iter;
+  return MUFFIN_OK;
+}
+
+int muffin_warm_start(muffin_ctx* c, muffin_cnn* net) {
+  if (!c || !net) return set_error("bad arguments"), MUFFIN_EINVAL;
+  if (c->N % 32) return set_error("warm start needs N to be a multiple of 32"), MUFFIN_EINVAL;
+  StreamScope scope(c);
+  MF_TRY(cnn_warm_input(c->Y, c->Hhat_T, c->g.pitch * c->N, c->cA, c->N, c->L, c->st));
+  MF_HIP(hipStreamSynchronize(c->st));
+  MF_TRY(muffin_cnn_predict(net, c->cA, c->cB, c->L, c->N));
+  MF_HIP(hipDeviceSynchronize());
+  MF_HIP(hipMemcpyAsync(c->X, c->cB, sizeof(float) * c->cube, hipMemcpyDeviceToDevice, c->st));
+  MF_TRY(launch_clamp_pos(c->X, c->cube, c->st));
+  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->cube * (c->J + 1), c->st));
+  MF_HIP(hipMemsetAsync(c->V, 0, sizeof(float) * c->cube, c->st));
   return MUFFIN_OK;
 }
 

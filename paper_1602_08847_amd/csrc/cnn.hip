@@ -1,0 +1,827 @@
+// Warm-start CNN: four 3x3 convolutions 1 -> 32 -> 32 -> 32 -> 1, circular padding, bias, ReLU
+// after the first three layers; BF16 weights and activations, FP32 accumulation, activations
+// rounded to BF16 (nearest, ties to even) when stored.  Training uses MSE and Adam on FP32
+// master weights.
+//
+// The two 32 -> 32 layers are implicit GEMMs on v_mfma_f32_32x32x16_bf16 (gfx950):
+//   forward  z[p][o]  = b[o] + sum_{tap, c} W[o][c][tap] a[p + tap][c]   M = 32 pixels, N = 32 o, K = 9 x 32
+//   data     dx[p][c] = sum_{tap, o} W[o][c][tap] dz[p - tap][o]         the forward kernel with taps
+//                                                                          mirrored and W transposed
+//   weight   dW[tap][o][c] = sum_p dz[p][o] a[p + tap][c]                M = 32 o, N = 32 c, K = pixels
+// Operand lane layout of the 32x32x16 BF16 MFMA (checked on the device): A[i][k] sits in lane
+// i + 32 (k / 8), element k % 8; B[k][j] in lane j + 32 (k / 8), element k % 8; D[i][j] in lane
+// j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8).
+// Activations are NHWC BF16 ([pixel][32]); network inputs and outputs are FP32 planes [B][N][N].
+#include "common.h"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace mf {
+
+constexpr int FC = 32;  // feature channels
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float bfround(float f) { return bf2f(f2bf(f)); }
+__device__ __forceinline__ bool bf_pos(uint16_t h) { return h != 0 && (h & 0x8000u) == 0; }
+__device__ __forceinline__ int wrapn(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
+
+// ------------------------------------------------------------------ layer 1 (1 -> 32), VALU
+// z[o] = b[o] + sum_tap W1[tap][o] x[p + tap] with x rounded to BF16.
+// mode 0: a1 = bf16(relu(z)) NHWC; mode 1: z FP32 [B][32][N][N].
+__global__ void __launch_bounds__(256) k_conv1_fwd(const float* __restrict__ x, const float* __restrict__ w1b,
+                                                   const float* __restrict__ b1, uint16_t* __restrict__ a1,
+                                                   float* __restrict__ zout, int N, long long P, int mode) {
+  __shared__ float sw[9 * FC + FC];
+  for (int i = threadIdx.x; i < 9 * FC + FC; i += 256) sw[i] = i < 9 * FC ? w1b[i] : b1[i - 9 * FC];
+  __syncthreads();
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  const long long n2 = (long long)N * N;
+  const long long b = p / n2;
+  const int yx = (int)(p - b * n2), y = yx / N, xx = yx - y * N;
+  const float* xb = x + b * n2;
+  float v[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int yy = wrapn(y + t / 3 - 1, N), xq = wrapn(xx + t % 3 - 1, N);
+    v[t] = bfround(xb[(long long)yy * N + xq]);
+  }
+  u16x8 out[4];
+#pragma unroll
+  for (int o = 0; o < FC; ++o) {
+    float z = sw[9 * FC + o];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) z = fmaf(sw[t * FC + o], v[t], z);
+    if (mode == 0) out[o / 8][o % 8] = f2bf(fmaxf(z, 0.f));
+    else zout[((b * FC + o) * N + y) * (long long)N + xx] = z;
+  }
+  if (mode == 0) {
+    u16x8* dst = reinterpret_cast<u16x8*>(a1 + p * FC);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = out[q];
+  }
+}
+
+// ------------------------------------------------------------------ 32 -> 32 layers, MFMA
+enum MmaMode { MM_ACT = 0, MM_Z = 1, MM_DMASK = 2, MM_DRAW = 3 };
+constexpr int TPX = 32, TROWS = 8;      // output tile: 32 pixels x 8 rows per workgroup
+constexpr int PSTR = 40;                // LDS pixel stride in bf16 (80 bytes: conflict-free 16-byte reads)
+
+// in: NHWC BF16 activations (or gradients); wg: [9][32 j][32 k] BF16 with B[k][j] = wg[tap][j][k];
+// the tap offset applied to the input is +(dy, dx) for tap = (dy + 1) * 3 + (dx + 1).
+template <int MODE>
+__global__ void __launch_bounds__(256) k_conv_mma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wg,
+                                                  const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                                  uint16_t* __restrict__ out16, float* __restrict__ out32, int N,
+                                                  int nimg) {
+  __shared__ __attribute__((aligned(16))) uint16_t tin[(TROWS + 2) * (TPX + 2) * PSTR];
+  __shared__ __attribute__((aligned(16))) uint16_t tw[9 * FC * PSTR];
+  const int tiles_x = N / TPX, tiles_y = N / TROWS;
+  int t = blockIdx.x;
+  const int tx = t % tiles_x;
+  t /= tiles_x;
+  const int ty = t % tiles_y;
+  const long long b = t / tiles_y;
+  const int x0 = tx * TPX, y0 = ty * TROWS;
+  const long long n2 = (long long)N * N;
+  const uint16_t* inb = in + b * n2 * FC;
+  // weights: 9 x 32 rows of 64 bytes
+  for (int i = threadIdx.x; i < 9 * FC * 4; i += 256) {
+    const int row = i >> 2, q = i & 3;
+    *reinterpret_cast<u16x8*>(tw + row * PSTR + q * 8) = *reinterpret_cast<const u16x8*>(wg + row * FC + q * 8);
+  }
+  // input tile with a one-pixel periodic halo
+  for (int i = threadIdx.x; i < (TROWS + 2) * (TPX + 2) * 4; i += 256) {
+    const int q = i & 3, pix = i >> 2;
+    const int r = pix / (TPX + 2), c = pix - r * (TPX + 2);
+    const int gy = wrapn(y0 + r - 1, N), gx = wrapn(x0 + c - 1, N);
+    *reinterpret_cast<u16x8*>(tin + pix * PSTR + q * 8) =
+        *reinterpret_cast<const u16x8*>(inb + ((long long)gy * N + gx) * FC + q * 8);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 31, kh8 = (lane >> 5) * 8;
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt) {
+    const int r = 2 * w + tt;  // output row within the tile
+    f32x16 acc = {};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;  // input offset +1 (halo)
+#pragma unroll
+      for (int kh = 0; kh < 2; ++kh) {
+        const u16x8 av = *reinterpret_cast<const u16x8*>(tin + ((r + dy) * (TPX + 2) + li + dx) * PSTR + kh * 16 + kh8);
+        const u16x8 bv = *reinterpret_cast<const u16x8*>(tw + (tap * FC + li) * PSTR + kh * 16 + kh8);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                      acc, 0, 0, 0);
+      }
+    }
+    const int y = y0 + r;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = (e & 3) + 4 * (lane >> 5) + 8 * (e >> 2);  // pixel within the 32-pixel row segment
+      const int j = li;                                        // output channel
+      const long long pix = b * n2 + (long long)y * N + x0 + i;
+      float v = acc[e];
+      if constexpr (MODE == MM_ACT) {
+        out16[pix * FC + j] = f2bf(fmaxf(v + bias[j], 0.f));
+      } else if constexpr (MODE == MM_Z) {
+        out32[((b * FC + j) * N + y) * (long long)N + x0 + i] = v + bias[j];
+      } else if constexpr (MODE == MM_DMASK) {
+        out16[pix * FC + j] = bf_pos(mask[pix * FC + j]) ? f2bf(v) : (uint16_t)0;
+      } else {
+        out32[((b * FC + j) * N + y) * (long long)N + x0 + i] = v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ weight gradient, MFMA
+// dW[tap][o][c] = sum_p dz[p][o] a[p + tap][c], db[o] = sum_p dz[p][o].  A workgroup of three
+// waves walks 32-pixel row segments; wave w owns the taps of row offset dy = w - 1.  Each
+// segment stages dz transposed ([o][32 px]) and a transposed for the three rows and three
+// column shifts ([row][dx][c][32 px]), so every operand is one aligned 16-byte LDS read.
+// Partial sums per workgroup: partial[blk][tap * 1024 + o * 32 + c] and [9216 + o].
+constexpr int WPART = 9 * FC * FC + FC;
+__global__ void __launch_bounds__(192) k_wgrad_mma(const uint16_t* __restrict__ dz, const uint16_t* __restrict__ a,
+                                                   float* __restrict__ partial, int N, long long nseg) {
+  __shared__ __attribute__((aligned(16))) uint16_t dzT[FC * PSTR];
+  __shared__ __attribute__((aligned(16))) uint16_t aT[3 * 3 * FC * PSTR];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 31, kh8 = (lane >> 5) * 8;
+  const long long n2 = (long long)N * N;
+  const int segs_x = N / TPX;
+  f32x16 acc[3] = {{}, {}, {}};
+  float dbacc = 0.f;
+  for (long long sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
+    const int sx = (int)(sgi % segs_x);
+    const long long rowid = sgi / segs_x;  // b * N + y
+    const long long b = rowid / N;
+    const int y = (int)(rowid - b * N), x0 = sx * TPX;
+    const uint16_t* dzb = dz + b * n2 * FC;
+    const uint16_t* ab = a + b * n2 * FC;
+    // dz segment, transposed: 32 px x 4 chunks of 8 channels
+    for (int i = threadIdx.x; i < TPX * 4; i += 192) {
+      const int px = i >> 2, q = i & 3;
+      const u16x8 v = *reinterpret_cast<const u16x8*>(dzb + ((long long)y * N + x0 + px) * FC + q * 8);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dzT[(q * 8 + e) * PSTR + px] = v[e];
+    }
+    // a rows y-1, y, y+1 and columns x0-1 .. x0+32, scattered to the three column shifts
+    for (int i = threadIdx.x; i < 3 * (TPX + 2) * 4; i += 192) {
+      const int q = i & 3, rest = i >> 2;
+      const int r = rest / (TPX + 2), c = rest - r * (TPX + 2);
+      const int gy = wrapn(y + r - 1, N), gx = wrapn(x0 + c - 1, N);
+      const u16x8 v = *reinterpret_cast<const u16x8*>(ab + ((long long)gy * N + gx) * FC + q * 8);
+#pragma unroll
+      for (int dxi = 0; dxi < 3; ++dxi) {
+        const int px = c - dxi;  // a[x + dx] with dx = dxi - 1 sits at column c = x - x0 + dxi
+        if (px >= 0 && px < TPX) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) aT[((r * 3 + dxi) * FC + q * 8 + e) * PSTR + px] = v[e];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int dxi = 0; dxi < 3; ++dxi) {
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const u16x8 av = *reinterpret_cast<const u16x8*>(dzT + li * PSTR + ks * 16 + kh8);
+        const u16x8 bv = *reinterpret_cast<const u16x8*>(aT + ((w * 3 + dxi) * FC + li) * PSTR + ks * 16 + kh8);
+        acc[dxi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                           __builtin_bit_cast(bf16x8, bv), acc[dxi], 0, 0, 0);
+      }
+    }
+    if (w == 1 && lane < 32) {
+      float s = 0.f;
+      for (int px = 0; px < TPX; ++px) s += bf2f(dzT[lane * PSTR + px]);
+      dbacc += s;
+    }
+    __syncthreads();
+  }
+  float* pb = partial + (long long)blockIdx.x * WPART;
+#pragma unroll
+  for (int dxi = 0; dxi < 3; ++dxi) {
+    const int tap = w * 3 + dxi;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int o = (e & 3) + 4 * (lane >> 5) + 8 * (e >> 2);
+      pb[tap * FC * FC + o * FC + li] = acc[dxi][e];
+    }
+  }
+  if (w == 1 && lane < 32) pb[9 * FC * FC + lane] = dbacc;
+}
+
+// ------------------------------------------------------------------ layer 4 (32 -> 1), VALU
+// z[p] = b4 + sum_{tap, c} W4[tap][c] a3[p + tap][c]
+__global__ void __launch_bounds__(256) k_conv4_fwd(const uint16_t* __restrict__ a3, const float* __restrict__ w4b,
+                                                   const float* __restrict__ b4, float* __restrict__ z, int N,
+                                                   long long P) {
+  __shared__ float sw[9 * FC];
+  for (int i = threadIdx.x; i < 9 * FC; i += 256) sw[i] = w4b[i];
+  __syncthreads();
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  const long long n2 = (long long)N * N;
+  const long long b = p / n2;
+  const int yx = (int)(p - b * n2), y = yx / N, xx = yx - y * N;
+  float acc = b4[0];
+  for (int t = 0; t < 9; ++t) {
+    const int yy = wrapn(y + t / 3 - 1, N), xq = wrapn(xx + t % 3 - 1, N);
+    const u16x8* src = reinterpret_cast<const u16x8*>(a3 + (b * n2 + (long long)yy * N + xq) * FC);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u16x8 v = src[q];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) acc = fmaf(sw[t * FC + q * 8 + e], bf2f(v[e]), acc);
+    }
+  }
+  z[p] = acc;
+}
+
+// dz4 = bf16(2 (z - t) / M); partial[block] = sum (z - t)^2 (FP64)
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ z, const float* __restrict__ tgt,
+                                             float* __restrict__ dz, double* __restrict__ partial, long long P,
+                                             float scale) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < P; p += (long long)gridDim.x * 256) {
+    const float r = z[p] - tgt[p];
+    s += (double)r * r;
+    dz[p] = bfround(scale * r);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Layer 4 data gradient: da3[p][c] = sum_tap W4[tap][c] dz4[p - tap]; mode 0: masked by a3 > 0 and
+// rounded to BF16 (NHWC); mode 1: FP32 [B][32][N][N] without mask.
+__global__ void __launch_bounds__(256) k_conv4_bwd_data(const float* __restrict__ dz4, const float* __restrict__ w4b,
+                                                        const uint16_t* __restrict__ a3, uint16_t* __restrict__ dz3,
+                                                        float* __restrict__ dx32, int N, long long P, int mode) {
+  __shared__ float sw[9 * FC];
+  for (int i = threadIdx.x; i < 9 * FC; i += 256) sw[i] = w4b[i];
+  __syncthreads();
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  const long long n2 = (long long)N * N;
+  const long long b = p / n2;
+  const int yx = (int)(p - b * n2), y = yx / N, xx = yx - y * N;
+  float d[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int yy = wrapn(y - (t / 3 - 1), N), xq = wrapn(xx - (t % 3 - 1), N);
+    d[t] = dz4[b * n2 + (long long)yy * N + xq];
+  }
+  u16x8 out[4];
+  u16x8 m[4];
+  if (mode == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[q] = reinterpret_cast<const u16x8*>(a3 + p * FC)[q];
+  }
+#pragma unroll
+  for (int c = 0; c < FC; ++c) {
+    float s = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) s = fmaf(sw[t * FC + c], d[t], s);
+    if (mode == 0) out[c / 8][c % 8] = bf_pos(m[c / 8][c % 8]) ? f2bf(s) : (uint16_t)0;
+    else dx32[((b * FC + c) * N + y) * (long long)N + xx] = s;
+  }
+  if (mode == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) reinterpret_cast<u16x8*>(dz3 + p * FC)[q] = out[q];
+  }
+}
+
+// Weight gradients of the single-channel layers, VALU.  Thread (g, c): c = lane % 32 is the
+// feature channel, g = tid / 32 one of 8 pixel groups.
+//   layer 4: dW4[tap][c] = sum_p dz4[p] a3[p + tap][c], db4 = sum_p dz4[p]
+//   layer 1: dW1[tap][o] = sum_p dz1[p][o] x[p + tap],   db1[o] = sum_p dz1[p][o]
+// partial[blk][tap * 32 + c] (9 x 32) and [288 + c] (bias; layer 4 uses entry 288 only).
+constexpr int SPART = 9 * FC + FC;
+template <int LAYER>
+__global__ void __launch_bounds__(256) k_wgrad_single(const float* __restrict__ dzs, const uint16_t* __restrict__ act,
+                                                      const uint16_t* __restrict__ dzm, const float* __restrict__ xin,
+                                                      float* __restrict__ partial, int N, long long P) {
+  __shared__ float red[8][SPART];
+  const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const long long n2 = (long long)N * N;
+  float acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long p = (long long)blockIdx.x * 8 + g; p < P; p += (long long)gridDim.x * 8) {
+    const long long b = p / n2;
+    const int yx = (int)(p - b * n2), y = yx / N, xx = yx - y * N;
+    const float d = (LAYER == 4) ? dzs[p] : bf2f(dzm[p * FC + c]);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const long long q = b * n2 + (long long)wrapn(y + t / 3 - 1, N) * N + wrapn(xx + t % 3 - 1, N);
+      const float v = (LAYER == 4) ? bf2f(act[q * FC + c]) : bfround(xin[q]);
+      acc[t] = fmaf(d, v, acc[t]);
+    }
+    acc[9] += d;
+  }
+#pragma unroll
+  for (int t = 0; t < 9; ++t) red[g][t * FC + c] = acc[t];
+  red[g][9 * FC + c] = acc[9];
+  __syncthreads();
+  for (int i = threadIdx.x; i < SPART; i += 256) {
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) s += red[k][i];
+    partial[(long long)blockIdx.x * SPART + i] = s;
+  }
+}
+
+// out[map(i)] = sum_blk partial[blk][i] for i < n, summed in FP64 in block order.
+// map: 0 identity; 1: [tap][o][c] -> [o][c][tap] (32 x 32 layers, bias after 9216);
+// 2: [tap][c] -> [c][tap] (single-channel layers, bias at 288 (layer 4: only entry 288 used)).
+__global__ void __launch_bounds__(256) k_reduce_partials(const float* __restrict__ partial, int stride, int n,
+                                                         int nblk, float* __restrict__ out, int map) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < nblk; ++k) s += partial[(long long)k * stride + i];
+  int dst = i;
+  if (map == 1 && i < 9 * FC * FC) {
+    const int tap = i / (FC * FC), o = (i / FC) % FC, c = i % FC;
+    dst = (o * FC + c) * 9 + tap;
+  } else if (map == 2 && i < 9 * FC) {
+    const int tap = i / FC, c = i % FC;
+    dst = c * 9 + tap;
+  }
+  out[dst] = (float)s;
+}
+
+// Adam on FP32 master weights.
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, int n, float lr, float b1, float b2, float eps,
+                                              float c1, float c2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Derived BF16 weights from the FP32 master parameters (layout of the parameter vector:
+// w1[32][1][3][3] b1[32] w2[32][32][3][3] b2[32] w3[32][32][3][3] b3[32] w4[1][32][3][3] b4[1]).
+struct CnnOffsets {
+  static constexpr int w1 = 0, b1 = 288, w2 = 320, b2 = 9536, w3 = 9568, b3 = 18784, w4 = 18816, b4 = 19104,
+                       total = 19105;
+};
+__global__ void __launch_bounds__(256) k_prep_weights(const float* __restrict__ prm, float* __restrict__ w1b,
+                                                      uint16_t* __restrict__ w2f, uint16_t* __restrict__ w2d,
+                                                      uint16_t* __restrict__ w3f, uint16_t* __restrict__ w3d,
+                                                      float* __restrict__ w4b) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < 9 * FC * FC) {
+    const int tap = i / (FC * FC), j = (i / FC) % FC, k = i % FC;
+    // forward: B[k = c][j = o] = W[o][c][tap]
+    w2f[i] = f2bf(prm[CnnOffsets::w2 + (j * FC + k) * 9 + tap]);
+    w3f[i] = f2bf(prm[CnnOffsets::w3 + (j * FC + k) * 9 + tap]);
+    // data gradient: B[k = o][j = c] = W[o][c][8 - tap]
+    w2d[i] = f2bf(prm[CnnOffsets::w2 + (k * FC + j) * 9 + (8 - tap)]);
+    w3d[i] = f2bf(prm[CnnOffsets::w3 + (k * FC + j) * 9 + (8 - tap)]);
+  }
+  if (i < 9 * FC) {
+    const int tap = i / FC, c = i % FC;
+    w1b[i] = bfround(prm[CnnOffsets::w1 + c * 9 + tap]);
+    w4b[i] = bfround(prm[CnnOffsets::w4 + c * 9 + tap]);
+  }
+}
+
+// x / s_l per plane (input normalisation of the warm start)
+__global__ void __launch_bounds__(256) k_scale_planes(const float* __restrict__ x, const float* __restrict__ s,
+                                                      int sstride, float* __restrict__ out, long long n2, int nimg) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n2 * nimg) return;
+  const long long b = i / n2;
+  out[i] = x[i] / s[b * sstride];
+}
+
+}  // namespace mf
+
+// ================================================================== C ABI
+using namespace mf;
+
+struct muffin_cnn {
+  hipStream_t user = nullptr, st = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  float *prm = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  float *w1b = nullptr, *w4b = nullptr;
+  uint16_t *w2f = nullptr, *w2d = nullptr, *w3f = nullptr, *w3d = nullptr;
+  long long cap = 0;  // pixel capacity of the workspaces
+  float* xin = nullptr;
+  uint16_t *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *g3 = nullptr, *g2 = nullptr, *g1 = nullptr;
+  float *z4 = nullptr, *dz4 = nullptr;
+  float* partial = nullptr;
+  double* dpart = nullptr;
+  double* dres = nullptr;
+  long long t = 0;
+};
+
+namespace {
+constexpr int kWgradBlocks = 1024;
+constexpr int kSingleBlocks = 1024;
+constexpr long long kChunkPixels = 16ll << 20;  // pixels per inference chunk
+
+struct CnnScope {
+  muffin_cnn* c;
+  bool ok;
+  explicit CnnScope(muffin_cnn* c_) : c(c_) {
+    ok = hipEventRecord(c->ev_in, c->user) == hipSuccess && hipStreamWaitEvent(c->st, c->ev_in, 0) == hipSuccess;
+  }
+  ~CnnScope() {
+    if (hipEventRecord(c->ev_out, c->st) == hipSuccess) (void)hipStreamWaitEvent(c->user, c->ev_out, 0);
+  }
+};
+
+template <typename T>
+int dal(T** p, size_t n) {
+  if (hipMalloc((void**)p, sizeof(T) * (n ? n : 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation failed");
+    return MUFFIN_ENOMEM;
+  }
+  return MUFFIN_OK;
+}
+
+void free_ws(muffin_cnn* c) {
+  void* ps[] = {c->xin, c->a1, c->a2, c->a3, c->g3, c->g2, c->g1, c->z4, c->dz4};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  c->xin = nullptr;
+  c->a1 = c->a2 = c->a3 = c->g3 = c->g2 = c->g1 = nullptr;
+  c->z4 = c->dz4 = nullptr;
+  c->cap = 0;
+}
+
+int ensure_ws(muffin_cnn* c, long long P) {
+  if (P <= c->cap) return MUFFIN_OK;
+  MF_HIP(hipStreamSynchronize(c->st));
+  free_ws(c);
+  MF_TRY(dal(&c->xin, P));
+  MF_TRY(dal(&c->a1, P * FC));
+  MF_TRY(dal(&c->a2, P * FC));
+  MF_TRY(dal(&c->a3, P * FC));
+  MF_TRY(dal(&c->g3, P * FC));
+  MF_TRY(dal(&c->g2, P * FC));
+  MF_TRY(dal(&c->g1, P * FC));
+  MF_TRY(dal(&c->z4, P));
+  MF_TRY(dal(&c->dz4, P));
+  c->cap = P;
+  return MUFFIN_OK;
+}
+
+int check_shape(int B, int N) {
+  if (B < 1 || N < 32 || N > 4096 || N % TPX || N % TROWS)
+    return set_error("CNN: need B >= 1 and N a multiple of 32 (32 <= N <= 4096)"), MUFFIN_EINVAL;
+  return MUFFIN_OK;
+}
+
+int prep_weights(muffin_cnn* c) {
+  hipLaunchKernelGGL(k_prep_weights, dim3((9 * FC * FC + 255) / 256), dim3(256), 0, c->st, c->prm, c->w1b, c->w2f,
+                     c->w2d, c->w3f, c->w3d, c->w4b);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
+
+// forward of P pixels (B images) from FP32 input planes; activations kept for training
+int forward(muffin_cnn* c, const float* x, int B, int N) {
+  const long long P = (long long)B * N * N;
+  const unsigned tiles = (unsigned)((long long)B * (N / TPX) * (N / TROWS));
+  hipLaunchKernelGGL(k_conv1_fwd, dim3(nb256(P)), dim3(256), 0, c->st, x, c->w1b, c->prm + CnnOffsets::b1, c->a1,
+                     (float*)nullptr, N, P, 0);
+  hipLaunchKernelGGL((k_conv_mma<MM_ACT>), dim3(tiles), dim3(256), 0, c->st, c->a1, c->w2f, c->prm + CnnOffsets::b2,
+                     (const uint16_t*)nullptr, c->a2, (float*)nullptr, N, B);
+  hipLaunchKernelGGL((k_conv_mma<MM_ACT>), dim3(tiles), dim3(256), 0, c->st, c->a2, c->w3f, c->prm + CnnOffsets::b3,
+                     (const uint16_t*)nullptr, c->a3, (float*)nullptr, N, B);
+  hipLaunchKernelGGL(k_conv4_fwd, dim3(nb256(P)), dim3(256), 0, c->st, c->a3, c->w4b, c->prm + CnnOffsets::b4, c->z4,
+                     N, P);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+int reduce_into(muffin_cnn* c, int stride, int n, int nblk, float* out, int map) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3((n + 255) / 256), dim3(256), 0, c->st, c->partial, stride, n, nblk, out,
+                     map);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+// loss and gradient (into c->grad) for targets tgt; x is the FP32 input
+int loss_grad(muffin_cnn* c, const float* x, const float* tgt, int B, int N, double* loss) {
+  const long long P = (long long)B * N * N;
+  MF_TRY(forward(c, x, B, N));
+  hipLaunchKernelGGL(k_mse, dim3(1024), dim3(256), 0, c->st, c->z4, tgt, c->dz4, c->dpart, P, (float)(2.0 / (double)P));
+  MF_TRY(launch_reduce_sum(c->dpart, 1024, c->dres, 0, c->st));
+  // layer 4
+  hipLaunchKernelGGL(k_wgrad_single<4>, dim3(kSingleBlocks), dim3(256), 0, c->st, c->dz4, c->a3,
+                     (const uint16_t*)nullptr, (const float*)nullptr, c->partial, N, P);
+  MF_TRY(reduce_into(c, SPART, 9 * FC, kSingleBlocks, c->grad + CnnOffsets::w4, 2));
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, c->st, c->partial + 9 * FC, SPART, 1, kSingleBlocks,
+                     c->grad + CnnOffsets::b4, 0);
+  hipLaunchKernelGGL(k_conv4_bwd_data, dim3(nb256(P)), dim3(256), 0, c->st, c->dz4, c->w4b, c->a3, c->g3,
+                     (float*)nullptr, N, P, 0);
+  const unsigned tiles = (unsigned)((long long)B * (N / TPX) * (N / TROWS));
+  const long long nseg = (long long)B * N * (N / TPX);
+  const unsigned wb = (unsigned)(nseg < kWgradBlocks ? nseg : kWgradBlocks);
+  // layer 3
+  hipLaunchKernelGGL(k_wgrad_mma, dim3(wb), dim3(192), 0, c->st, c->g3, c->a2, c->partial, N, nseg);
+  MF_TRY(reduce_into(c, WPART, WPART, (int)wb, c->grad + CnnOffsets::w3, 1));
+  hipLaunchKernelGGL((k_conv_mma<MM_DMASK>), dim3(tiles), dim3(256), 0, c->st, c->g3, c->w3d, (const float*)nullptr,
+                     c->a2, c->g2, (float*)nullptr, N, B);
+  // layer 2
+  hipLaunchKernelGGL(k_wgrad_mma, dim3(wb), dim3(192), 0, c->st, c->g2, c->a1, c->partial, N, nseg);
+  MF_TRY(reduce_into(c, WPART, WPART, (int)wb, c->grad + CnnOffsets::w2, 1));
+  hipLaunchKernelGGL((k_conv_mma<MM_DMASK>), dim3(tiles), dim3(256), 0, c->st, c->g2, c->w2d, (const float*)nullptr,
+                     c->a1, c->g1, (float*)nullptr, N, B);
+  // layer 1
+  hipLaunchKernelGGL(k_wgrad_single<1>, dim3(kSingleBlocks), dim3(256), 0, c->st, (const float*)nullptr,
+                     (const uint16_t*)nullptr, c->g1, x, c->partial, N, P);
+  MF_TRY(reduce_into(c, SPART, SPART, kSingleBlocks, c->grad + CnnOffsets::w1, 2));
+  MF_HIP(hipGetLastError());
+  if (loss) {
+    double h = 0;
+    MF_HIP(hipMemcpyAsync(&h, c->dres, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    MF_HIP(hipStreamSynchronize(c->st));
+    *loss = h / (double)P;
+  }
+  return MUFFIN_OK;
+}
+
+// host-side counter-based normal generator (splitmix64 + Box-Muller) for the initial weights
+double normal_draw(uint64_t seed, uint64_t i) {
+  auto mix = [](uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+  };
+  const double u1 = ((mix(seed * 0x100000001b3ull + 2 * i) >> 11) + 1.0) / 9007199254740993.0;
+  const double u2 = (mix(seed * 0x100000001b3ull + 2 * i + 1) >> 11) / 9007199254740992.0;
+  return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+}
+
+}  // namespace
+
+extern "C" {
+
+int muffin_cnn_create(muffin_cnn** out, int32_t features, uint64_t seed, void* hip_stream) {
+  if (!out) return set_error("out is NULL"), MUFFIN_EINVAL;
+  *out = nullptr;
+  if (features != FC) return set_error("CNN: only 32 feature channels are built"), MUFFIN_EINVAL;
+  muffin_cnn* c = new (std::nothrow) muffin_cnn();
+  if (!c) return set_error("host allocation failed"), MUFFIN_ENOMEM;
+  c->user = (hipStream_t)hip_stream;
+  auto fail = [&](int rc) {
+    muffin_cnn_free(c);
+    return rc;
+  };
+  if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+    return fail((set_error("CNN: stream or event creation failed"), MUFFIN_EHIP));
+  const int n = CnnOffsets::total;
+  int rc = MUFFIN_OK;
+  if ((rc = dal(&c->prm, n)) || (rc = dal(&c->grad, n)) || (rc = dal(&c->m, n)) || (rc = dal(&c->v, n)) ||
+      (rc = dal(&c->w1b, 9 * FC)) || (rc = dal(&c->w4b, 9 * FC)) || (rc = dal(&c->w2f, 9 * FC * FC)) ||
+      (rc = dal(&c->w2d, 9 * FC * FC)) || (rc = dal(&c->w3f, 9 * FC * FC)) || (rc = dal(&c->w3d, 9 * FC * FC)) ||
+      (rc = dal(&c->partial, (size_t)kWgradBlocks * WPART)) || (rc = dal(&c->dpart, 1024)) || (rc = dal(&c->dres, 4)))
+    return fail(rc);
+  // He-normal weights (std sqrt(2 / fan_in)), zero biases
+  std::vector<float> h(n, 0.f);
+  uint64_t k = 0;
+  auto fill = [&](int off, int cnt, int fan_in) {
+    const double sd = std::sqrt(2.0 / fan_in);
+    for (int i = 0; i < cnt; ++i) h[off + i] = (float)(sd * normal_draw(seed, k++));
+  };
+  fill(CnnOffsets::w1, 288, 9);
+  fill(CnnOffsets::w2, 9216, 288);
+  fill(CnnOffsets::w3, 9216, 288);
+  fill(CnnOffsets::w4, 288, 288);
+  if (hipMemcpy(c->prm, h.data(), sizeof(float) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->m, 0, sizeof(float) * n) != hipSuccess || hipMemset(c->v, 0, sizeof(float) * n) != hipSuccess)
+    return fail((set_error("CNN: upload failed"), MUFFIN_EHIP));
+  if ((rc = prep_weights(c)) || hipStreamSynchronize(c->st) != hipSuccess) return fail(rc ? rc : MUFFIN_EHIP);
+  *out = c;
+  return MUFFIN_OK;
+}
+
+void muffin_cnn_free(muffin_cnn* c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  free_ws(c);
+  void* ps[] = {c->prm, c->grad, c->m, c->v, c->w1b, c->w4b, c->w2f, c->w2d, c->w3f, c->w3d, c->partial, c->dpart,
+                c->dres};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->st) (void)hipStreamDestroy(c->st);
+  delete c;
+}
+
+int muffin_cnn_param_count(muffin_cnn* c, int32_t* n) {
+  if (!c || !n) return set_error("bad arguments"), MUFFIN_EINVAL;
+  *n = CnnOffsets::total;
+  return MUFFIN_OK;
+}
+
+int muffin_cnn_get_params(muffin_cnn* c, float* params, int32_t n) {
+  if (!c || !params || n != CnnOffsets::total) return set_error("bad arguments"), MUFFIN_EINVAL;
+  CnnScope s(c);
+  MF_HIP(hipMemcpyAsync(params, c->prm, sizeof(float) * n, hipMemcpyDeviceToHost, c->st));
+  MF_HIP(hipStreamSynchronize(c->st));
+  return MUFFIN_OK;
+}
+
+int muffin_cnn_set_params(muffin_cnn* c, const float* params, int32_t n) {
+  if (!c || !params || n != CnnOffsets::total) return set_error("bad arguments"), MUFFIN_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(params[i])) return set_error("CNN: non-finite parameter"), MUFFIN_ENONFINITE;
+  CnnScope s(c);
+  MF_HIP(hipMemcpyAsync(c->prm, params, sizeof(float) * n, hipMemcpyHostToDevice, c->st));
+  MF_HIP(hipMemsetAsync(c->m, 0, sizeof(float) * n, c->st));
+  MF_HIP(hipMemsetAsync(c->v, 0, sizeof(float) * n, c->st));
+  c->t = 0;
+  MF_TRY(prep_weights(c));
+  MF_HIP(hipStreamSynchronize(c->st));
+  return MUFFIN_OK;
+}
+
+int muffin_cnn_predict(muffin_cnn* c, const float* in, float* out, int32_t B, int32_t N) {
+  if (!c || !in || !out) return set_error("bad arguments"), MUFFIN_EINVAL;
+  MF_TRY(check_shape(B, N));
+  CnnScope s(c);
+  const long long n2 = (long long)N * N;
+  long long chunk = kChunkPixels / n2;
+  if (chunk < 1) chunk = 1;
+  if (chunk > B) chunk = B;
+  MF_TRY(ensure_ws(c, chunk * n2));
+  for (long long b0 = 0; b0 < B; b0 += chunk) {
+    const int nb = (int)((B - b0) < chunk ? (B - b0) : chunk);
+    MF_TRY(forward(c, in + b0 * n2, nb, N));
+    MF_HIP(hipMemcpyAsync(out + b0 * n2, c->z4, sizeof(float) * nb * n2, hipMemcpyDeviceToDevice, c->st));
+  }
+  return MUFFIN_OK;
+}
+
+int muffin_cnn_loss_grad(muffin_cnn* c, const float* in, const float* target, int32_t B, int32_t N, double* loss,
+                         float* grad) {
+  if (!c || !in || !target) return set_error("bad arguments"), MUFFIN_EINVAL;
+  MF_TRY(check_shape(B, N));
+  CnnScope s(c);
+  MF_TRY(ensure_ws(c, (long long)B * N * N));
+  MF_TRY(loss_grad(c, in, target, B, N, loss));
+  if (grad) {
+    MF_HIP(hipMemcpyAsync(grad, c->grad, sizeof(float) * CnnOffsets::total, hipMemcpyDeviceToHost, c->st));
+    MF_HIP(hipStreamSynchronize(c->st));
+  }
+  return MUFFIN_OK;
+}
+
+int muffin_cnn_train_step(muffin_cnn* c, const float* in, const float* target, int32_t B, int32_t N, float lr,
+                          double* loss) {
+  if (!c || !in || !target || !(lr > 0)) return set_error("bad arguments"), MUFFIN_EINVAL;
+  MF_TRY(check_shape(B, N));
+  CnnScope s(c);
+  MF_TRY(ensure_ws(c, (long long)B * N * N));
+  MF_TRY(loss_grad(c, in, target, B, N, loss));
+  c->t += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = (float)(1.0 - std::pow(0.9, (double)c->t)), c2 = (float)(1.0 - std::pow(0.999, (double)c->t));
+  hipLaunchKernelGGL(k_adam, dim3((CnnOffsets::total + 255) / 256), dim3(256), 0, c->st, c->prm, c->grad, c->m, c->v,
+                     CnnOffsets::total, lr, b1, b2, 1e-8f, c1, c2);
+  MF_HIP(hipGetLastError());
+  MF_TRY(prep_weights(c));
+  return MUFFIN_OK;
+}
+
+int muffin_cnn_layer(muffin_cnn* c, int32_t layer, int32_t op, const float* x, const float* dz, float* out,
+                     float* dparams, int32_t B, int32_t N) {
+  if (!c || layer < 1 || layer > 4 || (op != 0 && op != 1) || !x || !out) return set_error("bad arguments"), MUFFIN_EINVAL;
+  if (op == 1 && (!dz || !dparams)) return set_error("bad arguments"), MUFFIN_EINVAL;
+  MF_TRY(check_shape(B, N));
+  CnnScope s(c);
+  const long long P = (long long)B * N * N, n2 = (long long)N * N;
+  MF_TRY(ensure_ws(c, P));
+  const int cin = (layer == 1) ? 1 : FC, cout = (layer == 4) ? 1 : FC;
+  // stage x: FP32 [B][cin][N][N] -> BF16 NHWC (layers 2-4) or FP32 plane (layer 1)
+  std::vector<float> hx((size_t)P * cin);
+  MF_HIP(hipMemcpyAsync(hx.data(), x, sizeof(float) * hx.size(), hipMemcpyDeviceToHost, c->st));
+  std::vector<float> hdz;
+  if (op == 1) {
+    hdz.resize((size_t)P * cout);
+    MF_HIP(hipMemcpyAsync(hdz.data(), dz, sizeof(float) * hdz.size(), hipMemcpyDeviceToHost, c->st));
+  }
+  MF_HIP(hipStreamSynchronize(c->st));
+  auto to_bf = [](float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+  };
+  auto nhwc = [&](const std::vector<float>& src) {
+    std::vector<uint16_t> d((size_t)P * FC);
+    for (long long b = 0; b < B; ++b)
+      for (int ch = 0; ch < FC; ++ch)
+        for (long long q = 0; q < n2; ++q) d[(size_t)((b * n2 + q) * FC + ch)] = to_bf(src[(size_t)((b * FC + ch) * n2 + q)]);
+    return d;
+  };
+  const unsigned tiles = (unsigned)((long long)B * (N / TPX) * (N / TROWS));
+  if (cin == FC) {
+    auto v = nhwc(hx);
+    MF_HIP(hipMemcpyAsync(c->a2, v.data(), sizeof(uint16_t) * v.size(), hipMemcpyHostToDevice, c->st));
+  } else {
+    MF_HIP(hipMemcpyAsync(c->xin, hx.data(), sizeof(float) * P, hipMemcpyHostToDevice, c->st));
+  }
+  if (op == 0) {
+    if (layer == 1)
+      hipLaunchKernelGGL(k_conv1_fwd, dim3(nb256(P)), dim3(256), 0, c->st, c->xin, c->w1b, c->prm + CnnOffsets::b1,
+                         (uint16_t*)nullptr, out, N, P, 1);
+    else if (layer == 4)
+      hipLaunchKernelGGL(k_conv4_fwd, dim3(nb256(P)), dim3(256), 0, c->st, c->a2, c->w4b, c->prm + CnnOffsets::b4, out,
+                         N, P);
+    else
+      hipLaunchKernelGGL((k_conv_mma<MM_Z>), dim3(tiles), dim3(256), 0, c->st, c->a2, layer == 2 ? c->w2f : c->w3f,
+                         c->prm + (layer == 2 ? CnnOffsets::b2 : CnnOffsets::b3), (const uint16_t*)nullptr,
+                         (uint16_t*)nullptr, out, N, B);
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipStreamSynchronize(c->st));
+    return MUFFIN_OK;
+  }
+  // backward: dz rounded to BF16; dx without activation mask; parameter gradients to dparams
+  const int nw = cout * cin * 9 + cout;
+  float* gtmp = c->grad;  // reuse the gradient buffer as scratch
+  if (cout == FC) {
+    auto v = nhwc(hdz);
+    MF_HIP(hipMemcpyAsync(c->g3, v.data(), sizeof(uint16_t) * v.size(), hipMemcpyHostToDevice, c->st));
+  } else {
+    std::vector<float> r(hdz.size());
+    for (size_t i = 0; i < r.size(); ++i) {
+      uint32_t u = (uint32_t)to_bf(hdz[i]) << 16;
+      std::memcpy(&r[i], &u, 4);
+    }
+    MF_HIP(hipMemcpyAsync(c->dz4, r.data(), sizeof(float) * P, hipMemcpyHostToDevice, c->st));
+  }
+  const long long nseg = (long long)B * N * (N / TPX);
+  const unsigned wb = (unsigned)(nseg < kWgradBlocks ? nseg : kWgradBlocks);
+  if (layer == 4) {
+    hipLaunchKernelGGL(k_wgrad_single<4>, dim3(kSingleBlocks), dim3(256), 0, c->st, c->dz4, c->a2,
+                       (const uint16_t*)nullptr, (const float*)nullptr, c->partial, N, P);
+    MF_TRY(reduce_into(c, SPART, 9 * FC, kSingleBlocks, gtmp, 2));
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, c->st, c->partial + 9 * FC, SPART, 1, kSingleBlocks,
+                       gtmp + 9 * FC, 0);
+    hipLaunchKernelGGL(k_conv4_bwd_data, dim3(nb256(P)), dim3(256), 0, c->st, c->dz4, c->w4b, (const uint16_t*)nullptr,
+                       (uint16_t*)nullptr, out, N, P, 1);
+  } else if (layer == 1) {
+    hipLaunchKernelGGL(k_wgrad_single<1>, dim3(kSingleBlocks), dim3(256), 0, c->st, (const float*)nullptr,
+                       (const uint16_t*)nullptr, c->g3, c->xin, c->partial, N, P);
+    MF_TRY(reduce_into(c, SPART, SPART, kSingleBlocks, gtmp, 2));
+    MF_HIP(hipMemsetAsync(out, 0, sizeof(float) * P, c->st));  // input gradient of layer 1 is not used
+  } else {
+    hipLaunchKernelGGL(k_wgrad_mma, dim3(wb), dim3(192), 0, c->st, c->g3, c->a2, c->partial, N, nseg);
+    MF_TRY(reduce_into(c, WPART, WPART, (int)wb, gtmp, 1));
+    hipLaunchKernelGGL((k_conv_mma<MM_DRAW>), dim3(tiles), dim3(256), 0, c->st, c->g3, layer == 2 ? c->w2d : c->w3d,
+                       (const float*)nullptr, (const uint16_t*)nullptr, (uint16_t*)nullptr, out, N, B);
+  }
+  MF_HIP(hipGetLastError());
+  MF_HIP(hipMemcpyAsync(dparams, gtmp, sizeof(float) * nw, hipMemcpyDeviceToHost, c->st));
+  MF_HIP(hipStreamSynchronize(c->st));
+  return MUFFIN_OK;
+}
+
+}  // extern "C"
+
+// Warm start of a reconstruction context: normalise each dirty channel by its PSF sum (the
+// transfer function at zero frequency), run the network and use max(output, 0) as X.
+namespace mf {
+int cnn_warm_input(const float* Y, const float2* Hhat_T, int pitchN, float* out, int N, int L, hipStream_t st) {
+  // Hhat_T is [L][pitch][N]; entry (0, 0) of channel l sits at l * pitchN
+  const long long n2 = (long long)N * N;
+  hipLaunchKernelGGL(k_scale_planes, dim3(nb256(n2 * L)), dim3(256), 0, st, Y, reinterpret_cast<const float*>(Hhat_T),
+                     2 * pitchN, out, n2, L);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+}  // namespace mf

@@ -27,6 +27,9 @@ EXPORTS = [
     "muffin_set_x", "muffin_get_x", "muffin_get_u", "muffin_get_v", "muffin_state_size",
     "muffin_get_state", "muffin_set_state", "muffin_apply_op", "muffin_profile",
     "muffin_step_timed", "muffin_free", "muffin_strerror", "muffin_last_error",
+    "muffin_cnn_create", "muffin_cnn_param_count", "muffin_cnn_get_params", "muffin_cnn_set_params",
+    "muffin_cnn_predict", "muffin_cnn_loss_grad", "muffin_cnn_train_step", "muffin_cnn_layer",
+    "muffin_cnn_free", "muffin_warm_start",
 ]
 
 
@@ -61,6 +64,17 @@ _lib.muffin_strerror.argtypes = [ctypes.c_int]
 _lib.muffin_strerror.restype = ctypes.c_char_p
 _lib.muffin_last_error.argtypes = []
 _lib.muffin_last_error.restype = ctypes.c_char_p
+_lib.muffin_cnn_create.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.c_uint64, _vp]
+_lib.muffin_cnn_param_count.argtypes = [_vp, ctypes.POINTER(_i32)]
+_lib.muffin_cnn_get_params.argtypes = [_vp, _vp, _i32]
+_lib.muffin_cnn_set_params.argtypes = [_vp, _vp, _i32]
+_lib.muffin_cnn_predict.argtypes = [_vp, _vp, _vp, _i32, _i32]
+_lib.muffin_cnn_loss_grad.argtypes = [_vp, _vp, _vp, _i32, _i32, ctypes.POINTER(_dbl), _vp]
+_lib.muffin_cnn_train_step.argtypes = [_vp, _vp, _vp, _i32, _i32, ctypes.c_float, ctypes.POINTER(_dbl)]
+_lib.muffin_cnn_layer.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _i32]
+_lib.muffin_cnn_free.argtypes = [_vp]
+_lib.muffin_cnn_free.restype = None
+_lib.muffin_warm_start.argtypes = [_vp, _vp]
 
 
 class MuffinError(RuntimeError):
@@ -204,6 +218,10 @@ class Muffin:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(_lib.muffin_set_state(self._h, buf, len(blob)), "muffin_set_state")
 
+    def warm_start(self, net: "Cnn"):
+        _check(_lib.muffin_warm_start(self._h, net._h), "muffin_warm_start")
+        _torch().cuda.current_stream().synchronize()
+
     # ------------------------------------------------------------------ single operators
     def apply_op(self, op: int, x):
         torch = _torch()
@@ -216,6 +234,116 @@ class Muffin:
         _check(_lib.muffin_apply_op(self._h, op, _dev_ptr(x, in_shape, "in"),
                                     _dev_ptr(out, out_shape, "out")), "muffin_apply_op")
         return out
+
+
+class Cnn:
+    """The warm-start network (four 3x3 convolutions, BF16 MFMA kernels) on the current GPU."""
+
+    def __init__(self, seed: int = 0, features: int = 32):
+        h = ctypes.c_void_p()
+        _check(_lib.muffin_cnn_create(ctypes.byref(h), features, seed, _stream_handle()), "muffin_cnn_create")
+        self._h = h
+        n = _i32()
+        _check(_lib.muffin_cnn_param_count(self._h, ctypes.byref(n)), "muffin_cnn_param_count")
+        self.n_params = n.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.muffin_cnn_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(_lib.muffin_cnn_get_params(self._h, out.ctypes.data, self.n_params), "muffin_cnn_get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.shape != (self.n_params,):
+            raise ValueError("parameter vector has the wrong size")
+        _check(_lib.muffin_cnn_set_params(self._h, p.ctypes.data, self.n_params), "muffin_cnn_set_params")
+
+    @staticmethod
+    def _planes(x):
+        torch = _torch()
+        x = torch.as_tensor(x, dtype=torch.float32).cuda().contiguous()
+        if x.dim() != 3 or x.shape[1] != x.shape[2]:
+            raise ValueError("expected [B][N][N]")
+        return x
+
+    def predict(self, x):
+        torch = _torch()
+        x = self._planes(x)
+        out = torch.empty_like(x)
+        B, N = x.shape[0], x.shape[1]
+        _check(_lib.muffin_cnn_predict(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                       B, N), "muffin_cnn_predict")
+        torch.cuda.current_stream().synchronize()
+        return out
+
+    def loss_grad(self, x, target):
+        x, t = self._planes(x), self._planes(target)
+        loss = _dbl()
+        g = np.empty(self.n_params, dtype=np.float32)
+        _check(_lib.muffin_cnn_loss_grad(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                         x.shape[0], x.shape[1], ctypes.byref(loss), g.ctypes.data),
+               "muffin_cnn_loss_grad")
+        return loss.value, g
+
+    def train_step(self, x, target, lr: float) -> float:
+        x, t = self._planes(x), self._planes(target)
+        loss = _dbl()
+        _check(_lib.muffin_cnn_train_step(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                          x.shape[0], x.shape[1], lr, ctypes.byref(loss)), "muffin_cnn_train_step")
+        return loss.value
+
+    def layer(self, layer: int, op: int, x, dz=None):
+        """Single-layer forward (op 0) or backward (op 1) on FP32 [B][C][N][N] device tensors."""
+        torch = _torch()
+        x = torch.as_tensor(x, dtype=torch.float32).cuda().contiguous()
+        B, N = x.shape[0], x.shape[2]
+        cin, cout = (1 if layer == 1 else 32), (1 if layer == 4 else 32)
+        if op == 0:
+            out = torch.empty((B, cout, N, N), dtype=torch.float32, device="cuda")
+            _check(_lib.muffin_cnn_layer(self._h, layer, 0, ctypes.c_void_p(x.data_ptr()), None,
+                                         ctypes.c_void_p(out.data_ptr()), None, B, N), "muffin_cnn_layer")
+            return out
+        dz = torch.as_tensor(dz, dtype=torch.float32).cuda().contiguous()
+        out = torch.empty((B, cin, N, N), dtype=torch.float32, device="cuda")
+        dp = np.empty(cout * cin * 9 + cout, dtype=np.float32)
+        _check(_lib.muffin_cnn_layer(self._h, layer, 1, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(dz.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), dp.ctypes.data, B, N), "muffin_cnn_layer")
+        return out, dp
+
+
+def cnn_params_to_oracle(p: np.ndarray):
+    """Split the flat parameter vector into the [(w, b)] list of the network's four layers."""
+    p = np.asarray(p, dtype=np.float64)
+    shapes = [(32, 1), (32, 32), (32, 32), (1, 32)]
+    out, off = [], 0
+    for o, c in shapes:
+        w = p[off:off + o * c * 9].reshape(o, c, 3, 3)
+        off += o * c * 9
+        b = p[off:off + o]
+        off += o
+        out.append((w, b))
+    return out
+
+
+def cnn_params_from_oracle(params) -> np.ndarray:
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
 
 
 def last_error() -> str:

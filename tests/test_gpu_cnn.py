@@ -1,0 +1,99 @@
+"""Parity of the warm-start CNN (BF16 MFMA kernels) against the FP64 oracle on BF16-rounded
+operands: per layer forward, input gradient and weight gradient, the whole-network loss and
+gradient, one Adam step, inference and the warm start."""
+import numpy as np
+import pytest
+
+from oracle import cnn as oc
+from oracle import muffin as om
+from paper_1602_08847_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def net(lib):
+    with lib.Cnn(seed=3) as n:
+        yield n
+
+
+def rnd(shape, seed, scale=1.0):
+    return np.random.default_rng(seed).normal(scale=scale, size=shape)
+
+
+@pytest.mark.parametrize("layer", [1, 2, 3, 4])
+@pytest.mark.parametrize("N", [32, 64, 96])
+def test_layer_forward_and_backward(lib, net, layer, N):
+    B = 2
+    cin, cout = (1 if layer == 1 else 32), (1 if layer == 4 else 32)
+    params = lib.cnn_params_to_oracle(net.get_params())
+    w, b = params[layer - 1]
+    x = rnd((B, cin, N, N), 10 + layer)
+    dz = rnd((B, cout, N, N), 20 + layer, 1e-2)
+    xr, wr, dzr = oc.bf16_round(x), oc.bf16_round(w), oc.bf16_round(dz)
+    z = net.layer(layer, 0, x).double().cpu().numpy()
+    # only the FP32 accumulation order differs from the oracle on identical BF16 operands
+    assert rel(z, oc.conv_forward(xr, wr, b)) < 1e-5
+    dx, dp = net.layer(layer, 1, x, dz)
+    dw_ref, db_ref = oc.conv_weight_grad(xr, dzr)
+    nw = cout * cin * 9
+    assert rel(dp[:nw].reshape(w.shape), dw_ref) < 1e-5
+    assert rel(dp[nw:], db_ref) < 1e-5
+    if layer > 1:
+        assert rel(dx.double().cpu().numpy(), oc.conv_data_grad(dzr, wr)) < 1e-5
+
+
+def test_network_loss_and_gradient(lib, net):
+    B, N = 2, 64
+    x = np.abs(rnd((B, N, N), 31))
+    t = np.abs(rnd((B, N, N), 32, 0.5))
+    params = lib.cnn_params_to_oracle(net.get_params())
+    out, acts = oc.forward(params, x[:, None], bf16=True)
+    loss_ref, dout = oc.mse(out, t[:, None])
+    grads = oc.backward(params, acts, dout, bf16=True)
+    loss, g = net.loss_grad(x, t)
+    assert loss == pytest.approx(loss_ref, rel=1e-4)
+    # hidden activations are rounded to BF16 after an FP32 (GPU) or FP64 (oracle) sum, so a few
+    # round-half decisions can differ; each such flip moves one activation by one BF16 ulp
+    assert rel(g, lib.cnn_params_from_oracle(grads)) < 2e-3
+    pred = net.predict(x).double().cpu().numpy()
+    assert rel(pred, out[:, 0]) < 2e-3
+
+
+def test_adam_step_matches_oracle(lib):
+    B, N = 2, 32
+    x = np.abs(rnd((B, N, N), 41))
+    t = np.abs(rnd((B, N, N), 42, 0.5))
+    with lib.Cnn(seed=7) as n:
+        p0 = n.get_params().astype(np.float64)
+        _, g = n.loss_grad(x, t)
+        n.train_step(x, t, lr=1e-3)
+        p1 = n.get_params().astype(np.float64)
+    ref, _, _ = oc.adam_update(p0, g.astype(np.float64), np.zeros_like(p0), np.zeros_like(p0), t=1, lr=1e-3)
+    np.testing.assert_allclose(p1, ref, rtol=1e-5, atol=1e-8)
+
+
+def test_training_reduces_loss(lib):
+    B, N = 4, 32
+    x = np.abs(rnd((B, N, N), 51))
+    t = 0.5 * x
+    with lib.Cnn(seed=9) as n:
+        first = n.train_step(x, t, lr=3e-3)
+        for _ in range(60):
+            last = n.train_step(x, t, lr=3e-3)
+    assert last < 0.2 * first
+
+
+def test_warm_start_sets_positive_part_of_prediction(lib, net):
+    c = synth.make_cube(synth.CubeSpec(N=64, L=4, J=2, n_sources=4, n_baselines=100, seed=3))
+    with lib.Muffin(c.dirty, c.psf, J=2, mu_s=0.25, mu_lambda=3.0) as m:
+        m.warm_start(net)
+        X = m.get_x().double().cpu().numpy()
+        assert np.all(m.get_u().cpu().numpy() == 0) and np.all(m.get_v().cpu().numpy() == 0)
+    inp = c.dirty / c.psf.sum(axis=(1, 2))[:, None, None]
+    pred = net.predict(inp).double().cpu().numpy()
+    np.testing.assert_allclose(X, np.maximum(pred, 0), rtol=1e-5, atol=1e-6)
