@@ -144,7 +144,7 @@ int muffin_step_timed(muffin_ctx* ctx, int32_t n_iter, double* ms);
 
 /* ---------------------------------------------------------------------------------------------
  * Learned warm start (not part of the paper's method): a CNN that maps a dirty channel image,
- * normalised by the sum of its PSF, to an estimate of the reconstructed image; the primal-dual
+ * normalised by its PSF's main-lobe gain, to an estimate of the reconstructed image; the primal-dual
  * iteration refines from max(estimate, 0).  Four 3x3 convolutions 1 -> 32 -> 32 -> 32 -> 1 with
  * circular padding, bias, ReLU after the first three; BF16 weights and activations (rounded to
  * nearest even), FP32 accumulation; MSE loss and Adam (beta 0.9 / 0.999, eps 1e-8) on FP32 master
@@ -178,8 +178,8 @@ int muffin_cnn_train_step(muffin_cnn* net, const float* in, const float* target,
 int muffin_cnn_layer(muffin_cnn* net, int32_t layer, int32_t op, const float* x, const float* dz,
                      float* out, float* dparams, int32_t B, int32_t N);
 void muffin_cnn_free(muffin_cnn* net);
-/* Warm start: X = max(CNN(y_l / sum psf_l), 0) channel by channel, U = V = 0.  N must be a
- * multiple of 32. */
+/* Warm start: X = max(CNN(y_l / g_l), 0) channel by channel, U = V = 0, where g_l is the sum of
+ * psf_l over the 9 x 9 window centred on its origin.  N must be a multiple of 32. */
 int muffin_warm_start(muffin_ctx* ctx, muffin_cnn* net);
 
 void muffin_free(muffin_ctx* ctx);

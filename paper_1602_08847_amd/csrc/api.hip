@@ -27,7 +27,8 @@ int launch_power_spectrum(const float2* Hhat_T, float* P_T, const float* chan_w,
                           float scale, hipStream_t st);
 int launch_clamp_pos(float* x, long long n, hipStream_t st);
 int launch_scale_channels(float* x, const float* chan_w, long long npix, int nch, hipStream_t st);
-int cnn_warm_input(const float* Y, const float2* Hhat_T, int pitchN, float* out, int N, int L, hipStream_t st);
+int cnn_warm_input(const float* Y, const float* scale, float* out, int N, int L, hipStream_t st);
+int launch_psf_lobe(const float* psf, float* out, int N, int L, int radius, hipStream_t st);
 }  // namespace mf
 
 using namespace mf;
@@ -54,6 +55,7 @@ struct muffin_ctx {
   float2 *twL = nullptr, *csL = nullptr;
   float *W = nullptr, *WT = nullptr;
   float* chan_w = nullptr;
+  float* psf_lobe = nullptr;  // [L] sum of each PSF over the 9 x 9 window at its origin
   double* partial = nullptr;
   double* dres = nullptr;  // device scalars
   double tau = 0, sigma = 1, rho = 1, beta = 0, K2 = 0, Ws2 = 0, delta = 0;
@@ -276,7 +278,7 @@ void destroy(muffin_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   void* bufs[] = {c->X, c->U, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT, c->S, c->Hhat_T, c->P_T,
-                  c->tw, c->twL, c->csL, c->W, c->WT, c->chan_w, c->partial, c->dres};
+                  c->tw, c->twL, c->csL, c->W, c->WT, c->chan_w, c->psf_lobe, c->partial, c->dres};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   hipEvent_t evs[] = {c->ev_in, c->ev_out, c->e0, c->e1, c->ph[0], c->ph[1], c->ph[2], c->ph[3], c->ph[4]};
@@ -346,6 +348,7 @@ int init_impl(muffin_ctx* c, const muffin_params* p, const float* dirty, const f
   MF_TRY(dalloc(&c->WT, (long long)c->L * c->L));
   MF_TRY(dalloc(&c->partial, kMaxPartials));
   MF_TRY(dalloc(&c->dres, 16));
+  MF_TRY(dalloc(&c->psf_lobe, c->L));
   if (!c->chan_w_host.empty()) MF_TRY(dalloc(&c->chan_w, c->L));
 
   StreamScope scope(c);
@@ -387,6 +390,7 @@ int init_impl(muffin_ctx* c, const muffin_params* p, const float* dirty, const f
   MF_HIP(hipStreamSynchronize(st));
   if (bad != 0) return set_error("NaN or Inf in dirty or psf"), MUFFIN_ENONFINITE;
 
+  MF_TRY(launch_psf_lobe(c->cT, c->psf_lobe, c->N, c->L, 4, st));
   // transfer functions: Hhat = FFT2(ifftshift(psf)), P = w |Hhat|^2 / N^2
   const float inv_n2 = 1.f / ((float)c->N * c->N);
   MF_TRY(launch_rows_r2c(c->cT, c->S, c->L, c->g, c->tw, true, st));
@@ -688,7 +692,7 @@ int muffin_warm_start(muffin_ctx* c, muffin_cnn* net) {
   if (!c || !net) return set_error("bad arguments"), MUFFIN_EINVAL;
   if (c->N % 32) return set_error("warm start needs N to be a multiple of 32"), MUFFIN_EINVAL;
   StreamScope scope(c);
-  MF_TRY(cnn_warm_input(c->Y, c->Hhat_T, c->g.pitch * c->N, c->cA, c->N, c->L, c->st));
+  MF_TRY(cnn_warm_input(c->Y, c->psf_lobe, c->cA, c->N, c->L, c->st));
   MF_HIP(hipStreamSynchronize(c->st));
   MF_TRY(muffin_cnn_predict(net, c->cA, c->cB, c->L, c->N));
   MF_HIP(hipDeviceSynchronize());

@@ -813,14 +813,38 @@ int muffin_cnn_layer(muffin_cnn* c, int32_t layer, int32_t op, const float* x, c
 
 }  // extern "C"
 
-// Warm start of a reconstruction context: normalise each dirty channel by its PSF sum (the
-// transfer function at zero frequency), run the network and use max(output, 0) as X.
+// Warm start of a reconstruction context: each dirty channel is divided by the sum of its PSF over
+// the 9 x 9 window at the PSF origin (the gain of the PSF main lobe over the network's receptive
+// field), the network runs, and max(output, 0) becomes X.
 namespace mf {
-int cnn_warm_input(const float* Y, const float2* Hhat_T, int pitchN, float* out, int N, int L, hipStream_t st) {
-  // Hhat_T is [L][pitch][N]; entry (0, 0) of channel l sits at l * pitchN
+__global__ void __launch_bounds__(256) k_psf_lobe(const float* __restrict__ psf, float* __restrict__ out, int N,
+                                                  int radius) {
+  __shared__ float red[256];
+  const int l = blockIdx.x, w = 2 * radius + 1;
+  const float* p = psf + (long long)l * N * N;
+  float s = 0.f;
+  for (int i = threadIdx.x; i < w * w; i += 256) {
+    const int dy = i / w - radius, dx = i % w - radius;
+    s += p[(long long)wrapn(N / 2 + dy, N) * N + wrapn(N / 2 + dx, N)];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[l] = red[0];
+}
+
+int launch_psf_lobe(const float* psf, float* out, int N, int L, int radius, hipStream_t st) {
+  hipLaunchKernelGGL(k_psf_lobe, dim3(L), dim3(256), 0, st, psf, out, N, radius);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+int cnn_warm_input(const float* Y, const float* scale, float* out, int N, int L, hipStream_t st) {
   const long long n2 = (long long)N * N;
-  hipLaunchKernelGGL(k_scale_planes, dim3(nb256(n2 * L)), dim3(256), 0, st, Y, reinterpret_cast<const float*>(Hhat_T),
-                     2 * pitchN, out, n2, L);
+  hipLaunchKernelGGL(k_scale_planes, dim3(nb256(n2 * L)), dim3(256), 0, st, Y, scale, 1, out, n2, L);
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }

@@ -17,6 +17,10 @@ LIB_PATH = os.path.join(_HERE, "libmuffin.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libmuffin.so not built at {LIB_PATH}; run __graft_entry__.build()")
+# torch is loaded first so that libmuffin binds to the HIP runtime torch already uses (both carry
+# the same soname): device pointers and streams are shared with torch.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ESTEP, ESTATE = 0, -1, -2, -3, -4, -5, -6

@@ -1,0 +1,195 @@
+"""Learned warm start for the MUFFIN iteration: training data, training loop and the
+time-to-tolerance comparison against a cold start.
+
+Training pairs are (dirty channel image / PSF sum, plain-solver reconstruction of that channel):
+seeded synthetic cubes are reconstructed by the library's own primal-dual iteration, and the
+network is trained by the library's own forward/backward kernels (muffin_cnn_train_step).  The
+comparison runs both starts with identical step sizes against the same reference objective f_ref
+(the minimum of a long plain run) and counts iterations and seconds until
+(f - f_ref) / |f_ref| <= tol, including the network's inference time for the warm start.
+
+python -m paper_1602_08847_amd.warmstart --help
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import muffin, synth
+
+MU_S, MU_L = 0.25, 3.0
+
+
+def lobe_gain(psf: np.ndarray, radius: int = 4) -> np.ndarray:
+    """Sum of each PSF over the (2r+1)^2 window at its origin (N/2, N/2): the main-lobe gain."""
+    N = psf.shape[-1]
+    c = N // 2
+    return psf[:, c - radius:c + radius + 1, c - radius:c + radius + 1].sum(axis=(1, 2))
+
+
+def normalised_input(cube) -> np.ndarray:
+    """Dirty channel images divided by their PSF main-lobe gains (the network's input)."""
+    return (cube.dirty / lobe_gain(cube.psf)[:, None, None]).astype(np.float32)
+
+
+def build_training_set(n_cubes: int, spec: synth.CubeSpec, iters: int, sigma: float, seed0: int = 10000,
+                       log=print):
+    """Solve n_cubes seeded cubes with the plain iteration; returns GPU tensors (inputs, targets)."""
+    import torch
+    ins, tgs = [], []
+    t0 = time.time()
+    for i in range(n_cubes):
+        s = synth.CubeSpec(**{**spec.__dict__, "seed": seed0 + i})
+        cube = synth.make_cube(s, dtype=np.float32, with_sky=False)
+        with muffin.Muffin(cube.dirty, cube.psf, J=s.J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as m:
+            m.step(iters)
+            tgs.append(m.get_x())
+        ins.append(torch.from_numpy(normalised_input(cube)).cuda())
+        if log and (i + 1) % max(1, n_cubes // 8) == 0:
+            log(f"[warmstart] solved {i + 1}/{n_cubes} training cubes ({time.time() - t0:.1f}s)")
+    return torch.cat(ins), torch.cat(tgs)
+
+
+def train(net: muffin.Cnn, inputs, targets, epochs: int, batch: int, lr: float, seed: int = 0, log=print):
+    """Adam on shuffled batches of channel images; returns the per-epoch mean loss."""
+    import torch
+    n = inputs.shape[0]
+    g = torch.Generator().manual_seed(seed)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).cuda()
+        tot, cnt = 0.0, 0
+        for b0 in range(0, n - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            tot += net.train_step(inputs[idx].contiguous(), targets[idx].contiguous(), lr)
+            cnt += 1
+        hist.append(tot / max(cnt, 1))
+        if log:
+            log(f"[warmstart] epoch {ep + 1}/{epochs} loss {hist[-1]:.4e}")
+    return hist
+
+
+def time_to_tolerance(m: muffin.Muffin, f_ref: float, tol: float, check_every: int, max_iter: int,
+                      trace: list | None = None, trace_every: int = 500):
+    """Iterate until (f - f_ref)/|f_ref| <= tol; returns (iterations, seconds, final f).
+    With trace, (iteration, relative gap) pairs are appended every trace_every iterations."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    f = m.objective()[0]
+    if trace is not None:
+        trace.append((0, (f - f_ref) / abs(f_ref)))
+    while (f - f_ref) / abs(f_ref) > tol and it < max_iter:
+        m.step(check_every)
+        it += check_every
+        f = m.objective()[0]
+        if trace is not None and (it % trace_every == 0 or it in (50, 100, 200, 300)):
+            trace.append((it, (f - f_ref) / abs(f_ref)))
+        if it % 20000 == 0:
+            print(f"[warmstart] {it} iterations, gap {(f - f_ref) / abs(f_ref):.3e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return it, time.perf_counter() - t0, f
+
+
+def reference_objective(cube, J: int, sigma: float, iters: int, check_every: int = 100, log=None) -> float:
+    """Minimum objective over a long plain run (checked every check_every iterations)."""
+    best = math.inf
+    with muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as m:
+        for k in range(iters // check_every):
+            m.step(check_every)
+            best = min(best, m.objective()[0])
+            if log and ((k + 1) * check_every) % 20000 == 0:
+                log(f"[warmstart] reference run {(k + 1) * check_every} iterations, f {best:.10e}")
+    return best
+
+
+def compare(net: muffin.Cnn, cube, J: int, sigma: float, tol: float, f_ref: float, check_every: int,
+            max_iter: int) -> dict:
+    """Cold start (X = 0) against the warm start (X = max(CNN, 0)) on the same cube."""
+    import torch
+    out = {"tol": tol, "f_ref": f_ref, "sigma": sigma}
+    with muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as m:
+        out["f0_cold"] = float(m.objective()[0])
+        tr = []
+        it, sec, f = time_to_tolerance(m, f_ref, tol, check_every, max_iter, tr)
+        out.update(cold_iters=it, cold_s=sec, cold_f=f, cold_trace=tr)
+    with muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as m:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.warm_start(net)
+        torch.cuda.synchronize()
+        infer = time.perf_counter() - t0
+        out["f0_warm"] = float(m.objective()[0])
+        if cube.sky is not None:
+            x0 = m.get_x().double().cpu().numpy()
+            out["snr0_warm_db"] = float(10 * np.log10(np.sum(cube.sky ** 2) / np.sum((x0 - cube.sky) ** 2)))
+            out["snr_dirty_norm_db"] = float(10 * np.log10(np.sum(cube.sky ** 2) / np.sum(
+                (np.maximum(normalised_input(cube), 0) - cube.sky) ** 2)))
+        tr = []
+        it, sec, f = time_to_tolerance(m, f_ref, tol, check_every, max_iter, tr)
+        out.update(warm_iters=it, warm_s=sec + infer, warm_infer_s=infer, warm_f=f, warm_trace=tr)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--train-cubes", type=int, default=48)
+    ap.add_argument("--train-N", type=int, default=256)
+    ap.add_argument("--train-L", type=int, default=64)
+    ap.add_argument("--train-J", type=int, default=4)
+    ap.add_argument("--train-iters", type=int, default=1000)
+    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--sigma", type=float, default=100.0)
+    ap.add_argument("--test", default="cube256_L64_J4", help="workload name of the test cube")
+    ap.add_argument("--test-seed", type=int, default=0)
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--ref-iters", type=int, default=20000)
+    ap.add_argument("--check-every", type=int, default=20)
+    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--load-params", default=None, help="skip training: load a parameter vector (.npy)")
+    a = ap.parse_args(argv)
+    log = lambda s: print(s, file=sys.stderr, flush=True)
+    spec = synth.CubeSpec(N=a.train_N, L=a.train_L, J=a.train_J, n_sources=20, n_baselines=2000)
+    net = muffin.Cnn(seed=1)
+    t_data = t_train = 0.0
+    hist = []
+    if a.load_params:
+        net.set_params(np.load(a.load_params))
+    else:
+        t0 = time.time()
+        inputs, targets = build_training_set(a.train_cubes, spec, a.train_iters, a.sigma, log=log)
+        t_data = time.time() - t0
+        t0 = time.time()
+        hist = train(net, inputs, targets, a.epochs, a.batch, a.lr, log=log)
+        t_train = time.time() - t0
+        del inputs, targets
+    tspec = synth.WORKLOADS[a.test]
+    tspec = synth.CubeSpec(**{**tspec.__dict__, "seed": a.test_seed})
+    cube = synth.make_cube(tspec, dtype=np.float32)
+    t0 = time.time()
+    f_ref = reference_objective(cube, tspec.J, a.sigma, a.ref_iters, log=log)
+    t_ref = time.time() - t0
+    log(f"[warmstart] f_ref {f_ref:.8e} from {a.ref_iters} iterations ({t_ref:.1f}s)")
+    res = compare(net, cube, tspec.J, a.sigma, a.tol, f_ref, a.check_every, a.max_iter)
+    res.update(train_cubes=a.train_cubes, train_iters=a.train_iters, epochs=a.epochs, loss_hist=hist,
+               t_data_s=t_data, t_train_s=t_train, t_ref_s=t_ref, test=a.test, ref_iters=a.ref_iters)
+    line = json.dumps(res)
+    print(line, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(line + "\n")
+        np.save(a.out.replace(".json", "_params.npy"), net.get_params())
+    net.close()
+
+
+if __name__ == "__main__":
+    main()
