@@ -183,6 +183,33 @@ void muffin_cnn_free(muffin_cnn* net);
 int muffin_warm_start(muffin_ctx* ctx, muffin_cnn* net);
 
 void muffin_free(muffin_ctx* ctx);
+
+/* Autotuner: times every band height (rows per workgroup) of the IUWT band kernels, for each scale
+ * of this context's sizes, keeps the fastest (process-wide, per image side, scale and kernel) and
+ * recaptures the iteration.  Only scratch planes are written: the state is unchanged.  report (may
+ * be NULL) receives a JSON description of the candidates and choices, truncated to report_len. */
+int muffin_autotune(muffin_ctx* ctx, int32_t reps, char* report, size_t report_len);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batches of independent cubes of uneven sizes (not part of the paper's method).  Cubes that share
+ * N, J, generation, coarse weighting, mu_s, sigma and rho form one group: the per-channel phases
+ * run once over the packed channels of all cubes of a group, the per-pixel spectral step and the
+ * objective per cube (with the cube's own L, mu_lambda and tau).  Each group replays a captured
+ * graph on its own stream; groups run concurrently.  p, dirty and psf are arrays of n_cubes entries;
+ * every cube must pass muffin_init's checks.  Cube indices follow the input order.
+ * --------------------------------------------------------------------------------------------- */
+typedef struct muffin_batch muffin_batch;
+int muffin_batch_init(muffin_batch** out, int32_t n_cubes, const muffin_params* p, const float* const* dirty,
+                      const float* const* psf, int inputs_on_device, void* hip_stream);
+int muffin_batch_step(muffin_batch* batch, int32_t n_iter);
+/* n_iter iterations of every cube; *ms is the device time between two events of the caller's stream. */
+int muffin_batch_step_timed(muffin_batch* batch, int32_t n_iter, double* ms);
+int muffin_batch_objective(muffin_batch* batch, int32_t cube, double out[4]);
+int muffin_batch_get_x(muffin_batch* batch, int32_t cube, float* x, int on_device);
+int muffin_batch_info(muffin_batch* batch, int32_t cube, double out[8]);
+int muffin_batch_autotune(muffin_batch* batch, int32_t reps, char* report, size_t report_len);
+void muffin_batch_free(muffin_batch* batch);
+
 const char* muffin_strerror(int code);
 const char* muffin_last_error(void);
 

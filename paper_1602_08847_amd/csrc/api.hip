@@ -33,8 +33,19 @@ int launch_psf_lobe(const float* psf, float* out, int N, int L, int radius, hipS
 
 using namespace mf;
 
+// One cube of a context: its channels [ch0, ch0 + L) of the packed arrays, its spectral weight and
+// step sizes, and its cosine-transform tables.  A context built by muffin_init holds one segment;
+// a batch group holds every cube of one image side.
+struct Seg {
+  int ch0 = 0, L = 0;
+  double mu_l = 0, tau = 0, beta = 0, K2 = 0, delta = 0;
+  float *W = nullptr, *WT = nullptr;
+  float2 *twL = nullptr, *csL = nullptr;
+};
+
 struct muffin_ctx {
   muffin_params p{};
+  std::vector<Seg> segs;
   std::vector<float> chan_w_host;
   int N = 0, L = 0, J = 0, gen = 2;
   long long npix = 0, cube = 0;
@@ -52,13 +63,11 @@ struct muffin_ctx {
   float2* Hhat_T = nullptr;
   float* P_T = nullptr;
   float2* tw = nullptr;
-  float2 *twL = nullptr, *csL = nullptr;
-  float *W = nullptr, *WT = nullptr;
   float* chan_w = nullptr;
   float* psf_lobe = nullptr;  // [L] sum of each PSF over the 9 x 9 window at its origin
   double* partial = nullptr;
   double* dres = nullptr;  // device scalars
-  double tau = 0, sigma = 1, rho = 1, beta = 0, K2 = 0, Ws2 = 0, delta = 0;
+  double sigma = 1, rho = 1, Ws2 = 0;
   float omega_c = 1.f;
   long long iter = 0;
   hipGraph_t graph = nullptr;
@@ -200,23 +209,27 @@ int enqueue_gradient(muffin_ctx* c, const float* x, float* out, const float* s, 
 }
 
 int enqueue_spectral(muffin_ctx* c) {
-  SpectralArgs a;
-  a.X = c->X;
-  a.Q = c->Q;
-  a.V = c->V;
-  a.D = c->D;
-  a.W = c->W;
-  a.WT = c->WT;
-  a.twL = c->twL;
-  a.csL = c->csL;
-  a.npix = c->npix;
-  a.L = c->L;
-  a.use_fft = spectral_has_fft(c->L) ? 1 : 0;
-  a.tau = (float)c->tau;
-  a.mu_l = (float)c->p.mu_lambda;
-  a.smu_l = (float)(c->sigma * c->p.mu_lambda);
-  a.rho = (float)c->rho;
-  return launch_spectral_step(a, c->st);
+  for (const Seg& s : c->segs) {
+    const long long off = (long long)s.ch0 * c->npix;
+    SpectralArgs a;
+    a.X = c->X + off;
+    a.Q = c->Q + off;
+    a.V = c->V + off;
+    a.D = c->D + off;
+    a.W = s.W;
+    a.WT = s.WT;
+    a.twL = s.twL;
+    a.csL = s.csL;
+    a.npix = c->npix;
+    a.L = s.L;
+    a.use_fft = spectral_has_fft(s.L) ? 1 : 0;
+    a.tau = (float)s.tau;
+    a.mu_l = (float)s.mu_l;
+    a.smu_l = (float)(c->sigma * s.mu_l);
+    a.rho = (float)c->rho;
+    MF_TRY(launch_spectral_step(a, c->st));
+  }
+  return MUFFIN_OK;
 }
 
 // With marks, phase boundaries are recorded in marks[0..4] and, for the second-generation
@@ -236,38 +249,41 @@ int enqueue_iteration(muffin_ctx* c, hipEvent_t* marks, int timed_family = 0) {
   return MUFFIN_OK;
 }
 
-// Objective terms at X into dres[1..3] (data, spatial l1 unweighted by mu_s, spectral l1).
-int enqueue_objective(muffin_ctx* c) {
-  const long long np = c->npix;
+// Objective terms of segment si at X into dres[1..3] (data, spatial l1 unweighted by mu_s, spectral l1).
+int enqueue_objective(muffin_ctx* c, int si) {
+  const Seg& s = c->segs[si];
+  const long long np = c->npix, off = (long long)s.ch0 * np;
+  const int nch = s.L;
+  float* X = c->X + off;
   MF_HIP(hipMemsetAsync(c->dres, 0, sizeof(double) * 4, c->st));
   int nb = 0;
-  MF_TRY(launch_rows_r2c(c->X, c->S, c->L, c->g, c->tw, false, c->st));
-  MF_TRY(launch_cols(c->S, c->L, c->g, c->tw, COL_CPLX, nullptr, c->Hhat_T, 1.f / ((float)c->N * c->N), nullptr,
-                     c->st));
-  MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_RESID, nullptr, nullptr, nullptr, 0.f, c->Y, c->chan_w,
-                         c->partial, &nb, c->st));
+  MF_TRY(launch_rows_r2c(X, c->S, nch, c->g, c->tw, false, c->st));
+  MF_TRY(launch_cols(c->S, nch, c->g, c->tw, COL_CPLX, nullptr, c->Hhat_T + (long long)s.ch0 * c->g.pitch * c->N,
+                     1.f / ((float)c->N * c->N), nullptr, c->st));
+  MF_TRY(launch_rows_c2r(c->S, nch, c->g, c->tw, EPI_RESID, nullptr, nullptr, nullptr, 0.f, c->Y + off,
+                         c->chan_w ? c->chan_w + s.ch0 : nullptr, c->partial, &nb, c->st));
   MF_TRY(launch_reduce_sum(c->partial, nb, c->dres + 1, 0, c->st));
-  const float* cur = c->X;
+  const float* cur = X;
   float* bufs[2] = {c->cA, c->cB};
   for (int j = 0; j < c->J; ++j) {
     float* nxt = bufs[j & 1];
-    MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np),
-                         PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
+    MF_TRY(launch_atrous(SM_SMOOTH, c->N, nch, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np), PlaneOut{},
+                         0.f, 1.f, nullptr, nullptr, c->st));
     if (c->gen == 2)
-      MF_TRY(launch_atrous(SM_DETAIL_ABS, c->N, c->L, j, pref(nxt, np), PlaneRef{}, pref(cur, np), PlaneOut{},
+      MF_TRY(launch_atrous(SM_DETAIL_ABS, c->N, nch, j, pref(nxt, np), PlaneRef{}, pref(cur, np), PlaneOut{},
                            PlaneOut{}, 0.f, 1.f, c->partial, &nb, c->st));
     else
-      MF_TRY(launch_pointwise(PT_ABS_DIFF, c->N, c->L, pref(nxt, np), pref(cur, np), PlaneOut{}, 0.f, 1.f,
-                              c->partial, &nb, c->st));
+      MF_TRY(launch_pointwise(PT_ABS_DIFF, c->N, nch, pref(nxt, np), pref(cur, np), PlaneOut{}, 0.f, 1.f, c->partial,
+                              &nb, c->st));
     MF_TRY(launch_reduce_sum(c->partial, nb, c->dres + 2, 1, c->st));
     cur = nxt;
   }
   if (c->omega_c != 0.f) {
-    MF_TRY(launch_pointwise(PT_ABS, c->N, c->L, pref(cur, np), PlaneRef{}, PlaneOut{}, 0.f, 1.f, c->partial, &nb,
+    MF_TRY(launch_pointwise(PT_ABS, c->N, nch, pref(cur, np), PlaneRef{}, PlaneOut{}, 0.f, 1.f, c->partial, &nb,
                             c->st));
     MF_TRY(launch_reduce_sum(c->partial, nb, c->dres + 2, 1, c->st));
   }
-  MF_TRY(launch_dct_abs(c->X, c->WT, np, c->L, c->partial, &nb, c->st));
+  MF_TRY(launch_dct_abs(X, s.WT, np, nch, c->partial, &nb, c->st));
   MF_TRY(launch_reduce_sum(c->partial, nb, c->dres + 3, 0, c->st));
   return MUFFIN_OK;
 }
@@ -278,7 +294,12 @@ void destroy(muffin_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   void* bufs[] = {c->X, c->U, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT, c->S, c->Hhat_T, c->P_T,
-                  c->tw, c->twL, c->csL, c->W, c->WT, c->chan_w, c->psf_lobe, c->partial, c->dres};
+                  c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres};
+  for (Seg& s : c->segs) {
+    void* sb[] = {s.W, s.WT, s.twL, s.csL};
+    for (void* b : sb)
+      if (b) (void)hipFree(b);
+  }
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   hipEvent_t evs[] = {c->ev_in, c->ev_out, c->e0, c->e1, c->ph[0], c->ph[1], c->ph[2], c->ph[3], c->ph[4]};
@@ -302,20 +323,40 @@ int copy_out(float* dst, const float* src, size_t n, int on_device, hipStream_t 
   return MUFFIN_OK;
 }
 
-int init_impl(muffin_ctx* c, const muffin_params* p, const float* dirty, const float* psf, int on_device) {
+// Build a context over n cubes that share N, J, generation, coarse weighting, mu_s, sigma and rho
+// (checked by the caller); their channels are packed one cube after the other.
+int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float* const* dirty,
+               const float* const* psf, int on_device) {
+  const muffin_params* p = ps[0];
   c->p = *p;
+  c->p.chan_weight = nullptr;
   c->N = p->N;
-  c->L = p->L;
   c->J = p->J;
   c->gen = p->iuwt_gen;
   c->npix = (long long)p->N * p->N;
-  c->cube = c->npix * p->L;
   c->g = fft_geom(p->N);
   c->omega_c = p->penalize_coarse ? 1.f : 0.f;
   c->sigma = p->sigma;
   c->rho = p->rho;
-  if (p->chan_weight) c->chan_w_host.assign(p->chan_weight, p->chan_weight + p->L);
-  c->p.chan_weight = nullptr;
+  int total = 0;
+  bool any_w = false;
+  for (int i = 0; i < n; ++i) {
+    Seg s;
+    s.ch0 = total;
+    s.L = ps[i]->L;
+    s.mu_l = ps[i]->mu_lambda;
+    total += s.L;
+    any_w = any_w || ps[i]->chan_weight;
+    c->segs.push_back(s);
+  }
+  c->L = total;
+  c->cube = c->npix * total;
+  if (any_w) {
+    c->chan_w_host.assign(total, 1.f);
+    for (int i = 0; i < n; ++i)
+      if (ps[i]->chan_weight)
+        std::copy(ps[i]->chan_weight, ps[i]->chan_weight + ps[i]->L, c->chan_w_host.begin() + c->segs[i].ch0);
+  }
   MF_HIP(hipGetDevice(&c->device));
   MF_HIP(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking));
   for (hipEvent_t* e : {&c->ev_in, &c->ev_out}) MF_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
@@ -324,7 +365,7 @@ int init_impl(muffin_ctx* c, const muffin_params* p, const float* dirty, const f
   for (auto& e : c->kev) MF_HIP(hipEventCreate(&e));
   MF_TRY(fft_init_attrs(c->N));
   MF_TRY(atrous_init_attrs());
-  MF_TRY(spectral_init_attrs(c->L));
+  for (const Seg& s : c->segs) MF_TRY(spectral_init_attrs(s.L));
 
   const long long cube = c->cube;
   const long long spec = (long long)c->L * c->N * c->g.pitch;
@@ -342,10 +383,12 @@ int init_impl(muffin_ctx* c, const muffin_params* p, const float* dirty, const f
   MF_TRY(dalloc(&c->Hhat_T, spec));
   MF_TRY(dalloc(&c->P_T, spec));
   MF_TRY(dalloc(&c->tw, c->N));
-  MF_TRY(dalloc(&c->twL, c->L));
-  MF_TRY(dalloc(&c->csL, c->L));
-  MF_TRY(dalloc(&c->W, (long long)c->L * c->L));
-  MF_TRY(dalloc(&c->WT, (long long)c->L * c->L));
+  for (Seg& s : c->segs) {
+    MF_TRY(dalloc(&s.twL, s.L));
+    MF_TRY(dalloc(&s.csL, s.L));
+    MF_TRY(dalloc(&s.W, (long long)s.L * s.L));
+    MF_TRY(dalloc(&s.WT, (long long)s.L * s.L));
+  }
   MF_TRY(dalloc(&c->partial, kMaxPartials));
   MF_TRY(dalloc(&c->dres, 16));
   MF_TRY(dalloc(&c->psf_lobe, c->L));
@@ -356,31 +399,37 @@ int init_impl(muffin_ctx* c, const muffin_params* p, const float* dirty, const f
   hipStream_t st = c->st;
   MF_HIP(hipMemsetAsync(c->S, 0, sizeof(float2) * spec, st));
   MF_HIP(hipMemsetAsync(c->dres, 0, sizeof(double) * 16, st));
-  MF_TRY(copy_in(c->Y, dirty, cube, on_device, st));
-  MF_TRY(copy_in(c->cT, psf, cube, on_device, st));
+  for (int i = 0; i < n; ++i) {
+    const long long off = (long long)c->segs[i].ch0 * c->npix, cnt = (long long)c->segs[i].L * c->npix;
+    MF_TRY(copy_in(c->Y + off, dirty[i], cnt, on_device, st));
+    MF_TRY(copy_in(c->cT + off, psf[i], cnt, on_device, st));
+  }
   if (c->chan_w) MF_TRY(copy_in(c->chan_w, c->chan_w_host.data(), c->L, 0, st));
   {
     auto tw = fft_twiddles(c->N);
     MF_HIP(hipMemcpyAsync(c->tw, tw.data(), sizeof(float2) * c->N, hipMemcpyHostToDevice, st));
-    auto twl = fft_twiddles(c->L);
-    std::vector<float2> cs(c->L);
-    for (int k = 0; k < c->L; ++k) {
-      const double th = M_PI * k / (2.0 * c->L);
-      cs[k] = make_float2((float)std::cos(th), (float)std::sin(th));
-    }
-    MF_HIP(hipMemcpyAsync(c->twL, twl.data(), sizeof(float2) * c->L, hipMemcpyHostToDevice, st));
-    MF_HIP(hipMemcpyAsync(c->csL, cs.data(), sizeof(float2) * c->L, hipMemcpyHostToDevice, st));
-    std::vector<float> W((size_t)c->L * c->L), WT((size_t)c->L * c->L);
-    for (int l = 0; l < c->L; ++l)
-      for (int k = 0; k < c->L; ++k) {
-        const double s = (k == 0) ? std::sqrt(1.0 / c->L) : std::sqrt(2.0 / c->L);
-        const double v = s * std::cos(M_PI * (2.0 * l + 1.0) * k / (2.0 * c->L));
-        W[(size_t)l * c->L + k] = (float)v;
-        WT[(size_t)k * c->L + l] = (float)v;
+    for (Seg& s : c->segs) {
+      const int L = s.L;
+      auto twl = fft_twiddles(L);
+      std::vector<float2> cs(L);
+      for (int k = 0; k < L; ++k) {
+        const double th = M_PI * k / (2.0 * L);
+        cs[k] = make_float2((float)std::cos(th), (float)std::sin(th));
       }
-    MF_HIP(hipMemcpyAsync(c->W, W.data(), sizeof(float) * W.size(), hipMemcpyHostToDevice, st));
-    MF_HIP(hipMemcpyAsync(c->WT, WT.data(), sizeof(float) * WT.size(), hipMemcpyHostToDevice, st));
-    MF_HIP(hipStreamSynchronize(st));
+      std::vector<float> W((size_t)L * L), WT((size_t)L * L);
+      for (int l = 0; l < L; ++l)
+        for (int k = 0; k < L; ++k) {
+          const double sk = (k == 0) ? std::sqrt(1.0 / L) : std::sqrt(2.0 / L);
+          const double v = sk * std::cos(M_PI * (2.0 * l + 1.0) * k / (2.0 * L));
+          W[(size_t)l * L + k] = (float)v;
+          WT[(size_t)k * L + l] = (float)v;
+        }
+      MF_HIP(hipMemcpyAsync(s.twL, twl.data(), sizeof(float2) * L, hipMemcpyHostToDevice, st));
+      MF_HIP(hipMemcpyAsync(s.csL, cs.data(), sizeof(float2) * L, hipMemcpyHostToDevice, st));
+      MF_HIP(hipMemcpyAsync(s.W, W.data(), sizeof(float) * W.size(), hipMemcpyHostToDevice, st));
+      MF_HIP(hipMemcpyAsync(s.WT, WT.data(), sizeof(float) * WT.size(), hipMemcpyHostToDevice, st));
+      MF_HIP(hipStreamSynchronize(st));
+    }
   }
   // non-finite inputs
   MF_TRY(launch_count_nonfinite(c->Y, cube, c->partial, c->dres + 0, st));
@@ -402,21 +451,25 @@ int init_impl(muffin_ctx* c, const muffin_params* p, const float* dirty, const f
   MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_STORE, c->B, nullptr, nullptr, 0.f, nullptr, nullptr, nullptr,
                          nullptr, st));
   if (c->chan_w) MF_TRY(launch_scale_channels(c->B, c->chan_w, c->npix, c->L, st));
-  // beta = max_l w_l max_k |H_l(k)|^2 and ||W_s||^2 (FP64)
-  MF_TRY(launch_reduce_max(c->P_T, spec, (double)c->N * (double)c->N, c->partial, c->dres + 4, st));
+  // ||W_s||^2 (FP64, shared by the group) and, per cube, beta = max_l w_l max_k |H_l(k)|^2
   MF_TRY(launch_frame_bound(c->N, c->J, c->gen, c->omega_c, c->partial, c->dres + 5, st));
-  double hs[16];
-  MF_HIP(hipMemcpyAsync(hs, c->dres, sizeof(hs), hipMemcpyDeviceToHost, st));
-  MF_HIP(hipStreamSynchronize(st));
-  c->beta = hs[4];
-  c->Ws2 = hs[5];
-  c->K2 = p->mu_s * p->mu_s * c->Ws2 + p->mu_lambda * p->mu_lambda;
-  c->tau = p->tau > 0 ? p->tau : 0.99 / (c->beta / 2.0 + c->sigma * c->K2);
-  const double margin = 1.0 / c->tau - c->sigma * c->K2;
-  if (!(margin > c->beta / 2.0))
-    return set_error("step sizes violate 1/tau - sigma ||K||^2 > beta/2"), MUFFIN_ESTEP;
-  c->delta = 2.0 - (c->beta / 2.0) / margin;
-  if (!(c->rho < c->delta)) return set_error("rho must lie in (0, delta)"), MUFFIN_ESTEP;
+  MF_HIP(hipMemcpyAsync(&c->Ws2, c->dres + 5, sizeof(double), hipMemcpyDeviceToHost, st));
+  const long long per_ch = (long long)c->g.pitch * c->N;
+  for (size_t i = 0; i < c->segs.size(); ++i) {
+    Seg& s = c->segs[i];
+    MF_TRY(launch_reduce_max(c->P_T + s.ch0 * per_ch, s.L * per_ch, (double)c->N * (double)c->N, c->partial,
+                             c->dres + 4, st));
+    MF_HIP(hipMemcpyAsync(&s.beta, c->dres + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+    MF_HIP(hipStreamSynchronize(st));
+    s.K2 = c->p.mu_s * c->p.mu_s * c->Ws2 + s.mu_l * s.mu_l;
+    s.tau = ps[i]->tau > 0 ? ps[i]->tau : 0.99 / (s.beta / 2.0 + c->sigma * s.K2);
+    const double margin = 1.0 / s.tau - c->sigma * s.K2;
+    if (!(margin > s.beta / 2.0))
+      return set_error("step sizes violate 1/tau - sigma ||K||^2 > beta/2 (cube " + std::to_string(i) + ")"),
+             MUFFIN_ESTEP;
+    s.delta = 2.0 - (s.beta / 2.0) / margin;
+    if (!(c->rho < s.delta)) return set_error("rho must lie in (0, delta)"), MUFFIN_ESTEP;
+  }
 
   MF_HIP(hipMemsetAsync(c->X, 0, sizeof(float) * cube, st));
   MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * cube * (c->J + 1), st));
@@ -440,6 +493,68 @@ int ensure_graph(muffin_ctx* c) {
   MF_HIP(e);
   c->graph = gr;
   MF_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  return MUFFIN_OK;
+}
+
+// Autotuner: for every scale and band-kernel class of the iteration, time each band height that
+// divides N on the context's own sizes (writing only scratch planes) and keep the fastest.
+int autotune(muffin_ctx* c, int reps, std::string& rep) {
+  const long long np = c->npix, ucs = (long long)(c->J + 1) * np;
+  const int modes[2] = {c->gen == 2 ? DB_ANALYSIS : SM_DETAIL1, c->gen == 2 ? DB_ADJOINT : SM_SUBADD};
+  const char* names[2] = {"analysis", "adjoint"};
+  rep += "{\"N\": " + std::to_string(c->N) + ", \"channels\": " + std::to_string(c->L) + ", \"scales\": [";
+  for (int j = 0; j < c->J; ++j) {
+    for (int k = 0; k < 2; ++k) {
+      const int mode = modes[k];
+      double best = 1e30;
+      int best_ty = atrous_band_rows(c->N, j, mode);
+      std::string cand;
+      for (int TY = 16; TY <= c->N; TY *= 2) {
+        if (c->N % TY) continue;
+        MF_TRY(atrous_set_band_rows(c->N, j, mode, TY));
+        auto launch = [&]() -> int {
+          if (k == 0)
+            return launch_atrous(mode, c->N, c->L, j, pref(c->X, np), PlaneRef{}, PlaneRef{}, pout(c->cB, np),
+                                 pout(c->cT, np), 0.f, 1.f, nullptr, nullptr, c->st);
+          return launch_atrous(mode, c->N, c->L, j, c->gen == 2 ? pref(c->U + (long long)j * np, ucs) : pref(c->cA, np),
+                               pref(c->cA, np), pref(c->cA, np), pout(c->cB, np), PlaneOut{}, 0.f, 1.f, nullptr,
+                               nullptr, c->st);
+        };
+        MF_TRY(launch());
+        MF_HIP(hipEventRecord(c->e0, c->st));
+        for (int r = 0; r < reps; ++r) MF_TRY(launch());
+        MF_HIP(hipEventRecord(c->e1, c->st));
+        MF_HIP(hipEventSynchronize(c->e1));
+        float t = 0.f;
+        MF_HIP(hipEventElapsedTime(&t, c->e0, c->e1));
+        const double ms = t / reps;
+        if (!cand.empty()) cand += ", ";
+        cand += "\"" + std::to_string(TY) + "\": " + std::to_string(ms);
+        if (ms < best) {
+          best = ms;
+          best_ty = TY;
+        }
+      }
+      MF_TRY(atrous_set_band_rows(c->N, j, mode, best_ty));
+      if (j || k) rep += ", ";
+      rep += "{\"j\": " + std::to_string(j) + ", \"kernel\": \"" + names[k] + "\", \"rows\": " +
+             std::to_string(best_ty) + ", \"ms\": " + std::to_string(best) + ", \"candidates_ms\": {" + cand + "}}";
+    }
+  }
+  rep += "]}";
+  // recapture the iteration with the chosen tiles
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  return MUFFIN_OK;
+}
+
+int write_report(const std::string& rep, char* out, size_t len) {
+  if (!out || len == 0) return MUFFIN_OK;
+  const size_t n = rep.size() < len - 1 ? rep.size() : len - 1;
+  std::memcpy(out, rep.data(), n);
+  out[n] = 0;
   return MUFFIN_OK;
 }
 
@@ -480,7 +595,7 @@ int muffin_init(muffin_ctx** out, const muffin_params* p, const float* dirty, co
   muffin_ctx* c = new (std::nothrow) muffin_ctx();
   if (!c) return set_error("host allocation failed"), MUFFIN_ENOMEM;
   c->user = (hipStream_t)hip_stream;
-  const int rc = init_impl(c, p, dirty, psf, inputs_on_device);
+  const int rc = init_group(c, 1, &p, &dirty, &psf, inputs_on_device);
   if (rc != MUFFIN_OK) {
     destroy(c);
     return rc;
@@ -490,6 +605,183 @@ int muffin_init(muffin_ctx** out, const muffin_params* p, const float* dirty, co
 }
 
 void muffin_free(muffin_ctx* c) { destroy(c); }
+
+int muffin_autotune(muffin_ctx* c, int32_t reps, char* report, size_t report_len) {
+  if (!c || reps < 1) return set_error("bad arguments"), MUFFIN_EINVAL;
+  StreamScope scope(c);
+  std::string rep;
+  MF_TRY(autotune(c, reps, rep));
+  return write_report(rep, report, report_len);
+}
+
+// ---------------------------------------------------------------------------------- batches
+struct muffin_batch {
+  std::vector<muffin_ctx*> groups;
+  std::vector<std::pair<int, int>> map;  // cube -> (group, segment)
+  hipStream_t user = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+void muffin_batch_free(muffin_batch* b) {
+  if (!b) return;
+  for (muffin_ctx* g : b->groups) destroy(g);
+  if (b->e0) (void)hipEventDestroy(b->e0);
+  if (b->e1) (void)hipEventDestroy(b->e1);
+  delete b;
+}
+
+int muffin_batch_init(muffin_batch** out, int32_t n_cubes, const muffin_params* p, const float* const* dirty,
+                      const float* const* psf, int inputs_on_device, void* hip_stream) {
+  if (!out) return set_error("out is NULL"), MUFFIN_EINVAL;
+  *out = nullptr;
+  if (n_cubes < 1 || !p || !dirty || !psf) return set_error("bad arguments"), MUFFIN_EINVAL;
+  for (int i = 0; i < n_cubes; ++i) {
+    MF_TRY(validate(p + i));
+    if (!dirty[i] || !psf[i]) return set_error("dirty or psf is NULL"), MUFFIN_EINVAL;
+  }
+  muffin_batch* b = new (std::nothrow) muffin_batch();
+  if (!b) return set_error("host allocation failed"), MUFFIN_ENOMEM;
+  b->user = (hipStream_t)hip_stream;
+  b->map.assign(n_cubes, {-1, -1});
+  auto fail = [&](int rc) {
+    muffin_batch_free(b);
+    return rc;
+  };
+  if (hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess)
+    return fail((set_error("event creation failed"), MUFFIN_EHIP));
+  // group cubes that can share the per-channel phases
+  auto same = [&](const muffin_params& a, const muffin_params& c) {
+    return a.N == c.N && a.J == c.J && a.iuwt_gen == c.iuwt_gen && a.penalize_coarse == c.penalize_coarse &&
+           a.mu_s == c.mu_s && a.sigma == c.sigma && a.rho == c.rho;
+  };
+  std::vector<char> done(n_cubes, 0);
+  for (int i = 0; i < n_cubes; ++i) {
+    if (done[i]) continue;
+    std::vector<int> idx;
+    for (int k = i; k < n_cubes; ++k)
+      if (!done[k] && same(p[i], p[k])) {
+        idx.push_back(k);
+        done[k] = 1;
+      }
+    std::vector<const muffin_params*> ps;
+    std::vector<const float*> ds, fs;
+    for (int k : idx) {
+      ps.push_back(p + k);
+      ds.push_back(dirty[k]);
+      fs.push_back(psf[k]);
+    }
+    muffin_ctx* g = new (std::nothrow) muffin_ctx();
+    if (!g) return fail((set_error("host allocation failed"), MUFFIN_ENOMEM));
+    g->user = b->user;
+    const int rc = init_group(g, (int)idx.size(), ps.data(), ds.data(), fs.data(), inputs_on_device);
+    if (rc != MUFFIN_OK) {
+      destroy(g);
+      return fail(rc);
+    }
+    for (size_t s = 0; s < idx.size(); ++s) b->map[idx[s]] = {(int)b->groups.size(), (int)s};
+    b->groups.push_back(g);
+  }
+  *out = b;
+  return MUFFIN_OK;
+}
+
+// All groups replay their graphs concurrently, each on its own stream, between two events of the
+// caller's stream.
+static int batch_run(muffin_batch* b, int n_iter, double* ms) {
+  MF_HIP(hipEventRecord(b->e0, b->user));
+  for (muffin_ctx* g : b->groups) {
+    MF_HIP(hipStreamWaitEvent(g->st, b->e0, 0));
+    MF_TRY(ensure_graph(g));
+    for (int i = 0; i < n_iter; ++i) MF_HIP(hipGraphLaunch(g->gexec, g->st));
+    MF_HIP(hipEventRecord(g->ev_out, g->st));
+    g->iter += n_iter;
+  }
+  for (muffin_ctx* g : b->groups) MF_HIP(hipStreamWaitEvent(b->user, g->ev_out, 0));
+  MF_HIP(hipEventRecord(b->e1, b->user));
+  if (ms) {
+    MF_HIP(hipEventSynchronize(b->e1));
+    float t = 0.f;
+    MF_HIP(hipEventElapsedTime(&t, b->e0, b->e1));
+    *ms = t;
+  }
+  return MUFFIN_OK;
+}
+
+int muffin_batch_step(muffin_batch* b, int32_t n_iter) {
+  if (!b || n_iter < 0) return set_error("bad arguments"), MUFFIN_EINVAL;
+  return n_iter ? batch_run(b, n_iter, nullptr) : MUFFIN_OK;
+}
+
+int muffin_batch_step_timed(muffin_batch* b, int32_t n_iter, double* ms) {
+  if (!b || !ms || n_iter < 1) return set_error("bad arguments"), MUFFIN_EINVAL;
+  // capture every group's graph first so that capture stays out of the timed region
+  for (muffin_ctx* g : b->groups) MF_TRY(ensure_graph(g));
+  return batch_run(b, n_iter, ms);
+}
+
+static int batch_cube(muffin_batch* b, int32_t cube, muffin_ctx** g, int* si) {
+  if (!b || cube < 0 || cube >= (int)b->map.size()) return set_error("bad cube index"), MUFFIN_EINVAL;
+  *g = b->groups[b->map[cube].first];
+  *si = b->map[cube].second;
+  return MUFFIN_OK;
+}
+
+int muffin_batch_objective(muffin_batch* b, int32_t cube, double out[4]) {
+  muffin_ctx* g;
+  int si;
+  MF_TRY(batch_cube(b, cube, &g, &si));
+  if (!out) return set_error("bad arguments"), MUFFIN_EINVAL;
+  StreamScope scope(g);
+  MF_TRY(enqueue_objective(g, si));
+  double h[4];
+  MF_HIP(hipMemcpyAsync(h, g->dres, sizeof(h), hipMemcpyDeviceToHost, g->st));
+  MF_HIP(hipStreamSynchronize(g->st));
+  out[1] = h[1];
+  out[2] = g->p.mu_s * h[2];
+  out[3] = g->segs[si].mu_l * h[3];
+  out[0] = out[1] + out[2] + out[3];
+  if (!std::isfinite(out[0])) return set_error("objective is not finite"), MUFFIN_ENONFINITE;
+  return MUFFIN_OK;
+}
+
+int muffin_batch_get_x(muffin_batch* b, int32_t cube, float* x, int on_device) {
+  muffin_ctx* g;
+  int si;
+  MF_TRY(batch_cube(b, cube, &g, &si));
+  if (!x) return set_error("bad arguments"), MUFFIN_EINVAL;
+  StreamScope scope(g);
+  const Seg& s = g->segs[si];
+  return copy_out(x, g->X + (long long)s.ch0 * g->npix, (size_t)s.L * g->npix, on_device, g->st);
+}
+
+int muffin_batch_info(muffin_batch* b, int32_t cube, double out[8]) {
+  muffin_ctx* g;
+  int si;
+  MF_TRY(batch_cube(b, cube, &g, &si));
+  if (!out) return set_error("bad arguments"), MUFFIN_EINVAL;
+  const Seg& s = g->segs[si];
+  out[0] = s.tau;
+  out[1] = g->sigma;
+  out[2] = g->rho;
+  out[3] = s.beta;
+  out[4] = s.K2;
+  out[5] = g->Ws2;
+  out[6] = s.delta;
+  out[7] = (double)g->iter;
+  return MUFFIN_OK;
+}
+
+int muffin_batch_autotune(muffin_batch* b, int32_t reps, char* report, size_t report_len) {
+  if (!b || reps < 1) return set_error("bad arguments"), MUFFIN_EINVAL;
+  std::string rep = "[";
+  for (size_t i = 0; i < b->groups.size(); ++i) {
+    StreamScope scope(b->groups[i]);
+    if (i) rep += ", ";
+    MF_TRY(autotune(b->groups[i], reps, rep));
+  }
+  rep += "]";
+  return write_report(rep, report, report_len);
+}
 
 int muffin_step(muffin_ctx* c, int32_t n_iter) {
   if (!c || n_iter < 0) return set_error("bad context or n_iter"), MUFFIN_EINVAL;
@@ -558,13 +850,13 @@ int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[8]) {
 int muffin_objective(muffin_ctx* c, double out[4]) {
   if (!c || !out) return set_error("bad arguments"), MUFFIN_EINVAL;
   StreamScope scope(c);
-  MF_TRY(enqueue_objective(c));
+  MF_TRY(enqueue_objective(c, 0));
   double h[4];
   MF_HIP(hipMemcpyAsync(h, c->dres, sizeof(h), hipMemcpyDeviceToHost, c->st));
   MF_HIP(hipStreamSynchronize(c->st));
   out[1] = h[1];
   out[2] = c->p.mu_s * h[2];
-  out[3] = c->p.mu_lambda * h[3];
+  out[3] = c->segs[0].mu_l * h[3];
   out[0] = out[1] + out[2] + out[3];
   if (!std::isfinite(out[0])) return set_error("objective is not finite"), MUFFIN_ENONFINITE;
   return MUFFIN_OK;
@@ -600,13 +892,14 @@ int muffin_solve(muffin_ctx* c, int32_t max_iter, int32_t check_every, double to
 
 int muffin_info(muffin_ctx* c, double out[8]) {
   if (!c || !out) return set_error("bad arguments"), MUFFIN_EINVAL;
-  out[0] = c->tau;
+  const Seg& s = c->segs[0];
+  out[0] = s.tau;
   out[1] = c->sigma;
   out[2] = c->rho;
-  out[3] = c->beta;
-  out[4] = c->K2;
+  out[3] = s.beta;
+  out[4] = s.K2;
   out[5] = c->Ws2;
-  out[6] = c->delta;
+  out[6] = s.delta;
   out[7] = (double)c->iter;
   return MUFFIN_OK;
 }
@@ -655,8 +948,8 @@ int muffin_get_state(muffin_ctx* c, void* blob, size_t bytes) {
   h.gen = c->gen;
   h.pc = c->p.penalize_coarse;
   h.mu_s = c->p.mu_s;
-  h.mu_l = c->p.mu_lambda;
-  h.tau = c->tau;
+  h.mu_l = c->segs[0].mu_l;
+  h.tau = c->segs[0].tau;
   h.sigma = c->sigma;
   h.rho = c->rho;
   h.iter = c->iter;
@@ -676,7 +969,7 @@ int muffin_set_state(muffin_ctx* c, const void* blob, size_t bytes) {
   BlobHeader h;
   std::memcpy(&h, blob, sizeof(h));
   if (h.magic != kMagic || h.N != c->N || h.L != c->L || h.J != c->J || h.gen != c->gen ||
-      h.pc != c->p.penalize_coarse || h.mu_s != c->p.mu_s || h.mu_l != c->p.mu_lambda || h.tau != c->tau ||
+      h.pc != c->p.penalize_coarse || h.mu_s != c->p.mu_s || h.mu_l != c->segs[0].mu_l || h.tau != c->segs[0].tau ||
       h.sigma != c->sigma || h.rho != c->rho)
     return set_error("checkpoint sizes or parameters differ from the context"), MUFFIN_ESTATE;
   const float* f = (const float*)((const char*)blob + sizeof(h));
@@ -750,9 +1043,9 @@ int muffin_apply_op(muffin_ctx* c, int op, const float* in, float* out) {
                               nullptr, c->st);
     }
     case MUFFIN_OP_DCT:
-      return launch_dct(in, out, c->WT, np, c->L, c->st);
+      return launch_dct(in, out, c->segs[0].WT, np, c->L, c->st);
     case MUFFIN_OP_IDCT:
-      return launch_dct(in, out, c->W, np, c->L, c->st);
+      return launch_dct(in, out, c->segs[0].W, np, c->L, c->st);
     default:
       return set_error("unknown operator"), MUFFIN_EINVAL;
   }

@@ -100,6 +100,10 @@ enum AtrousMode {
   DB_ANALYSIS = 5,    // out2 = c' = H_j(A); w = A - H_j(c'); u(out) update  (second generation)
   DB_ADJOINT = 6      // out = A + H_j(B - H_j(A))  (A = u_j, B = a; second generation Horner step)
 };
+// band height (rows per workgroup) of the band kernels, default or autotuned; set_band_rows records
+// an autotuned choice for (N, j, kernel class of mode)
+int atrous_band_rows(int N, int j, int mode);
+int atrous_set_band_rows(int N, int j, int mode, int TY);
 // true if the double-smoothing kernels fit in LDS at scale j for image side N
 bool atrous_double_fits(int N, int j, int* TX, int* TY);
 int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out,

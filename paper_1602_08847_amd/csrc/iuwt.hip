@@ -13,6 +13,9 @@
 // bands, keeping neighbouring bands' edge rows in its own L2.
 #include "common.h"
 
+#include <map>
+#include <mutex>
+
 namespace mf {
 
 __device__ __forceinline__ float satf(float u) { return fminf(1.f, fmaxf(-1.f, u)); }
@@ -246,7 +249,7 @@ __global__ void __launch_bounds__(1024) k_band(AtrousArgs a) {
 constexpr int kKR = 8;   // rows per round, single-smoothing modes
 constexpr int kKR2 = 4;  // rows per round, double-smoothing modes (keeps them within 128 VGPRs)
 
-static int band_rows(int N, int j) {
+static int band_rows_default(int N, int j) {
   // about 32 s rows per band (band edges cost 4s or 8s extra row loads per class), at least 64
   int target = 32 << j;
   if (target < 64) target = 64;
@@ -256,9 +259,30 @@ static int band_rows(int N, int j) {
   return TY;
 }
 
+// Band heights chosen by the autotuner, per (N, scale, kernel class); process-wide.
+static std::mutex g_tune_mu;
+static std::map<long long, int> g_tune;
+static long long tune_key(int N, int j, int cls) { return ((long long)N << 16) | (j << 8) | cls; }
+
+int atrous_class(int mode) { return (mode == DB_ANALYSIS) ? 0 : (mode == DB_ADJOINT ? 1 : 2); }
+
+int atrous_band_rows(int N, int j, int mode) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(N, j, atrous_class(mode)));
+  return it != g_tune.end() ? it->second : band_rows_default(N, j);
+}
+
+int atrous_set_band_rows(int N, int j, int mode, int TY) {
+  if (TY < 1 || TY > N || N % TY) return set_error("band rows must divide N"), MUFFIN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (TY == 0) g_tune.erase(tune_key(N, j, atrous_class(mode)));
+  else g_tune[tune_key(N, j, atrous_class(mode))] = TY;
+  return MUFFIN_OK;
+}
+
 bool atrous_double_fits(int N, int j, int* TXo, int* TYo) {
   if (TXo) *TXo = N;
-  if (TYo) *TYo = band_rows(N, j);
+  if (TYo) *TYo = atrous_band_rows(N, j, DB_ANALYSIS);
   return true;
 }
 
@@ -278,7 +302,7 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   const bool dbl = (mode == DB_ANALYSIS || mode == DB_ADJOINT);
   if (N > 1024) return set_error("atrous: N > 1024"), MUFFIN_EINVAL;
   a.TX = N;
-  a.TY = band_rows(N, j);
+  a.TY = atrous_band_rows(N, j, mode);
   a.tiles_x = 1;
   a.tiles_per_ch = N / a.TY;
   const long long nb = (long long)a.tiles_per_ch * nch;

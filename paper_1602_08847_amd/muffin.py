@@ -33,7 +33,9 @@ EXPORTS = [
     "muffin_step_timed", "muffin_free", "muffin_strerror", "muffin_last_error",
     "muffin_cnn_create", "muffin_cnn_param_count", "muffin_cnn_get_params", "muffin_cnn_set_params",
     "muffin_cnn_predict", "muffin_cnn_loss_grad", "muffin_cnn_train_step", "muffin_cnn_layer",
-    "muffin_cnn_free", "muffin_warm_start",
+    "muffin_cnn_free", "muffin_warm_start", "muffin_autotune", "muffin_batch_init", "muffin_batch_step",
+    "muffin_batch_step_timed", "muffin_batch_objective", "muffin_batch_get_x", "muffin_batch_info",
+    "muffin_batch_autotune", "muffin_batch_free",
 ]
 
 
@@ -79,6 +81,17 @@ _lib.muffin_cnn_layer.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _i3
 _lib.muffin_cnn_free.argtypes = [_vp]
 _lib.muffin_cnn_free.restype = None
 _lib.muffin_warm_start.argtypes = [_vp, _vp]
+_lib.muffin_autotune.argtypes = [_vp, _i32, ctypes.c_char_p, ctypes.c_size_t]
+_lib.muffin_batch_init.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(Params), ctypes.POINTER(_vp),
+                                   ctypes.POINTER(_vp), ctypes.c_int, _vp]
+_lib.muffin_batch_step.argtypes = [_vp, _i32]
+_lib.muffin_batch_step_timed.argtypes = [_vp, _i32, ctypes.POINTER(_dbl)]
+_lib.muffin_batch_objective.argtypes = [_vp, _i32, ctypes.POINTER(_dbl)]
+_lib.muffin_batch_get_x.argtypes = [_vp, _i32, _vp, ctypes.c_int]
+_lib.muffin_batch_info.argtypes = [_vp, _i32, ctypes.POINTER(_dbl)]
+_lib.muffin_batch_autotune.argtypes = [_vp, _i32, ctypes.c_char_p, ctypes.c_size_t]
+_lib.muffin_batch_free.argtypes = [_vp]
+_lib.muffin_batch_free.restype = None
 
 
 class MuffinError(RuntimeError):
@@ -222,6 +235,11 @@ class Muffin:
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(_lib.muffin_set_state(self._h, buf, len(blob)), "muffin_set_state")
 
+    def autotune(self, reps: int = 3) -> str:
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(_lib.muffin_autotune(self._h, reps, buf, len(buf)), "muffin_autotune")
+        return buf.value.decode()
+
     def warm_start(self, net: "Cnn"):
         _check(_lib.muffin_warm_start(self._h, net._h), "muffin_warm_start")
         _torch().cuda.current_stream().synchronize()
@@ -330,6 +348,86 @@ class Cnn:
         _check(_lib.muffin_cnn_layer(self._h, layer, 1, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(dz.data_ptr()),
                                      ctypes.c_void_p(out.data_ptr()), dp.ctypes.data, B, N), "muffin_cnn_layer")
         return out, dp
+
+
+class Batch:
+    """Independent cubes of uneven sizes advanced together (muffin_batch_*)."""
+
+    def __init__(self, cubes, J: int, mu_s: float, mu_lambda, iuwt_gen: int = 2, sigma: float = 1.0,
+                 rho: float = 1.0, tau=0.0):
+        """cubes: list of (dirty, psf) pairs of [L_i][N_i][N_i] arrays; mu_lambda and tau may be
+        scalars or per-cube sequences."""
+        torch = _torch()
+        n = len(cubes)
+        mls = list(mu_lambda) if np.ndim(mu_lambda) else [mu_lambda] * n
+        taus = list(tau) if np.ndim(tau) else [tau] * n
+        self._keep = []
+        ps = (Params * n)()
+        dptr = (_vp * n)()
+        fptr = (_vp * n)()
+        self.shapes = []
+        for i, (d, f) in enumerate(cubes):
+            d = torch.as_tensor(d, dtype=torch.float32).cuda().contiguous()
+            f = torch.as_tensor(f, dtype=torch.float32).cuda().contiguous()
+            L, N, _ = d.shape
+            self.shapes.append((L, N))
+            self._keep += [d, f]
+            ps[i] = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=1, reserved=0, mu_s=mu_s,
+                           mu_lambda=mls[i], tau=taus[i], sigma=sigma, rho=rho)
+            dptr[i] = d.data_ptr()
+            fptr[i] = f.data_ptr()
+        h = ctypes.c_void_p()
+        _check(_lib.muffin_batch_init(ctypes.byref(h), n, ps, dptr, fptr, 1, _stream_handle()), "muffin_batch_init")
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.muffin_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def step(self, n: int = 1):
+        _check(_lib.muffin_batch_step(self._h, n), "muffin_batch_step")
+
+    def step_timed(self, n: int) -> float:
+        ms = _dbl()
+        _check(_lib.muffin_batch_step_timed(self._h, n, ctypes.byref(ms)), "muffin_batch_step_timed")
+        return ms.value
+
+    def objective(self, cube: int) -> np.ndarray:
+        out = (_dbl * 4)()
+        _check(_lib.muffin_batch_objective(self._h, cube, out), "muffin_batch_objective")
+        return np.array(out[:])
+
+    def info(self, cube: int) -> dict:
+        out = (_dbl * 8)()
+        _check(_lib.muffin_batch_info(self._h, cube, out), "muffin_batch_info")
+        return dict(zip(["tau", "sigma", "rho", "beta", "K2", "Ws2", "delta", "iter"], out[:]))
+
+    def get_x(self, cube: int):
+        torch = _torch()
+        L, N = self.shapes[cube]
+        out = torch.empty((L, N, N), dtype=torch.float32, device="cuda")
+        _check(_lib.muffin_batch_get_x(self._h, cube, ctypes.c_void_p(out.data_ptr()), 1), "muffin_batch_get_x")
+        torch.cuda.current_stream().synchronize()
+        return out
+
+    def autotune(self, reps: int = 3) -> str:
+        buf = ctypes.create_string_buffer(1 << 20)
+        _check(_lib.muffin_batch_autotune(self._h, reps, buf, len(buf)), "muffin_batch_autotune")
+        return buf.value.decode()
 
 
 def cnn_params_to_oracle(p: np.ndarray):

@@ -1,7 +1,7 @@
 """Learned warm start for the MUFFIN iteration: training data, training loop and the
 time-to-tolerance comparison against a cold start.
 
-Training pairs are (dirty channel image / PSF sum, plain-solver reconstruction of that channel):
+Training pairs are (dirty channel image / PSF main-lobe gain, plain-solver reconstruction of that channel):
 seeded synthetic cubes are reconstructed by the library's own primal-dual iteration, and the
 network is trained by the library's own forward/backward kernels (muffin_cnn_train_step).  The
 comparison runs both starts with identical step sizes against the same reference objective f_ref

@@ -1,0 +1,58 @@
+"""Uneven batches and the band-height autotuner: both must leave the arithmetic unchanged, so a
+batch reproduces separate contexts bit for bit and a tuned context reproduces an untuned one."""
+import json
+
+import numpy as np
+import pytest
+
+from oracle import muffin as om
+from paper_1602_08847_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [synth.CubeSpec(N=64, L=8, J=3, n_sources=4, n_baselines=100, seed=1),
+         synth.CubeSpec(N=96, L=5, J=3, n_sources=4, n_baselines=150, seed=2),
+         synth.CubeSpec(N=64, L=3, J=3, n_sources=3, n_baselines=80, seed=3),
+         synth.CubeSpec(N=128, L=17, J=3, n_sources=6, n_baselines=300, seed=4)]
+
+
+@pytest.fixture(scope="module")
+def cubes():
+    return [synth.make_cube(s, dtype=np.float32) for s in SPECS]
+
+
+def test_batch_matches_separate_contexts_bitwise(lib, cubes):
+    mls = [3.0, 2.0, 3.0, 1.5]
+    with lib.Batch([(c.dirty, c.psf) for c in cubes], J=3, mu_s=0.25, mu_lambda=mls, sigma=10.0) as b:
+        b.step(12)
+        for i, c in enumerate(cubes):
+            with lib.Muffin(c.dirty, c.psf, J=3, mu_s=0.25, mu_lambda=mls[i], sigma=10.0) as m:
+                assert b.info(i)["tau"] == m.info()["tau"]
+                m.step(12)
+                np.testing.assert_array_equal(b.get_x(i).cpu().numpy(), m.get_x().cpu().numpy())
+                np.testing.assert_allclose(b.objective(i), m.objective(), rtol=1e-12)
+
+
+def test_batch_step_matches_oracle_per_cube(lib, cubes):
+    with lib.Batch([(c.dirty, c.psf) for c in cubes[:2]], J=3, mu_s=0.25, mu_lambda=3.0) as b:
+        b.step(5)
+        for i, c in enumerate(cubes[:2]):
+            p = om.Problem(dirty=c.dirty.astype(np.float64), psf=c.psf.astype(np.float64), J=3, mu_s=0.25,
+                           mu_l=3.0)
+            st, _ = om.solve(p, 5, tau=b.info(i)["tau"])
+            x = b.get_x(i).double().cpu().numpy()
+            assert np.linalg.norm(x - st.X) / np.linalg.norm(st.X) < 1e-4
+
+
+def test_autotune_keeps_results_and_reports_choices(lib, cubes):
+    c = cubes[3]
+    with lib.Muffin(c.dirty, c.psf, J=3, mu_s=0.25, mu_lambda=3.0) as a:
+        a.step(6)
+        xa = a.get_x().cpu().numpy()
+    with lib.Muffin(c.dirty, c.psf, J=3, mu_s=0.25, mu_lambda=3.0) as t:
+        rep = json.loads(t.autotune(reps=2))
+        assert rep["N"] == 128 and len(rep["scales"]) == 6
+        for s in rep["scales"]:
+            assert 128 % s["rows"] == 0 and str(s["rows"]) in s["candidates_ms"]
+        t.step(6)
+        np.testing.assert_array_equal(t.get_x().cpu().numpy(), xa)
