@@ -515,10 +515,10 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
         auto launch = [&]() -> int {
           if (k == 0)
             return launch_atrous(mode, c->N, c->L, j, pref(c->X, np), PlaneRef{}, PlaneRef{}, pout(c->cB, np),
-                                 pout(c->cT, np), 0.f, 1.f, nullptr, nullptr, c->st);
+                                 pout(c->cT, np), 0.f, 1.f, nullptr, nullptr, c->st, 1);
           return launch_atrous(mode, c->N, c->L, j, c->gen == 2 ? pref(c->U + (long long)j * np, ucs) : pref(c->cA, np),
                                pref(c->cA, np), pref(c->cA, np), pout(c->cB, np), PlaneOut{}, 0.f, 1.f, nullptr,
-                               nullptr, c->st);
+                               nullptr, c->st, 1);
         };
         MF_TRY(launch());
         MF_HIP(hipEventRecord(c->e0, c->st));

@@ -107,7 +107,8 @@ int atrous_set_band_rows(int N, int j, int mode, int TY);
 // true if the double-smoothing kernels fit in LDS at scale j for image side N
 bool atrous_double_fits(int N, int j, int* TX, int* TY);
 int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out,
-                  PlaneOut out2, float coef, float rho, double* partial, int* nblocks_out, hipStream_t st);
+                  PlaneOut out2, float coef, float rho, double* partial, int* nblocks_out, hipStream_t st,
+                  int trial = 0);  // trial: the autotuner's timing launch (same code, own symbol)
 enum PointMode {
   PT_DETAIL1 = 0,  // w = E - A; u update (first-generation detail, no smoothing)
   PT_COARSE = 1,   // w = A; u update

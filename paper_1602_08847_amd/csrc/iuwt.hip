@@ -78,7 +78,7 @@ struct BandPre {
 };
 
 template <int MODE, int KR>
-__global__ void __launch_bounds__(1024) k_band(AtrousArgs a) {
+__device__ __forceinline__ void band_body(const AtrousArgs& a) {
   constexpr bool DBL = (MODE == DB_ANALYSIS || MODE == DB_ADJOINT);
   extern __shared__ float sm[];
   const int N = a.N, s = 1 << a.j, x = threadIdx.x, TY = a.TY;
@@ -246,6 +246,18 @@ __global__ void __launch_bounds__(1024) k_band(AtrousArgs a) {
   }
 }
 
+template <int MODE, int KR>
+__global__ void __launch_bounds__(1024) k_band(AtrousArgs a) {
+  band_body<MODE, KR>(a);
+}
+
+// The autotuner's timing launches run the same code under a symbol of their own, so that a
+// profile of a run keeps the trials of other band heights apart from the iteration's launches.
+template <int MODE, int KR>
+__global__ void __launch_bounds__(1024) k_band_trial(AtrousArgs a) {
+  band_body<MODE, KR>(a);
+}
+
 constexpr int kKR = 8;   // rows per round, single-smoothing modes
 constexpr int kKR2 = 4;  // rows per round, double-smoothing modes (keeps them within 128 VGPRs)
 
@@ -264,7 +276,15 @@ static std::mutex g_tune_mu;
 static std::map<long long, int> g_tune;
 static long long tune_key(int N, int j, int cls) { return ((long long)N << 16) | (j << 8) | cls; }
 
-int atrous_class(int mode) { return (mode == DB_ANALYSIS) ? 0 : (mode == DB_ADJOINT ? 1 : 2); }
+int atrous_class(int mode) {
+  switch (mode) {
+    case DB_ANALYSIS: return 0;
+    case DB_ADJOINT: return 1;
+    case SM_DETAIL1: return 2;
+    case SM_SUBADD: return 3;
+    default: return 4;
+  }
+}
 
 int atrous_band_rows(int N, int j, int mode) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -273,7 +293,7 @@ int atrous_band_rows(int N, int j, int mode) {
 }
 
 int atrous_set_band_rows(int N, int j, int mode, int TY) {
-  if (TY < 1 || TY > N || N % TY) return set_error("band rows must divide N"), MUFFIN_EINVAL;
+  if (TY != 0 && (TY < 1 || TY > N || N % TY)) return set_error("band rows must divide N"), MUFFIN_EINVAL;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (TY == 0) g_tune.erase(tune_key(N, j, atrous_class(mode)));
   else g_tune[tune_key(N, j, atrous_class(mode))] = TY;
@@ -287,7 +307,7 @@ bool atrous_double_fits(int N, int j, int* TXo, int* TYo) {
 }
 
 int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out, PlaneOut out2,
-                  float coef, float rho, double* partial, int* nblocks_out, hipStream_t st) {
+                  float coef, float rho, double* partial, int* nblocks_out, hipStream_t st, int trial) {
   AtrousArgs a;
   a.A = A;
   a.B = B;
@@ -317,6 +337,17 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   a.small = (dbl ? 4 * s : 2 * s) + a.TY >= N ? 1 : 0;  // row indices may leave [-N, 2N)
   const size_t shm = sizeof(float) * (size_t)2 * kKR * N;
   const dim3 grid((unsigned)nb), block((unsigned)N);
+  if (trial) {
+    switch (mode) {
+      case SM_SUBADD: hipLaunchKernelGGL((k_band_trial<SM_SUBADD, kKR>), grid, block, shm, st, a); break;
+      case SM_DETAIL1: hipLaunchKernelGGL((k_band_trial<SM_DETAIL1, kKR>), grid, block, shm, st, a); break;
+      case DB_ANALYSIS: hipLaunchKernelGGL((k_band_trial<DB_ANALYSIS, kKR2>), grid, block, shm, st, a); break;
+      case DB_ADJOINT: hipLaunchKernelGGL((k_band_trial<DB_ADJOINT, kKR2>), grid, block, shm, st, a); break;
+      default: set_error("atrous: no trial variant for this mode"); return MUFFIN_EINVAL;
+    }
+    MF_HIP(hipGetLastError());
+    return MUFFIN_OK;
+  }
   switch (mode) {
     case SM_SMOOTH: hipLaunchKernelGGL((k_band<SM_SMOOTH, kKR>), grid, block, shm, st, a); break;
     case SM_SUBADD: hipLaunchKernelGGL((k_band<SM_SUBADD, kKR>), grid, block, shm, st, a); break;
@@ -341,6 +372,14 @@ int atrous_init_attrs() {
   MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_DETAIL1, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ANALYSIS, kKR2>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ADJOINT, kKR2>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_SUBADD, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_DETAIL1, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<DB_ANALYSIS, kKR2>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<DB_ADJOINT, kKR2>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   return MUFFIN_OK;
 }
 
