@@ -36,6 +36,8 @@ KERNEL_BYTES = {
     "k_band<DB_ANALYSIS> (one scale of analysis + spatial dual step)": 16.0,
     # reads u_j and the running adjoint sum a, writes the new sum
     "k_band<DB_ADJOINT> (one scale of the adjoint Horner step)": 12.0,
+    # reads c_{J-1}, u_{J-1} and the coarse dual u_J, writes u_{J-1} and u_J
+    "k_band<DB_ANALYSIS_C> (last scale of analysis + spatial and coarse dual steps)": 20.0,
 }
 
 
@@ -182,8 +184,9 @@ def main():
     vox = N * N * L
     fams = {
         "k_spectral_fft (fused spectral step)": (ph[3], 1),
-        "k_band<DB_ANALYSIS> (one scale of analysis + spatial dual step)": (ph[5], J),
+        "k_band<DB_ANALYSIS> (one scale of analysis + spatial dual step)": (ph[5], J - 1 if ph[7] > 0 else J),
         "k_band<DB_ADJOINT> (one scale of the adjoint Horner step)": (ph[6], J),
+        "k_band<DB_ANALYSIS_C> (last scale of analysis + spatial and coarse dual steps)": (ph[7], 1),
     }
     dom = max(fams, key=lambda k: fams[k][0] * fams[k][1])
     k_ms = fams[dom][0]
@@ -206,7 +209,8 @@ def main():
         "iteration_alg_frac": round(b_alg * vox / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_ms": {"adjoint": round(ph[1], 3), "gradient": round(ph[2], 3),
                      "spectral": round(ph[3], 3), "analysis_dual": round(ph[4], 3),
-                     "analysis_launch": round(ph[5], 4), "adjoint_launch": round(ph[6], 4)},
+                     "analysis_launch": round(ph[5], 4), "adjoint_launch": round(ph[6], 4),
+                     "analysis_coarse_launch": round(ph[7], 4)},
     }
     cpu = None
     if not args.no_cpu:

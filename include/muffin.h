@@ -132,8 +132,10 @@ int muffin_apply_op(muffin_ctx* ctx, int op, const float* in, float* out);
  * report the average device milliseconds per iteration of each kernel family:
  *   ms[0] whole iteration, [1] spatial adjoint (IUWT^dagger), [2] gradient FFT passes,
  *   [3] fused spectral kernel, [4] spatial analysis and dual update,
- *   [5] mean duration of one scale's fused analysis + dual-update launch, [6] mean duration of one
- *   scale's fused adjoint launch (both 0 for the first-generation transform), [7] reserved (0).
+ *   [5] mean duration of one scale's fused analysis + dual-update launch (scales 0..J-2, and J-1
+ *   when the coarse plane is not penalised), [6] mean duration of one scale's fused adjoint launch,
+ *   [7] duration of the last scale's analysis launch that also updates the coarse plane's dual
+ *   (0 when the coarse plane is not penalised); [5]-[7] are 0 for the first-generation transform.
  * Needs n_iter >= 2 for both [5] and [6].
  * The iterations advance the state like muffin_step. */
 int muffin_profile(muffin_ctx* ctx, int32_t n_iter, double ms[8]);

@@ -184,6 +184,14 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
                            pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
     } else if (atrous_double_fits(c->N, j, nullptr, nullptr)) {
       if (timed) MF_HIP(hipEventRecord(c->kev[2 * j], c->st));
+      if (j == J - 1 && c->omega_c != 0.f) {
+        // last scale: c_J goes straight into the coarse plane's dual step
+        MF_TRY(launch_atrous(DB_ANALYSIS_C, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                             pout(c->U + (long long)J * np, ucs), coef, rho, nullptr, nullptr, c->st, 0,
+                             coef * c->omega_c));
+        if (timed) MF_HIP(hipEventRecord(c->kev[2 * j + 1], c->st));
+        return MUFFIN_OK;
+      }
       MF_TRY(launch_atrous(DB_ANALYSIS, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
                            pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
       if (timed) MF_HIP(hipEventRecord(c->kev[2 * j + 1], c->st));
@@ -195,8 +203,10 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
     }
     cur = nxt;
   }
-  MF_TRY(launch_pointwise(PT_COARSE, c->N, c->L, pref(cur, np), PlaneRef{}, pout(c->U + (long long)J * np, ucs),
-                          coef * c->omega_c, rho, nullptr, nullptr, c->st));
+  // with omega = 0 on the coarse plane its dual stays where it is
+  if (c->omega_c != 0.f)
+    MF_TRY(launch_pointwise(PT_COARSE, c->N, c->L, pref(cur, np), PlaneRef{}, pout(c->U + (long long)J * np, ucs),
+                            coef * c->omega_c, rho, nullptr, nullptr, c->st));
   return MUFFIN_OK;
 }
 
@@ -505,7 +515,8 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
   rep += "{\"N\": " + std::to_string(c->N) + ", \"channels\": " + std::to_string(c->L) + ", \"scales\": [";
   for (int j = 0; j < c->J; ++j) {
     for (int k = 0; k < 2; ++k) {
-      const int mode = modes[k];
+      const bool fused_coarse = k == 0 && c->gen == 2 && j == c->J - 1 && c->omega_c != 0.f;
+      const int mode = fused_coarse ? DB_ANALYSIS_C : modes[k];
       double best = 1e30;
       int best_ty = atrous_band_rows(c->N, j, mode);
       std::string cand;
@@ -515,7 +526,7 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
         auto launch = [&]() -> int {
           if (k == 0)
             return launch_atrous(mode, c->N, c->L, j, pref(c->X, np), PlaneRef{}, PlaneRef{}, pout(c->cB, np),
-                                 pout(c->cT, np), 0.f, 1.f, nullptr, nullptr, c->st, 1);
+                                 pout(c->cT, np), 0.f, 1.f, nullptr, nullptr, c->st, 1, 0.f);
           return launch_atrous(mode, c->N, c->L, j, c->gen == 2 ? pref(c->U + (long long)j * np, ucs) : pref(c->cA, np),
                                pref(c->cA, np), pref(c->cA, np), pout(c->cB, np), PlaneOut{}, 0.f, 1.f, nullptr,
                                nullptr, c->st, 1);
@@ -814,7 +825,8 @@ int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[8]) {
   if (!c || !ms || n_iter < 1) return set_error("bad arguments"), MUFFIN_EINVAL;
   for (int i = 0; i < 8; ++i) ms[i] = 0;
   StreamScope scope(c);
-  int n_ad = 0, n_an = 0;
+  int n_ad = 0, n_an = 0, n_ac = 0;
+  const bool fused_coarse = c->gen == 2 && c->omega_c != 0.f;
   for (int it = 0; it < n_iter; ++it) {
     // alternate which kernel family is bracketed so the marks do not pile up in one iteration
     const int fam = 1 + (it & 1);
@@ -834,6 +846,9 @@ int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[8]) {
         if (fam == 1) {
           ms[6] += tk;
           ++n_ad;
+        } else if (fused_coarse && j == c->J - 1) {
+          ms[7] += tk;
+          ++n_ac;
         } else {
           ms[5] += tk;
           ++n_an;
@@ -842,6 +857,7 @@ int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[8]) {
     }
   }
   if (n_an) ms[5] /= n_an;
+  if (n_ac) ms[7] /= n_ac;
   if (n_ad) ms[6] /= n_ad;
   c->iter += n_iter;
   return MUFFIN_OK;

@@ -38,6 +38,16 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// XCD-aware block order.  Consecutive workgroup ids are dealt round-robin to the 8 XCDs, each
+// with its own L2; this maps id b to logical block xcd_remap(b) so that XCD x (ids b = x, x + 8,
+// ...) walks one contiguous range of logical blocks, and neighbouring blocks that share cache
+// lines or halo rows meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = b & 7, i = b >> 3;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 // ------------------------------------------------------------------ complex helpers
 __host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -98,7 +108,9 @@ enum AtrousMode {
   SM_DETAIL_ABS = 3,  // partial[block] = sum |E - H_j(A)|
   SM_DETAIL1 = 4,     // out2 = H_j(A); w = A - H_j(A); u(out) update  (first generation)
   DB_ANALYSIS = 5,    // out2 = c' = H_j(A); w = A - H_j(c'); u(out) update  (second generation)
-  DB_ADJOINT = 6      // out = A + H_j(B - H_j(A))  (A = u_j, B = a; second generation Horner step)
+  DB_ADJOINT = 6,     // out = A + H_j(B - H_j(A))  (A = u_j, B = a; second generation Horner step)
+  DB_ANALYSIS_C = 7   // DB_ANALYSIS at the last scale with the coarse plane's dual update fused:
+                      // u2(out2) <- rho*sat(u2 + coef2*c') + (1-rho)*u2 instead of storing c'
 };
 // band height (rows per workgroup) of the band kernels, default or autotuned; set_band_rows records
 // an autotuned choice for (N, j, kernel class of mode)
@@ -108,7 +120,8 @@ int atrous_set_band_rows(int N, int j, int mode, int TY);
 bool atrous_double_fits(int N, int j, int* TX, int* TY);
 int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out,
                   PlaneOut out2, float coef, float rho, double* partial, int* nblocks_out, hipStream_t st,
-                  int trial = 0);  // trial: the autotuner's timing launch (same code, own symbol)
+                  int trial = 0,  // trial: the autotuner's timing launch (same code, own symbol)
+                  float coef2 = 0.f);  // DB_ANALYSIS_C: the coarse plane's dual step sigma*mu_s*omega
 enum PointMode {
   PT_DETAIL1 = 0,  // w = E - A; u update (first-generation detail, no smoothing)
   PT_COARSE = 1,   // w = A; u update

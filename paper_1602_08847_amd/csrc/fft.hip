@@ -79,8 +79,11 @@ __global__ void __launch_bounds__(512) k_cols(float2* __restrict__ S, int pitch,
   constexpr int CB = col_block<N>();
   constexpr int LS = lstride<N>();
   extern __shared__ float2 lds[];
-  const int ch = blockIdx.x / ncb;
-  const int c0 = (blockIdx.x % ncb) * CB;
+  // column blocks of one channel are neighbours in memory (CB columns of a row are less than a
+  // cache line at large N): keep them on one XCD
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int ch = blk / ncb;
+  const int c0 = (blk % ncb) * CB;
   const int nthr = CB * T;
   float2* Sc = S + (long long)ch * N * pitch;
   for (int idx = threadIdx.x; idx < N * CB; idx += nthr) {

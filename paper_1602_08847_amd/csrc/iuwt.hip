@@ -9,6 +9,8 @@
 //   SM_DETAIL1     out2 = H_j A and u update with w = A - H_j A              (first generation)
 //   DB_ANALYSIS    c' = H_j c (written to out2), w = c - H_j c', u update     (second generation)
 //   DB_ADJOINT     out = u + H_j (a - H_j u)  (A = u, B = a)                  (second generation)
+//   DB_ANALYSIS_C  DB_ANALYSIS whose c' feeds the coarse plane's dual update (out2 = that plane)
+//                  instead of being stored: the last scale of the analysis
 // Workgroups are ordered so that each XCD (blocks b, b + 8, ...) walks a contiguous range of
 // bands, keeping neighbouring bands' edge rows in its own L2.
 #include "common.h"
@@ -40,16 +42,9 @@ struct AtrousArgs {
   int N, j, TX, TY;
   int tiles_x, tiles_per_ch, nblocks;
   int small;  // halo may exceed N: wrap with a full modulo
-  float coef, rho;
+  float coef, rho, coef2;
   double* partial;
 };
-
-// XCD-aware block order: block b runs on XCD b % 8; XCD x gets a contiguous range of tiles.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  const int per = nb >> 3, rem = nb & 7;
-  const int x = b & 7, i = b >> 3;
-  return x * per + (x < rem ? x : rem) + i;
-}
 
 __device__ __forceinline__ int wrap_idx(int v, int N, int small) {
   if (small) {
@@ -74,12 +69,13 @@ __device__ __forceinline__ float b3(float c0, float c1, float c2, float c3, floa
 // which extends the first stage by 2s rows on each side of the band.
 template <int KR>
 struct BandPre {
-  float a[KR], b[KR], e[KR], u[KR];
+  float a[KR], b[KR], e[KR], u[KR], u2[KR];
 };
 
 template <int MODE, int KR>
 __device__ __forceinline__ void band_body(const AtrousArgs& a) {
-  constexpr bool DBL = (MODE == DB_ANALYSIS || MODE == DB_ADJOINT);
+  constexpr bool ANA = (MODE == DB_ANALYSIS || MODE == DB_ANALYSIS_C);
+  constexpr bool DBL = (ANA || MODE == DB_ADJOINT);
   extern __shared__ float sm[];
   const int N = a.N, s = 1 << a.j, x = threadIdx.x, TY = a.TY;
   const int small = a.small;
@@ -119,8 +115,10 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
             P.e[kk] = E[(long long)y * N + x];
           if constexpr (MODE == SM_DETAIL || MODE == SM_DETAIL1) P.u[kk] = O[(long long)y * N + x];
           if constexpr (MODE == DB_ADJOINT) P.e[kk] = B[(long long)wrap_idx(y, N, small) * N + x];
-          if constexpr (MODE == DB_ANALYSIS)
+          if constexpr (ANA)
             if (m >= 4) P.u[kk] = O[(long long)(y - 2 * s) * N + x];
+          if constexpr (MODE == DB_ANALYSIS_C)
+            if (y >= y0 && y < y0 + TY) P.u2[kk] = O2[(long long)y * N + x];
         }
       }
     }
@@ -206,6 +204,11 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
           float qin = P[kk];
           if constexpr (MODE == DB_ADJOINT) {
             qin = cur.e[kk] - qin;
+          } else if constexpr (MODE == DB_ANALYSIS_C) {
+            if (y >= y0 && y < y0 + TY) {
+              const float u2 = cur.u2[kk];
+              O2[(long long)y * N + x] = a.rho * satf(u2 + a.coef2 * qin) + (1.f - a.rho) * u2;
+            }
           } else {
             if (y >= y0 && y < y0 + TY) O2[(long long)y * N + x] = qin;
           }
@@ -278,7 +281,8 @@ static long long tune_key(int N, int j, int cls) { return ((long long)N << 16) |
 
 int atrous_class(int mode) {
   switch (mode) {
-    case DB_ANALYSIS: return 0;
+    case DB_ANALYSIS:
+    case DB_ANALYSIS_C: return 0;
     case DB_ADJOINT: return 1;
     case SM_DETAIL1: return 2;
     case SM_SUBADD: return 3;
@@ -307,7 +311,8 @@ bool atrous_double_fits(int N, int j, int* TXo, int* TYo) {
 }
 
 int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out, PlaneOut out2,
-                  float coef, float rho, double* partial, int* nblocks_out, hipStream_t st, int trial) {
+                  float coef, float rho, double* partial, int* nblocks_out, hipStream_t st, int trial,
+                  float coef2) {
   AtrousArgs a;
   a.A = A;
   a.B = B;
@@ -318,8 +323,9 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   a.j = j;
   a.coef = coef;
   a.rho = rho;
+  a.coef2 = coef2;
   a.partial = partial;
-  const bool dbl = (mode == DB_ANALYSIS || mode == DB_ADJOINT);
+  const bool dbl = (mode == DB_ANALYSIS || mode == DB_ADJOINT || mode == DB_ANALYSIS_C);
   if (N > 1024) return set_error("atrous: N > 1024"), MUFFIN_EINVAL;
   a.TX = N;
   a.TY = atrous_band_rows(N, j, mode);
@@ -335,7 +341,7 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   a.nblocks = (int)nb;
   const int s = 1 << j;
   a.small = (dbl ? 4 * s : 2 * s) + a.TY >= N ? 1 : 0;  // row indices may leave [-N, 2N)
-  const size_t shm = sizeof(float) * (size_t)2 * kKR * N;
+  const size_t shm = sizeof(float) * (size_t)2 * (dbl ? kKR2 : kKR) * N;
   const dim3 grid((unsigned)nb), block((unsigned)N);
   if (trial) {
     switch (mode) {
@@ -343,6 +349,9 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
       case SM_DETAIL1: hipLaunchKernelGGL((k_band_trial<SM_DETAIL1, kKR>), grid, block, shm, st, a); break;
       case DB_ANALYSIS: hipLaunchKernelGGL((k_band_trial<DB_ANALYSIS, kKR2>), grid, block, shm, st, a); break;
       case DB_ADJOINT: hipLaunchKernelGGL((k_band_trial<DB_ADJOINT, kKR2>), grid, block, shm, st, a); break;
+      case DB_ANALYSIS_C:
+        hipLaunchKernelGGL((k_band_trial<DB_ANALYSIS_C, kKR2>), grid, block, shm, st, a);
+        break;
       default: set_error("atrous: no trial variant for this mode"); return MUFFIN_EINVAL;
     }
     MF_HIP(hipGetLastError());
@@ -356,6 +365,7 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
     case SM_DETAIL1: hipLaunchKernelGGL((k_band<SM_DETAIL1, kKR>), grid, block, shm, st, a); break;
     case DB_ANALYSIS: hipLaunchKernelGGL((k_band<DB_ANALYSIS, kKR2>), grid, block, shm, st, a); break;
     case DB_ADJOINT: hipLaunchKernelGGL((k_band<DB_ADJOINT, kKR2>), grid, block, shm, st, a); break;
+    case DB_ANALYSIS_C: hipLaunchKernelGGL((k_band<DB_ANALYSIS_C, kKR2>), grid, block, shm, st, a); break;
     default: set_error("atrous: bad mode"); return MUFFIN_EINVAL;
   }
   MF_HIP(hipGetLastError());
@@ -372,6 +382,10 @@ int atrous_init_attrs() {
   MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_DETAIL1, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ANALYSIS, kKR2>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ADJOINT, kKR2>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band<DB_ANALYSIS_C, kKR2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<DB_ANALYSIS_C, kKR2>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_SUBADD, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_DETAIL1, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,

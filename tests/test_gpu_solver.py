@@ -44,6 +44,30 @@ def test_trajectory_matches_oracle_small_cube(lib, small, gen):
     assert abs(f - f_ref) / abs(f_ref) < 1e-4
 
 
+@pytest.mark.parametrize("penalize_coarse,rho", [(False, 1.0), (True, 0.8)])
+def test_trajectory_coarse_plane_and_relaxation(lib, small, penalize_coarse, rho):
+    """The last analysis scale updates the coarse dual in the same launch; check it with the coarse
+    plane unpenalised (omega = 0 there, its dual stays 0) and with relaxation rho < 1."""
+    c = small
+    dirty, psf = f32(c.dirty), f32(c.psf)
+    omega = np.ones(4)
+    omega[3] = 1.0 if penalize_coarse else 0.0
+    p = om.Problem(dirty=dirty, psf=psf, J=3, mu_s=0.25, mu_l=3.0, omega=omega, sigma=10.0, rho=rho)
+    tau = om.step_sizes(p)[0]
+    st, _ = om.solve(p, 20, tau=tau)
+    with lib.Muffin(dirty, psf, J=3, mu_s=0.25, mu_lambda=3.0, penalize_coarse=penalize_coarse, tau=tau,
+                    sigma=10.0, rho=rho) as m:
+        m.step(20)
+        X = m.get_x().double().cpu().numpy()
+        U = m.get_u().double().cpu().numpy()
+        V = m.get_v().double().cpu().numpy()
+    assert rel(X, st.X) < 1e-4
+    assert rel(U, st.U) < 1e-4
+    assert rel(V, st.V) < 1e-4
+    if not penalize_coarse:
+        assert np.all(U[:, 3] == 0)
+
+
 def test_single_iteration_matches_oracle_tightly(lib, small):
     c = small
     dirty, psf = f32(c.dirty), f32(c.psf)
