@@ -67,6 +67,15 @@ __device__ __forceinline__ float b3(float c0, float c1, float c2, float c3, floa
 // round is computed, so memory latency overlaps the LDS passes and barriers.  Double-smoothing
 // modes chain a second window over the first stage's output in the same class, two steps behind,
 // which extends the first stage by 2s rows on each side of the band.
+// Plane accesses by a 32-bit byte offset from a uniform base (a channel plane is < 4 GiB), so the
+// address is an SGPR pair plus one VGPR.
+__device__ __forceinline__ float ldp(const float* __restrict__ p, unsigned idx) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + (idx << 2));
+}
+__device__ __forceinline__ void stp(float* __restrict__ p, unsigned idx, float v) {
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(p) + (idx << 2)) = v;
+}
+
 template <int KR>
 struct BandPre {
   float a[KR], b[KR], e[KR], u[KR], u2[KR];
@@ -98,49 +107,35 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
     const int M1 = (TY + 2 * E1 - r + s - 1) / s;
     return M1 > 0 ? M1 + 4 : 0;
   };
+  // Every load of a round is issued unconditionally: steps past the end of a class, and operands
+  // of steps that have none, read a row of the same set at a clamped index, so the number of
+  // loads in flight is the same on every path and the compiler waits only for the round it uses.
+  const int ylast = y0 + TY - 1;
   auto load_round = [&](BandPre<KR>& P, int r, int t0) {
     const int first = y0 + r - E1, ns = nsteps(r);
 #pragma unroll
     for (int kk = 0; kk < KR; ++kk) {
-      const int t = t0 + kk;
-      if (t < ns) {
-        // step t brings row y_m + 2s (m = t - 4) into the window
-        const long long g = (long long)wrap_idx(first + (t - 2) * s, N, small) * N + x;
-        P.a[kk] = A[g];
-        if constexpr (MODE == SM_SUBADD) P.b[kk] = B[g];
-        const int m = t - 4;
-        if (m >= 0) {
-          const int y = first + m * s;
-          if constexpr (MODE == SM_SUBADD || MODE == SM_DETAIL || MODE == SM_DETAIL_ABS)
-            P.e[kk] = E[(long long)y * N + x];
-          if constexpr (MODE == SM_DETAIL || MODE == SM_DETAIL1) P.u[kk] = O[(long long)y * N + x];
-          if constexpr (MODE == DB_ADJOINT) P.e[kk] = B[(long long)wrap_idx(y, N, small) * N + x];
-          if constexpr (ANA)
-            if (m >= 4) P.u[kk] = O[(long long)(y - 2 * s) * N + x];
-          if constexpr (MODE == DB_ANALYSIS_C)
-            if (y >= y0 && y < y0 + TY) P.u2[kk] = O2[(long long)y * N + x];
-        }
-      }
+      const int t = min(t0 + kk, ns - 1);
+      // step t brings row y_m + 2s (m = t - 4) into the window
+      const unsigned g = (unsigned)(wrap_idx(first + (t - 2) * s, N, small) * N + x);
+      P.a[kk] = ldp(A, g);
+      if constexpr (MODE == SM_SUBADD) P.b[kk] = ldp(B, g);
+      const int m = max(t - 4, 0);
+      const int y = first + m * s;
+      const unsigned gb = (unsigned)(min(y, ylast) * N + x);  // a row of the band
+      if constexpr (MODE == SM_SUBADD || MODE == SM_DETAIL || MODE == SM_DETAIL_ABS) P.e[kk] = ldp(E, gb);
+      if constexpr (MODE == SM_DETAIL || MODE == SM_DETAIL1) P.u[kk] = ldp(O, gb);
+      if constexpr (MODE == DB_ADJOINT) P.e[kk] = ldp(B, (unsigned)(wrap_idx(y, N, small) * N + x));
+      if constexpr (ANA) P.u[kk] = ldp(O, (unsigned)(min(first + (max(m, 4) - 2) * s, ylast) * N + x));
+      if constexpr (MODE == DB_ANALYSIS_C) P.u2[kk] = ldp(O2, (unsigned)(min(max(y, y0), ylast) * N + x));
     }
   };
   double acc = 0.0;
   int round = 0;
-  int r = 0;
-  while (r < s && nsteps(r) == 0) ++r;
-  int t0 = 0;
-  BandPre<KR> cur, nxt;
-  if (r < s) load_round(cur, r, t0);
   float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
   float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
-  while (r < s) {
+  auto process = [&](const BandPre<KR>& cur, int r, int t0) {
     const int ns = nsteps(r), first = y0 + r - E1;
-    int rn = r, tn = t0 + KR;
-    if (tn >= ns) {
-      rn = r + 1;
-      tn = 0;
-      while (rn < s && nsteps(rn) == 0) ++rn;
-    }
-    if (rn < s) load_round(nxt, rn, tn);
     float pv[KR], cen1[KR], cen2[KR];
 #pragma unroll
     for (int kk = 0; kk < KR; ++kk) {
@@ -177,18 +172,18 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
       for (int kk = 0; kk < KR; ++kk) {
         const int m = t0 + kk - 4;
         if (m < 0 || t0 + kk >= ns) continue;
-        const long long g = (long long)(first + m * s) * N + x;  // inside the band
+        const unsigned g = (unsigned)((first + m * s) * N + x);  // inside the band
         const float v = P[kk];
         if constexpr (MODE == SM_SMOOTH) {
-          O[g] = v;
+          stp(O, g, v);
         } else if constexpr (MODE == SM_SUBADD) {
-          O[g] = cur.e[kk] + v;
+          stp(O, g, cur.e[kk] + v);
         } else if constexpr (MODE == SM_DETAIL || MODE == SM_DETAIL1) {
           const float e = (MODE == SM_DETAIL) ? cur.e[kk] : cen1[kk];
           const float w = e - v;
           const float u = cur.u[kk];
-          O[g] = a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u;
-          if (MODE == SM_DETAIL1) O2[g] = v;
+          stp(O, g, a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u);
+          if (MODE == SM_DETAIL1) stp(O2, g, v);
         } else {
           acc += fabs((double)cur.e[kk] - (double)v);
         }
@@ -207,10 +202,10 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
           } else if constexpr (MODE == DB_ANALYSIS_C) {
             if (y >= y0 && y < y0 + TY) {
               const float u2 = cur.u2[kk];
-              O2[(long long)y * N + x] = a.rho * satf(u2 + a.coef2 * qin) + (1.f - a.rho) * u2;
+              stp(O2, (unsigned)(y * N + x), a.rho * satf(u2 + a.coef2 * qin) + (1.f - a.rho) * u2);
             }
           } else {
-            if (y >= y0 && y < y0 + TY) O2[(long long)y * N + x] = qin;
+            if (y >= y0 && y < y0 + TY) stp(O2, (unsigned)(y * N + x), qin);
           }
           if (m >= 4) rv[kk] = b3(q0, q1, q2, q3, qin);
           q0 = q1;
@@ -228,20 +223,46 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
         if (m < 4 || t0 + kk >= ns) continue;
         const float* row = buf2 + kk * N;
         const float R = b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]);
-        const long long g = (long long)(first + m * s - 2 * s) * N + x;  // stage-2 row, inside the band
+        const unsigned g = (unsigned)((first + m * s - 2 * s) * N + x);  // stage-2 row, inside the band
         if constexpr (MODE == DB_ADJOINT) {
-          O[g] = cen2[kk] + R;
+          stp(O, g, cen2[kk] + R);
         } else {
           const float w = cen2[kk] - R;
           const float u = cur.u[kk];
-          O[g] = a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u;
+          stp(O, g, a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u);
         }
       }
     }
     ++round;
-    cur = nxt;
-    r = rn;
-    t0 = tn;
+  };
+  // next round after (r, t0): the following KR steps of class r, else the first steps of the next
+  // class that has any
+  auto advance = [&](int& r, int& t0) {
+    t0 += KR;
+    if (t0 >= nsteps(r)) {
+      t0 = 0;
+      ++r;
+      while (r < s && nsteps(r) == 0) ++r;
+    }
+  };
+  int r = 0;
+  while (r < s && nsteps(r) == 0) ++r;
+  if (r < s) {
+    // round k + 1 loads while round k is computed; the copy into cur at the end of the round is
+    // the only wait for those loads
+    BandPre<KR> cur, nxt;
+    int t0 = 0;
+    load_round(cur, r, t0);
+    while (true) {
+      int rn = r, tn = t0;
+      advance(rn, tn);
+      load_round(nxt, rn < s ? rn : r, rn < s ? tn : t0);  // past the end: repeats this round, unused
+      process(cur, r, t0);
+      if (rn >= s) break;
+      cur = nxt;
+      r = rn;
+      t0 = tn;
+    }
   }
   if constexpr (MODE == SM_DETAIL_ABS) {
     const double tot = block_sum_atrous(acc);
