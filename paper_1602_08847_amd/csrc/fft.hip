@@ -19,6 +19,7 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, f
                                                   int pitch, long long npairs, const float2* __restrict__ tw,
                                                   int shift) {
   constexpr int T = Plan<N>::T;
+  constexpr int NI = N / T;  // entries of one transform per thread
   constexpr int FPB = (256 / T) > 0 ? (256 / T) : 1;
   constexpr int LS = lstride<N>();
   __shared__ float2 lds[FPB * LS];
@@ -39,10 +40,16 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, f
     }
     const float* pa = xc + (long long)ra * N;
     const float* pb = xc + (long long)rb * N;
-    for (int i = t; i < N; i += T) {
-      const int c = shift ? (i + N / 2) % N : i;
-      buf[lpad(i)] = make_float2(pa[c], pb[c]);
+    // all N/T loads of the thread in flight at once, then into LDS
+    float va[NI], vb[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int c = shift ? (t + i * T + N / 2) % N : t + i * T;
+      va[i] = pa[c];
+      vb[i] = pb[c];
     }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) buf[lpad(t + i * T)] = make_float2(va[i], vb[i]);
   }
   lds_barrier();
   fft_lds<N, false>(buf, t, active, tw);
@@ -85,26 +92,54 @@ __global__ void __launch_bounds__(512) k_cols(float2* __restrict__ S, int pitch,
   const int ch = blk / ncb;
   const int c0 = (blk % ncb) * CB;
   const int nthr = CB * T;
+  constexpr int NI = N / T;  // entries per thread: N * CB / nthr
   float2* Sc = S + (long long)ch * N * pitch;
-  for (int idx = threadIdx.x; idx < N * CB; idx += nthr) {
-    const int r = idx / CB, c = idx % CB;
-    lds[c * LS + lpad(r)] = Sc[(long long)r * pitch + c0 + c];
+  {
+    // all loads of the thread in flight at once, then into LDS
+    float2 v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int idx = threadIdx.x + i * nthr;
+      v[i] = Sc[(long long)(idx / CB) * pitch + c0 + idx % CB];
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int idx = threadIdx.x + i * nthr;
+      lds[(idx % CB) * LS + lpad(idx / CB)] = v[i];
+    }
   }
-  lds_barrier();
   const int f = threadIdx.x / T, t = threadIdx.x % T;
+  const long long mrow = ((long long)ch * pitch + c0 + f) * N;  // transposed multiplier row
+  // the multiplier: fetched after the forward transform, all of the thread's entries at once (held
+  // across the transform it would cost an occupancy step)
+  float mr[MODE == COL_REAL ? NI : 1];
+  float2 mc[(MODE == COL_CPLX || MODE == COL_CPLX_CONJ) ? NI : 1];
+  lds_barrier();
   float2* buf = lds + f * LS;
   fft_lds<N, false>(buf, t, true, tw);
-  const long long mrow = ((long long)ch * pitch + c0 + f) * N;  // transposed multiplier row
+  if constexpr (MODE == COL_REAL) {
+    const float* __restrict__ mp = Mr + mrow + t;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) mr[i] = mp[i * T];
+  }
+  if constexpr (MODE == COL_CPLX || MODE == COL_CPLX_CONJ) {
+    const float2* __restrict__ mp = Mc + mrow + t;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) mc[i] = mp[i * T];
+  }
   if constexpr (MODE == COL_FWD) {
-    for (int r = t; r < N; r += T) outT[mrow + r] = buf[lpad(r)];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) outT[mrow + t + i * T] = buf[lpad(t + i * T)];
     return;
   } else {
-    for (int r = t; r < N; r += T) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int r = t + i * T;
       float2 v = buf[lpad(r)];
       if constexpr (MODE == COL_REAL) {
-        v = cscale(v, Mr[mrow + r] * scale);
+        v = cscale(v, mr[i] * scale);
       } else {
-        float2 m = Mc[mrow + r];
+        float2 m = mc[i];
         if (MODE == COL_CPLX_CONJ) m.y = -m.y;
         v = cscale(cmul(v, m), scale);
       }
@@ -113,9 +148,10 @@ __global__ void __launch_bounds__(512) k_cols(float2* __restrict__ S, int pitch,
     // fft_lds begins with reads of this thread group's own entries only after a barrier
     lds_barrier();
     fft_lds<N, true>(buf, t, true, tw);
-    for (int idx = threadIdx.x; idx < N * CB; idx += nthr) {
-      const int r = idx / CB, c = idx % CB;
-      Sc[(long long)r * pitch + c0 + c] = lds[c * LS + lpad(r)];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int idx = threadIdx.x + i * nthr;
+      Sc[(long long)(idx / CB) * pitch + c0 + idx % CB] = lds[(idx % CB) * LS + lpad(idx / CB)];
     }
   }
 }
@@ -142,6 +178,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
                                                   float s_scale, const float* __restrict__ y,
                                                   const float* __restrict__ chan_w, double* __restrict__ partial) {
   constexpr int T = Plan<N>::T;
+  constexpr int NI = N / T;  // entries of one transform per thread
   constexpr int FPB = (256 / T) > 0 ? (256 / T) : 1;
   constexpr int LS = lstride<N>();
   __shared__ float2 lds[FPB * LS];
@@ -151,23 +188,36 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
   float2* buf = lds + (f < FPB ? f : 0) * LS;
   long long ch = 0;
   int r0 = 0;
+  long long o0 = 0, o1 = 0;
+  // epilogue operands of the thread's outputs, fetched after the transform, all at once
+  constexpr int NE = (EPI == EPI_STORE) ? 1 : NI;
+  float e0[NE], e1[NE], s0[NE], s1[NE];
   if (active) {
     ch = pair / (N / 2);
     r0 = 2 * (int)(pair % (N / 2));
+    o0 = (ch * N + r0) * (long long)N;
+    o1 = o0 + N;
     const float2* sa = S + (ch * N + r0) * (long long)pitch;
     const float2* sb = sa + pitch;
-    for (int k = t; k < N; k += T) {
-      float2 a, bb;
-      if (k <= N / 2) {
-        a = sa[k];
-        bb = sb[k];
-        if (k == 0 || k == N / 2) {
-          a.y = 0.f;
-          bb.y = 0.f;
-        }
-      } else {
-        a = cconj(sa[N - k]);
-        bb = cconj(sb[N - k]);
+    // entries above N/2 are the conjugates of stored ones (Hermitian symmetry of real rows)
+    float2 va[NI], vb[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int k = t + i * T;
+      const int ks = k <= N / 2 ? k : N - k;
+      va[i] = sa[ks];
+      vb[i] = sb[ks];
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int k = t + i * T;
+      float2 a = va[i], bb = vb[i];
+      if (k == 0 || k == N / 2) {
+        a.y = 0.f;
+        bb.y = 0.f;
+      } else if (k > N / 2) {
+        a = cconj(a);
+        bb = cconj(bb);
       }
       // Z = A + i B
       buf[lpad(k)] = make_float2(a.x - bb.y, a.y + bb.x);
@@ -177,24 +227,40 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
   fft_lds<N, true>(buf, t, active, tw);
   double acc = 0.0;
   if (active) {
-    const long long o0 = (ch * N + r0) * (long long)N;
-    const long long o1 = o0 + N;
-    for (int n = t; n < N; n += T) {
+    if constexpr (EPI != EPI_STORE) {
+      const float* __restrict__ ep = ((EPI == EPI_GRAD) ? b : y) + o0 + t;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        e0[i] = ep[i * T];
+        e1[i] = ep[N + i * T];
+      }
+      if (EPI == EPI_GRAD && s) {
+        const float* __restrict__ sp = s + o0 + t;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          s0[i] = sp[i * T];
+          s1[i] = sp[N + i * T];
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int n = t + i * T;
       const float2 z = buf[lpad(n)];
       if constexpr (EPI == EPI_STORE) {
         out[o0 + n] = z.x;
         out[o1 + n] = z.y;
       } else if constexpr (EPI == EPI_GRAD) {
-        float g0 = z.x - b[o0 + n], g1 = z.y - b[o1 + n];
+        float g0 = z.x - e0[i], g1 = z.y - e1[i];
         if (s) {
-          g0 += s_scale * s[o0 + n];
-          g1 += s_scale * s[o1 + n];
+          g0 += s_scale * s0[i];
+          g1 += s_scale * s1[i];
         }
         out[o0 + n] = g0;
         out[o1 + n] = g1;
       } else {
-        const double r0d = (double)z.x - (double)y[o0 + n];
-        const double r1d = (double)z.y - (double)y[o1 + n];
+        const double r0d = (double)z.x - (double)e0[i];
+        const double r1d = (double)z.y - (double)e1[i];
         acc += r0d * r0d + r1d * r1d;
       }
     }
