@@ -41,18 +41,9 @@ struct AtrousArgs {
   PlaneOut out, out2;
   int N, j, TX, TY;
   int tiles_x, tiles_per_ch, nblocks;
-  int small;  // halo may exceed N: wrap with a full modulo
   float coef, rho, coef2;
   double* partial;
 };
-
-__device__ __forceinline__ int wrap_idx(int v, int N, int small) {
-  if (small) {
-    v %= N;
-    return v < 0 ? v + N : v;
-  }
-  return v < 0 ? v + N : (v >= N ? v - N : v);
-}
 
 __device__ __forceinline__ float b3(float c0, float c1, float c2, float c3, float c4) {
   return 0.0625f * (c0 + c4) + 0.25f * (c1 + c3) + 0.375f * c2;
@@ -62,20 +53,16 @@ __device__ __forceinline__ float b3(float c0, float c1, float c2, float c3, floa
 // column x.  Rows are visited residue class by residue class modulo s, so the vertical 5-tap
 // filter is a sliding window of five registers fed by one coalesced row load per step (the first
 // four steps of a class only fill the window).  Steps are grouped in rounds of KR; the KR vertical
-// results of a round go through LDS for the horizontal taps (x +- s, x +- 2s, periodic).  Every
-// global load of the next round (input rows and epilogue operands) is issued before the current
-// round is computed, so memory latency overlaps the LDS passes and barriers.  Double-smoothing
-// modes chain a second window over the first stage's output in the same class, two steps behind,
-// which extends the first stage by 2s rows on each side of the band.
-// Plane accesses by a 32-bit byte offset from a uniform base (a channel plane is < 4 GiB), so the
-// address is an SGPR pair plus one VGPR.
-__device__ __forceinline__ float ldp(const float* __restrict__ p, unsigned idx) {
-  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(p) + (idx << 2));
-}
-__device__ __forceinline__ void stp(float* __restrict__ p, unsigned idx, float v) {
-  *reinterpret_cast<float*>(reinterpret_cast<char*>(p) + (idx << 2)) = v;
-}
-
+// results of a round go through LDS for the horizontal taps (x +- s, x +- 2s, periodic).  Double-
+// smoothing modes chain a second window over the first stage's output in the same class, two
+// steps behind, which extends the first stage by 2s rows on each side of the band.
+//
+// The schedule is kept cheap for the scalar unit, which issues the uniform bookkeeping of all the
+// waves of a SIMD: each class is padded to whole rounds, so every step loads, filters and shifts
+// its windows the same way and only the stores test whether the step is a real output; the rows
+// of the load streams are byte offsets advanced by s rows per step with one conditional wrap (a
+// full modulo is taken once per class).  The next round's loads are all issued before the current
+// round is computed, so their latency overlaps the LDS passes and barriers.
 template <int KR>
 struct BandPre {
   float a[KR], b[KR], e[KR], u[KR], u2[KR];
@@ -85,77 +72,102 @@ template <int MODE, int KR>
 __device__ __forceinline__ void band_body(const AtrousArgs& a) {
   constexpr bool ANA = (MODE == DB_ANALYSIS || MODE == DB_ANALYSIS_C);
   constexpr bool DBL = (ANA || MODE == DB_ADJOINT);
+  // which load streams a mode has: a at step row (t - 2)s, e at (t - 4)s, u at (t - 4)s or, for the
+  // analysis, (t - 6)s (the stage-2 row)
+  constexpr bool LB = (MODE == SM_SUBADD);
+  constexpr bool LE = (MODE == SM_SUBADD || MODE == SM_DETAIL || MODE == SM_DETAIL_ABS || MODE == DB_ADJOINT);
+  constexpr bool LU = (MODE == SM_DETAIL || MODE == SM_DETAIL1);
   extern __shared__ float sm[];
-  const int N = a.N, s = 1 << a.j, x = threadIdx.x, TY = a.TY;
-  const int small = a.small;
+  const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
   float* buf1 = sm;                            // [2][KR][N] single stage, [KR][N] double
   float* buf2 = sm + (DBL ? KR : 2 * KR) * N;  // [KR][N]
   const int b = xcd_remap(blockIdx.x, a.nblocks);
   const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
-  const int y0 = band * TY;
+  const int y0 = band * TY, y1 = y0 + TY;
   const int E1 = DBL ? 2 * s : 0;
-  const float* __restrict__ A = a.A.p + ch * a.A.cs;
-  const float* __restrict__ B = (MODE == SM_SUBADD || MODE == DB_ADJOINT) ? a.B.p + ch * a.B.cs : nullptr;
-  const float* __restrict__ E =
-      (MODE == SM_SUBADD || MODE == SM_DETAIL || MODE == SM_DETAIL_ABS) ? a.E.p + ch * a.E.cs : nullptr;
+  const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
+  const char* __restrict__ B =
+      (MODE == SM_SUBADD || MODE == DB_ADJOINT) ? reinterpret_cast<const char*>(a.B.p + ch * a.B.cs) : nullptr;
+  const char* __restrict__ E = (MODE == SM_SUBADD || MODE == SM_DETAIL || MODE == SM_DETAIL_ABS)
+                                   ? reinterpret_cast<const char*>(a.E.p + ch * a.E.cs)
+                                   : nullptr;
   float* __restrict__ O = a.out.p ? a.out.p + ch * a.out.cs : nullptr;
   float* __restrict__ O2 = a.out2.p ? a.out2.p + ch * a.out2.cs : nullptr;
-  const int xm2 = wrap_idx(x - 2 * s, N, 1), xm1 = wrap_idx(x - s, N, 1);
-  const int xp1 = wrap_idx(x + s, N, 1), xp2 = wrap_idx(x + 2 * s, N, 1);
-  // class r: stage-1 outputs at rows first(r) + m s, m < M1(r); load steps t = m + 4
-  auto nsteps = [&](int r) -> int {
-    const int M1 = (TY + 2 * E1 - r + s - 1) / s;
-    return M1 > 0 ? M1 + 4 : 0;
+  const int xm2 = ((x - 2 * s) % N + N) % N, xm1 = ((x - s) % N + N) % N;
+  const int xp1 = (x + s) % N, xp2 = (x + 2 * s) % N;
+  // bytes; a step of s rows is a step of s mod N rows on the periodic plane
+  const int rowb = N * 4, planeb = N * N * 4, stepb = (s % N) * rowb;
+  const unsigned xb = (unsigned)x * 4u;
+  auto at = [&](const char* base, int off) -> float {
+    return *reinterpret_cast<const float*>(base + off + xb);
   };
-  // Every load of a round is issued unconditionally: steps past the end of a class, and operands
-  // of steps that have none, read a row of the same set at a clamped index, so the number of
-  // loads in flight is the same on every path and the compiler waits only for the round it uses.
-  const int ylast = y0 + TY - 1;
-  auto load_round = [&](BandPre<KR>& P, int r, int t0) {
-    const int first = y0 + r - E1, ns = nsteps(r);
+  auto put = [&](float* base, int y, float v) {  // row y of the band
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
+  };
+  // class r: stage-1 outputs at rows first(r) + m s, m < M1(r); steps t = m + 4, padded to rounds
+  auto nsteps = [&](int r) -> int {
+    const int v = TY + 2 * E1 - r;
+    return v > 0 ? ((v + s - 1) >> jj) + 4 : 0;
+  };
+  auto padded = [&](int ns) -> int { return (ns + KR - 1) / KR * KR; };
+  auto rowoff = [&](int y) -> int {  // byte offset of row y mod N
+    y %= N;
+    return (y < 0 ? y + N : y) * rowb;
+  };
+  auto adv = [&](int& o) {
+    o += stepb;
+    if (o >= planeb) o -= planeb;
+  };
+  // load stream: the next round to load is steps [lt, lt + KR) of class lr
+  int lr = 0, lt = 0, oa = 0, oe = 0, ou = 0;
+  auto start_class = [&](int r) {
+    const int f = y0 + r - E1;
+    oa = rowoff(f - 2 * s);
+    if constexpr (LE || LU || MODE == DB_ANALYSIS_C) oe = rowoff(f - 4 * s);
+    if constexpr (ANA) ou = rowoff(f - 6 * s);
+  };
+  auto load_round = [&](BandPre<KR>& P) {
 #pragma unroll
     for (int kk = 0; kk < KR; ++kk) {
-      const int t = min(t0 + kk, ns - 1);
-      // step t brings row y_m + 2s (m = t - 4) into the window
-      const unsigned g = (unsigned)(wrap_idx(first + (t - 2) * s, N, small) * N + x);
-      P.a[kk] = ldp(A, g);
-      if constexpr (MODE == SM_SUBADD) P.b[kk] = ldp(B, g);
-      const int m = max(t - 4, 0);
-      const int y = first + m * s;
-      const unsigned gb = (unsigned)(min(y, ylast) * N + x);  // a row of the band
-      if constexpr (MODE == SM_SUBADD || MODE == SM_DETAIL || MODE == SM_DETAIL_ABS) P.e[kk] = ldp(E, gb);
-      if constexpr (MODE == SM_DETAIL || MODE == SM_DETAIL1) P.u[kk] = ldp(O, gb);
-      if constexpr (MODE == DB_ADJOINT) P.e[kk] = ldp(B, (unsigned)(wrap_idx(y, N, small) * N + x));
-      if constexpr (ANA) P.u[kk] = ldp(O, (unsigned)(min(first + (max(m, 4) - 2) * s, ylast) * N + x));
-      if constexpr (MODE == DB_ANALYSIS_C) P.u2[kk] = ldp(O2, (unsigned)(min(max(y, y0), ylast) * N + x));
+      P.a[kk] = at(A, oa);
+      if constexpr (LB) P.b[kk] = at(B, oa);
+      if constexpr (LE) P.e[kk] = at(MODE == DB_ADJOINT ? B : E, oe);
+      if constexpr (LU) P.u[kk] = at(reinterpret_cast<const char*>(O), oe);
+      if constexpr (ANA) P.u[kk] = at(reinterpret_cast<const char*>(O), ou);
+      if constexpr (MODE == DB_ANALYSIS_C) P.u2[kk] = at(reinterpret_cast<const char*>(O2), oe);
+      adv(oa);
+      if constexpr (LE || LU || MODE == DB_ANALYSIS_C) adv(oe);
+      if constexpr (ANA) adv(ou);
+    }
+  };
+  auto advance_load = [&]() {
+    lt += KR;
+    if (lt >= padded(nsteps(lr))) {
+      lt = 0;
+      do {
+        ++lr;
+      } while (lr < s && nsteps(lr) == 0);
+      if (lr < s) start_class(lr);
     }
   };
   double acc = 0.0;
   int round = 0;
   float w0 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
   float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
-  auto process = [&](const BandPre<KR>& cur, int r, int t0) {
-    const int ns = nsteps(r), first = y0 + r - E1;
+  // round of steps [t0, t0 + KR) of a class with ns real steps whose first stage-1 row is first
+  auto process = [&](const BandPre<KR>& cur, int t0, int ns, int first) {
     float pv[KR], cen1[KR], cen2[KR];
 #pragma unroll
     for (int kk = 0; kk < KR; ++kk) {
-      const int t = t0 + kk;
-      pv[kk] = 0.f;
-      cen1[kk] = 0.f;
-      cen2[kk] = 0.f;
-      if (t < ns) {
-        float w4 = cur.a[kk];
-        if constexpr (MODE == SM_SUBADD) w4 -= cur.b[kk];
-        if (t >= 4) {
-          pv[kk] = b3(w0, w1, w2, w3, w4);
-          cen1[kk] = w2;
-          cen2[kk] = w0;
-        }
-        w0 = w1;
-        w1 = w2;
-        w2 = w3;
-        w3 = w4;
-      }
+      float w4 = cur.a[kk];
+      if constexpr (MODE == SM_SUBADD) w4 -= cur.b[kk];
+      pv[kk] = b3(w0, w1, w2, w3, w4);
+      cen1[kk] = w2;
+      cen2[kk] = w0;
+      w0 = w1;
+      w1 = w2;
+      w2 = w3;
+      w3 = w4;
     }
     float* L1 = buf1 + (DBL ? 0 : (round & 1) * KR * N);
 #pragma unroll
@@ -172,18 +184,18 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
       for (int kk = 0; kk < KR; ++kk) {
         const int m = t0 + kk - 4;
         if (m < 0 || t0 + kk >= ns) continue;
-        const unsigned g = (unsigned)((first + m * s) * N + x);  // inside the band
+        const int y = first + m * s;  // inside the band
         const float v = P[kk];
         if constexpr (MODE == SM_SMOOTH) {
-          stp(O, g, v);
+          put(O, y, v);
         } else if constexpr (MODE == SM_SUBADD) {
-          stp(O, g, cur.e[kk] + v);
+          put(O, y, cur.e[kk] + v);
         } else if constexpr (MODE == SM_DETAIL || MODE == SM_DETAIL1) {
           const float e = (MODE == SM_DETAIL) ? cur.e[kk] : cen1[kk];
           const float w = e - v;
           const float u = cur.u[kk];
-          stp(O, g, a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u);
-          if (MODE == SM_DETAIL1) stp(O2, g, v);
+          put(O, y, a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u);
+          if (MODE == SM_DETAIL1) put(O2, y, v);
         } else {
           acc += fabs((double)cur.e[kk] - (double)v);
         }
@@ -193,26 +205,24 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
 #pragma unroll
       for (int kk = 0; kk < KR; ++kk) {
         const int m = t0 + kk - 4;
-        rv[kk] = 0.f;
-        if (m >= 0 && t0 + kk < ns) {
+        float qin = P[kk];
+        if constexpr (MODE == DB_ADJOINT) qin = cur.e[kk] - qin;
+        if constexpr (ANA) {
           const int y = first + m * s;
-          float qin = P[kk];
-          if constexpr (MODE == DB_ADJOINT) {
-            qin = cur.e[kk] - qin;
-          } else if constexpr (MODE == DB_ANALYSIS_C) {
-            if (y >= y0 && y < y0 + TY) {
+          if (m >= 0 && t0 + kk < ns && y >= y0 && y < y1) {
+            if constexpr (MODE == DB_ANALYSIS_C) {
               const float u2 = cur.u2[kk];
-              stp(O2, (unsigned)(y * N + x), a.rho * satf(u2 + a.coef2 * qin) + (1.f - a.rho) * u2);
+              put(O2, y, a.rho * satf(u2 + a.coef2 * qin) + (1.f - a.rho) * u2);
+            } else {
+              put(O2, y, qin);
             }
-          } else {
-            if (y >= y0 && y < y0 + TY) stp(O2, (unsigned)(y * N + x), qin);
           }
-          if (m >= 4) rv[kk] = b3(q0, q1, q2, q3, qin);
-          q0 = q1;
-          q1 = q2;
-          q2 = q3;
-          q3 = qin;
         }
+        rv[kk] = b3(q0, q1, q2, q3, qin);
+        q0 = q1;
+        q1 = q2;
+        q2 = q3;
+        q3 = qin;
       }
 #pragma unroll
       for (int kk = 0; kk < KR; ++kk) buf2[kk * N + x] = rv[kk];
@@ -223,45 +233,43 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
         if (m < 4 || t0 + kk >= ns) continue;
         const float* row = buf2 + kk * N;
         const float R = b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]);
-        const unsigned g = (unsigned)((first + m * s - 2 * s) * N + x);  // stage-2 row, inside the band
+        const int y = first + (m - 2) * s;  // stage-2 row, inside the band
         if constexpr (MODE == DB_ADJOINT) {
-          stp(O, g, cen2[kk] + R);
+          put(O, y, cen2[kk] + R);
         } else {
           const float w = cen2[kk] - R;
           const float u = cur.u[kk];
-          stp(O, g, a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u);
+          put(O, y, a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u);
         }
       }
     }
     ++round;
   };
-  // next round after (r, t0): the following KR steps of class r, else the first steps of the next
-  // class that has any
-  auto advance = [&](int& r, int& t0) {
-    t0 += KR;
-    if (t0 >= nsteps(r)) {
-      t0 = 0;
-      ++r;
-      while (r < s && nsteps(r) == 0) ++r;
-    }
-  };
   int r = 0;
   while (r < s && nsteps(r) == 0) ++r;
   if (r < s) {
-    // round k + 1 loads while round k is computed; the copy into cur at the end of the round is
-    // the only wait for those loads
+    lr = r;
+    start_class(lr);
+    int pt = 0, pns = nsteps(r), pfirst = y0 + r - E1;
     BandPre<KR> cur, nxt;
-    int t0 = 0;
-    load_round(cur, r, t0);
+    load_round(cur);
+    advance_load();
     while (true) {
-      int rn = r, tn = t0;
-      advance(rn, tn);
-      load_round(nxt, rn < s ? rn : r, rn < s ? tn : t0);  // past the end: repeats this round, unused
-      process(cur, r, t0);
-      if (rn >= s) break;
+      // past the last class the load stream reads further rows of the plane, unused
+      load_round(nxt);
+      advance_load();
+      process(cur, pt, pns, pfirst);
+      pt += KR;
+      if (pt >= padded(pns)) {
+        do {
+          ++r;
+        } while (r < s && nsteps(r) == 0);
+        if (r >= s) break;
+        pt = 0;
+        pns = nsteps(r);
+        pfirst = y0 + r - E1;
+      }
       cur = nxt;
-      r = rn;
-      t0 = tn;
     }
   }
   if constexpr (MODE == SM_DETAIL_ABS) {
@@ -361,7 +369,6 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   }
   a.nblocks = (int)nb;
   const int s = 1 << j;
-  a.small = (dbl ? 4 * s : 2 * s) + a.TY >= N ? 1 : 0;  // row indices may leave [-N, 2N)
   const size_t shm = sizeof(float) * (size_t)2 * (dbl ? kKR2 : kKR) * N;
   const dim3 grid((unsigned)nb), block((unsigned)N);
   if (trial) {
