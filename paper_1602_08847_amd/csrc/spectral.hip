@@ -99,13 +99,11 @@ struct SpecGeom {
   static constexpr int T = Plan<L>::T;
   static constexpr int NF = (256 / T) > 0 ? (256 / T) : 1;  // transforms (pixel pairs) per block
   static constexpr int PXB = 2 * NF;                        // pixels per block
-  static constexpr int VS = PXB + 1;  // odd row stride of the staged dual spectra: column reads
-                                      // (one coefficient per lane) fall in distinct banks
   // odd transform stride: the per-pixel steps read one entry of each of 16 transforms at once
   static constexpr int LS = lstride<L>();
   static constexpr int NT = NF * T;                       // threads per block
   static constexpr int PER = (L * PXB + NT - 1) / NT;     // (channel, pixel) elements per thread
-  static constexpr size_t shm = sizeof(float) * ((L * VS + 1) & ~1) + sizeof(float2) * NF * LS;
+  static constexpr size_t shm = sizeof(float2) * NF * LS;
 };
 
 __device__ __forceinline__ int dct_slot(int l, int L) { return (l & 1) ? L - 1 - (l >> 1) : (l >> 1); }
@@ -115,88 +113,101 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   using G = SpecGeom<L>;
   constexpr int T = G::T, NF = G::NF, PXB = G::PXB, LS = G::LS;
   constexpr int NT = NF * T;
-  extern __shared__ float sm[];
-  constexpr int VS = G::VS;
-  float* Vs = sm;                                                   // [L][VS] dual spectra
-  float2* buf = reinterpret_cast<float2*>(sm + ((L * VS + 1) & ~1));  // [NF][LS] transforms
+  constexpr int PER = G::PER;
+  extern __shared__ float2 buf[];  // [NF][LS] transforms; pixel p is part p & 1 of transform p / 2
   const long long npix = a.npix;
   const long long pix0 = (long long)blockIdx.x * PXB;
-  // every global read of the block is issued here: V (staged through LDS for the transform-major
-  // reads of the inverse transform, and kept for the dual step), x and q (for the primal step)
-  constexpr int PER = G::PER;
-  float vreg[PER], xreg[PER], qreg[PER];
+  // Element i of a thread is (channel, pixel) = (idx / PXB, idx % PXB), idx = threadIdx.x + i NT.
+  // When NT is a multiple of PXB the pixel is the same for all i and the channel steps by
+  // NT / PXB, so every access is a uniform base for i plus one byte offset per thread.
+  constexpr bool FIXP = (NT % PXB) == 0;
+  constexpr int LSTEP = FIXP ? NT / PXB : 1;
+  const int l0 = threadIdx.x / PXB, p0 = threadIdx.x - l0 * PXB;
+  const bool q0ok = pix0 + p0 < npix;
+  const unsigned voff = FIXP ? (unsigned)(((long long)l0 * npix + pix0 + p0) * 4) : 0u;
+  const long long cstride = (long long)LSTEP * npix * 4;
+  auto el_l = [&](int i) -> int { return FIXP ? l0 + i * LSTEP : (threadIdx.x + i * NT) / PXB; };
+  auto el_p = [&](int i) -> int { return FIXP ? p0 : (threadIdx.x + i * NT) % PXB; };
+  auto el_ok = [&](int i) -> bool {
+    if constexpr (FIXP) return q0ok;
+    const int idx = threadIdx.x + i * NT;
+    return idx < L * PXB && pix0 + idx % PXB < npix;
+  };
+  auto el_ptr = [&](const float* base, int i) -> const float* {
+    if constexpr (FIXP) return reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + i * cstride + voff);
+    return base + (long long)el_l(i) * npix + pix0 + el_p(i);
+  };
+  auto el_out = [&](float* base, int i) -> float* { return const_cast<float*>(el_ptr(base, i)); };
+  // V of the thread's elements, kept in registers for the dual step
+  float vreg[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) vreg[i] = el_ok(i) ? *el_ptr(a.V, i) : 0.f;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    const int idx = threadIdx.x + i * NT;
-    vreg[i] = xreg[i] = qreg[i] = 0.f;
-    if (idx < L * PXB) {
-      const int l = idx / PXB, p = idx - l * PXB;
-      const long long q = pix0 + p;
-      if (q < npix) {
-        const long long o = (long long)l * npix + q;
-        vreg[i] = a.V[o];
-        xreg[i] = a.X[o];
-        qreg[i] = a.Q[o];
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int idx = threadIdx.x + i * NT;
-    if (idx < L * PXB) {
-      const int l = idx / PXB, p = idx - l * PXB;
-      Vs[l * VS + p] = vreg[i];
+    if (FIXP || threadIdx.x + i * NT < L * PXB) {
+      const int p = el_p(i);
+      reinterpret_cast<float*>(buf + (p >> 1) * LS + lpad(el_l(i)))[p & 1] = vreg[i];
     }
   }
   lds_barrier();
   const int f = threadIdx.x / T, t = threadIdx.x - f * T;
   float2* fb = buf + f * LS;
   {
-    // t = mu_l * DCT-III(V): build the spectra of pixels 2f and 2f+1 packed as one complex array
+    // t = mu_l * DCT-III(V), pre-twiddle in place: slot k becomes exp(i pi k / 2L) (Y_k - i Y_{L-k})
+    // with Y = s h mu_l V (Y_L = 0), for both packed pixels; one thread owns slots k and L - k
     const float c0 = a.mu_l * sqrtf(1.f / L), c1 = a.mu_l * rsqrtf(2.f * L);
-    const float* va = Vs + 2 * f;
-    for (int k = t; k < L; k += T) {
-      const float sk = k ? c1 : c0;
-      const float ya = va[k * VS] * sk, yb = va[k * VS + 1] * sk;
-      const float ra = k ? va[(L - k) * VS] * c1 : 0.f, rb = k ? va[(L - k) * VS + 1] * c1 : 0.f;
+    auto twiddled = [&](float2 yk, float2 ym, int k) -> float2 {  // yk = Y_k, ym = Y_{L-k} of (a, b)
       const float2 e = a.csL[k];
-      const float2 Va = make_float2(ya * e.x + ra * e.y, ya * e.y - ra * e.x);
-      const float2 Vb = make_float2(yb * e.x + rb * e.y, yb * e.y - rb * e.x);
-      fb[lpad(k)] = make_float2(Va.x - Vb.y, Va.y + Vb.x);
+      const float2 Va = make_float2(yk.x * e.x + ym.x * e.y, yk.x * e.y - ym.x * e.x);
+      const float2 Vb = make_float2(yk.y * e.x + ym.y * e.y, yk.y * e.y - ym.y * e.x);
+      return make_float2(Va.x - Vb.y, Va.y + Vb.x);
+    };
+    for (int k = t; 2 * k <= L; k += T) {
+      const float2 zk = fb[lpad(k)];
+      if (k == 0) {
+        fb[lpad(0)] = twiddled(make_float2(zk.x * c0, zk.y * c0), make_float2(0.f, 0.f), 0);
+      } else {
+        const float2 zm = fb[lpad(L - k)];
+        const float2 yk = make_float2(zk.x * c1, zk.y * c1), ym = make_float2(zm.x * c1, zm.y * c1);
+        fb[lpad(k)] = twiddled(yk, ym, k);
+        if (2 * k != L) fb[lpad(L - k)] = twiddled(ym, yk, L - k);
+      }
     }
   }
   lds_barrier();
   fft_lds<L, true>(fb, t, true, a.twL);
-  // primal step per (channel, pixel); d goes back into the same slot for the forward transform
+  // primal step per (channel, pixel); x and q are fetched here, all at once, and d goes back into
+  // the same slot for the forward transform
+  float xreg[PER], qreg[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    const int idx = threadIdx.x + i * NT;
-    if (idx >= L * PXB) continue;
-    const int l = idx / PXB, p = idx - l * PXB;
-    const long long q = pix0 + p;
+    xreg[i] = el_ok(i) ? *el_ptr(a.X, i) : 0.f;
+    qreg[i] = el_ok(i) ? *el_ptr(a.Q, i) : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    if (!FIXP && threadIdx.x + i * NT >= L * PXB) continue;
+    const int l = el_l(i), p = el_p(i);
     float* slot = reinterpret_cast<float*>(buf + (p >> 1) * LS + lpad(dct_slot(l, L))) + (p & 1);
     const float tv = *slot;
     float d = 0.f;
-    if (q < npix) {
-      const long long o = (long long)l * npix + q;
+    if (el_ok(i)) {
       const float x = xreg[i];
       const float xt = fmaxf(x - a.tau * (qreg[i] + tv), 0.f);
       d = 2.f * xt - x;
-      a.D[o] = d;
-      a.X[o] = a.rho * xt + (1.f - a.rho) * x;
+      *el_out(a.D, i) = d;
+      *el_out(a.X, i) = a.rho * xt + (1.f - a.rho) * x;
     }
     *slot = d;
   }
   lds_barrier();
   fft_lds<L, false>(fb, t, true, a.twL);
-  // spectral dual step per (coefficient, pixel)
+  // spectral dual step per (coefficient, pixel): element i now stands for coefficient k = el_l(i)
   const float s0 = a.smu_l * sqrtf(1.f / L), s1 = a.smu_l * sqrtf(2.f / L);
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    const int idx = threadIdx.x + i * NT;
-    if (idx >= L * PXB) continue;
-    const int k = idx / PXB, p = idx - k * PXB;
-    const long long q = pix0 + p;
+    if (!FIXP && threadIdx.x + i * NT >= L * PXB) continue;
+    const int k = el_l(i), p = el_p(i);
     const float2* fp = buf + (p >> 1) * LS;
     const float2 zk = fp[lpad(k)];
     const float2 zm = cconj(fp[lpad(k ? L - k : 0)]);
@@ -208,9 +219,9 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     }
     const float2 e = a.csL[k];
     const float c = (v.x * e.x + v.y * e.y) * (k ? s1 : s0);
-    if (q < npix) {
+    if (el_ok(i)) {
       const float vo = vreg[i];
-      a.V[(long long)k * npix + q] = a.rho * satf_s(vo + c) + (1.f - a.rho) * vo;
+      *el_out(a.V, i) = a.rho * satf_s(vo + c) + (1.f - a.rho) * vo;
     }
   }
 }
