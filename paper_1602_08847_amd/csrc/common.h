@@ -58,19 +58,20 @@ __host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y
 __host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
 // ------------------------------------------------------------------ FFT geometry
-// Column blocking of the half spectrum: CB columns of N/2+1 per block, pitch = ncb * CB.
+// Column blocking of the half spectrum: the N/2+1 columns in ncb blocks of CB, pitch = ncb * CB.
 struct FftGeom {
   int N = 0;
   int CB = 8;       // columns per block in the column pass
   int ncb = 0;      // column blocks
-  int pitch = 0;    // complex entries per spectrum row (>= N/2 + 1)
+  int pitch = 0;    // columns over all blocks (>= N/2 + 1); a channel holds N * pitch entries
 };
 bool fft_supported(int N);
 FftGeom fft_geom(int N);
 // Twiddle table exp(-2 pi i m / N), m = 0..N-1, built in FP64 on the host.
 std::vector<float2> fft_twiddles(int N);
 
-// Row pass, real -> half spectrum.  x: [nch][N][N] (channel stride N*N), S: [nch][N][pitch].
+// Row pass, real -> half spectrum.  x: [nch][N][N] (channel stride N*N), S: column-blocked
+// [nch][ncb][N][CB] (entry (row, col) of a channel at ((col / CB) N + row) CB + col % CB).
 // With shift, the input is read with an (N/2, N/2) circular shift (ifftshift of a centred PSF).
 int launch_rows_r2c(const float* x, float2* S, int nch, const FftGeom& g, const float2* tw,
                     bool shift, hipStream_t st);

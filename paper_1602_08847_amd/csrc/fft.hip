@@ -1,7 +1,7 @@
 // Real 2-D FFT convolution passes for the data term (Algorithm 1, eq. (grad)).
 //
 // A channel's gradient H^dagger H x is C2R(P . R2C(x)) with P = w |H(k)|^2 / N^2, computed in
-// three passes over an [N][pitch] half spectrum:
+// three passes over a column-blocked half spectrum ([ncb][N][CB] per channel, pitch = ncb CB):
 //   1. rows:    two real rows packed as one complex row, one N-point complex FFT, then split;
 //   2. columns: CB columns per workgroup, N-point forward FFT, pointwise multiply, inverse FFT;
 //   3. rows:    Hermitian completion of two rows, inverse FFT, real/imaginary parts are the rows,
@@ -12,6 +12,14 @@
 #include <cmath>
 
 namespace mf {
+
+// columns per block of the half spectrum (and per workgroup of the column pass)
+template <int N>
+constexpr int col_block() {
+  constexpr int T = Plan<N>::T;
+  constexpr int cb = 512 / T;
+  return cb < 8 ? 8 : (cb > 32 ? 32 : cb);
+}
 
 // ------------------------------------------------------------------ pass 1: rows, real -> half spectrum
 template <int N>
@@ -54,8 +62,10 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, f
   lds_barrier();
   fft_lds<N, false>(buf, t, active, tw);
   if (active) {
-    float2* sa = S + (ch * N + r0) * (long long)pitch;
-    float2* sb = sa + pitch;
+    // blocked half spectrum: entry (row, col) at ((ch ncb + col / CB) N + row) CB + col % CB, so
+    // the transform pair's rows r0, r0 + 1 are neighbours within every column block
+    constexpr int CB = col_block<N>();
+    float2* sblk = S + (ch * N) * (long long)pitch + (long long)r0 * CB;
     for (int k = t; k <= N / 2; k += T) {
       const float2 zk = buf[lpad(k)];
       const float2 zm = cconj(buf[lpad((N - k) % N)]);
@@ -63,19 +73,14 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, f
       const float2 a = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
       const float2 d = csub(zk, zm);
       const float2 bb = make_float2(0.5f * d.y, -0.5f * d.x);
-      sa[k] = a;
-      sb[k] = bb;
+      float2* e = sblk + (long long)(k / CB) * N * CB + k % CB;
+      e[0] = a;
+      e[CB] = bb;
     }
   }
 }
 
 // ------------------------------------------------------------------ pass 2: columns
-template <int N>
-constexpr int col_block() {
-  constexpr int T = Plan<N>::T;
-  constexpr int cb = 512 / T;
-  return cb < 8 ? 8 : (cb > 32 ? 32 : cb);
-}
 
 template <int N, int MODE>
 __global__ void __launch_bounds__(512) k_cols(float2* __restrict__ S, int pitch, int ncb,
@@ -86,27 +91,25 @@ __global__ void __launch_bounds__(512) k_cols(float2* __restrict__ S, int pitch,
   constexpr int CB = col_block<N>();
   constexpr int LS = lstride<N>();
   extern __shared__ float2 lds[];
-  // column blocks of one channel are neighbours in memory (CB columns of a row are less than a
-  // cache line at large N): keep them on one XCD
+  // consecutive column blocks of a channel run on one XCD
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int ch = blk / ncb;
   const int c0 = (blk % ncb) * CB;
   const int nthr = CB * T;
   constexpr int NI = N / T;  // entries per thread: N * CB / nthr
-  float2* Sc = S + (long long)ch * N * pitch;
+  // the block's CB columns are one contiguous [N][CB] run of the blocked half spectrum; entry i of
+  // the thread is element threadIdx.x + i * nthr of it: row r0 + i * (nthr / CB), column cc
+  constexpr int RSTEP = nthr / CB;
+  const int r0 = threadIdx.x / CB, cc = threadIdx.x % CB;
+  float2* Sb = S + (long long)ch * N * pitch + (long long)c0 * N;
+  auto sent = [&](int i) -> float2* { return Sb + threadIdx.x + i * nthr; };
   {
     // all loads of the thread in flight at once, then into LDS
     float2 v[NI];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-      const int idx = threadIdx.x + i * nthr;
-      v[i] = Sc[(long long)(idx / CB) * pitch + c0 + idx % CB];
-    }
+    for (int i = 0; i < NI; ++i) v[i] = *sent(i);
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-      const int idx = threadIdx.x + i * nthr;
-      lds[(idx % CB) * LS + lpad(idx / CB)] = v[i];
-    }
+    for (int i = 0; i < NI; ++i) lds[cc * LS + lpad(r0 + i * RSTEP)] = v[i];
   }
   const int f = threadIdx.x / T, t = threadIdx.x % T;
   const long long mrow = ((long long)ch * pitch + c0 + f) * N;  // transposed multiplier row
@@ -117,6 +120,7 @@ __global__ void __launch_bounds__(512) k_cols(float2* __restrict__ S, int pitch,
   lds_barrier();
   float2* buf = lds + f * LS;
   fft_lds<N, false>(buf, t, true, tw);
+  __builtin_amdgcn_sched_barrier(0);  // the multiplier loads stay after the transform
   if constexpr (MODE == COL_REAL) {
     const float* __restrict__ mp = Mr + mrow + t;
 #pragma unroll
@@ -149,10 +153,7 @@ __global__ void __launch_bounds__(512) k_cols(float2* __restrict__ S, int pitch,
     lds_barrier();
     fft_lds<N, true>(buf, t, true, tw);
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-      const int idx = threadIdx.x + i * nthr;
-      Sc[(long long)(idx / CB) * pitch + c0 + idx % CB] = lds[(idx % CB) * LS + lpad(idx / CB)];
-    }
+    for (int i = 0; i < NI; ++i) *sent(i) = lds[cc * LS + lpad(r0 + i * RSTEP)];
   }
 }
 
@@ -197,16 +198,17 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
     r0 = 2 * (int)(pair % (N / 2));
     o0 = (ch * N + r0) * (long long)N;
     o1 = o0 + N;
-    const float2* sa = S + (ch * N + r0) * (long long)pitch;
-    const float2* sb = sa + pitch;
+    constexpr int CB = col_block<N>();
+    const float2* sblk = S + (ch * N) * (long long)pitch + (long long)r0 * CB;  // blocked layout
     // entries above N/2 are the conjugates of stored ones (Hermitian symmetry of real rows)
     float2 va[NI], vb[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
       const int k = t + i * T;
       const int ks = k <= N / 2 ? k : N - k;
-      va[i] = sa[ks];
-      vb[i] = sb[ks];
+      const float2* e = sblk + (long long)(ks / CB) * N * CB + ks % CB;
+      va[i] = e[0];
+      vb[i] = e[CB];
     }
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
@@ -225,6 +227,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
   }
   lds_barrier();
   fft_lds<N, true>(buf, t, active, tw);
+  __builtin_amdgcn_sched_barrier(0);  // the epilogue loads stay after the transform
   double acc = 0.0;
   if (active) {
     if constexpr (EPI != EPI_STORE) {

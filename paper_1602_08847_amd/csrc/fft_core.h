@@ -164,6 +164,13 @@ __device__ __forceinline__ void dftR(float2* v) {
 // All threads of the workgroup must call it (it synchronises the workgroup).
 template <int N, bool INV, int S = 0>
 __device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const float2* __restrict__ tw) {
+  if constexpr (S == 0) {
+    // a kernel with two transforms would otherwise have the second one's twiddle loads merged
+    // into the first and kept live in registers in between: offset the table by an opaque zero
+    int zero = 0;
+    asm volatile("" : "+s"(zero));
+    tw += zero;
+  }
   if constexpr (S < Plan<N>::nst) {
     constexpr int T = Plan<N>::T;
     constexpr int R = Plan<N>::rad[S];
@@ -172,6 +179,17 @@ __device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const f
     constexpr int PER = (NB + T - 1) / T;
     constexpr int TWS = N / (Ns * R);  // twiddle table stride
     float2 v[PER][R];
+    // the stage's twiddles (a table in global memory, cache-resident) are requested first, so they
+    // arrive while the LDS reads and the barrier complete
+    float2 w[PER][R];
+    if constexpr (Ns > 1) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int k = (t + i * T) % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[i][r] = tw[r * k * TWS];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int b = t + i * T;
@@ -189,9 +207,9 @@ __device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const f
         if constexpr (Ns > 1) {
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            float2 w = tw[r * k * TWS];
-            if (INV) w.y = -w.y;
-            v[i][r] = cmul(v[i][r], w);
+            float2 wr = w[i][r];
+            if (INV) wr.y = -wr.y;
+            v[i][r] = cmul(v[i][r], wr);
           }
         }
         dftR<R, INV>(v[i]);
