@@ -186,8 +186,20 @@ __device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const f
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
         const int k = (t + i * T) % Ns;
+        if constexpr (R >= 8) {
+          // w^r from the table's w, w^2, w^4 (and w^8): at most three products per twiddle
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[i][r] = tw[r * k * TWS];
+          for (int r = 1; r < R; r *= 2) w[i][r] = tw[r * k * TWS];
+#pragma unroll
+          for (int r = 3; r < R; ++r) {
+            if ((r & (r - 1)) == 0) continue;
+            const int hi = 1 << (31 - __builtin_clz(r));
+            w[i][r] = cmul(w[i][hi], w[i][r - hi]);
+          }
+        } else {
+#pragma unroll
+          for (int r = 1; r < R; ++r) w[i][r] = tw[r * k * TWS];
+        }
       }
     }
 #pragma unroll
