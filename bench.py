@@ -28,7 +28,8 @@ def alg_bytes_per_voxel(N, J):
     return 42.0 + 8.0 * (J + 1) + 2.0 * (N + 2) / N
 
 
-# Algorithmic HBM bytes per voxel of one launch of each hot kernel family
+# Algorithmic HBM bytes per voxel of one launch of each hot kernel, and its slot k in the
+# library's profile (mean launch time at 8 + 2k, launches per iteration at 9 + 2k)
 KERNEL_BYTES = {
     # reads x, q, V and writes x, d, V
     "k_spectral_fft (fused spectral step)": 24.0,
@@ -38,6 +39,20 @@ KERNEL_BYTES = {
     "k_band<DB_ADJOINT> (one scale of the adjoint Horner step)": 12.0,
     # reads c_{J-1}, u_{J-1} and the coarse dual u_J, writes u_{J-1} and u_J
     "k_band<DB_ANALYSIS_C> (last scale of analysis + spatial and coarse dual steps)": 20.0,
+    # reads c_j, u_j, u_{j+1}, writes u_j, u_{j+1}, c_{j+2}
+    "k_pair<PR_ANALYSIS> (two scales of analysis + spatial dual steps)": 24.0,
+    # reads u_{j+1}, u_j and a, writes the new sum
+    "k_pair<PR_ADJOINT> (two adjoint Horner steps)": 16.0,
+    # reads c_{J-2}, u_{J-2}, u_{J-1}, u_J, writes u_{J-2}, u_{J-1}, u_J
+    "k_pair<PR_ANALYSIS_C> (last two analysis scales + spatial and coarse dual steps)": 28.0,
+}
+PROFILE_SLOT = {
+    "k_band<DB_ANALYSIS> (one scale of analysis + spatial dual step)": 0,
+    "k_band<DB_ADJOINT> (one scale of the adjoint Horner step)": 1,
+    "k_band<DB_ANALYSIS_C> (last scale of analysis + spatial and coarse dual steps)": 2,
+    "k_pair<PR_ANALYSIS> (two scales of analysis + spatial dual steps)": 3,
+    "k_pair<PR_ADJOINT> (two adjoint Horner steps)": 4,
+    "k_pair<PR_ANALYSIS_C> (last two analysis scales + spatial and coarse dual steps)": 5,
 }
 
 
@@ -182,12 +197,10 @@ def main():
           f"objective {obj[0]:.6e}; phases ms {np.round(ph[:5], 3).tolist()}", file=sys.stderr, flush=True)
 
     vox = N * N * L
-    fams = {
-        "k_spectral_fft (fused spectral step)": (ph[3], 1),
-        "k_band<DB_ANALYSIS> (one scale of analysis + spatial dual step)": (ph[5], J - 1 if ph[7] > 0 else J),
-        "k_band<DB_ADJOINT> (one scale of the adjoint Horner step)": (ph[6], J),
-        "k_band<DB_ANALYSIS_C> (last scale of analysis + spatial and coarse dual steps)": (ph[7], 1),
-    }
+    fams = {"k_spectral_fft (fused spectral step)": (ph[3], 1.0)}
+    for name, k in PROFILE_SLOT.items():
+        if ph[9 + 2 * k] > 0:
+            fams[name] = (ph[8 + 2 * k], ph[9 + 2 * k])
     dom = max(fams, key=lambda k: fams[k][0] * fams[k][1])
     k_ms = fams[dom][0]
     k_gbs = KERNEL_BYTES[dom] * vox / (k_ms * 1e-3) / 1e9
@@ -208,9 +221,8 @@ def main():
         "iteration_alg_bytes_per_voxel": round(b_alg, 3),
         "iteration_alg_frac": round(b_alg * vox / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_ms": {"adjoint": round(ph[1], 3), "gradient": round(ph[2], 3),
-                     "spectral": round(ph[3], 3), "analysis_dual": round(ph[4], 3),
-                     "analysis_launch": round(ph[5], 4), "adjoint_launch": round(ph[6], 4),
-                     "analysis_coarse_launch": round(ph[7], 4)},
+                     "spectral": round(ph[3], 3), "analysis_dual": round(ph[4], 3)},
+        "launch_ms": {name: [round(v[0], 4), v[1]] for name, v in fams.items()},
     }
     cpu = None
     if not args.no_cpu:

@@ -48,6 +48,10 @@ extern "C" {
 
 typedef struct muffin_ctx muffin_ctx;
 
+/* Run the IUWT one launch per scale instead of fusing consecutive scales into one launch (the
+ * results are the same bit for bit; the fused form moves fewer bytes). */
+#define MUFFIN_FLAG_SINGLE_SCALE 1
+
 /* Problem and algorithm parameters (Sec. 2 eqs. (reg), (RegAll); Sec. 3, Algorithm 1). */
 typedef struct {
   int32_t N;                /* image side; N = 2^a or 3 * 2^a with 8 <= N <= 1024 */
@@ -55,7 +59,7 @@ typedef struct {
   int32_t J;                /* IUWT detail scales, 1 <= J <= 6; W_s yields J+1 planes */
   int32_t iuwt_gen;         /* 1 or 2: first or second generation IUWT (the paper uses 2, Sec. 4) */
   int32_t penalize_coarse;  /* 1: the coarse plane is part of W_s's l1 term; 0: it is not */
-  int32_t reserved;
+  int32_t flags;            /* MUFFIN_FLAG_* bits, 0 by default */
   double mu_s;              /* spatial weight mu_s >= 0 (eq. (RegAll)) */
   double mu_lambda;         /* spectral weight mu_lambda >= 0 (eq. (RegAll)) */
   double tau;               /* primal step; <= 0 selects 0.99 / (beta/2 + sigma ||K||^2) */
@@ -129,16 +133,17 @@ int muffin_set_state(muffin_ctx* ctx, const void* blob, size_t bytes);
 int muffin_apply_op(muffin_ctx* ctx, int op, const float* in, float* out);
 
 /* Time n_iter iterations with HIP events on the library's stream, without graph replay, and
- * report the average device milliseconds per iteration of each kernel family:
+ * report average device milliseconds:
  *   ms[0] whole iteration, [1] spatial adjoint (IUWT^dagger), [2] gradient FFT passes,
- *   [3] fused spectral kernel, [4] spatial analysis and dual update,
- *   [5] mean duration of one scale's fused analysis + dual-update launch (scales 0..J-2, and J-1
- *   when the coarse plane is not penalised), [6] mean duration of one scale's fused adjoint launch,
- *   [7] duration of the last scale's analysis launch that also updates the coarse plane's dual
- *   (0 when the coarse plane is not penalised); [5]-[7] are 0 for the first-generation transform.
- * Needs n_iter >= 2 for both [5] and [6].
+ *   [3] fused spectral kernel, [4] spatial analysis and dual update; [5..7] are 0;
+ *   ms[8 + 2k] mean duration of one launch of kind k and ms[9 + 2k] launches of kind k per
+ *   iteration, for the second-generation band kernels: k = 0 one analysis scale with its dual
+ *   step, 1 one adjoint Horner step, 2 the last analysis scale with the coarse plane's dual step,
+ *   3 two analysis scales in one launch, 4 two adjoint steps in one launch, 5 the last two
+ *   analysis scales with the coarse plane's dual step; k = 6, 7 are 0.
+ * Each kernel family (adjoint, analysis) is bracketed in every other iteration, so n_iter >= 2.
  * The iterations advance the state like muffin_step. */
-int muffin_profile(muffin_ctx* ctx, int32_t n_iter, double ms[8]);
+int muffin_profile(muffin_ctx* ctx, int32_t n_iter, double ms[24]);
 
 /* Time n_iter iterations (graph replay) with HIP events on the library's stream: *ms is the
  * total device time.  Advances the state like muffin_step. */

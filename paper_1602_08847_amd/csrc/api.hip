@@ -54,9 +54,9 @@ struct muffin_ctx {
   hipStream_t user = nullptr, st = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, e0 = nullptr, e1 = nullptr;
   hipEvent_t ph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t kev[16] = {};  // per-launch timing marks (profiling only)
-  double kms_an = 0, kms_ad = 0;  // summed per-launch times of the last profiled iteration
-  int kn_an = 0, kn_ad = 0;
+  hipEvent_t kev[16] = {};  // per-launch timing marks of one kernel family (profiling only)
+  int kkind[8] = {};        // launch kind of each bracketed launch
+  int nk = 0;               // bracketed launches
   float *X = nullptr, *U = nullptr, *V = nullptr, *D = nullptr, *Q = nullptr, *B = nullptr, *Y = nullptr;
   float *cA = nullptr, *cB = nullptr, *cT = nullptr;
   float2* S = nullptr;
@@ -107,6 +107,7 @@ int validate(const muffin_params* p) {
   if (!fft_supported(p->N)) return set_error("N must be 2^a or 3*2^a with 8 <= N <= 1024"), MUFFIN_EINVAL;
   if (p->L < 1 || p->L > 512) return set_error("L must be in [1, 512]"), MUFFIN_EINVAL;
   if (p->J < 1 || p->J > 6) return set_error("J must be in [1, 6]"), MUFFIN_EINVAL;
+  if (p->flags & ~MUFFIN_FLAG_SINGLE_SCALE) return set_error("unknown flags"), MUFFIN_EINVAL;
   if (p->iuwt_gen != 1 && p->iuwt_gen != 2) return set_error("iuwt_gen must be 1 or 2"), MUFFIN_EINVAL;
   if (p->penalize_coarse != 0 && p->penalize_coarse != 1)
     return set_error("penalize_coarse must be 0 or 1"), MUFFIN_EINVAL;
@@ -124,7 +125,28 @@ int validate(const muffin_params* p) {
 }
 
 // ---------------------------------------------------------------- phases
+// Launch kinds reported by muffin_profile.
+enum LaunchKind { K_DB_ANALYSIS = 0, K_DB_ADJOINT = 1, K_DB_ANALYSIS_C = 2, K_PR_ANALYSIS = 3, K_PR_ADJOINT = 4,
+                  K_PR_ANALYSIS_C = 5, K_KINDS = 8 };
+
+// Brackets one launch with timing marks when timed (at most 8 per family).
+template <class F>
+static int timed_launch(muffin_ctx* c, bool timed, int kind, F&& launch) {
+  timed = timed && c->nk < 8;
+  if (timed) MF_HIP(hipEventRecord(c->kev[2 * c->nk], c->st));
+  MF_TRY(launch());
+  if (timed) {
+    MF_HIP(hipEventRecord(c->kev[2 * c->nk + 1], c->st));
+    c->kkind[c->nk++] = kind;
+  }
+  return MUFFIN_OK;
+}
+
+static bool use_pairs(const muffin_ctx* c) { return c->gen == 2 && !(c->p.flags & MUFFIN_FLAG_SINGLE_SCALE); }
+
 // Spatial adjoint of omega-weighted U; returns the buffer holding a = W_s^dagger (omega u).
+// Second generation: Horner steps a <- u_j + H_j (a - H_j u_j) from the coarsest scale down, two
+// scales per launch where possible.
 int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omega_c, const float** result,
                     bool timed = false) {
   const int J = c->J;
@@ -140,25 +162,30 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omeg
     acs = np;
     nb = 1;
   }
-  for (int j = J - 1; j >= 0; --j) {
-    const float* uj = Ubase + (long long)j * np;
+  const bool pairs = use_pairs(c);
+  for (int j = J - 1; j >= 0;) {
     float* dst = bufs[nb];
-    if (c->gen == 2 && atrous_double_fits(c->N, j, nullptr, nullptr)) {
-      if (timed) MF_HIP(hipEventRecord(c->kev[2 * j], c->st));
-      MF_TRY(launch_atrous(DB_ADJOINT, c->N, c->L, j, pref(uj, ucs), pref(a, acs), PlaneRef{}, pout(dst, np),
-                           PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
-      if (timed) MF_HIP(hipEventRecord(c->kev[2 * j + 1], c->st));
+    if (c->gen == 2 && pairs && j >= 1) {
+      // scales j and j - 1
+      const float* uh = Ubase + (long long)j * np;
+      const float* ul = Ubase + (long long)(j - 1) * np;
+      MF_TRY(timed_launch(c, timed, K_PR_ADJOINT, [&] {
+        return launch_pair(PR_ADJOINT, c->N, c->L, j - 1, pref(uh, ucs), pref(ul, ucs), pref(a, acs), pout(dst, np),
+                           PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f, c->st);
+      }));
+      j -= 2;
+    } else if (c->gen == 2) {
+      const float* uj = Ubase + (long long)j * np;
+      MF_TRY(timed_launch(c, timed, K_DB_ADJOINT, [&] {
+        return launch_atrous(DB_ADJOINT, c->N, c->L, j, pref(uj, ucs), pref(a, acs), PlaneRef{}, pout(dst, np),
+                             PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st);
+      }));
+      j -= 1;
     } else {
-      const float* sub = uj;
-      long long scs = ucs;
-      if (c->gen == 2) {
-        MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(uj, ucs), PlaneRef{}, PlaneRef{}, pout(c->cT, np),
-                             PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
-        sub = c->cT;
-        scs = np;
-      }
-      MF_TRY(launch_atrous(SM_SUBADD, c->N, c->L, j, pref(a, acs), pref(sub, scs), pref(uj, ucs), pout(dst, np),
+      const float* uj = Ubase + (long long)j * np;
+      MF_TRY(launch_atrous(SM_SUBADD, c->N, c->L, j, pref(a, acs), pref(uj, ucs), pref(uj, ucs), pout(dst, np),
                            PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
+      j -= 1;
     }
     a = dst;
     acs = np;
@@ -168,45 +195,61 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omeg
   return MUFFIN_OK;
 }
 
-// Analysis of the channel images in (stride np) fused with the spatial dual step on U.
+// Analysis of the channel images in (stride np) fused with the spatial dual step on U; second
+// generation: two scales per launch where possible, the last one feeding the coarse plane's step.
 int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
   const int J = c->J;
   const long long np = c->npix, ucs = (long long)(J + 1) * np;
   const float coef = (float)(c->sigma * c->p.mu_s);
   const float rho = (float)c->rho;
+  const float coefc = coef * c->omega_c;
+  const bool coarse = c->omega_c != 0.f;  // with omega = 0 on the coarse plane its dual stays put
+  float* Uc = c->U + (long long)J * np;
   const float* cur = in;
   float* bufs[2] = {c->cA, c->cB};
-  for (int j = 0; j < J; ++j) {
-    float* nxt = bufs[j & 1];
+  int nb = 0;
+  const bool pairs = use_pairs(c);
+  for (int j = 0; j < J;) {
+    float* nxt = bufs[nb];
     float* uj = c->U + (long long)j * np;
     if (c->gen == 1) {
       MF_TRY(launch_atrous(SM_DETAIL1, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
                            pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
-    } else if (atrous_double_fits(c->N, j, nullptr, nullptr)) {
-      if (timed) MF_HIP(hipEventRecord(c->kev[2 * j], c->st));
-      if (j == J - 1 && c->omega_c != 0.f) {
-        // last scale: c_J goes straight into the coarse plane's dual step
-        MF_TRY(launch_atrous(DB_ANALYSIS_C, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
-                             pout(c->U + (long long)J * np, ucs), coef, rho, nullptr, nullptr, c->st, 0,
-                             coef * c->omega_c));
-        if (timed) MF_HIP(hipEventRecord(c->kev[2 * j + 1], c->st));
+      j += 1;
+    } else if (pairs && j + 1 < J) {
+      float* uj1 = c->U + (long long)(j + 1) * np;
+      const bool last = j + 2 == J;
+      if (last && coarse) {
+        MF_TRY(timed_launch(c, timed, K_PR_ANALYSIS_C, [&] {
+          return launch_pair(PR_ANALYSIS_C, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                             pout(uj1, ucs), pout(Uc, ucs), coef, rho, coefc, c->st);
+        }));
         return MUFFIN_OK;
       }
-      MF_TRY(launch_atrous(DB_ANALYSIS, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
-                           pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
-      if (timed) MF_HIP(hipEventRecord(c->kev[2 * j + 1], c->st));
+      MF_TRY(timed_launch(c, timed, K_PR_ANALYSIS, [&] {
+        return launch_pair(PR_ANALYSIS, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                           pout(uj1, ucs), pout(nxt, np), coef, rho, 0.f, c->st);
+      }));
+      j += 2;
+    } else if (j == J - 1 && coarse) {
+      MF_TRY(timed_launch(c, timed, K_DB_ANALYSIS_C, [&] {
+        return launch_atrous(DB_ANALYSIS_C, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                             pout(Uc, ucs), coef, rho, nullptr, nullptr, c->st, 0, coefc);
+      }));
+      return MUFFIN_OK;
     } else {
-      MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np),
-                           PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
-      MF_TRY(launch_atrous(SM_DETAIL, c->N, c->L, j, pref(nxt, np), PlaneRef{}, pref(cur, np), pout(uj, ucs),
-                           PlaneOut{}, coef, rho, nullptr, nullptr, c->st));
+      MF_TRY(timed_launch(c, timed, K_DB_ANALYSIS, [&] {
+        return launch_atrous(DB_ANALYSIS, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                             pout(nxt, np), coef, rho, nullptr, nullptr, c->st);
+      }));
+      j += 1;
     }
     cur = nxt;
+    nb ^= 1;
   }
-  // with omega = 0 on the coarse plane its dual stays where it is
-  if (c->omega_c != 0.f)
-    MF_TRY(launch_pointwise(PT_COARSE, c->N, c->L, pref(cur, np), PlaneRef{}, pout(c->U + (long long)J * np, ucs),
-                            coef * c->omega_c, rho, nullptr, nullptr, c->st));
+  if (c->gen == 1 && coarse)
+    MF_TRY(launch_pointwise(PT_COARSE, c->N, c->L, pref(cur, np), PlaneRef{}, pout(Uc, ucs), coefc, rho, nullptr,
+                            nullptr, c->st));
   return MUFFIN_OK;
 }
 
@@ -506,51 +549,92 @@ int ensure_graph(muffin_ctx* c) {
   return MUFFIN_OK;
 }
 
-// Autotuner: for every scale and band-kernel class of the iteration, time each band height that
-// divides N on the context's own sizes (writing only scratch planes) and keep the fastest.
+// Autotuner: for every band or pair launch of the iteration, time each band height that divides N
+// on the context's own sizes (reading state, writing only scratch planes) and keep the fastest.
 int autotune(muffin_ctx* c, int reps, std::string& rep) {
   const long long np = c->npix, ucs = (long long)(c->J + 1) * np;
-  const int modes[2] = {c->gen == 2 ? DB_ANALYSIS : SM_DETAIL1, c->gen == 2 ? DB_ADJOINT : SM_SUBADD};
-  const char* names[2] = {"analysis", "adjoint"};
+  const int J = c->J;
+  const bool pairs = use_pairs(c), coarse = c->omega_c != 0.f;
+  struct TL {
+    int mode, j;
+    const char* name;
+  };
+  std::vector<TL> sched;
+  for (int j = 0; j < J;) {
+    if (c->gen == 1) {
+      sched.push_back({SM_DETAIL1, j, "analysis"});
+      j += 1;
+    } else if (pairs && j + 1 < J) {
+      sched.push_back({(j + 2 == J && coarse) ? PR_ANALYSIS_C : PR_ANALYSIS, j, "analysis pair"});
+      j += 2;
+    } else {
+      sched.push_back({(j == J - 1 && coarse) ? DB_ANALYSIS_C : DB_ANALYSIS, j, "analysis"});
+      j += 1;
+    }
+  }
+  for (int j = J - 1; j >= 0;) {
+    if (c->gen == 1) {
+      sched.push_back({SM_SUBADD, j, "adjoint"});
+      j -= 1;
+    } else if (pairs && j >= 1) {
+      sched.push_back({PR_ADJOINT, j - 1, "adjoint pair"});
+      j -= 2;
+    } else {
+      sched.push_back({DB_ADJOINT, j, "adjoint"});
+      j -= 1;
+    }
+  }
   rep += "{\"N\": " + std::to_string(c->N) + ", \"channels\": " + std::to_string(c->L) + ", \"scales\": [";
-  for (int j = 0; j < c->J; ++j) {
-    for (int k = 0; k < 2; ++k) {
-      const bool fused_coarse = k == 0 && c->gen == 2 && j == c->J - 1 && c->omega_c != 0.f;
-      const int mode = fused_coarse ? DB_ANALYSIS_C : modes[k];
-      double best = 1e30;
-      int best_ty = atrous_band_rows(c->N, j, mode);
-      std::string cand;
-      for (int TY = 16; TY <= c->N; TY *= 2) {
-        if (c->N % TY) continue;
-        MF_TRY(atrous_set_band_rows(c->N, j, mode, TY));
-        auto launch = [&]() -> int {
-          if (k == 0)
+  bool firstrep = true;
+  for (const TL& L : sched) {
+    const int mode = L.mode, j = L.j;
+    double best = 1e30;
+    int best_ty = atrous_band_rows(c->N, j, mode);
+    std::string cand;
+    for (int TY = 16; TY <= c->N; TY *= 2) {
+      if (c->N % TY) continue;
+      MF_TRY(atrous_set_band_rows(c->N, j, mode, TY));
+      auto launch = [&]() -> int {
+        switch (mode) {
+          case PR_ANALYSIS:
+          case PR_ANALYSIS_C:
+            return launch_pair(mode, c->N, c->L, j, pref(c->X, np), PlaneRef{}, PlaneRef{}, pout(c->cB, np),
+                               pout(c->cT, np), pout(c->cA, np), 0.f, 1.f, 0.f, c->st, 1);
+          case PR_ADJOINT:
+            return launch_pair(mode, c->N, c->L, j, pref(c->U + (long long)(j + 1) * np, ucs),
+                               pref(c->U + (long long)j * np, ucs), pref(c->cA, np), pout(c->cB, np), PlaneOut{},
+                               PlaneOut{}, 0.f, 1.f, 0.f, c->st, 1);
+          case DB_ADJOINT:
+            return launch_atrous(mode, c->N, c->L, j, pref(c->U + (long long)j * np, ucs), pref(c->cA, np),
+                                 pref(c->cA, np), pout(c->cB, np), PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st, 1);
+          case SM_SUBADD:
+            return launch_atrous(mode, c->N, c->L, j, pref(c->cA, np), pref(c->cA, np), pref(c->cA, np),
+                                 pout(c->cB, np), PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st, 1);
+          default:  // analysis kernels of one scale
             return launch_atrous(mode, c->N, c->L, j, pref(c->X, np), PlaneRef{}, PlaneRef{}, pout(c->cB, np),
                                  pout(c->cT, np), 0.f, 1.f, nullptr, nullptr, c->st, 1, 0.f);
-          return launch_atrous(mode, c->N, c->L, j, c->gen == 2 ? pref(c->U + (long long)j * np, ucs) : pref(c->cA, np),
-                               pref(c->cA, np), pref(c->cA, np), pout(c->cB, np), PlaneOut{}, 0.f, 1.f, nullptr,
-                               nullptr, c->st, 1);
-        };
-        MF_TRY(launch());
-        MF_HIP(hipEventRecord(c->e0, c->st));
-        for (int r = 0; r < reps; ++r) MF_TRY(launch());
-        MF_HIP(hipEventRecord(c->e1, c->st));
-        MF_HIP(hipEventSynchronize(c->e1));
-        float t = 0.f;
-        MF_HIP(hipEventElapsedTime(&t, c->e0, c->e1));
-        const double ms = t / reps;
-        if (!cand.empty()) cand += ", ";
-        cand += "\"" + std::to_string(TY) + "\": " + std::to_string(ms);
-        if (ms < best) {
-          best = ms;
-          best_ty = TY;
         }
+      };
+      MF_TRY(launch());
+      MF_HIP(hipEventRecord(c->e0, c->st));
+      for (int r = 0; r < reps; ++r) MF_TRY(launch());
+      MF_HIP(hipEventRecord(c->e1, c->st));
+      MF_HIP(hipEventSynchronize(c->e1));
+      float tm = 0.f;
+      MF_HIP(hipEventElapsedTime(&tm, c->e0, c->e1));
+      const double ms = tm / reps;
+      if (!cand.empty()) cand += ", ";
+      cand += "\"" + std::to_string(TY) + "\": " + std::to_string(ms);
+      if (ms < best) {
+        best = ms;
+        best_ty = TY;
       }
-      MF_TRY(atrous_set_band_rows(c->N, j, mode, best_ty));
-      if (j || k) rep += ", ";
-      rep += "{\"j\": " + std::to_string(j) + ", \"kernel\": \"" + names[k] + "\", \"rows\": " +
-             std::to_string(best_ty) + ", \"ms\": " + std::to_string(best) + ", \"candidates_ms\": {" + cand + "}}";
     }
+    MF_TRY(atrous_set_band_rows(c->N, j, mode, best_ty));
+    if (!firstrep) rep += ", ";
+    firstrep = false;
+    rep += "{\"j\": " + std::to_string(j) + ", \"kernel\": \"" + L.name + "\", \"rows\": " +
+           std::to_string(best_ty) + ", \"ms\": " + std::to_string(best) + ", \"candidates_ms\": {" + cand + "}}";
   }
   rep += "]}";
   // recapture the iteration with the chosen tiles
@@ -663,7 +747,7 @@ int muffin_batch_init(muffin_batch** out, int32_t n_cubes, const muffin_params* 
   // group cubes that can share the per-channel phases
   auto same = [&](const muffin_params& a, const muffin_params& c) {
     return a.N == c.N && a.J == c.J && a.iuwt_gen == c.iuwt_gen && a.penalize_coarse == c.penalize_coarse &&
-           a.mu_s == c.mu_s && a.sigma == c.sigma && a.rho == c.rho;
+           a.mu_s == c.mu_s && a.sigma == c.sigma && a.rho == c.rho && a.flags == c.flags;
   };
   std::vector<char> done(n_cubes, 0);
   for (int i = 0; i < n_cubes; ++i) {
@@ -821,44 +905,39 @@ int muffin_step_timed(muffin_ctx* c, int32_t n_iter, double* ms) {
   return MUFFIN_OK;
 }
 
-int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[8]) {
+int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[24]) {
   if (!c || !ms || n_iter < 1) return set_error("bad arguments"), MUFFIN_EINVAL;
-  for (int i = 0; i < 8; ++i) ms[i] = 0;
+  for (int i = 0; i < 24; ++i) ms[i] = 0;
   StreamScope scope(c);
-  int n_ad = 0, n_an = 0, n_ac = 0;
-  const bool fused_coarse = c->gen == 2 && c->omega_c != 0.f;
+  double ksum[K_KINDS] = {};
+  int kcnt[K_KINDS] = {}, fam_iters[3] = {0, 0, 0};
   for (int it = 0; it < n_iter; ++it) {
     // alternate which kernel family is bracketed so the marks do not pile up in one iteration
-    const int fam = 1 + (it & 1);
-    MF_TRY(enqueue_iteration(c, c->ph, c->gen == 2 ? fam : 0));
+    const int fam = c->gen == 2 ? 1 + (it & 1) : 0;
+    c->nk = 0;
+    MF_TRY(enqueue_iteration(c, c->ph, fam));
     MF_HIP(hipEventSynchronize(c->ph[4]));
-    float t[4];
-    for (int k = 0; k < 4; ++k) MF_HIP(hipEventElapsedTime(&t[k], c->ph[k], c->ph[k + 1]));
+    float tph[4];
+    for (int k = 0; k < 4; ++k) MF_HIP(hipEventElapsedTime(&tph[k], c->ph[k], c->ph[k + 1]));
     for (int k = 0; k < 4; ++k) {
-      ms[k + 1] += t[k] / n_iter;
-      ms[0] += t[k] / n_iter;
+      ms[k + 1] += tph[k] / n_iter;
+      ms[0] += tph[k] / n_iter;
     }
-    if (c->gen == 2) {
-      for (int j = 0; j < c->J; ++j) {
-        if (!atrous_double_fits(c->N, j, nullptr, nullptr)) continue;
-        float tk = 0.f;
-        MF_HIP(hipEventElapsedTime(&tk, c->kev[2 * j], c->kev[2 * j + 1]));
-        if (fam == 1) {
-          ms[6] += tk;
-          ++n_ad;
-        } else if (fused_coarse && j == c->J - 1) {
-          ms[7] += tk;
-          ++n_ac;
-        } else {
-          ms[5] += tk;
-          ++n_an;
-        }
-      }
+    for (int i = 0; i < c->nk; ++i) {
+      float tk = 0.f;
+      MF_HIP(hipEventElapsedTime(&tk, c->kev[2 * i], c->kev[2 * i + 1]));
+      ksum[c->kkind[i]] += tk;
+      ++kcnt[c->kkind[i]];
     }
+    ++fam_iters[fam];
   }
-  if (n_an) ms[5] /= n_an;
-  if (n_ac) ms[7] /= n_ac;
-  if (n_ad) ms[6] /= n_ad;
+  c->nk = 0;
+  for (int k = 0; k < K_KINDS; ++k) {
+    if (!kcnt[k]) continue;
+    const int fam = (k == K_DB_ADJOINT || k == K_PR_ADJOINT) ? 1 : 2;
+    ms[8 + 2 * k] = ksum[k] / kcnt[k];
+    ms[9 + 2 * k] = fam_iters[fam] ? (double)kcnt[k] / fam_iters[fam] : 0.0;
+  }
   c->iter += n_iter;
   return MUFFIN_OK;
 }

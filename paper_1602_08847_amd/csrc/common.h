@@ -110,9 +110,16 @@ enum AtrousMode {
   SM_DETAIL1 = 4,     // out2 = H_j(A); w = A - H_j(A); u(out) update  (first generation)
   DB_ANALYSIS = 5,    // out2 = c' = H_j(A); w = A - H_j(c'); u(out) update  (second generation)
   DB_ADJOINT = 6,     // out = A + H_j(B - H_j(A))  (A = u_j, B = a; second generation Horner step)
-  DB_ANALYSIS_C = 7   // DB_ANALYSIS at the last scale with the coarse plane's dual update fused:
+  DB_ANALYSIS_C = 7,  // DB_ANALYSIS at the last scale with the coarse plane's dual update fused:
                       // u2(out2) <- rho*sat(u2 + coef2*c') + (1-rho)*u2 instead of storing c'
+  // two consecutive scales j, j+1 in one pass (second generation):
+  PR_ANALYSIS = 8,    // A = c_j; out = u_j, out2 = u_{j+1} (dual updates); out3 = c_{j+2} = H_{j+1} H_j c_j
+  PR_ANALYSIS_C = 9,  // PR_ANALYSIS with c_{j+2} feeding the coarse plane's dual update (out3, coef2)
+  PR_ADJOINT = 10     // A = u_{j+1}, B = u_j, E = a: out = two Horner steps, scale j+1 then j
 };
+// launch of a pair kernel: j is the finer scale of the pair
+int launch_pair(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out, PlaneOut out2,
+                PlaneOut out3, float coef, float rho, float coef2, hipStream_t st, int trial = 0);
 // band height (rows per workgroup) of the band kernels, default or autotuned; set_band_rows records
 // an autotuned choice for (N, j, kernel class of mode)
 int atrous_band_rows(int N, int j, int mode);

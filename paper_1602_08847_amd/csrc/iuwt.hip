@@ -38,7 +38,7 @@ __device__ __forceinline__ double block_sum_atrous(double v) {
 
 struct AtrousArgs {
   PlaneRef A, B, E;
-  PlaneOut out, out2;
+  PlaneOut out, out2, out3;
   int N, j, TX, TY;
   int tiles_x, tiles_per_ch, nblocks;
   float coef, rho, coef2;
@@ -290,13 +290,286 @@ __global__ void __launch_bounds__(1024) k_band_trial(AtrousArgs a) {
   band_body<MODE, KR>(a);
 }
 
+// ------------------------------------------------------------------ pairs of scales
+// Two consecutive scales j, j + 1 in one pass, so the plane between them (c_{j+1} of the analysis,
+// the running sum of the adjoint) never leaves the chip.  With s = 2^j the rows are visited
+// residue class by residue class modulo s, where H_j has its taps 1 and 2 class steps apart and
+// H_{j+1} 2 and 4: each vertical filter is a register window (5 entries for H_j, 9 for H_{j+1})
+// and each horizontal filter a pass through LDS.  Load index i of class r is row
+// y0 + r + (i - 10) s; the chained stages need 10 class steps of halo on either side.
+//   PR_ANALYSIS:  c1 = H_j c (index t - 2 after loading c(t)), w_j = c - H_j c1 (t - 4),
+//                 c2 = H_{j+1} c1 (t - 6), w_{j+1} = c1 - H_{j+1} c2 (t - 10)
+//   PR_ADJOINT:   h = H_{j+1} u_{j+1} (t - 4), a' = u_{j+1} + H_{j+1}(a - h) (t - 8),
+//                 a'' = u_j + H_j(a' - H_j u_j) (t - 10)
+// Every stage performs the same operations in the same order as the one-scale kernels, so the
+// results are identical to running them one after the other.
+template <int KR>
+struct PairPre {
+  float p0[KR], p1[KR], p2[KR], p3[KR];
+};
+
+template <int MODE, int KR>
+__device__ __forceinline__ void pair_body(const AtrousArgs& a) {
+  constexpr bool ADJ = (MODE == PR_ADJOINT);
+  constexpr bool CO = (MODE == PR_ANALYSIS_C);
+  constexpr int HALO = 10;
+  extern __shared__ float sm[];
+  const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
+  float* bA = sm;
+  float* bB = sm + KR * N;
+  float* bC = sm + 2 * KR * N;
+  float* bD = sm + 3 * KR * N;
+  const int b = xcd_remap(blockIdx.x, a.nblocks);
+  const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
+  const int y0 = band * TY;
+  const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
+  const char* __restrict__ Bp = ADJ ? reinterpret_cast<const char*>(a.B.p + ch * a.B.cs) : nullptr;
+  const char* __restrict__ Ep = ADJ ? reinterpret_cast<const char*>(a.E.p + ch * a.E.cs) : nullptr;
+  float* __restrict__ O = a.out.p + ch * a.out.cs;
+  float* __restrict__ O2 = ADJ ? nullptr : a.out2.p + ch * a.out2.cs;
+  float* __restrict__ O3 = ADJ ? nullptr : a.out3.p + ch * a.out3.cs;
+  auto modx = [&](int v) { return (v % N + N) % N; };
+  const int xm1 = modx(x - s), xm2 = modx(x - 2 * s), xm4 = modx(x - 4 * s);
+  const int xp1 = modx(x + s), xp2 = modx(x + 2 * s), xp4 = modx(x + 4 * s);
+  auto hj = [&](const float* row) { return b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]); };
+  auto hj1 = [&](const float* row) { return b3(row[xm4], row[xm2], row[x], row[xp2], row[xp4]); };
+  const int rowb = N * 4, planeb = N * N * 4, stepb = (s % N) * rowb;
+  const unsigned xb = (unsigned)x * 4u;
+  auto at = [&](const char* base, int off) -> float {
+    return *reinterpret_cast<const float*>(base + off + xb);
+  };
+  auto put = [&](float* base, int y, float v) {
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
+  };
+  auto upd = [&](float u, float w, float coef) { return a.rho * satf(u + coef * w) + (1.f - a.rho) * u; };
+  auto nsteps = [&](int r) -> int {
+    const int v = TY - r;
+    return v > 0 ? ((v + s - 1) >> jj) + 2 * HALO : 0;
+  };
+  auto padded = [&](int ns) -> int { return (ns + KR - 1) / KR * KR; };
+  auto rowoff = [&](int y) -> int {
+    y %= N;
+    return (y < 0 ? y + N : y) * rowb;
+  };
+  auto adv = [&](int& o) {
+    o += stepb;
+    if (o >= planeb) o -= planeb;
+  };
+  // load streams: p0 at index t, p1 at t - 4, p2 at t - 6 (adjoint: u_j) or t - 10 (analysis:
+  // u_{j+1}), p3 at t - 6 (coarse plane)
+  int lr = 0, lt = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+  auto start_class = [&](int r) {
+    const int f = y0 + r - HALO * s;
+    o0 = rowoff(f);
+    o1 = rowoff(f - 4 * s);
+    o2 = rowoff(f - (ADJ ? 6 : 10) * s);
+    if constexpr (CO) o3 = rowoff(f - 6 * s);
+  };
+  auto load_round = [&](PairPre<KR>& P) {
+#pragma unroll
+    for (int kk = 0; kk < KR; ++kk) {
+      P.p0[kk] = at(A, o0);
+      if constexpr (ADJ) {
+        P.p1[kk] = at(Ep, o1);
+        P.p2[kk] = at(Bp, o2);
+      } else {
+        P.p1[kk] = at(reinterpret_cast<const char*>(O), o1);
+        P.p2[kk] = at(reinterpret_cast<const char*>(O2), o2);
+        if constexpr (CO) P.p3[kk] = at(reinterpret_cast<const char*>(O3), o3);
+      }
+      adv(o0);
+      adv(o1);
+      adv(o2);
+      if constexpr (CO) adv(o3);
+    }
+  };
+  auto advance_load = [&]() {
+    lt += KR;
+    if (lt >= padded(nsteps(lr))) {
+      lt = 0;
+      do {
+        ++lr;
+      } while (lr < s && nsteps(lr) == 0);
+      if (lr < s) start_class(lr);
+    }
+  };
+  // windows, oldest first
+  float wa[9], wb[9], wc[5], wd[5];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) wa[i] = wb[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) wc[i] = wd[i] = 0.f;
+  auto push9 = [](float (&w)[9], float v) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = w[i + 1];
+    w[8] = v;
+  };
+  auto push5 = [](float (&w)[5], float v) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = w[i + 1];
+    w[4] = v;
+  };
+  auto v9 = [](const float (&w)[9]) { return b3(w[0], w[2], w[4], w[6], w[8]); };
+  auto v5 = [](const float (&w)[5]) { return b3(w[0], w[1], w[2], w[3], w[4]); };
+  // round of steps [t0, t0 + KR) of a class with ns steps whose load index 0 is row first
+  auto process = [&](const PairPre<KR>& cur, int t0, int ns, int first) {
+    if constexpr (ADJ) {
+      // wa: u_{j+1} (t-8..t), wc: u_j (t-10..t-6), wb: a - H_{j+1} u_{j+1} (t-12..t-4),
+      // wd: a' - H_j u_j (t-12..t-8)
+      float pv1[KR], pv3[KR], cuh[KR], cul[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        push9(wa, cur.p0[kk]);
+        pv1[kk] = v9(wa);
+        cuh[kk] = wa[0];
+        push5(wc, cur.p2[kk]);
+        pv3[kk] = v5(wc);
+        cul[kk] = wc[0];
+      }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        bA[kk * N + x] = pv1[kk];
+        bB[kk * N + x] = pv3[kk];
+      }
+      lds_barrier();
+      float pv2[KR], h0[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const float h1 = hj1(bA + kk * N);
+        h0[kk] = hj(bB + kk * N);
+        push9(wb, cur.p1[kk] - h1);
+        pv2[kk] = v9(wb);
+      }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) bC[kk * N + x] = pv2[kk];
+      lds_barrier();
+      float pv4[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const float a1 = cuh[kk] + hj1(bC + kk * N);
+        push5(wd, a1 - h0[kk]);
+        pv4[kk] = v5(wd);
+      }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) bD[kk * N + x] = pv4[kk];
+      lds_barrier();
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const int t = t0 + kk;
+        if (t >= 2 * HALO && t < ns) put(O, first + (t - HALO) * s, cul[kk] + hj(bD + kk * N));
+      }
+    } else {
+      // wc: c (t-4..t), wa: c1 (t-10..t-2), wb: c2 (t-14..t-6)
+      float pv1[KR], cc4[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        push5(wc, cur.p0[kk]);
+        pv1[kk] = v5(wc);
+        cc4[kk] = wc[0];
+      }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) bA[kk * N + x] = pv1[kk];
+      lds_barrier();
+      float pv2[KR], pv3[KR], cc10[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        push9(wa, hj(bA + kk * N));
+        pv2[kk] = b3(wa[4], wa[5], wa[6], wa[7], wa[8]);
+        pv3[kk] = v9(wa);
+        cc10[kk] = wa[0];
+      }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        bB[kk * N + x] = pv2[kk];
+        bC[kk * N + x] = pv3[kk];
+      }
+      lds_barrier();
+      float pv4[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const int t = t0 + kk;
+        const float w = cc4[kk] - hj(bB + kk * N);
+        if (t >= HALO + 4 && t < ns - 6) put(O, first + (t - 4) * s, upd(cur.p1[kk], w, a.coef));
+        const float c2 = hj1(bC + kk * N);
+        if (t >= HALO + 6 && t < ns - 4) {
+          if constexpr (CO) {
+            put(O3, first + (t - 6) * s, upd(cur.p3[kk], c2, a.coef2));
+          } else {
+            put(O3, first + (t - 6) * s, c2);
+          }
+        }
+        push9(wb, c2);
+        pv4[kk] = v9(wb);
+      }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) bD[kk * N + x] = pv4[kk];
+      lds_barrier();
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const int t = t0 + kk;
+        if (t >= 2 * HALO && t < ns)
+          put(O2, first + (t - HALO) * s, upd(cur.p2[kk], cc10[kk] - hj1(bD + kk * N), a.coef));
+      }
+    }
+  };
+  int r = 0;
+  while (r < s && nsteps(r) == 0) ++r;
+  if (r < s) {
+    lr = r;
+    start_class(lr);
+    int pt = 0, pns = nsteps(r), pfirst = y0 + r - HALO * s;
+    PairPre<KR> cur, nxt;
+    load_round(cur);
+    advance_load();
+    while (true) {
+      load_round(nxt);  // past the last class: further rows of the planes, unused
+      advance_load();
+      process(cur, pt, pns, pfirst);
+      pt += KR;
+      if (pt >= padded(pns)) {
+        do {
+          ++r;
+        } while (r < s && nsteps(r) == 0);
+        if (r >= s) break;
+        pt = 0;
+        pns = nsteps(r);
+        pfirst = y0 + r - HALO * s;
+      }
+      cur = nxt;
+    }
+  }
+}
+
+template <int MODE, int KR>
+__global__ void __launch_bounds__(1024) k_pair(AtrousArgs a) {
+  pair_body<MODE, KR>(a);
+}
+
+template <int MODE, int KR>
+__global__ void __launch_bounds__(1024) k_pair_trial(AtrousArgs a) {
+  pair_body<MODE, KR>(a);
+}
+
 constexpr int kKR = 8;   // rows per round, single-smoothing modes
 constexpr int kKR2 = 4;  // rows per round, double-smoothing modes (keeps them within 128 VGPRs)
+constexpr int kKRP = 2;  // rows per round, pair kernels (keeps them within 128 VGPRs)
 
 static int band_rows_default(int N, int j) {
   // about 32 s rows per band (band edges cost 4s or 8s extra row loads per class), at least 64
   int target = 32 << j;
   if (target < 64) target = 64;
+  int TY = 1;
+  while (TY * 2 <= target && TY * 2 <= N) TY *= 2;
+  while (N % TY) TY >>= 1;
+  return TY;
+}
+
+static bool is_pair(int mode) { return mode == PR_ANALYSIS || mode == PR_ANALYSIS_C || mode == PR_ADJOINT; }
+
+static int pair_rows_default(int N, int j) {
+  // the pairs' halo is 10 s rows on either side: about 64 s rows per band, at least 128
+  int target = 64 << j;
+  if (target < 128) target = 128;
   int TY = 1;
   while (TY * 2 <= target && TY * 2 <= N) TY *= 2;
   while (N % TY) TY >>= 1;
@@ -315,6 +588,9 @@ int atrous_class(int mode) {
     case DB_ADJOINT: return 1;
     case SM_DETAIL1: return 2;
     case SM_SUBADD: return 3;
+    case PR_ANALYSIS:
+    case PR_ANALYSIS_C: return 5;
+    case PR_ADJOINT: return 6;
     default: return 4;
   }
 }
@@ -322,7 +598,8 @@ int atrous_class(int mode) {
 int atrous_band_rows(int N, int j, int mode) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(tune_key(N, j, atrous_class(mode)));
-  return it != g_tune.end() ? it->second : band_rows_default(N, j);
+  if (it != g_tune.end()) return it->second;
+  return is_pair(mode) ? pair_rows_default(N, j) : band_rows_default(N, j);
 }
 
 int atrous_set_band_rows(int N, int j, int mode, int TY) {
@@ -400,6 +677,49 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   return MUFFIN_OK;
 }
 
+int launch_pair(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out, PlaneOut out2,
+                PlaneOut out3, float coef, float rho, float coef2, hipStream_t st, int trial) {
+  if (!is_pair(mode)) return set_error("pair: bad mode"), MUFFIN_EINVAL;
+  if (N > 1024) return set_error("pair: N > 1024"), MUFFIN_EINVAL;
+  AtrousArgs a{};
+  a.A = A;
+  a.B = B;
+  a.E = E;
+  a.out = out;
+  a.out2 = out2;
+  a.out3 = out3;
+  a.N = N;
+  a.j = j;
+  a.coef = coef;
+  a.rho = rho;
+  a.coef2 = coef2;
+  a.TX = N;
+  a.TY = atrous_band_rows(N, j, mode);
+  a.tiles_x = 1;
+  a.tiles_per_ch = N / a.TY;
+  const long long nb = (long long)a.tiles_per_ch * nch;
+  if (nb > 0x7fffffffLL) return set_error("pair: grid too large"), MUFFIN_EINVAL;
+  a.nblocks = (int)nb;
+  const size_t shm = sizeof(float) * (size_t)4 * kKRP * N;
+  const dim3 grid((unsigned)nb), block((unsigned)N);
+  switch (mode) {
+    case PR_ANALYSIS:
+      if (trial) hipLaunchKernelGGL((k_pair_trial<PR_ANALYSIS, kKRP>), grid, block, shm, st, a);
+      else hipLaunchKernelGGL((k_pair<PR_ANALYSIS, kKRP>), grid, block, shm, st, a);
+      break;
+    case PR_ANALYSIS_C:
+      if (trial) hipLaunchKernelGGL((k_pair_trial<PR_ANALYSIS_C, kKRP>), grid, block, shm, st, a);
+      else hipLaunchKernelGGL((k_pair<PR_ANALYSIS_C, kKRP>), grid, block, shm, st, a);
+      break;
+    default:
+      if (trial) hipLaunchKernelGGL((k_pair_trial<PR_ADJOINT, kKRP>), grid, block, shm, st, a);
+      else hipLaunchKernelGGL((k_pair<PR_ADJOINT, kKRP>), grid, block, shm, st, a);
+      break;
+  }
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
 int atrous_init_attrs() {
   const int shm = (int)(sizeof(float) * 2 * kKR * 1024);
   MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_SMOOTH, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
@@ -414,6 +734,17 @@ int atrous_init_attrs() {
                              shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<DB_ANALYSIS_C, kKR2>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  const int shmp = (int)(sizeof(float) * 4 * kKRP * 1024);
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair<PR_ANALYSIS, kKRP>, hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair<PR_ANALYSIS_C, kKRP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair<PR_ADJOINT, kKRP>, hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair_trial<PR_ANALYSIS, kKRP>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair_trial<PR_ANALYSIS_C, kKRP>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair_trial<PR_ADJOINT, kKRP>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_SUBADD, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_DETAIL1, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,

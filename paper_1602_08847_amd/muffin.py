@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("N", ctypes.c_int32), ("L", ctypes.c_int32), ("J", ctypes.c_int32),
         ("iuwt_gen", ctypes.c_int32), ("penalize_coarse", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
         ("mu_s", ctypes.c_double), ("mu_lambda", ctypes.c_double),
         ("tau", ctypes.c_double), ("sigma", ctypes.c_double), ("rho", ctypes.c_double),
         ("chan_weight", ctypes.POINTER(ctypes.c_float)),
@@ -94,6 +94,9 @@ _lib.muffin_batch_free.argtypes = [_vp]
 _lib.muffin_batch_free.restype = None
 
 
+FLAG_SINGLE_SCALE = 1  # one IUWT launch per scale (same results as the fused pairs of scales)
+
+
 class MuffinError(RuntimeError):
     def __init__(self, code: int, where: str):
         msg = _lib.muffin_last_error().decode(errors="replace")
@@ -132,7 +135,7 @@ class Muffin:
 
     def __init__(self, dirty, psf, J: int, mu_s: float, mu_lambda: float, iuwt_gen: int = 2,
                  penalize_coarse: bool = True, tau: float = 0.0, sigma: float = 1.0,
-                 rho: float = 1.0, chan_weight=None):
+                 rho: float = 1.0, chan_weight=None, flags: int = 0):
         torch = _torch()
         dirty = torch.as_tensor(dirty, dtype=torch.float32).cuda().contiguous()
         psf = torch.as_tensor(psf, dtype=torch.float32).cuda().contiguous()
@@ -142,7 +145,7 @@ class Muffin:
         self.N, self.L, self.J = N, L, J
         self._cw = None
         p = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=int(bool(penalize_coarse)),
-                   reserved=0, mu_s=mu_s, mu_lambda=mu_lambda, tau=tau, sigma=sigma, rho=rho)
+                   flags=flags, mu_s=mu_s, mu_lambda=mu_lambda, tau=tau, sigma=sigma, rho=rho)
         if chan_weight is not None:
             self._cw = np.ascontiguousarray(chan_weight, dtype=np.float32)
             if self._cw.shape != (L,):
@@ -181,7 +184,7 @@ class Muffin:
         return ms.value
 
     def profile(self, n: int) -> np.ndarray:
-        out = (ctypes.c_double * 8)()
+        out = (ctypes.c_double * 24)()
         _check(_lib.muffin_profile(self._h, n, out), "muffin_profile")
         return np.array(out[:])
 
@@ -372,7 +375,7 @@ class Batch:
             L, N, _ = d.shape
             self.shapes.append((L, N))
             self._keep += [d, f]
-            ps[i] = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=1, reserved=0, mu_s=mu_s,
+            ps[i] = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=1, flags=0, mu_s=mu_s,
                            mu_lambda=mls[i], tau=taus[i], sigma=sigma, rho=rho)
             dptr[i] = d.data_ptr()
             fptr[i] = f.data_ptr()

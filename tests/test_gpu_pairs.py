@@ -1,0 +1,60 @@
+"""Two IUWT scales per launch against one scale per launch: the fused pair kernels perform the same
+operations in the same order, so the iterates agree bit for bit, for odd and even J (the schedule
+then ends in a single scale or a pair), with and without the coarse plane's penalty, with
+relaxation, and for image sides where the coarse taps wrap around the image several times."""
+import numpy as np
+import pytest
+
+from paper_1602_08847_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # N, L, J, penalize_coarse, rho
+    (64, 8, 1, True, 1.0),
+    (64, 8, 2, True, 1.0),
+    (64, 8, 3, True, 1.0),
+    (64, 8, 4, False, 0.8),
+    (96, 5, 5, True, 0.9),
+    (128, 4, 6, True, 1.0),
+    (16, 3, 4, True, 1.0),
+    (8, 2, 3, False, 1.0),
+    (12, 3, 5, True, 1.0),
+    (256, 3, 5, True, 1.0),
+]
+
+
+@pytest.mark.parametrize("N,L,J,pc,rho", CASES)
+def test_pairs_match_single_scale_bitwise(lib, N, L, J, pc, rho):
+    c = synth.make_cube(synth.CubeSpec(N=N, L=L, J=J, n_sources=max(2, N // 16), n_baselines=max(8, N * 2),
+                                       seed=N + J))
+    out = {}
+    for flags in (0, lib.FLAG_SINGLE_SCALE):
+        with lib.Muffin(c.dirty, c.psf, J=J, mu_s=0.25, mu_lambda=3.0, penalize_coarse=pc, sigma=10.0, rho=rho,
+                        flags=flags) as m:
+            m.step(7)
+            out[flags] = (m.get_x().cpu().numpy(), m.get_u().cpu().numpy(), m.get_v().cpu().numpy())
+    for a, b in zip(out[0], out[lib.FLAG_SINGLE_SCALE]):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_pairs_autotuned_match_single_scale(lib):
+    c = synth.make_cube(synth.CubeSpec(N=128, L=6, J=5, n_sources=6, n_baselines=300, seed=9))
+    kw = dict(J=5, mu_s=0.25, mu_lambda=3.0, sigma=10.0)
+    with lib.Muffin(c.dirty, c.psf, **kw) as a, lib.Muffin(c.dirty, c.psf, flags=lib.FLAG_SINGLE_SCALE, **kw) as b:
+        a.autotune(reps=1)
+        a.step(5)
+        b.step(5)
+        np.testing.assert_array_equal(a.get_u().cpu().numpy(), b.get_u().cpu().numpy())
+
+
+@pytest.mark.parametrize("J,counts", [(5, {1: 1, 2: 1, 3: 2, 4: 2}), (4, {3: 1, 4: 2, 5: 1})])
+def test_profile_reports_the_launch_schedule(lib, J, counts):
+    c = synth.make_cube(synth.CubeSpec(N=64, L=4, J=J, n_sources=3, n_baselines=100, seed=2))
+    with lib.Muffin(c.dirty, c.psf, J=J, mu_s=0.25, mu_lambda=3.0) as m:
+        ms = m.profile(4)
+    assert np.all(ms[5:8] == 0)
+    for k in range(8):
+        assert ms[9 + 2 * k] == counts.get(k, 0), (k, ms)
+        assert (ms[8 + 2 * k] > 0) == (k in counts)
+    assert ms[0] == pytest.approx(sum(ms[1:5]), rel=1e-6)
