@@ -144,6 +144,53 @@ static int timed_launch(muffin_ctx* c, bool timed, int kind, F&& launch) {
 
 static bool use_pairs(const muffin_ctx* c) { return c->gen == 2 && !(c->p.flags & MUFFIN_FLAG_SINGLE_SCALE); }
 
+// The band and pair launches of the two IUWT phases, in order; j is the (finer) scale of a launch.
+// Pairs sit at the finest scales, where their 10 s rows of halo are cheapest: the analysis pairs
+// (0, 1), (2, 3), ... and, for odd J, leaves the coarsest scale alone; the adjoint, which runs from
+// the coarsest scale down, then starts with that scale alone.
+struct IuwtStep {
+  int mode, j;
+  const char* name;
+};
+
+static std::vector<IuwtStep> analysis_schedule(const muffin_ctx* c) {
+  const int J = c->J;
+  const bool pairs = use_pairs(c), coarse = c->omega_c != 0.f;
+  std::vector<IuwtStep> v;
+  for (int j = 0; j < J;) {
+    if (c->gen == 1) {
+      v.push_back({SM_DETAIL1, j, "analysis"});
+      j += 1;
+    } else if (pairs && j + 1 < J) {
+      v.push_back({(j + 2 == J && coarse) ? PR_ANALYSIS_C : PR_ANALYSIS, j, "analysis pair"});
+      j += 2;
+    } else {
+      v.push_back({(j == J - 1 && coarse) ? DB_ANALYSIS_C : DB_ANALYSIS, j, "analysis"});
+      j += 1;
+    }
+  }
+  return v;
+}
+
+static std::vector<IuwtStep> adjoint_schedule(const muffin_ctx* c) {
+  const int J = c->J;
+  const bool pairs = use_pairs(c);
+  std::vector<IuwtStep> v;
+  for (int j = J - 1; j >= 0;) {
+    if (c->gen == 1) {
+      v.push_back({SM_SUBADD, j, "adjoint"});
+      j -= 1;
+    } else if (pairs && j >= 1 && !(j == J - 1 && (J & 1))) {
+      v.push_back({PR_ADJOINT, j - 1, "adjoint pair"});
+      j -= 2;
+    } else {
+      v.push_back({DB_ADJOINT, j, "adjoint"});
+      j -= 1;
+    }
+  }
+  return v;
+}
+
 // Spatial adjoint of omega-weighted U; returns the buffer holding a = W_s^dagger (omega u).
 // Second generation: Horner steps a <- u_j + H_j (a - H_j u_j) from the coarsest scale down, two
 // scales per launch where possible.
@@ -162,30 +209,25 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omeg
     acs = np;
     nb = 1;
   }
-  const bool pairs = use_pairs(c);
-  for (int j = J - 1; j >= 0;) {
+  for (const IuwtStep& st : adjoint_schedule(c)) {
     float* dst = bufs[nb];
-    if (c->gen == 2 && pairs && j >= 1) {
-      // scales j and j - 1
-      const float* uh = Ubase + (long long)j * np;
-      const float* ul = Ubase + (long long)(j - 1) * np;
+    const int j = st.j;
+    const float* uj = Ubase + (long long)j * np;
+    if (st.mode == PR_ADJOINT) {
+      // steps j + 1 then j
+      const float* uh = Ubase + (long long)(j + 1) * np;
       MF_TRY(timed_launch(c, timed, K_PR_ADJOINT, [&] {
-        return launch_pair(PR_ADJOINT, c->N, c->L, j - 1, pref(uh, ucs), pref(ul, ucs), pref(a, acs), pout(dst, np),
+        return launch_pair(PR_ADJOINT, c->N, c->L, j, pref(uh, ucs), pref(uj, ucs), pref(a, acs), pout(dst, np),
                            PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f, c->st);
       }));
-      j -= 2;
-    } else if (c->gen == 2) {
-      const float* uj = Ubase + (long long)j * np;
+    } else if (st.mode == DB_ADJOINT) {
       MF_TRY(timed_launch(c, timed, K_DB_ADJOINT, [&] {
         return launch_atrous(DB_ADJOINT, c->N, c->L, j, pref(uj, ucs), pref(a, acs), PlaneRef{}, pout(dst, np),
                              PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st);
       }));
-      j -= 1;
     } else {
-      const float* uj = Ubase + (long long)j * np;
       MF_TRY(launch_atrous(SM_SUBADD, c->N, c->L, j, pref(a, acs), pref(uj, ucs), pref(uj, ucs), pout(dst, np),
                            PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
-      j -= 1;
     }
     a = dst;
     acs = np;
@@ -208,41 +250,36 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
   const float* cur = in;
   float* bufs[2] = {c->cA, c->cB};
   int nb = 0;
-  const bool pairs = use_pairs(c);
-  for (int j = 0; j < J;) {
+  for (const IuwtStep& st : analysis_schedule(c)) {
     float* nxt = bufs[nb];
+    const int j = st.j;
     float* uj = c->U + (long long)j * np;
-    if (c->gen == 1) {
-      MF_TRY(launch_atrous(SM_DETAIL1, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
-                           pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
-      j += 1;
-    } else if (pairs && j + 1 < J) {
-      float* uj1 = c->U + (long long)(j + 1) * np;
-      const bool last = j + 2 == J;
-      if (last && coarse) {
-        MF_TRY(timed_launch(c, timed, K_PR_ANALYSIS_C, [&] {
-          return launch_pair(PR_ANALYSIS_C, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
-                             pout(uj1, ucs), pout(Uc, ucs), coef, rho, coefc, c->st);
+    switch (st.mode) {
+      case SM_DETAIL1:
+        MF_TRY(launch_atrous(SM_DETAIL1, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                             pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
+        break;
+      case PR_ANALYSIS_C:
+      case PR_ANALYSIS: {
+        float* uj1 = c->U + (long long)(j + 1) * np;
+        const bool co = st.mode == PR_ANALYSIS_C;
+        MF_TRY(timed_launch(c, timed, co ? K_PR_ANALYSIS_C : K_PR_ANALYSIS, [&] {
+          return launch_pair(st.mode, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                             pout(uj1, ucs), co ? pout(Uc, ucs) : pout(nxt, np), coef, rho, co ? coefc : 0.f, c->st);
         }));
-        return MUFFIN_OK;
+        break;
       }
-      MF_TRY(timed_launch(c, timed, K_PR_ANALYSIS, [&] {
-        return launch_pair(PR_ANALYSIS, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
-                           pout(uj1, ucs), pout(nxt, np), coef, rho, 0.f, c->st);
-      }));
-      j += 2;
-    } else if (j == J - 1 && coarse) {
-      MF_TRY(timed_launch(c, timed, K_DB_ANALYSIS_C, [&] {
-        return launch_atrous(DB_ANALYSIS_C, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
-                             pout(Uc, ucs), coef, rho, nullptr, nullptr, c->st, 0, coefc);
-      }));
-      return MUFFIN_OK;
-    } else {
-      MF_TRY(timed_launch(c, timed, K_DB_ANALYSIS, [&] {
-        return launch_atrous(DB_ANALYSIS, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
-                             pout(nxt, np), coef, rho, nullptr, nullptr, c->st);
-      }));
-      j += 1;
+      case DB_ANALYSIS_C:
+        MF_TRY(timed_launch(c, timed, K_DB_ANALYSIS_C, [&] {
+          return launch_atrous(DB_ANALYSIS_C, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                               pout(Uc, ucs), coef, rho, nullptr, nullptr, c->st, 0, coefc);
+        }));
+        break;
+      default:
+        MF_TRY(timed_launch(c, timed, K_DB_ANALYSIS, [&] {
+          return launch_atrous(DB_ANALYSIS, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
+                               pout(nxt, np), coef, rho, nullptr, nullptr, c->st);
+        }));
     }
     cur = nxt;
     nb ^= 1;
@@ -553,40 +590,11 @@ int ensure_graph(muffin_ctx* c) {
 // on the context's own sizes (reading state, writing only scratch planes) and keep the fastest.
 int autotune(muffin_ctx* c, int reps, std::string& rep) {
   const long long np = c->npix, ucs = (long long)(c->J + 1) * np;
-  const int J = c->J;
-  const bool pairs = use_pairs(c), coarse = c->omega_c != 0.f;
-  struct TL {
-    int mode, j;
-    const char* name;
-  };
-  std::vector<TL> sched;
-  for (int j = 0; j < J;) {
-    if (c->gen == 1) {
-      sched.push_back({SM_DETAIL1, j, "analysis"});
-      j += 1;
-    } else if (pairs && j + 1 < J) {
-      sched.push_back({(j + 2 == J && coarse) ? PR_ANALYSIS_C : PR_ANALYSIS, j, "analysis pair"});
-      j += 2;
-    } else {
-      sched.push_back({(j == J - 1 && coarse) ? DB_ANALYSIS_C : DB_ANALYSIS, j, "analysis"});
-      j += 1;
-    }
-  }
-  for (int j = J - 1; j >= 0;) {
-    if (c->gen == 1) {
-      sched.push_back({SM_SUBADD, j, "adjoint"});
-      j -= 1;
-    } else if (pairs && j >= 1) {
-      sched.push_back({PR_ADJOINT, j - 1, "adjoint pair"});
-      j -= 2;
-    } else {
-      sched.push_back({DB_ADJOINT, j, "adjoint"});
-      j -= 1;
-    }
-  }
+  std::vector<IuwtStep> sched = analysis_schedule(c);
+  for (const IuwtStep& st : adjoint_schedule(c)) sched.push_back(st);
   rep += "{\"N\": " + std::to_string(c->N) + ", \"channels\": " + std::to_string(c->L) + ", \"scales\": [";
   bool firstrep = true;
-  for (const TL& L : sched) {
+  for (const IuwtStep& L : sched) {
     const int mode = L.mode, j = L.j;
     double best = 1e30;
     int best_ty = atrous_band_rows(c->N, j, mode);
