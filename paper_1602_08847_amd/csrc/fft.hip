@@ -92,6 +92,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
   constexpr int CB = col_block<N>();
   constexpr int LS = lstride<N>();
   extern __shared__ float2 lds[];
+  float2* twl = lds + CB * LS;  // [N] twiddle table, copied once so the stages read it from LDS
+  for (int i = threadIdx.x; i < N; i += CB * T) twl[i] = tw[i];
   // consecutive column blocks of a channel run on one XCD
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int ch = blk / ncb;
@@ -120,7 +122,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
   float2 mc[(MODE == COL_CPLX || MODE == COL_CPLX_CONJ) ? NI : 1];
   lds_barrier();
   float2* buf = lds + f * LS;
-  fft_lds<N, false>(buf, t, true, tw);
+  fft_lds<N, false>(buf, t, true, twl);
   __builtin_amdgcn_sched_barrier(0);  // the multiplier loads stay after the transform
   if constexpr (MODE == COL_REAL) {
     const float* __restrict__ mp = Mr + mrow + t;
@@ -152,7 +154,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
     }
     // fft_lds begins with reads of this thread group's own entries only after a barrier
     lds_barrier();
-    fft_lds<N, true>(buf, t, true, tw);
+    fft_lds<N, true>(buf, t, true, twl);
 #pragma unroll
     for (int i = 0; i < NI; ++i) *sent(i) = lds[cc * LS + lpad(r0 + i * RSTEP)];
   }
@@ -335,7 +337,7 @@ static int cols_n(float2* S, int nch, const FftGeom& g, const float2* tw, int mo
   constexpr int T = Plan<N>::T;
   constexpr int CB = col_block<N>();
   constexpr int LS = lstride<N>();
-  const size_t shm = sizeof(float2) * CB * LS;
+  const size_t shm = sizeof(float2) * (CB * LS + N);  // columns, then the twiddle table
   const dim3 grid((unsigned)(nch * g.ncb)), block(CB * T);
   switch (mode) {
     case COL_FWD:
@@ -490,7 +492,7 @@ int launch_rows_c2r(const float2* S, int nch, const FftGeom& g, const float2* tw
 
 template <int N>
 static int attrs_n() {
-  constexpr int shm = (int)(sizeof(float2) * col_block<N>() * lstride<N>());
+  constexpr int shm = (int)(sizeof(float2) * (col_block<N>() * lstride<N>() + N));
   MF_HIP(hipFuncSetAttribute((const void*)k_cols<N, COL_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_cols<N, COL_REAL>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_cols<N, COL_CPLX>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));

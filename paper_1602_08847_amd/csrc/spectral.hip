@@ -103,7 +103,7 @@ struct SpecGeom {
   static constexpr int LS = lstride<L>();
   static constexpr int NT = NF * T;                       // threads per block
   static constexpr int PER = (L * PXB + NT - 1) / NT;     // (channel, pixel) elements per thread
-  static constexpr size_t shm = sizeof(float2) * NF * LS;
+  static constexpr size_t shm = sizeof(float2) * (NF * LS + L);  // transforms, then the twiddles
 };
 
 __device__ __forceinline__ int dct_slot(int l, int L) { return (l & 1) ? L - 1 - (l >> 1) : (l >> 1); }
@@ -115,6 +115,8 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   constexpr int NT = NF * T;
   constexpr int PER = G::PER;
   extern __shared__ float2 buf[];  // [NF][LS] transforms; pixel p is part p & 1 of transform p / 2
+  float2* twl = buf + NF * LS;     // [L] twiddle table, copied once so the stages read it from LDS
+  for (int i = threadIdx.x; i < L; i += NT) twl[i] = a.twL[i];
   const long long npix = a.npix;
   const long long pix0 = (long long)blockIdx.x * PXB;
   // Element i of a thread is (channel, pixel) = (idx / PXB, idx % PXB), idx = threadIdx.x + i NT.
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     }
   }
   lds_barrier();
-  fft_lds<L, true>(fb, t, true, a.twL);
+  fft_lds<L, true>(fb, t, true, twl);
   // primal step per (channel, pixel); x and q are fetched here, all at once, and d goes back into
   // the same slot for the forward transform
   float xreg[PER], qreg[PER];
@@ -201,7 +203,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     *slot = d;
   }
   lds_barrier();
-  fft_lds<L, false>(fb, t, true, a.twL);
+  fft_lds<L, false>(fb, t, true, twl);
   // spectral dual step per (coefficient, pixel): element i now stands for coefficient k = el_l(i)
   const float s0 = a.smu_l * sqrtf(1.f / L), s1 = a.smu_l * sqrtf(2.f / L);
 #pragma unroll
