@@ -83,8 +83,9 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, f
 // ------------------------------------------------------------------ pass 2: columns
 
 template <int N, int MODE>
-// two workgroups per CU: the register budget is capped at 128 (radix-16 plans fit without spills)
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_cols(float2* __restrict__ S, int pitch, int ncb,
+// two workgroups per CU: the register budget is capped at 128 for power-of-two sizes (their
+// radix-16/8 plans fit without spills; the radix-3 plans would spill, so they keep the default)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((N & (N - 1)) == 0 ? 4 : 1))) k_cols(float2* __restrict__ S, int pitch, int ncb,
                                               const float2* __restrict__ tw, const float* __restrict__ Mr,
                                               const float2* __restrict__ Mc, float scale,
                                               float2* __restrict__ outT) {

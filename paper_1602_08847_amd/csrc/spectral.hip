@@ -89,6 +89,94 @@ __global__ void __launch_bounds__(256) k_spectral_step(SpectralArgs a) {
 }
 
 
+// Channel counts without an FFT plan, L <= 256: the same step with the two cosine transforms as
+// dense products.  A workgroup owns 64 pixels, one per lane, and stages their dual spectra and d
+// across all L channels in LDS.  A wave computes CW channels at a time, so the cosine-table
+// entries it needs are the same in every lane (scalar loads) and each LDS read feeds CW FMAs;
+// the sums run over k in order, as in k_spectral_step.
+constexpr int PXM = 64;
+constexpr int kMatMaxL = 256;
+// the cosine tables are read-only for the whole launch: read them through the constant address
+// space, so that the wave-uniform reads become scalar loads
+typedef const float __attribute__((address_space(4)))* const_fp;
+
+template <int CW>
+__global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
+  extern __shared__ float sm[];
+  const int L = a.L;
+  float* Vs = sm;            // [L][PXM]
+  float* Ds = sm + L * PXM;  // [L][PXM]
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long npix = a.npix;
+  const long long pix = (long long)blockIdx.x * PXM + lane;
+  const bool pok = pix < npix;
+  for (int l = wv; l < L; l += 4) Vs[l * PXM + lane] = pok ? a.V[(long long)l * npix + pix] : 0.f;
+  lds_barrier();
+  // primal step, channels l0 .. l0 + CW - 1 of this wave
+  for (int l0 = wv * CW; l0 < L; l0 += 4 * CW) {
+    float xr[CW], qr[CW], acc[CW];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      const long long o = (long long)min(l0 + c, L - 1) * npix + (pok ? pix : 0);
+      xr[c] = a.X[o];  // fetched now, used after the sums
+      qr[c] = a.Q[o];
+      acc[c] = 0.f;
+    }
+    const_fp Wr[CW];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) Wr[c] = (const_fp)(a.W + (long long)min(l0 + c, L - 1) * L);
+#pragma unroll 4
+    for (int k = 0; k < L; ++k) {
+      const float v = Vs[k * PXM + lane];
+#pragma unroll
+      for (int c = 0; c < CW; ++c) acc[c] = fmaf(Wr[c][k], v, acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      const int l = l0 + c;
+      if (l >= L) break;
+      float d = 0.f;
+      if (pok) {
+        const long long o = (long long)l * npix + pix;
+        const float x = xr[c];
+        const float tv = a.mu_l * acc[c];
+        const float xt = fmaxf(x - a.tau * (qr[c] + tv), 0.f);
+        d = 2.f * xt - x;
+        a.D[o] = d;
+        a.X[o] = a.rho * xt + (1.f - a.rho) * x;
+      }
+      Ds[l * PXM + lane] = d;
+    }
+  }
+  lds_barrier();
+  // spectral dual step, coefficients k0 .. k0 + CW - 1 of this wave
+  for (int k0 = wv * CW; k0 < L; k0 += 4 * CW) {
+    float acc[CW];
+    const_fp Wr[CW];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      acc[c] = 0.f;
+      Wr[c] = (const_fp)(a.WT + (long long)min(k0 + c, L - 1) * L);
+    }
+#pragma unroll 4
+    for (int l = 0; l < L; ++l) {
+      const float dv = Ds[l * PXM + lane];
+#pragma unroll
+      for (int c = 0; c < CW; ++c) acc[c] = fmaf(Wr[c][l], dv, acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      const int k = k0 + c;
+      if (k >= L) break;
+      if (pok) {
+        const float v = Vs[k * PXM + lane];
+        a.V[(long long)k * npix + pix] = a.rho * satf_s(v + a.smu_l * acc[c]) + (1.f - a.rho) * v;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ FFT-based fused step
 // Orthonormal DCT-II of a length-L spectrum x: v = (x_0, x_2, ..., x_{L-2}, x_{L-1}, ..., x_3, x_1),
 // X_k = s_k Re(exp(-i pi k / 2L) FFT(v)_k).  Its inverse: Y_k = s_k h_k X_k (h_0 = 1, h_k = 1/2),
@@ -276,6 +364,13 @@ int launch_spectral_step(const SpectralArgs& a, hipStream_t st) {
   if (a.use_fft) {
     MF_SPEC_DISPATCH(a.L, spectral_fft_n, a, st)
   }
+  if (a.L <= kMatMaxL) {
+    const size_t shm = sizeof(float) * 2 * (size_t)a.L * PXM;
+    const long long nblk = (a.npix + PXM - 1) / PXM;
+    hipLaunchKernelGGL(k_spectral_mat<8>, dim3((unsigned)nblk), dim3(256), shm, st, a);
+    MF_HIP(hipGetLastError());
+    return MUFFIN_OK;
+  }
   const size_t shm = sizeof(float) * 2 * (size_t)a.L * PX;
   const long long nblk = (a.npix + PX - 1) / PX;
   hipLaunchKernelGGL(k_spectral_step, dim3((unsigned)nblk), dim3(256), shm, st, a);
@@ -355,6 +450,8 @@ int launch_dct_abs(const float* in, const float* WT, long long npix, int L, doub
 int spectral_direct_attrs(int L) {
   const int shm = (int)(sizeof(float) * 2 * (size_t)L * PX);
   MF_HIP(hipFuncSetAttribute((const void*)k_spectral_step, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+  MF_HIP(hipFuncSetAttribute((const void*)k_spectral_mat<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(float) * 2 * kMatMaxL * PXM)));
   MF_HIP(hipFuncSetAttribute((const void*)k_pix_matvec<false>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_pix_matvec<true>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   return MUFFIN_OK;
