@@ -384,48 +384,53 @@ template <bool ABS>
 __global__ void __launch_bounds__(256) k_pix_matvec(const float* __restrict__ in, float* __restrict__ out,
                                                     const float* __restrict__ M, long long npix, int L,
                                                     double* __restrict__ partial) {
+  // 64 pixels per workgroup, one per lane; a wave computes 8 output rows at a time from
+  // wave-uniform matrix rows (scalar loads), each LDS read feeding 8 FMAs; sums run over j in order
+  constexpr int CW = 8;
   extern __shared__ float sm[];
-  float* Is = sm;  // [L][PX]
-  const int p = threadIdx.x & (PX - 1);
-  const int g = threadIdx.x >> 5;
-  const long long pix0 = (long long)blockIdx.x * PX;
-  const long long pix = pix0 + p;
-  for (int idx = threadIdx.x; idx < L * PX; idx += 256) {
-    const int l = idx / PX, pp = idx % PX;
-    const long long q = pix0 + pp;
-    Is[idx] = (q < npix) ? in[(long long)l * npix + q] : 0.f;
-  }
+  float* Is = sm;  // [L][PXM]
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const long long pix = (long long)blockIdx.x * PXM + lane;
+  const bool pok = pix < npix;
+  for (int l = wv; l < L; l += 4) Is[l * PXM + lane] = pok ? in[(long long)l * npix + pix] : 0.f;
   lds_barrier();
   double acc_abs = 0.0;
-  for (int ib = g; ib < L; ib += 32) {
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int j = 0; j < L; ++j) {
-      const float v = Is[j * PX + p];
+  for (int i0 = wv * CW; i0 < L; i0 += 4 * CW) {
+    float acc[CW];
+    const_fp Mr[CW];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (ib + 8 * i < L) acc[i] = fmaf(M[(ib + 8 * i) * L + j], v, acc[i]);
+    for (int c = 0; c < CW; ++c) {
+      acc[c] = 0.f;
+      Mr[c] = (const_fp)(M + (long long)min(i0 + c, L - 1) * L);
+    }
+#pragma unroll 4
+    for (int j = 0; j < L; ++j) {
+      const float v = Is[j * PXM + lane];
+#pragma unroll
+      for (int c = 0; c < CW; ++c) acc[c] = fmaf(Mr[c][j], v, acc[c]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = ib + 8 * i;
-      if (r < L && pix < npix) {
-        if (ABS) acc_abs += fabs((double)acc[i]);
-        else out[(long long)r * npix + pix] = acc[i];
+    for (int c = 0; c < CW; ++c) {
+      const int r = i0 + c;
+      if (r < L && pok) {
+        if (ABS) acc_abs += fabs((double)acc[c]);
+        else out[(long long)r * npix + pix] = acc[c];
       }
     }
   }
   if constexpr (ABS) {
     for (int off = 32; off > 0; off >>= 1) acc_abs += __shfl_down(acc_abs, off, 64);
     __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc_abs;
+    if (lane == 0) red[wv] = acc_abs;
     lds_barrier();
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
   }
 }
 
 int launch_dct(const float* in, float* out, const float* Wmat, long long npix, int L, hipStream_t st) {
-  const size_t shm = sizeof(float) * (size_t)L * PX;
-  const long long nblk = (npix + PX - 1) / PX;
+  const size_t shm = sizeof(float) * (size_t)L * PXM;
+  const long long nblk = (npix + PXM - 1) / PXM;
   hipLaunchKernelGGL(k_pix_matvec<false>, dim3((unsigned)nblk), dim3(256), shm, st, in, out, Wmat, npix, L,
                      (double*)nullptr);
   MF_HIP(hipGetLastError());
@@ -434,8 +439,8 @@ int launch_dct(const float* in, float* out, const float* Wmat, long long npix, i
 
 int launch_dct_abs(const float* in, const float* WT, long long npix, int L, double* partial, int* nblocks_out,
                    hipStream_t st) {
-  const size_t shm = sizeof(float) * (size_t)L * PX;
-  const long long nblk = (npix + PX - 1) / PX;
+  const size_t shm = sizeof(float) * (size_t)L * PXM;
+  const long long nblk = (npix + PXM - 1) / PXM;
   if (nblk > kMaxPartials) {
     set_error("dct_abs: too many blocks for the partial-sum buffer");
     return MUFFIN_EINVAL;

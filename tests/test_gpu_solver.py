@@ -83,6 +83,26 @@ def test_single_iteration_matches_oracle_tightly(lib, small):
         assert rel(m.get_v().double().cpu().numpy(), st.V) < 1e-5
 
 
+@pytest.mark.parametrize("N,L", [(16, 100), (16, 260), (16, 384)])
+def test_single_iteration_spectral_paths(lib, N, L):
+    """One iteration with the spectral step on each of its paths: dense cosine products (L <= 256
+    without an FFT plan), the direct kernel (larger L without a plan), an FFT with a radix-3 plan."""
+    c = synth.make_cube(synth.CubeSpec(N=N, L=L, J=2, n_sources=3, n_baselines=40, seed=L))
+    dirty, psf = f32(c.dirty), f32(c.psf)
+    p = om.Problem(dirty=dirty, psf=psf, J=2, mu_s=0.25, mu_l=3.0)
+    tau = om.step_sizes(p)[0]
+    r = np.random.default_rng(6)
+    x0 = f32(np.abs(r.normal(size=dirty.shape)))
+    st = om.iterate(p, om.init_state(p, x0), tau)
+    st = om.iterate(p, st, tau)
+    with lib.Muffin(dirty, psf, J=2, mu_s=0.25, mu_lambda=3.0, tau=tau) as m:
+        m.set_x(x0)
+        m.step(2)
+        assert rel(m.get_x().double().cpu().numpy(), st.X) < 1e-5
+        assert rel(m.get_u().double().cpu().numpy(), st.U) < 1e-5
+        assert rel(m.get_v().double().cpu().numpy(), st.V) < 1e-5
+
+
 def delta_psf(L, N):
     psf = np.zeros((L, N, N))
     psf[:, N // 2, N // 2] = 1.0
