@@ -43,9 +43,9 @@ constexpr int span_before(int s) {
   return p;
 }
 
-// LDS addressing: one padding slot every 16 complex entries breaks power-of-two strides;
+// LDS addressing: one padding slot every 32 complex entries breaks power-of-two strides;
 // the per-transform stride is odd so that transforms side by side fall in different banks.
-__host__ __device__ constexpr int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lpad(int i) { return i + (i >> 5); }
 template <int N>
 constexpr int lstride() {
   int s = lpad(N - 1) + 1;
