@@ -45,6 +45,12 @@ KERNEL_BYTES = {
     "k_pair<PR_ADJOINT> (two adjoint Horner steps)": 16.0,
     # reads c_{J-2}, u_{J-2}, u_{J-1}, u_J, writes u_{J-2}, u_{J-1}, u_J
     "k_pair<PR_ANALYSIS_C> (last two analysis scales + spatial and coarse dual steps)": 28.0,
+    # reads c_j, u_j, u_{j+1}, u_{j+2}, writes u_j, u_{j+1}, u_{j+2}, c_{j+3}
+    "k_triple<TR_ANALYSIS> (three scales of analysis + spatial dual steps)": 32.0,
+    # reads u_{j+2}, u_{j+1}, u_j and a, writes the new sum
+    "k_triple<TR_ADJOINT> (three adjoint Horner steps)": 20.0,
+    # reads c_{J-3}, the three u planes and u_J, writes the three u planes and u_J
+    "k_triple<TR_ANALYSIS_C> (last three analysis scales + spatial and coarse dual steps)": 36.0,
 }
 PROFILE_SLOT = {
     "k_band<DB_ANALYSIS> (one scale of analysis + spatial dual step)": 0,
@@ -53,6 +59,9 @@ PROFILE_SLOT = {
     "k_pair<PR_ANALYSIS> (two scales of analysis + spatial dual steps)": 3,
     "k_pair<PR_ADJOINT> (two adjoint Horner steps)": 4,
     "k_pair<PR_ANALYSIS_C> (last two analysis scales + spatial and coarse dual steps)": 5,
+    "k_triple<TR_ANALYSIS> (three scales of analysis + spatial dual steps)": 6,
+    "k_triple<TR_ADJOINT> (three adjoint Horner steps)": 7,
+    "k_triple<TR_ANALYSIS_C> (last three analysis scales + spatial and coarse dual steps)": 8,
 }
 
 

@@ -48,8 +48,8 @@ extern "C" {
 
 typedef struct muffin_ctx muffin_ctx;
 
-/* Run the IUWT one launch per scale instead of fusing consecutive scales into one launch (the
- * results are the same bit for bit; the fused form moves fewer bytes). */
+/* Run the IUWT one launch per scale instead of fusing two or three consecutive scales into one
+ * launch (the results are the same bit for bit; the fused form moves fewer bytes). */
 #define MUFFIN_FLAG_SINGLE_SCALE 1
 
 /* Problem and algorithm parameters (Sec. 2 eqs. (reg), (RegAll); Sec. 3, Algorithm 1). */
@@ -140,10 +140,12 @@ int muffin_apply_op(muffin_ctx* ctx, int op, const float* in, float* out);
  *   iteration, for the second-generation band kernels: k = 0 one analysis scale with its dual
  *   step, 1 one adjoint Horner step, 2 the last analysis scale with the coarse plane's dual step,
  *   3 two analysis scales in one launch, 4 two adjoint steps in one launch, 5 the last two
- *   analysis scales with the coarse plane's dual step; k = 6, 7 are 0.
+ *   analysis scales with the coarse plane's dual step, 6 three analysis scales in one launch,
+ *   7 three adjoint steps in one launch, 8 the last three analysis scales with the coarse plane's
+ *   dual step; k = 9..11 are 0.
  * Each kernel family (adjoint, analysis) is bracketed in every other iteration, so n_iter >= 2.
  * The iterations advance the state like muffin_step. */
-int muffin_profile(muffin_ctx* ctx, int32_t n_iter, double ms[24]);
+int muffin_profile(muffin_ctx* ctx, int32_t n_iter, double ms[32]);
 
 /* Time n_iter iterations (graph replay) with HIP events on the library's stream: *ms is the
  * total device time.  Advances the state like muffin_step. */

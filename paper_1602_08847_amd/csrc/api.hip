@@ -127,7 +127,7 @@ int validate(const muffin_params* p) {
 // ---------------------------------------------------------------- phases
 // Launch kinds reported by muffin_profile.
 enum LaunchKind { K_DB_ANALYSIS = 0, K_DB_ADJOINT = 1, K_DB_ANALYSIS_C = 2, K_PR_ANALYSIS = 3, K_PR_ADJOINT = 4,
-                  K_PR_ANALYSIS_C = 5, K_KINDS = 8 };
+                  K_PR_ANALYSIS_C = 5, K_TR_ANALYSIS = 6, K_TR_ADJOINT = 7, K_TR_ANALYSIS_C = 8, K_KINDS = 12 };
 
 // Brackets one launch with timing marks when timed (at most 8 per family).
 template <class F>
@@ -144,49 +144,54 @@ static int timed_launch(muffin_ctx* c, bool timed, int kind, F&& launch) {
 
 static bool use_pairs(const muffin_ctx* c) { return c->gen == 2 && !(c->p.flags & MUFFIN_FLAG_SINGLE_SCALE); }
 
-// The band and pair launches of the two IUWT phases, in order; j is the (finer) scale of a launch.
-// Pairs sit at the finest scales, where their 10 s rows of halo are cheapest: the analysis pairs
-// (0, 1), (2, 3), ... and, for odd J, leaves the coarsest scale alone; the adjoint, which runs from
-// the coarsest scale down, then starts with that scale alone.
+// The band, pair and triple launches of the two IUWT phases, in order; j is the finest scale of a
+// launch.  Consecutive scales are grouped into one launch each, from the finest scale up: J = 1..6
+// gives groups of 1; 2; 3; 2, 2; 3, 2; 3, 3 scales (at J = 4 two pairs move as few bytes as a
+// triple and a single scale, with smaller halos).  The adjoint runs the same groups from the
+// coarsest scale down.
 struct IuwtStep {
   int mode, j;
   const char* name;
 };
 
-static std::vector<IuwtStep> analysis_schedule(const muffin_ctx* c) {
+static std::vector<int> iuwt_groups(const muffin_ctx* c) {
   const int J = c->J;
-  const bool pairs = use_pairs(c), coarse = c->omega_c != 0.f;
+  if (c->gen == 1 || (c->p.flags & MUFFIN_FLAG_SINGLE_SCALE)) return std::vector<int>(J, 1);
+  static const std::vector<int> g[7] = {{}, {1}, {2}, {3}, {2, 2}, {3, 2}, {3, 3}};
+  return g[J];
+}
+
+static std::vector<IuwtStep> analysis_schedule(const muffin_ctx* c) {
+  const bool coarse = c->omega_c != 0.f;
+  const std::vector<int> groups = iuwt_groups(c);
   std::vector<IuwtStep> v;
-  for (int j = 0; j < J;) {
-    if (c->gen == 1) {
-      v.push_back({SM_DETAIL1, j, "analysis"});
-      j += 1;
-    } else if (pairs && j + 1 < J) {
-      v.push_back({(j + 2 == J && coarse) ? PR_ANALYSIS_C : PR_ANALYSIS, j, "analysis pair"});
-      j += 2;
-    } else {
-      v.push_back({(j == J - 1 && coarse) ? DB_ANALYSIS_C : DB_ANALYSIS, j, "analysis"});
-      j += 1;
+  int j = 0;
+  for (size_t k = 0; k < groups.size(); ++k) {
+    const bool last = k + 1 == groups.size() && coarse;
+    switch (groups[k]) {
+      case 3: v.push_back({last ? TR_ANALYSIS_C : TR_ANALYSIS, j, "analysis triple"}); break;
+      case 2: v.push_back({last ? PR_ANALYSIS_C : PR_ANALYSIS, j, "analysis pair"}); break;
+      default:
+        if (c->gen == 1) v.push_back({SM_DETAIL1, j, "analysis"});
+        else v.push_back({last ? DB_ANALYSIS_C : DB_ANALYSIS, j, "analysis"});
     }
+    j += groups[k];
   }
   return v;
 }
 
 static std::vector<IuwtStep> adjoint_schedule(const muffin_ctx* c) {
-  const int J = c->J;
-  const bool pairs = use_pairs(c);
+  const std::vector<int> groups = iuwt_groups(c);
   std::vector<IuwtStep> v;
-  for (int j = J - 1; j >= 0;) {
-    if (c->gen == 1) {
-      v.push_back({SM_SUBADD, j, "adjoint"});
-      j -= 1;
-    } else if (pairs && j >= 1 && !(j == J - 1 && (J & 1))) {
-      v.push_back({PR_ADJOINT, j - 1, "adjoint pair"});
-      j -= 2;
-    } else {
-      v.push_back({DB_ADJOINT, j, "adjoint"});
-      j -= 1;
+  int top = c->J;  // one past the coarsest scale left
+  for (size_t k = groups.size(); k-- > 0;) {
+    const int j = top - groups[k];
+    switch (groups[k]) {
+      case 3: v.push_back({TR_ADJOINT, j, "adjoint triple"}); break;
+      case 2: v.push_back({PR_ADJOINT, j, "adjoint pair"}); break;
+      default: v.push_back({c->gen == 1 ? SM_SUBADD : DB_ADJOINT, j, "adjoint"});
     }
+    top = j;
   }
   return v;
 }
@@ -213,7 +218,14 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omeg
     float* dst = bufs[nb];
     const int j = st.j;
     const float* uj = Ubase + (long long)j * np;
-    if (st.mode == PR_ADJOINT) {
+    if (st.mode == TR_ADJOINT) {
+      // steps j + 2, j + 1, j
+      MF_TRY(timed_launch(c, timed, K_TR_ADJOINT, [&] {
+        return launch_triple(TR_ADJOINT, c->N, c->L, j, pref(Ubase + (long long)(j + 2) * np, ucs),
+                             pref(Ubase + (long long)(j + 1) * np, ucs), pref(uj, ucs), pref(a, acs), pout(dst, np),
+                             PlaneOut{}, PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f, c->st);
+      }));
+    } else if (st.mode == PR_ADJOINT) {
       // steps j + 1 then j
       const float* uh = Ubase + (long long)(j + 1) * np;
       MF_TRY(timed_launch(c, timed, K_PR_ADJOINT, [&] {
@@ -266,6 +278,18 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
         MF_TRY(timed_launch(c, timed, co ? K_PR_ANALYSIS_C : K_PR_ANALYSIS, [&] {
           return launch_pair(st.mode, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
                              pout(uj1, ucs), co ? pout(Uc, ucs) : pout(nxt, np), coef, rho, co ? coefc : 0.f, c->st);
+        }));
+        break;
+      }
+      case TR_ANALYSIS_C:
+      case TR_ANALYSIS: {
+        float* uj1 = c->U + (long long)(j + 1) * np;
+        float* uj2 = c->U + (long long)(j + 2) * np;
+        const bool co = st.mode == TR_ANALYSIS_C;
+        MF_TRY(timed_launch(c, timed, co ? K_TR_ANALYSIS_C : K_TR_ANALYSIS, [&] {
+          return launch_triple(st.mode, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, PlaneRef{},
+                               pout(uj, ucs), pout(uj1, ucs), pout(uj2, ucs), co ? pout(Uc, ucs) : pout(nxt, np), coef,
+                               rho, co ? coefc : 0.f, c->st);
         }));
         break;
       }
@@ -608,6 +632,16 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
           case PR_ANALYSIS_C:
             return launch_pair(mode, c->N, c->L, j, pref(c->X, np), PlaneRef{}, PlaneRef{}, pout(c->cB, np),
                                pout(c->cT, np), pout(c->cA, np), 0.f, 1.f, 0.f, c->st, 1);
+          case TR_ANALYSIS:
+          case TR_ANALYSIS_C:
+            return launch_triple(mode, c->N, c->L, j, pref(c->X, np), PlaneRef{}, PlaneRef{}, PlaneRef{},
+                                 pout(c->cB, np), pout(c->cT, np), pout(c->cA, np), pout(c->D, np), 0.f, 1.f, 0.f,
+                                 c->st, 1);
+          case TR_ADJOINT:
+            return launch_triple(mode, c->N, c->L, j, pref(c->U + (long long)(j + 2) * np, ucs),
+                                 pref(c->U + (long long)(j + 1) * np, ucs), pref(c->U + (long long)j * np, ucs),
+                                 pref(c->cA, np), pout(c->cB, np), PlaneOut{}, PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f,
+                                 c->st, 1);
           case PR_ADJOINT:
             return launch_pair(mode, c->N, c->L, j, pref(c->U + (long long)(j + 1) * np, ucs),
                                pref(c->U + (long long)j * np, ucs), pref(c->cA, np), pout(c->cB, np), PlaneOut{},
@@ -913,9 +947,9 @@ int muffin_step_timed(muffin_ctx* c, int32_t n_iter, double* ms) {
   return MUFFIN_OK;
 }
 
-int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[24]) {
+int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[32]) {
   if (!c || !ms || n_iter < 1) return set_error("bad arguments"), MUFFIN_EINVAL;
-  for (int i = 0; i < 24; ++i) ms[i] = 0;
+  for (int i = 0; i < 32; ++i) ms[i] = 0;
   StreamScope scope(c);
   double ksum[K_KINDS] = {};
   int kcnt[K_KINDS] = {}, fam_iters[3] = {0, 0, 0};
@@ -942,7 +976,7 @@ int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[24]) {
   c->nk = 0;
   for (int k = 0; k < K_KINDS; ++k) {
     if (!kcnt[k]) continue;
-    const int fam = (k == K_DB_ADJOINT || k == K_PR_ADJOINT) ? 1 : 2;
+    const int fam = (k == K_DB_ADJOINT || k == K_PR_ADJOINT || k == K_TR_ADJOINT) ? 1 : 2;
     ms[8 + 2 * k] = ksum[k] / kcnt[k];
     ms[9 + 2 * k] = fam_iters[fam] ? (double)kcnt[k] / fam_iters[fam] : 0.0;
   }

@@ -115,11 +115,19 @@ enum AtrousMode {
   // two consecutive scales j, j+1 in one pass (second generation):
   PR_ANALYSIS = 8,    // A = c_j; out = u_j, out2 = u_{j+1} (dual updates); out3 = c_{j+2} = H_{j+1} H_j c_j
   PR_ANALYSIS_C = 9,  // PR_ANALYSIS with c_{j+2} feeding the coarse plane's dual update (out3, coef2)
-  PR_ADJOINT = 10     // A = u_{j+1}, B = u_j, E = a: out = two Horner steps, scale j+1 then j
+  PR_ADJOINT = 10,    // A = u_{j+1}, B = u_j, E = a: out = two Horner steps, scale j+1 then j
+  // three consecutive scales j, j+1, j+2 in one pass (second generation):
+  TR_ANALYSIS = 11,   // A = c_j; out, out2, out3 = u_j, u_{j+1}, u_{j+2} (dual updates); out4 = c_{j+3}
+  TR_ANALYSIS_C = 12, // TR_ANALYSIS with c_{j+3} feeding the coarse plane's dual update (out4, coef2)
+  TR_ADJOINT = 13     // A = u_{j+2}, B = u_{j+1}, E = u_j, F = a: out = Horner steps j+2, j+1, j
 };
 // launch of a pair kernel: j is the finer scale of the pair
 int launch_pair(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out, PlaneOut out2,
                 PlaneOut out3, float coef, float rho, float coef2, hipStream_t st, int trial = 0);
+// launch of a triple kernel: j is the finest of its three scales
+int launch_triple(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneRef F, PlaneOut out,
+                  PlaneOut out2, PlaneOut out3, PlaneOut out4, float coef, float rho, float coef2, hipStream_t st,
+                  int trial = 0);
 // band height (rows per workgroup) of the band kernels, default or autotuned; set_band_rows records
 // an autotuned choice for (N, j, kernel class of mode)
 int atrous_band_rows(int N, int j, int mode);

@@ -37,8 +37,8 @@ __device__ __forceinline__ double block_sum_atrous(double v) {
 }
 
 struct AtrousArgs {
-  PlaneRef A, B, E;
-  PlaneOut out, out2, out3;
+  PlaneRef A, B, E, F;
+  PlaneOut out, out2, out3, out4;
   int N, j, TX, TY;
   int tiles_x, tiles_per_ch, nblocks;
   float coef, rho, coef2;
@@ -550,6 +550,229 @@ __global__ void __launch_bounds__(1024) k_pair_trial(AtrousArgs a) {
   pair_body<MODE, KR>(a);
 }
 
+// ------------------------------------------------------------------ triples of scales
+// Three consecutive scales j, j + 1, j + 2 in one pass, the same way as the pairs: with s = 2^j,
+// H_j, H_{j+1} and H_{j+2} have their vertical taps 1 and 2, 2 and 4, 4 and 8 class steps apart
+// (windows of 5, 9 and 17 entries), one row per round, four LDS barriers per row.  Load index i of
+// class r is row y0 + r + (i - 22) s.
+//   TR_ANALYSIS:  c1 = H_j c (index t - 2 after loading c(t)), w_j = c - H_j c1 (t - 4),
+//                 c2 = H_{j+1} c1 (t - 6), w_{j+1} = c1 - H_{j+1} c2 (t - 10),
+//                 c3 = H_{j+2} c2 (t - 14), w_{j+2} = c2 - H_{j+2} c3 (t - 22)
+//   TR_ADJOINT:   a1 = u_{j+2} + H_{j+2}(a - H_{j+2} u_{j+2}) (t - 16),
+//                 a2 = u_{j+1} + H_{j+1}(a1 - H_{j+1} u_{j+1}) (t - 20),
+//                 a3 = u_j + H_j(a2 - H_j u_j) (t - 22)
+// As with the pairs, every stage repeats the one-scale kernels' operations in their order.
+struct TriPre {
+  float p0, p1, p2, p3, p4;
+};
+
+template <int MODE>
+__device__ __forceinline__ void triple_body(const AtrousArgs& a) {
+  constexpr bool ADJ = (MODE == TR_ADJOINT);
+  constexpr bool CO = (MODE == TR_ANALYSIS_C);
+  constexpr int HALO = 22;
+  extern __shared__ float sm[];
+  const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
+  float* bA = sm;
+  float* bB = sm + N;
+  float* bC = sm + 2 * N;
+  float* bD = sm + 3 * N;
+  float* bE = sm + 4 * N;
+  float* bF = sm + 5 * N;
+  const int b = xcd_remap(blockIdx.x, a.nblocks);
+  const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
+  const int y0 = band * TY;
+  const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
+  const char* __restrict__ Bp = ADJ ? reinterpret_cast<const char*>(a.B.p + ch * a.B.cs) : nullptr;
+  const char* __restrict__ Ep = ADJ ? reinterpret_cast<const char*>(a.E.p + ch * a.E.cs) : nullptr;
+  const char* __restrict__ Fp = ADJ ? reinterpret_cast<const char*>(a.F.p + ch * a.F.cs) : nullptr;
+  float* __restrict__ O = a.out.p + ch * a.out.cs;
+  float* __restrict__ O2 = ADJ ? nullptr : a.out2.p + ch * a.out2.cs;
+  float* __restrict__ O3 = ADJ ? nullptr : a.out3.p + ch * a.out3.cs;
+  float* __restrict__ O4 = ADJ ? nullptr : a.out4.p + ch * a.out4.cs;
+  auto modx = [&](int v) { return (v % N + N) % N; };
+  const int xm1 = modx(x - s), xm2 = modx(x - 2 * s), xm4 = modx(x - 4 * s), xm8 = modx(x - 8 * s);
+  const int xp1 = modx(x + s), xp2 = modx(x + 2 * s), xp4 = modx(x + 4 * s), xp8 = modx(x + 8 * s);
+  auto h0 = [&](const float* row) { return b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]); };
+  auto h1 = [&](const float* row) { return b3(row[xm4], row[xm2], row[x], row[xp2], row[xp4]); };
+  auto h2 = [&](const float* row) { return b3(row[xm8], row[xm4], row[x], row[xp4], row[xp8]); };
+  const int rowb = N * 4, planeb = N * N * 4, stepb = (s % N) * rowb;
+  const unsigned xb = (unsigned)x * 4u;
+  auto at = [&](const char* base, int off) -> float {
+    return *reinterpret_cast<const float*>(base + off + xb);
+  };
+  auto put = [&](float* base, int y, float v) {
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
+  };
+  auto upd = [&](float u, float w, float coef) { return a.rho * satf(u + coef * w) + (1.f - a.rho) * u; };
+  auto nsteps = [&](int r) -> int {
+    const int v = TY - r;
+    return v > 0 ? ((v + s - 1) >> jj) + 2 * HALO : 0;
+  };
+  auto rowoff = [&](int y) -> int {
+    y %= N;
+    return (y < 0 ? y + N : y) * rowb;
+  };
+  auto adv = [&](int& o) {
+    o += stepb;
+    if (o >= planeb) o -= planeb;
+  };
+  // load streams (load index of step t):
+  //   analysis  p0 c (t), p1 u_j (t - 4), p2 u_{j+1} (t - 10), p3 u_{j+2} (t - 22), p4 coarse (t - 14)
+  //   adjoint   p0 u_{j+2} (t), p1 a (t - 8), p2 u_{j+1} (t - 12), p3 u_j (t - 18)
+  constexpr int D1 = ADJ ? 8 : 4, D2 = ADJ ? 12 : 10, D3 = ADJ ? 18 : 22, D4 = 14;
+  int lr = 0, lt = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0;
+  auto start_class = [&](int r) {
+    const int f = y0 + r - HALO * s;
+    o0 = rowoff(f);
+    o1 = rowoff(f - D1 * s);
+    o2 = rowoff(f - D2 * s);
+    o3 = rowoff(f - D3 * s);
+    if constexpr (CO) o4 = rowoff(f - D4 * s);
+  };
+  auto load_step = [&](TriPre& P) {
+    P.p0 = at(A, o0);
+    if constexpr (ADJ) {
+      P.p1 = at(Fp, o1);
+      P.p2 = at(Bp, o2);
+      P.p3 = at(Ep, o3);
+    } else {
+      P.p1 = at(reinterpret_cast<const char*>(O), o1);
+      P.p2 = at(reinterpret_cast<const char*>(O2), o2);
+      P.p3 = at(reinterpret_cast<const char*>(O3), o3);
+      if constexpr (CO) P.p4 = at(reinterpret_cast<const char*>(O4), o4);
+    }
+    adv(o0);
+    adv(o1);
+    adv(o2);
+    adv(o3);
+    if constexpr (CO) adv(o4);
+  };
+  auto advance_load = [&]() {
+    ++lt;
+    if (lt >= nsteps(lr)) {
+      lt = 0;
+      do {
+        ++lr;
+      } while (lr < s && nsteps(lr) == 0);
+      if (lr < s) start_class(lr);
+    }
+  };
+  // windows, oldest first
+  float w17a[17], w17b[17], w9a[9], w9b[9], w5a[5], w5b[5];
+#pragma unroll
+  for (int i = 0; i < 17; ++i) w17a[i] = w17b[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) w9a[i] = w9b[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) w5a[i] = w5b[i] = 0.f;
+  auto push = [](auto& w, float v) {
+    constexpr int n = sizeof(w) / sizeof(w[0]);
+#pragma unroll
+    for (int i = 0; i < n - 1; ++i) w[i] = w[i + 1];
+    w[n - 1] = v;
+  };
+  auto v17 = [](const float (&w)[17]) { return b3(w[0], w[4], w[8], w[12], w[16]); };
+  auto v9 = [](const float (&w)[9]) { return b3(w[0], w[2], w[4], w[6], w[8]); };
+  auto v5 = [](const float (&w)[5]) { return b3(w[0], w[1], w[2], w[3], w[4]); };
+  // step t of a class with ns steps whose load index 0 is row first
+  auto process = [&](const TriPre& cur, int t, int ns, int first) {
+    if constexpr (ADJ) {
+      // w17a: u_{j+2} (t-16..t), w9a: u_{j+1} (t-20..t-12), w5a: u_j (t-22..t-18),
+      // w17b: a - H_{j+2} u_{j+2} (t-24..t-8), w9b: a1 - H_{j+1} u_{j+1} (t-24..t-16),
+      // w5b: a2 - H_j u_j (t-24..t-20)
+      push(w17a, cur.p0);
+      push(w9a, cur.p2);
+      push(w5a, cur.p3);
+      const float cu2 = w17a[0], cu1 = w9a[0], cu0 = w5a[0];
+      bA[x] = v17(w17a);
+      bC[x] = v9(w9a);
+      bE[x] = v5(w5a);
+      lds_barrier();
+      const float hh1 = h1(bC), hh0 = h0(bE);
+      push(w17b, cur.p1 - h2(bA));
+      bB[x] = v17(w17b);
+      lds_barrier();
+      const float a1 = cu2 + h2(bB);
+      push(w9b, a1 - hh1);
+      bD[x] = v9(w9b);
+      lds_barrier();
+      const float a2 = cu1 + h1(bD);
+      push(w5b, a2 - hh0);
+      bF[x] = v5(w5b);
+      lds_barrier();
+      if (t >= 2 * HALO && t < ns) put(O, first + (t - HALO) * s, cu0 + h0(bF));
+    } else {
+      // w5a: c (t-4..t), w9a: c1 (t-10..t-2), w17a: c2 (t-22..t-6), w17b: c3 (t-30..t-14)
+      push(w5a, cur.p0);
+      const float cc0 = w5a[0];
+      bA[x] = v5(w5a);
+      lds_barrier();
+      push(w9a, h0(bA));
+      const float cc1 = w9a[0];
+      bB[x] = b3(w9a[4], w9a[5], w9a[6], w9a[7], w9a[8]);
+      bC[x] = v9(w9a);
+      lds_barrier();
+      const float wj = cc0 - h0(bB);
+      if (t >= HALO + 4 && t < ns - 18) put(O, first + (t - 4) * s, upd(cur.p1, wj, a.coef));
+      push(w17a, h1(bC));
+      const float cc2 = w17a[0];
+      bD[x] = b3(w17a[8], w17a[10], w17a[12], w17a[14], w17a[16]);
+      bE[x] = v17(w17a);
+      lds_barrier();
+      const float wj1 = cc1 - h1(bD);
+      if (t >= HALO + 10 && t < ns - 12) put(O2, first + (t - 10) * s, upd(cur.p2, wj1, a.coef));
+      const float c3 = h2(bE);
+      if (t >= HALO + 14 && t < ns - 8) {
+        if constexpr (CO) {
+          put(O4, first + (t - 14) * s, upd(cur.p4, c3, a.coef2));
+        } else {
+          put(O4, first + (t - 14) * s, c3);
+        }
+      }
+      push(w17b, c3);
+      bF[x] = v17(w17b);
+      lds_barrier();
+      if (t >= 2 * HALO && t < ns) put(O3, first + (t - HALO) * s, upd(cur.p3, cc2 - h2(bF), a.coef));
+    }
+  };
+  int r = 0;
+  while (r < s && nsteps(r) == 0) ++r;
+  if (r < s) {
+    lr = r;
+    start_class(lr);
+    int pt = 0, pns = nsteps(r), pfirst = y0 + r - HALO * s;
+    TriPre cur, nxt;
+    load_step(cur);
+    advance_load();
+    while (true) {
+      load_step(nxt);  // past the last class: further rows of the planes, unused
+      advance_load();
+      process(cur, pt, pns, pfirst);
+      if (++pt >= pns) {
+        do {
+          ++r;
+        } while (r < s && nsteps(r) == 0);
+        if (r >= s) break;
+        pt = 0;
+        pns = nsteps(r);
+        pfirst = y0 + r - HALO * s;
+      }
+      cur = nxt;
+    }
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(1024) k_triple(AtrousArgs a) {
+  triple_body<MODE>(a);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(1024) k_triple_trial(AtrousArgs a) {
+  triple_body<MODE>(a);
+}
+
 constexpr int kKR = 8;   // rows per round, single-smoothing modes
 constexpr int kKR2 = 4;  // rows per round, double-smoothing modes (keeps them within 128 VGPRs)
 constexpr int kKRP = 2;  // rows per round, pair kernels (keeps them within 128 VGPRs)
@@ -565,6 +788,17 @@ static int band_rows_default(int N, int j) {
 }
 
 static bool is_pair(int mode) { return mode == PR_ANALYSIS || mode == PR_ANALYSIS_C || mode == PR_ADJOINT; }
+static bool is_triple(int mode) { return mode == TR_ANALYSIS || mode == TR_ANALYSIS_C || mode == TR_ADJOINT; }
+
+static int triple_rows_default(int N, int j) {
+  // the triples' halo is 22 s rows on either side: about 128 s rows per band, at least 256
+  int target = 128 << j;
+  if (target < 256) target = 256;
+  int TY = 1;
+  while (TY * 2 <= target && TY * 2 <= N) TY *= 2;
+  while (N % TY) TY >>= 1;
+  return TY;
+}
 
 static int pair_rows_default(int N, int j) {
   // the pairs' halo is 10 s rows on either side: about 64 s rows per band, at least 128
@@ -591,6 +825,9 @@ int atrous_class(int mode) {
     case PR_ANALYSIS:
     case PR_ANALYSIS_C: return 5;
     case PR_ADJOINT: return 6;
+    case TR_ANALYSIS:
+    case TR_ANALYSIS_C: return 7;
+    case TR_ADJOINT: return 8;
     default: return 4;
   }
 }
@@ -599,6 +836,7 @@ int atrous_band_rows(int N, int j, int mode) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(tune_key(N, j, atrous_class(mode)));
   if (it != g_tune.end()) return it->second;
+  if (is_triple(mode)) return triple_rows_default(N, j);
   return is_pair(mode) ? pair_rows_default(N, j) : band_rows_default(N, j);
 }
 
@@ -714,6 +952,52 @@ int launch_pair(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRe
     default:
       if (trial) hipLaunchKernelGGL((k_pair_trial<PR_ADJOINT, kKRP>), grid, block, shm, st, a);
       else hipLaunchKernelGGL((k_pair<PR_ADJOINT, kKRP>), grid, block, shm, st, a);
+      break;
+  }
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+int launch_triple(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneRef F, PlaneOut out,
+                  PlaneOut out2, PlaneOut out3, PlaneOut out4, float coef, float rho, float coef2, hipStream_t st,
+                  int trial) {
+  if (!is_triple(mode)) return set_error("triple: bad mode"), MUFFIN_EINVAL;
+  if (N > 1024) return set_error("triple: N > 1024"), MUFFIN_EINVAL;
+  AtrousArgs a{};
+  a.A = A;
+  a.B = B;
+  a.E = E;
+  a.F = F;
+  a.out = out;
+  a.out2 = out2;
+  a.out3 = out3;
+  a.out4 = out4;
+  a.N = N;
+  a.j = j;
+  a.coef = coef;
+  a.rho = rho;
+  a.coef2 = coef2;
+  a.TX = N;
+  a.TY = atrous_band_rows(N, j, mode);
+  a.tiles_x = 1;
+  a.tiles_per_ch = N / a.TY;
+  const long long nb = (long long)a.tiles_per_ch * nch;
+  if (nb > 0x7fffffffLL) return set_error("triple: grid too large"), MUFFIN_EINVAL;
+  a.nblocks = (int)nb;
+  const size_t shm = sizeof(float) * (size_t)6 * N;
+  const dim3 grid((unsigned)nb), block((unsigned)N);
+  switch (mode) {
+    case TR_ANALYSIS:
+      if (trial) hipLaunchKernelGGL((k_triple_trial<TR_ANALYSIS>), grid, block, shm, st, a);
+      else hipLaunchKernelGGL((k_triple<TR_ANALYSIS>), grid, block, shm, st, a);
+      break;
+    case TR_ANALYSIS_C:
+      if (trial) hipLaunchKernelGGL((k_triple_trial<TR_ANALYSIS_C>), grid, block, shm, st, a);
+      else hipLaunchKernelGGL((k_triple<TR_ANALYSIS_C>), grid, block, shm, st, a);
+      break;
+    default:
+      if (trial) hipLaunchKernelGGL((k_triple_trial<TR_ADJOINT>), grid, block, shm, st, a);
+      else hipLaunchKernelGGL((k_triple<TR_ADJOINT>), grid, block, shm, st, a);
       break;
   }
   MF_HIP(hipGetLastError());

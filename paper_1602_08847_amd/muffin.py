@@ -184,7 +184,7 @@ class Muffin:
         return ms.value
 
     def profile(self, n: int) -> np.ndarray:
-        out = (ctypes.c_double * 24)()
+        out = (ctypes.c_double * 32)()
         _check(_lib.muffin_profile(self._h, n, out), "muffin_profile")
         return np.array(out[:])
 

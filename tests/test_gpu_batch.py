@@ -51,10 +51,9 @@ def test_autotune_keeps_results_and_reports_choices(lib, cubes):
         xa = a.get_x().cpu().numpy()
     with lib.Muffin(c.dirty, c.psf, J=3, mu_s=0.25, mu_lambda=3.0) as t:
         rep = json.loads(t.autotune(reps=2))
-        # J = 3: analysis scales (0, 1) as a pair and 2 alone; adjoint step 2 alone, then (1, 0) as a pair
-        assert rep["N"] == 128 and len(rep["scales"]) == 4
-        assert [(s["j"], s["kernel"]) for s in rep["scales"]] == [
-            (0, "analysis pair"), (2, "analysis"), (2, "adjoint"), (0, "adjoint pair")]
+        # J = 3: the three analysis scales in one launch, the three adjoint steps in another
+        assert rep["N"] == 128 and len(rep["scales"]) == 2
+        assert [(s["j"], s["kernel"]) for s in rep["scales"]] == [(0, "analysis triple"), (0, "adjoint triple")]
         for s in rep["scales"]:
             assert 128 % s["rows"] == 0 and str(s["rows"]) in s["candidates_ms"]
         t.step(6)

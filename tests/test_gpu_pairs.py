@@ -1,7 +1,8 @@
-"""Two IUWT scales per launch against one scale per launch: the fused pair kernels perform the same
-operations in the same order, so the iterates agree bit for bit, for odd and even J (the schedule
-then ends in a single scale or a pair), with and without the coarse plane's penalty, with
-relaxation, and for image sides where the coarse taps wrap around the image several times."""
+"""Two or three IUWT scales per launch against one scale per launch: the fused pair and triple kernels
+perform the same operations in the same order, so the iterates agree bit for bit, for every J
+(schedules of singles, pairs and triples, each with or without the coarse plane), with and without
+the coarse plane's penalty, with relaxation, and for image sides where the coarse taps wrap around
+the image several times."""
 import numpy as np
 import pytest
 
@@ -48,13 +49,16 @@ def test_pairs_autotuned_match_single_scale(lib):
         np.testing.assert_array_equal(a.get_u().cpu().numpy(), b.get_u().cpu().numpy())
 
 
-@pytest.mark.parametrize("J,counts", [(5, {1: 1, 2: 1, 3: 2, 4: 2}), (4, {3: 1, 4: 2, 5: 1})])
+# launch kinds: 0 one analysis scale, 1 one adjoint step, 2 last analysis scale with the coarse plane,
+# 3/4/5 the same for pairs, 6/7/8 for triples
+@pytest.mark.parametrize("J,counts", [(5, {6: 1, 5: 1, 4: 1, 7: 1}), (4, {3: 1, 4: 2, 5: 1}),
+                                      (3, {8: 1, 7: 1}), (6, {6: 1, 8: 1, 7: 2}), (1, {2: 1, 1: 1})])
 def test_profile_reports_the_launch_schedule(lib, J, counts):
-    c = synth.make_cube(synth.CubeSpec(N=64, L=4, J=J, n_sources=3, n_baselines=100, seed=2))
+    c = synth.make_cube(synth.CubeSpec(N=128, L=4, J=J, n_sources=3, n_baselines=100, seed=2))
     with lib.Muffin(c.dirty, c.psf, J=J, mu_s=0.25, mu_lambda=3.0) as m:
         ms = m.profile(4)
-    assert np.all(ms[5:8] == 0)
-    for k in range(8):
+    assert len(ms) == 32 and np.all(ms[5:8] == 0)
+    for k in range(12):
         assert ms[9 + 2 * k] == counts.get(k, 0), (k, ms)
         assert (ms[8 + 2 * k] > 0) == (k in counts)
     assert ms[0] == pytest.approx(sum(ms[1:5]), rel=1e-6)
