@@ -571,6 +571,9 @@ __device__ __forceinline__ void triple_body(const AtrousArgs& a) {
   constexpr bool ADJ = (MODE == TR_ADJOINT);
   constexpr bool CO = (MODE == TR_ANALYSIS_C);
   constexpr int HALO = 22;
+  // the adjoint runs its four stages skewed over four consecutive steps (one barrier per step,
+  // double-buffered LDS); the analysis runs them one after the other within a step
+  constexpr int SKEW = ADJ ? 4 : 0;
   extern __shared__ float sm[];
   const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
   float* bA = sm;
@@ -605,9 +608,11 @@ __device__ __forceinline__ void triple_body(const AtrousArgs& a) {
     *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
   };
   auto upd = [&](float u, float w, float coef) { return a.rho * satf(u + coef * w) + (1.f - a.rho) * u; };
+  // steps of class r: its M rows plus the halo on both sides, plus SKEW steps that drain the
+  // skewed stages
   auto nsteps = [&](int r) -> int {
     const int v = TY - r;
-    return v > 0 ? ((v + s - 1) >> jj) + 2 * HALO : 0;
+    return v > 0 ? ((v + s - 1) >> jj) + 2 * HALO + SKEW : 0;
   };
   auto rowoff = [&](int y) -> int {
     y %= N;
@@ -675,33 +680,56 @@ __device__ __forceinline__ void triple_body(const AtrousArgs& a) {
   auto v17 = [](const float (&w)[17]) { return b3(w[0], w[4], w[8], w[12], w[16]); };
   auto v9 = [](const float (&w)[9]) { return b3(w[0], w[2], w[4], w[6], w[8]); };
   auto v5 = [](const float (&w)[5]) { return b3(w[0], w[1], w[2], w[3], w[4]); };
+  // delay lines of the skewed adjoint: value of step T - 1 first
+  float dA[1] = {0.f}, dC[1] = {0.f}, dE[2] = {0.f, 0.f};
+  float dU2[2] = {0.f, 0.f}, dU1[3] = {0.f, 0.f, 0.f}, dU0[4] = {0.f, 0.f, 0.f, 0.f};
+  auto delay = [](auto& d, float v) -> float {  // returns the value of D steps ago, stores v
+    constexpr int n = sizeof(d) / sizeof(d[0]);
+    const float out = d[n - 1];
+#pragma unroll
+    for (int i = n - 1; i > 0; --i) d[i] = d[i - 1];
+    d[0] = v;
+    return out;
+  };
+  int par = 0;  // LDS parity of the skewed adjoint
   // step t of a class with ns steps whose load index 0 is row first
   auto process = [&](const TriPre& cur, int t, int ns, int first) {
     if constexpr (ADJ) {
-      // w17a: u_{j+2} (t-16..t), w9a: u_{j+1} (t-20..t-12), w5a: u_j (t-22..t-18),
-      // w17b: a - H_{j+2} u_{j+2} (t-24..t-8), w9b: a1 - H_{j+1} u_{j+1} (t-24..t-16),
-      // w5b: a2 - H_j u_j (t-24..t-20)
+      // At step T: stage 1 of step T, stage 2 of T - 1, stage 3 of T - 2, stage 4 of T - 3 and the
+      // output of T - 4, where step t is the one-step-per-stage schedule's step t:
+      //   w17a: u_{j+2} (t-16..t), w9a: u_{j+1} (t-20..t-12), w5a: u_j (t-22..t-18),
+      //   w17b: a - H_{j+2} u_{j+2} (t-24..t-8), w9b: a1 - H_{j+1} u_{j+1} (t-24..t-16),
+      //   w5b: a2 - H_j u_j (t-24..t-20)
+      float* wr = sm + par * 6 * N;        // written this step
+      float* rd = sm + (par ^ 1) * 6 * N;  // written last step
+      const float hA = h2(rd), hC = h1(rd + 2 * N), hE = h0(rd + 4 * N);  // stage 1 of T - 1
+      const float gB = h2(rd + N);      // stage 2 of T - 2
+      const float gD = h1(rd + 3 * N);  // stage 3 of T - 3
+      const float gF = h0(rd + 5 * N);  // stage 4 of T - 4
+      // stage 1, step T
       push(w17a, cur.p0);
       push(w9a, cur.p2);
       push(w5a, cur.p3);
-      const float cu2 = w17a[0], cu1 = w9a[0], cu0 = w5a[0];
-      bA[x] = v17(w17a);
-      bC[x] = v9(w9a);
-      bE[x] = v5(w5a);
+      wr[x] = v17(w17a);
+      wr[2 * N + x] = v9(w9a);
+      wr[4 * N + x] = v5(w5a);
+      // stage 2, step T - 1: a - H_{j+2} u_{j+2}
+      push(w17b, delay(dA, cur.p1) - hA);
+      wr[N + x] = v17(w17b);
+      // stage 3, step T - 2: a1 = u_{j+2} + H_{j+2}(...), then a1 - H_{j+1} u_{j+1}
+      const float a1 = delay(dU2, w17a[0]) + gB;
+      push(w9b, a1 - delay(dC, hC));
+      wr[3 * N + x] = v9(w9b);
+      // stage 4, step T - 3: a2 = u_{j+1} + H_{j+1}(...), then a2 - H_j u_j
+      const float a2 = delay(dU1, w9a[0]) + gD;
+      push(w5b, a2 - delay(dE, hE));
+      wr[5 * N + x] = v5(w5b);
+      // output, step T - 4: u_j + H_j(...)
+      const float out = delay(dU0, w5a[0]) + gF;
+      const int to = t - SKEW;
+      if (to >= 2 * HALO && to < ns - SKEW) put(O, first + (to - HALO) * s, out);
       lds_barrier();
-      const float hh1 = h1(bC), hh0 = h0(bE);
-      push(w17b, cur.p1 - h2(bA));
-      bB[x] = v17(w17b);
-      lds_barrier();
-      const float a1 = cu2 + h2(bB);
-      push(w9b, a1 - hh1);
-      bD[x] = v9(w9b);
-      lds_barrier();
-      const float a2 = cu1 + h1(bD);
-      push(w5b, a2 - hh0);
-      bF[x] = v5(w5b);
-      lds_barrier();
-      if (t >= 2 * HALO && t < ns) put(O, first + (t - HALO) * s, cu0 + h0(bF));
+      par ^= 1;
     } else {
       // w5a: c (t-4..t), w9a: c1 (t-10..t-2), w17a: c2 (t-22..t-6), w17b: c3 (t-30..t-14)
       push(w5a, cur.p0);
@@ -984,7 +1012,7 @@ int launch_triple(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   const long long nb = (long long)a.tiles_per_ch * nch;
   if (nb > 0x7fffffffLL) return set_error("triple: grid too large"), MUFFIN_EINVAL;
   a.nblocks = (int)nb;
-  const size_t shm = sizeof(float) * (size_t)6 * N;
+  const size_t shm = sizeof(float) * (size_t)(mode == TR_ADJOINT ? 12 : 6) * N;
   const dim3 grid((unsigned)nb), block((unsigned)N);
   switch (mode) {
     case TR_ANALYSIS:
