@@ -70,11 +70,20 @@ PROFILE_SLOT = {
 # iteration, times the factor a 1 GiB elementwise copy (--calib-copy) gives for the same counter.
 # An entry holds only for the kernel sources it was taken on (hash below); otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "k_pair<PR_ANALYSIS> (two scales of analysis + spatial dual steps)": {
+    "k_triple<TR_ANALYSIS> (three scales of analysis + spatial dual steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h"],
-        "sha256": "4bf7d4e3c0dc78aa",
-        "fetch_kib": 1732655.5,
+        "sha256": "0e5f2affaf649e0a",
+        "fetch_kib": 2189370.1,
+        "write_kib": 4194304.0,
+        "fetch_factor": 2.0,
+        "write_factor": 1.0,
+    },
+    "k_pair<PR_ANALYSIS_C> (last two analysis scales + spatial and coarse dual steps)": {
+        "workload": "cube1024_L256_J5",
+        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h"],
+        "sha256": "0e5f2affaf649e0a",
+        "fetch_kib": 2428977.5,
         "write_kib": 3145728.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0,
@@ -82,26 +91,17 @@ MEASURED_TRAFFIC = {
     "k_pair<PR_ADJOINT> (two adjoint Horner steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h"],
-        "sha256": "4bf7d4e3c0dc78aa",
-        "fetch_kib": 1669683.1,
+        "sha256": "0e5f2affaf649e0a",
+        "fetch_kib": 1821747.5,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0,
     },
-    "k_band<DB_ANALYSIS_C> (last scale of analysis + spatial and coarse dual steps)": {
+    "k_triple<TR_ADJOINT> (three adjoint Horner steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h"],
-        "sha256": "4bf7d4e3c0dc78aa",
-        "fetch_kib": 2293573.4,
-        "write_kib": 2097152.0,
-        "fetch_factor": 2.0,
-        "write_factor": 1.0,
-    },
-    "k_band<DB_ADJOINT> (one scale of the adjoint Horner step)": {
-        "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h"],
-        "sha256": "4bf7d4e3c0dc78aa",
-        "fetch_kib": 1183791.5,
+        "sha256": "0e5f2affaf649e0a",
+        "fetch_kib": 2197557.0,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0,
@@ -109,8 +109,8 @@ MEASURED_TRAFFIC = {
     "k_spectral_fft (fused spectral step)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/spectral.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/fft_core.h"],
-        "sha256": "dd87dc98b7c9b8e4",
-        "fetch_kib": 1573093.4,
+        "sha256": "df0c3580a66062d7",
+        "fetch_kib": 1573108.1,
         "write_kib": 3145728.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0,
