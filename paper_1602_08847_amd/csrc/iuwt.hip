@@ -45,8 +45,16 @@ struct AtrousArgs {
   double* partial;
 };
 
+// The rounding of the filter and of the dual update is written out (the power-of-two weights scale
+// exactly, the 3/8 tap and the step are fused): every kernel, whichever way the compiler lays out its
+// inlined copies, then rounds them alike, which keeps the one-scale and fused launches bit-identical.
 __device__ __forceinline__ float b3(float c0, float c1, float c2, float c3, float c4) {
-  return 0.0625f * (c0 + c4) + 0.25f * (c1 + c3) + 0.375f * c2;
+  return __builtin_fmaf(0.375f, c2, 0.0625f * (c0 + c4) + 0.25f * (c1 + c3));
+}
+
+// relaxed dual update rho * sat(u + coef w) + (1 - rho) u
+__device__ __forceinline__ float dual_upd(float u, float w, float coef, float rho) {
+  return __builtin_fmaf(rho, satf(__builtin_fmaf(coef, w, u)), (1.f - rho) * u);
 }
 
 // Band kernel: one workgroup of N threads owns rows [y0, y0 + TY) of one channel, thread x owns
@@ -194,7 +202,7 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
           const float e = (MODE == SM_DETAIL) ? cur.e[kk] : cen1[kk];
           const float w = e - v;
           const float u = cur.u[kk];
-          put(O, y, a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u);
+          put(O, y, dual_upd(u, w, a.coef, a.rho));
           if (MODE == SM_DETAIL1) put(O2, y, v);
         } else {
           acc += fabs((double)cur.e[kk] - (double)v);
@@ -212,7 +220,7 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
           if (m >= 0 && t0 + kk < ns && y >= y0 && y < y1) {
             if constexpr (MODE == DB_ANALYSIS_C) {
               const float u2 = cur.u2[kk];
-              put(O2, y, a.rho * satf(u2 + a.coef2 * qin) + (1.f - a.rho) * u2);
+              put(O2, y, dual_upd(u2, qin, a.coef2, a.rho));
             } else {
               put(O2, y, qin);
             }
@@ -239,7 +247,7 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
         } else {
           const float w = cen2[kk] - R;
           const float u = cur.u[kk];
-          put(O, y, a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u);
+          put(O, y, dual_upd(u, w, a.coef, a.rho));
         }
       }
     }
@@ -341,7 +349,7 @@ __device__ __forceinline__ void pair_body(const AtrousArgs& a) {
   auto put = [&](float* base, int y, float v) {
     *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
   };
-  auto upd = [&](float u, float w, float coef) { return a.rho * satf(u + coef * w) + (1.f - a.rho) * u; };
+  auto upd = [&](float u, float w, float coef) { return dual_upd(u, w, coef, a.rho); };
   auto nsteps = [&](int r) -> int {
     const int v = TY - r;
     return v > 0 ? ((v + s - 1) >> jj) + 2 * HALO : 0;
@@ -607,7 +615,7 @@ __device__ __forceinline__ void triple_body(const AtrousArgs& a) {
   auto put = [&](float* base, int y, float v) {
     *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
   };
-  auto upd = [&](float u, float w, float coef) { return a.rho * satf(u + coef * w) + (1.f - a.rho) * u; };
+  auto upd = [&](float u, float w, float coef) { return dual_upd(u, w, coef, a.rho); };
   // steps of class r: its M rows plus the halo on both sides, plus SKEW steps that drain the
   // skewed stages
   auto nsteps = [&](int r) -> int {
@@ -770,23 +778,52 @@ __device__ __forceinline__ void triple_body(const AtrousArgs& a) {
     lr = r;
     start_class(lr);
     int pt = 0, pns = nsteps(r), pfirst = y0 + r - HALO * s;
-    TriPre cur, nxt;
-    load_step(cur);
-    advance_load();
-    while (true) {
-      load_step(nxt);  // past the last class: further rows of the planes, unused
-      advance_load();
-      process(cur, pt, pns, pfirst);
+    auto next_step = [&]() -> bool {  // false when the band is done
       if (++pt >= pns) {
         do {
           ++r;
         } while (r < s && nsteps(r) == 0);
-        if (r >= s) break;
+        if (r >= s) return false;
         pt = 0;
         pns = nsteps(r);
         pfirst = y0 + r - HALO * s;
       }
-      cur = nxt;
+      return true;
+    };
+    if constexpr (ADJ) {
+      // loads one step ahead (two would not fit the adjoint's registers)
+      TriPre cur, nxt;
+      load_step(cur);
+      advance_load();
+      while (true) {
+        load_step(nxt);  // past the last class: further rows of the planes, unused
+        advance_load();
+        process(cur, pt, pns, pfirst);
+        if (!next_step()) break;
+        cur = nxt;
+      }
+      return;
+    }
+    // loads run two steps ahead of the computation; the loop is unrolled three times so the three
+    // buffers keep fixed roles and no register copy waits for a load in flight
+    TriPre q0, q1, q2;
+    load_step(q0);
+    advance_load();
+    load_step(q1);
+    advance_load();
+    while (true) {
+      load_step(q2);  // past the last class: further rows of the planes, unused
+      advance_load();
+      process(q0, pt, pns, pfirst);
+      if (!next_step()) break;
+      load_step(q0);
+      advance_load();
+      process(q1, pt, pns, pfirst);
+      if (!next_step()) break;
+      load_step(q1);
+      advance_load();
+      process(q2, pt, pns, pfirst);
+      if (!next_step()) break;
     }
   }
 }
@@ -1087,7 +1124,7 @@ __global__ void __launch_bounds__(256) k_point(PointArgs a) {
       const float w = (MODE == PT_DETAIL1) ? a.E.p[ch * a.E.cs + i] - A[i] : A[i];
       float* up = a.out.p + ch * a.out.cs + i;
       const float u = *up;
-      *up = a.rho * satf(u + a.coef * w) + (1.f - a.rho) * u;
+      *up = dual_upd(u, w, a.coef, a.rho);
     } else if constexpr (MODE == PT_ABS_DIFF) {
       acc += fabs((double)a.E.p[ch * a.E.cs + i] - (double)A[i]);
     } else if constexpr (MODE == PT_ABS) {
