@@ -72,49 +72,49 @@ PROFILE_SLOT = {
 MEASURED_TRAFFIC = {
     "k_triple<TR_ANALYSIS> (three scales of analysis + spatial dual steps)": {
         "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h"],
-        "sha256": "0e5f2affaf649e0a",
-        "fetch_kib": 2189370.1,
+        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
+        "sha256": "48b3f0079106265a",
+        "fetch_kib": 2191452.4,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
-        "write_factor": 1.0,
+        "write_factor": 1.0
     },
     "k_pair<PR_ANALYSIS_C> (last two analysis scales + spatial and coarse dual steps)": {
         "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h"],
-        "sha256": "0e5f2affaf649e0a",
+        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
+        "sha256": "48b3f0079106265a",
         "fetch_kib": 2428977.5,
         "write_kib": 3145728.0,
         "fetch_factor": 2.0,
-        "write_factor": 1.0,
+        "write_factor": 1.0
     },
     "k_pair<PR_ADJOINT> (two adjoint Horner steps)": {
         "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h"],
-        "sha256": "0e5f2affaf649e0a",
+        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
+        "sha256": "48b3f0079106265a",
         "fetch_kib": 1821747.5,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
-        "write_factor": 1.0,
+        "write_factor": 1.0
     },
     "k_triple<TR_ADJOINT> (three adjoint Horner steps)": {
         "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h"],
-        "sha256": "0e5f2affaf649e0a",
-        "fetch_kib": 2197557.0,
+        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
+        "sha256": "48b3f0079106265a",
+        "fetch_kib": 2197551.5,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
-        "write_factor": 1.0,
+        "write_factor": 1.0
     },
     "k_spectral_fft (fused spectral step)": {
         "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/spectral.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/fft_core.h"],
-        "sha256": "df0c3580a66062d7",
-        "fetch_kib": 1573108.1,
+        "sources": ["paper_1602_08847_amd/csrc/spectral.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/fft_core.h", "paper_1602_08847_amd/csrc/api.hip"],
+        "sha256": "418885c69537c3f6",
+        "fetch_kib": 1573123.2,
         "write_kib": 3145728.0,
         "fetch_factor": 2.0,
-        "write_factor": 1.0,
-    },
+        "write_factor": 1.0
+    }
 }
 
 

@@ -26,9 +26,9 @@ int spectral_init_attrs(int L);
 int launch_power_spectrum(const float2* Hhat_T, float* P_T, const float* chan_w, long long per_ch, int nch,
                           float scale, hipStream_t st);
 int launch_clamp_pos(float* x, long long n, hipStream_t st);
-int launch_scale_channels(float* x, const float* chan_w, long long npix, int nch, hipStream_t st);
-int cnn_warm_input(const float* Y, const float* scale, float* out, int N, int L, hipStream_t st);
-int launch_psf_lobe(const float* psf, float* out, int N, int L, int radius, hipStream_t st);
+int launch_scale_channels(float* x, const float* chan_w, long long npix, long long cs, int nch, hipStream_t st);
+int cnn_warm_input(const float* Y, long long cs, const float* scale, float* out, int N, int L, hipStream_t st);
+int launch_psf_lobe(const float* psf, long long cs, float* out, int N, int L, int radius, hipStream_t st);
 }  // namespace mf
 
 using namespace mf;
@@ -48,7 +48,13 @@ struct muffin_ctx {
   std::vector<Seg> segs;
   std::vector<float> chan_w_host;
   int N = 0, L = 0, J = 0, gen = 2;
-  long long npix = 0, cube = 0;
+  // Every N x N plane of the cube buffers sits in a slot of cs floats: N^2 plus one row, rounded up
+  // to 32 floats, plus 32 more (128 bytes).  The spectral step walks each pixel across all the
+  // channels; with planes a power of two apart those accesses fall on few HBM channels, and the
+  // extra 128 bytes spread them (at 1024^2 x 256 the step runs 1.8 -> 1.4 ms, while the row-wise
+  // IUWT kernels keep their speed).  cube = cs * L.  The planes of U, which are only walked row by
+  // row, are us floats apart (ucube = us * L * (J + 1)).
+  long long npix = 0, cs = 0, cube = 0, us = 0, ucube = 0;
   FftGeom g;
   int device = 0;
   hipStream_t user = nullptr, st = nullptr;
@@ -199,11 +205,12 @@ static std::vector<IuwtStep> adjoint_schedule(const muffin_ctx* c) {
 // Spatial adjoint of omega-weighted U; returns the buffer holding a = W_s^dagger (omega u).
 // Second generation: Horner steps a <- u_j + H_j (a - H_j u_j) from the coarsest scale down, two
 // scales per launch where possible.
-int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omega_c, const float** result,
-                    bool timed = false) {
+// Ubase: plane j of channel l at Ubase + l ucs + j ups.  The result has channel stride cs.
+int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ups, long long ucs, float omega_c,
+                    const float** result, bool timed = false) {
   const int J = c->J;
-  const long long np = c->npix;
-  const float* a = Ubase + (long long)J * np;  // coarse plane
+  const long long np = c->cs;
+  const float* a = Ubase + (long long)J * ups;  // coarse plane
   long long acs = ucs;
   float* bufs[2] = {c->cA, c->cB};
   int nb = 0;
@@ -217,17 +224,17 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omeg
   for (const IuwtStep& st : adjoint_schedule(c)) {
     float* dst = bufs[nb];
     const int j = st.j;
-    const float* uj = Ubase + (long long)j * np;
+    const float* uj = Ubase + (long long)j * ups;
     if (st.mode == TR_ADJOINT) {
       // steps j + 2, j + 1, j
       MF_TRY(timed_launch(c, timed, K_TR_ADJOINT, [&] {
-        return launch_triple(TR_ADJOINT, c->N, c->L, j, pref(Ubase + (long long)(j + 2) * np, ucs),
-                             pref(Ubase + (long long)(j + 1) * np, ucs), pref(uj, ucs), pref(a, acs), pout(dst, np),
+        return launch_triple(TR_ADJOINT, c->N, c->L, j, pref(Ubase + (long long)(j + 2) * ups, ucs),
+                             pref(Ubase + (long long)(j + 1) * ups, ucs), pref(uj, ucs), pref(a, acs), pout(dst, np),
                              PlaneOut{}, PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f, c->st);
       }));
     } else if (st.mode == PR_ADJOINT) {
       // steps j + 1 then j
-      const float* uh = Ubase + (long long)(j + 1) * np;
+      const float* uh = Ubase + (long long)(j + 1) * ups;
       MF_TRY(timed_launch(c, timed, K_PR_ADJOINT, [&] {
         return launch_pair(PR_ADJOINT, c->N, c->L, j, pref(uh, ucs), pref(uj, ucs), pref(a, acs), pout(dst, np),
                            PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f, c->st);
@@ -249,23 +256,23 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ucs, float omeg
   return MUFFIN_OK;
 }
 
-// Analysis of the channel images in (stride np) fused with the spatial dual step on U; second
+// Analysis of the channel images in (stride cs) fused with the spatial dual step on U; second
 // generation: two scales per launch where possible, the last one feeding the coarse plane's step.
 int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
   const int J = c->J;
-  const long long np = c->npix, ucs = (long long)(J + 1) * np;
+  const long long np = c->cs, us = c->us, ucs = (long long)(J + 1) * us;
   const float coef = (float)(c->sigma * c->p.mu_s);
   const float rho = (float)c->rho;
   const float coefc = coef * c->omega_c;
   const bool coarse = c->omega_c != 0.f;  // with omega = 0 on the coarse plane its dual stays put
-  float* Uc = c->U + (long long)J * np;
+  float* Uc = c->U + (long long)J * us;
   const float* cur = in;
   float* bufs[2] = {c->cA, c->cB};
   int nb = 0;
   for (const IuwtStep& st : analysis_schedule(c)) {
     float* nxt = bufs[nb];
     const int j = st.j;
-    float* uj = c->U + (long long)j * np;
+    float* uj = c->U + (long long)j * us;
     switch (st.mode) {
       case SM_DETAIL1:
         MF_TRY(launch_atrous(SM_DETAIL1, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
@@ -273,7 +280,7 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
         break;
       case PR_ANALYSIS_C:
       case PR_ANALYSIS: {
-        float* uj1 = c->U + (long long)(j + 1) * np;
+        float* uj1 = c->U + (long long)(j + 1) * us;
         const bool co = st.mode == PR_ANALYSIS_C;
         MF_TRY(timed_launch(c, timed, co ? K_PR_ANALYSIS_C : K_PR_ANALYSIS, [&] {
           return launch_pair(st.mode, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
@@ -283,8 +290,8 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
       }
       case TR_ANALYSIS_C:
       case TR_ANALYSIS: {
-        float* uj1 = c->U + (long long)(j + 1) * np;
-        float* uj2 = c->U + (long long)(j + 2) * np;
+        float* uj1 = c->U + (long long)(j + 1) * us;
+        float* uj2 = c->U + (long long)(j + 2) * us;
         const bool co = st.mode == TR_ANALYSIS_C;
         MF_TRY(timed_launch(c, timed, co ? K_TR_ANALYSIS_C : K_TR_ANALYSIS, [&] {
           return launch_triple(st.mode, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, PlaneRef{},
@@ -315,16 +322,16 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
 }
 
 int enqueue_gradient(muffin_ctx* c, const float* x, float* out, const float* s, float s_scale) {
-  MF_TRY(launch_rows_r2c(x, c->S, c->L, c->g, c->tw, false, c->st));
+  MF_TRY(launch_rows_r2c(x, c->cs, c->S, c->L, c->g, c->tw, false, c->st));
   MF_TRY(launch_cols(c->S, c->L, c->g, c->tw, COL_REAL, c->P_T, nullptr, 1.f, nullptr, c->st));
-  MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_GRAD, out, c->B, s, s_scale, nullptr, nullptr, nullptr,
+  MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_GRAD, out, c->cs, c->B, s, s_scale, nullptr, nullptr, nullptr,
                          nullptr, c->st));
   return MUFFIN_OK;
 }
 
 int enqueue_spectral(muffin_ctx* c) {
   for (const Seg& s : c->segs) {
-    const long long off = (long long)s.ch0 * c->npix;
+    const long long off = (long long)s.ch0 * c->cs;
     SpectralArgs a;
     a.X = c->X + off;
     a.Q = c->Q + off;
@@ -335,6 +342,7 @@ int enqueue_spectral(muffin_ctx* c) {
     a.twL = s.twL;
     a.csL = s.csL;
     a.npix = c->npix;
+    a.cs = c->cs;
     a.L = s.L;
     a.use_fft = spectral_has_fft(s.L) ? 1 : 0;
     a.tau = (float)s.tau;
@@ -349,10 +357,10 @@ int enqueue_spectral(muffin_ctx* c) {
 // With marks, phase boundaries are recorded in marks[0..4] and, for the second-generation
 // transform, each scale's fused adjoint (marks pass 1) or analysis launch is bracketed in kev.
 int enqueue_iteration(muffin_ctx* c, hipEvent_t* marks, int timed_family = 0) {
-  const long long ucs = (long long)(c->J + 1) * c->npix;
+  const long long ucs = (long long)(c->J + 1) * c->us;
   if (marks) MF_HIP(hipEventRecord(marks[0], c->st));
   const float* s = nullptr;
-  MF_TRY(enqueue_adjoint(c, c->U, ucs, c->omega_c, &s, timed_family == 1));
+  MF_TRY(enqueue_adjoint(c, c->U, c->us, ucs, c->omega_c, &s, timed_family == 1));
   if (marks) MF_HIP(hipEventRecord(marks[1], c->st));
   MF_TRY(enqueue_gradient(c, c->X, c->Q, s, (float)c->p.mu_s));
   if (marks) MF_HIP(hipEventRecord(marks[2], c->st));
@@ -366,15 +374,15 @@ int enqueue_iteration(muffin_ctx* c, hipEvent_t* marks, int timed_family = 0) {
 // Objective terms of segment si at X into dres[1..3] (data, spatial l1 unweighted by mu_s, spectral l1).
 int enqueue_objective(muffin_ctx* c, int si) {
   const Seg& s = c->segs[si];
-  const long long np = c->npix, off = (long long)s.ch0 * np;
+  const long long np = c->cs, off = (long long)s.ch0 * np;
   const int nch = s.L;
   float* X = c->X + off;
   MF_HIP(hipMemsetAsync(c->dres, 0, sizeof(double) * 4, c->st));
   int nb = 0;
-  MF_TRY(launch_rows_r2c(X, c->S, nch, c->g, c->tw, false, c->st));
+  MF_TRY(launch_rows_r2c(X, np, c->S, nch, c->g, c->tw, false, c->st));
   MF_TRY(launch_cols(c->S, nch, c->g, c->tw, COL_CPLX, nullptr, c->Hhat_T + (long long)s.ch0 * c->g.pitch * c->N,
                      1.f / ((float)c->N * c->N), nullptr, c->st));
-  MF_TRY(launch_rows_c2r(c->S, nch, c->g, c->tw, EPI_RESID, nullptr, nullptr, nullptr, 0.f, c->Y + off,
+  MF_TRY(launch_rows_c2r(c->S, nch, c->g, c->tw, EPI_RESID, nullptr, np, nullptr, nullptr, 0.f, c->Y + off,
                          c->chan_w ? c->chan_w + s.ch0 : nullptr, c->partial, &nb, c->st));
   MF_TRY(launch_reduce_sum(c->partial, nb, c->dres + 1, 0, c->st));
   const float* cur = X;
@@ -397,7 +405,7 @@ int enqueue_objective(muffin_ctx* c, int si) {
                             c->st));
     MF_TRY(launch_reduce_sum(c->partial, nb, c->dres + 2, 1, c->st));
   }
-  MF_TRY(launch_dct_abs(X, s.WT, np, nch, c->partial, &nb, c->st));
+  MF_TRY(launch_dct_abs(X, s.WT, c->npix, np, nch, c->partial, &nb, c->st));
   MF_TRY(launch_reduce_sum(c->partial, nb, c->dres + 3, 0, c->st));
   return MUFFIN_OK;
 }
@@ -437,6 +445,26 @@ int copy_out(float* dst, const float* src, size_t n, int on_device, hipStream_t 
   return MUFFIN_OK;
 }
 
+// n planes of np floats from src (planes sps floats apart) to dst (dps apart); waits for the copy
+// when host memory is involved.
+int copy_planes(float* dst, long long dps, const float* src, long long sps, long long n, long long np,
+                hipMemcpyKind kind, hipStream_t st) {
+  if (n <= 0) return MUFFIN_OK;
+  MF_HIP(hipMemcpy2DAsync(dst, sizeof(float) * dps, src, sizeof(float) * sps, sizeof(float) * np, (size_t)n, kind,
+                          st));
+  if (kind != hipMemcpyDeviceToDevice) MF_HIP(hipStreamSynchronize(st));
+  return MUFFIN_OK;
+}
+// the caller's dense [n][N][N] layout <-> the library's plane slots of ps floats (cs by default)
+int planes_in(muffin_ctx* c, float* dst, const float* src, long long n, int on_device, long long ps = 0) {
+  return copy_planes(dst, ps ? ps : c->cs, src, c->npix, n, c->npix,
+                     on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->st);
+}
+int planes_out(muffin_ctx* c, float* dst, const float* src, long long n, int on_device, long long ps = 0) {
+  return copy_planes(dst, c->npix, src, ps ? ps : c->cs, n, c->npix,
+                     on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st);
+}
+
 // Build a context over n cubes that share N, J, generation, coarse weighting, mu_s, sigma and rho
 // (checked by the caller); their channels are packed one cube after the other.
 int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float* const* dirty,
@@ -448,6 +476,8 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   c->J = p->J;
   c->gen = p->iuwt_gen;
   c->npix = (long long)p->N * p->N;
+  c->cs = (c->npix + p->N + 31) / 32 * 32 + 32;
+  c->us = c->npix;
   c->g = fft_geom(p->N);
   c->omega_c = p->penalize_coarse ? 1.f : 0.f;
   c->sigma = p->sigma;
@@ -464,7 +494,8 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
     c->segs.push_back(s);
   }
   c->L = total;
-  c->cube = c->npix * total;
+  c->cube = c->cs * total;
+  c->ucube = c->us * total * (c->J + 1);
   if (any_w) {
     c->chan_w_host.assign(total, 1.f);
     for (int i = 0; i < n; ++i)
@@ -484,7 +515,7 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   const long long cube = c->cube;
   const long long spec = (long long)c->L * c->N * c->g.pitch;
   MF_TRY(dalloc(&c->X, cube));
-  MF_TRY(dalloc(&c->U, cube * (c->J + 1)));
+  MF_TRY(dalloc(&c->U, c->ucube));
   MF_TRY(dalloc(&c->V, cube));
   MF_TRY(dalloc(&c->D, cube));
   MF_TRY(dalloc(&c->Q, cube));
@@ -513,10 +544,14 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   hipStream_t st = c->st;
   MF_HIP(hipMemsetAsync(c->S, 0, sizeof(float2) * spec, st));
   MF_HIP(hipMemsetAsync(c->dres, 0, sizeof(double) * 16, st));
+  // the slot padding of every cube buffer stays zero
+  for (float* b : {c->X, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT})
+    MF_HIP(hipMemsetAsync(b, 0, sizeof(float) * cube, st));
+  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, st));
   for (int i = 0; i < n; ++i) {
-    const long long off = (long long)c->segs[i].ch0 * c->npix, cnt = (long long)c->segs[i].L * c->npix;
-    MF_TRY(copy_in(c->Y + off, dirty[i], cnt, on_device, st));
-    MF_TRY(copy_in(c->cT + off, psf[i], cnt, on_device, st));
+    const long long off = (long long)c->segs[i].ch0 * c->cs;
+    MF_TRY(planes_in(c, c->Y + off, dirty[i], c->segs[i].L, on_device));
+    MF_TRY(planes_in(c, c->cT + off, psf[i], c->segs[i].L, on_device));
   }
   if (c->chan_w) MF_TRY(copy_in(c->chan_w, c->chan_w_host.data(), c->L, 0, st));
   {
@@ -553,18 +588,18 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   MF_HIP(hipStreamSynchronize(st));
   if (bad != 0) return set_error("NaN or Inf in dirty or psf"), MUFFIN_ENONFINITE;
 
-  MF_TRY(launch_psf_lobe(c->cT, c->psf_lobe, c->N, c->L, 4, st));
+  MF_TRY(launch_psf_lobe(c->cT, c->cs, c->psf_lobe, c->N, c->L, 4, st));
   // transfer functions: Hhat = FFT2(ifftshift(psf)), P = w |Hhat|^2 / N^2
   const float inv_n2 = 1.f / ((float)c->N * c->N);
-  MF_TRY(launch_rows_r2c(c->cT, c->S, c->L, c->g, c->tw, true, st));
+  MF_TRY(launch_rows_r2c(c->cT, c->cs, c->S, c->L, c->g, c->tw, true, st));
   MF_TRY(launch_cols(c->S, c->L, c->g, c->tw, COL_FWD, nullptr, nullptr, 1.f, c->Hhat_T, st));
   MF_TRY(launch_power_spectrum(c->Hhat_T, c->P_T, c->chan_w, (long long)c->g.pitch * c->N, c->L, inv_n2, st));
   // b = w H^dagger y
-  MF_TRY(launch_rows_r2c(c->Y, c->S, c->L, c->g, c->tw, false, st));
+  MF_TRY(launch_rows_r2c(c->Y, c->cs, c->S, c->L, c->g, c->tw, false, st));
   MF_TRY(launch_cols(c->S, c->L, c->g, c->tw, COL_CPLX_CONJ, nullptr, c->Hhat_T, inv_n2, nullptr, st));
-  MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_STORE, c->B, nullptr, nullptr, 0.f, nullptr, nullptr, nullptr,
-                         nullptr, st));
-  if (c->chan_w) MF_TRY(launch_scale_channels(c->B, c->chan_w, c->npix, c->L, st));
+  MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_STORE, c->B, c->cs, nullptr, nullptr, 0.f, nullptr, nullptr,
+                         nullptr, nullptr, st));
+  if (c->chan_w) MF_TRY(launch_scale_channels(c->B, c->chan_w, c->npix, c->cs, c->L, st));
   // ||W_s||^2 (FP64, shared by the group) and, per cube, beta = max_l w_l max_k |H_l(k)|^2
   MF_TRY(launch_frame_bound(c->N, c->J, c->gen, c->omega_c, c->partial, c->dres + 5, st));
   MF_HIP(hipMemcpyAsync(&c->Ws2, c->dres + 5, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -586,7 +621,7 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   }
 
   MF_HIP(hipMemsetAsync(c->X, 0, sizeof(float) * cube, st));
-  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * cube * (c->J + 1), st));
+  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, st));
   MF_HIP(hipMemsetAsync(c->V, 0, sizeof(float) * cube, st));
   MF_HIP(hipMemsetAsync(c->D, 0, sizeof(float) * cube, st));
   MF_HIP(hipStreamSynchronize(st));
@@ -613,7 +648,7 @@ int ensure_graph(muffin_ctx* c) {
 // Autotuner: for every band or pair launch of the iteration, time each band height that divides N
 // on the context's own sizes (reading state, writing only scratch planes) and keep the fastest.
 int autotune(muffin_ctx* c, int reps, std::string& rep) {
-  const long long np = c->npix, ucs = (long long)(c->J + 1) * np;
+  const long long np = c->cs, us = c->us, ucs = (long long)(c->J + 1) * us;
   std::vector<IuwtStep> sched = analysis_schedule(c);
   for (const IuwtStep& st : adjoint_schedule(c)) sched.push_back(st);
   rep += "{\"N\": " + std::to_string(c->N) + ", \"channels\": " + std::to_string(c->L) + ", \"scales\": [";
@@ -638,16 +673,16 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
                                  pout(c->cB, np), pout(c->cT, np), pout(c->cA, np), pout(c->D, np), 0.f, 1.f, 0.f,
                                  c->st, 1);
           case TR_ADJOINT:
-            return launch_triple(mode, c->N, c->L, j, pref(c->U + (long long)(j + 2) * np, ucs),
-                                 pref(c->U + (long long)(j + 1) * np, ucs), pref(c->U + (long long)j * np, ucs),
+            return launch_triple(mode, c->N, c->L, j, pref(c->U + (long long)(j + 2) * us, ucs),
+                                 pref(c->U + (long long)(j + 1) * us, ucs), pref(c->U + (long long)j * us, ucs),
                                  pref(c->cA, np), pout(c->cB, np), PlaneOut{}, PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f,
                                  c->st, 1);
           case PR_ADJOINT:
-            return launch_pair(mode, c->N, c->L, j, pref(c->U + (long long)(j + 1) * np, ucs),
-                               pref(c->U + (long long)j * np, ucs), pref(c->cA, np), pout(c->cB, np), PlaneOut{},
+            return launch_pair(mode, c->N, c->L, j, pref(c->U + (long long)(j + 1) * us, ucs),
+                               pref(c->U + (long long)j * us, ucs), pref(c->cA, np), pout(c->cB, np), PlaneOut{},
                                PlaneOut{}, 0.f, 1.f, 0.f, c->st, 1);
           case DB_ADJOINT:
-            return launch_atrous(mode, c->N, c->L, j, pref(c->U + (long long)j * np, ucs), pref(c->cA, np),
+            return launch_atrous(mode, c->N, c->L, j, pref(c->U + (long long)j * us, ucs), pref(c->cA, np),
                                  pref(c->cA, np), pout(c->cB, np), PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st, 1);
           case SM_SUBADD:
             return launch_atrous(mode, c->N, c->L, j, pref(c->cA, np), pref(c->cA, np), pref(c->cA, np),
@@ -888,7 +923,7 @@ int muffin_batch_get_x(muffin_batch* b, int32_t cube, float* x, int on_device) {
   if (!x) return set_error("bad arguments"), MUFFIN_EINVAL;
   StreamScope scope(g);
   const Seg& s = g->segs[si];
-  return copy_out(x, g->X + (long long)s.ch0 * g->npix, (size_t)s.L * g->npix, on_device, g->st);
+  return planes_out(g, x, g->X + (long long)s.ch0 * g->cs, s.L, on_device);
 }
 
 int muffin_batch_info(muffin_batch* b, int32_t cube, double out[8]) {
@@ -1044,9 +1079,9 @@ int muffin_info(muffin_ctx* c, double out[8]) {
 int muffin_set_x(muffin_ctx* c, const float* x0, int on_device) {
   if (!c || !x0) return set_error("bad arguments"), MUFFIN_EINVAL;
   StreamScope scope(c);
-  MF_TRY(copy_in(c->X, x0, c->cube, on_device, c->st));
+  MF_TRY(planes_in(c, c->X, x0, c->L, on_device));
   MF_TRY(launch_clamp_pos(c->X, c->cube, c->st));
-  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->cube * (c->J + 1), c->st));
+  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, c->st));
   MF_HIP(hipMemsetAsync(c->V, 0, sizeof(float) * c->cube, c->st));
   return MUFFIN_OK;
 }
@@ -1054,22 +1089,22 @@ int muffin_set_x(muffin_ctx* c, const float* x0, int on_device) {
 int muffin_get_x(muffin_ctx* c, float* x, int on_device) {
   if (!c || !x) return set_error("bad arguments"), MUFFIN_EINVAL;
   StreamScope scope(c);
-  return copy_out(x, c->X, c->cube, on_device, c->st);
+  return planes_out(c, x, c->X, c->L, on_device);
 }
 int muffin_get_u(muffin_ctx* c, float* u, int on_device) {
   if (!c || !u) return set_error("bad arguments"), MUFFIN_EINVAL;
   StreamScope scope(c);
-  return copy_out(u, c->U, c->cube * (c->J + 1), on_device, c->st);
+  return planes_out(c, u, c->U, (long long)c->L * (c->J + 1), on_device, c->us);
 }
 int muffin_get_v(muffin_ctx* c, float* v, int on_device) {
   if (!c || !v) return set_error("bad arguments"), MUFFIN_EINVAL;
   StreamScope scope(c);
-  return copy_out(v, c->V, c->cube, on_device, c->st);
+  return planes_out(c, v, c->V, c->L, on_device);
 }
 
 int muffin_state_size(muffin_ctx* c, size_t* bytes) {
   if (!c || !bytes) return set_error("bad arguments"), MUFFIN_EINVAL;
-  *bytes = sizeof(BlobHeader) + sizeof(float) * (size_t)c->cube * (c->J + 3);
+  *bytes = sizeof(BlobHeader) + sizeof(float) * (size_t)c->npix * c->L * (c->J + 3);
   return MUFFIN_OK;
 }
 
@@ -1093,9 +1128,10 @@ int muffin_get_state(muffin_ctx* c, void* blob, size_t bytes) {
   std::memcpy(blob, &h, sizeof(h));
   float* f = (float*)((char*)blob + sizeof(h));
   StreamScope scope(c);
-  MF_TRY(copy_out(f, c->X, c->cube, 0, c->st));
-  MF_TRY(copy_out(f + c->cube, c->U, c->cube * (c->J + 1), 0, c->st));
-  MF_TRY(copy_out(f + c->cube * (c->J + 2), c->V, c->cube, 0, c->st));
+  const long long dense = c->npix * c->L;  // the blob holds X, U, V in the dense layout
+  MF_TRY(planes_out(c, f, c->X, c->L, 0));
+  MF_TRY(planes_out(c, f + dense, c->U, (long long)c->L * (c->J + 1), 0, c->us));
+  MF_TRY(planes_out(c, f + dense * (c->J + 2), c->V, c->L, 0));
   return MUFFIN_OK;
 }
 
@@ -1111,9 +1147,10 @@ int muffin_set_state(muffin_ctx* c, const void* blob, size_t bytes) {
     return set_error("checkpoint sizes or parameters differ from the context"), MUFFIN_ESTATE;
   const float* f = (const float*)((const char*)blob + sizeof(h));
   StreamScope scope(c);
-  MF_TRY(copy_in(c->X, f, c->cube, 0, c->st));
-  MF_TRY(copy_in(c->U, f + c->cube, c->cube * (c->J + 1), 0, c->st));
-  MF_TRY(copy_in(c->V, f + c->cube * (c->J + 2), c->cube, 0, c->st));
+  const long long dense = c->npix * c->L;
+  MF_TRY(planes_in(c, c->X, f, c->L, 0));
+  MF_TRY(planes_in(c, c->U, f + dense, (long long)c->L * (c->J + 1), 0, c->us));
+  MF_TRY(planes_in(c, c->V, f + dense * (c->J + 2), c->L, 0));
   c->iter = h.iter;
   return MUFFIN_OK;
 }
@@ -1122,13 +1159,13 @@ int muffin_warm_start(muffin_ctx* c, muffin_cnn* net) {
   if (!c || !net) return set_error("bad arguments"), MUFFIN_EINVAL;
   if (c->N % 32) return set_error("warm start needs N to be a multiple of 32"), MUFFIN_EINVAL;
   StreamScope scope(c);
-  MF_TRY(cnn_warm_input(c->Y, c->psf_lobe, c->cA, c->N, c->L, c->st));
+  MF_TRY(cnn_warm_input(c->Y, c->cs, c->psf_lobe, c->cA, c->N, c->L, c->st));  // dense planes
   MF_HIP(hipStreamSynchronize(c->st));
   MF_TRY(muffin_cnn_predict(net, c->cA, c->cB, c->L, c->N));
   MF_HIP(hipDeviceSynchronize());
-  MF_HIP(hipMemcpyAsync(c->X, c->cB, sizeof(float) * c->cube, hipMemcpyDeviceToDevice, c->st));
+  MF_TRY(planes_in(c, c->X, c->cB, c->L, 1));
   MF_TRY(launch_clamp_pos(c->X, c->cube, c->st));
-  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->cube * (c->J + 1), c->st));
+  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, c->st));
   MF_HIP(hipMemsetAsync(c->V, 0, sizeof(float) * c->cube, c->st));
   return MUFFIN_OK;
 }
@@ -1136,53 +1173,58 @@ int muffin_warm_start(muffin_ctx* c, muffin_cnn* net) {
 int muffin_apply_op(muffin_ctx* c, int op, const float* in, float* out) {
   if (!c || !in || !out) return set_error("bad arguments"), MUFFIN_EINVAL;
   StreamScope scope(c);
-  const long long np = c->npix;
+  // in and out are dense (planes np floats apart); the scratch planes use the library's slots
+  const long long np = c->npix, cs = c->cs;
   const float inv_n2 = 1.f / ((float)c->N * c->N);
   switch (op) {
     case MUFFIN_OP_H:
     case MUFFIN_OP_HT:
-      MF_TRY(launch_rows_r2c(in, c->S, c->L, c->g, c->tw, false, c->st));
+      MF_TRY(launch_rows_r2c(in, np, c->S, c->L, c->g, c->tw, false, c->st));
       MF_TRY(launch_cols(c->S, c->L, c->g, c->tw, op == MUFFIN_OP_H ? COL_CPLX : COL_CPLX_CONJ, nullptr, c->Hhat_T,
                          inv_n2, nullptr, c->st));
-      MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_STORE, out, nullptr, nullptr, 0.f, nullptr, nullptr,
+      MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_STORE, out, np, nullptr, nullptr, 0.f, nullptr, nullptr,
                              nullptr, nullptr, c->st));
       return MUFFIN_OK;
     case MUFFIN_OP_GRAD:
-      return enqueue_gradient(c, in, out, nullptr, 0.f);
+      // the epilogue reads b in the slots: the operand and result go through scratch planes
+      MF_TRY(planes_in(c, c->cT, in, c->L, 1));
+      MF_TRY(enqueue_gradient(c, c->cT, c->cA, nullptr, 0.f));
+      return planes_out(c, out, c->cA, c->L, 1);
     case MUFFIN_OP_IUWT: {
       const long long ucs = (long long)(c->J + 1) * np;
       const float* cur = in;
       float* bufs[2] = {c->cA, c->cB};
       for (int j = 0; j < c->J; ++j) {
         float* nxt = bufs[j & 1];
-        MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(nxt, np),
+        const long long ccs = cur == in ? np : cs;
+        MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(cur, ccs), PlaneRef{}, PlaneRef{}, pout(nxt, cs),
                              PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
         float* wj = out + (long long)j * np;
         if (c->gen == 2) {
           // w = c_j - H_j c_{j+1}: smooth c_{j+1} into the output plane, then subtract
-          MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(nxt, np), PlaneRef{}, PlaneRef{}, pout(c->cT, np),
+          MF_TRY(launch_atrous(SM_SMOOTH, c->N, c->L, j, pref(nxt, cs), PlaneRef{}, PlaneRef{}, pout(c->cT, cs),
                                PlaneOut{}, 0.f, 1.f, nullptr, nullptr, c->st));
-          MF_TRY(launch_pointwise(PT_SUB, c->N, c->L, pref(c->cT, np), pref(cur, np), pout(wj, ucs), 0.f, 1.f,
+          MF_TRY(launch_pointwise(PT_SUB, c->N, c->L, pref(c->cT, cs), pref(cur, ccs), pout(wj, ucs), 0.f, 1.f,
                                   nullptr, nullptr, c->st));
         } else {
-          MF_TRY(launch_pointwise(PT_SUB, c->N, c->L, pref(nxt, np), pref(cur, np), pout(wj, ucs), 0.f, 1.f, nullptr,
+          MF_TRY(launch_pointwise(PT_SUB, c->N, c->L, pref(nxt, cs), pref(cur, ccs), pout(wj, ucs), 0.f, 1.f, nullptr,
                                   nullptr, c->st));
         }
         cur = nxt;
       }
-      return launch_pointwise(PT_COPY, c->N, c->L, pref(cur, np), PlaneRef{},
+      return launch_pointwise(PT_COPY, c->N, c->L, pref(cur, cs), PlaneRef{},
                               pout(out + (long long)c->J * np, ucs), 1.f, 1.f, nullptr, nullptr, c->st);
     }
     case MUFFIN_OP_IUWT_ADJ: {
       const float* a = nullptr;
-      MF_TRY(enqueue_adjoint(c, in, (long long)(c->J + 1) * np, 1.f, &a));
-      return launch_pointwise(PT_COPY, c->N, c->L, pref(a, np), PlaneRef{}, pout(out, np), 1.f, 1.f, nullptr,
+      MF_TRY(enqueue_adjoint(c, in, np, (long long)(c->J + 1) * np, 1.f, &a));
+      return launch_pointwise(PT_COPY, c->N, c->L, pref(a, cs), PlaneRef{}, pout(out, np), 1.f, 1.f, nullptr,
                               nullptr, c->st);
     }
     case MUFFIN_OP_DCT:
-      return launch_dct(in, out, c->segs[0].WT, np, c->L, c->st);
+      return launch_dct(in, out, c->segs[0].WT, np, np, c->L, c->st);
     case MUFFIN_OP_IDCT:
-      return launch_dct(in, out, c->segs[0].W, np, c->L, c->st);
+      return launch_dct(in, out, c->segs[0].W, np, np, c->L, c->st);
     default:
       return set_error("unknown operator"), MUFFIN_EINVAL;
   }

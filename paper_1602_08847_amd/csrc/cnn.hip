@@ -408,12 +408,14 @@ __global__ void __launch_bounds__(256) k_prep_weights(const float* __restrict__ 
 }
 
 // x / s_l per plane (input normalisation of the warm start)
-__global__ void __launch_bounds__(256) k_scale_planes(const float* __restrict__ x, const float* __restrict__ s,
-                                                      int sstride, float* __restrict__ out, long long n2, int nimg) {
+// out[b][p] = x[b xcs + p] / s[b sstride] over nimg planes of n2 pixels (x has channel stride xcs)
+__global__ void __launch_bounds__(256) k_scale_planes(const float* __restrict__ x, long long xcs,
+                                                      const float* __restrict__ s, int sstride,
+                                                      float* __restrict__ out, long long n2, int nimg) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i >= n2 * nimg) return;
   const long long b = i / n2;
-  out[i] = x[i] / s[b * sstride];
+  out[i] = x[b * xcs + (i - b * n2)] / s[b * sstride];
 }
 
 }  // namespace mf
@@ -817,11 +819,11 @@ int muffin_cnn_layer(muffin_cnn* c, int32_t layer, int32_t op, const float* x, c
 // the 9 x 9 window at the PSF origin (the gain of the PSF main lobe over the network's receptive
 // field), the network runs, and max(output, 0) becomes X.
 namespace mf {
-__global__ void __launch_bounds__(256) k_psf_lobe(const float* __restrict__ psf, float* __restrict__ out, int N,
-                                                  int radius) {
+__global__ void __launch_bounds__(256) k_psf_lobe(const float* __restrict__ psf, long long cs,
+                                                  float* __restrict__ out, int N, int radius) {
   __shared__ float red[256];
   const int l = blockIdx.x, w = 2 * radius + 1;
-  const float* p = psf + (long long)l * N * N;
+  const float* p = psf + (long long)l * cs;
   float s = 0.f;
   for (int i = threadIdx.x; i < w * w; i += 256) {
     const int dy = i / w - radius, dx = i % w - radius;
@@ -836,15 +838,15 @@ __global__ void __launch_bounds__(256) k_psf_lobe(const float* __restrict__ psf,
   if (threadIdx.x == 0) out[l] = red[0];
 }
 
-int launch_psf_lobe(const float* psf, float* out, int N, int L, int radius, hipStream_t st) {
-  hipLaunchKernelGGL(k_psf_lobe, dim3(L), dim3(256), 0, st, psf, out, N, radius);
+int launch_psf_lobe(const float* psf, long long cs, float* out, int N, int L, int radius, hipStream_t st) {
+  hipLaunchKernelGGL(k_psf_lobe, dim3(L), dim3(256), 0, st, psf, cs, out, N, radius);
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }
 
-int cnn_warm_input(const float* Y, const float* scale, float* out, int N, int L, hipStream_t st) {
+int cnn_warm_input(const float* Y, long long cs, const float* scale, float* out, int N, int L, hipStream_t st) {
   const long long n2 = (long long)N * N;
-  hipLaunchKernelGGL(k_scale_planes, dim3(nb256(n2 * L)), dim3(256), 0, st, Y, scale, 1, out, n2, L);
+  hipLaunchKernelGGL(k_scale_planes, dim3(nb256(n2 * L)), dim3(256), 0, st, Y, cs, scale, 1, out, n2, L);
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }

@@ -70,10 +70,11 @@ FftGeom fft_geom(int N);
 // Twiddle table exp(-2 pi i m / N), m = 0..N-1, built in FP64 on the host.
 std::vector<float2> fft_twiddles(int N);
 
-// Row pass, real -> half spectrum.  x: [nch][N][N] (channel stride N*N), S: column-blocked
-// [nch][ncb][N][CB] (entry (row, col) of a channel at ((col / CB) N + row) CB + col % CB).
-// With shift, the input is read with an (N/2, N/2) circular shift (ifftshift of a centred PSF).
-int launch_rows_r2c(const float* x, float2* S, int nch, const FftGeom& g, const float2* tw,
+// Row pass, real -> half spectrum.  x: nch planes of N x N, channel stride cs floats (>= N*N);
+// S: column-blocked [nch][ncb][N][CB] (entry (row, col) of a channel at
+// ((col / CB) N + row) CB + col % CB).  With shift, the input is read with an (N/2, N/2) circular
+// shift (ifftshift of a centred PSF).
+int launch_rows_r2c(const float* x, long long cs, float2* S, int nch, const FftGeom& g, const float2* tw,
                     bool shift, hipStream_t st);
 
 enum ColMode { COL_FWD = 0, COL_REAL = 1, COL_CPLX = 2, COL_CPLX_CONJ = 3 };
@@ -84,12 +85,13 @@ int launch_cols(float2* S, int nch, const FftGeom& g, const float2* tw, int mode
                 const float2* Mc, float scale, float2* outT, hipStream_t st);
 
 enum RowEpi { EPI_STORE = 0, EPI_GRAD = 1, EPI_RESID = 2 };
-// Row pass, half spectrum -> real, with an epilogue per pixel (g = inverse transform):
+// Row pass, half spectrum -> real, with an epilogue per pixel (g = inverse transform); out, b, s
+// and y are nch planes of N x N with channel stride cs floats:
 //   EPI_STORE: out = g
 //   EPI_GRAD : out = g - b + s_scale * s      (s may be NULL)
 //   EPI_RESID: partial[block] = sum over the block of 0.5 * w_l * (g - y)^2   (FP64)
 int launch_rows_c2r(const float2* S, int nch, const FftGeom& g, const float2* tw, int epi,
-                    float* out, const float* b, const float* s, float s_scale, const float* y,
+                    float* out, long long cs, const float* b, const float* s, float s_scale, const float* y,
                     const float* chan_w, double* partial, int* nblocks_out, hipStream_t st);
 
 // ------------------------------------------------------------------ IUWT (a trous)
@@ -160,16 +162,19 @@ struct SpectralArgs {
   const float2* twL;  // FFT twiddles exp(-2 pi i m / L)
   const float2* csL;  // exp(i pi k / 2L)
   long long npix;     // N*N
+  long long cs;       // floats between the channel planes of X, Q, V and D (>= npix)
   int L;
   int use_fft;        // 1: FFT-based cosine transforms (L has an FFT plan), 0: cosine table
   float tau, mu_l, smu_l, rho;
 };
 bool spectral_has_fft(int L);
 int launch_spectral_step(const SpectralArgs& a, hipStream_t st);
-// out = X W_lambda (inverse = false) or X W_lambda^dagger (inverse = true), per pixel.
-int launch_dct(const float* in, float* out, const float* Wmat, long long npix, int L, hipStream_t st);
+// out = X W_lambda (inverse = false) or X W_lambda^dagger (inverse = true), per pixel; in and out
+// hold L planes of npix pixels with channel stride cs floats.
+int launch_dct(const float* in, float* out, const float* Wmat, long long npix, long long cs, int L,
+               hipStream_t st);
 // partial[block] = sum |X W_lambda| over the block's pixels.
-int launch_dct_abs(const float* in, const float* WT, long long npix, int L, double* partial,
+int launch_dct_abs(const float* in, const float* WT, long long npix, long long cs, int L, double* partial,
                    int* nblocks_out, hipStream_t st);
 
 // ------------------------------------------------------------------ reductions (FP64)

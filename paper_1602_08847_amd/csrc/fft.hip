@@ -23,7 +23,7 @@ constexpr int col_block() {
 
 // ------------------------------------------------------------------ pass 1: rows, real -> half spectrum
 template <int N>
-__global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, float2* __restrict__ S,
+__global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, long long cs, float2* __restrict__ S,
                                                   int pitch, long long npairs, const float2* __restrict__ tw,
                                                   int shift) {
   constexpr int T = Plan<N>::T;
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, f
   if (active) {
     ch = pair / (N / 2);
     r0 = 2 * (int)(pair % (N / 2));
-    const float* xc = x + ch * (long long)N * N;
+    const float* xc = x + ch * cs;
     int ra = r0, rb = r0 + 1;
     if (shift) {
       ra = (ra + N / 2) % N;
@@ -179,7 +179,7 @@ __device__ __forceinline__ double block_sum_d(double v) {
 template <int N, int EPI>
 __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, int pitch, long long npairs,
                                                   const float2* __restrict__ tw, float* __restrict__ out,
-                                                  const float* __restrict__ b, const float* __restrict__ s,
+                                                  long long cs, const float* __restrict__ b, const float* __restrict__ s,
                                                   float s_scale, const float* __restrict__ y,
                                                   const float* __restrict__ chan_w, double* __restrict__ partial) {
   constexpr int T = Plan<N>::T;
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
   if (active) {
     ch = pair / (N / 2);
     r0 = 2 * (int)(pair % (N / 2));
-    o0 = (ch * N + r0) * (long long)N;
+    o0 = ch * cs + (long long)r0 * N;
     o1 = o0 + N;
     constexpr int CB = col_block<N>();
     const float2* sblk = S + (ch * N) * (long long)pitch + (long long)r0 * CB;  // blocked layout
@@ -320,13 +320,13 @@ std::vector<float2> fft_twiddles(int N) {
 }
 
 template <int N>
-static int rows_r2c_n(const float* x, float2* S, int nch, const FftGeom& g, const float2* tw, bool shift,
+static int rows_r2c_n(const float* x, long long cs, float2* S, int nch, const FftGeom& g, const float2* tw, bool shift,
                       hipStream_t st) {
   constexpr int T = Plan<N>::T;
   constexpr int FPB = (256 / T) > 0 ? (256 / T) : 1;
   const long long npairs = (long long)nch * (N / 2);
   const long long nblk = (npairs + FPB - 1) / FPB;
-  hipLaunchKernelGGL(k_rows_r2c<N>, dim3((unsigned)nblk), dim3(FPB * T), 0, st, x, S, g.pitch, npairs, tw,
+  hipLaunchKernelGGL(k_rows_r2c<N>, dim3((unsigned)nblk), dim3(FPB * T), 0, st, x, cs, S, g.pitch, npairs, tw,
                      shift ? 1 : 0);
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
@@ -364,7 +364,7 @@ static int cols_n(float2* S, int nch, const FftGeom& g, const float2* tw, int mo
 
 template <int N>
 static int rows_c2r_n(const float2* S, int nch, const FftGeom& g, const float2* tw, int epi, float* out,
-                      const float* b, const float* s, float s_scale, const float* y, const float* chan_w,
+                      long long cs, const float* b, const float* s, float s_scale, const float* y, const float* chan_w,
                       double* partial, int* nblocks_out, hipStream_t st) {
   constexpr int T = Plan<N>::T;
   constexpr int FPB = (256 / T) > 0 ? (256 / T) : 1;
@@ -378,15 +378,15 @@ static int rows_c2r_n(const float2* S, int nch, const FftGeom& g, const float2* 
   const dim3 grid((unsigned)nblk), block(FPB * T);
   switch (epi) {
     case EPI_STORE:
-      hipLaunchKernelGGL((k_rows_c2r<N, EPI_STORE>), grid, block, 0, st, S, g.pitch, npairs, tw, out, b, s, s_scale,
+      hipLaunchKernelGGL((k_rows_c2r<N, EPI_STORE>), grid, block, 0, st, S, g.pitch, npairs, tw, out, cs, b, s, s_scale,
                          y, chan_w, partial);
       break;
     case EPI_GRAD:
-      hipLaunchKernelGGL((k_rows_c2r<N, EPI_GRAD>), grid, block, 0, st, S, g.pitch, npairs, tw, out, b, s, s_scale,
+      hipLaunchKernelGGL((k_rows_c2r<N, EPI_GRAD>), grid, block, 0, st, S, g.pitch, npairs, tw, out, cs, b, s, s_scale,
                          y, chan_w, partial);
       break;
     case EPI_RESID:
-      hipLaunchKernelGGL((k_rows_c2r<N, EPI_RESID>), grid, block, 0, st, S, g.pitch, npairs, tw, out, b, s, s_scale,
+      hipLaunchKernelGGL((k_rows_c2r<N, EPI_RESID>), grid, block, 0, st, S, g.pitch, npairs, tw, out, cs, b, s, s_scale,
                          y, chan_w, partial);
       break;
     default:
@@ -417,9 +417,10 @@ static int rows_c2r_n(const float2* S, int nch, const FftGeom& g, const float2* 
     default: set_error("unsupported FFT size"); return MUFFIN_EINVAL; \
   }
 
-int launch_rows_r2c(const float* x, float2* S, int nch, const FftGeom& g, const float2* tw, bool shift,
-                    hipStream_t st) {
-#define CALL(n) rows_r2c_n<n>(x, S, nch, g, tw, shift, st)
+int launch_rows_r2c(const float* x, long long cs, float2* S, int nch, const FftGeom& g, const float2* tw,
+                    bool shift, hipStream_t st) {
+  if (cs < (long long)g.N * g.N) return set_error("rows_r2c: channel stride below N*N"), MUFFIN_EINVAL;
+#define CALL(n) rows_r2c_n<n>(x, cs, S, nch, g, tw, shift, st)
   switch (g.N) {
     case 8: return CALL(8);
     case 16: return CALL(16);
@@ -466,9 +467,10 @@ int launch_cols(float2* S, int nch, const FftGeom& g, const float2* tw, int mode
 }
 
 int launch_rows_c2r(const float2* S, int nch, const FftGeom& g, const float2* tw, int epi, float* out,
-                    const float* b, const float* s, float s_scale, const float* y, const float* chan_w,
-                    double* partial, int* nblocks_out, hipStream_t st) {
-#define CALL(n) rows_c2r_n<n>(S, nch, g, tw, epi, out, b, s, s_scale, y, chan_w, partial, nblocks_out, st)
+                    long long cs, const float* b, const float* s, float s_scale, const float* y,
+                    const float* chan_w, double* partial, int* nblocks_out, hipStream_t st) {
+  if (cs < (long long)g.N * g.N) return set_error("rows_c2r: channel stride below N*N"), MUFFIN_EINVAL;
+#define CALL(n) rows_c2r_n<n>(S, nch, g, tw, epi, out, cs, b, s, s_scale, y, chan_w, partial, nblocks_out, st)
   switch (g.N) {
     case 8: return CALL(8);
     case 16: return CALL(16);

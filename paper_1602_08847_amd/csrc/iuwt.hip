@@ -1186,17 +1186,17 @@ int launch_clamp_pos(float* x, long long n, hipStream_t st) {
 }
 
 __global__ void __launch_bounds__(256) k_scale_channels(float* __restrict__ x, const float* __restrict__ w,
-                                                        long long npix) {
+                                                        long long npix, long long cs) {
   const float s = w[blockIdx.y];
-  float* xc = x + (long long)blockIdx.y * npix;
+  float* xc = x + (long long)blockIdx.y * cs;
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < npix; i += (long long)gridDim.x * 256)
     xc[i] *= s;
 }
 
-int launch_scale_channels(float* x, const float* chan_w, long long npix, int nch, hipStream_t st) {
+int launch_scale_channels(float* x, const float* chan_w, long long npix, long long cs, int nch, hipStream_t st) {
   long long nb = (npix + 255) / 256;
   if (nb > 1024) nb = 1024;
-  hipLaunchKernelGGL(k_scale_channels, dim3((unsigned)nb, (unsigned)nch), dim3(256), 0, st, x, chan_w, npix);
+  hipLaunchKernelGGL(k_scale_channels, dim3((unsigned)nb, (unsigned)nch), dim3(256), 0, st, x, chan_w, npix, cs);
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }

@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(256) k_spectral_step(SpectralArgs a) {
   for (int idx = threadIdx.x; idx < L * PX; idx += 256) {
     const int l = idx / PX, pp = idx % PX;
     const long long q = pix0 + pp;
-    Vs[idx] = (q < a.npix) ? a.V[(long long)l * a.npix + q] : 0.f;
+    Vs[idx] = (q < a.npix) ? a.V[(long long)l * a.cs + q] : 0.f;
   }
   lds_barrier();
   // primal step, channel rows l = g + 8 i (four per pass)
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) k_spectral_step(SpectralArgs a) {
       if (l < L) {
         float d = 0.f;
         if (pv) {
-          const long long o = (long long)l * a.npix + pix;
+          const long long o = (long long)l * a.cs + pix;
           const float x = a.X[o];
           const float t = a.mu_l * acc[i];
           const float xt = fmaxf(x - a.tau * (a.Q[o] + t), 0.f);
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) k_spectral_step(SpectralArgs a) {
       const int k = ks[i];
       if (k < L && pv) {
         const float v = Vs[k * PX + p];
-        a.V[(long long)k * a.npix + pix] = a.rho * satf_s(v + a.smu_l * acc[i]) + (1.f - a.rho) * v;
+        a.V[(long long)k * a.cs + pix] = a.rho * satf_s(v + a.smu_l * acc[i]) + (1.f - a.rho) * v;
       }
     }
   }
@@ -108,17 +108,17 @@ __global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
   float* Ds = sm + L * PXM;  // [L][PXM]
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const long long npix = a.npix;
+  const long long npix = a.npix, cs = a.cs;
   const long long pix = (long long)blockIdx.x * PXM + lane;
   const bool pok = pix < npix;
-  for (int l = wv; l < L; l += 4) Vs[l * PXM + lane] = pok ? a.V[(long long)l * npix + pix] : 0.f;
+  for (int l = wv; l < L; l += 4) Vs[l * PXM + lane] = pok ? a.V[(long long)l * cs + pix] : 0.f;
   lds_barrier();
   // primal step, channels l0 .. l0 + CW - 1 of this wave
   for (int l0 = wv * CW; l0 < L; l0 += 4 * CW) {
     float xr[CW], qr[CW], acc[CW];
 #pragma unroll
     for (int c = 0; c < CW; ++c) {
-      const long long o = (long long)min(l0 + c, L - 1) * npix + (pok ? pix : 0);
+      const long long o = (long long)min(l0 + c, L - 1) * cs + (pok ? pix : 0);
       xr[c] = a.X[o];  // fetched now, used after the sums
       qr[c] = a.Q[o];
       acc[c] = 0.f;
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
       if (l >= L) break;
       float d = 0.f;
       if (pok) {
-        const long long o = (long long)l * npix + pix;
+        const long long o = (long long)l * cs + pix;
         const float x = xr[c];
         const float tv = a.mu_l * acc[c];
         const float xt = fmaxf(x - a.tau * (qr[c] + tv), 0.f);
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
       if (k >= L) break;
       if (pok) {
         const float v = Vs[k * PXM + lane];
-        a.V[(long long)k * npix + pix] = a.rho * satf_s(v + a.smu_l * acc[c]) + (1.f - a.rho) * v;
+        a.V[(long long)k * cs + pix] = a.rho * satf_s(v + a.smu_l * acc[c]) + (1.f - a.rho) * v;
       }
     }
   }
@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   extern __shared__ float2 buf[];  // [NF][LS] transforms; pixel p is part p & 1 of transform p / 2
   float2* twl = buf + NF * LS;     // [L] twiddle table, copied once so the stages read it from LDS
   for (int i = threadIdx.x; i < L; i += NT) twl[i] = a.twL[i];
-  const long long npix = a.npix;
+  const long long npix = a.npix, cs = a.cs;
   const long long pix0 = (long long)blockIdx.x * PXB;
   // Element i of a thread is (channel, pixel) = (idx / PXB, idx % PXB), idx = threadIdx.x + i NT.
   // When NT is a multiple of PXB the pixel is the same for all i and the channel steps by
@@ -214,8 +214,8 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   constexpr int LSTEP = FIXP ? NT / PXB : 1;
   const int l0 = threadIdx.x / PXB, p0 = threadIdx.x - l0 * PXB;
   const bool q0ok = pix0 + p0 < npix;
-  const unsigned voff = FIXP ? (unsigned)(((long long)l0 * npix + pix0 + p0) * 4) : 0u;
-  const long long cstride = (long long)LSTEP * npix * 4;
+  const unsigned voff = FIXP ? (unsigned)(((long long)l0 * cs + pix0 + p0) * 4) : 0u;
+  const long long cstride = (long long)LSTEP * cs * 4;
   auto el_l = [&](int i) -> int { return FIXP ? l0 + i * LSTEP : (threadIdx.x + i * NT) / PXB; };
   auto el_p = [&](int i) -> int { return FIXP ? p0 : (threadIdx.x + i * NT) % PXB; };
   auto el_ok = [&](int i) -> bool {
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   };
   auto el_ptr = [&](const float* base, int i) -> const float* {
     if constexpr (FIXP) return reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + i * cstride + voff);
-    return base + (long long)el_l(i) * npix + pix0 + el_p(i);
+    return base + (long long)el_l(i) * cs + pix0 + el_p(i);
   };
   auto el_out = [&](float* base, int i) -> float* { return const_cast<float*>(el_ptr(base, i)); };
   // V of the thread's elements, kept in registers for the dual step
@@ -382,7 +382,7 @@ int launch_spectral_step(const SpectralArgs& a, hipStream_t st) {
 // sum of |out| per workgroup.
 template <bool ABS>
 __global__ void __launch_bounds__(256) k_pix_matvec(const float* __restrict__ in, float* __restrict__ out,
-                                                    const float* __restrict__ M, long long npix, int L,
+                                                    const float* __restrict__ M, long long npix, long long cs, int L,
                                                     double* __restrict__ partial) {
   // 64 pixels per workgroup, one per lane; a wave computes 8 output rows at a time from
   // wave-uniform matrix rows (scalar loads), each LDS read feeding 8 FMAs; sums run over j in order
@@ -393,7 +393,7 @@ __global__ void __launch_bounds__(256) k_pix_matvec(const float* __restrict__ in
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long long pix = (long long)blockIdx.x * PXM + lane;
   const bool pok = pix < npix;
-  for (int l = wv; l < L; l += 4) Is[l * PXM + lane] = pok ? in[(long long)l * npix + pix] : 0.f;
+  for (int l = wv; l < L; l += 4) Is[l * PXM + lane] = pok ? in[(long long)l * cs + pix] : 0.f;
   lds_barrier();
   double acc_abs = 0.0;
   for (int i0 = wv * CW; i0 < L; i0 += 4 * CW) {
@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(256) k_pix_matvec(const float* __restrict__ in
       const int r = i0 + c;
       if (r < L && pok) {
         if (ABS) acc_abs += fabs((double)acc[c]);
-        else out[(long long)r * npix + pix] = acc[c];
+        else out[(long long)r * cs + pix] = acc[c];
       }
     }
   }
@@ -428,16 +428,17 @@ __global__ void __launch_bounds__(256) k_pix_matvec(const float* __restrict__ in
   }
 }
 
-int launch_dct(const float* in, float* out, const float* Wmat, long long npix, int L, hipStream_t st) {
+int launch_dct(const float* in, float* out, const float* Wmat, long long npix, long long cs, int L, hipStream_t st) {
   const size_t shm = sizeof(float) * (size_t)L * PXM;
   const long long nblk = (npix + PXM - 1) / PXM;
-  hipLaunchKernelGGL(k_pix_matvec<false>, dim3((unsigned)nblk), dim3(256), shm, st, in, out, Wmat, npix, L,
+  hipLaunchKernelGGL(k_pix_matvec<false>, dim3((unsigned)nblk), dim3(256), shm, st, in, out, Wmat, npix, cs, L,
                      (double*)nullptr);
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }
 
-int launch_dct_abs(const float* in, const float* WT, long long npix, int L, double* partial, int* nblocks_out,
+int launch_dct_abs(const float* in, const float* WT, long long npix, long long cs, int L, double* partial,
+                   int* nblocks_out,
                    hipStream_t st) {
   const size_t shm = sizeof(float) * (size_t)L * PXM;
   const long long nblk = (npix + PXM - 1) / PXM;
@@ -447,7 +448,7 @@ int launch_dct_abs(const float* in, const float* WT, long long npix, int L, doub
   }
   if (nblocks_out) *nblocks_out = (int)nblk;
   hipLaunchKernelGGL(k_pix_matvec<true>, dim3((unsigned)nblk), dim3(256), shm, st, in, (float*)nullptr, WT, npix,
-                     L, partial);
+                     cs, L, partial);
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }
