@@ -51,6 +51,9 @@ KERNEL_BYTES = {
     "k_triple<TR_ADJOINT> (three adjoint Horner steps)": 20.0,
     # reads c_{J-3}, the three u planes and u_J, writes the three u planes and u_J
     "k_triple<TR_ANALYSIS_C> (last three analysis scales + spatial and coarse dual steps)": 36.0,
+    # reads c_{J-2} and the old u_{J-2}, u_{J-1}, u_J; writes the new ones and the adjoint sum after
+    # the next iteration's first two Horner steps
+    "k_fused (last analysis pair + next iteration's first adjoint pair)": 32.0,
 }
 PROFILE_SLOT = {
     "k_band<DB_ANALYSIS> (one scale of analysis + spatial dual step)": 0,
@@ -62,6 +65,7 @@ PROFILE_SLOT = {
     "k_triple<TR_ANALYSIS> (three scales of analysis + spatial dual steps)": 6,
     "k_triple<TR_ADJOINT> (three adjoint Horner steps)": 7,
     "k_triple<TR_ANALYSIS_C> (last three analysis scales + spatial and coarse dual steps)": 8,
+    "k_fused (last analysis pair + next iteration's first adjoint pair)": 9,
 }
 
 

@@ -51,6 +51,13 @@ typedef struct muffin_ctx muffin_ctx;
 /* Run the IUWT one launch per scale instead of fusing two or three consecutive scales into one
  * launch (the results are the same bit for bit; the fused form moves fewer bytes). */
 #define MUFFIN_FLAG_SINGLE_SCALE 1
+/* End each iteration's analysis with one launch that also runs the next iteration's first two
+ * adjoint steps over the planes it has just updated (second generation, coarse plane penalised,
+ * last scale group a pair; otherwise ignored).  Same results bit for bit, 12 bytes per voxel
+ * fewer; it keeps a second copy of three dual planes.  Off by default: on MI355X the band kernels
+ * are limited by instruction issue rather than HBM, and the fused launch costs about as much as
+ * the two it replaces plus its longer halo. */
+#define MUFFIN_FLAG_FUSED_TAIL 2
 
 /* Problem and algorithm parameters (Sec. 2 eqs. (reg), (RegAll); Sec. 3, Algorithm 1). */
 typedef struct {
@@ -142,7 +149,9 @@ int muffin_apply_op(muffin_ctx* ctx, int op, const float* in, float* out);
  *   3 two analysis scales in one launch, 4 two adjoint steps in one launch, 5 the last two
  *   analysis scales with the coarse plane's dual step, 6 three analysis scales in one launch,
  *   7 three adjoint steps in one launch, 8 the last three analysis scales with the coarse plane's
- *   dual step; k = 9..11 are 0.
+ *   dual step, 9 the last two analysis scales with the coarse plane's dual step fused with the
+ *   next iteration's first two adjoint steps (which then leave the adjoint phase); k = 10, 11
+ *   are 0.
  * Each kernel family (adjoint, analysis) is bracketed in every other iteration, so n_iter >= 2.
  * The iterations advance the state like muffin_step. */
 int muffin_profile(muffin_ctx* ctx, int32_t n_iter, double ms[32]);

@@ -76,8 +76,19 @@ struct muffin_ctx {
   double sigma = 1, rho = 1, Ws2 = 0;
   float omega_c = 1.f;
   long long iter = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // Fused tail (MUFFIN_FLAG_FUSED_TAIL; second generation, coarse plane penalised, last group a
+  // pair): the last analysis
+  // launch also runs the next iteration's first adjoint pair on the planes it has just updated
+  // (PR_FUSED).  Those three planes (scales jf, jf + 1 and the coarse plane) alternate between U
+  // and U2 ([L][3] planes, us floats apart) from one iteration to the next, so that a band's halo
+  // still reads the old values; upar names the buffer holding the current ones (0: U, 1: U2).
+  // Acar carries the adjoint's running sum after that pair into the next iteration; acar_ok is
+  // false when U was set from outside and Acar has to be recomputed.
+  bool fused = false, acar_ok = true;
+  int jf = 0, upar = 0;
+  float *U2 = nullptr, *Acar = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};  // one iteration per parity of upar
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -113,7 +124,7 @@ int validate(const muffin_params* p) {
   if (!fft_supported(p->N)) return set_error("N must be 2^a or 3*2^a with 8 <= N <= 1024"), MUFFIN_EINVAL;
   if (p->L < 1 || p->L > 512) return set_error("L must be in [1, 512]"), MUFFIN_EINVAL;
   if (p->J < 1 || p->J > 6) return set_error("J must be in [1, 6]"), MUFFIN_EINVAL;
-  if (p->flags & ~MUFFIN_FLAG_SINGLE_SCALE) return set_error("unknown flags"), MUFFIN_EINVAL;
+  if (p->flags & ~(MUFFIN_FLAG_SINGLE_SCALE | MUFFIN_FLAG_FUSED_TAIL)) return set_error("unknown flags"), MUFFIN_EINVAL;
   if (p->iuwt_gen != 1 && p->iuwt_gen != 2) return set_error("iuwt_gen must be 1 or 2"), MUFFIN_EINVAL;
   if (p->penalize_coarse != 0 && p->penalize_coarse != 1)
     return set_error("penalize_coarse must be 0 or 1"), MUFFIN_EINVAL;
@@ -133,7 +144,7 @@ int validate(const muffin_params* p) {
 // ---------------------------------------------------------------- phases
 // Launch kinds reported by muffin_profile.
 enum LaunchKind { K_DB_ANALYSIS = 0, K_DB_ADJOINT = 1, K_DB_ANALYSIS_C = 2, K_PR_ANALYSIS = 3, K_PR_ADJOINT = 4,
-                  K_PR_ANALYSIS_C = 5, K_TR_ANALYSIS = 6, K_TR_ADJOINT = 7, K_TR_ANALYSIS_C = 8, K_KINDS = 12 };
+                  K_PR_ANALYSIS_C = 5, K_TR_ANALYSIS = 6, K_TR_ADJOINT = 7, K_TR_ANALYSIS_C = 8, K_PR_FUSED = 9, K_KINDS = 12 };
 
 // Brackets one launch with timing marks when timed (at most 8 per family).
 template <class F>
@@ -149,6 +160,16 @@ static int timed_launch(muffin_ctx* c, bool timed, int kind, F&& launch) {
 }
 
 static bool use_pairs(const muffin_ctx* c) { return c->gen == 2 && !(c->p.flags & MUFFIN_FLAG_SINGLE_SCALE); }
+
+// Plane k of U in the buffers of parity par (see muffin_ctx::upar): pointer and channel stride.
+static PlaneOut uplane(const muffin_ctx* c, int k, int par) {
+  if (c->fused && par && k >= c->jf) return PlaneOut{c->U2 + (long long)(k - c->jf) * c->us, 3 * c->us};
+  return PlaneOut{c->U + (long long)k * c->us, (long long)(c->J + 1) * c->us};
+}
+static PlaneRef uref(const muffin_ctx* c, int k, int par) {
+  const PlaneOut o = uplane(c, k, par);
+  return PlaneRef{o.p, o.cs};
+}
 
 // The band, pair and triple launches of the two IUWT phases, in order; j is the finest scale of a
 // launch.  Consecutive scales are grouped into one launch each, from the finest scale up: J = 1..6
@@ -176,7 +197,10 @@ static std::vector<IuwtStep> analysis_schedule(const muffin_ctx* c) {
     const bool last = k + 1 == groups.size() && coarse;
     switch (groups[k]) {
       case 3: v.push_back({last ? TR_ANALYSIS_C : TR_ANALYSIS, j, "analysis triple"}); break;
-      case 2: v.push_back({last ? PR_ANALYSIS_C : PR_ANALYSIS, j, "analysis pair"}); break;
+      case 2:
+        if (last && c->fused) v.push_back({PR_FUSED, j, "analysis pair + next adjoint pair"});
+        else v.push_back({last ? PR_ANALYSIS_C : PR_ANALYSIS, j, "analysis pair"});
+        break;
       default:
         if (c->gen == 1) v.push_back({SM_DETAIL1, j, "analysis"});
         else v.push_back({last ? DB_ANALYSIS_C : DB_ANALYSIS, j, "analysis"});
@@ -205,23 +229,30 @@ static std::vector<IuwtStep> adjoint_schedule(const muffin_ctx* c) {
 // Spatial adjoint of omega-weighted U; returns the buffer holding a = W_s^dagger (omega u).
 // Second generation: Horner steps a <- u_j + H_j (a - H_j u_j) from the coarsest scale down, two
 // scales per launch where possible.
-// Ubase: plane j of channel l at Ubase + l ucs + j ups.  The result has channel stride cs.
+// Ubase: plane j of channel l at Ubase + l ucs + j ups.  The result has channel stride cs.  With
+// carried, the first launch of the schedule is skipped and the Horner steps start from that plane
+// (channel stride cs): the fused tail of the last iteration has already run them.
 int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ups, long long ucs, float omega_c,
-                    const float** result, bool timed = false) {
+                    const float** result, bool timed = false, const float* carried = nullptr) {
   const int J = c->J;
   const long long np = c->cs;
   const float* a = Ubase + (long long)J * ups;  // coarse plane
   long long acs = ucs;
   float* bufs[2] = {c->cA, c->cB};
   int nb = 0;
-  if (omega_c != 1.f) {
+  std::vector<IuwtStep> sched = adjoint_schedule(c);
+  if (carried) {
+    sched.erase(sched.begin());
+    a = carried;
+    acs = np;
+  } else if (omega_c != 1.f) {
     MF_TRY(launch_pointwise(PT_COPY, c->N, c->L, pref(a, acs), PlaneRef{}, pout(c->cA, np), omega_c, 1.f, nullptr,
                             nullptr, c->st));
     a = c->cA;
     acs = np;
     nb = 1;
   }
-  for (const IuwtStep& st : adjoint_schedule(c)) {
+  for (const IuwtStep& st : sched) {
     float* dst = bufs[nb];
     const int j = st.j;
     const float* uj = Ubase + (long long)j * ups;
@@ -258,7 +289,7 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ups, long long 
 
 // Analysis of the channel images in (stride cs) fused with the spatial dual step on U; second
 // generation: two scales per launch where possible, the last one feeding the coarse plane's step.
-int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
+int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false, int par = 0) {
   const int J = c->J;
   const long long np = c->cs, us = c->us, ucs = (long long)(J + 1) * us;
   const float coef = (float)(c->sigma * c->p.mu_s);
@@ -274,6 +305,13 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false) {
     const int j = st.j;
     float* uj = c->U + (long long)j * us;
     switch (st.mode) {
+      case PR_FUSED:
+        MF_TRY(timed_launch(c, timed, K_PR_FUSED, [&] {
+          return launch_fused_pair(c->N, c->L, j, pref(cur, np), uref(c, j, par), uref(c, j + 1, par),
+                                   uref(c, J, par), uplane(c, j, par ^ 1), uplane(c, j + 1, par ^ 1),
+                                   uplane(c, J, par ^ 1), pout(c->Acar, np), coef, rho, coefc, c->st);
+        }));
+        break;
       case SM_DETAIL1:
         MF_TRY(launch_atrous(SM_DETAIL1, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
                              pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
@@ -356,17 +394,18 @@ int enqueue_spectral(muffin_ctx* c) {
 
 // With marks, phase boundaries are recorded in marks[0..4] and, for the second-generation
 // transform, each scale's fused adjoint (marks pass 1) or analysis launch is bracketed in kev.
-int enqueue_iteration(muffin_ctx* c, hipEvent_t* marks, int timed_family = 0) {
+// par: parity of the fused tail's planes at the start of the iteration (it flips at the end).
+int enqueue_iteration(muffin_ctx* c, hipEvent_t* marks, int timed_family = 0, int par = 0) {
   const long long ucs = (long long)(c->J + 1) * c->us;
   if (marks) MF_HIP(hipEventRecord(marks[0], c->st));
   const float* s = nullptr;
-  MF_TRY(enqueue_adjoint(c, c->U, c->us, ucs, c->omega_c, &s, timed_family == 1));
+  MF_TRY(enqueue_adjoint(c, c->U, c->us, ucs, c->omega_c, &s, timed_family == 1, c->fused ? c->Acar : nullptr));
   if (marks) MF_HIP(hipEventRecord(marks[1], c->st));
   MF_TRY(enqueue_gradient(c, c->X, c->Q, s, (float)c->p.mu_s));
   if (marks) MF_HIP(hipEventRecord(marks[2], c->st));
   MF_TRY(enqueue_spectral(c));
   if (marks) MF_HIP(hipEventRecord(marks[3], c->st));
-  MF_TRY(enqueue_dual_update(c, c->D, timed_family == 2));
+  MF_TRY(enqueue_dual_update(c, c->D, timed_family == 2, par));
   if (marks) MF_HIP(hipEventRecord(marks[4], c->st));
   return MUFFIN_OK;
 }
@@ -413,10 +452,12 @@ int enqueue_objective(muffin_ctx* c, int si) {
 void destroy(muffin_ctx* c) {
   if (!c) return;
   if (c->st) (void)hipStreamSynchronize(c->st);
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
+  for (int k = 0; k < 2; ++k) {
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+  }
   void* bufs[] = {c->X, c->U, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT, c->S, c->Hhat_T, c->P_T,
-                  c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres};
+                  c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres, c->U2, c->Acar};
   for (Seg& s : c->segs) {
     void* sb[] = {s.W, s.WT, s.twL, s.csL};
     for (void* b : sb)
@@ -496,6 +537,9 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   c->L = total;
   c->cube = c->cs * total;
   c->ucube = c->us * total * (c->J + 1);
+  c->fused = (p->flags & MUFFIN_FLAG_FUSED_TAIL) && use_pairs(c) && c->omega_c == 1.f && !iuwt_groups(c).empty() &&
+             iuwt_groups(c).back() == 2;
+  c->jf = c->J - 2;
   if (any_w) {
     c->chan_w_host.assign(total, 1.f);
     for (int i = 0; i < n; ++i)
@@ -516,6 +560,10 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   const long long spec = (long long)c->L * c->N * c->g.pitch;
   MF_TRY(dalloc(&c->X, cube));
   MF_TRY(dalloc(&c->U, c->ucube));
+  if (c->fused) {
+    MF_TRY(dalloc(&c->U2, c->us * total * 3));
+    MF_TRY(dalloc(&c->Acar, cube));
+  }
   MF_TRY(dalloc(&c->V, cube));
   MF_TRY(dalloc(&c->D, cube));
   MF_TRY(dalloc(&c->Q, cube));
@@ -548,6 +596,11 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   for (float* b : {c->X, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT})
     MF_HIP(hipMemsetAsync(b, 0, sizeof(float) * cube, st));
   MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, st));
+  if (c->fused) {
+    // U = 0: the carried adjoint sum of zero planes is exactly zero
+    MF_HIP(hipMemsetAsync(c->U2, 0, sizeof(float) * c->us * total * 3, st));
+    MF_HIP(hipMemsetAsync(c->Acar, 0, sizeof(float) * cube, st));
+  }
   for (int i = 0; i < n; ++i) {
     const long long off = (long long)c->segs[i].ch0 * c->cs;
     MF_TRY(planes_in(c, c->Y + off, dirty[i], c->segs[i].L, on_device));
@@ -628,20 +681,53 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   return MUFFIN_OK;
 }
 
-// Capture one iteration into a graph (capture records the work without running it).
+// Capture one iteration into a graph per parity of the fused tail's planes (capture records the
+// work without running it).
 int ensure_graph(muffin_ctx* c) {
-  if (c->gexec) return MUFFIN_OK;
-  MF_HIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-  const int rc = enqueue_iteration(c, nullptr);
-  hipGraph_t gr = nullptr;
-  const hipError_t e = hipStreamEndCapture(c->st, &gr);
-  if (rc != MUFFIN_OK) {
-    if (gr) (void)hipGraphDestroy(gr);
-    return rc;
+  for (int par = 0; par < (c->fused ? 2 : 1); ++par) {
+    if (c->gexec[par]) continue;
+    MF_HIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_iteration(c, nullptr, 0, par);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->st, &gr);
+    if (rc != MUFFIN_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    MF_HIP(e);
+    c->graph[par] = gr;
+    MF_HIP(hipGraphInstantiate(&c->gexec[par], c->graph[par], nullptr, nullptr, 0));
   }
-  MF_HIP(e);
-  c->graph = gr;
-  MF_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  return MUFFIN_OK;
+}
+
+void drop_graphs(muffin_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->gexec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+}
+
+// Before iterating: with a fused tail, the carried adjoint sum must match the current planes (it
+// does unless U was set from outside); recompute it with the plain adjoint pair if not.
+int ensure_carry(muffin_ctx* c) {
+  if (!c->fused || c->acar_ok) return MUFFIN_OK;
+  const int j = c->jf, par = c->upar;
+  MF_TRY(launch_pair(PR_ADJOINT, c->N, c->L, j, uref(c, j + 1, par), uref(c, j, par), uref(c, c->J, par),
+                     pout(c->Acar, c->cs), PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f, c->st));
+  c->acar_ok = true;
+  return MUFFIN_OK;
+}
+
+// n iterations by graph replay, the parity of the fused tail's planes flipping after each.
+int replay(muffin_ctx* c, int n) {
+  MF_TRY(ensure_carry(c));
+  for (int i = 0; i < n; ++i) {
+    MF_HIP(hipGraphLaunch(c->gexec[c->upar], c->st));
+    if (c->fused) c->upar ^= 1;
+  }
   return MUFFIN_OK;
 }
 
@@ -650,7 +736,9 @@ int ensure_graph(muffin_ctx* c) {
 int autotune(muffin_ctx* c, int reps, std::string& rep) {
   const long long np = c->cs, us = c->us, ucs = (long long)(c->J + 1) * us;
   std::vector<IuwtStep> sched = analysis_schedule(c);
-  for (const IuwtStep& st : adjoint_schedule(c)) sched.push_back(st);
+  std::vector<IuwtStep> adj = adjoint_schedule(c);
+  if (c->fused) adj.erase(adj.begin());  // run by the fused tail (the plain pair only as a prologue)
+  for (const IuwtStep& st : adj) sched.push_back(st);
   rep += "{\"N\": " + std::to_string(c->N) + ", \"channels\": " + std::to_string(c->L) + ", \"scales\": [";
   bool firstrep = true;
   for (const IuwtStep& L : sched) {
@@ -663,6 +751,10 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
       MF_TRY(atrous_set_band_rows(c->N, j, mode, TY));
       auto launch = [&]() -> int {
         switch (mode) {
+          case PR_FUSED:
+            return launch_fused_pair(c->N, c->L, j, pref(c->X, np), uref(c, j, c->upar), uref(c, j + 1, c->upar),
+                                     uref(c, c->J, c->upar), pout(c->cB, np), pout(c->cT, np), pout(c->cA, np),
+                                     pout(c->D, np), 0.f, 1.f, 0.f, c->st, 1);
           case PR_ANALYSIS:
           case PR_ANALYSIS_C:
             return launch_pair(mode, c->N, c->L, j, pref(c->X, np), PlaneRef{}, PlaneRef{}, pout(c->cB, np),
@@ -715,10 +807,7 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
   }
   rep += "]}";
   // recapture the iteration with the chosen tiles
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
-  c->gexec = nullptr;
-  c->graph = nullptr;
+  drop_graphs(c);
   return MUFFIN_OK;
 }
 
@@ -864,7 +953,7 @@ static int batch_run(muffin_batch* b, int n_iter, double* ms) {
   for (muffin_ctx* g : b->groups) {
     MF_HIP(hipStreamWaitEvent(g->st, b->e0, 0));
     MF_TRY(ensure_graph(g));
-    for (int i = 0; i < n_iter; ++i) MF_HIP(hipGraphLaunch(g->gexec, g->st));
+    MF_TRY(replay(g, n_iter));
     MF_HIP(hipEventRecord(g->ev_out, g->st));
     g->iter += n_iter;
   }
@@ -961,7 +1050,7 @@ int muffin_step(muffin_ctx* c, int32_t n_iter) {
   StreamScope scope(c);
   if (!scope.ok) return set_error("stream ordering failed"), MUFFIN_EHIP;
   MF_TRY(ensure_graph(c));
-  for (int i = 0; i < n_iter; ++i) MF_HIP(hipGraphLaunch(c->gexec, c->st));
+  MF_TRY(replay(c, n_iter));
   c->iter += n_iter;
   return MUFFIN_OK;
 }
@@ -971,8 +1060,9 @@ int muffin_step_timed(muffin_ctx* c, int32_t n_iter, double* ms) {
   StreamScope scope(c);
   if (!scope.ok) return set_error("stream ordering failed"), MUFFIN_EHIP;
   MF_TRY(ensure_graph(c));
+  MF_TRY(ensure_carry(c));
   MF_HIP(hipEventRecord(c->e0, c->st));
-  for (int i = 0; i < n_iter; ++i) MF_HIP(hipGraphLaunch(c->gexec, c->st));
+  MF_TRY(replay(c, n_iter));
   MF_HIP(hipEventRecord(c->e1, c->st));
   MF_HIP(hipEventSynchronize(c->e1));
   float t = 0.f;
@@ -988,11 +1078,13 @@ int muffin_profile(muffin_ctx* c, int32_t n_iter, double ms[32]) {
   StreamScope scope(c);
   double ksum[K_KINDS] = {};
   int kcnt[K_KINDS] = {}, fam_iters[3] = {0, 0, 0};
+  MF_TRY(ensure_carry(c));
   for (int it = 0; it < n_iter; ++it) {
     // alternate which kernel family is bracketed so the marks do not pile up in one iteration
     const int fam = c->gen == 2 ? 1 + (it & 1) : 0;
     c->nk = 0;
-    MF_TRY(enqueue_iteration(c, c->ph, fam));
+    MF_TRY(enqueue_iteration(c, c->ph, fam, c->upar));
+    if (c->fused) c->upar ^= 1;
     MF_HIP(hipEventSynchronize(c->ph[4]));
     float tph[4];
     for (int k = 0; k < 4; ++k) MF_HIP(hipEventElapsedTime(&tph[k], c->ph[k], c->ph[k + 1]));
@@ -1062,6 +1154,38 @@ int muffin_solve(muffin_ctx* c, int32_t max_iter, int32_t check_every, double to
   return MUFFIN_OK;
 }
 
+// U = 0 (with the fused tail: current planes in U, carried adjoint sum zero, which is exact).
+static int zero_dual(muffin_ctx* c) {
+  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, c->st));
+  if (c->fused) {
+    MF_HIP(hipMemsetAsync(c->Acar, 0, sizeof(float) * c->cube, c->st));
+    c->upar = 0;
+    c->acar_ok = true;
+  }
+  MF_HIP(hipMemsetAsync(c->V, 0, sizeof(float) * c->cube, c->st));
+  return MUFFIN_OK;
+}
+
+// U to or from the caller's dense [L][J+1][N][N] array.  With the fused tail's current planes
+// in U2, its three planes of every channel are copied on their own.
+static int u_out(muffin_ctx* c, float* dst, int on_device) {
+  MF_TRY(planes_out(c, dst, c->U, (long long)c->L * (c->J + 1), on_device, c->us));
+  if (c->fused && c->upar) {
+    const long long np = c->npix;
+    MF_TRY(copy_planes(dst + (long long)c->jf * np, (c->J + 1) * np, c->U2, 3 * c->us, c->L, 3 * np,
+                       on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st));
+  }
+  return MUFFIN_OK;
+}
+static int u_in(muffin_ctx* c, const float* src, int on_device) {
+  MF_TRY(planes_in(c, c->U, src, (long long)c->L * (c->J + 1), on_device, c->us));
+  if (c->fused) {
+    c->upar = 0;
+    c->acar_ok = false;  // recomputed before the next iteration
+  }
+  return MUFFIN_OK;
+}
+
 int muffin_info(muffin_ctx* c, double out[8]) {
   if (!c || !out) return set_error("bad arguments"), MUFFIN_EINVAL;
   const Seg& s = c->segs[0];
@@ -1081,9 +1205,7 @@ int muffin_set_x(muffin_ctx* c, const float* x0, int on_device) {
   StreamScope scope(c);
   MF_TRY(planes_in(c, c->X, x0, c->L, on_device));
   MF_TRY(launch_clamp_pos(c->X, c->cube, c->st));
-  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, c->st));
-  MF_HIP(hipMemsetAsync(c->V, 0, sizeof(float) * c->cube, c->st));
-  return MUFFIN_OK;
+  return zero_dual(c);
 }
 
 int muffin_get_x(muffin_ctx* c, float* x, int on_device) {
@@ -1094,7 +1216,7 @@ int muffin_get_x(muffin_ctx* c, float* x, int on_device) {
 int muffin_get_u(muffin_ctx* c, float* u, int on_device) {
   if (!c || !u) return set_error("bad arguments"), MUFFIN_EINVAL;
   StreamScope scope(c);
-  return planes_out(c, u, c->U, (long long)c->L * (c->J + 1), on_device, c->us);
+  return u_out(c, u, on_device);
 }
 int muffin_get_v(muffin_ctx* c, float* v, int on_device) {
   if (!c || !v) return set_error("bad arguments"), MUFFIN_EINVAL;
@@ -1130,7 +1252,7 @@ int muffin_get_state(muffin_ctx* c, void* blob, size_t bytes) {
   StreamScope scope(c);
   const long long dense = c->npix * c->L;  // the blob holds X, U, V in the dense layout
   MF_TRY(planes_out(c, f, c->X, c->L, 0));
-  MF_TRY(planes_out(c, f + dense, c->U, (long long)c->L * (c->J + 1), 0, c->us));
+  MF_TRY(u_out(c, f + dense, 0));
   MF_TRY(planes_out(c, f + dense * (c->J + 2), c->V, c->L, 0));
   return MUFFIN_OK;
 }
@@ -1149,7 +1271,7 @@ int muffin_set_state(muffin_ctx* c, const void* blob, size_t bytes) {
   StreamScope scope(c);
   const long long dense = c->npix * c->L;
   MF_TRY(planes_in(c, c->X, f, c->L, 0));
-  MF_TRY(planes_in(c, c->U, f + dense, (long long)c->L * (c->J + 1), 0, c->us));
+  MF_TRY(u_in(c, f + dense, 0));
   MF_TRY(planes_in(c, c->V, f + dense * (c->J + 2), c->L, 0));
   c->iter = h.iter;
   return MUFFIN_OK;
@@ -1165,9 +1287,7 @@ int muffin_warm_start(muffin_ctx* c, muffin_cnn* net) {
   MF_HIP(hipDeviceSynchronize());
   MF_TRY(planes_in(c, c->X, c->cB, c->L, 1));
   MF_TRY(launch_clamp_pos(c->X, c->cube, c->st));
-  MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, c->st));
-  MF_HIP(hipMemsetAsync(c->V, 0, sizeof(float) * c->cube, c->st));
-  return MUFFIN_OK;
+  return zero_dual(c);
 }
 
 int muffin_apply_op(muffin_ctx* c, int op, const float* in, float* out) {

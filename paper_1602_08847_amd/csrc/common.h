@@ -121,11 +121,19 @@ enum AtrousMode {
   // three consecutive scales j, j+1, j+2 in one pass (second generation):
   TR_ANALYSIS = 11,   // A = c_j; out, out2, out3 = u_j, u_{j+1}, u_{j+2} (dual updates); out4 = c_{j+3}
   TR_ANALYSIS_C = 12, // TR_ANALYSIS with c_{j+3} feeding the coarse plane's dual update (out4, coef2)
-  TR_ADJOINT = 13     // A = u_{j+2}, B = u_{j+1}, E = u_j, F = a: out = Horner steps j+2, j+1, j
+  TR_ADJOINT = 13,    // A = u_{j+2}, B = u_{j+1}, E = u_j, F = a: out = Horner steps j+2, j+1, j
+  // the last analysis pair (scales j, j+1, coarse plane) fused with the next iteration's first
+  // adjoint pair over the planes it has just updated:
+  PR_FUSED = 14       // A = c_j; B, E, F = old u_j, u_{j+1}, coarse; out, out2, out3 = new ones;
+                      // out4 = two Horner steps (scale j+1 then j) starting from the new coarse plane
 };
 // launch of a pair kernel: j is the finer scale of the pair
 int launch_pair(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out, PlaneOut out2,
                 PlaneOut out3, float coef, float rho, float coef2, hipStream_t st, int trial = 0);
+// launch of the fused pair (PR_FUSED): j is the finer scale of the pair
+int launch_fused_pair(int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneRef F, PlaneOut out,
+                      PlaneOut out2, PlaneOut out3, PlaneOut out4, float coef, float rho, float coef2,
+                      hipStream_t st, int trial = 0);
 // launch of a triple kernel: j is the finest of its three scales
 int launch_triple(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneRef F, PlaneOut out,
                   PlaneOut out2, PlaneOut out3, PlaneOut out4, float coef, float rho, float coef2, hipStream_t st,

@@ -838,6 +838,209 @@ __global__ void __launch_bounds__(1024) k_triple_trial(AtrousArgs a) {
   triple_body<MODE>(a);
 }
 
+// ------------------------------------------------------------------ fused pair
+// The last analysis pair of an iteration (scales j, j + 1 and the coarse plane's dual step) and
+// the first adjoint pair of the next iteration, which works on exactly the planes the analysis
+// has just updated, in one pass.  With t the load index of c_j:
+//   analysis:  c1 = H_j c (t - 2), w_j (t - 4), c2 = H_{j+1} c1 (t - 6), w_{j+1} (t - 10), giving
+//              the new u_j (t - 4), coarse plane u_c (t - 6) and u_{j+1} (t - 10)
+//   adjoint, one step behind, on those values (index T = t - 11 of u_{j+1}):
+//              h = H_{j+1} u_{j+1} (T - 4), a' = u_{j+1} + H_{j+1}(u_c - h) (T - 8),
+//              a'' = u_j + H_j(a' - H_j u_j) (T - 10 = t - 21)
+// The new u_j and u_c wait 13 and 9 steps until the adjoint reaches them, in LDS rings of one
+// slot per step (each thread reads back only what it wrote, so the rings need no barrier).  The four stages of a step share three LDS barriers: the analysis and adjoint stages of
+// one phase read rows written in the phase before.  The old planes are read from B, E, F and the
+// new ones written to out, out2, out3, so a band's halo always reads the values its neighbours
+// are replacing; a'' goes to out4.  Every stage repeats the operations of the analysis pair and
+// the adjoint pair in their order: planes and a'' are bit-identical to the two launches.
+struct FusedPre {
+  float p0, p1, p2, p3;
+};
+
+__device__ __forceinline__ void fused_body(const AtrousArgs& a) {
+  constexpr int HALO = 20;  // 10 class steps for the analysis, 10 for the adjoint
+  constexpr int SKEW = 1;   // the adjoint stages run one step behind
+  extern __shared__ float sm[];
+  const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
+  float* bA = sm;  // analysis rows
+  float* bB = sm + N;
+  float* bC = sm + 2 * N;
+  float* bD = sm + 3 * N;
+  float* qA = sm + 4 * N;  // adjoint rows
+  float* qB = sm + 5 * N;
+  float* qC = sm + 6 * N;
+  float* qD = sm + 7 * N;
+  constexpr int DJ = 13, DC = 9;  // delays of the new u_j and u_c
+  float* ringJ = sm + 8 * N;      // [DJ][N]
+  float* ringC = sm + (8 + DJ) * N;  // [DC][N]
+  const int b = xcd_remap(blockIdx.x, a.nblocks);
+  const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
+  const int y0 = band * TY;
+  const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
+  const char* __restrict__ Bp = reinterpret_cast<const char*>(a.B.p + ch * a.B.cs);
+  const char* __restrict__ Ep = reinterpret_cast<const char*>(a.E.p + ch * a.E.cs);
+  const char* __restrict__ Fp = reinterpret_cast<const char*>(a.F.p + ch * a.F.cs);
+  float* __restrict__ O = a.out.p + ch * a.out.cs;
+  float* __restrict__ O2 = a.out2.p + ch * a.out2.cs;
+  float* __restrict__ O3 = a.out3.p + ch * a.out3.cs;
+  float* __restrict__ O4 = a.out4.p + ch * a.out4.cs;
+  auto modx = [&](int v) { return (v % N + N) % N; };
+  const int xm1 = modx(x - s), xm2 = modx(x - 2 * s), xm4 = modx(x - 4 * s);
+  const int xp1 = modx(x + s), xp2 = modx(x + 2 * s), xp4 = modx(x + 4 * s);
+  auto hj = [&](const float* row) { return b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]); };
+  auto hj1 = [&](const float* row) { return b3(row[xm4], row[xm2], row[x], row[xp2], row[xp4]); };
+  const int rowb = N * 4, planeb = N * N * 4, stepb = (s % N) * rowb;
+  const unsigned xb = (unsigned)x * 4u;
+  auto at = [&](const char* base, int off) -> float {
+    return *reinterpret_cast<const float*>(base + off + xb);
+  };
+  auto put = [&](float* base, int y, float v) {
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
+  };
+  auto upd = [&](float u, float w, float coef) { return dual_upd(u, w, coef, a.rho); };
+  auto nsteps = [&](int r) -> int {
+    const int v = TY - r;
+    return v > 0 ? ((v + s - 1) >> jj) + 2 * HALO + SKEW : 0;
+  };
+  auto rowoff = [&](int y) -> int {
+    y %= N;
+    return (y < 0 ? y + N : y) * rowb;
+  };
+  auto adv = [&](int& o) {
+    o += stepb;
+    if (o >= planeb) o -= planeb;
+  };
+  // load streams: p0 c (t), p1 old u_j (t - 4), p2 old u_{j+1} (t - 10), p3 old coarse (t - 6)
+  int lr = 0, lt = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+  auto start_class = [&](int r) {
+    const int f = y0 + r - HALO * s;
+    o0 = rowoff(f);
+    o1 = rowoff(f - 4 * s);
+    o2 = rowoff(f - 10 * s);
+    o3 = rowoff(f - 6 * s);
+  };
+  auto load_step = [&](FusedPre& P) {
+    P.p0 = at(A, o0);
+    P.p1 = at(Bp, o1);
+    P.p2 = at(Ep, o2);
+    P.p3 = at(Fp, o3);
+    adv(o0);
+    adv(o1);
+    adv(o2);
+    adv(o3);
+  };
+  auto advance_load = [&]() {
+    ++lt;
+    if (lt >= nsteps(lr)) {
+      lt = 0;
+      do {
+        ++lr;
+      } while (lr < s && nsteps(lr) == 0);
+      if (lr < s) start_class(lr);
+    }
+  };
+  // windows, oldest first.  Analysis: wc c (t-4..t), wa c1 (t-10..t-2), wb c2 (t-14..t-6).
+  // Adjoint: ya u_{j+1} (T-8..T), yc u_j (T-10..T-6), yb u_c - h (T-12..T-4), yd a' - H_j u_j
+  // (T-12..T-8).
+  float wc[5], wa[9], wb[9], ya[9], yb[9], yc[5], yd[5];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) wa[i] = wb[i] = ya[i] = yb[i] = 0.f;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) wc[i] = yc[i] = yd[i] = 0.f;
+  // ring slots of the current step; the new u_{j+1} of the last step
+#pragma unroll
+  for (int i = 0; i < DJ; ++i) ringJ[i * N + x] = 0.f;
+#pragma unroll
+  for (int i = 0; i < DC; ++i) ringC[i * N + x] = 0.f;
+  int rj = 0, rc = 0;
+  float pend1 = 0.f;
+  auto push = [](auto& w, float v) {
+    constexpr int n = sizeof(w) / sizeof(w[0]);
+#pragma unroll
+    for (int i = 0; i < n - 1; ++i) w[i] = w[i + 1];
+    w[n - 1] = v;
+  };
+  auto v9 = [](const float (&w)[9]) { return b3(w[0], w[2], w[4], w[6], w[8]); };
+  auto v5 = [](const float (&w)[5]) { return b3(w[0], w[1], w[2], w[3], w[4]); };
+  // step t of a class with ns steps whose load index 0 is row first; index i is a row of the band
+  // when HALO <= i < ns - HALO - SKEW
+  auto process = [&](const FusedPre& cur, int t, int ns, int first) {
+    const int lo = HALO, hi = ns - HALO - SKEW;
+    // phase 1: analysis H_j of c (vertical); adjoint H_{j+1} of u_{j+1} and H_j of u_j (vertical)
+    push(wc, cur.p0);
+    const float cc4 = wc[0];
+    bA[x] = v5(wc);
+    push(ya, pend1);
+    const float cuh = ya[0];
+    qA[x] = v9(ya);
+    push(yc, ringJ[rj * N + x]);  // u_j of 13 steps ago
+    const float cul = yc[0];
+    qB[x] = v5(yc);
+    lds_barrier();
+    // phase 2: c1, the vertical parts of H_j c1 and H_{j+1} c1; u_c - H_{j+1} u_{j+1}
+    push(wa, hj(bA));
+    const float cc10 = wa[0];
+    bB[x] = b3(wa[4], wa[5], wa[6], wa[7], wa[8]);
+    bC[x] = v9(wa);
+    const float h1 = hj1(qA);
+    const float h0 = hj(qB);
+    push(yb, ringC[rc * N + x] - h1);  // u_c of 9 steps ago
+    qC[x] = v9(yb);
+    lds_barrier();
+    // phase 3: new u_j and coarse plane, vertical H_{j+1} of c2; a' and a' - H_j u_j
+    const float nuj = upd(cur.p1, cc4 - hj(bB), a.coef);
+    if (t - 4 >= lo && t - 4 < hi) put(O, first + (t - 4) * s, nuj);
+    const float c2 = hj1(bC);
+    const float nuc = upd(cur.p3, c2, a.coef2);
+    if (t - 6 >= lo && t - 6 < hi) put(O3, first + (t - 6) * s, nuc);
+    push(wb, c2);
+    bD[x] = v9(wb);
+    const float a1 = cuh + hj1(qC);
+    push(yd, a1 - h0);
+    qD[x] = v5(yd);
+    ringJ[rj * N + x] = nuj;
+    ringC[rc * N + x] = nuc;
+    rj = rj + 1 == DJ ? 0 : rj + 1;
+    rc = rc + 1 == DC ? 0 : rc + 1;
+    lds_barrier();
+    // phase 4: new u_{j+1}; a''
+    const float nu1 = upd(cur.p2, cc10 - hj1(bD), a.coef);
+    if (t - 10 >= lo && t - 10 < hi) put(O2, first + (t - 10) * s, nu1);
+    pend1 = nu1;
+    if (t - 21 >= lo && t - 21 < hi) put(O4, first + (t - 21) * s, cul + hj(qD));
+  };
+  int r = 0;
+  while (r < s && nsteps(r) == 0) ++r;
+  if (r < s) {
+    lr = r;
+    start_class(lr);
+    int pt = 0, pns = nsteps(r), pfirst = y0 + r - HALO * s;
+    FusedPre cur, nxt;
+    load_step(cur);
+    advance_load();
+    while (true) {
+      load_step(nxt);  // past the last class: further rows of the planes, unused
+      advance_load();
+      process(cur, pt, pns, pfirst);
+      if (++pt >= pns) {
+        do {
+          ++r;
+        } while (r < s && nsteps(r) == 0);
+        if (r >= s) break;
+        pt = 0;
+        pns = nsteps(r);
+        pfirst = y0 + r - HALO * s;
+      }
+      cur = nxt;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_fused(AtrousArgs a) { fused_body(a); }
+constexpr int kFusedRows = 8 + 13 + 9;  // LDS rows of N floats: eight stage rows, the two rings
+
+__global__ void __launch_bounds__(1024) k_fused_trial(AtrousArgs a) { fused_body(a); }
+
 constexpr int kKR = 8;   // rows per round, single-smoothing modes
 constexpr int kKR2 = 4;  // rows per round, double-smoothing modes (keeps them within 128 VGPRs)
 constexpr int kKRP = 2;  // rows per round, pair kernels (keeps them within 128 VGPRs)
@@ -893,6 +1096,7 @@ int atrous_class(int mode) {
     case TR_ANALYSIS:
     case TR_ANALYSIS_C: return 7;
     case TR_ADJOINT: return 8;
+    case PR_FUSED: return 9;
     default: return 4;
   }
 }
@@ -901,7 +1105,7 @@ int atrous_band_rows(int N, int j, int mode) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(tune_key(N, j, atrous_class(mode)));
   if (it != g_tune.end()) return it->second;
-  if (is_triple(mode)) return triple_rows_default(N, j);
+  if (is_triple(mode) || mode == PR_FUSED) return triple_rows_default(N, j);  // halos of 21 and 22 steps
   return is_pair(mode) ? pair_rows_default(N, j) : band_rows_default(N, j);
 }
 
@@ -1069,6 +1273,39 @@ int launch_triple(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   return MUFFIN_OK;
 }
 
+int launch_fused_pair(int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneRef F, PlaneOut out,
+                      PlaneOut out2, PlaneOut out3, PlaneOut out4, float coef, float rho, float coef2,
+                      hipStream_t st, int trial) {
+  if (N > 1024) return set_error("fused pair: N > 1024"), MUFFIN_EINVAL;
+  AtrousArgs a{};
+  a.A = A;
+  a.B = B;
+  a.E = E;
+  a.F = F;
+  a.out = out;
+  a.out2 = out2;
+  a.out3 = out3;
+  a.out4 = out4;
+  a.N = N;
+  a.j = j;
+  a.coef = coef;
+  a.rho = rho;
+  a.coef2 = coef2;
+  a.TX = N;
+  a.TY = atrous_band_rows(N, j, PR_FUSED);
+  a.tiles_x = 1;
+  a.tiles_per_ch = N / a.TY;
+  const long long nb = (long long)a.tiles_per_ch * nch;
+  if (nb > 0x7fffffffLL) return set_error("fused pair: grid too large"), MUFFIN_EINVAL;
+  a.nblocks = (int)nb;
+  const size_t shm = sizeof(float) * kFusedRows * (size_t)N;
+  const dim3 grid((unsigned)nb), block((unsigned)N);
+  if (trial) hipLaunchKernelGGL(k_fused_trial, grid, block, shm, st, a);
+  else hipLaunchKernelGGL(k_fused, grid, block, shm, st, a);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
 int atrous_init_attrs() {
   const int shm = (int)(sizeof(float) * 2 * kKR * 1024);
   MF_HIP(hipFuncSetAttribute((const void*)k_band<SM_SMOOTH, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
@@ -1096,6 +1333,9 @@ int atrous_init_attrs() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_SUBADD, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              shm));
+  const int shmf = (int)(sizeof(float) * kFusedRows * 1024);
+  MF_HIP(hipFuncSetAttribute((const void*)k_fused, hipFuncAttributeMaxDynamicSharedMemorySize, shmf));
+  MF_HIP(hipFuncSetAttribute((const void*)k_fused_trial, hipFuncAttributeMaxDynamicSharedMemorySize, shmf));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_DETAIL1, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<DB_ANALYSIS, kKR2>,

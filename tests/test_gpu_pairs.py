@@ -1,8 +1,8 @@
-"""Two or three IUWT scales per launch against one scale per launch: the fused pair and triple kernels
-perform the same operations in the same order, so the iterates agree bit for bit, for every J
-(schedules of singles, pairs and triples, each with or without the coarse plane), with and without
-the coarse plane's penalty, with relaxation, and for image sides where the coarse taps wrap around
-the image several times."""
+"""Two or three IUWT scales per launch, and the last analysis pair fused with the next iteration's
+first adjoint pair, against one scale per launch: the fused kernels perform the same operations in
+the same order, so the iterates agree bit for bit, for every J (schedules of singles, pairs and
+triples, each with or without the coarse plane), with and without the coarse plane's penalty, with
+relaxation, and for image sides where the coarse taps wrap around the image several times."""
 import numpy as np
 import pytest
 
@@ -30,19 +30,22 @@ def test_pairs_match_single_scale_bitwise(lib, N, L, J, pc, rho):
     c = synth.make_cube(synth.CubeSpec(N=N, L=L, J=J, n_sources=max(2, N // 16), n_baselines=max(8, N * 2),
                                        seed=N + J))
     out = {}
-    for flags in (0, lib.FLAG_SINGLE_SCALE):
+    for flags in (0, lib.FLAG_FUSED_TAIL, lib.FLAG_SINGLE_SCALE):
         with lib.Muffin(c.dirty, c.psf, J=J, mu_s=0.25, mu_lambda=3.0, penalize_coarse=pc, sigma=10.0, rho=rho,
                         flags=flags) as m:
-            m.step(7)
+            m.step(7)  # odd: the fused tail's planes end in its second buffer
             out[flags] = (m.get_x().cpu().numpy(), m.get_u().cpu().numpy(), m.get_v().cpu().numpy())
-    for a, b in zip(out[0], out[lib.FLAG_SINGLE_SCALE]):
-        np.testing.assert_array_equal(a, b)
+    for flags in (0, lib.FLAG_FUSED_TAIL):
+        for a, b in zip(out[flags], out[lib.FLAG_SINGLE_SCALE]):
+            np.testing.assert_array_equal(a, b)
 
 
-def test_pairs_autotuned_match_single_scale(lib):
+@pytest.mark.parametrize("flags", [0, 2])
+def test_pairs_autotuned_match_single_scale(lib, flags):
     c = synth.make_cube(synth.CubeSpec(N=128, L=6, J=5, n_sources=6, n_baselines=300, seed=9))
     kw = dict(J=5, mu_s=0.25, mu_lambda=3.0, sigma=10.0)
-    with lib.Muffin(c.dirty, c.psf, **kw) as a, lib.Muffin(c.dirty, c.psf, flags=lib.FLAG_SINGLE_SCALE, **kw) as b:
+    with lib.Muffin(c.dirty, c.psf, flags=flags, **kw) as a, \
+            lib.Muffin(c.dirty, c.psf, flags=lib.FLAG_SINGLE_SCALE, **kw) as b:
         a.autotune(reps=1)
         a.step(5)
         b.step(5)
@@ -50,12 +53,16 @@ def test_pairs_autotuned_match_single_scale(lib):
 
 
 # launch kinds: 0 one analysis scale, 1 one adjoint step, 2 last analysis scale with the coarse plane,
-# 3/4/5 the same for pairs, 6/7/8 for triples
-@pytest.mark.parametrize("J,counts", [(5, {6: 1, 5: 1, 4: 1, 7: 1}), (4, {3: 1, 4: 2, 5: 1}),
-                                      (3, {8: 1, 7: 1}), (6, {6: 1, 8: 1, 7: 2}), (1, {2: 1, 1: 1})])
-def test_profile_reports_the_launch_schedule(lib, J, counts):
+# 3/4/5 the same for pairs, 6/7/8 for triples, 9 the last analysis pair fused with the next
+# iteration's first adjoint pair (coarse plane penalised, last group a pair)
+@pytest.mark.parametrize("J,pc,flags,counts", [
+    (5, True, 0, {6: 1, 5: 1, 4: 1, 7: 1}), (4, True, 0, {3: 1, 4: 2, 5: 1}), (2, True, 0, {5: 1, 4: 1}),
+    (3, True, 0, {8: 1, 7: 1}), (6, True, 0, {6: 1, 8: 1, 7: 2}), (1, True, 0, {2: 1, 1: 1}),
+    (5, True, 2, {6: 1, 9: 1, 7: 1}), (4, True, 2, {3: 1, 9: 1, 4: 1}), (2, True, 2, {9: 1}),
+    (5, False, 2, {6: 1, 3: 1, 4: 1, 7: 1}), (3, True, 2, {8: 1, 7: 1})])
+def test_profile_reports_the_launch_schedule(lib, J, pc, flags, counts):
     c = synth.make_cube(synth.CubeSpec(N=128, L=4, J=J, n_sources=3, n_baselines=100, seed=2))
-    with lib.Muffin(c.dirty, c.psf, J=J, mu_s=0.25, mu_lambda=3.0) as m:
+    with lib.Muffin(c.dirty, c.psf, J=J, mu_s=0.25, mu_lambda=3.0, penalize_coarse=pc, flags=flags) as m:
         ms = m.profile(4)
     assert len(ms) == 32 and np.all(ms[5:8] == 0)
     for k in range(12):

@@ -136,9 +136,12 @@ def test_closed_form_spectral_soft_threshold(lib):
         np.testing.assert_allclose(m.get_x().cpu().numpy(), expect, atol=2e-4)
 
 
-def test_checkpoint_resume_is_bitwise(lib, small):
+# with the fused tail (J = 4 and 5) the checkpoint is taken with its planes in the second buffer (7
+# iterations), and the carried adjoint sum is rebuilt after set_state
+@pytest.mark.parametrize("J,flags", [(3, 0), (5, 0), (4, 2), (5, 2)])
+def test_checkpoint_resume_is_bitwise(lib, small, J, flags):
     c = small
-    kw = dict(J=3, mu_s=0.25, mu_lambda=3.0)
+    kw = dict(J=J, mu_s=0.25, mu_lambda=3.0, flags=flags)
     with lib.Muffin(c.dirty, c.psf, **kw) as a:
         a.step(7)
         blob = a.get_state()
@@ -162,14 +165,19 @@ def test_checkpoint_rejects_other_parameters(lib, small):
         assert e.value.code == lib.ESTATE
 
 
-def test_graph_replay_equals_eager_launches(lib, small):
+@pytest.mark.parametrize("J,flags", [(3, 0), (5, 0), (5, 2)])
+def test_graph_replay_equals_eager_launches(lib, small, J, flags):
     c = small
-    kw = dict(J=3, mu_s=0.25, mu_lambda=3.0)
+    kw = dict(J=J, mu_s=0.25, mu_lambda=3.0, flags=flags)
     with lib.Muffin(c.dirty, c.psf, **kw) as a, lib.Muffin(c.dirty, c.psf, **kw) as b:
-        a.step(6)
-        b.profile(6)
+        a.step(5)
+        b.profile(5)
         np.testing.assert_array_equal(a.get_x().cpu().numpy(), b.get_x().cpu().numpy())
+        np.testing.assert_array_equal(a.get_u().cpu().numpy(), b.get_u().cpu().numpy())
         np.testing.assert_array_equal(a.get_v().cpu().numpy(), b.get_v().cpu().numpy())
+        a.step(2)  # the two paths also continue alike
+        b.step(2)
+        np.testing.assert_array_equal(a.get_x().cpu().numpy(), b.get_x().cpu().numpy())
 
 
 def test_error_paths(lib, small):
