@@ -77,35 +77,26 @@ MEASURED_TRAFFIC = {
     "k_triple<TR_ANALYSIS> (three scales of analysis + spatial dual steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "48b3f0079106265a",
-        "fetch_kib": 2191452.4,
+        "sha256": "d88f4e8cc9086415",
+        "fetch_kib": 2201710.2,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     },
-    "k_pair<PR_ANALYSIS_C> (last two analysis scales + spatial and coarse dual steps)": {
+    "k_fused (last analysis pair + next iteration's first adjoint pair)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "48b3f0079106265a",
-        "fetch_kib": 2428977.5,
-        "write_kib": 3145728.0,
-        "fetch_factor": 2.0,
-        "write_factor": 1.0
-    },
-    "k_pair<PR_ADJOINT> (two adjoint Horner steps)": {
-        "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "48b3f0079106265a",
-        "fetch_kib": 1821747.5,
-        "write_kib": 1048576.0,
+        "sha256": "d88f4e8cc9086415",
+        "fetch_kib": 2857076.4,
+        "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     },
     "k_triple<TR_ADJOINT> (three adjoint Horner steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "48b3f0079106265a",
-        "fetch_kib": 2197551.5,
+        "sha256": "d88f4e8cc9086415",
+        "fetch_kib": 2201697.5,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -113,8 +104,8 @@ MEASURED_TRAFFIC = {
     "k_spectral_fft (fused spectral step)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/spectral.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/fft_core.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "418885c69537c3f6",
-        "fetch_kib": 1573123.2,
+        "sha256": "3fe679042eef52ec",
+        "fetch_kib": 1573124.6,
         "write_kib": 3145728.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -172,6 +163,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cube1024_L256_J5")
     ap.add_argument("--gen", type=int, default=2)
+    ap.add_argument("--flags", type=int, default=0, help="library flags (1: one IUWT scale per launch, 2: no fused tail)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=6)
     ap.add_argument("--autotune", type=int, default=1, help="1: tune the band kernels' row bands first")
@@ -197,7 +189,7 @@ def main():
     dirty = torch.from_numpy(cube.dirty).cuda()
     psf = torch.from_numpy(cube.psf).cuda()
     del cube
-    m = muffin.Muffin(dirty, psf, J=J, mu_s=0.25, mu_lambda=3.0, iuwt_gen=args.gen)
+    m = muffin.Muffin(dirty, psf, J=J, mu_s=0.25, mu_lambda=3.0, iuwt_gen=args.gen, flags=args.flags)
     del dirty, psf
     torch.cuda.synchronize()
     print(f"[bench] context ready, tau={m.info()['tau']:.3e}", file=sys.stderr, flush=True)
@@ -277,7 +269,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "N": N, "L": L, "J": J, "iuwt_gen": args.gen,
-                   "sources": spec.n_sources, "baselines": spec.n_baselines},
+                   "sources": spec.n_sources, "baselines": spec.n_baselines, "flags": args.flags},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

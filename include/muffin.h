@@ -51,13 +51,12 @@ typedef struct muffin_ctx muffin_ctx;
 /* Run the IUWT one launch per scale instead of fusing two or three consecutive scales into one
  * launch (the results are the same bit for bit; the fused form moves fewer bytes). */
 #define MUFFIN_FLAG_SINGLE_SCALE 1
-/* End each iteration's analysis with one launch that also runs the next iteration's first two
- * adjoint steps over the planes it has just updated (second generation, coarse plane penalised,
- * last scale group a pair; otherwise ignored).  Same results bit for bit, 12 bytes per voxel
- * fewer; it keeps a second copy of three dual planes.  Off by default: on MI355X the band kernels
- * are limited by instruction issue rather than HBM, and the fused launch costs about as much as
- * the two it replaces plus its longer halo. */
-#define MUFFIN_FLAG_FUSED_TAIL 2
+/* By default (second generation, coarse plane penalised, last scale group a pair) each
+ * iteration's analysis ends with one launch that also runs the next iteration's first two adjoint
+ * steps over the planes it has just updated: 12 bytes per voxel fewer, the same results bit for
+ * bit, and a second copy of three dual planes in memory.  This flag runs the two launches
+ * separately instead. */
+#define MUFFIN_FLAG_NO_FUSED_TAIL 2
 
 /* Problem and algorithm parameters (Sec. 2 eqs. (reg), (RegAll); Sec. 3, Algorithm 1). */
 typedef struct {

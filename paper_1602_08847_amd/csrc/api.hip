@@ -76,8 +76,8 @@ struct muffin_ctx {
   double sigma = 1, rho = 1, Ws2 = 0;
   float omega_c = 1.f;
   long long iter = 0;
-  // Fused tail (MUFFIN_FLAG_FUSED_TAIL; second generation, coarse plane penalised, last group a
-  // pair): the last analysis
+  // Fused tail (unless MUFFIN_FLAG_NO_FUSED_TAIL; second generation, coarse plane penalised, last
+  // group a pair): the last analysis
   // launch also runs the next iteration's first adjoint pair on the planes it has just updated
   // (PR_FUSED).  Those three planes (scales jf, jf + 1 and the coarse plane) alternate between U
   // and U2 ([L][3] planes, us floats apart) from one iteration to the next, so that a band's halo
@@ -124,7 +124,8 @@ int validate(const muffin_params* p) {
   if (!fft_supported(p->N)) return set_error("N must be 2^a or 3*2^a with 8 <= N <= 1024"), MUFFIN_EINVAL;
   if (p->L < 1 || p->L > 512) return set_error("L must be in [1, 512]"), MUFFIN_EINVAL;
   if (p->J < 1 || p->J > 6) return set_error("J must be in [1, 6]"), MUFFIN_EINVAL;
-  if (p->flags & ~(MUFFIN_FLAG_SINGLE_SCALE | MUFFIN_FLAG_FUSED_TAIL)) return set_error("unknown flags"), MUFFIN_EINVAL;
+  if (p->flags & ~(MUFFIN_FLAG_SINGLE_SCALE | MUFFIN_FLAG_NO_FUSED_TAIL))
+    return set_error("unknown flags"), MUFFIN_EINVAL;
   if (p->iuwt_gen != 1 && p->iuwt_gen != 2) return set_error("iuwt_gen must be 1 or 2"), MUFFIN_EINVAL;
   if (p->penalize_coarse != 0 && p->penalize_coarse != 1)
     return set_error("penalize_coarse must be 0 or 1"), MUFFIN_EINVAL;
@@ -537,8 +538,8 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   c->L = total;
   c->cube = c->cs * total;
   c->ucube = c->us * total * (c->J + 1);
-  c->fused = (p->flags & MUFFIN_FLAG_FUSED_TAIL) && use_pairs(c) && c->omega_c == 1.f && !iuwt_groups(c).empty() &&
-             iuwt_groups(c).back() == 2;
+  c->fused = !(p->flags & MUFFIN_FLAG_NO_FUSED_TAIL) && use_pairs(c) && c->omega_c == 1.f &&
+             !iuwt_groups(c).empty() && iuwt_groups(c).back() == 2;
   c->jf = c->J - 2;
   if (any_w) {
     c->chan_w_host.assign(total, 1.f);

@@ -17,6 +17,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 namespace mf {
 
@@ -574,33 +575,38 @@ struct TriPre {
   float p0, p1, p2, p3, p4;
 };
 
-template <int MODE>
-__device__ __forceinline__ void triple_body(const AtrousArgs& a) {
-  constexpr bool ADJ = (MODE == TR_ADJOINT);
-  constexpr bool CO = (MODE == TR_ANALYSIS_C);
-  constexpr int HALO = 22;
-  // the adjoint runs its four stages skewed over four consecutive steps (one barrier per step,
-  // double-buffered LDS); the analysis runs them one after the other within a step
-  constexpr int SKEW = ADJ ? 4 : 0;
+// compile-time step residue of an unrolled step loop
+template <int P>
+using Phase = std::integral_constant<int, P>;
+
+// Analysis triple, skewed: at step T it runs stage 1 of step T, stage 2 of T - 1, ..., stage 5 of
+// T - 4, each stage reading the LDS rows the stage before it wrote in the previous step (two sets
+// of rows, by step parity), so one barrier per step serves all five.  With t the step a stage
+// works for and c loaded at index t:
+//   S1: c into the window of H_j (vertical part of c1 = H_j c at t - 2)
+//   S2: c1 (t - 2); vertical parts of H_j c1 (t - 4) and of c2 = H_{j+1} c1 (t - 6)
+//   S3: w_j = c - H_j c1 (t - 4) and the dual step of u_j; c2 (t - 6); vertical parts of
+//       H_{j+1} c2 (t - 10) and of c3 = H_{j+2} c2 (t - 14)
+//   S4: w_{j+1} = c1 - H_{j+1} c2 (t - 10) and the dual step of u_{j+1}; c3 (t - 14), stored (or
+//       the coarse plane's dual step); vertical part of H_{j+2} c3 (t - 22)
+//   S5: w_{j+2} = c2 - H_{j+2} c3 (t - 22) and the dual step of u_{j+2}
+// c, c1 and c2 wait two steps between the stage that has them and the one that uses them (two-slot
+// rings), and the u streams are loaded at the indices where their stage reaches them.  The windows
+// are phase windows as in the adjoint triple (the loop is unrolled four times), and the operations
+// are those of the one-scale kernels in their order.
+template <int RS, bool CO>
+__device__ __forceinline__ void triple_an_body(const AtrousArgs& a) {
+  constexpr int HALO = 22, SKEW = 4;
   extern __shared__ float sm[];
   const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
-  float* bA = sm;
-  float* bB = sm + N;
-  float* bC = sm + 2 * N;
-  float* bD = sm + 3 * N;
-  float* bE = sm + 4 * N;
-  float* bF = sm + 5 * N;
   const int b = xcd_remap(blockIdx.x, a.nblocks);
   const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
   const int y0 = band * TY;
   const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
-  const char* __restrict__ Bp = ADJ ? reinterpret_cast<const char*>(a.B.p + ch * a.B.cs) : nullptr;
-  const char* __restrict__ Ep = ADJ ? reinterpret_cast<const char*>(a.E.p + ch * a.E.cs) : nullptr;
-  const char* __restrict__ Fp = ADJ ? reinterpret_cast<const char*>(a.F.p + ch * a.F.cs) : nullptr;
   float* __restrict__ O = a.out.p + ch * a.out.cs;
-  float* __restrict__ O2 = ADJ ? nullptr : a.out2.p + ch * a.out2.cs;
-  float* __restrict__ O3 = ADJ ? nullptr : a.out3.p + ch * a.out3.cs;
-  float* __restrict__ O4 = ADJ ? nullptr : a.out4.p + ch * a.out4.cs;
+  float* __restrict__ O2 = a.out2.p + ch * a.out2.cs;
+  float* __restrict__ O3 = a.out3.p + ch * a.out3.cs;
+  float* __restrict__ O4 = a.out4.p + ch * a.out4.cs;
   auto modx = [&](int v) { return (v % N + N) % N; };
   const int xm1 = modx(x - s), xm2 = modx(x - 2 * s), xm4 = modx(x - 4 * s), xm8 = modx(x - 8 * s);
   const int xp1 = modx(x + s), xp2 = modx(x + 2 * s), xp4 = modx(x + 4 * s), xp8 = modx(x + 8 * s);
@@ -616,8 +622,6 @@ __device__ __forceinline__ void triple_body(const AtrousArgs& a) {
     *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
   };
   auto upd = [&](float u, float w, float coef) { return dual_upd(u, w, coef, a.rho); };
-  // steps of class r: its M rows plus the halo on both sides, plus SKEW steps that drain the
-  // skewed stages
   auto nsteps = [&](int r) -> int {
     const int v = TY - r;
     return v > 0 ? ((v + s - 1) >> jj) + 2 * HALO + SKEW : 0;
@@ -630,10 +634,9 @@ __device__ __forceinline__ void triple_body(const AtrousArgs& a) {
     o += stepb;
     if (o >= planeb) o -= planeb;
   };
-  // load streams (load index of step t):
-  //   analysis  p0 c (t), p1 u_j (t - 4), p2 u_{j+1} (t - 10), p3 u_{j+2} (t - 22), p4 coarse (t - 14)
-  //   adjoint   p0 u_{j+2} (t), p1 a (t - 8), p2 u_{j+1} (t - 12), p3 u_j (t - 18)
-  constexpr int D1 = ADJ ? 8 : 4, D2 = ADJ ? 12 : 10, D3 = ADJ ? 18 : 22, D4 = 14;
+  // load streams (load index of step T): p0 c (T), p1 u_j (T - 6), p2 u_{j+1} (T - 13),
+  // p3 u_{j+2} (T - 26), p4 coarse plane (T - 17)
+  constexpr int D1 = 6, D2 = 13, D3 = 26, D4 = 17;
   int lr = 0, lt = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0;
   auto start_class = [&](int r) {
     const int f = y0 + r - HALO * s;
@@ -645,16 +648,10 @@ __device__ __forceinline__ void triple_body(const AtrousArgs& a) {
   };
   auto load_step = [&](TriPre& P) {
     P.p0 = at(A, o0);
-    if constexpr (ADJ) {
-      P.p1 = at(Fp, o1);
-      P.p2 = at(Bp, o2);
-      P.p3 = at(Ep, o3);
-    } else {
-      P.p1 = at(reinterpret_cast<const char*>(O), o1);
-      P.p2 = at(reinterpret_cast<const char*>(O2), o2);
-      P.p3 = at(reinterpret_cast<const char*>(O3), o3);
-      if constexpr (CO) P.p4 = at(reinterpret_cast<const char*>(O4), o4);
-    }
+    P.p1 = at(reinterpret_cast<const char*>(O), o1);
+    P.p2 = at(reinterpret_cast<const char*>(O2), o2);
+    P.p3 = at(reinterpret_cast<const char*>(O3), o3);
+    if constexpr (CO) P.p4 = at(reinterpret_cast<const char*>(O4), o4);
     adv(o0);
     adv(o1);
     adv(o2);
@@ -671,106 +668,81 @@ __device__ __forceinline__ void triple_body(const AtrousArgs& a) {
       if (lr < s) start_class(lr);
     }
   };
-  // windows, oldest first
-  float w17a[17], w17b[17], w9a[9], w9b[9], w5a[5], w5b[5];
+  // windows, oldest first: c (S1), c1 by residue mod 2 (S2), c2 and c3 by residue mod 4 (S3, S4)
+  float wc[5], v1[2][5], v2[4][5], v3[4][5];
 #pragma unroll
-  for (int i = 0; i < 17; ++i) w17a[i] = w17b[i] = 0.f;
+  for (int i = 0; i < 5; ++i) {
+    wc[i] = 0.f;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) w9a[i] = w9b[i] = 0.f;
+    for (int q = 0; q < 2; ++q) v1[q][i] = 0.f;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) w5a[i] = w5b[i] = 0.f;
-  auto push = [](auto& w, float v) {
-    constexpr int n = sizeof(w) / sizeof(w[0]);
-#pragma unroll
-    for (int i = 0; i < n - 1; ++i) w[i] = w[i + 1];
-    w[n - 1] = v;
+    for (int q = 0; q < 4; ++q) v2[q][i] = v3[q][i] = 0.f;
+  }
+  // two-step rings (slot = residue mod 2): c (S1 -> S3), c1 (S2 -> S4), c2 (S3 -> S5)
+  float r0[2] = {0.f, 0.f}, r1[2] = {0.f, 0.f}, r2[2] = {0.f, 0.f};
+  auto push = [](float (&w)[5], float v) {
+    w[0] = w[1];
+    w[1] = w[2];
+    w[2] = w[3];
+    w[3] = w[4];
+    w[4] = v;
   };
-  auto v17 = [](const float (&w)[17]) { return b3(w[0], w[4], w[8], w[12], w[16]); };
-  auto v9 = [](const float (&w)[9]) { return b3(w[0], w[2], w[4], w[6], w[8]); };
   auto v5 = [](const float (&w)[5]) { return b3(w[0], w[1], w[2], w[3], w[4]); };
-  // delay lines of the skewed adjoint: value of step T - 1 first
-  float dA[1] = {0.f}, dC[1] = {0.f}, dE[2] = {0.f, 0.f};
-  float dU2[2] = {0.f, 0.f}, dU1[3] = {0.f, 0.f, 0.f}, dU0[4] = {0.f, 0.f, 0.f, 0.f};
-  auto delay = [](auto& d, float v) -> float {  // returns the value of D steps ago, stores v
-    constexpr int n = sizeof(d) / sizeof(d[0]);
-    const float out = d[n - 1];
-#pragma unroll
-    for (int i = n - 1; i > 0; --i) d[i] = d[i - 1];
-    d[0] = v;
-    return out;
-  };
-  int par = 0;  // LDS parity of the skewed adjoint
-  // step t of a class with ns steps whose load index 0 is row first
-  auto process = [&](const TriPre& cur, int t, int ns, int first) {
-    if constexpr (ADJ) {
-      // At step T: stage 1 of step T, stage 2 of T - 1, stage 3 of T - 2, stage 4 of T - 3 and the
-      // output of T - 4, where step t is the one-step-per-stage schedule's step t:
-      //   w17a: u_{j+2} (t-16..t), w9a: u_{j+1} (t-20..t-12), w5a: u_j (t-22..t-18),
-      //   w17b: a - H_{j+2} u_{j+2} (t-24..t-8), w9b: a1 - H_{j+1} u_{j+1} (t-24..t-16),
-      //   w5b: a2 - H_j u_j (t-24..t-20)
-      float* wr = sm + par * 6 * N;        // written this step
-      float* rd = sm + (par ^ 1) * 6 * N;  // written last step
-      const float hA = h2(rd), hC = h1(rd + 2 * N), hE = h0(rd + 4 * N);  // stage 1 of T - 1
-      const float gB = h2(rd + N);      // stage 2 of T - 2
-      const float gD = h1(rd + 3 * N);  // stage 3 of T - 3
-      const float gF = h0(rd + 5 * N);  // stage 4 of T - 4
-      // stage 1, step T
-      push(w17a, cur.p0);
-      push(w9a, cur.p2);
-      push(w5a, cur.p3);
-      wr[x] = v17(w17a);
-      wr[2 * N + x] = v9(w9a);
-      wr[4 * N + x] = v5(w5a);
-      // stage 2, step T - 1: a - H_{j+2} u_{j+2}
-      push(w17b, delay(dA, cur.p1) - hA);
-      wr[N + x] = v17(w17b);
-      // stage 3, step T - 2: a1 = u_{j+2} + H_{j+2}(...), then a1 - H_{j+1} u_{j+1}
-      const float a1 = delay(dU2, w17a[0]) + gB;
-      push(w9b, a1 - delay(dC, hC));
-      wr[3 * N + x] = v9(w9b);
-      // stage 4, step T - 3: a2 = u_{j+1} + H_{j+1}(...), then a2 - H_j u_j
-      const float a2 = delay(dU1, w9a[0]) + gD;
-      push(w5b, a2 - delay(dE, hE));
-      wr[5 * N + x] = v5(w5b);
-      // output, step T - 4: u_j + H_j(...)
-      const float out = delay(dU0, w5a[0]) + gF;
-      const int to = t - SKEW;
-      if (to >= 2 * HALO && to < ns - SKEW) put(O, first + (to - HALO) * s, out);
-      lds_barrier();
-      par ^= 1;
-    } else {
-      // w5a: c (t-4..t), w9a: c1 (t-10..t-2), w17a: c2 (t-22..t-6), w17b: c3 (t-30..t-14)
-      push(w5a, cur.p0);
-      const float cc0 = w5a[0];
-      bA[x] = v5(w5a);
-      lds_barrier();
-      push(w9a, h0(bA));
-      const float cc1 = w9a[0];
-      bB[x] = b3(w9a[4], w9a[5], w9a[6], w9a[7], w9a[8]);
-      bC[x] = v9(w9a);
-      lds_barrier();
-      const float wj = cc0 - h0(bB);
-      if (t >= HALO + 4 && t < ns - 18) put(O, first + (t - 4) * s, upd(cur.p1, wj, a.coef));
-      push(w17a, h1(bC));
-      const float cc2 = w17a[0];
-      bD[x] = b3(w17a[8], w17a[10], w17a[12], w17a[14], w17a[16]);
-      bE[x] = v17(w17a);
-      lds_barrier();
-      const float wj1 = cc1 - h1(bD);
-      if (t >= HALO + 10 && t < ns - 12) put(O2, first + (t - 10) * s, upd(cur.p2, wj1, a.coef));
-      const float c3 = h2(bE);
-      if (t >= HALO + 14 && t < ns - 8) {
+  // step T (residue P mod 4); stage k works for step T - k + 1, whose load index 0 is row first
+  // of a class with ns steps (T counts within the class, which the skew does not cross: SKEW
+  // extra steps at the end of every class drain it)
+  auto process = [&](auto ph, const TriPre& cur, int T, int ns, int first) {
+    constexpr int P = decltype(ph)::value, P2 = P & 1;
+    float* wr = sm + P2 * 6 * RS;        // rows written this step
+    float* rd = sm + (P2 ^ 1) * 6 * RS;  // rows written last step
+    const int lo = HALO, hi = ns - HALO - SKEW;  // load indices of the band's own rows
+    const float cc0 = r0[P2], cc1 = r1[P2], cc2 = r2[P2];  // written two steps ago
+    // S5, step T - 4: u_{j+2} at T - 26
+    {
+      const float w2 = cc2 - h2(rd + 5 * RS);
+      if (T - 26 >= lo && T - 26 < hi) put(O3, first + (T - 26) * s, upd(cur.p3, w2, a.coef));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // S4, step T - 3: u_{j+1} at T - 13, c3 at T - 17
+    {
+      const float w1 = cc1 - h1(rd + 3 * RS);
+      if (T - 13 >= lo && T - 13 < hi) put(O2, first + (T - 13) * s, upd(cur.p2, w1, a.coef));
+      const float c3 = h2(rd + 4 * RS);
+      if (T - 17 >= lo && T - 17 < hi) {
         if constexpr (CO) {
-          put(O4, first + (t - 14) * s, upd(cur.p4, c3, a.coef2));
+          put(O4, first + (T - 17) * s, upd(cur.p4, c3, a.coef2));
         } else {
-          put(O4, first + (t - 14) * s, c3);
+          put(O4, first + (T - 17) * s, c3);
         }
       }
-      push(w17b, c3);
-      bF[x] = v17(w17b);
-      lds_barrier();
-      if (t >= 2 * HALO && t < ns) put(O3, first + (t - HALO) * s, upd(cur.p3, cc2 - h2(bF), a.coef));
+      push(v3[P], c3);
+      wr[5 * RS + x] = v5(v3[P]);
     }
+    __builtin_amdgcn_sched_barrier(0);
+    // S3, step T - 2: u_j at T - 6, c2
+    {
+      const float w0 = cc0 - h0(rd + RS);
+      if (T - 6 >= lo && T - 6 < hi) put(O, first + (T - 6) * s, upd(cur.p1, w0, a.coef));
+      const float c2 = h1(rd + 2 * RS);
+      push(v2[P], c2);
+      r2[P2] = v2[P][0];
+      wr[3 * RS + x] = b3(v2[P][2], v2[(P + 2) & 3][3], v2[P][3], v2[(P + 2) & 3][4], v2[P][4]);
+      wr[4 * RS + x] = v5(v2[P]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // S2, step T - 1: c1
+    {
+      const float c1 = h0(rd);
+      push(v1[P2], c1);
+      r1[P2] = v1[P2][0];
+      wr[RS + x] = b3(v1[P2][2], v1[P2 ^ 1][3], v1[P2][3], v1[P2 ^ 1][4], v1[P2][4]);
+      wr[2 * RS + x] = v5(v1[P2]);
+    }
+    // S1, step T: c
+    push(wc, cur.p0);
+    r0[P2] = wc[0];
+    wr[x] = v5(wc);
+    lds_barrier();
   };
   int r = 0;
   while (r < s && nsteps(r) == 0) ++r;
@@ -790,89 +762,313 @@ __device__ __forceinline__ void triple_body(const AtrousArgs& a) {
       }
       return true;
     };
-    if constexpr (ADJ) {
-      // loads one step ahead (two would not fit the adjoint's registers)
-      TriPre cur, nxt;
-      load_step(cur);
-      advance_load();
-      while (true) {
-        load_step(nxt);  // past the last class: further rows of the planes, unused
-        advance_load();
-        process(cur, pt, pns, pfirst);
-        if (!next_step()) break;
-        cur = nxt;
-      }
-      return;
-    }
-    // loads run two steps ahead of the computation; the loop is unrolled three times so the three
-    // buffers keep fixed roles and no register copy waits for a load in flight
-    TriPre q0, q1, q2;
+    // Loads three steps ahead, four buffers taking turns, so that no copy waits for a load in
+    // flight.  The scheduling barriers keep each step's loads from moving up into earlier steps.
+    TriPre q0, q1, q2, q3;
     load_step(q0);
     advance_load();
     load_step(q1);
     advance_load();
+    load_step(q2);
+    advance_load();
     while (true) {
-      load_step(q2);  // past the last class: further rows of the planes, unused
+      load_step(q3);  // past the last class: further rows of the planes, unused
       advance_load();
-      process(q0, pt, pns, pfirst);
+      process(Phase<0>{}, q0, pt, pns, pfirst);
       if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
       load_step(q0);
       advance_load();
-      process(q1, pt, pns, pfirst);
+      process(Phase<1>{}, q1, pt, pns, pfirst);
       if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
       load_step(q1);
       advance_load();
-      process(q2, pt, pns, pfirst);
+      process(Phase<2>{}, q2, pt, pns, pfirst);
       if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
+      load_step(q2);
+      advance_load();
+      process(Phase<3>{}, q3, pt, pns, pfirst);
+      if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(1024) k_triple(AtrousArgs a) {
-  triple_body<MODE>(a);
+// Adjoint triple with phase windows.  A window whose filter taps lie d steps apart (d = 4 for
+// H_{j+2}, 2 for H_{j+1}) is kept as d windows of five entries, one per step residue mod d, and a
+// step shifts only the one of its own residue: 4 register moves instead of 16 or 8.  The main loop
+// is unrolled four times so that every residue, the LDS parity and the slots of the 1-, 2- and
+// 4-step delay lines are compile-time constants (the 3-step line still shifts).  The values and
+// the operations on them are those of the shifting form, in the same order.
+// LDS rows are RS floats apart (RS >= N, a compile-time constant), so every row and slot offset is
+// an instruction immediate: with the residues fixed, nothing per row has to be held in a register.
+template <int RS>
+__device__ __forceinline__ void triple_adj_body(const AtrousArgs& a) {
+  constexpr int HALO = 22, SKEW = 4;
+  extern __shared__ float sm[];
+  const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
+  const int b = xcd_remap(blockIdx.x, a.nblocks);
+  const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
+  const int y0 = band * TY;
+  const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
+  const char* __restrict__ Bp = reinterpret_cast<const char*>(a.B.p + ch * a.B.cs);
+  const char* __restrict__ Ep = reinterpret_cast<const char*>(a.E.p + ch * a.E.cs);
+  const char* __restrict__ Fp = reinterpret_cast<const char*>(a.F.p + ch * a.F.cs);
+  float* __restrict__ O = a.out.p + ch * a.out.cs;
+  auto modx = [&](int v) { return (v % N + N) % N; };
+  const int xm1 = modx(x - s), xm2 = modx(x - 2 * s), xm4 = modx(x - 4 * s), xm8 = modx(x - 8 * s);
+  const int xp1 = modx(x + s), xp2 = modx(x + 2 * s), xp4 = modx(x + 4 * s), xp8 = modx(x + 8 * s);
+  auto h0 = [&](const float* row) { return b3(row[xm2], row[xm1], row[x], row[xp1], row[xp2]); };
+  auto h1 = [&](const float* row) { return b3(row[xm4], row[xm2], row[x], row[xp2], row[xp4]); };
+  auto h2 = [&](const float* row) { return b3(row[xm8], row[xm4], row[x], row[xp4], row[xp8]); };
+  const int rowb = N * 4, planeb = N * N * 4, stepb = (s % N) * rowb;
+  const unsigned xb = (unsigned)x * 4u;
+  auto at = [&](const char* base, int off) -> float {
+    return *reinterpret_cast<const float*>(base + off + xb);
+  };
+  auto put = [&](float* base, int y, float v) {
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
+  };
+  auto nsteps = [&](int r) -> int {
+    const int v = TY - r;
+    return v > 0 ? ((v + s - 1) >> jj) + 2 * HALO + SKEW : 0;
+  };
+  auto rowoff = [&](int y) -> int {
+    y %= N;
+    return (y < 0 ? y + N : y) * rowb;
+  };
+  auto adv = [&](int& o) {
+    o += stepb;
+    if (o >= planeb) o -= planeb;
+  };
+  // load streams (load index of step t): p0 u_{j+2} (t), p1 a (t - 8), p2 u_{j+1} (t - 12),
+  // p3 u_j (t - 18)
+  int lr = 0, lt = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+  auto start_class = [&](int r) {
+    const int f = y0 + r - HALO * s;
+    o0 = rowoff(f);
+    o1 = rowoff(f - 8 * s);
+    o2 = rowoff(f - 12 * s);
+    o3 = rowoff(f - 18 * s);
+  };
+  auto load_step = [&](TriPre& P) {
+    P.p0 = at(A, o0);
+    P.p1 = at(Fp, o1);
+    P.p2 = at(Bp, o2);
+    P.p3 = at(Ep, o3);
+    adv(o0);
+    adv(o1);
+    adv(o2);
+    adv(o3);
+  };
+  auto advance_load = [&]() {
+    ++lt;
+    if (lt >= nsteps(lr)) {
+      lt = 0;
+      do {
+        ++lr;
+      } while (lr < s && nsteps(lr) == 0);
+      if (lr < s) start_class(lr);
+    }
+  };
+  // windows, oldest first: u_{j+2} and a - H_{j+2} u_{j+2} by residue mod 4, u_{j+1} and
+  // a1 - H_{j+1} u_{j+1} by residue mod 2, u_j and a2 - H_j u_j
+  float ua[4][5], ub[4][5], va[2][5], vb[2][5], wa[5], wb[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ua[q][i] = ub[q][i] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) va[q][i] = vb[q][i] = 0.f;
+    wa[i] = wb[i] = 0.f;
+  }
+  // delay lines: dA, dC one step, in registers; in LDS, four slots per line indexed by the residue
+  // (a line of d steps reads slot P - d before step P writes slot P; each thread reads only its
+  // own column): dE two steps, dU1 three, dU0 four.  u_{j+2} two steps before the oldest entry of
+  // ua[P] is the oldest entry of ua[P + 2], which was last pushed two steps ago.
+  float dA = 0.f, dC = 0.f;
+  float* dE = sm + 12 * RS;
+  float* dU1 = sm + 16 * RS;
+  float* dU0 = sm + 20 * RS;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dE[q * RS + x] = dU1[q * RS + x] = dU0[q * RS + x] = 0.f;
+  auto push = [](float (&w)[5], float v) {
+    w[0] = w[1];
+    w[1] = w[2];
+    w[2] = w[3];
+    w[3] = w[4];
+    w[4] = v;
+  };
+  auto v5 = [](const float (&w)[5]) { return b3(w[0], w[1], w[2], w[3], w[4]); };
+  // step t (residue P mod 4) of a class with ns steps whose load index 0 is row first.  At step
+  // T: stage 1 of step T, stage 2 of T - 1, stage 3 of T - 2, stage 4 of T - 3 and the output of
+  // T - 4, where step t is the one-step-per-stage schedule's step t.
+  auto process = [&](auto ph, const TriPre& cur, int t, int ns, int first) {
+    constexpr int P = decltype(ph)::value, P2 = P & 1;
+    float* wr = sm + P2 * 6 * RS;        // written this step
+    float* rd = sm + (P2 ^ 1) * 6 * RS;  // written last step
+    // Each stage reads its horizontal filters of last step's rows just before it needs them (the
+    // scheduling barriers keep the compiler from issuing all thirty LDS reads at once, which would
+    // hold thirty more registers).  Stage 1 of T - 1 wrote rows 0, 2, 4; stage 2 of T - 2 row 1,
+    // stage 3 of T - 3 row 3, stage 4 of T - 4 row 5.
+    // stage 1, step T
+    push(ua[P], cur.p0);
+    push(va[P2], cur.p2);
+    push(wa, cur.p3);
+    wr[x] = v5(ua[P]);
+    wr[2 * RS + x] = v5(va[P2]);
+    wr[4 * RS + x] = v5(wa);
+    __builtin_amdgcn_sched_barrier(0);
+    // stage 2, step T - 1: a - H_{j+2} u_{j+2}
+    const float hA = h2(rd);
+    const float a_old = dA;
+    dA = cur.p1;
+    push(ub[P], a_old - hA);
+    wr[RS + x] = v5(ub[P]);
+    __builtin_amdgcn_sched_barrier(0);
+    // stage 3, step T - 2: a1 = u_{j+2} + H_{j+2}(...), then a1 - H_{j+1} u_{j+1}
+    const float gB = h2(rd + RS), hC = h1(rd + 2 * RS);
+    const float a1 = ua[(P + 2) & 3][0] + gB;
+    const float c_old = dC;
+    dC = hC;
+    push(vb[P2], a1 - c_old);
+    wr[3 * RS + x] = v5(vb[P2]);
+    __builtin_amdgcn_sched_barrier(0);
+    // stage 4, step T - 3: a2 = u_{j+1} + H_{j+1}(...), then a2 - H_j u_j
+    const float gD = h1(rd + 3 * RS), hE = h0(rd + 4 * RS);
+    const float u1 = dU1[((P + 1) & 3) * RS + x];
+    dU1[P * RS + x] = va[P2][0];
+    const float a2 = u1 + gD;
+    const float e_old = dE[((P + 2) & 3) * RS + x];
+    dE[P * RS + x] = hE;
+    push(wb, a2 - e_old);
+    wr[5 * RS + x] = v5(wb);
+    __builtin_amdgcn_sched_barrier(0);
+    // output, step T - 4: u_j + H_j(...)
+    const float gF = h0(rd + 5 * RS);
+    const float u0 = dU0[P * RS + x];
+    dU0[P * RS + x] = wa[0];
+    const float out = u0 + gF;
+    const int to = t - SKEW;
+    if (to >= 2 * HALO && to < ns - SKEW) put(O, first + (to - HALO) * s, out);
+    lds_barrier();
+  };
+  int r = 0;
+  while (r < s && nsteps(r) == 0) ++r;
+  if (r < s) {
+    lr = r;
+    start_class(lr);
+    int pt = 0, pns = nsteps(r), pfirst = y0 + r - HALO * s;
+    auto next_step = [&]() -> bool {  // false when the band is done
+      if (++pt >= pns) {
+        do {
+          ++r;
+        } while (r < s && nsteps(r) == 0);
+        if (r >= s) return false;
+        pt = 0;
+        pns = nsteps(r);
+        pfirst = y0 + r - HALO * s;
+      }
+      return true;
+    };
+    // Loads three steps ahead, four buffers taking turns, so that no copy waits for a load in
+    // flight.  The scheduling barriers keep each step's loads from moving up into earlier steps.
+    TriPre q0, q1, q2, q3;
+    load_step(q0);
+    advance_load();
+    load_step(q1);
+    advance_load();
+    load_step(q2);
+    advance_load();
+    while (true) {
+      load_step(q3);  // past the last class: further rows of the planes, unused
+      advance_load();
+      process(Phase<0>{}, q0, pt, pns, pfirst);
+      if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
+      load_step(q0);
+      advance_load();
+      process(Phase<1>{}, q1, pt, pns, pfirst);
+      if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
+      load_step(q1);
+      advance_load();
+      process(Phase<2>{}, q2, pt, pns, pfirst);
+      if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
+      load_step(q2);
+      advance_load();
+      process(Phase<3>{}, q3, pt, pns, pfirst);
+      if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(1024) k_triple_trial(AtrousArgs a) {
-  triple_body<MODE>(a);
+template <int RS, bool CO>
+__global__ void __launch_bounds__(1024) k_triple_an(AtrousArgs a) {
+  triple_an_body<RS, CO>(a);
 }
+
+template <int RS, bool CO>
+__global__ void __launch_bounds__(1024) k_triple_an_trial(AtrousArgs a) {
+  triple_an_body<RS, CO>(a);
+}
+
+template <int RS>
+__global__ void __launch_bounds__(1024) k_triple_adj(AtrousArgs a) {
+  triple_adj_body<RS>(a);
+}
+
+template <int RS>
+__global__ void __launch_bounds__(1024) k_triple_adj_trial(AtrousArgs a) {
+  triple_adj_body<RS>(a);
+}
+
+constexpr int kAdjRows = 24;  // LDS rows of the adjoint triple: 2 x 6 stage rows, 3 x 4 delay slots
+constexpr int kAnRows = 12;   // LDS rows of the analysis triple: 2 x 6 stage rows
+// row stride of the triples' LDS rows: the smallest of 64, 256, 1024 floats that holds a row
+static int tri_row_stride(int N) { return N <= 64 ? 64 : (N <= 256 ? 256 : 1024); }
 
 // ------------------------------------------------------------------ fused pair
 // The last analysis pair of an iteration (scales j, j + 1 and the coarse plane's dual step) and
 // the first adjoint pair of the next iteration, which works on exactly the planes the analysis
-// has just updated, in one pass.  With t the load index of c_j:
-//   analysis:  c1 = H_j c (t - 2), w_j (t - 4), c2 = H_{j+1} c1 (t - 6), w_{j+1} (t - 10), giving
-//              the new u_j (t - 4), coarse plane u_c (t - 6) and u_{j+1} (t - 10)
-//   adjoint, one step behind, on those values (index T = t - 11 of u_{j+1}):
-//              h = H_{j+1} u_{j+1} (T - 4), a' = u_{j+1} + H_{j+1}(u_c - h) (T - 8),
-//              a'' = u_j + H_j(a' - H_j u_j) (T - 10 = t - 21)
-// The new u_j and u_c wait 13 and 9 steps until the adjoint reaches them, in LDS rings of one
-// slot per step (each thread reads back only what it wrote, so the rings need no barrier).  The four stages of a step share three LDS barriers: the analysis and adjoint stages of
-// one phase read rows written in the phase before.  The old planes are read from B, E, F and the
-// new ones written to out, out2, out3, so a band's halo always reads the values its neighbours
-// are replacing; a'' goes to out4.  Every stage repeats the operations of the analysis pair and
-// the adjoint pair in their order: planes and a'' are bit-identical to the two launches.
+// has just updated, in one pass.  Stages, for analysis step t (c_j loaded at index t):
+//   A1  c into the window of H_j (vertical part of c1 = H_j c at t - 2)
+//   A2  c1 (t - 2); vertical parts of H_j c1 (t - 4) and of c2 = H_{j+1} c1 (t - 6)
+//   A3  w_j (t - 4): new u_j; c2 (t - 6): new coarse plane u_c; vertical part of H_{j+1} c2
+//   A4  w_{j+1} (t - 10): new u_{j+1}
+//   B1  (adjoint index tau = t - 10) vertical parts of H_{j+1} u_{j+1} (tau - 4) and of
+//       H_j u_j (tau - 8)
+//   B2  h = H_{j+1} u_{j+1}; vertical part of H_{j+1}(u_c - h) (tau - 8)
+//   B3  a' = u_{j+1} + H_{j+1}(u_c - h) (tau - 8); vertical part of H_j(a' - H_j u_j)
+//   B4  a'' = u_j + H_j(a' - H_j u_j) (tau - 10 = t - 20)
+// They are skewed like the triples: wall step T runs A1 for t = T, A2 for T - 1, A3 for T - 2, A4
+// and B1 for T - 3, B2 for T - 4, B3 for T - 5 and B4 for T - 6, each stage reading the LDS rows
+// its predecessor wrote in the previous step (two sets of rows, by step parity), so one barrier
+// per step serves all of them.  The new u_j and u_c wait 13 and 10 steps for B1 and B2 in LDS
+// rings (each thread reads back only what it wrote); the other carried values wait in registers.
+// The old dual planes are read from B, E, F and the new ones written to out, out2, out3 (two
+// buffers, so that a band's halo always reads old values); a'' goes to out4.  Windows are phase
+// windows, the loop is unrolled four times and the LDS rows are RS floats apart (see the
+// triples).  Every stage repeats the operations of the analysis pair and the adjoint pair in
+// their order: planes and a'' are bit-identical to the two separate launches.
 struct FusedPre {
   float p0, p1, p2, p3;
 };
+constexpr int kFusedDJ = 13, kFusedDC = 10;          // delays of the new u_j and u_c
+constexpr int kFusedRows = 16 + kFusedDJ + kFusedDC;  // LDS rows: 2 x 8 stage rows, the two rings
 
+template <int RS>
 __device__ __forceinline__ void fused_body(const AtrousArgs& a) {
   constexpr int HALO = 20;  // 10 class steps for the analysis, 10 for the adjoint
-  constexpr int SKEW = 1;   // the adjoint stages run one step behind
+  constexpr int SKEW = 6;   // the last stage works for the step six steps back
   extern __shared__ float sm[];
   const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
-  float* bA = sm;  // analysis rows
-  float* bB = sm + N;
-  float* bC = sm + 2 * N;
-  float* bD = sm + 3 * N;
-  float* qA = sm + 4 * N;  // adjoint rows
-  float* qB = sm + 5 * N;
-  float* qC = sm + 6 * N;
-  float* qD = sm + 7 * N;
-  constexpr int DJ = 13, DC = 9;  // delays of the new u_j and u_c
-  float* ringJ = sm + 8 * N;      // [DJ][N]
-  float* ringC = sm + (8 + DJ) * N;  // [DC][N]
+  float* ringJ = sm + 16 * RS;
+  float* ringC = sm + (16 + kFusedDJ) * RS;
   const int b = xcd_remap(blockIdx.x, a.nblocks);
   const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
   const int y0 = band * TY;
@@ -910,14 +1106,16 @@ __device__ __forceinline__ void fused_body(const AtrousArgs& a) {
     o += stepb;
     if (o >= planeb) o -= planeb;
   };
-  // load streams: p0 c (t), p1 old u_j (t - 4), p2 old u_{j+1} (t - 10), p3 old coarse (t - 6)
+  // load streams (load index of wall step T): p0 c (T), p1 old u_j (T - 6), p2 old u_{j+1}
+  // (T - 13), p3 old coarse plane (T - 8)
+  constexpr int D1 = 6, D2 = 13, D3 = 8;
   int lr = 0, lt = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0;
   auto start_class = [&](int r) {
     const int f = y0 + r - HALO * s;
     o0 = rowoff(f);
-    o1 = rowoff(f - 4 * s);
-    o2 = rowoff(f - 10 * s);
-    o3 = rowoff(f - 6 * s);
+    o1 = rowoff(f - D1 * s);
+    o2 = rowoff(f - D2 * s);
+    o3 = rowoff(f - D3 * s);
   };
   auto load_step = [&](FusedPre& P) {
     P.p0 = at(A, o0);
@@ -939,75 +1137,103 @@ __device__ __forceinline__ void fused_body(const AtrousArgs& a) {
       if (lr < s) start_class(lr);
     }
   };
-  // windows, oldest first.  Analysis: wc c (t-4..t), wa c1 (t-10..t-2), wb c2 (t-14..t-6).
-  // Adjoint: ya u_{j+1} (T-8..T), yc u_j (T-10..T-6), yb u_c - h (T-12..T-4), yd a' - H_j u_j
-  // (T-12..T-8).
-  float wc[5], wa[9], wb[9], ya[9], yb[9], yc[5], yd[5];
+  // windows, oldest first (9-entry windows with taps two steps apart as two phase windows):
+  // wc c (A1), wa c1 (A2), wb c2 (A3), ya new u_{j+1} (B1), yc new u_j (B1), yb u_c - h (B2),
+  // yd a' - H_j u_j (B3)
+  float wc[5], wa[2][5], wb[2][5], ya[2][5], yb[2][5], yc[5], yd[5];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) wa[i] = wb[i] = ya[i] = yb[i] = 0.f;
+  for (int i = 0; i < 5; ++i) {
+    wc[i] = yc[i] = yd[i] = 0.f;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) wc[i] = yc[i] = yd[i] = 0.f;
-  // ring slots of the current step; the new u_{j+1} of the last step
+    for (int q = 0; q < 2; ++q) wa[q][i] = wb[q][i] = ya[q][i] = yb[q][i] = 0.f;
+  }
+  // register rings: c (A1 -> A3) and c1 (A2 -> A4) two steps, u_{j+1} (B1 -> B3) two steps, u_j
+  // (B1 -> B4) three steps in four slots, H_j u_j (B2 -> B3) one step in two slots
+  float r4[2] = {0.f, 0.f}, r10[2] = {0.f, 0.f}, rh[2] = {0.f, 0.f}, rl[4] = {0.f, 0.f, 0.f, 0.f};
+  float rh0[2] = {0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < DJ; ++i) ringJ[i * N + x] = 0.f;
+  for (int i = 0; i < kFusedDJ; ++i) ringJ[i * RS + x] = 0.f;
 #pragma unroll
-  for (int i = 0; i < DC; ++i) ringC[i * N + x] = 0.f;
-  int rj = 0, rc = 0;
-  float pend1 = 0.f;
-  auto push = [](auto& w, float v) {
-    constexpr int n = sizeof(w) / sizeof(w[0]);
-#pragma unroll
-    for (int i = 0; i < n - 1; ++i) w[i] = w[i + 1];
-    w[n - 1] = v;
+  for (int i = 0; i < kFusedDC; ++i) ringC[i * RS + x] = 0.f;
+  int rj = 0, rc = 0;  // ring slots of the current step
+  auto push = [](float (&w)[5], float v) {
+    w[0] = w[1];
+    w[1] = w[2];
+    w[2] = w[3];
+    w[3] = w[4];
+    w[4] = v;
   };
-  auto v9 = [](const float (&w)[9]) { return b3(w[0], w[2], w[4], w[6], w[8]); };
   auto v5 = [](const float (&w)[5]) { return b3(w[0], w[1], w[2], w[3], w[4]); };
-  // step t of a class with ns steps whose load index 0 is row first; index i is a row of the band
-  // when HALO <= i < ns - HALO - SKEW
-  auto process = [&](const FusedPre& cur, int t, int ns, int first) {
-    const int lo = HALO, hi = ns - HALO - SKEW;
-    // phase 1: analysis H_j of c (vertical); adjoint H_{j+1} of u_{j+1} and H_j of u_j (vertical)
+  // wall step T (residue P mod 4) of a class with ns steps whose load index 0 is row first
+  auto process = [&](auto ph, const FusedPre& cur, int T, int ns, int first) {
+    constexpr int P = decltype(ph)::value, P2 = P & 1, Q2 = P2 ^ 1;
+    float* wr = sm + P2 * 8 * RS;  // rows written this step: 0..3 analysis, 4..7 adjoint
+    float* rd = sm + Q2 * 8 * RS;  // rows written last step
+    const int lo = HALO, hi = ns - HALO - SKEW;  // load indices of the band's own rows
+    // carried values, all written before this step
+    const float cc4 = r4[P2], cc10 = r10[P2], cuh = rh[P2], cul = rl[(P + 1) & 3], h0 = rh0[Q2];
+    const float uj_b1 = ringJ[rj * RS + x];  // new u_j of 13 steps ago
+    const float uc_b2 = ringC[rc * RS + x];  // new u_c of 10 steps ago
+    // B4, t = T - 6: a'' at T - 26
+    {
+      const float out = cul + hj(rd + 7 * RS);
+      if (T - 26 >= lo && T - 26 < hi) put(O4, first + (T - 26) * s, out);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // B3, t = T - 5: a' and a' - H_j u_j
+    {
+      const float a1 = cuh + hj1(rd + 6 * RS);
+      push(yd, a1 - h0);
+      wr[7 * RS + x] = v5(yd);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // B2, t = T - 4: u_c - H_{j+1} u_{j+1}, and H_j u_j for B3
+    {
+      const float h1 = hj1(rd + 4 * RS);
+      rh0[P2] = hj(rd + 5 * RS);
+      push(yb[P2], uc_b2 - h1);
+      wr[6 * RS + x] = v5(yb[P2]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // A4 and B1, t = T - 3: new u_{j+1} at T - 13, then the adjoint's vertical parts
+    {
+      const float nu1 = upd(cur.p2, cc10 - hj1(rd + 3 * RS), a.coef);
+      if (T - 13 >= lo && T - 13 < hi) put(O2, first + (T - 13) * s, nu1);
+      push(ya[P2], nu1);
+      rh[P2] = ya[P2][0];
+      wr[4 * RS + x] = v5(ya[P2]);
+      push(yc, uj_b1);
+      rl[P] = yc[0];
+      wr[5 * RS + x] = v5(yc);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // A3, t = T - 2: new u_j at T - 6 and coarse plane at T - 8; c2
+    {
+      const float nuj = upd(cur.p1, cc4 - hj(rd + RS), a.coef);
+      if (T - 6 >= lo && T - 6 < hi) put(O, first + (T - 6) * s, nuj);
+      const float c2 = hj1(rd + 2 * RS);
+      const float nuc = upd(cur.p3, c2, a.coef2);
+      if (T - 8 >= lo && T - 8 < hi) put(O3, first + (T - 8) * s, nuc);
+      push(wb[P2], c2);
+      wr[3 * RS + x] = v5(wb[P2]);
+      ringJ[rj * RS + x] = nuj;
+      ringC[rc * RS + x] = nuc;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // A2, t = T - 1: c1
+    {
+      push(wa[P2], hj(rd));
+      r10[P2] = wa[P2][0];
+      wr[RS + x] = b3(wa[P2][2], wa[Q2][3], wa[P2][3], wa[Q2][4], wa[P2][4]);
+      wr[2 * RS + x] = v5(wa[P2]);
+    }
+    // A1, t = T: c
     push(wc, cur.p0);
-    const float cc4 = wc[0];
-    bA[x] = v5(wc);
-    push(ya, pend1);
-    const float cuh = ya[0];
-    qA[x] = v9(ya);
-    push(yc, ringJ[rj * N + x]);  // u_j of 13 steps ago
-    const float cul = yc[0];
-    qB[x] = v5(yc);
+    r4[P2] = wc[0];
+    wr[x] = v5(wc);
+    rj = rj + 1 == kFusedDJ ? 0 : rj + 1;
+    rc = rc + 1 == kFusedDC ? 0 : rc + 1;
     lds_barrier();
-    // phase 2: c1, the vertical parts of H_j c1 and H_{j+1} c1; u_c - H_{j+1} u_{j+1}
-    push(wa, hj(bA));
-    const float cc10 = wa[0];
-    bB[x] = b3(wa[4], wa[5], wa[6], wa[7], wa[8]);
-    bC[x] = v9(wa);
-    const float h1 = hj1(qA);
-    const float h0 = hj(qB);
-    push(yb, ringC[rc * N + x] - h1);  // u_c of 9 steps ago
-    qC[x] = v9(yb);
-    lds_barrier();
-    // phase 3: new u_j and coarse plane, vertical H_{j+1} of c2; a' and a' - H_j u_j
-    const float nuj = upd(cur.p1, cc4 - hj(bB), a.coef);
-    if (t - 4 >= lo && t - 4 < hi) put(O, first + (t - 4) * s, nuj);
-    const float c2 = hj1(bC);
-    const float nuc = upd(cur.p3, c2, a.coef2);
-    if (t - 6 >= lo && t - 6 < hi) put(O3, first + (t - 6) * s, nuc);
-    push(wb, c2);
-    bD[x] = v9(wb);
-    const float a1 = cuh + hj1(qC);
-    push(yd, a1 - h0);
-    qD[x] = v5(yd);
-    ringJ[rj * N + x] = nuj;
-    ringC[rc * N + x] = nuc;
-    rj = rj + 1 == DJ ? 0 : rj + 1;
-    rc = rc + 1 == DC ? 0 : rc + 1;
-    lds_barrier();
-    // phase 4: new u_{j+1}; a''
-    const float nu1 = upd(cur.p2, cc10 - hj1(bD), a.coef);
-    if (t - 10 >= lo && t - 10 < hi) put(O2, first + (t - 10) * s, nu1);
-    pend1 = nu1;
-    if (t - 21 >= lo && t - 21 < hi) put(O4, first + (t - 21) * s, cul + hj(qD));
   };
   int r = 0;
   while (r < s && nsteps(r) == 0) ++r;
@@ -1015,31 +1241,60 @@ __device__ __forceinline__ void fused_body(const AtrousArgs& a) {
     lr = r;
     start_class(lr);
     int pt = 0, pns = nsteps(r), pfirst = y0 + r - HALO * s;
-    FusedPre cur, nxt;
-    load_step(cur);
-    advance_load();
-    while (true) {
-      load_step(nxt);  // past the last class: further rows of the planes, unused
-      advance_load();
-      process(cur, pt, pns, pfirst);
+    auto next_step = [&]() -> bool {  // false when the band is done
       if (++pt >= pns) {
         do {
           ++r;
         } while (r < s && nsteps(r) == 0);
-        if (r >= s) break;
+        if (r >= s) return false;
         pt = 0;
         pns = nsteps(r);
         pfirst = y0 + r - HALO * s;
       }
-      cur = nxt;
+      return true;
+    };
+    // loads three steps ahead, four buffers taking turns (see the triples)
+    FusedPre q0, q1, q2, q3;
+    load_step(q0);
+    advance_load();
+    load_step(q1);
+    advance_load();
+    load_step(q2);
+    advance_load();
+    while (true) {
+      load_step(q3);  // past the last class: further rows of the planes, unused
+      advance_load();
+      process(Phase<0>{}, q0, pt, pns, pfirst);
+      if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
+      load_step(q0);
+      advance_load();
+      process(Phase<1>{}, q1, pt, pns, pfirst);
+      if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
+      load_step(q1);
+      advance_load();
+      process(Phase<2>{}, q2, pt, pns, pfirst);
+      if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
+      load_step(q2);
+      advance_load();
+      process(Phase<3>{}, q3, pt, pns, pfirst);
+      if (!next_step()) break;
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
 
-__global__ void __launch_bounds__(1024) k_fused(AtrousArgs a) { fused_body(a); }
-constexpr int kFusedRows = 8 + 13 + 9;  // LDS rows of N floats: eight stage rows, the two rings
+template <int RS>
+__global__ void __launch_bounds__(1024) k_fused(AtrousArgs a) {
+  fused_body<RS>(a);
+}
 
-__global__ void __launch_bounds__(1024) k_fused_trial(AtrousArgs a) { fused_body(a); }
+template <int RS>
+__global__ void __launch_bounds__(1024) k_fused_trial(AtrousArgs a) {
+  fused_body<RS>(a);
+}
 
 constexpr int kKR = 8;   // rows per round, single-smoothing modes
 constexpr int kKR2 = 4;  // rows per round, double-smoothing modes (keeps them within 128 VGPRs)
@@ -1253,22 +1508,43 @@ int launch_triple(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   const long long nb = (long long)a.tiles_per_ch * nch;
   if (nb > 0x7fffffffLL) return set_error("triple: grid too large"), MUFFIN_EINVAL;
   a.nblocks = (int)nb;
-  const size_t shm = sizeof(float) * (size_t)(mode == TR_ADJOINT ? 12 : 6) * N;
   const dim3 grid((unsigned)nb), block((unsigned)N);
-  switch (mode) {
-    case TR_ANALYSIS:
-      if (trial) hipLaunchKernelGGL((k_triple_trial<TR_ANALYSIS>), grid, block, shm, st, a);
-      else hipLaunchKernelGGL((k_triple<TR_ANALYSIS>), grid, block, shm, st, a);
-      break;
-    case TR_ANALYSIS_C:
-      if (trial) hipLaunchKernelGGL((k_triple_trial<TR_ANALYSIS_C>), grid, block, shm, st, a);
-      else hipLaunchKernelGGL((k_triple<TR_ANALYSIS_C>), grid, block, shm, st, a);
-      break;
-    default:
-      if (trial) hipLaunchKernelGGL((k_triple_trial<TR_ADJOINT>), grid, block, shm, st, a);
-      else hipLaunchKernelGGL((k_triple<TR_ADJOINT>), grid, block, shm, st, a);
-      break;
+  if (mode == TR_ADJOINT) {
+    const int RS = tri_row_stride(N);
+    const size_t shma = sizeof(float) * kAdjRows * (size_t)RS;
+    switch (RS) {
+      case 64:
+        if (trial) hipLaunchKernelGGL(k_triple_adj_trial<64>, grid, block, shma, st, a);
+        else hipLaunchKernelGGL(k_triple_adj<64>, grid, block, shma, st, a);
+        break;
+      case 256:
+        if (trial) hipLaunchKernelGGL(k_triple_adj_trial<256>, grid, block, shma, st, a);
+        else hipLaunchKernelGGL(k_triple_adj<256>, grid, block, shma, st, a);
+        break;
+      default:
+        if (trial) hipLaunchKernelGGL(k_triple_adj_trial<1024>, grid, block, shma, st, a);
+        else hipLaunchKernelGGL(k_triple_adj<1024>, grid, block, shma, st, a);
+    }
+    MF_HIP(hipGetLastError());
+    return MUFFIN_OK;
   }
+  const int RS = tri_row_stride(N);
+  const size_t shm = sizeof(float) * kAnRows * (size_t)RS;
+  const bool co = mode == TR_ANALYSIS_C;
+#define MF_TRI_AN(rs)                                                                              \
+  if (co) {                                                                                        \
+    if (trial) hipLaunchKernelGGL((k_triple_an_trial<rs, true>), grid, block, shm, st, a);         \
+    else hipLaunchKernelGGL((k_triple_an<rs, true>), grid, block, shm, st, a);                     \
+  } else {                                                                                         \
+    if (trial) hipLaunchKernelGGL((k_triple_an_trial<rs, false>), grid, block, shm, st, a);        \
+    else hipLaunchKernelGGL((k_triple_an<rs, false>), grid, block, shm, st, a);                    \
+  }
+  switch (RS) {
+    case 64: MF_TRI_AN(64) break;
+    case 256: MF_TRI_AN(256) break;
+    default: MF_TRI_AN(1024)
+  }
+#undef MF_TRI_AN
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }
@@ -1298,10 +1574,22 @@ int launch_fused_pair(int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E,
   const long long nb = (long long)a.tiles_per_ch * nch;
   if (nb > 0x7fffffffLL) return set_error("fused pair: grid too large"), MUFFIN_EINVAL;
   a.nblocks = (int)nb;
-  const size_t shm = sizeof(float) * kFusedRows * (size_t)N;
+  const int RS = tri_row_stride(N);
+  const size_t shm = sizeof(float) * kFusedRows * (size_t)RS;
   const dim3 grid((unsigned)nb), block((unsigned)N);
-  if (trial) hipLaunchKernelGGL(k_fused_trial, grid, block, shm, st, a);
-  else hipLaunchKernelGGL(k_fused, grid, block, shm, st, a);
+  switch (RS) {
+    case 64:
+      if (trial) hipLaunchKernelGGL(k_fused_trial<64>, grid, block, shm, st, a);
+      else hipLaunchKernelGGL(k_fused<64>, grid, block, shm, st, a);
+      break;
+    case 256:
+      if (trial) hipLaunchKernelGGL(k_fused_trial<256>, grid, block, shm, st, a);
+      else hipLaunchKernelGGL(k_fused<256>, grid, block, shm, st, a);
+      break;
+    default:
+      if (trial) hipLaunchKernelGGL(k_fused_trial<1024>, grid, block, shm, st, a);
+      else hipLaunchKernelGGL(k_fused<1024>, grid, block, shm, st, a);
+  }
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }
@@ -1333,9 +1621,13 @@ int atrous_init_attrs() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_SUBADD, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              shm));
+  const int shma = (int)(sizeof(float) * kAdjRows * 1024);
+  MF_HIP(hipFuncSetAttribute((const void*)k_triple_adj<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, shma));
+  MF_HIP(hipFuncSetAttribute((const void*)k_triple_adj_trial<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             shma));
   const int shmf = (int)(sizeof(float) * kFusedRows * 1024);
-  MF_HIP(hipFuncSetAttribute((const void*)k_fused, hipFuncAttributeMaxDynamicSharedMemorySize, shmf));
-  MF_HIP(hipFuncSetAttribute((const void*)k_fused_trial, hipFuncAttributeMaxDynamicSharedMemorySize, shmf));
+  MF_HIP(hipFuncSetAttribute((const void*)k_fused<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, shmf));
+  MF_HIP(hipFuncSetAttribute((const void*)k_fused_trial<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, shmf));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_DETAIL1, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<DB_ANALYSIS, kKR2>,

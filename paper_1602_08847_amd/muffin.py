@@ -95,7 +95,7 @@ _lib.muffin_batch_free.restype = None
 
 
 FLAG_SINGLE_SCALE = 1  # one IUWT launch per scale (same results as the fused pairs of scales)
-FLAG_FUSED_TAIL = 2  # last analysis pair fused with the next iteration's first adjoint pair (same results)
+FLAG_NO_FUSED_TAIL = 2  # last analysis pair and the next first adjoint pair as two launches (same results)
 
 
 class MuffinError(RuntimeError):
