@@ -163,7 +163,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cube1024_L256_J5")
     ap.add_argument("--gen", type=int, default=2)
-    ap.add_argument("--flags", type=int, default=0, help="library flags (1: one IUWT scale per launch, 2: no fused tail)")
+    ap.add_argument("--flags", type=int, default=0, help="library flags (1: one IUWT scale per launch, 2: no fused tail, 4: fused tail)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=6)
     ap.add_argument("--autotune", type=int, default=1, help="1: tune the band kernels' row bands first")
@@ -287,7 +287,7 @@ def bench_batch(args):
     cubes = [synth.make_cube(s, dtype=np.float32, with_sky=False) for s in specs]
     print(f"[bench] generated 32 uneven cubes in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     vox = sum(s.N * s.N * s.L for s in specs)
-    b = muffin.Batch([(c.dirty, c.psf) for c in cubes], J=4, mu_s=0.25, mu_lambda=3.0)
+    b = muffin.Batch([(c.dirty, c.psf) for c in cubes], J=4, mu_s=0.25, mu_lambda=3.0, flags=args.flags)
     del cubes
     tune = b.autotune(reps=3) if args.autotune else None
     b.step(args.warmup)

@@ -51,12 +51,16 @@ typedef struct muffin_ctx muffin_ctx;
 /* Run the IUWT one launch per scale instead of fusing two or three consecutive scales into one
  * launch (the results are the same bit for bit; the fused form moves fewer bytes). */
 #define MUFFIN_FLAG_SINGLE_SCALE 1
-/* By default (second generation, coarse plane penalised, last scale group a pair) each
+/* Fused tail (second generation, coarse plane penalised, last scale group a pair): each
  * iteration's analysis ends with one launch that also runs the next iteration's first two adjoint
- * steps over the planes it has just updated: 12 bytes per voxel fewer, the same results bit for
- * bit, and a second copy of three dual planes in memory.  This flag runs the two launches
- * separately instead. */
+ * steps over the planes it has just updated.  It moves 12 bytes per voxel fewer, gives the same
+ * results bit for bit, and keeps a second copy of three dual planes in memory; but it needs large
+ * bands to pay for its longer halo.  By default it is used when the channels alone fill the GPU
+ * (L at least the number of compute units) with at least 64 rows per residue class, and
+ * muffin_autotune keeps whichever of the fused and the separate launches it measures faster.
+ * NO_FUSED_TAIL always runs the two launches separately, FUSED_TAIL always fuses them. */
 #define MUFFIN_FLAG_NO_FUSED_TAIL 2
+#define MUFFIN_FLAG_FUSED_TAIL 4
 
 /* Problem and algorithm parameters (Sec. 2 eqs. (reg), (RegAll); Sec. 3, Algorithm 1). */
 typedef struct {

@@ -76,15 +76,15 @@ struct muffin_ctx {
   double sigma = 1, rho = 1, Ws2 = 0;
   float omega_c = 1.f;
   long long iter = 0;
-  // Fused tail (unless MUFFIN_FLAG_NO_FUSED_TAIL; second generation, coarse plane penalised, last
-  // group a pair): the last analysis
+  // Fused tail (second generation, coarse plane penalised, last group a pair: fused_ok; whether
+  // it runs: fused, see MUFFIN_FLAG_FUSED_TAIL): the last analysis
   // launch also runs the next iteration's first adjoint pair on the planes it has just updated
   // (PR_FUSED).  Those three planes (scales jf, jf + 1 and the coarse plane) alternate between U
   // and U2 ([L][3] planes, us floats apart) from one iteration to the next, so that a band's halo
   // still reads the old values; upar names the buffer holding the current ones (0: U, 1: U2).
   // Acar carries the adjoint's running sum after that pair into the next iteration; acar_ok is
   // false when U was set from outside and Acar has to be recomputed.
-  bool fused = false, acar_ok = true;
+  bool fused_ok = false, fused = false, acar_ok = true;
   int jf = 0, upar = 0;
   float *U2 = nullptr, *Acar = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};  // one iteration per parity of upar
@@ -124,8 +124,10 @@ int validate(const muffin_params* p) {
   if (!fft_supported(p->N)) return set_error("N must be 2^a or 3*2^a with 8 <= N <= 1024"), MUFFIN_EINVAL;
   if (p->L < 1 || p->L > 512) return set_error("L must be in [1, 512]"), MUFFIN_EINVAL;
   if (p->J < 1 || p->J > 6) return set_error("J must be in [1, 6]"), MUFFIN_EINVAL;
-  if (p->flags & ~(MUFFIN_FLAG_SINGLE_SCALE | MUFFIN_FLAG_NO_FUSED_TAIL))
+  if (p->flags & ~(MUFFIN_FLAG_SINGLE_SCALE | MUFFIN_FLAG_NO_FUSED_TAIL | MUFFIN_FLAG_FUSED_TAIL))
     return set_error("unknown flags"), MUFFIN_EINVAL;
+  if ((p->flags & MUFFIN_FLAG_NO_FUSED_TAIL) && (p->flags & MUFFIN_FLAG_FUSED_TAIL))
+    return set_error("FUSED_TAIL and NO_FUSED_TAIL exclude each other"), MUFFIN_EINVAL;
   if (p->iuwt_gen != 1 && p->iuwt_gen != 2) return set_error("iuwt_gen must be 1 or 2"), MUFFIN_EINVAL;
   if (p->penalize_coarse != 0 && p->penalize_coarse != 1)
     return set_error("penalize_coarse must be 0 or 1"), MUFFIN_EINVAL;
@@ -538,9 +540,16 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   c->L = total;
   c->cube = c->cs * total;
   c->ucube = c->us * total * (c->J + 1);
-  c->fused = !(p->flags & MUFFIN_FLAG_NO_FUSED_TAIL) && use_pairs(c) && c->omega_c == 1.f &&
-             !iuwt_groups(c).empty() && iuwt_groups(c).back() == 2;
+  c->fused_ok = !(p->flags & MUFFIN_FLAG_NO_FUSED_TAIL) && use_pairs(c) && c->omega_c == 1.f &&
+                !iuwt_groups(c).empty() && iuwt_groups(c).back() == 2;
   c->jf = c->J - 2;
+  if (c->fused_ok) {
+    // default: whole-channel bands fill the GPU and a residue class is long against the halo
+    int ncu = 0;
+    MF_HIP(hipGetDevice(&c->device));
+    MF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+    c->fused = (p->flags & MUFFIN_FLAG_FUSED_TAIL) || (total >= ncu && (c->N >> c->jf) >= 64);
+  }
   if (any_w) {
     c->chan_w_host.assign(total, 1.f);
     for (int i = 0; i < n; ++i)
@@ -561,7 +570,7 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   const long long spec = (long long)c->L * c->N * c->g.pitch;
   MF_TRY(dalloc(&c->X, cube));
   MF_TRY(dalloc(&c->U, c->ucube));
-  if (c->fused) {
+  if (c->fused_ok) {
     MF_TRY(dalloc(&c->U2, c->us * total * 3));
     MF_TRY(dalloc(&c->Acar, cube));
   }
@@ -597,7 +606,7 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   for (float* b : {c->X, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT})
     MF_HIP(hipMemsetAsync(b, 0, sizeof(float) * cube, st));
   MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, st));
-  if (c->fused) {
+  if (c->fused_ok) {
     // U = 0: the carried adjoint sum of zero planes is exactly zero
     MF_HIP(hipMemsetAsync(c->U2, 0, sizeof(float) * c->us * total * 3, st));
     MF_HIP(hipMemsetAsync(c->Acar, 0, sizeof(float) * cube, st));
@@ -711,6 +720,23 @@ void drop_graphs(muffin_ctx* c) {
   }
 }
 
+// Switch the fused tail on or off between iterations: its planes go back to U when it is switched
+// off while they are in U2, and the carried sum is rebuilt when it is switched on.
+int set_fused(muffin_ctx* c, bool on) {
+  if (on == c->fused) return MUFFIN_OK;
+  if (on && !c->fused_ok) return set_error("fused tail not available for this context"), MUFFIN_EINVAL;
+  if (!on && c->upar) {
+    const long long np = c->npix;
+    MF_TRY(copy_planes(c->U + (long long)c->jf * c->us, (c->J + 1) * c->us, c->U2, 3 * c->us, c->L, 3 * np,
+                       hipMemcpyDeviceToDevice, c->st));
+    c->upar = 0;
+  }
+  if (on) c->acar_ok = false;
+  c->fused = on;
+  drop_graphs(c);
+  return MUFFIN_OK;
+}
+
 // Before iterating: with a fused tail, the carried adjoint sum must match the current planes (it
 // does unless U was set from outside); recompute it with the plain adjoint pair if not.
 int ensure_carry(muffin_ctx* c) {
@@ -736,10 +762,15 @@ int replay(muffin_ctx* c, int n) {
 // on the context's own sizes (reading state, writing only scratch planes) and keep the fastest.
 int autotune(muffin_ctx* c, int reps, std::string& rep) {
   const long long np = c->cs, us = c->us, ucs = (long long)(c->J + 1) * us;
+  // the schedule without the fused tail, plus the fused launch when it is available; the faster
+  // of the fused launch and the two it replaces is kept
+  const bool was_fused = c->fused;
+  c->fused = false;
   std::vector<IuwtStep> sched = analysis_schedule(c);
-  std::vector<IuwtStep> adj = adjoint_schedule(c);
-  if (c->fused) adj.erase(adj.begin());  // run by the fused tail (the plain pair only as a prologue)
-  for (const IuwtStep& st : adj) sched.push_back(st);
+  for (const IuwtStep& st : adjoint_schedule(c)) sched.push_back(st);
+  c->fused = was_fused;
+  if (c->fused_ok) sched.push_back({PR_FUSED, c->jf, "analysis pair + next adjoint pair"});
+  double t_fused = 0, t_an = 0, t_adj = 0;
   rep += "{\"N\": " + std::to_string(c->N) + ", \"channels\": " + std::to_string(c->L) + ", \"scales\": [";
   bool firstrep = true;
   for (const IuwtStep& L : sched) {
@@ -801,12 +832,21 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
       }
     }
     MF_TRY(atrous_set_band_rows(c->N, j, mode, best_ty));
+    if (mode == PR_FUSED) t_fused = best;
+    if (mode == PR_ANALYSIS_C && j == c->jf) t_an = best;
+    if (mode == PR_ADJOINT && j == c->jf) t_adj = best;
     if (!firstrep) rep += ", ";
     firstrep = false;
     rep += "{\"j\": " + std::to_string(j) + ", \"kernel\": \"" + L.name + "\", \"rows\": " +
            std::to_string(best_ty) + ", \"ms\": " + std::to_string(best) + ", \"candidates_ms\": {" + cand + "}}";
   }
-  rep += "]}";
+  rep += "]";
+  if (c->fused_ok) {
+    if (!(c->p.flags & MUFFIN_FLAG_FUSED_TAIL)) MF_TRY(set_fused(c, t_fused < t_an + t_adj));
+    rep += std::string(", \"fused_tail\": ") + (c->fused ? "true" : "false") +
+           ", \"fused_ms\": " + std::to_string(t_fused) + ", \"separate_ms\": " + std::to_string(t_an + t_adj);
+  }
+  rep += "}";
   // recapture the iteration with the chosen tiles
   drop_graphs(c);
   return MUFFIN_OK;

@@ -96,6 +96,7 @@ _lib.muffin_batch_free.restype = None
 
 FLAG_SINGLE_SCALE = 1  # one IUWT launch per scale (same results as the fused pairs of scales)
 FLAG_NO_FUSED_TAIL = 2  # last analysis pair and the next first adjoint pair as two launches (same results)
+FLAG_FUSED_TAIL = 4  # always fuse them (by default: when the cube is large enough, or as autotuned)
 
 
 class MuffinError(RuntimeError):
@@ -358,7 +359,7 @@ class Batch:
     """Independent cubes of uneven sizes advanced together (muffin_batch_*)."""
 
     def __init__(self, cubes, J: int, mu_s: float, mu_lambda, iuwt_gen: int = 2, sigma: float = 1.0,
-                 rho: float = 1.0, tau=0.0):
+                 rho: float = 1.0, tau=0.0, flags: int = 0):
         """cubes: list of (dirty, psf) pairs of [L_i][N_i][N_i] arrays; mu_lambda and tau may be
         scalars or per-cube sequences."""
         torch = _torch()
@@ -376,7 +377,7 @@ class Batch:
             L, N, _ = d.shape
             self.shapes.append((L, N))
             self._keep += [d, f]
-            ps[i] = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=1, flags=0, mu_s=mu_s,
+            ps[i] = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=1, flags=flags, mu_s=mu_s,
                            mu_lambda=mls[i], tau=taus[i], sigma=sigma, rho=rho)
             dptr[i] = d.data_ptr()
             fptr[i] = f.data_ptr()

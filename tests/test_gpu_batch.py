@@ -58,3 +58,29 @@ def test_autotune_keeps_results_and_reports_choices(lib, cubes):
             assert 128 % s["rows"] == 0 and str(s["rows"]) in s["candidates_ms"]
         t.step(6)
         np.testing.assert_array_equal(t.get_x().cpu().numpy(), xa)
+
+
+@pytest.mark.parametrize("shape,flags", [("small", 0), ("small", 4), ("wide", 0)])
+def test_autotune_chooses_the_fused_tail(lib, cubes, shape, flags):
+    """The autotuner times the fused tail against the two launches it replaces and keeps the faster
+    one (flag 4 keeps it fused); the iterates do not change either way.  The small cube starts
+    without it (too few channels); the wide one (256 channels of 256^2, J = 4) starts with it, its
+    planes in the second buffer when the autotuner may switch it off."""
+    if shape == "small":
+        c, J = cubes[3], 5
+    else:
+        c, J = synth.make_cube(synth.CubeSpec(N=256, L=256, J=4, n_sources=8, n_baselines=400, seed=5)), 4
+    kw = dict(J=J, mu_s=0.25, mu_lambda=3.0)
+    with lib.Muffin(c.dirty, c.psf, flags=2, **kw) as a:
+        a.step(5)
+        xa, ua = a.get_x().cpu().numpy(), a.get_u().cpu().numpy()
+    with lib.Muffin(c.dirty, c.psf, flags=flags, **kw) as t:
+        t.step(3)  # odd: a fused tail's planes sit in its second buffer when the choice is made
+        rep = json.loads(t.autotune(reps=1))
+        kernels = [s["kernel"] for s in rep["scales"]]
+        assert "analysis pair + next adjoint pair" in kernels and "adjoint pair" in kernels
+        assert isinstance(rep["fused_tail"], bool)
+        assert rep["fused_tail"] == (flags == 4 or rep["fused_ms"] < rep["separate_ms"])
+        t.step(2)
+        np.testing.assert_array_equal(t.get_x().cpu().numpy(), xa)
+        np.testing.assert_array_equal(t.get_u().cpu().numpy(), ua)

@@ -30,17 +30,17 @@ def test_pairs_match_single_scale_bitwise(lib, N, L, J, pc, rho):
     c = synth.make_cube(synth.CubeSpec(N=N, L=L, J=J, n_sources=max(2, N // 16), n_baselines=max(8, N * 2),
                                        seed=N + J))
     out = {}
-    for flags in (0, lib.FLAG_NO_FUSED_TAIL, lib.FLAG_SINGLE_SCALE):
+    for flags in (lib.FLAG_FUSED_TAIL, lib.FLAG_NO_FUSED_TAIL, lib.FLAG_SINGLE_SCALE):
         with lib.Muffin(c.dirty, c.psf, J=J, mu_s=0.25, mu_lambda=3.0, penalize_coarse=pc, sigma=10.0, rho=rho,
                         flags=flags) as m:
             m.step(7)  # odd: the fused tail's planes end in its second buffer
             out[flags] = (m.get_x().cpu().numpy(), m.get_u().cpu().numpy(), m.get_v().cpu().numpy())
-    for flags in (0, lib.FLAG_NO_FUSED_TAIL):
+    for flags in (lib.FLAG_FUSED_TAIL, lib.FLAG_NO_FUSED_TAIL):
         for a, b in zip(out[flags], out[lib.FLAG_SINGLE_SCALE]):
             np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("flags", [0, 2])
+@pytest.mark.parametrize("flags", [0, 2, 4])
 def test_pairs_autotuned_match_single_scale(lib, flags):
     c = synth.make_cube(synth.CubeSpec(N=128, L=6, J=5, n_sources=6, n_baselines=300, seed=9))
     kw = dict(J=5, mu_s=0.25, mu_lambda=3.0, sigma=10.0)
@@ -54,12 +54,14 @@ def test_pairs_autotuned_match_single_scale(lib, flags):
 
 # launch kinds: 0 one analysis scale, 1 one adjoint step, 2 last analysis scale with the coarse plane,
 # 3/4/5 the same for pairs, 6/7/8 for triples, 9 the last analysis pair fused with the next
-# iteration's first adjoint pair (coarse plane penalised, last group a pair; flag 2 turns it off)
+# iteration's first adjoint pair (coarse plane penalised, last group a pair; flag 4 forces it, flag 2
+# turns it off, and by default a cube of 4 channels is too small for it)
 @pytest.mark.parametrize("J,pc,flags,counts", [
     (5, True, 2, {6: 1, 5: 1, 4: 1, 7: 1}), (4, True, 2, {3: 1, 4: 2, 5: 1}), (2, True, 2, {5: 1, 4: 1}),
+    (5, True, 0, {6: 1, 5: 1, 4: 1, 7: 1}),
     (3, True, 0, {8: 1, 7: 1}), (6, True, 0, {6: 1, 8: 1, 7: 2}), (1, True, 0, {2: 1, 1: 1}),
-    (5, True, 0, {6: 1, 9: 1, 7: 1}), (4, True, 0, {3: 1, 9: 1, 4: 1}), (2, True, 0, {9: 1}),
-    (5, False, 0, {6: 1, 3: 1, 4: 1, 7: 1}), (3, True, 2, {8: 1, 7: 1})])
+    (5, True, 4, {6: 1, 9: 1, 7: 1}), (4, True, 4, {3: 1, 9: 1, 4: 1}), (2, True, 4, {9: 1}),
+    (5, False, 4, {6: 1, 3: 1, 4: 1, 7: 1}), (3, True, 4, {8: 1, 7: 1})])
 def test_profile_reports_the_launch_schedule(lib, J, pc, flags, counts):
     c = synth.make_cube(synth.CubeSpec(N=128, L=4, J=J, n_sources=3, n_baselines=100, seed=2))
     with lib.Muffin(c.dirty, c.psf, J=J, mu_s=0.25, mu_lambda=3.0, penalize_coarse=pc, flags=flags) as m:
