@@ -93,7 +93,8 @@ __global__ void __launch_bounds__(256) k_spectral_step(SpectralArgs a) {
 // dense products.  A workgroup owns 64 pixels, one per lane, and stages their dual spectra and d
 // across all L channels in LDS.  A wave computes CW channels at a time, so the cosine-table
 // entries it needs are the same in every lane (scalar loads) and each LDS read feeds CW FMAs;
-// the sums run over k in order, as in k_spectral_step.
+// the sums run over k in order, as in k_spectral_step.  The k loops are unrolled sixteen times, so
+// that each table row is read sixteen entries per scalar load.
 constexpr int PXM = 64;
 constexpr int kMatMaxL = 256;
 // the cosine tables are read-only for the whole launch: read them through the constant address
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
     const_fp Wr[CW];
 #pragma unroll
     for (int c = 0; c < CW; ++c) Wr[c] = (const_fp)(a.W + (long long)min(l0 + c, L - 1) * L);
-#pragma unroll 4
+#pragma unroll 16
     for (int k = 0; k < L; ++k) {
       const float v = Vs[k * PXM + lane];
 #pragma unroll
@@ -159,7 +160,7 @@ __global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
       acc[c] = 0.f;
       Wr[c] = (const_fp)(a.WT + (long long)min(k0 + c, L - 1) * L);
     }
-#pragma unroll 4
+#pragma unroll 16
     for (int l = 0; l < L; ++l) {
       const float dv = Ds[l * PXM + lane];
 #pragma unroll
