@@ -22,6 +22,9 @@ CASES = [
     (8, 2, 3, False, 1.0),
     (12, 3, 5, True, 1.0),
     (256, 3, 5, True, 1.0),
+    # N = 8: the fused pair's taps (scales 2, 3 at J = 4; 3, 4 at J = 5) span or exceed the side
+    (8, 2, 4, True, 1.0),
+    (8, 2, 5, True, 0.9),
 ]
 
 
