@@ -77,8 +77,8 @@ MEASURED_TRAFFIC = {
     "k_triple<TR_ANALYSIS> (three scales of analysis + spatial dual steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "d88f4e8cc9086415",
-        "fetch_kib": 2201710.2,
+        "sha256": "5db10344d1e4897a",
+        "fetch_kib": 2306156.9,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -86,8 +86,8 @@ MEASURED_TRAFFIC = {
     "k_fused (last analysis pair + next iteration's first adjoint pair)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "d88f4e8cc9086415",
-        "fetch_kib": 2857076.4,
+        "sha256": "5db10344d1e4897a",
+        "fetch_kib": 2857076.2,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -95,8 +95,8 @@ MEASURED_TRAFFIC = {
     "k_triple<TR_ADJOINT> (three adjoint Horner steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "d88f4e8cc9086415",
-        "fetch_kib": 2201697.5,
+        "sha256": "5db10344d1e4897a",
+        "fetch_kib": 2201697.8,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -104,8 +104,8 @@ MEASURED_TRAFFIC = {
     "k_spectral_fft (fused spectral step)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/spectral.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/fft_core.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "3fe679042eef52ec",
-        "fetch_kib": 1573124.6,
+        "sha256": "3a928947755fd6a0",
+        "fetch_kib": 1573123.8,
         "write_kib": 3145728.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0

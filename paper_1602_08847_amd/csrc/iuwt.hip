@@ -560,17 +560,18 @@ __global__ void __launch_bounds__(1024) k_pair_trial(AtrousArgs a) {
 }
 
 // ------------------------------------------------------------------ triples of scales
-// Three consecutive scales j, j + 1, j + 2 in one pass, the same way as the pairs: with s = 2^j,
+// Three consecutive scales j, j + 1, j + 2 in one pass, in the pairs' visiting order: with s = 2^j,
 // H_j, H_{j+1} and H_{j+2} have their vertical taps 1 and 2, 2 and 4, 4 and 8 class steps apart
-// (windows of 5, 9 and 17 entries), one row per round, four LDS barriers per row.  Load index i of
-// class r is row y0 + r + (i - 22) s.
-//   TR_ANALYSIS:  c1 = H_j c (index t - 2 after loading c(t)), w_j = c - H_j c1 (t - 4),
+// (windows of 5, 9 and 17 entries), one row per step.  Load index i of class r is row
+// y0 + r + (i - 22) s; with c loaded at index t the one-stage-per-step schedule is
+//   TR_ANALYSIS:  c1 = H_j c (index t - 2), w_j = c - H_j c1 (t - 4),
 //                 c2 = H_{j+1} c1 (t - 6), w_{j+1} = c1 - H_{j+1} c2 (t - 10),
 //                 c3 = H_{j+2} c2 (t - 14), w_{j+2} = c2 - H_{j+2} c3 (t - 22)
 //   TR_ADJOINT:   a1 = u_{j+2} + H_{j+2}(a - H_{j+2} u_{j+2}) (t - 16),
 //                 a2 = u_{j+1} + H_{j+1}(a1 - H_{j+1} u_{j+1}) (t - 20),
 //                 a3 = u_j + H_j(a2 - H_j u_j) (t - 22)
-// As with the pairs, every stage repeats the one-scale kernels' operations in their order.
+// and both kernels run these stages skewed over consecutive steps (below).  As with the pairs,
+// every stage repeats the one-scale kernels' operations in their order.
 struct TriPre {
   float p0, p1, p2, p3, p4;
 };
