@@ -1,0 +1,77 @@
+"""Parity at the full size of the timed single-cube workload (1024 x 1024 pixels, 256 channels, J = 5,
+mu_s = 0.25, mu_lambda = 3, sigma = rho = 1) in the launch configuration the benchmark times
+(autotuned band rows and fused-tail choice, graph replay): two iterations from a seeded positive
+X0 against the FP64 oracle, X1 and V1 compared in full, U1, X2 and U2 on three channels.
+
+X2 is the first iterate whose spatial adjoint term reads the sum the previous iteration's last
+analysis launch carried over (when the autotuner picks the fused tail), and U2 the first analysis
+that runs after it."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import muffin as om
+from paper_1602_08847_amd import synth
+from two_step_oracle import two_passes_sampled
+
+pytestmark = pytest.mark.gpu
+
+CHANS = [0, 137, 255]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def log(msg):
+    print(f"[fullsize] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.mark.timeout(900)
+def test_full_size_two_iterations_match_oracle(lib):
+    import torch
+    spec = synth.WORKLOADS["cube1024_L256_J5"]
+    N, L, J = spec.N, spec.L, spec.J
+    t0 = time.time()
+    cube = synth.make_cube(spec, dtype=np.float32, with_sky=False)
+    rng = np.random.default_rng(7)
+    X0 = np.abs(rng.standard_normal(size=(L, N, N), dtype=np.float32)) * np.float32(8.0 * cube.dirty.std())
+    log(f"cube {N}x{N}x{L} J={J} generated ({time.time() - t0:.1f}s)")
+
+    with lib.Muffin(cube.dirty, cube.psf, J=J, mu_s=0.25, mu_lambda=3.0) as m:
+        tune = m.autotune(reps=3)
+        log(f"autotuned: {tune}")
+        tau_gpu = m.info()["tau"]
+        m.set_x(X0)
+        m.step(1)
+        X1 = m.get_x().cpu().numpy()
+        V1 = m.get_v().cpu().numpy()
+        U1 = m.get_u()[CHANS].cpu().numpy()
+        m.step(1)
+        X2 = m.get_x()[CHANS].cpu().numpy()
+        U2 = m.get_u()[CHANS].cpu().numpy()
+    torch.cuda.empty_cache()
+    log(f"two GPU iterations done ({time.time() - t0:.1f}s)")
+
+    dirty, psf = cube.dirty.astype(np.float64), cube.psf.astype(np.float64)
+    del cube
+    p = om.Problem(dirty=dirty, psf=psf, J=J, mu_s=0.25, mu_l=3.0)
+    tau = om.step_sizes(p)[0]
+    assert abs(tau_gpu - tau) / tau < 1e-5
+    ref = two_passes_sampled(dirty, psf, X0.astype(np.float64), J, 0.25, 3.0, tau, CHANS, workers=16)
+    log(f"oracle done ({time.time() - t0:.1f}s)")
+
+    # both branches of the positive part and of both saturations are taken
+    assert 0 < np.mean(ref["X2"] == 0) < 1
+    assert 0 < np.mean(np.abs(ref["V1"]) == 1) < 1
+    assert 0 < np.mean(np.abs(ref["U1"]) == 1) < 1 and 0 < np.mean(np.abs(ref["U2"]) == 1) < 1
+
+    errs = {k: rel(got, ref[k]) for k, got in (("X1", X1), ("V1", V1), ("U1", U1), ("X2", X2), ("U2", U2))}
+    log(f"relative errors {errs}")
+    for k, e in errs.items():
+        assert e < 1e-5, (k, e)
+    # and entry by entry, against each array's scale
+    for k, got in (("X1", X1), ("V1", V1), ("U1", U1), ("X2", X2), ("U2", U2)):
+        assert np.max(np.abs(got - ref[k])) <= 1e-4 * np.max(np.abs(ref[k])), k
