@@ -124,4 +124,8 @@ def test_trained_warm_start_gains_over_cold_start(lib):
                 for k in (200, 800):
                     m.step(k)
                     f[mode].append(m.objective()[0])
+        # the fixed-budget comparison: the warm start reaches the cold run's 1000-iteration objective sooner
+        b = ws.compare_budget(n, cube, 3, 100.0, budget=1000, check_every=50)
     assert all(w < c for w, c in zip(f["warm"], f["cold"])), f
+    assert b["f_target"] == pytest.approx(f["cold"][-1], rel=1e-12)
+    assert b["warm_reached"] and b["warm_iters"] < b["cold_iters"] and b["warm_f"] <= b["f_target"], b
