@@ -46,14 +46,14 @@ KERNEL_BYTES = {
     # reads c_{J-2}, u_{J-2}, u_{J-1}, u_J, writes u_{J-2}, u_{J-1}, u_J
     "k_pair<PR_ANALYSIS_C> (last two analysis scales + spatial and coarse dual steps)": 28.0,
     # reads c_j, u_j, u_{j+1}, u_{j+2}, writes u_j, u_{j+1}, u_{j+2}, c_{j+3}
-    "k_triple<TR_ANALYSIS> (three scales of analysis + spatial dual steps)": 32.0,
+    "k_triple_an<RS, false> (three scales of analysis + spatial dual steps)": 32.0,
     # reads u_{j+2}, u_{j+1}, u_j and a, writes the new sum
-    "k_triple<TR_ADJOINT> (three adjoint Horner steps)": 20.0,
+    "k_triple_adj<RS> (three adjoint Horner steps)": 20.0,
     # reads c_{J-3}, the three u planes and u_J, writes the three u planes and u_J
-    "k_triple<TR_ANALYSIS_C> (last three analysis scales + spatial and coarse dual steps)": 36.0,
+    "k_triple_an<RS, true> (last three analysis scales + spatial and coarse dual steps)": 36.0,
     # reads c_{J-2} and the old u_{J-2}, u_{J-1}, u_J; writes the new ones and the adjoint sum after
     # the next iteration's first two Horner steps
-    "k_fused (last analysis pair + next iteration's first adjoint pair)": 32.0,
+    "k_fused<RS> (last analysis pair + next iteration's first adjoint pair)": 32.0,
 }
 PROFILE_SLOT = {
     "k_band<DB_ANALYSIS> (one scale of analysis + spatial dual step)": 0,
@@ -62,10 +62,10 @@ PROFILE_SLOT = {
     "k_pair<PR_ANALYSIS> (two scales of analysis + spatial dual steps)": 3,
     "k_pair<PR_ADJOINT> (two adjoint Horner steps)": 4,
     "k_pair<PR_ANALYSIS_C> (last two analysis scales + spatial and coarse dual steps)": 5,
-    "k_triple<TR_ANALYSIS> (three scales of analysis + spatial dual steps)": 6,
-    "k_triple<TR_ADJOINT> (three adjoint Horner steps)": 7,
-    "k_triple<TR_ANALYSIS_C> (last three analysis scales + spatial and coarse dual steps)": 8,
-    "k_fused (last analysis pair + next iteration's first adjoint pair)": 9,
+    "k_triple_an<RS, false> (three scales of analysis + spatial dual steps)": 6,
+    "k_triple_adj<RS> (three adjoint Horner steps)": 7,
+    "k_triple_an<RS, true> (last three analysis scales + spatial and coarse dual steps)": 8,
+    "k_fused<RS> (last analysis pair + next iteration's first adjoint pair)": 9,
 }
 
 
@@ -74,29 +74,29 @@ PROFILE_SLOT = {
 # iteration, times the factor a 1 GiB elementwise copy (--calib-copy) gives for the same counter.
 # An entry holds only for the kernel sources it was taken on (hash below); otherwise traffic is null.
 MEASURED_TRAFFIC = {
-    "k_triple<TR_ANALYSIS> (three scales of analysis + spatial dual steps)": {
+    "k_triple_an<RS, false> (three scales of analysis + spatial dual steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "5db10344d1e4897a",
-        "fetch_kib": 2306156.9,
+        "sha256": "1565ca0eec50436b",
+        "fetch_kib": 2306157.1,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     },
-    "k_fused (last analysis pair + next iteration's first adjoint pair)": {
+    "k_fused<RS> (last analysis pair + next iteration's first adjoint pair)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "5db10344d1e4897a",
-        "fetch_kib": 2857076.2,
+        "sha256": "1565ca0eec50436b",
+        "fetch_kib": 2857077.1,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     },
-    "k_triple<TR_ADJOINT> (three adjoint Horner steps)": {
+    "k_triple_adj<RS> (three adjoint Horner steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "5db10344d1e4897a",
-        "fetch_kib": 2201697.8,
+        "sha256": "1565ca0eec50436b",
+        "fetch_kib": 2191368.9,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -104,9 +104,9 @@ MEASURED_TRAFFIC = {
     "k_spectral_fft (fused spectral step)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/spectral.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/fft_core.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "3a928947755fd6a0",
-        "fetch_kib": 1573123.8,
-        "write_kib": 3145728.0,
+        "sha256": "142e61509296cdce",
+        "fetch_kib": 1573064.9,
+        "write_kib": 3145845.9,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     }

@@ -48,6 +48,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
+// Streaming (nontemporal) global accesses: the line is marked for early eviction instead of being
+// kept in L2 and the Infinity Cache.  They pay where the data is not read again soon (a plane the
+// next launch does not touch) and cost where it is: a kernel that re-reads its own halo rows, or a
+// launch whose output the very next launch reads, loses the cache hits.  Which kernels use them is
+// decided by measurement, kernel by kernel.
+__device__ __forceinline__ float ld_stream(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_stream(float* p, float v) { __builtin_nontemporal_store(v, p); }
+
 // ------------------------------------------------------------------ complex helpers
 __host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

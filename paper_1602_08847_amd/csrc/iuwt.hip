@@ -617,7 +617,8 @@ __device__ __forceinline__ void triple_an_body(const AtrousArgs& a) {
   const int rowb = N * 4, planeb = N * N * 4, stepb = (s % N) * rowb;
   const unsigned xb = (unsigned)x * 4u;
   auto at = [&](const char* base, int off) -> float {
-    return *reinterpret_cast<const float*>(base + off + xb);
+    // streaming loads (the stores stay cached: the next launch reads c_{j+3})
+    return ld_stream(reinterpret_cast<const float*>(base + off + xb));
   };
   auto put = [&](float* base, int y, float v) {
     *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
@@ -827,10 +828,11 @@ __device__ __forceinline__ void triple_adj_body(const AtrousArgs& a) {
   const int rowb = N * 4, planeb = N * N * 4, stepb = (s % N) * rowb;
   const unsigned xb = (unsigned)x * 4u;
   auto at = [&](const char* base, int off) -> float {
-    return *reinterpret_cast<const float*>(base + off + xb);
+    // streaming: every row is read once, and the new sum is next read two launches later
+    return ld_stream(reinterpret_cast<const float*>(base + off + xb));
   };
   auto put = [&](float* base, int y, float v) {
-    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
+    st_stream(reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb), v);
   };
   auto nsteps = [&](int r) -> int {
     const int v = TY - r;

@@ -229,10 +229,11 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     return base + (long long)el_l(i) * cs + pix0 + el_p(i);
   };
   auto el_out = [&](float* base, int i) -> float* { return const_cast<float*>(el_ptr(base, i)); };
-  // V of the thread's elements, kept in registers for the dual step
+  // V of the thread's elements, kept in registers for the dual step.  X, q, V and d are each
+  // touched once per iteration here, so the kernel's global accesses are streaming.
   float vreg[PER];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) vreg[i] = el_ok(i) ? *el_ptr(a.V, i) : 0.f;
+  for (int i = 0; i < PER; ++i) vreg[i] = el_ok(i) ? ld_stream(el_ptr(a.V, i)) : 0.f;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     if (FIXP || threadIdx.x + i * NT < L * PXB) {
@@ -272,8 +273,8 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   float xreg[PER], qreg[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    xreg[i] = el_ok(i) ? *el_ptr(a.X, i) : 0.f;
-    qreg[i] = el_ok(i) ? *el_ptr(a.Q, i) : 0.f;
+    xreg[i] = el_ok(i) ? ld_stream(el_ptr(a.X, i)) : 0.f;
+    qreg[i] = el_ok(i) ? ld_stream(el_ptr(a.Q, i)) : 0.f;
   }
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
@@ -286,8 +287,8 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
       const float x = xreg[i];
       const float xt = fmaxf(x - a.tau * (qreg[i] + tv), 0.f);
       d = 2.f * xt - x;
-      *el_out(a.D, i) = d;
-      *el_out(a.X, i) = a.rho * xt + (1.f - a.rho) * x;
+      st_stream(el_out(a.D, i), d);
+      st_stream(el_out(a.X, i), a.rho * xt + (1.f - a.rho) * x);
     }
     *slot = d;
   }
@@ -312,7 +313,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     const float c = (v.x * e.x + v.y * e.y) * (k ? s1 : s0);
     if (el_ok(i)) {
       const float vo = vreg[i];
-      *el_out(a.V, i) = a.rho * satf_s(vo + c) + (1.f - a.rho) * vo;
+      st_stream(el_out(a.V, i), a.rho * satf_s(vo + c) + (1.f - a.rho) * vo);
     }
   }
 }
