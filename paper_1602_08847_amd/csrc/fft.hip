@@ -48,13 +48,14 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const float* __restrict__ x, l
     }
     const float* pa = xc + (long long)ra * N;
     const float* pb = xc + (long long)rb * N;
-    // all N/T loads of the thread in flight at once, then into LDS
+    // all N/T loads of the thread in flight at once, then into LDS; x is read once per pass
+    // (streaming), while the half spectrum this pass writes stays cached for the next pass
     float va[NI], vb[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
       const int c = shift ? (t + i * T + N / 2) % N : t + i * T;
-      va[i] = pa[c];
-      vb[i] = pb[c];
+      va[i] = ld_stream(pa + c);
+      vb[i] = ld_stream(pb + c);
     }
 #pragma unroll
     for (int i = 0; i < NI; ++i) buf[lpad(t + i * T)] = make_float2(va[i], vb[i]);
@@ -128,7 +129,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu((N & (
   if constexpr (MODE == COL_REAL) {
     const float* __restrict__ mp = Mr + mrow + t;
 #pragma unroll
-    for (int i = 0; i < NI; ++i) mr[i] = mp[i * T];
+    for (int i = 0; i < NI; ++i) mr[i] = ld_stream(mp + i * T);  // constant, read once per pass
   }
   if constexpr (MODE == COL_CPLX || MODE == COL_CPLX_CONJ) {
     const float2* __restrict__ mp = Mc + mrow + t;
@@ -238,15 +239,15 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
       const float* __restrict__ ep = ((EPI == EPI_GRAD) ? b : y) + o0 + t;
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
-        e0[i] = ep[i * T];
-        e1[i] = ep[N + i * T];
+        e0[i] = ld_stream(ep + i * T);  // b or y, and below the adjoint term: read once (streaming)
+        e1[i] = ld_stream(ep + N + i * T);
       }
       if (EPI == EPI_GRAD && s) {
         const float* __restrict__ sp = s + o0 + t;
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
-          s0[i] = sp[i * T];
-          s1[i] = sp[N + i * T];
+          s0[i] = ld_stream(sp + i * T);
+          s1[i] = ld_stream(sp + N + i * T);
         }
       }
     }
