@@ -56,11 +56,16 @@ def build_training_set(n_cubes: int, spec: synth.CubeSpec, iters: int, sigma: fl
 
 
 def train(net: muffin.Cnn, inputs, targets, epochs: int, batch: int, lr: float, seed: int = 0, log=print):
-    """Adam on shuffled batches of channel images; returns the per-epoch mean loss."""
+    """Adam on shuffled batches of channel images; returns the per-epoch mean loss.
+
+    An epoch whose mean loss is not below the best so far halves the learning rate, and the
+    network ends with the parameters of its best epoch (a late Adam step can throw the loss back
+    up by several times)."""
     import torch
     n = inputs.shape[0]
     g = torch.Generator().manual_seed(seed)
     hist = []
+    best, best_params = math.inf, None
     for ep in range(epochs):
         perm = torch.randperm(n, generator=g).cuda()
         tot, cnt = 0.0, 0
@@ -69,8 +74,14 @@ def train(net: muffin.Cnn, inputs, targets, epochs: int, batch: int, lr: float, 
             tot += net.train_step(inputs[idx].contiguous(), targets[idx].contiguous(), lr)
             cnt += 1
         hist.append(tot / max(cnt, 1))
+        if hist[-1] < best:
+            best, best_params = hist[-1], net.get_params()
+        else:
+            lr *= 0.5
         if log:
-            log(f"[warmstart] epoch {ep + 1}/{epochs} loss {hist[-1]:.4e}")
+            log(f"[warmstart] epoch {ep + 1}/{epochs} loss {hist[-1]:.4e} (lr {lr:.2e})")
+    if best_params is not None:
+        net.set_params(best_params)
     return hist
 
 
