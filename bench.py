@@ -78,7 +78,7 @@ MEASURED_TRAFFIC = {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
         "sha256": "1565ca0eec50436b",
-        "fetch_kib": 2306157.1,
+        "fetch_kib": 2201710.1,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -87,7 +87,7 @@ MEASURED_TRAFFIC = {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
         "sha256": "1565ca0eec50436b",
-        "fetch_kib": 2857077.1,
+        "fetch_kib": 2857076.8,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -96,7 +96,7 @@ MEASURED_TRAFFIC = {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
         "sha256": "1565ca0eec50436b",
-        "fetch_kib": 2191368.9,
+        "fetch_kib": 2191524.2,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -105,8 +105,8 @@ MEASURED_TRAFFIC = {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/spectral.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/fft_core.h", "paper_1602_08847_amd/csrc/api.hip"],
         "sha256": "142e61509296cdce",
-        "fetch_kib": 1573064.9,
-        "write_kib": 3145845.9,
+        "fetch_kib": 1573064.6,
+        "write_kib": 3145827.1,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     }
