@@ -186,9 +186,12 @@ struct IuwtStep {
 
 static std::vector<int> iuwt_groups(const muffin_ctx* c) {
   const int J = c->J;
-  if (c->gen == 1 || (c->p.flags & MUFFIN_FLAG_SINGLE_SCALE)) return std::vector<int>(J, 1);
+  if (c->p.flags & MUFFIN_FLAG_SINGLE_SCALE) return std::vector<int>(J, 1);
+  // first generation: pairs only, a single scale first so that the last analysis group is a pair
+  // and takes the coarse plane's dual step
+  static const std::vector<int> g1[7] = {{}, {1}, {2}, {1, 2}, {2, 2}, {1, 2, 2}, {2, 2, 2}};
   static const std::vector<int> g[7] = {{}, {1}, {2}, {3}, {2, 2}, {3, 2}, {3, 3}};
-  return g[J];
+  return c->gen == 1 ? g1[J] : g[J];
 }
 
 static std::vector<IuwtStep> analysis_schedule(const muffin_ctx* c) {
@@ -201,7 +204,8 @@ static std::vector<IuwtStep> analysis_schedule(const muffin_ctx* c) {
     switch (groups[k]) {
       case 3: v.push_back({last ? TR_ANALYSIS_C : TR_ANALYSIS, j, "analysis triple"}); break;
       case 2:
-        if (last && c->fused) v.push_back({PR_FUSED, j, "analysis pair + next adjoint pair"});
+        if (c->gen == 1) v.push_back({last ? P1_ANALYSIS_C : P1_ANALYSIS, j, "analysis pair"});
+        else if (last && c->fused) v.push_back({PR_FUSED, j, "analysis pair + next adjoint pair"});
         else v.push_back({last ? PR_ANALYSIS_C : PR_ANALYSIS, j, "analysis pair"});
         break;
       default:
@@ -221,7 +225,7 @@ static std::vector<IuwtStep> adjoint_schedule(const muffin_ctx* c) {
     const int j = top - groups[k];
     switch (groups[k]) {
       case 3: v.push_back({TR_ADJOINT, j, "adjoint triple"}); break;
-      case 2: v.push_back({PR_ADJOINT, j, "adjoint pair"}); break;
+      case 2: v.push_back({c->gen == 1 ? P1_ADJOINT : PR_ADJOINT, j, "adjoint pair"}); break;
       default: v.push_back({c->gen == 1 ? SM_SUBADD : DB_ADJOINT, j, "adjoint"});
     }
     top = j;
@@ -266,11 +270,11 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ups, long long 
                              pref(Ubase + (long long)(j + 1) * ups, ucs), pref(uj, ucs), pref(a, acs), pout(dst, np),
                              PlaneOut{}, PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f, c->st);
       }));
-    } else if (st.mode == PR_ADJOINT) {
+    } else if (st.mode == PR_ADJOINT || st.mode == P1_ADJOINT) {
       // steps j + 1 then j
       const float* uh = Ubase + (long long)(j + 1) * ups;
       MF_TRY(timed_launch(c, timed, K_PR_ADJOINT, [&] {
-        return launch_pair(PR_ADJOINT, c->N, c->L, j, pref(uh, ucs), pref(uj, ucs), pref(a, acs), pout(dst, np),
+        return launch_pair(st.mode, c->N, c->L, j, pref(uh, ucs), pref(uj, ucs), pref(a, acs), pout(dst, np),
                            PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f, c->st);
       }));
     } else if (st.mode == DB_ADJOINT) {
@@ -319,10 +323,12 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false, int 
         MF_TRY(launch_atrous(SM_DETAIL1, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
                              pout(nxt, np), coef, rho, nullptr, nullptr, c->st));
         break;
+      case P1_ANALYSIS_C:
+      case P1_ANALYSIS:
       case PR_ANALYSIS_C:
       case PR_ANALYSIS: {
         float* uj1 = c->U + (long long)(j + 1) * us;
-        const bool co = st.mode == PR_ANALYSIS_C;
+        const bool co = st.mode == PR_ANALYSIS_C || st.mode == P1_ANALYSIS_C;
         MF_TRY(timed_launch(c, timed, co ? K_PR_ANALYSIS_C : K_PR_ANALYSIS, [&] {
           return launch_pair(st.mode, c->N, c->L, j, pref(cur, np), PlaneRef{}, PlaneRef{}, pout(uj, ucs),
                              pout(uj1, ucs), co ? pout(Uc, ucs) : pout(nxt, np), coef, rho, co ? coefc : 0.f, c->st);
@@ -356,7 +362,8 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false, int 
     cur = nxt;
     nb ^= 1;
   }
-  if (c->gen == 1 && coarse)
+  // a first-generation schedule that ends with a single scale updates the coarse plane's dual here
+  if (c->gen == 1 && coarse && analysis_schedule(c).back().mode == SM_DETAIL1)
     MF_TRY(launch_pointwise(PT_COARSE, c->N, c->L, pref(cur, np), PlaneRef{}, pout(Uc, ucs), coefc, rho, nullptr,
                             nullptr, c->st));
   return MUFFIN_OK;
@@ -789,6 +796,8 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
                                      pout(c->D, np), 0.f, 1.f, 0.f, c->st, 1);
           case PR_ANALYSIS:
           case PR_ANALYSIS_C:
+          case P1_ANALYSIS:
+          case P1_ANALYSIS_C:
             return launch_pair(mode, c->N, c->L, j, pref(c->X, np), PlaneRef{}, PlaneRef{}, pout(c->cB, np),
                                pout(c->cT, np), pout(c->cA, np), 0.f, 1.f, 0.f, c->st, 1);
           case TR_ANALYSIS:
@@ -802,6 +811,7 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
                                  pref(c->cA, np), pout(c->cB, np), PlaneOut{}, PlaneOut{}, PlaneOut{}, 0.f, 1.f, 0.f,
                                  c->st, 1);
           case PR_ADJOINT:
+          case P1_ADJOINT:
             return launch_pair(mode, c->N, c->L, j, pref(c->U + (long long)(j + 1) * us, ucs),
                                pref(c->U + (long long)j * us, ucs), pref(c->cA, np), pout(c->cB, np), PlaneOut{},
                                PlaneOut{}, 0.f, 1.f, 0.f, c->st, 1);

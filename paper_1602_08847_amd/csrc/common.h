@@ -132,8 +132,12 @@ enum AtrousMode {
   TR_ADJOINT = 13,    // A = u_{j+2}, B = u_{j+1}, E = u_j, F = a: out = Horner steps j+2, j+1, j
   // the last analysis pair (scales j, j+1, coarse plane) fused with the next iteration's first
   // adjoint pair over the planes it has just updated:
-  PR_FUSED = 14       // A = c_j; B, E, F = old u_j, u_{j+1}, coarse; out, out2, out3 = new ones;
+  PR_FUSED = 14,      // A = c_j; B, E, F = old u_j, u_{j+1}, coarse; out, out2, out3 = new ones;
                       // out4 = two Horner steps (scale j+1 then j) starting from the new coarse plane
+  // two consecutive scales j, j+1 in one pass (first generation):
+  P1_ANALYSIS = 15,   // A = c_j; out = u_j, out2 = u_{j+1} (dual updates, w = c - H c); out3 = c_{j+2}
+  P1_ANALYSIS_C = 16, // P1_ANALYSIS with c_{j+2} feeding the coarse plane's dual update (out3, coef2)
+  P1_ADJOINT = 17     // A = u_{j+1}, B = u_j, E = a: out = u_j + H_j(a' - u_j), a' = u_{j+1} + H_{j+1}(a - u_{j+1})
 };
 // launch of a pair kernel: j is the finer scale of the pair
 int launch_pair(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out, PlaneOut out2,

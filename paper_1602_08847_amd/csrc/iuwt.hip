@@ -310,6 +310,10 @@ __global__ void __launch_bounds__(1024) k_band_trial(AtrousArgs a) {
 //                 c2 = H_{j+1} c1 (t - 6), w_{j+1} = c1 - H_{j+1} c2 (t - 10)
 //   PR_ADJOINT:   h = H_{j+1} u_{j+1} (t - 4), a' = u_{j+1} + H_{j+1}(a - h) (t - 8),
 //                 a'' = u_j + H_j(a' - H_j u_j) (t - 10)
+// The first generation smooths once per scale, so its pairs need 6 class steps of halo:
+//   P1_ANALYSIS:  c1 = H_j c (t - 2), w_j = c - c1 (t - 2), c2 = H_{j+1} c1 (t - 6),
+//                 w_{j+1} = c1 - c2 (t - 6)
+//   P1_ADJOINT:   a' = u_{j+1} + H_{j+1}(a - u_{j+1}) (t - 4), a'' = u_j + H_j(a' - u_j) (t - 6)
 // Every stage performs the same operations in the same order as the one-scale kernels, so the
 // results are identical to running them one after the other.
 template <int KR>
@@ -319,9 +323,10 @@ struct PairPre {
 
 template <int MODE, int KR>
 __device__ __forceinline__ void pair_body(const AtrousArgs& a) {
-  constexpr bool ADJ = (MODE == PR_ADJOINT);
-  constexpr bool CO = (MODE == PR_ANALYSIS_C);
-  constexpr int HALO = 10;
+  constexpr bool G1 = (MODE == P1_ANALYSIS || MODE == P1_ANALYSIS_C || MODE == P1_ADJOINT);
+  constexpr bool ADJ = (MODE == PR_ADJOINT || MODE == P1_ADJOINT);
+  constexpr bool CO = (MODE == PR_ANALYSIS_C || MODE == P1_ANALYSIS_C);
+  constexpr int HALO = G1 ? 6 : 10;
   extern __shared__ float sm[];
   const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
   float* bA = sm;
@@ -364,14 +369,17 @@ __device__ __forceinline__ void pair_body(const AtrousArgs& a) {
     o += stepb;
     if (o >= planeb) o -= planeb;
   };
-  // load streams: p0 at index t, p1 at t - 4, p2 at t - 6 (adjoint: u_j) or t - 10 (analysis:
-  // u_{j+1}), p3 at t - 6 (coarse plane)
+  // load streams: p0 at index t, p1 at t - D1, p2 at t - D2, p3 at t - 6 (coarse plane).  Second
+  // generation: p1 at t - 4, p2 at t - 6 (adjoint: u_j) or t - 10 (analysis: u_{j+1}); first
+  // generation: analysis u_j at t - 2 and u_{j+1} at t - 6, adjoint a at t and u_j at t - 4
+  constexpr int D1 = G1 ? (ADJ ? 0 : 2) : 4;
+  constexpr int D2 = G1 ? (ADJ ? 4 : 6) : (ADJ ? 6 : 10);
   int lr = 0, lt = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0;
   auto start_class = [&](int r) {
     const int f = y0 + r - HALO * s;
     o0 = rowoff(f);
-    o1 = rowoff(f - 4 * s);
-    o2 = rowoff(f - (ADJ ? 6 : 10) * s);
+    o1 = rowoff(f - D1 * s);
+    o2 = rowoff(f - D2 * s);
     if constexpr (CO) o3 = rowoff(f - 6 * s);
   };
   auto load_round = [&](PairPre<KR>& P) {
@@ -403,11 +411,11 @@ __device__ __forceinline__ void pair_body(const AtrousArgs& a) {
     }
   };
   // windows, oldest first
-  float wa[9], wb[9], wc[5], wd[5];
+  float wa[9], wb[9], wc[5], wd[5], we[5];
 #pragma unroll
   for (int i = 0; i < 9; ++i) wa[i] = wb[i] = 0.f;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) wc[i] = wd[i] = 0.f;
+  for (int i = 0; i < 5; ++i) wc[i] = wd[i] = we[i] = 0.f;
   auto push9 = [](float (&w)[9], float v) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) w[i] = w[i + 1];
@@ -422,7 +430,75 @@ __device__ __forceinline__ void pair_body(const AtrousArgs& a) {
   auto v5 = [](const float (&w)[5]) { return b3(w[0], w[1], w[2], w[3], w[4]); };
   // round of steps [t0, t0 + KR) of a class with ns steps whose load index 0 is row first
   auto process = [&](const PairPre<KR>& cur, int t0, int ns, int first) {
-    if constexpr (ADJ) {
+    if constexpr (G1 && ADJ) {
+      // wa: a - u_{j+1} (t-8..t), wd: u_{j+1} (t-4..t), wc: a' - u_j (t-8..t-4), we: u_j (t-8..t-4)
+      float pv1[KR], cuh[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        push9(wa, cur.p1[kk] - cur.p0[kk]);
+        pv1[kk] = v9(wa);
+        push5(wd, cur.p0[kk]);
+        cuh[kk] = wd[0];
+      }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) bA[kk * N + x] = pv1[kk];
+      lds_barrier();
+      float pv2[KR], cul[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const float a1 = cuh[kk] + hj1(bA + kk * N);  // a' at t - 4
+        push5(wc, a1 - cur.p2[kk]);
+        pv2[kk] = v5(wc);
+        push5(we, cur.p2[kk]);
+        cul[kk] = we[2];  // u_j at t - 6
+      }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) bB[kk * N + x] = pv2[kk];
+      lds_barrier();
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const int t = t0 + kk;
+        if (t >= 2 * HALO && t < ns) put(O, first + (t - HALO) * s, cul[kk] + hj(bB + kk * N));
+      }
+    } else if constexpr (G1) {
+      // wc: c (t-4..t), wa: c1 (t-10..t-2)
+      float pv1[KR], cc2[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        push5(wc, cur.p0[kk]);
+        pv1[kk] = v5(wc);
+        cc2[kk] = wc[2];
+      }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) bA[kk * N + x] = pv1[kk];
+      lds_barrier();
+      float pv2[KR], cc6[KR];
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const int t = t0 + kk;
+        const float c1 = hj(bA + kk * N);  // c1 at t - 2
+        if (t >= HALO + 2 && t < ns - HALO + 2) put(O, first + (t - 2) * s, upd(cur.p1[kk], cc2[kk] - c1, a.coef));
+        push9(wa, c1);
+        pv2[kk] = v9(wa);
+        cc6[kk] = wa[4];
+      }
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) bB[kk * N + x] = pv2[kk];
+      lds_barrier();
+#pragma unroll
+      for (int kk = 0; kk < KR; ++kk) {
+        const int t = t0 + kk;
+        const float c2 = hj1(bB + kk * N);  // c2 at t - 6
+        if (t >= 2 * HALO && t < ns) {
+          put(O2, first + (t - HALO) * s, upd(cur.p2[kk], cc6[kk] - c2, a.coef));
+          if constexpr (CO) {
+            put(O3, first + (t - HALO) * s, upd(cur.p3[kk], c2, a.coef2));
+          } else {
+            put(O3, first + (t - HALO) * s, c2);
+          }
+        }
+      }
+    } else if constexpr (ADJ) {
       // wa: u_{j+1} (t-8..t), wc: u_j (t-10..t-6), wb: a - H_{j+1} u_{j+1} (t-12..t-4),
       // wd: a' - H_j u_j (t-12..t-8)
       float pv1[KR], pv3[KR], cuh[KR], cul[KR];
@@ -1313,7 +1389,10 @@ static int band_rows_default(int N, int j) {
   return TY;
 }
 
-static bool is_pair(int mode) { return mode == PR_ANALYSIS || mode == PR_ANALYSIS_C || mode == PR_ADJOINT; }
+static bool is_pair(int mode) {
+  return mode == PR_ANALYSIS || mode == PR_ANALYSIS_C || mode == PR_ADJOINT || mode == P1_ANALYSIS ||
+         mode == P1_ANALYSIS_C || mode == P1_ADJOINT;
+}
 static bool is_triple(int mode) { return mode == TR_ANALYSIS || mode == TR_ANALYSIS_C || mode == TR_ADJOINT; }
 
 static int triple_rows_default(int N, int j) {
@@ -1355,6 +1434,9 @@ int atrous_class(int mode) {
     case TR_ANALYSIS_C: return 7;
     case TR_ADJOINT: return 8;
     case PR_FUSED: return 9;
+    case P1_ANALYSIS:
+    case P1_ANALYSIS_C: return 10;
+    case P1_ADJOINT: return 11;
     default: return 4;
   }
 }
@@ -1475,6 +1557,18 @@ int launch_pair(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRe
     case PR_ANALYSIS_C:
       if (trial) hipLaunchKernelGGL((k_pair_trial<PR_ANALYSIS_C, kKRP>), grid, block, shm, st, a);
       else hipLaunchKernelGGL((k_pair<PR_ANALYSIS_C, kKRP>), grid, block, shm, st, a);
+      break;
+    case P1_ANALYSIS:
+      if (trial) hipLaunchKernelGGL((k_pair_trial<P1_ANALYSIS, kKRP>), grid, block, shm, st, a);
+      else hipLaunchKernelGGL((k_pair<P1_ANALYSIS, kKRP>), grid, block, shm, st, a);
+      break;
+    case P1_ANALYSIS_C:
+      if (trial) hipLaunchKernelGGL((k_pair_trial<P1_ANALYSIS_C, kKRP>), grid, block, shm, st, a);
+      else hipLaunchKernelGGL((k_pair<P1_ANALYSIS_C, kKRP>), grid, block, shm, st, a);
+      break;
+    case P1_ADJOINT:
+      if (trial) hipLaunchKernelGGL((k_pair_trial<P1_ADJOINT, kKRP>), grid, block, shm, st, a);
+      else hipLaunchKernelGGL((k_pair<P1_ADJOINT, kKRP>), grid, block, shm, st, a);
       break;
     default:
       if (trial) hipLaunchKernelGGL((k_pair_trial<PR_ADJOINT, kKRP>), grid, block, shm, st, a);
@@ -1621,6 +1715,16 @@ int atrous_init_attrs() {
   MF_HIP(hipFuncSetAttribute((const void*)k_pair_trial<PR_ANALYSIS_C, kKRP>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
   MF_HIP(hipFuncSetAttribute((const void*)k_pair_trial<PR_ADJOINT, kKRP>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair<P1_ANALYSIS, kKRP>, hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair<P1_ANALYSIS_C, kKRP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair<P1_ADJOINT, kKRP>, hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair_trial<P1_ANALYSIS, kKRP>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair_trial<P1_ANALYSIS_C, kKRP>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
+  MF_HIP(hipFuncSetAttribute((const void*)k_pair_trial<P1_ADJOINT, kKRP>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, shmp));
   MF_HIP(hipFuncSetAttribute((const void*)k_band_trial<SM_SUBADD, kKR>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              shm));

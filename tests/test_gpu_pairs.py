@@ -1,8 +1,9 @@
 """Two or three IUWT scales per launch, and the last analysis pair fused with the next iteration's
 first adjoint pair, against one scale per launch: the fused kernels perform the same operations in
 the same order, so the iterates agree bit for bit, for every J (schedules of singles, pairs and
-triples, each with or without the coarse plane), with and without the coarse plane's penalty, with
-relaxation, and for image sides where the coarse taps wrap around the image several times."""
+triples, each with or without the coarse plane), for both generations of the transform, with and
+without the coarse plane's penalty, with relaxation, and for image sides where the coarse taps
+wrap around the image several times."""
 import numpy as np
 import pytest
 
@@ -43,10 +44,39 @@ def test_pairs_match_single_scale_bitwise(lib, N, L, J, pc, rho):
             np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("flags", [0, 2, 4])
-def test_pairs_autotuned_match_single_scale(lib, flags):
+# first generation: pairs only ({1, 2}, {2, 2}, {1, 2, 2}, {2, 2, 2} scales per launch)
+G1_CASES = [
+    # N, L, J, penalize_coarse, rho
+    (64, 8, 2, True, 1.0),
+    (64, 8, 3, True, 1.0),
+    (64, 8, 4, False, 0.8),
+    (96, 5, 5, True, 0.9),
+    (128, 4, 6, True, 1.0),
+    (16, 3, 4, True, 1.0),
+    (8, 2, 3, False, 1.0),
+    (12, 3, 5, True, 1.0),
+    (8, 2, 5, True, 0.9),
+]
+
+
+@pytest.mark.parametrize("N,L,J,pc,rho", G1_CASES)
+def test_first_generation_pairs_match_single_scale_bitwise(lib, N, L, J, pc, rho):
+    c = synth.make_cube(synth.CubeSpec(N=N, L=L, J=J, n_sources=max(2, N // 16), n_baselines=max(8, N * 2),
+                                       seed=N + J + 100))
+    out = {}
+    for flags in (0, lib.FLAG_SINGLE_SCALE):
+        with lib.Muffin(c.dirty, c.psf, J=J, mu_s=0.25, mu_lambda=3.0, iuwt_gen=1, penalize_coarse=pc, sigma=10.0,
+                        rho=rho, flags=flags) as m:
+            m.step(7)
+            out[flags] = (m.get_x().cpu().numpy(), m.get_u().cpu().numpy(), m.get_v().cpu().numpy())
+    for a, b in zip(out[0], out[lib.FLAG_SINGLE_SCALE]):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("flags,gen", [(0, 2), (2, 2), (4, 2), (0, 1)])
+def test_pairs_autotuned_match_single_scale(lib, flags, gen):
     c = synth.make_cube(synth.CubeSpec(N=128, L=6, J=5, n_sources=6, n_baselines=300, seed=9))
-    kw = dict(J=5, mu_s=0.25, mu_lambda=3.0, sigma=10.0)
+    kw = dict(J=5, mu_s=0.25, mu_lambda=3.0, sigma=10.0, iuwt_gen=gen)
     with lib.Muffin(c.dirty, c.psf, flags=flags, **kw) as a, \
             lib.Muffin(c.dirty, c.psf, flags=lib.FLAG_SINGLE_SCALE, **kw) as b:
         a.autotune(reps=1)
