@@ -77,8 +77,8 @@ MEASURED_TRAFFIC = {
     "k_triple_an<RS, false> (three scales of analysis + spatial dual steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "1565ca0eec50436b",
-        "fetch_kib": 2201710.1,
+        "sha256": "341a505af5bedb9a",
+        "fetch_kib": 2201709.0,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -86,8 +86,8 @@ MEASURED_TRAFFIC = {
     "k_fused<RS> (last analysis pair + next iteration's first adjoint pair)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "1565ca0eec50436b",
-        "fetch_kib": 2857076.8,
+        "sha256": "341a505af5bedb9a",
+        "fetch_kib": 2857077.0,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -95,8 +95,8 @@ MEASURED_TRAFFIC = {
     "k_triple_adj<RS> (three adjoint Horner steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "1565ca0eec50436b",
-        "fetch_kib": 2191524.2,
+        "sha256": "341a505af5bedb9a",
+        "fetch_kib": 2191400.4,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -104,9 +104,9 @@ MEASURED_TRAFFIC = {
     "k_spectral_fft (fused spectral step)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/spectral.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/fft_core.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "142e61509296cdce",
-        "fetch_kib": 1573064.6,
-        "write_kib": 3145827.1,
+        "sha256": "bf9402abe78f9961",
+        "fetch_kib": 1573065.0,
+        "write_kib": 3145877.9,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     }

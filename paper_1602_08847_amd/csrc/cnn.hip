@@ -346,15 +346,25 @@ __global__ void __launch_bounds__(256) k_wgrad_single(const float* __restrict__ 
   }
 }
 
-// out[map(i)] = sum_blk partial[blk][i] for i < n, summed in FP64 in block order.
+// out[map(i)] = sum_blk partial[blk][i] for i < n, in FP64.  A workgroup reduces 32 consecutive
+// entries; its 8 thread groups take every 8th block (group g: blocks g, g + 8, ... in order), and
+// the 8 group sums are added in group order, so the result does not depend on timing.
 // map: 0 identity; 1: [tap][o][c] -> [o][c][tap] (32 x 32 layers, bias after 9216);
 // 2: [tap][c] -> [c][tap] (single-channel layers, bias at 288 (layer 4: only entry 288 used)).
+constexpr int kRedEntries = 32, kRedGroups = 8;  // entries per workgroup, block groups per entry
 __global__ void __launch_bounds__(256) k_reduce_partials(const float* __restrict__ partial, int stride, int n,
                                                          int nblk, float* __restrict__ out, int map) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
+  __shared__ double red[kRedGroups][kRedEntries];
+  const int e = threadIdx.x % kRedEntries, g = threadIdx.x / kRedEntries;
+  const int i = blockIdx.x * kRedEntries + e;
   double s = 0.0;
-  for (int k = 0; k < nblk; ++k) s += partial[(long long)k * stride + i];
+  if (i < n)
+    for (int k = g; k < nblk; k += kRedGroups) s += partial[(long long)k * stride + i];
+  red[g][e] = s;
+  __syncthreads();
+  if (g != 0 || i >= n) return;
+  s = red[0][e];
+  for (int q = 1; q < kRedGroups; ++q) s += red[q][e];
   int dst = i;
   if (map == 1 && i < 9 * FC * FC) {
     const int tap = i / (FC * FC), o = (i / FC) % FC, c = i % FC;
@@ -524,8 +534,8 @@ int forward(muffin_cnn* c, const float* x, int B, int N) {
 }
 
 int reduce_into(muffin_cnn* c, int stride, int n, int nblk, float* out, int map) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3((n + 255) / 256), dim3(256), 0, c->st, c->partial, stride, n, nblk, out,
-                     map);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((n + kRedEntries - 1) / kRedEntries), dim3(256), 0, c->st, c->partial,
+                     stride, n, nblk, out, map);
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }
