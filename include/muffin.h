@@ -154,7 +154,7 @@ int muffin_apply_op(muffin_ctx* ctx, int op, const float* in, float* out);
  *   7 three adjoint steps in one launch, 8 the last three analysis scales with the coarse plane's
  *   dual step, 9 the last two analysis scales with the coarse plane's dual step fused with the
  *   next iteration's first two adjoint steps (which then leave the adjoint phase); k = 10, 11
- *   are 0.
+ *   are 0, and so is every kind of a first-generation context.
  * Each kernel family (adjoint, analysis) is bracketed in every other iteration, so n_iter >= 2.
  * The iterations advance the state like muffin_step. */
 int muffin_profile(muffin_ctx* ctx, int32_t n_iter, double ms[32]);
