@@ -90,32 +90,42 @@ __global__ void __launch_bounds__(256) k_spectral_step(SpectralArgs a) {
 
 
 // Channel counts without an FFT plan, L <= 256: the same step with the two cosine transforms as
-// dense products.  A workgroup owns 64 pixels, one per lane, and stages their dual spectra and d
-// across all L channels in LDS.  A wave computes CW channels at a time, so the cosine-table
-// entries it needs are the same in every lane (scalar loads) and each LDS read feeds CW FMAs;
-// the sums run over k in order, as in k_spectral_step.  The k loops are unrolled sixteen times, so
-// that each table row is read sixteen entries per scalar load.
+// dense products.  A workgroup owns 64 pixels, one per lane, and stages their dual spectra across
+// all L channels in LDS.  A wave computes CW channels at a time, so the cosine-table entries it
+// needs are the same in every lane (scalar loads) and each LDS read feeds CW FMAs; the sums run
+// over k in order, as in k_spectral_step.  The k loops are unrolled sixteen times, so that each
+// table row is read sixteen entries per scalar load.
+//
+// One LDS array serves both products: the primal step reads V from it and keeps the d of its own
+// channels in registers (at most MAXM chunks of CW per wave); once every wave is done with V, d
+// replaces it, and the dual step reads each thread's few V entries back from global memory.  With
+// half the LDS per workgroup, twice as many workgroups fit on a CU to hide the LDS and
+// scalar-load latency.
 constexpr int PXM = 64;
 constexpr int kMatMaxL = 256;
 // the cosine tables are read-only for the whole launch: read them through the constant address
 // space, so that the wave-uniform reads become scalar loads
 typedef const float __attribute__((address_space(4)))* const_fp;
 
-template <int CW>
+template <int CW, int MAXM>
 __global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
-  extern __shared__ float sm[];
+  extern __shared__ float sm[];  // [L][PXM]: V during the primal step, then d
   const int L = a.L;
-  float* Vs = sm;            // [L][PXM]
-  float* Ds = sm + L * PXM;  // [L][PXM]
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long long npix = a.npix, cs = a.cs;
   const long long pix = (long long)blockIdx.x * PXM + lane;
   const bool pok = pix < npix;
-  for (int l = wv; l < L; l += 4) Vs[l * PXM + lane] = pok ? a.V[(long long)l * cs + pix] : 0.f;
+  for (int l = wv; l < L; l += 4) sm[l * PXM + lane] = pok ? a.V[(long long)l * cs + pix] : 0.f;
   lds_barrier();
-  // primal step, channels l0 .. l0 + CW - 1 of this wave
-  for (int l0 = wv * CW; l0 < L; l0 += 4 * CW) {
+  // primal step, channels l0 .. l0 + CW - 1 of this wave for l0 = wv CW + 4 CW m
+  float dreg[MAXM][CW];
+#pragma unroll
+  for (int m = 0; m < MAXM; ++m) {
+    const int l0 = wv * CW + 4 * CW * m;
+#pragma unroll
+    for (int c = 0; c < CW; ++c) dreg[m][c] = 0.f;
+    if (l0 >= L) continue;
     float xr[CW], qr[CW], acc[CW];
 #pragma unroll
     for (int c = 0; c < CW; ++c) {
@@ -129,26 +139,31 @@ __global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
     for (int c = 0; c < CW; ++c) Wr[c] = (const_fp)(a.W + (long long)min(l0 + c, L - 1) * L);
 #pragma unroll 16
     for (int k = 0; k < L; ++k) {
-      const float v = Vs[k * PXM + lane];
+      const float v = sm[k * PXM + lane];
 #pragma unroll
       for (int c = 0; c < CW; ++c) acc[c] = fmaf(Wr[c][k], v, acc[c]);
     }
 #pragma unroll
     for (int c = 0; c < CW; ++c) {
       const int l = l0 + c;
-      if (l >= L) break;
-      float d = 0.f;
-      if (pok) {
-        const long long o = (long long)l * cs + pix;
-        const float x = xr[c];
-        const float tv = a.mu_l * acc[c];
-        const float xt = fmaxf(x - a.tau * (qr[c] + tv), 0.f);
-        d = 2.f * xt - x;
-        a.D[o] = d;
-        a.X[o] = a.rho * xt + (1.f - a.rho) * x;
-      }
-      Ds[l * PXM + lane] = d;
+      if (l >= L || !pok) continue;
+      const long long o = (long long)l * cs + pix;
+      const float x = xr[c];
+      const float tv = a.mu_l * acc[c];
+      const float xt = fmaxf(x - a.tau * (qr[c] + tv), 0.f);
+      const float d = 2.f * xt - x;
+      a.D[o] = d;
+      a.X[o] = a.rho * xt + (1.f - a.rho) * x;
+      dreg[m][c] = d;
     }
+  }
+  lds_barrier();  // every wave is done with V
+#pragma unroll
+  for (int m = 0; m < MAXM; ++m) {
+    const int l0 = wv * CW + 4 * CW * m;
+#pragma unroll
+    for (int c = 0; c < CW; ++c)
+      if (l0 + c < L) sm[(l0 + c) * PXM + lane] = dreg[m][c];
   }
   lds_barrier();
   // spectral dual step, coefficients k0 .. k0 + CW - 1 of this wave
@@ -162,7 +177,7 @@ __global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
     }
 #pragma unroll 16
     for (int l = 0; l < L; ++l) {
-      const float dv = Ds[l * PXM + lane];
+      const float dv = sm[l * PXM + lane];
 #pragma unroll
       for (int c = 0; c < CW; ++c) acc[c] = fmaf(Wr[c][l], dv, acc[c]);
     }
@@ -171,8 +186,9 @@ __global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
       const int k = k0 + c;
       if (k >= L) break;
       if (pok) {
-        const float v = Vs[k * PXM + lane];
-        a.V[(long long)k * cs + pix] = a.rho * satf_s(v + a.smu_l * acc[c]) + (1.f - a.rho) * v;
+        float* vp = a.V + (long long)k * cs + pix;
+        const float v = *vp;
+        *vp = a.rho * satf_s(v + a.smu_l * acc[c]) + (1.f - a.rho) * v;
       }
     }
   }
@@ -367,9 +383,12 @@ int launch_spectral_step(const SpectralArgs& a, hipStream_t st) {
     MF_SPEC_DISPATCH(a.L, spectral_fft_n, a, st)
   }
   if (a.L <= kMatMaxL) {
-    const size_t shm = sizeof(float) * 2 * (size_t)a.L * PXM;
+    // one LDS array of L x PXM; each wave keeps the d of up to MAXM chunks of 8 channels
+    const size_t shm = sizeof(float) * (size_t)a.L * PXM;
     const long long nblk = (a.npix + PXM - 1) / PXM;
-    hipLaunchKernelGGL(k_spectral_mat<8>, dim3((unsigned)nblk), dim3(256), shm, st, a);
+    if (a.L <= 64) hipLaunchKernelGGL((k_spectral_mat<8, 2>), dim3((unsigned)nblk), dim3(256), shm, st, a);
+    else if (a.L <= 128) hipLaunchKernelGGL((k_spectral_mat<8, 4>), dim3((unsigned)nblk), dim3(256), shm, st, a);
+    else hipLaunchKernelGGL((k_spectral_mat<8, 8>), dim3((unsigned)nblk), dim3(256), shm, st, a);
     MF_HIP(hipGetLastError());
     return MUFFIN_OK;
   }
@@ -458,8 +477,8 @@ int launch_dct_abs(const float* in, const float* WT, long long npix, long long c
 int spectral_direct_attrs(int L) {
   const int shm = (int)(sizeof(float) * 2 * (size_t)L * PX);
   MF_HIP(hipFuncSetAttribute((const void*)k_spectral_step, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
-  MF_HIP(hipFuncSetAttribute((const void*)k_spectral_mat<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)(sizeof(float) * 2 * kMatMaxL * PXM)));
+  MF_HIP(hipFuncSetAttribute((const void*)k_spectral_mat<8, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(float) * kMatMaxL * PXM)));
   MF_HIP(hipFuncSetAttribute((const void*)k_pix_matvec<false>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   MF_HIP(hipFuncSetAttribute((const void*)k_pix_matvec<true>, hipFuncAttributeMaxDynamicSharedMemorySize, shm));
   return MUFFIN_OK;
