@@ -78,7 +78,7 @@ MEASURED_TRAFFIC = {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
         "sha256": "341a505af5bedb9a",
-        "fetch_kib": 2201709.0,
+        "fetch_kib": 2201708.6,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -87,7 +87,7 @@ MEASURED_TRAFFIC = {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
         "sha256": "341a505af5bedb9a",
-        "fetch_kib": 2857077.0,
+        "fetch_kib": 2857076.1,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -96,7 +96,7 @@ MEASURED_TRAFFIC = {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
         "sha256": "341a505af5bedb9a",
-        "fetch_kib": 2191400.4,
+        "fetch_kib": 2191529.2,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
@@ -104,9 +104,9 @@ MEASURED_TRAFFIC = {
     "k_spectral_fft (fused spectral step)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/spectral.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/fft_core.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "bf9402abe78f9961",
-        "fetch_kib": 1573065.0,
-        "write_kib": 3145877.9,
+        "sha256": "019ba098b55c9d08",
+        "fetch_kib": 1573067.9,
+        "write_kib": 3145835.8,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     }
