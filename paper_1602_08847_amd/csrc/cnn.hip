@@ -79,36 +79,42 @@ constexpr int PSTR = 40;                // LDS pixel stride in bf16 (80 bytes: c
 
 // in: NHWC BF16 activations (or gradients); wg: [9][32 j][32 k] BF16 with B[k][j] = wg[tap][j][k];
 // the tap offset applied to the input is +(dy, dx) for tap = (dy + 1) * 3 + (dx + 1).
-template <int MODE>
-__global__ void __launch_bounds__(256) k_conv_mma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wg,
-                                                  const float* __restrict__ bias, const uint16_t* __restrict__ mask,
-                                                  uint16_t* __restrict__ out16, float* __restrict__ out32, int N,
-                                                  int nimg) {
-  __shared__ __attribute__((aligned(16))) uint16_t tin[(TROWS + 2) * (TPX + 2) * PSTR];
-  __shared__ __attribute__((aligned(16))) uint16_t tw[9 * FC * PSTR];
+constexpr int kTileChunks = (TROWS + 2) * (TPX + 2) * 4;  // 16-byte chunks of a haloed input tile
+constexpr int kTileLoads = (kTileChunks + 255) / 256;     // of them per thread
+
+// 16-byte chunk k of the haloed input tile t (one-pixel periodic halo)
+__device__ __forceinline__ const u16x8* tile_chunk(const uint16_t* in, long long t, int k, int N) {
   const int tiles_x = N / TPX, tiles_y = N / TROWS;
-  int t = blockIdx.x;
-  const int tx = t % tiles_x;
-  t /= tiles_x;
-  const int ty = t % tiles_y;
-  const long long b = t / tiles_y;
-  const int x0 = tx * TPX, y0 = ty * TROWS;
-  const long long n2 = (long long)N * N;
-  const uint16_t* inb = in + b * n2 * FC;
-  // weights: 9 x 32 rows of 64 bytes
-  for (int i = threadIdx.x; i < 9 * FC * 4; i += 256) {
+  const int tx = (int)(t % tiles_x);
+  const long long rest = t / tiles_x;
+  const int ty = (int)(rest % tiles_y);
+  const long long b = rest / tiles_y;
+  const int q = k & 3, pix = k >> 2;
+  const int r = pix / (TPX + 2), c = pix - r * (TPX + 2);
+  const int gy = wrapn(ty * TROWS + r - 1, N), gx = wrapn(tx * TPX + c - 1, N);
+  return reinterpret_cast<const u16x8*>(in + b * (long long)N * N * FC + ((long long)gy * N + gx) * FC + q * 8);
+}
+
+__device__ __forceinline__ void stage_weights(uint16_t* tw, const uint16_t* wg) {
+  for (int i = threadIdx.x; i < 9 * FC * 4; i += 256) {  // 9 x 32 rows of 64 bytes
     const int row = i >> 2, q = i & 3;
     *reinterpret_cast<u16x8*>(tw + row * PSTR + q * 8) = *reinterpret_cast<const u16x8*>(wg + row * FC + q * 8);
   }
-  // input tile with a one-pixel periodic halo
-  for (int i = threadIdx.x; i < (TROWS + 2) * (TPX + 2) * 4; i += 256) {
-    const int q = i & 3, pix = i >> 2;
-    const int r = pix / (TPX + 2), c = pix - r * (TPX + 2);
-    const int gy = wrapn(y0 + r - 1, N), gx = wrapn(x0 + c - 1, N);
-    *reinterpret_cast<u16x8*>(tin + pix * PSTR + q * 8) =
-        *reinterpret_cast<const u16x8*>(inb + ((long long)gy * N + gx) * FC + q * 8);
-  }
-  __syncthreads();
+}
+
+// The MFMA sums of tile t (8 rows of 32 pixels x 32 outputs: wave w owns rows 2w, 2w + 1) from
+// its haloed input tile tc and the weights tw, both in LDS, and the epilogue of MODE.
+template <int MODE>
+__device__ __forceinline__ void conv_tile(const uint16_t* tc, const uint16_t* tw, long long t,
+                                          const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                          uint16_t* __restrict__ out16, float* __restrict__ out32, int N) {
+  const int tiles_x = N / TPX, tiles_y = N / TROWS;
+  const int tx = (int)(t % tiles_x);
+  const long long rest = t / tiles_x;
+  const int ty = (int)(rest % tiles_y);
+  const long long b = rest / tiles_y;
+  const int x0 = tx * TPX, y0 = ty * TROWS;
+  const long long n2 = (long long)N * N;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 31, kh8 = (lane >> 5) * 8;
 #pragma unroll
@@ -120,7 +126,7 @@ __global__ void __launch_bounds__(256) k_conv_mma(const uint16_t* __restrict__ i
       const int dy = tap / 3, dx = tap % 3;  // input offset +1 (halo)
 #pragma unroll
       for (int kh = 0; kh < 2; ++kh) {
-        const u16x8 av = *reinterpret_cast<const u16x8*>(tin + ((r + dy) * (TPX + 2) + li + dx) * PSTR + kh * 16 + kh8);
+        const u16x8 av = *reinterpret_cast<const u16x8*>(tc + ((r + dy) * (TPX + 2) + li + dx) * PSTR + kh * 16 + kh8);
         const u16x8 bv = *reinterpret_cast<const u16x8*>(tw + (tap * FC + li) * PSTR + kh * 16 + kh8);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
                                                       acc, 0, 0, 0);
@@ -143,6 +149,65 @@ __global__ void __launch_bounds__(256) k_conv_mma(const uint16_t* __restrict__ i
         out32[((b * FC + j) * N + y) * (long long)N + x0 + i] = v;
       }
     }
+  }
+}
+
+// One tile per workgroup (the backward and single-layer modes).
+template <int MODE>
+__global__ void __launch_bounds__(256) k_conv_mma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wg,
+                                                  const float* __restrict__ bias, const uint16_t* __restrict__ mask,
+                                                  uint16_t* __restrict__ out16, float* __restrict__ out32, int N,
+                                                  int nimg) {
+  __shared__ __attribute__((aligned(16))) uint16_t tin[(TROWS + 2) * (TPX + 2) * PSTR];
+  __shared__ __attribute__((aligned(16))) uint16_t tw[9 * FC * PSTR];
+  (void)nimg;
+  stage_weights(tw, wg);
+  for (int k = threadIdx.x; k < kTileChunks; k += 256)
+    *reinterpret_cast<u16x8*>(tin + (k >> 2) * PSTR + (k & 3) * 8) = *tile_chunk(in, blockIdx.x, k, N);
+  __syncthreads();
+  conv_tile<MODE>(tin, tw, blockIdx.x, bias, mask, out16, out32, N);
+}
+
+// Forward activations, persistent: each workgroup stages the weights once and walks the tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's input loads are in flight while the
+// MFMAs of the current one run, into the other half of a double-buffered LDS tile.  (The other
+// modes keep one tile per workgroup: there the double buffer and the prefetch registers would cut
+// the workgroups per CU from three to two.)
+constexpr int kConvBlocks = 512;  // two resident workgroups per CU
+unsigned conv_grid(long long tiles) { return (unsigned)(tiles < kConvBlocks ? tiles : kConvBlocks); }
+
+__global__ void __launch_bounds__(256) k_conv_act(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wg,
+                                                  const float* __restrict__ bias, uint16_t* __restrict__ out16, int N,
+                                                  int nimg) {
+  __shared__ __attribute__((aligned(16))) uint16_t tin[2][(TROWS + 2) * (TPX + 2) * PSTR];
+  __shared__ __attribute__((aligned(16))) uint16_t tw[9 * FC * PSTR];
+  const long long ntiles = (long long)nimg * (N / TPX) * (N / TROWS);
+  stage_weights(tw, wg);
+  long long t = blockIdx.x;
+  if (t < ntiles)
+    for (int k = threadIdx.x; k < kTileChunks; k += 256)
+      *reinterpret_cast<u16x8*>(tin[0] + (k >> 2) * PSTR + (k & 3) * 8) = *tile_chunk(in, t, k, N);
+  int cur = 0;
+  for (; t < ntiles; t += gridDim.x) {
+    __syncthreads();  // the current tile is in place, and every wave is done with the other buffer
+    const long long nt = t + gridDim.x;
+    u16x8 pre[kTileLoads];
+    if (nt < ntiles) {
+#pragma unroll
+      for (int m = 0; m < kTileLoads; ++m) {
+        const int k = threadIdx.x + 256 * m;
+        if (k < kTileChunks) pre[m] = *tile_chunk(in, nt, k, N);
+      }
+    }
+    conv_tile<MM_ACT>(tin[cur], tw, t, bias, nullptr, out16, nullptr, N);
+    if (nt < ntiles) {
+#pragma unroll
+      for (int m = 0; m < kTileLoads; ++m) {
+        const int k = threadIdx.x + 256 * m;
+        if (k < kTileChunks) *reinterpret_cast<u16x8*>(tin[cur ^ 1] + (k >> 2) * PSTR + (k & 3) * 8) = pre[m];
+      }
+    }
+    cur ^= 1;
   }
 }
 
@@ -523,10 +588,10 @@ int forward(muffin_cnn* c, const float* x, int B, int N) {
   const unsigned tiles = (unsigned)((long long)B * (N / TPX) * (N / TROWS));
   hipLaunchKernelGGL(k_conv1_fwd, dim3(nb256(P)), dim3(256), 0, c->st, x, c->w1b, c->prm + CnnOffsets::b1, c->a1,
                      (float*)nullptr, N, P, 0);
-  hipLaunchKernelGGL((k_conv_mma<MM_ACT>), dim3(tiles), dim3(256), 0, c->st, c->a1, c->w2f, c->prm + CnnOffsets::b2,
-                     (const uint16_t*)nullptr, c->a2, (float*)nullptr, N, B);
-  hipLaunchKernelGGL((k_conv_mma<MM_ACT>), dim3(tiles), dim3(256), 0, c->st, c->a2, c->w3f, c->prm + CnnOffsets::b3,
-                     (const uint16_t*)nullptr, c->a3, (float*)nullptr, N, B);
+  hipLaunchKernelGGL(k_conv_act, dim3(conv_grid(tiles)), dim3(256), 0, c->st, c->a1, c->w2f, c->prm + CnnOffsets::b2,
+                     c->a2, N, B);
+  hipLaunchKernelGGL(k_conv_act, dim3(conv_grid(tiles)), dim3(256), 0, c->st, c->a2, c->w3f, c->prm + CnnOffsets::b3,
+                     c->a3, N, B);
   hipLaunchKernelGGL(k_conv4_fwd, dim3(nb256(P)), dim3(256), 0, c->st, c->a3, c->w4b, c->prm + CnnOffsets::b4, c->z4,
                      N, P);
   MF_HIP(hipGetLastError());
