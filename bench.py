@@ -4,7 +4,8 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube1024_L256_J5
 
 One step is one full iteration of Algorithm 1 over the whole cube (spatial adjoint, gradient,
 fused spectral step, spatial dual step).  Inputs are synthetic (seeded generator), uploaded to HBM
-before timing.  Prints one JSON line.
+before timing.  Prints one JSON line.  Other workloads: --workload batch32 (32 uneven cubes
+advanced together), --workload cnn (the warm-start network's inference and training step).
 """
 import argparse
 import hashlib
@@ -180,6 +181,8 @@ def main():
 
     if args.workload.startswith("batch"):
         return bench_batch(args)
+    if args.workload == "cnn":
+        return bench_cnn(args)
     spec = synth.WORKLOADS[args.workload]
     N, L, J = spec.N, spec.L, spec.J
     t0 = time.time()
@@ -314,6 +317,61 @@ def bench_batch(args):
     }
     print(json.dumps(line), flush=True)
     b.close()
+
+
+def bench_cnn(args):
+    """The warm-start network: inference over the 256 planes of the 1024^2 x 256 cube (the warm start
+    of the timed single-cube workload, wall time per cube) and training steps on batches of 16
+    planes of 256^2 (forward, backward, Adam)."""
+    import torch
+    from paper_1602_08847_amd import muffin, synth
+
+    spec = synth.WORKLOADS["cube1024_L256_J5"]
+    N, L = spec.N, spec.L
+    cube = synth.make_cube(spec, dtype=np.float32, with_sky=False)
+    net = muffin.Cnn(seed=1)
+    m = muffin.Muffin(cube.dirty, cube.psf, J=spec.J, mu_s=0.25, mu_lambda=3.0)
+    del cube
+    for _ in range(args.warmup):
+        m.warm_start(net)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        m.warm_start(net)
+    torch.cuda.synchronize()
+    ms_inf = (time.perf_counter() - t0) * 1e3 / args.steps
+    m.close()
+    g = torch.Generator().manual_seed(0)
+    x = torch.rand((16, 256, 256), generator=g).cuda()
+    y = torch.rand((16, 256, 256), generator=g).cuda()
+    for _ in range(args.warmup):
+        net.train_step(x, y, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(x, y, 1e-4)
+    torch.cuda.synchronize()
+    ms_train = (time.perf_counter() - t0) * 1e3 / args.steps
+    net.close()
+    # four 3x3 layers 1 -> 32 -> 32 -> 32 -> 1, a multiply-add counted as two flops
+    flop_per_px = 2 * 9 * (32 + 32 * 32 + 32 * 32 + 32)
+    tflops = flop_per_px * N * N * L / (ms_inf * 1e-3) / 1e12
+    line = {
+        "metric": "CNN warm start: wall ms per 1024^2x256 cube (inference, normalisation and clamp included)",
+        "value": ms_inf,
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "higher_is_better": False,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "cnn", "planes": L, "N": N, "features": 32, "train_batch": [16, 256, 256]},
+        "train_step_ms": ms_train,
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(tflops / 2500.0, 4), "scope": "whole warm start, all four layers"},
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
