@@ -78,7 +78,7 @@ MEASURED_TRAFFIC = {
     "k_triple_an<RS, false> (three scales of analysis + spatial dual steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "341a505af5bedb9a",
+        "sha256": "a12d85cecaee1fee",
         "fetch_kib": 2201708.6,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
@@ -87,7 +87,7 @@ MEASURED_TRAFFIC = {
     "k_fused<RS> (last analysis pair + next iteration's first adjoint pair)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "341a505af5bedb9a",
+        "sha256": "a12d85cecaee1fee",
         "fetch_kib": 2857076.1,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
@@ -96,7 +96,7 @@ MEASURED_TRAFFIC = {
     "k_triple_adj<RS> (three adjoint Horner steps)": {
         "workload": "cube1024_L256_J5",
         "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "341a505af5bedb9a",
+        "sha256": "a12d85cecaee1fee",
         "fetch_kib": 2191529.2,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,

@@ -305,7 +305,8 @@ __global__ void __launch_bounds__(1024) k_band_trial(AtrousArgs a) {
 // residue class by residue class modulo s, where H_j has its taps 1 and 2 class steps apart and
 // H_{j+1} 2 and 4: each vertical filter is a register window (5 entries for H_j, 9 for H_{j+1})
 // and each horizontal filter a pass through LDS.  Load index i of class r is row
-// y0 + r + (i - 10) s; the chained stages need 10 class steps of halo on either side.
+// y0 + r + (i - HALO) s; the chained stages of the second generation need HALO = 10 class steps
+// of halo on either side.
 //   PR_ANALYSIS:  c1 = H_j c (index t - 2 after loading c(t)), w_j = c - H_j c1 (t - 4),
 //                 c2 = H_{j+1} c1 (t - 6), w_{j+1} = c1 - H_{j+1} c2 (t - 10)
 //   PR_ADJOINT:   h = H_{j+1} u_{j+1} (t - 4), a' = u_{j+1} + H_{j+1}(a - h) (t - 8),
