@@ -83,10 +83,11 @@ def test_single_iteration_matches_oracle_tightly(lib, small):
         assert rel(m.get_v().double().cpu().numpy(), st.V) < 1e-5
 
 
-@pytest.mark.parametrize("N,L", [(16, 100), (16, 260), (16, 384)])
+@pytest.mark.parametrize("N,L", [(16, 100), (16, 200), (16, 260), (16, 384)])
 def test_single_iteration_spectral_paths(lib, N, L):
     """One iteration with the spectral step on each of its paths: dense cosine products (L <= 256
-    without an FFT plan), the direct kernel (larger L without a plan), an FFT with a radix-3 plan."""
+    without an FFT plan; 100 and 200 channels take the kernels for up to 128 and 256), the direct
+    kernel (larger L without a plan), an FFT with a radix-3 plan."""
     c = synth.make_cube(synth.CubeSpec(N=N, L=L, J=2, n_sources=3, n_baselines=40, seed=L))
     dirty, psf = f32(c.dirty), f32(c.psf)
     p = om.Problem(dirty=dirty, psf=psf, J=2, mu_s=0.25, mu_l=3.0)
