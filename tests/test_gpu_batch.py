@@ -21,24 +21,26 @@ def cubes():
     return [synth.make_cube(s, dtype=np.float32) for s in SPECS]
 
 
-def test_batch_matches_separate_contexts_bitwise(lib, cubes):
+@pytest.mark.parametrize("gen", [2, 1])
+def test_batch_matches_separate_contexts_bitwise(lib, cubes, gen):
     mls = [3.0, 2.0, 3.0, 1.5]
-    with lib.Batch([(c.dirty, c.psf) for c in cubes], J=3, mu_s=0.25, mu_lambda=mls, sigma=10.0) as b:
+    with lib.Batch([(c.dirty, c.psf) for c in cubes], J=3, mu_s=0.25, mu_lambda=mls, sigma=10.0, iuwt_gen=gen) as b:
         b.step(12)
         for i, c in enumerate(cubes):
-            with lib.Muffin(c.dirty, c.psf, J=3, mu_s=0.25, mu_lambda=mls[i], sigma=10.0) as m:
+            with lib.Muffin(c.dirty, c.psf, J=3, mu_s=0.25, mu_lambda=mls[i], sigma=10.0, iuwt_gen=gen) as m:
                 assert b.info(i)["tau"] == m.info()["tau"]
                 m.step(12)
                 np.testing.assert_array_equal(b.get_x(i).cpu().numpy(), m.get_x().cpu().numpy())
                 np.testing.assert_allclose(b.objective(i), m.objective(), rtol=1e-12)
 
 
-def test_batch_step_matches_oracle_per_cube(lib, cubes):
-    with lib.Batch([(c.dirty, c.psf) for c in cubes[:2]], J=3, mu_s=0.25, mu_lambda=3.0) as b:
+@pytest.mark.parametrize("gen", [2, 1])
+def test_batch_step_matches_oracle_per_cube(lib, cubes, gen):
+    with lib.Batch([(c.dirty, c.psf) for c in cubes[:2]], J=3, mu_s=0.25, mu_lambda=3.0, iuwt_gen=gen) as b:
         b.step(5)
         for i, c in enumerate(cubes[:2]):
             p = om.Problem(dirty=c.dirty.astype(np.float64), psf=c.psf.astype(np.float64), J=3, mu_s=0.25,
-                           mu_l=3.0)
+                           mu_l=3.0, gen=gen)
             st, _ = om.solve(p, 5, tau=b.info(i)["tau"])
             x = b.get_x(i).double().cpu().numpy()
             assert np.linalg.norm(x - st.X) / np.linalg.norm(st.X) < 1e-4
