@@ -166,10 +166,10 @@ def test_checkpoint_rejects_other_parameters(lib, small):
         assert e.value.code == lib.ESTATE
 
 
-@pytest.mark.parametrize("J,flags", [(3, 0), (5, 2), (5, 4)])
-def test_graph_replay_equals_eager_launches(lib, small, J, flags):
+@pytest.mark.parametrize("J,flags,gen", [(3, 0, 2), (5, 2, 2), (5, 4, 2), (5, 0, 1)])
+def test_graph_replay_equals_eager_launches(lib, small, J, flags, gen):
     c = small
-    kw = dict(J=J, mu_s=0.25, mu_lambda=3.0, flags=flags)
+    kw = dict(J=J, mu_s=0.25, mu_lambda=3.0, flags=flags, iuwt_gen=gen)
     with lib.Muffin(c.dirty, c.psf, **kw) as a, lib.Muffin(c.dirty, c.psf, **kw) as b:
         a.step(5)
         b.profile(5)
