@@ -2,8 +2,8 @@
 (autotuned band rows and fused-tail choice, graph replay), against the FP64 oracle:
 
 * the single cube (1024 x 1024 pixels, 256 channels, J = 5, mu_s = 0.25, mu_lambda = 3,
-  sigma = rho = 1): two iterations from a seeded positive X0, X1 and V1 compared in full, U1, X2
-  and U2 on three channels;
+  sigma = rho = 1), with either generation of the IUWT: two iterations from a seeded positive X0,
+  X1 and V1 compared in full, U1, X2 and U2 on three channels;
 * the batch of 32 uneven cubes: two iterations from zero, X1 and X2 on four sampled cubes.
 
 X2 is the first iterate whose spatial adjoint term reads the sum the previous iteration's last
@@ -33,7 +33,8 @@ def log(msg):
 
 
 @pytest.mark.timeout(900)
-def test_full_size_two_iterations_match_oracle(lib):
+@pytest.mark.parametrize("gen", [2, 1])
+def test_full_size_two_iterations_match_oracle(lib, gen):
     import torch
     spec = synth.WORKLOADS["cube1024_L256_J5"]
     N, L, J = spec.N, spec.L, spec.J
@@ -43,7 +44,7 @@ def test_full_size_two_iterations_match_oracle(lib):
     X0 = np.abs(rng.standard_normal(size=(L, N, N), dtype=np.float32)) * np.float32(8.0 * cube.dirty.std())
     log(f"cube {N}x{N}x{L} J={J} generated ({time.time() - t0:.1f}s)")
 
-    with lib.Muffin(cube.dirty, cube.psf, J=J, mu_s=0.25, mu_lambda=3.0) as m:
+    with lib.Muffin(cube.dirty, cube.psf, J=J, mu_s=0.25, mu_lambda=3.0, iuwt_gen=gen) as m:
         tune = m.autotune(reps=3)
         log(f"autotuned: {tune}")
         tau_gpu = m.info()["tau"]
@@ -60,10 +61,10 @@ def test_full_size_two_iterations_match_oracle(lib):
 
     dirty, psf = cube.dirty.astype(np.float64), cube.psf.astype(np.float64)
     del cube
-    p = om.Problem(dirty=dirty, psf=psf, J=J, mu_s=0.25, mu_l=3.0)
+    p = om.Problem(dirty=dirty, psf=psf, J=J, mu_s=0.25, mu_l=3.0, gen=gen)
     tau = om.step_sizes(p)[0]
     assert abs(tau_gpu - tau) / tau < 1e-5
-    ref = two_passes_sampled(dirty, psf, X0.astype(np.float64), J, 0.25, 3.0, tau, CHANS, workers=16)
+    ref = two_passes_sampled(dirty, psf, X0.astype(np.float64), J, 0.25, 3.0, tau, CHANS, gen=gen, workers=16)
     log(f"oracle done ({time.time() - t0:.1f}s)")
 
     # both branches of the positive part and of both saturations are taken
