@@ -285,8 +285,69 @@ def step_sizes(p: Problem):
 
 
 # --------------------------------------------------------------------------
-# Algorithm 1
+# The primal-dual method (Sec. 3)
+#
+# The problem of eq. (reg) + eq. (RegAll) has the form
+#     min_X  f(X) + g(X) + h(K X)
+# with f the smooth data term (gradient eq. (grad)), g the indicator of the
+# positive orthant, h = ||.||_1 and K the stacked analysis operator of the
+# prior.  The method Sec. 3 uses for it (the one it cites for its step sizes)
+# alternates a forward-backward step on X with a proximal step on the dual
+# variable of K, then relaxes both.  Below, that step is written once for any
+# (f, g, h, K), and the MUFFIN iteration is that step with MUFFIN's operators.
 # --------------------------------------------------------------------------
+def primal_dual_step(x, duals, grad_f, K, K_adj, prox_g, prox_h_conj, tau, sigma, rho):
+    """One step of the primal-dual method for min f(x) + g(x) + h(K x).
+
+    ``duals`` is a tuple of dual blocks, one per block of K's output; ``K`` maps a
+    primal point to a tuple of such blocks and ``K_adj`` a tuple back to the primal
+    space.  With p = prox_g(x - tau (grad_f(x) + K^dagger y)) and
+    q = prox_{sigma h*}(y + sigma K (2p - x)), the new point is rho (p, q) + (1 - rho) (x, y).
+    """
+    p = prox_g(x - tau * (grad_f(x) + K_adj(*duals)))
+    ext = K(2.0 * p - x)
+    q = tuple(prox_h_conj(y + sigma * k) for y, k in zip(duals, ext))
+    x_new = rho * p + (1.0 - rho) * x
+    duals_new = tuple(rho * qi + (1.0 - rho) * yi for qi, yi in zip(q, duals))
+    return x_new, duals_new
+
+
+def l1_conj_prox(z):
+    """prox of sigma h* for h = ||.||_1: h* is the indicator of the unit l-infinity ball, whose prox
+    (for any sigma) is the projection onto that ball, entry by entry: ``sat`` (Sec. 3)."""
+    return sat(z)
+
+
+@dataclass
+class AnalysisOperator:
+    """K of the prior in eq. (RegAll): K X = (mu_s omega W_s x_l for every channel l,
+    mu_lambda X W_lambda), so that mu_s sum_l ||omega W_s x_l||_1 + mu_lambda sum_n ||W_lambda x^n||_1
+    = ||K X||_1.  Its dual variable is the pair (U, V) of Sec. 3."""
+    J: int
+    gen: int
+    mu_s: float
+    mu_l: float
+    omega: np.ndarray  # (J+1,)
+
+    def spatial(self, x):
+        """mu_s omega W_s x for one channel image (N, N) -> (J+1, N, N)."""
+        return self.mu_s * self.omega[:, None, None] * iuwt(x, self.J, self.gen)
+
+    def spatial_adjoint(self, u):
+        """mu_s W_s^dagger (omega u) for one channel's decomposition (J+1, N, N) -> (N, N)."""
+        return self.mu_s * iuwt_adjoint(self.omega[:, None, None] * u, self.J, self.gen)
+
+    def apply(self, X):
+        return np.stack([self.spatial(x) for x in X]), self.mu_l * spectral(X)
+
+    def adjoint(self, U, V):
+        return np.stack([self.spatial_adjoint(u) for u in U]) + self.mu_l * spectral_adjoint(V)
+
+
+def analysis_operator(p: Problem) -> AnalysisOperator:
+    return AnalysisOperator(J=p.J, gen=p.gen, mu_s=p.mu_s, mu_l=p.mu_l, omega=plane_weights(p.J, p.omega))
+
+
 @dataclass
 class State:
     X: np.ndarray  # (L, N, N)
@@ -296,41 +357,44 @@ class State:
 
 
 def init_state(p: Problem, X0=None) -> State:
-    """Initialise x, U and V (Algorithm 1): X = max(X0, 0) or 0, U = V = 0."""
+    """Initial point (Algorithm 1, "Initialize"): X = max(X0, 0) or 0, U = V = 0."""
     L, N = p.L, p.N
     X = np.zeros((L, N, N)) if X0 is None else positive(np.asarray(X0, dtype=np.float64))
     return State(X=X, U=np.zeros((L, p.J + 1, N, N)), V=np.zeros((L, N, N)))
 
 
 def iterate(p: Problem, st: State, tau: float) -> State:
-    """One pass of Algorithm 1's loop body."""
-    om = plane_weights(p.J, p.omega)
-    X, U, V = st.X, st.U, st.V
-    grad = data_gradient(p.psf, X, p.dirty, p.w)
-    s = p.mu_s * np.stack([iuwt_adjoint(om[:, None, None] * U[l], p.J, p.gen)
-                           for l in range(p.L)])
-    t = p.mu_l * spectral_adjoint(V)
-    Xt = positive(X - tau * (grad + s + t))
-    D = 2.0 * Xt - X
-    Ut = sat(U + p.sigma * p.mu_s * om[None, :, None, None]
-             * np.stack([iuwt(D[l], p.J, p.gen) for l in range(p.L)]))
-    Vt = sat(V + p.sigma * p.mu_l * spectral(D))
-    r = p.rho
-    return State(X=r * Xt + (1 - r) * X, U=r * Ut + (1 - r) * U, V=r * Vt + (1 - r) * V,
-                 k=st.k + 1)
+    """One MUFFIN iteration (Algorithm 1): the primal-dual step with f the data term, g the
+    positivity indicator, h = ||.||_1 and K the stacked analysis operator."""
+    K = analysis_operator(p)
+    X, (U, V) = primal_dual_step(st.X, (st.U, st.V), lambda x: data_gradient(p.psf, x, p.dirty, p.w),
+                                 K.apply, K.adjoint, positive, l1_conj_prox, tau, p.sigma, p.rho)
+    return State(X=X, U=U, V=V, k=st.k + 1)
 
 
-def solve(p: Problem, n_iter: int, X0=None, tau: float | None = None, record_every: int = 0):
-    """Run n_iter iterations of Algorithm 1 from init_state; returns (state, objective history)."""
+def solve(p: Problem, n_iter: int, X0=None, tau: float | None = None, record_every: int = 0, state=None):
+    """Run n_iter iterations of Algorithm 1 from init_state (or from ``state``); returns
+    (state, objective history every record_every iterations)."""
     if tau is None:
         tau = step_sizes(p)[0]
-    st = init_state(p, X0)
+    st = init_state(p, X0) if state is None else state
     hist = []
     for it in range(n_iter):
         st = iterate(p, st, tau)
         if record_every and (it + 1) % record_every == 0:
             hist.append(objective(p, st.X)[0])
     return st, np.array(hist)
+
+
+def two_step_calibration(p: Problem, n1: int, n2: int, tau1: float | None = None, tau2: float | None = None):
+    """The calibration strategy of Sec. 4: step 1 runs the method with mu_lambda = 0 (the problem
+    separates over the channels), step 2 keeps mu_s and starts the full method (mu_lambda of p)
+    from step 1's X; U and V start at 0 in both steps (Algorithm 1's initialisation with step 1's
+    X as the initial condition).  Returns (state after step 1, state after step 2)."""
+    p1 = Problem(**{**p.__dict__, "mu_l": 0.0})
+    st1, _ = solve(p1, n1, tau=tau1)
+    st2, _ = solve(p, n2, X0=st1.X, tau=tau2)
+    return st1, st2
 
 
 def snr_db(X, X_true) -> float:

@@ -1,13 +1,21 @@
-"""Two passes of Algorithm 1 from (X0, U = 0, V = 0), evaluated only where a full-size cube
+"""Two steps of the MUFFIN iteration from (X0, U = 0, V = 0), evaluated only where a full-size cube
 (1024 x 1024 x 256 voxels, J = 5) stays affordable in FP64 on the host.
 
-Every per-channel operator of the iteration (the data gradient, the IUWT and its adjoint) acts on
-one channel at a time, and the spectral operators act on one pixel spectrum at a time.  The first
-pass therefore needs the data gradient of every channel (an FFT per channel, run on a thread pool)
-but no wavelet transform beyond the sampled channels; the second pass needs the full spectral
-dual V1 only through its adjoint, one cosine sum per sampled channel.  The steps are those of the
-oracle's ``iterate`` in the same order, restricted to the sampled channels where the result allows
-it (a CPU test pins this restriction to ``iterate`` itself on a small cube).
+Both steps are the oracle's generic ``primal_dual_step`` applied to a restriction of the problem
+that leaves the sampled results unchanged:
+
+* the proximal maps (positive part, l-infinity projection) and the relaxation act entry by entry,
+  so a dual variable may be restricted to any subset of its entries;
+* the spatial half of the analysis operator acts on one channel at a time, the spectral half on
+  one pixel spectrum at a time.
+
+Step 1 therefore runs on the whole X with the dual restricted to (U on the sampled channels, all
+of V); since U = V = 0 its adjoint term vanishes, so no wavelet transform beyond the sampled
+channels is needed, only the data gradient of every channel (an FFT per channel, on a thread
+pool).  Step 2 runs channel by channel on the sampled channels with the dual U_c; the spectral
+dual V1 enters that channel's primal step only through the fixed term mu_lambda (V1 W_lambda^T)_c,
+which is added to the gradient.  A CPU test pins this restriction to the oracle's whole-cube
+``iterate`` on a small cube.
 
 Test infrastructure only: it calls the oracle and nothing else.
 """
@@ -37,35 +45,37 @@ def data_gradient_threaded(psf, x, y, workers: int = 8, chunk: int = 4) -> np.nd
 
 def two_passes_sampled(dirty, psf, X0, J, mu_s, mu_l, tau, chans, sigma=1.0, rho=1.0, omega=None, gen=2,
                        workers: int = 8) -> dict:
-    """X1 and V1 in full; U1, X2 and U2 on the channels ``chans`` (all FP64).
-
-    Pass 1 starts from U = V = 0, so its spatial and spectral adjoint terms vanish and
-    X~1 = (X0 - tau grad(X0))_+.  The dual steps take D1 = 2 X~1 - X0 (Algorithm 1).
-    Pass 2 at channel c: X~2 = (X1 - tau (grad_c(X1) + mu_s W_s^T(omega U1_c) + mu_l (V1 W_lambda^T)_c))_+,
-    D2 = 2 X~2 - X1, U~2 = sat(U1_c + sigma mu_s omega W_s D2); then relaxation by rho.
-    """
-    om_w = om.plane_weights(J, omega)[:, None, None]
-    r = rho
+    """X1 and V1 in full; U1, X2 and U2 on the channels ``chans`` (all FP64)."""
+    K = om.AnalysisOperator(J=J, gen=gen, mu_s=mu_s, mu_l=mu_l, omega=om.plane_weights(J, omega))
+    chans = list(chans)
     X0 = om.positive(np.asarray(X0, dtype=np.float64))  # the oracle's initial state clips X0
-    g0 = data_gradient_threaded(psf, X0, dirty, workers)
-    Xt1 = om.positive(X0 - tau * g0)
-    del g0
-    D1 = 2.0 * Xt1 - X0
-    V1 = r * om.sat(sigma * mu_l * om.spectral(D1))  # V0 = 0
-    X1 = r * Xt1 + (1.0 - r) * X0
-    del Xt1
-    T1 = om.spectral_adjoint(V1)[chans]
-    out = {"X1": X1, "V1": V1, "U1": [], "X2": [], "U2": []}
+    L, N = X0.shape[0], X0.shape[1]
+
+    # step 1: dual (U on the sampled channels, V) = 0
+    def K1(X):
+        return np.stack([K.spatial(X[c]) for c in chans]), mu_l * om.spectral(X)
+
+    def K1_adj(Uc, V):
+        assert not np.any(Uc) and not np.any(V)  # the restricted adjoint is exact only at 0
+        return 0.0
+
+    duals0 = (np.zeros((len(chans), J + 1, N, N)), np.zeros((L, N, N)))
+    X1, (U1, V1) = om.primal_dual_step(X0, duals0, lambda x: data_gradient_threaded(psf, x, dirty, workers),
+                                       K1, K1_adj, om.positive, om.l1_conj_prox, tau, sigma, rho)
+
+    # step 2, one sampled channel at a time
+    W = om.dct_matrix(L)
+    out = {"X1": X1, "V1": V1, "U1": U1, "X2": [], "U2": []}
     for i, c in enumerate(chans):
-        U1c = r * om.sat(sigma * mu_s * om_w * om.iuwt(D1[c], J, gen))  # U0 = 0
-        grad = om.data_gradient(psf[c:c + 1], X1[c:c + 1], dirty[c:c + 1])[0]
-        s = mu_s * om.iuwt_adjoint(om_w * U1c, J, gen)
-        Xt2 = om.positive(X1[c] - tau * (grad + s + mu_l * T1[i]))
-        D2 = 2.0 * Xt2 - X1[c]
-        Ut2 = om.sat(U1c + sigma * mu_s * om_w * om.iuwt(D2, J, gen))
-        out["U1"].append(U1c)
-        out["X2"].append(r * Xt2 + (1.0 - r) * X1[c])
-        out["U2"].append(r * Ut2 + (1.0 - r) * U1c)
-    for k in ("U1", "X2", "U2"):
+        spec_c = mu_l * (W[c] @ V1.reshape(L, -1)).reshape(N, N)  # mu_lambda (V1 W_lambda^T)_c
+
+        def grad_c(x, c=c, spec_c=spec_c):
+            return om.data_gradient(psf[c:c + 1], x[None], dirty[c:c + 1])[0] + spec_c
+
+        x2, (u2,) = om.primal_dual_step(X1[c], (U1[i],), grad_c, lambda x: (K.spatial(x),), K.spatial_adjoint,
+                                        om.positive, om.l1_conj_prox, tau, sigma, rho)
+        out["X2"].append(x2)
+        out["U2"].append(u2)
+    for k in ("X2", "U2"):
         out[k] = np.stack(out[k])
     return out
