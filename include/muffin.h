@@ -198,6 +198,16 @@ int muffin_cnn_train_step(muffin_cnn* net, const float* in, const float* target,
  * for layer 1) and dparams (host) = weight then bias gradients of the layer. */
 int muffin_cnn_layer(muffin_cnn* net, int32_t layer, int32_t op, const float* x, const float* dz,
                      float* out, float* dparams, int32_t B, int32_t N);
+/* Allocation-free inference, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same network output
+ * as muffin_cnn_predict, bit for bit, computed with a workspace the library holds in a static
+ * device array (two BF16 activation planes of 2^20 pixels x 32 features, 128 MiB per GPU, kept
+ * until the process ends) instead of workspaces allocated on first use.  in and out are device
+ * arrays [B][N][N]; planes are processed in chunks of floor(2^20 / N^2), so N^2 <= 2^20 (N <= 1024,
+ * N a multiple of 32), else EINVAL.  The call allocates nothing and launches no memset.  Every call
+ * on one GPU shares that GPU's workspace: calls that overlap in time on one GPU (two networks, two
+ * streams, two threads) race and must be ordered by the caller. */
+int muffin_cnn_predict_noalloc(muffin_cnn* net, const float* in, float* out, int32_t B, int32_t N);
 void muffin_cnn_free(muffin_cnn* net);
 /* Warm start: X = max(CNN(y_l / g_l), 0) channel by channel, U = V = 0, where g_l is the sum of
  * psf_l over the 9 x 9 window centred on its origin.  N must be a multiple of 32. */

@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 namespace mf {
@@ -499,6 +500,7 @@ __global__ void __launch_bounds__(256) k_scale_planes(const float* __restrict__ 
 using namespace mf;
 
 struct muffin_cnn {
+  int device = 0;
   hipStream_t user = nullptr, st = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   float *prm = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
@@ -582,20 +584,51 @@ int prep_weights(muffin_cnn* c) {
 
 unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
 
-// forward of P pixels (B images) from FP32 input planes; activations kept for training
-int forward(muffin_cnn* c, const float* x, int B, int N) {
+// forward of P pixels (B images) from FP32 input planes into the activation planes a1, a2, a3
+// (BF16, 32 features per pixel; a3 may be a1, which layer 3 no longer reads) and the output z
+int forward_into(muffin_cnn* c, const float* x, int B, int N, uint16_t* a1, uint16_t* a2, uint16_t* a3, float* z) {
   const long long P = (long long)B * N * N;
   const unsigned tiles = (unsigned)((long long)B * (N / TPX) * (N / TROWS));
-  hipLaunchKernelGGL(k_conv1_fwd, dim3(nb256(P)), dim3(256), 0, c->st, x, c->w1b, c->prm + CnnOffsets::b1, c->a1,
+  hipLaunchKernelGGL(k_conv1_fwd, dim3(nb256(P)), dim3(256), 0, c->st, x, c->w1b, c->prm + CnnOffsets::b1, a1,
                      (float*)nullptr, N, P, 0);
-  hipLaunchKernelGGL(k_conv_act, dim3(conv_grid(tiles)), dim3(256), 0, c->st, c->a1, c->w2f, c->prm + CnnOffsets::b2,
-                     c->a2, N, B);
-  hipLaunchKernelGGL(k_conv_act, dim3(conv_grid(tiles)), dim3(256), 0, c->st, c->a2, c->w3f, c->prm + CnnOffsets::b3,
-                     c->a3, N, B);
-  hipLaunchKernelGGL(k_conv4_fwd, dim3(nb256(P)), dim3(256), 0, c->st, c->a3, c->w4b, c->prm + CnnOffsets::b4, c->z4,
-                     N, P);
+  hipLaunchKernelGGL(k_conv_act, dim3(conv_grid(tiles)), dim3(256), 0, c->st, a1, c->w2f, c->prm + CnnOffsets::b2, a2,
+                     N, B);
+  hipLaunchKernelGGL(k_conv_act, dim3(conv_grid(tiles)), dim3(256), 0, c->st, a2, c->w3f, c->prm + CnnOffsets::b3, a3,
+                     N, B);
+  hipLaunchKernelGGL(k_conv4_fwd, dim3(nb256(P)), dim3(256), 0, c->st, a3, c->w4b, c->prm + CnnOffsets::b4, z, N, P);
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
+}
+
+// forward with the network's own workspaces; activations kept for training
+int forward(muffin_cnn* c, const float* x, int B, int N) { return forward_into(c, x, B, N, c->a1, c->a2, c->a3, c->z4); }
+
+// ------------------------------------------------------------------ allocation-free inference
+// Workspace of muffin_cnn_predict_noalloc: two BF16 activation planes of kNoAllocPixels pixels
+// with 32 features each (128 MiB), one copy per GPU, held until the process ends.  Host code
+// never uses the array's name as an address: the device address of each GPU's copy is looked up
+// once per device (scratch_setup) and kept in scratch_dev.
+constexpr long long kNoAllocPixels = 1ll << 20;
+__device__ __align__(256) uint16_t scratch[2 * kNoAllocPixels * FC];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+uint16_t* scratch_dev[kMaxDevices] = {};
+
+// with device dev current: record the address of its copy of scratch (once per device)
+int scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return set_error("CNN: device index out of range"), MUFFIN_EINVAL;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_dev[dev]) return MUFFIN_OK;
+  void* p = nullptr;
+  MF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return set_error("CNN: no device address for the inference workspace"), MUFFIN_EHIP;
+  scratch_dev[dev] = static_cast<uint16_t*>(p);
+  return MUFFIN_OK;
+}
+
+uint16_t* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  return (dev >= 0 && dev < kMaxDevices) ? scratch_dev[dev] : nullptr;
 }
 
 int reduce_into(muffin_cnn* c, int stride, int n, int nblk, float* out, int map) {
@@ -674,6 +707,8 @@ int muffin_cnn_create(muffin_cnn** out, int32_t features, uint64_t seed, void* h
     muffin_cnn_free(c);
     return rc;
   };
+  if (hipGetDevice(&c->device) != hipSuccess) return fail((set_error("CNN: no current device"), MUFFIN_EHIP));
+  if (const int rc0 = scratch_setup(c->device)) return fail(rc0);
   if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
@@ -759,6 +794,26 @@ int muffin_cnn_predict(muffin_cnn* c, const float* in, float* out, int32_t B, in
     const int nb = (int)((B - b0) < chunk ? (B - b0) : chunk);
     MF_TRY(forward(c, in + b0 * n2, nb, N));
     MF_HIP(hipMemcpyAsync(out + b0 * n2, c->z4, sizeof(float) * nb * n2, hipMemcpyDeviceToDevice, c->st));
+  }
+  return MUFFIN_OK;
+}
+
+int muffin_cnn_predict_noalloc(muffin_cnn* c, const float* in, float* out, int32_t B, int32_t N) {
+  if (!c || !in || !out) return set_error("bad arguments"), MUFFIN_EINVAL;
+  MF_TRY(check_shape(B, N));
+  const long long n2 = (long long)N * N;
+  if (n2 > kNoAllocPixels)
+    return set_error("CNN: the allocation-free inference takes planes of at most 2^20 pixels (N <= 1024)"),
+           MUFFIN_EINVAL;
+  uint16_t* ws = scratch_of(c->device);
+  if (!ws) return set_error("CNN: inference workspace not set up on this device"), MUFFIN_EHIP;
+  uint16_t* a1 = ws;
+  uint16_t* a2 = ws + kNoAllocPixels * FC;
+  CnnScope s(c);
+  const long long chunk = (kNoAllocPixels / n2) < B ? (kNoAllocPixels / n2) : B;
+  for (long long b0 = 0; b0 < B; b0 += chunk) {
+    const int nb = (int)((B - b0) < chunk ? (B - b0) : chunk);
+    MF_TRY(forward_into(c, in + b0 * n2, nb, N, a1, a2, a1, out + b0 * n2));
   }
   return MUFFIN_OK;
 }

@@ -32,7 +32,7 @@ EXPORTS = [
     "muffin_get_state", "muffin_set_state", "muffin_apply_op", "muffin_profile",
     "muffin_step_timed", "muffin_free", "muffin_strerror", "muffin_last_error",
     "muffin_cnn_create", "muffin_cnn_param_count", "muffin_cnn_get_params", "muffin_cnn_set_params",
-    "muffin_cnn_predict", "muffin_cnn_loss_grad", "muffin_cnn_train_step", "muffin_cnn_layer",
+    "muffin_cnn_predict", "muffin_cnn_predict_noalloc", "muffin_cnn_loss_grad", "muffin_cnn_train_step", "muffin_cnn_layer",
     "muffin_cnn_free", "muffin_warm_start", "muffin_autotune", "muffin_batch_init", "muffin_batch_step",
     "muffin_batch_step_timed", "muffin_batch_objective", "muffin_batch_get_x", "muffin_batch_info",
     "muffin_batch_autotune", "muffin_batch_free",
@@ -75,6 +75,7 @@ _lib.muffin_cnn_param_count.argtypes = [_vp, ctypes.POINTER(_i32)]
 _lib.muffin_cnn_get_params.argtypes = [_vp, _vp, _i32]
 _lib.muffin_cnn_set_params.argtypes = [_vp, _vp, _i32]
 _lib.muffin_cnn_predict.argtypes = [_vp, _vp, _vp, _i32, _i32]
+_lib.muffin_cnn_predict_noalloc.argtypes = [_vp, _vp, _vp, _i32, _i32]
 _lib.muffin_cnn_loss_grad.argtypes = [_vp, _vp, _vp, _i32, _i32, ctypes.POINTER(_dbl), _vp]
 _lib.muffin_cnn_train_step.argtypes = [_vp, _vp, _vp, _i32, _i32, ctypes.c_float, ctypes.POINTER(_dbl)]
 _lib.muffin_cnn_layer.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _i32, _i32]
@@ -317,6 +318,20 @@ class Cnn:
         B, N = x.shape[0], x.shape[1]
         _check(_lib.muffin_cnn_predict(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                        B, N), "muffin_cnn_predict")
+        torch.cuda.current_stream().synchronize()
+        return out
+
+    def predict_noalloc(self, x, out=None):
+        """predict() through the allocation-free entry point (library-held workspace); out, if
+        given, is a preallocated contiguous float32 device tensor of x's shape."""
+        torch = _torch()
+        x = self._planes(x)
+        if out is None:
+            out = torch.empty_like(x)
+        B, N = x.shape[0], x.shape[1]
+        _check(_lib.muffin_cnn_predict_noalloc(self._h, ctypes.c_void_p(x.data_ptr()),
+                                               _dev_ptr(out, tuple(x.shape), "out"), B, N),
+               "muffin_cnn_predict_noalloc")
         torch.cuda.current_stream().synchronize()
         return out
 
