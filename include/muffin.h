@@ -91,13 +91,36 @@ int muffin_init(muffin_ctx** out, const muffin_params* p, const float* dirty, co
  * dual steps, relaxation).  Iterations after the first call replay a captured HIP graph. */
 int muffin_step(muffin_ctx* ctx, int32_t n_iter);
 
-/* Iterate until a stopping rule holds (Algorithm 1, "until stopping criterion"): every
- * check_every iterations the objective f is evaluated; with f_ref finite the run stops at the
- * first check where (f - f_ref)/|f_ref| <= tol, otherwise when the relative change of f between
- * two checks is <= tol.  Stops after max_iter iterations at most.  iters_done / f_final may be
- * NULL.  Returns ENONFINITE if f becomes non-finite. */
-int muffin_solve(muffin_ctx* ctx, int32_t max_iter, int32_t check_every, double tol, double f_ref,
+/* Stopping rules of muffin_solve (Algorithm 1 ends "until stopping criterion" without naming one). */
+#define MUFFIN_STOP_OBJECTIVE 0 /* objective f: gap to f_ref, or relative change between checks */
+#define MUFFIN_STOP_CHANGE 1    /* iterates: relative change of X, U and V over one iteration */
+
+/* Iterate until a stopping rule holds (Algorithm 1, "until stopping criterion"), in windows of
+ * check_every iterations (the last window may be shorter), at most max_iter iterations.
+ *  - MUFFIN_STOP_OBJECTIVE: after each window the objective f (eq. (reg) + eq. (RegAll)) is
+ *    evaluated; with f_ref finite the run stops at the first window where (f - f_ref)/|f_ref| <= tol,
+ *    otherwise where |f - f_prev| <= tol |f| against the previous window's f.
+ *  - MUFFIN_STOP_CHANGE: the last iteration of each window is monitored as by muffin_step_monitored;
+ *    the run stops at the first window where max(||dX||/||X||, ||dU||/||U||, ||dV||/||V||) <= tol
+ *    (a ratio with a zero change counts as 0); f_ref is ignored and f is evaluated once, at the end.
+ * iters_done and f_final (the objective at the end; may be NULL) report where it stopped.
+ * Errors: EINVAL (arguments, unknown rule), ENONFINITE if f or the iterates become non-finite
+ * (iters_done and f_final still report the state). */
+int muffin_solve(muffin_ctx* ctx, int32_t max_iter, int32_t check_every, int32_t rule, double tol, double f_ref,
                  int32_t* iters_done, double* f_final);
+
+/* n_iter >= 1 iterations (Algorithm 1) whose last one is monitored: out receives, in FP64,
+ * {||X_k - X_{k-1}||_2, ||X_k||_2, ||U_k - U_{k-1}||_2, ||U_k||_2, ||V_k - V_{k-1}||_2, ||V_k||_2} over the
+ * whole cube, the convergence norms of the primal and both dual variables (Sec. 3; a fixed point of
+ * the iteration has all three changes zero).  The first call allocates device copies of X, U and V
+ * (8 + 4(J+1) bytes per voxel) that the context keeps; the monitored iteration is not part of the
+ * captured graph's timing. */
+int muffin_step_monitored(muffin_ctx* ctx, int32_t n_iter, double out[6]);
+
+/* Reconstruction SNR of Sec. 4 against a sky truth X* [L][N][N] (host or device):
+ * 10 log10(||X*||^2 / ||X - X*||^2) over the cube, sums in FP64 (+inf if X equals X*).  The truth
+ * is copied into a scratch buffer of the context; the state is unchanged. */
+int muffin_snr(muffin_ctx* ctx, const float* truth, int on_device, double* snr_db);
 
 /* Objective of eq. (reg) + eq. (RegAll) at the current X, reduced in FP64:
  * out[0] total, out[1] data term sum_l w_l/2 ||y_l - H_l x_l||^2, out[2] mu_s-weighted spatial l1,
@@ -108,16 +131,22 @@ int muffin_objective(muffin_ctx* ctx, double out[4]);
  * [6] delta (rho must lie in (0, delta)), [7] iterations done. */
 int muffin_info(muffin_ctx* ctx, double out[8]);
 
-/* Replace X by max(x0, 0) (a warm start) and reset U = V = 0.  x0 is [L][N][N]. */
+/* Initial point (Algorithm 1, "Initialize"; Sec. 4, calibration step 2 starts the full method from
+ * step 1's X): X = max(x0, 0), which keeps X inside the positivity constraint, and U = V = 0.
+ * x0 is [L][N][N] on the host or the device; the caller keeps it. */
 int muffin_set_x(muffin_ctx* ctx, const float* x0, int on_device);
-/* Copy X, U or V out of the context (sizes [L][N][N], [L][J+1][N][N], [L][N][N]). */
+/* Copy out the primal variable X [L][N][N] and the dual variables U [L][J+1][N][N] (one IUWT
+ * decomposition per channel, eq. (anaylsespat)) and V [L][N][N] (cosine coefficients of each pixel
+ * spectrum) of Algorithm 1, into caller memory (host or device). */
 int muffin_get_x(muffin_ctx* ctx, float* x, int on_device);
 int muffin_get_u(muffin_ctx* ctx, float* u, int on_device);
 int muffin_get_v(muffin_ctx* ctx, float* v, int on_device);
 
-/* Checkpoint: a host blob holding a header (sizes, parameters, iteration count) and X, U, V.
- * muffin_state_size gives its size in bytes.  muffin_set_state rejects a blob written by a
- * context of other sizes or parameters with ESTATE.  Restoring and continuing reproduces an
+/* Checkpoint of the state (X, U, V) of Algorithm 1, so that a run (e.g. a calibration of Sec. 4
+ * spread over several jobs) can stop and resume: a host blob holding a header (sizes, parameters,
+ * iteration count) and X, U, V.  muffin_state_size gives its size in bytes; get_state needs a
+ * caller buffer of at least that size (EINVAL otherwise).  muffin_set_state rejects a blob written
+ * by a context of other sizes or parameters with ESTATE.  Restoring and continuing reproduces an
  * uninterrupted run bit for bit. */
 int muffin_state_size(muffin_ctx* ctx, size_t* bytes);
 int muffin_get_state(muffin_ctx* ctx, void* blob, size_t bytes);
@@ -132,6 +161,12 @@ int muffin_set_state(muffin_ctx* ctx, const void* blob, size_t bytes);
  *   MUFFIN_OP_IUWT_ADJ U -> cube          W_s^dagger u_l per channel (eq. (adjointspat) without mu_s)
  *   MUFFIN_OP_DCT      cube -> cube       X W_lambda (cosine coefficients of each pixel spectrum)
  *   MUFFIN_OP_IDCT     cube -> cube       V W_lambda^dagger
+ *   MUFFIN_OP_IUWT_SCHED cube -> U        W_s x_l per channel through the iteration's own analysis
+ *                                         launches (the scale groups of the spatial dual step, the
+ *                                         fused tail when the context uses it) applied to zero dual
+ *                                         planes with sigma mu_s = rho = 1 (eq. (anaylsespat)): valid
+ *                                         where every |W_s x| <= 1, since the dual step saturates;
+ *                                         the coarse plane only when it is penalised (else 0)
  * The context's state is not changed.  EINVAL for an unknown op. */
 #define MUFFIN_OP_H 1
 #define MUFFIN_OP_HT 2
@@ -140,6 +175,7 @@ int muffin_set_state(muffin_ctx* ctx, const void* blob, size_t bytes);
 #define MUFFIN_OP_IUWT_ADJ 5
 #define MUFFIN_OP_DCT 6
 #define MUFFIN_OP_IDCT 7
+#define MUFFIN_OP_IUWT_SCHED 8
 int muffin_apply_op(muffin_ctx* ctx, int op, const float* in, float* out);
 
 /* Time n_iter iterations with HIP events on the library's stream, without graph replay, and
@@ -210,8 +246,13 @@ int muffin_cnn_layer(muffin_cnn* net, int32_t layer, int32_t op, const float* x,
 int muffin_cnn_predict_noalloc(muffin_cnn* net, const float* in, float* out, int32_t B, int32_t N);
 void muffin_cnn_free(muffin_cnn* net);
 /* Warm start: X = max(CNN(y_l / g_l), 0) channel by channel, U = V = 0, where g_l is the sum of
- * psf_l over the 9 x 9 window centred on its origin.  N must be a multiple of 32. */
+ * psf_l over the 9 x 9 window centred on its origin.  N must be a multiple of 32.  The network's
+ * stream is ordered after the context's and the context's after the network's, without host
+ * synchronisation. */
 int muffin_warm_start(muffin_ctx* ctx, muffin_cnn* net);
+/* The network input the warm start builds, y_l / g_l as above, written to out [L][N][N] (host or
+ * device), so that a caller can train on or check exactly what muffin_warm_start feeds the network. */
+int muffin_warm_input(muffin_ctx* ctx, float* out, int on_device);
 
 void muffin_free(muffin_ctx* ctx);
 
@@ -237,6 +278,11 @@ int muffin_batch_step(muffin_batch* batch, int32_t n_iter);
 int muffin_batch_step_timed(muffin_batch* batch, int32_t n_iter, double* ms);
 int muffin_batch_objective(muffin_batch* batch, int32_t cube, double out[4]);
 int muffin_batch_get_x(muffin_batch* batch, int32_t cube, float* x, int on_device);
+/* Initial point of one cube of the batch (Algorithm 1, "Initialize"), as muffin_set_x: its X becomes
+ * max(x0, 0) and its U and V zero; the other cubes are unchanged. */
+int muffin_batch_set_x(muffin_batch* batch, int32_t cube, const float* x0, int on_device);
+/* SNR of one cube of the batch against its truth [L][N][N], as muffin_snr. */
+int muffin_batch_snr(muffin_batch* batch, int32_t cube, const float* truth, int on_device, double* snr_db);
 int muffin_batch_info(muffin_batch* batch, int32_t cube, double out[8]);
 int muffin_batch_autotune(muffin_batch* batch, int32_t reps, char* report, size_t report_len);
 void muffin_batch_free(muffin_batch* batch);

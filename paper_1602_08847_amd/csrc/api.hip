@@ -28,6 +28,7 @@ int launch_power_spectrum(const float2* Hhat_T, float* P_T, const float* chan_w,
 int launch_clamp_pos(float* x, long long n, hipStream_t st);
 int launch_scale_channels(float* x, const float* chan_w, long long npix, long long cs, int nch, hipStream_t st);
 int cnn_warm_input(const float* Y, long long cs, const float* scale, float* out, int N, int L, hipStream_t st);
+int cnn_predict_after(muffin_cnn* net, const float* in, float* out, int B, int N, hipStream_t after);
 int launch_psf_lobe(const float* psf, long long cs, float* out, int N, int L, int radius, hipStream_t st);
 }  // namespace mf
 
@@ -72,7 +73,16 @@ struct muffin_ctx {
   float* chan_w = nullptr;
   float* psf_lobe = nullptr;  // [L] sum of each PSF over the 9 x 9 window at its origin
   double* partial = nullptr;
-  double* dres = nullptr;  // device scalars
+  double* dres = nullptr;  // device scalars: [1..3] objective terms, [5] ||W_s||^2, [6..11] convergence
+                           // norms, [12..13] SNR sums
+  // Every cube of the context has mu_lambda = 0 (the paper's first calibration step, Sec. 4): the
+  // spectral term of the primal step vanishes, so the primal step runs in the gradient's last pass
+  // channel by channel (with each channel's tau from tau_ch) and the spectral kernel is skipped; V
+  // then never changes (it stays saturated, and sat(V) = V).
+  bool local_primal = false;
+  float* tau_ch = nullptr;  // [L] tau of each channel's cube (FP32, as the spectral kernel uses it)
+  // copies of X, U (dense [L][J+1] planes) and V before a monitored iteration (allocated on first use)
+  float *Xs = nullptr, *Us = nullptr, *Vs = nullptr;
   double sigma = 1, rho = 1, Ws2 = 0;
   float omega_c = 1.f;
   long long iter = 0;
@@ -377,6 +387,20 @@ int enqueue_gradient(muffin_ctx* c, const float* x, float* out, const float* s, 
   return MUFFIN_OK;
 }
 
+// mu_lambda = 0: gradient and the relaxed primal step of every channel in the three FFT passes;
+// x is read and written in place and d goes to D.
+int enqueue_local_primal(muffin_ctx* c, const float* s, float s_scale) {
+  PrimalEpi pe;
+  pe.D = c->D;
+  pe.tau_ch = c->tau_ch;
+  pe.rho = (float)c->rho;
+  MF_TRY(launch_rows_r2c(c->X, c->cs, c->S, c->L, c->g, c->tw, false, c->st));
+  MF_TRY(launch_cols(c->S, c->L, c->g, c->tw, COL_REAL, c->P_T, nullptr, 1.f, nullptr, c->st));
+  MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_PRIMAL, c->X, c->cs, c->B, s, s_scale, nullptr, nullptr,
+                         nullptr, nullptr, c->st, pe));
+  return MUFFIN_OK;
+}
+
 int enqueue_spectral(muffin_ctx* c) {
   for (const Seg& s : c->segs) {
     const long long off = (long long)s.ch0 * c->cs;
@@ -411,9 +435,14 @@ int enqueue_iteration(muffin_ctx* c, hipEvent_t* marks, int timed_family = 0, in
   const float* s = nullptr;
   MF_TRY(enqueue_adjoint(c, c->U, c->us, ucs, c->omega_c, &s, timed_family == 1, c->fused ? c->Acar : nullptr));
   if (marks) MF_HIP(hipEventRecord(marks[1], c->st));
-  MF_TRY(enqueue_gradient(c, c->X, c->Q, s, (float)c->p.mu_s));
-  if (marks) MF_HIP(hipEventRecord(marks[2], c->st));
-  MF_TRY(enqueue_spectral(c));
+  if (c->local_primal) {
+    MF_TRY(enqueue_local_primal(c, s, (float)c->p.mu_s));
+    if (marks) MF_HIP(hipEventRecord(marks[2], c->st));
+  } else {
+    MF_TRY(enqueue_gradient(c, c->X, c->Q, s, (float)c->p.mu_s));
+    if (marks) MF_HIP(hipEventRecord(marks[2], c->st));
+    MF_TRY(enqueue_spectral(c));
+  }
   if (marks) MF_HIP(hipEventRecord(marks[3], c->st));
   MF_TRY(enqueue_dual_update(c, c->D, timed_family == 2, par));
   if (marks) MF_HIP(hipEventRecord(marks[4], c->st));
@@ -467,7 +496,7 @@ void destroy(muffin_ctx* c) {
     if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
   }
   void* bufs[] = {c->X, c->U, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT, c->S, c->Hhat_T, c->P_T,
-                  c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres, c->U2, c->Acar};
+                  c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres, c->U2, c->Acar, c->tau_ch, c->Xs, c->Us, c->Vs};
   for (Seg& s : c->segs) {
     void* sb[] = {s.W, s.WT, s.twL, s.csL};
     for (void* b : sb)
@@ -690,11 +719,70 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
     if (!(c->rho < s.delta)) return set_error("rho must lie in (0, delta)"), MUFFIN_ESTEP;
   }
 
+  c->local_primal = true;
+  for (const Seg& s : c->segs) c->local_primal = c->local_primal && s.mu_l == 0.0;
+  {
+    std::vector<float> tch(c->L);
+    for (const Seg& s : c->segs)
+      for (int l = 0; l < s.L; ++l) tch[s.ch0 + l] = (float)s.tau;
+    MF_TRY(dalloc(&c->tau_ch, c->L));
+    MF_HIP(hipMemcpyAsync(c->tau_ch, tch.data(), sizeof(float) * c->L, hipMemcpyHostToDevice, st));
+    MF_HIP(hipStreamSynchronize(st));
+  }
+
   MF_HIP(hipMemsetAsync(c->X, 0, sizeof(float) * cube, st));
   MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, st));
   MF_HIP(hipMemsetAsync(c->V, 0, sizeof(float) * cube, st));
   MF_HIP(hipMemsetAsync(c->D, 0, sizeof(float) * cube, st));
   MF_HIP(hipStreamSynchronize(st));
+  return MUFFIN_OK;
+}
+
+// Before a monitored iteration: X, U (the planes of the current parity, into dense planes) and V
+// are copied aside (the copies are allocated on first use).
+int snapshot_state(muffin_ctx* c) {
+  const long long np = c->npix, J1 = c->J + 1;
+  if (!c->Xs) MF_TRY(dalloc(&c->Xs, c->cube));
+  if (!c->Vs) MF_TRY(dalloc(&c->Vs, c->cube));
+  if (!c->Us) MF_TRY(dalloc(&c->Us, (long long)c->L * J1 * np));
+  MF_HIP(hipMemcpyAsync(c->Xs, c->X, sizeof(float) * c->cube, hipMemcpyDeviceToDevice, c->st));
+  MF_HIP(hipMemcpyAsync(c->Vs, c->V, sizeof(float) * c->cube, hipMemcpyDeviceToDevice, c->st));
+  for (int k = 0; k <= c->J; ++k) {
+    const PlaneOut u = uplane(c, k, c->upar);
+    MF_TRY(copy_planes(c->Us + k * np, J1 * np, u.p, u.cs, c->L, np, hipMemcpyDeviceToDevice, c->st));
+  }
+  return MUFFIN_OK;
+}
+
+// After it: out = {||X - Xs||, ||X||, ||U - Us||, ||U||, ||V - Vs||, ||V||} (FP64, L2 over the cube).
+int state_change(muffin_ctx* c, double out[6]) {
+  const long long np = c->npix, J1 = c->J + 1;
+  MF_TRY(launch_diff_norms(c->X, c->cs, c->Xs, c->cs, np, c->L, c->partial, c->dres + 6, c->dres + 7, 0, c->st));
+  for (int k = 0; k <= c->J; ++k) {
+    const PlaneOut u = uplane(c, k, c->upar);
+    MF_TRY(launch_diff_norms(u.p, u.cs, c->Us + k * np, J1 * np, np, c->L, c->partial, c->dres + 8, c->dres + 9,
+                             k > 0, c->st));
+  }
+  MF_TRY(launch_diff_norms(c->V, c->cs, c->Vs, c->cs, np, c->L, c->partial, c->dres + 10, c->dres + 11, 0, c->st));
+  double h[6];
+  MF_HIP(hipMemcpyAsync(h, c->dres + 6, sizeof(h), hipMemcpyDeviceToHost, c->st));
+  MF_HIP(hipStreamSynchronize(c->st));
+  for (int i = 0; i < 6; ++i) out[i] = std::sqrt(h[i]);
+  return MUFFIN_OK;
+}
+
+// SNR of the channels [ch0, ch0 + nch) of X against a dense truth cube (Sec. 4):
+// 10 log10(||X*||^2 / ||X - X*||^2); the truth is staged in the scratch planes cT.
+int snr_of(muffin_ctx* c, int ch0, int nch, const float* truth, int on_device, double* snr) {
+  const long long np = c->npix, off = (long long)ch0 * c->cs;
+  MF_TRY(copy_planes(c->cT + off, c->cs, truth, np, nch, np,
+                     on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->st));
+  MF_TRY(launch_diff_norms(c->cT + off, c->cs, c->X + off, c->cs, np, nch, c->partial, c->dres + 12, c->dres + 13, 0,
+                           c->st));
+  double h[2];
+  MF_HIP(hipMemcpyAsync(h, c->dres + 12, sizeof(h), hipMemcpyDeviceToHost, c->st));
+  MF_HIP(hipStreamSynchronize(c->st));
+  *snr = 10.0 * std::log10(h[1] / h[0]);
   return MUFFIN_OK;
 }
 
@@ -1056,6 +1144,34 @@ int muffin_batch_objective(muffin_batch* b, int32_t cube, double out[4]) {
   return MUFFIN_OK;
 }
 
+int muffin_batch_set_x(muffin_batch* b, int32_t cube, const float* x0, int on_device) {
+  muffin_ctx* g;
+  int si;
+  MF_TRY(batch_cube(b, cube, &g, &si));
+  if (!x0) return set_error("bad arguments"), MUFFIN_EINVAL;
+  StreamScope scope(g);
+  const Seg& s = g->segs[si];
+  const long long off = (long long)s.ch0 * g->cs, J1 = g->J + 1;
+  MF_TRY(planes_in(g, g->X + off, x0, s.L, on_device));
+  MF_TRY(launch_clamp_pos(g->X + off, (long long)s.L * g->cs, g->st));
+  // this cube's duals: U (both buffers of the fused tail's planes) and V; the carried adjoint sum
+  // of zero planes is zero, so its rows for these channels stay consistent
+  MF_HIP(hipMemsetAsync(g->U + (long long)s.ch0 * J1 * g->us, 0, sizeof(float) * s.L * J1 * g->us, g->st));
+  if (g->U2) MF_HIP(hipMemsetAsync(g->U2 + (long long)s.ch0 * 3 * g->us, 0, sizeof(float) * s.L * 3 * g->us, g->st));
+  if (g->Acar) MF_HIP(hipMemsetAsync(g->Acar + off, 0, sizeof(float) * s.L * g->cs, g->st));
+  MF_HIP(hipMemsetAsync(g->V + off, 0, sizeof(float) * s.L * g->cs, g->st));
+  return MUFFIN_OK;
+}
+
+int muffin_batch_snr(muffin_batch* b, int32_t cube, const float* truth, int on_device, double* snr_db) {
+  muffin_ctx* g;
+  int si;
+  MF_TRY(batch_cube(b, cube, &g, &si));
+  if (!truth || !snr_db) return set_error("bad arguments"), MUFFIN_EINVAL;
+  StreamScope scope(g);
+  return snr_of(g, g->segs[si].ch0, g->segs[si].L, truth, on_device, snr_db);
+}
+
 int muffin_batch_get_x(muffin_batch* b, int32_t cube, float* x, int on_device) {
   muffin_ctx* g;
   int si;
@@ -1177,32 +1293,72 @@ int muffin_objective(muffin_ctx* c, double out[4]) {
   return MUFFIN_OK;
 }
 
-int muffin_solve(muffin_ctx* c, int32_t max_iter, int32_t check_every, double tol, double f_ref,
+int muffin_step_monitored(muffin_ctx* c, int32_t n_iter, double out[6]) {
+  if (!c || !out || n_iter < 1) return set_error("bad arguments"), MUFFIN_EINVAL;
+  StreamScope scope(c);
+  if (!scope.ok) return set_error("stream ordering failed"), MUFFIN_EHIP;
+  MF_TRY(ensure_graph(c));
+  if (n_iter > 1) MF_TRY(replay(c, n_iter - 1));
+  MF_TRY(snapshot_state(c));
+  MF_TRY(replay(c, 1));
+  c->iter += n_iter;
+  return state_change(c, out);
+}
+
+int muffin_solve(muffin_ctx* c, int32_t max_iter, int32_t check_every, int32_t rule, double tol, double f_ref,
                  int32_t* iters_done, double* f_final) {
-  if (!c || max_iter < 0 || check_every < 1 || !(tol >= 0)) return set_error("bad arguments"), MUFFIN_EINVAL;
+  if (!c || max_iter < 0 || check_every < 1 || !(tol >= 0) ||
+      (rule != MUFFIN_STOP_OBJECTIVE && rule != MUFFIN_STOP_CHANGE))
+    return set_error("bad arguments"), MUFFIN_EINVAL;
   int done = 0;
-  double f = NAN, f_prev = NAN, o[4];
+  double f = NAN, f_prev = NAN, o[4], nrm[6];
+  auto rel = [](double d, double n) { return d == 0.0 ? 0.0 : d / n; };
+  auto finish = [&](int rc) {
+    if (iters_done) *iters_done = done;
+    if (f_final) *f_final = f;
+    return rc;
+  };
   while (done < max_iter) {
     const int n = (max_iter - done < check_every) ? max_iter - done : check_every;
-    MF_TRY(muffin_step(c, n));
-    done += n;
+    bool stop = false;
+    if (rule == MUFFIN_STOP_CHANGE) {
+      const int rc = muffin_step_monitored(c, n, nrm);
+      if (rc != MUFFIN_OK) return finish(rc);
+      done += n;
+      const double ch = std::fmax(rel(nrm[0], nrm[1]), std::fmax(rel(nrm[2], nrm[3]), rel(nrm[4], nrm[5])));
+      if (!std::isfinite(ch)) return finish((set_error("iterates became non-finite"), MUFFIN_ENONFINITE));
+      stop = ch <= tol;
+    } else {
+      MF_TRY(muffin_step(c, n));
+      done += n;
+    }
+    if (rule == MUFFIN_STOP_OBJECTIVE || stop || done >= max_iter) {
+      const int rc = muffin_objective(c, o);
+      f = o[0];
+      if (rc != MUFFIN_OK) return finish(rc);
+    }
+    if (rule == MUFFIN_STOP_OBJECTIVE) {
+      if (std::isfinite(f_ref)) {
+        stop = (f - f_ref) / std::fabs(f_ref) <= tol;
+      } else {
+        stop = std::isfinite(f_prev) && std::fabs(f - f_prev) <= tol * std::fabs(f);
+      }
+      f_prev = f;
+    }
+    if (stop) break;
+  }
+  if (done == 0) {
     const int rc = muffin_objective(c, o);
     f = o[0];
-    if (rc != MUFFIN_OK) {
-      if (iters_done) *iters_done = done;
-      if (f_final) *f_final = f;
-      return rc;
-    }
-    if (std::isfinite(f_ref)) {
-      if ((f - f_ref) / std::fabs(f_ref) <= tol) break;
-    } else if (std::isfinite(f_prev) && std::fabs(f - f_prev) <= tol * std::fabs(f)) {
-      break;
-    }
-    f_prev = f;
+    if (rc != MUFFIN_OK) return finish(rc);
   }
-  if (iters_done) *iters_done = done;
-  if (f_final) *f_final = f;
-  return MUFFIN_OK;
+  return finish(MUFFIN_OK);
+}
+
+int muffin_snr(muffin_ctx* c, const float* truth, int on_device, double* snr_db) {
+  if (!c || !truth || !snr_db) return set_error("bad arguments"), MUFFIN_EINVAL;
+  StreamScope scope(c);
+  return snr_of(c, 0, c->L, truth, on_device, snr_db);
 }
 
 // U = 0 (with the fused tail: current planes in U, carried adjoint sum zero, which is exact).
@@ -1328,14 +1484,20 @@ int muffin_set_state(muffin_ctx* c, const void* blob, size_t bytes) {
   return MUFFIN_OK;
 }
 
+int muffin_warm_input(muffin_ctx* c, float* out, int on_device) {
+  if (!c || !out) return set_error("bad arguments"), MUFFIN_EINVAL;
+  StreamScope scope(c);
+  MF_TRY(cnn_warm_input(c->Y, c->cs, c->psf_lobe, c->cA, c->N, c->L, c->st));  // dense planes
+  return copy_out(out, c->cA, (size_t)(c->npix * c->L), on_device, c->st);
+}
+
 int muffin_warm_start(muffin_ctx* c, muffin_cnn* net) {
   if (!c || !net) return set_error("bad arguments"), MUFFIN_EINVAL;
   if (c->N % 32) return set_error("warm start needs N to be a multiple of 32"), MUFFIN_EINVAL;
   StreamScope scope(c);
   MF_TRY(cnn_warm_input(c->Y, c->cs, c->psf_lobe, c->cA, c->N, c->L, c->st));  // dense planes
-  MF_HIP(hipStreamSynchronize(c->st));
-  MF_TRY(muffin_cnn_predict(net, c->cA, c->cB, c->L, c->N));
-  MF_HIP(hipDeviceSynchronize());
+  // the network's stream runs after this stream's work so far, and this stream after the network's
+  MF_TRY(cnn_predict_after(net, c->cA, c->cB, c->L, c->N, c->st));
   MF_TRY(planes_in(c, c->X, c->cB, c->L, 1));
   MF_TRY(launch_clamp_pos(c->X, c->cube, c->st));
   return zero_dual(c);
@@ -1391,6 +1553,49 @@ int muffin_apply_op(muffin_ctx* c, int op, const float* in, float* out) {
       MF_TRY(enqueue_adjoint(c, in, np, (long long)(c->J + 1) * np, 1.f, &a));
       return launch_pointwise(PT_COPY, c->N, c->L, pref(a, cs), PlaneRef{}, pout(out, np), 1.f, 1.f, nullptr,
                               nullptr, c->st);
+    }
+    case MUFFIN_OP_IUWT_SCHED: {
+      // the iteration's own analysis launches (triples, pairs, the fused tail when the context uses
+      // it) on zero dual planes with sigma mu_s = rho = 1: each dual plane becomes sat(w) = w
+      const long long J1 = c->J + 1, us = c->us;
+      if (!c->Us) MF_TRY(dalloc(&c->Us, (long long)c->L * J1 * np));
+      float *U2s = nullptr, *Acs = nullptr;
+      if (c->fused) {
+        MF_TRY(dalloc(&U2s, (long long)c->L * 3 * us));
+        MF_TRY(dalloc(&Acs, c->cube));
+        MF_HIP(hipMemsetAsync(U2s, 0, sizeof(float) * c->L * 3 * us, c->st));
+      }
+      MF_HIP(hipMemsetAsync(c->Us, 0, sizeof(float) * c->L * J1 * np, c->st));
+      MF_TRY(planes_in(c, c->cT, in, c->L, 1));
+      float *U0 = c->U, *U20 = c->U2, *Ac0 = c->Acar;
+      const double sg = c->sigma, ms = c->p.mu_s, rh = c->rho;
+      c->U = c->Us;
+      c->U2 = U2s;
+      c->Acar = Acs;
+      c->sigma = 1.0;
+      c->p.mu_s = 1.0;
+      c->rho = 1.0;
+      const int rc = enqueue_dual_update(c, c->cT, false, 0);
+      c->U = U0;
+      c->U2 = U20;
+      c->Acar = Ac0;
+      c->sigma = sg;
+      c->p.mu_s = ms;
+      c->rho = rh;
+      int rc2 = rc;
+      if (rc == MUFFIN_OK) {
+        // planes below the fused tail's are in the dense scratch, the tail's three in its second buffer
+        rc2 = copy_planes(out, J1 * np, c->Us, J1 * np, c->L, J1 * np, hipMemcpyDeviceToDevice, c->st);
+        if (rc2 == MUFFIN_OK && c->fused)
+          rc2 = copy_planes(out + (long long)c->jf * np, J1 * np, U2s, 3 * us, c->L, 3 * np, hipMemcpyDeviceToDevice,
+                            c->st);
+      }
+      if (U2s || Acs) {
+        (void)hipStreamSynchronize(c->st);
+        if (U2s) (void)hipFree(U2s);
+        if (Acs) (void)hipFree(Acs);
+      }
+      return rc2;
     }
     case MUFFIN_OP_DCT:
       return launch_dct(in, out, c->segs[0].WT, np, np, c->L, c->st);

@@ -968,6 +968,17 @@ __global__ void __launch_bounds__(256) k_psf_lobe(const float* __restrict__ psf,
   if (threadIdx.x == 0) out[l] = red[0];
 }
 
+// The network's inference ordered against another stream (a reconstruction context's): the
+// network's stream waits for the work enqueued on ``after`` so far, and ``after`` waits for the
+// inference, without synchronising the host.
+int cnn_predict_after(muffin_cnn* net, const float* in, float* out, int B, int N, hipStream_t after) {
+  hipStream_t saved = net->user;
+  net->user = after;
+  const int rc = muffin_cnn_predict(net, in, out, B, N);
+  net->user = saved;
+  return rc;
+}
+
 int launch_psf_lobe(const float* psf, long long cs, float* out, int N, int L, int radius, hipStream_t st) {
   hipLaunchKernelGGL(k_psf_lobe, dim3(L), dim3(256), 0, st, psf, cs, out, N, radius);
   MF_HIP(hipGetLastError());

@@ -92,15 +92,25 @@ enum ColMode { COL_FWD = 0, COL_REAL = 1, COL_CPLX = 2, COL_CPLX_CONJ = 3 };
 int launch_cols(float2* S, int nch, const FftGeom& g, const float2* tw, int mode, const float* Mr,
                 const float2* Mc, float scale, float2* outT, hipStream_t st);
 
-enum RowEpi { EPI_STORE = 0, EPI_GRAD = 1, EPI_RESID = 2 };
+enum RowEpi { EPI_STORE = 0, EPI_GRAD = 1, EPI_RESID = 2, EPI_PRIMAL = 3 };
+// Operands of the primal epilogue: the relaxed primal step of one channel when the spectral weight
+// is zero (the spectral term t vanishes, so the step needs no other channel).
+struct PrimalEpi {
+  float* D = nullptr;             // d = 2 x~ - x, channel stride cs
+  const float* tau_ch = nullptr;  // [nch] primal step of each channel's cube
+  float rho = 1.f;
+};
 // Row pass, half spectrum -> real, with an epilogue per pixel (g = inverse transform); out, b, s
 // and y are nch planes of N x N with channel stride cs floats:
-//   EPI_STORE: out = g
-//   EPI_GRAD : out = g - b + s_scale * s      (s may be NULL)
-//   EPI_RESID: partial[block] = sum over the block of 0.5 * w_l * (g - y)^2   (FP64)
+//   EPI_STORE : out = g
+//   EPI_GRAD  : out = g - b + s_scale * s      (s may be NULL)
+//   EPI_RESID : partial[block] = sum over the block of 0.5 * w_l * (g - y)^2   (FP64)
+//   EPI_PRIMAL: q = g - b + s_scale * s, x~ = (x - tau q)_+ with x = out; D = 2 x~ - x and
+//               out = rho x~ + (1 - rho) x (the primal step and relaxation at mu_lambda = 0)
 int launch_rows_c2r(const float2* S, int nch, const FftGeom& g, const float2* tw, int epi,
                     float* out, long long cs, const float* b, const float* s, float s_scale, const float* y,
-                    const float* chan_w, double* partial, int* nblocks_out, hipStream_t st);
+                    const float* chan_w, double* partial, int* nblocks_out, hipStream_t st,
+                    const PrimalEpi& pe = PrimalEpi{});
 
 // ------------------------------------------------------------------ IUWT (a trous)
 // Pointer + channel stride (in floats) of one plane per channel.
@@ -209,6 +219,10 @@ int launch_frame_bound(int N, int J, int gen, double omega_coarse, double* parti
 // Scan for non-finite values; dst[0] += count (as double).
 int launch_count_nonfinite(const float* x, long long n, double* partial, double* dst,
                            hipStream_t st);
+// Over nplanes planes of npix floats (plane k of a at a + k acs, of b at b + k bcs; b may be NULL
+// for zeros): dst_diff (+)= sum (a - b)^2 and dst_a (+)= sum a^2, in FP64 in a fixed order.
+int launch_diff_norms(const float* a, long long acs, const float* b, long long bcs, long long npix, int nplanes,
+                      double* partial, double* dst_diff, double* dst_a, int accumulate, hipStream_t st);
 constexpr int kMaxPartials = 1 << 20;
 
 }  // namespace mf

@@ -182,7 +182,8 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
                                                   const float2* __restrict__ tw, float* __restrict__ out,
                                                   long long cs, const float* __restrict__ b, const float* __restrict__ s,
                                                   float s_scale, const float* __restrict__ y,
-                                                  const float* __restrict__ chan_w, double* __restrict__ partial) {
+                                                  const float* __restrict__ chan_w, double* __restrict__ partial,
+                                                  PrimalEpi pe) {
   constexpr int T = Plan<N>::T;
   constexpr int NI = N / T;  // entries of one transform per thread
   constexpr int FPB = (256 / T) > 0 ? (256 / T) : 1;
@@ -197,7 +198,8 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
   long long o0 = 0, o1 = 0;
   // epilogue operands of the thread's outputs, fetched after the transform, all at once
   constexpr int NE = (EPI == EPI_STORE) ? 1 : NI;
-  float e0[NE], e1[NE], s0[NE], s1[NE];
+  constexpr int NX = (EPI == EPI_PRIMAL) ? NI : 1;
+  float e0[NE], e1[NE], s0[NE], s1[NE], x0[NX], x1[NX];
   if (active) {
     ch = pair / (N / 2);
     r0 = 2 * (int)(pair % (N / 2));
@@ -236,18 +238,26 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
   double acc = 0.0;
   if (active) {
     if constexpr (EPI != EPI_STORE) {
-      const float* __restrict__ ep = ((EPI == EPI_GRAD) ? b : y) + o0 + t;
+      const float* __restrict__ ep = ((EPI == EPI_GRAD || EPI == EPI_PRIMAL) ? b : y) + o0 + t;
 #pragma unroll
       for (int i = 0; i < NI; ++i) {
         e0[i] = ld_stream(ep + i * T);  // b or y, and below the adjoint term: read once (streaming)
         e1[i] = ld_stream(ep + N + i * T);
       }
-      if (EPI == EPI_GRAD && s) {
+      if ((EPI == EPI_GRAD || EPI == EPI_PRIMAL) && s) {
         const float* __restrict__ sp = s + o0 + t;
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
           s0[i] = ld_stream(sp + i * T);
           s1[i] = ld_stream(sp + N + i * T);
+        }
+      }
+      if constexpr (EPI == EPI_PRIMAL) {
+        const float* __restrict__ xp = out + o0 + t;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          x0[i] = ld_stream(xp + i * T);
+          x1[i] = ld_stream(xp + N + i * T);
         }
       }
     }
@@ -266,6 +276,20 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const float2* __restrict__ S, 
         }
         out[o0 + n] = g0;
         out[o1 + n] = g1;
+      } else if constexpr (EPI == EPI_PRIMAL) {
+        // q as in EPI_GRAD, then the primal step of the spectral kernel with its term t = 0
+        float q0 = z.x - e0[i], q1 = z.y - e1[i];
+        if (s) {
+          q0 += s_scale * s0[i];
+          q1 += s_scale * s1[i];
+        }
+        const float tau = pe.tau_ch[ch];
+        const float xa = x0[i], xb = x1[i];
+        const float ta = fmaxf(xa - tau * q0, 0.f), tb = fmaxf(xb - tau * q1, 0.f);
+        st_stream(pe.D + o0 + n, 2.f * ta - xa);
+        st_stream(pe.D + o1 + n, 2.f * tb - xb);
+        st_stream(out + o0 + n, pe.rho * ta + (1.f - pe.rho) * xa);
+        st_stream(out + o1 + n, pe.rho * tb + (1.f - pe.rho) * xb);
       } else {
         const double r0d = (double)z.x - (double)e0[i];
         const double r1d = (double)z.y - (double)e1[i];
@@ -366,7 +390,7 @@ static int cols_n(float2* S, int nch, const FftGeom& g, const float2* tw, int mo
 template <int N>
 static int rows_c2r_n(const float2* S, int nch, const FftGeom& g, const float2* tw, int epi, float* out,
                       long long cs, const float* b, const float* s, float s_scale, const float* y, const float* chan_w,
-                      double* partial, int* nblocks_out, hipStream_t st) {
+                      double* partial, int* nblocks_out, hipStream_t st, const PrimalEpi& pe) {
   constexpr int T = Plan<N>::T;
   constexpr int FPB = (256 / T) > 0 ? (256 / T) : 1;
   const long long npairs = (long long)nch * (N / 2);
@@ -380,15 +404,20 @@ static int rows_c2r_n(const float2* S, int nch, const FftGeom& g, const float2* 
   switch (epi) {
     case EPI_STORE:
       hipLaunchKernelGGL((k_rows_c2r<N, EPI_STORE>), grid, block, 0, st, S, g.pitch, npairs, tw, out, cs, b, s, s_scale,
-                         y, chan_w, partial);
+                         y, chan_w, partial, pe);
       break;
     case EPI_GRAD:
       hipLaunchKernelGGL((k_rows_c2r<N, EPI_GRAD>), grid, block, 0, st, S, g.pitch, npairs, tw, out, cs, b, s, s_scale,
-                         y, chan_w, partial);
+                         y, chan_w, partial, pe);
       break;
     case EPI_RESID:
       hipLaunchKernelGGL((k_rows_c2r<N, EPI_RESID>), grid, block, 0, st, S, g.pitch, npairs, tw, out, cs, b, s, s_scale,
-                         y, chan_w, partial);
+                         y, chan_w, partial, pe);
+      break;
+    case EPI_PRIMAL:
+      if (!pe.D || !pe.tau_ch) return set_error("rows_c2r: primal epilogue needs D and tau"), MUFFIN_EINVAL;
+      hipLaunchKernelGGL((k_rows_c2r<N, EPI_PRIMAL>), grid, block, 0, st, S, g.pitch, npairs, tw, out, cs, b, s,
+                         s_scale, y, chan_w, partial, pe);
       break;
     default:
       set_error("rows_c2r: bad epilogue");
@@ -469,9 +498,9 @@ int launch_cols(float2* S, int nch, const FftGeom& g, const float2* tw, int mode
 
 int launch_rows_c2r(const float2* S, int nch, const FftGeom& g, const float2* tw, int epi, float* out,
                     long long cs, const float* b, const float* s, float s_scale, const float* y,
-                    const float* chan_w, double* partial, int* nblocks_out, hipStream_t st) {
+                    const float* chan_w, double* partial, int* nblocks_out, hipStream_t st, const PrimalEpi& pe) {
   if (cs < (long long)g.N * g.N) return set_error("rows_c2r: channel stride below N*N"), MUFFIN_EINVAL;
-#define CALL(n) rows_c2r_n<n>(S, nch, g, tw, epi, out, cs, b, s, s_scale, y, chan_w, partial, nblocks_out, st)
+#define CALL(n) rows_c2r_n<n>(S, nch, g, tw, epi, out, cs, b, s, s_scale, y, chan_w, partial, nblocks_out, st, pe)
   switch (g.N) {
     case 8: return CALL(8);
     case 16: return CALL(16);

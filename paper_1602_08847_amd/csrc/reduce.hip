@@ -128,4 +128,55 @@ int launch_count_nonfinite(const float* x, long long n, double* partial, double*
   return launch_reduce_sum(partial, (int)nb, dst, 1, st);
 }
 
+// Squared distances for the convergence norms and the SNR: over nplanes planes of npix floats
+// (plane k of a at a + k acs, of b at b + k bcs), partial[blk] = sum (a - b)^2 and
+// partial[nblk + blk] = sum a^2, in FP64 (b == NULL reads as 0).
+__global__ void __launch_bounds__(256) k_diff_norms(const float* __restrict__ a, long long acs,
+                                                    const float* __restrict__ b, long long bcs, long long npix,
+                                                    double* __restrict__ partial) {
+  __shared__ double r0[256], r1[256];
+  const long long k = blockIdx.y;
+  const float* ap = a + k * acs;
+  const float* bp = b ? b + k * bcs : nullptr;
+  double sd = 0.0, sa = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < npix; i += (long long)gridDim.x * 256) {
+    const double av = (double)ap[i];
+    const double d = bp ? av - (double)bp[i] : av;
+    sd += d * d;
+    sa += av * av;
+  }
+  r0[threadIdx.x] = sd;
+  r1[threadIdx.x] = sa;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      r0[threadIdx.x] += r0[threadIdx.x + w];
+      r1[threadIdx.x] += r1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const long long nblk = (long long)gridDim.x * gridDim.y;
+    const long long blk = k * gridDim.x + blockIdx.x;
+    partial[blk] = r0[0];
+    partial[nblk + blk] = r1[0];
+  }
+}
+
+int launch_diff_norms(const float* a, long long acs, const float* b, long long bcs, long long npix, int nplanes,
+                      double* partial, double* dst_diff, double* dst_a, int accumulate, hipStream_t st) {
+  if (nplanes < 1 || npix < 1) return set_error("diff_norms: empty operand"), MUFFIN_EINVAL;
+  if (nplanes > 65535) return set_error("diff_norms: too many planes"), MUFFIN_EINVAL;
+  long long per = (npix + 4 * 256 - 1) / (4 * 256);
+  if (per > 64) per = 64;
+  while (per > 1 && per * nplanes * 2 > kMaxPartials) per >>= 1;
+  const long long nblk = per * nplanes;
+  if (2 * nblk > kMaxPartials) return set_error("diff_norms: too many blocks for the partial sums"), MUFFIN_EINVAL;
+  hipLaunchKernelGGL(k_diff_norms, dim3((unsigned)per, (unsigned)nplanes), dim3(256), 0, st, a, acs, b, bcs, npix,
+                     partial);
+  MF_HIP(hipGetLastError());
+  MF_TRY(launch_reduce_sum(partial, (int)nblk, dst_diff, accumulate, st));
+  return launch_reduce_sum(partial + nblk, (int)nblk, dst_a, accumulate, st);
+}
+
 }  // namespace mf

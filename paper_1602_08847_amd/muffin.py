@@ -24,7 +24,7 @@ import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ESTEP, ESTATE = 0, -1, -2, -3, -4, -5, -6
-OP_H, OP_HT, OP_GRAD, OP_IUWT, OP_IUWT_ADJ, OP_DCT, OP_IDCT = 1, 2, 3, 4, 5, 6, 7
+OP_H, OP_HT, OP_GRAD, OP_IUWT, OP_IUWT_ADJ, OP_DCT, OP_IDCT, OP_IUWT_SCHED = 1, 2, 3, 4, 5, 6, 7, 8
 
 EXPORTS = [
     "muffin_init", "muffin_step", "muffin_solve", "muffin_objective", "muffin_info",
@@ -35,7 +35,8 @@ EXPORTS = [
     "muffin_cnn_predict", "muffin_cnn_predict_noalloc", "muffin_cnn_loss_grad", "muffin_cnn_train_step", "muffin_cnn_layer",
     "muffin_cnn_free", "muffin_warm_start", "muffin_autotune", "muffin_batch_init", "muffin_batch_step",
     "muffin_batch_step_timed", "muffin_batch_objective", "muffin_batch_get_x", "muffin_batch_info",
-    "muffin_batch_autotune", "muffin_batch_free",
+    "muffin_batch_autotune", "muffin_batch_free", "muffin_step_monitored", "muffin_snr", "muffin_batch_snr",
+    "muffin_warm_input", "muffin_batch_set_x",
 ]
 
 
@@ -53,7 +54,12 @@ class Params(ctypes.Structure):
 _vp, _i32, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
 _lib.muffin_init.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(Params), _vp, _vp, ctypes.c_int, _vp]
 _lib.muffin_step.argtypes = [_vp, _i32]
-_lib.muffin_solve.argtypes = [_vp, _i32, _i32, _dbl, _dbl, ctypes.POINTER(_i32), ctypes.POINTER(_dbl)]
+_lib.muffin_solve.argtypes = [_vp, _i32, _i32, _i32, _dbl, _dbl, ctypes.POINTER(_i32), ctypes.POINTER(_dbl)]
+_lib.muffin_step_monitored.argtypes = [_vp, _i32, ctypes.POINTER(_dbl)]
+_lib.muffin_snr.argtypes = [_vp, _vp, ctypes.c_int, ctypes.POINTER(_dbl)]
+_lib.muffin_batch_snr.argtypes = [_vp, _i32, _vp, ctypes.c_int, ctypes.POINTER(_dbl)]
+_lib.muffin_warm_input.argtypes = [_vp, _vp, ctypes.c_int]
+_lib.muffin_batch_set_x.argtypes = [_vp, _i32, _vp, ctypes.c_int]
 _lib.muffin_objective.argtypes = [_vp, ctypes.POINTER(_dbl)]
 _lib.muffin_info.argtypes = [_vp, ctypes.POINTER(_dbl)]
 for _n in ("muffin_set_x", "muffin_get_x", "muffin_get_u", "muffin_get_v"):
@@ -98,6 +104,7 @@ _lib.muffin_batch_free.restype = None
 FLAG_SINGLE_SCALE = 1  # one IUWT launch per scale (same results as the fused pairs of scales)
 FLAG_NO_FUSED_TAIL = 2  # last analysis pair and the next first adjoint pair as two launches (same results)
 FLAG_FUSED_TAIL = 4  # always fuse them (by default: when the cube is large enough, or as autotuned)
+STOP_OBJECTIVE, STOP_CHANGE = 0, 1  # stopping rules of muffin_solve
 
 
 class MuffinError(RuntimeError):
@@ -191,11 +198,29 @@ class Muffin:
         _check(_lib.muffin_profile(self._h, n, out), "muffin_profile")
         return np.array(out[:])
 
-    def solve(self, max_iter: int, check_every: int = 10, tol: float = 1e-4, f_ref: float = math.nan):
+    def solve(self, max_iter: int, check_every: int = 10, tol: float = 1e-4, f_ref: float = math.nan,
+              rule: int = STOP_OBJECTIVE):
         it, f = _i32(), _dbl()
-        _check(_lib.muffin_solve(self._h, max_iter, check_every, tol, f_ref, ctypes.byref(it),
+        _check(_lib.muffin_solve(self._h, max_iter, check_every, rule, tol, f_ref, ctypes.byref(it),
                                  ctypes.byref(f)), "muffin_solve")
         return it.value, f.value
+
+    def step_monitored(self, n: int = 1) -> dict:
+        out = (_dbl * 6)()
+        _check(_lib.muffin_step_monitored(self._h, n, out), "muffin_step_monitored")
+        keys = ["dX", "X", "dU", "U", "dV", "V"]
+        return dict(zip(keys, out[:]))
+
+    def snr(self, truth) -> float:
+        torch = _torch()
+        t = torch.as_tensor(truth, dtype=torch.float32).cuda().contiguous()
+        out = _dbl()
+        _check(_lib.muffin_snr(self._h, _dev_ptr(t, (self.L, self.N, self.N), "truth"), 1, ctypes.byref(out)),
+               "muffin_snr")
+        return out.value
+
+    def warm_input(self):
+        return self._get(_lib.muffin_warm_input, (self.L, self.N, self.N))
 
     def objective(self) -> np.ndarray:
         out = (ctypes.c_double * 4)()
@@ -256,7 +281,7 @@ class Muffin:
         L, N, J = self.L, self.N, self.J
         cube, ucube = (L, N, N), (L, J + 1, N, N)
         in_shape = ucube if op == OP_IUWT_ADJ else cube
-        out_shape = ucube if op == OP_IUWT else cube
+        out_shape = ucube if op in (OP_IUWT, OP_IUWT_SCHED) else cube
         x = torch.as_tensor(x, dtype=torch.float32).cuda().contiguous()
         out = torch.empty(out_shape, dtype=torch.float32, device="cuda")
         _check(_lib.muffin_apply_op(self._h, op, _dev_ptr(x, in_shape, "in"),
@@ -443,6 +468,22 @@ class Batch:
         _check(_lib.muffin_batch_get_x(self._h, cube, ctypes.c_void_p(out.data_ptr()), 1), "muffin_batch_get_x")
         torch.cuda.current_stream().synchronize()
         return out
+
+    def set_x(self, cube: int, x0):
+        torch = _torch()
+        L, N = self.shapes[cube]
+        x0 = torch.as_tensor(x0, dtype=torch.float32).cuda().contiguous()
+        _check(_lib.muffin_batch_set_x(self._h, cube, _dev_ptr(x0, (L, N, N), "x0"), 1), "muffin_batch_set_x")
+        torch.cuda.current_stream().synchronize()
+
+    def snr(self, cube: int, truth) -> float:
+        torch = _torch()
+        L, N = self.shapes[cube]
+        t = torch.as_tensor(truth, dtype=torch.float32).cuda().contiguous()
+        out = _dbl()
+        _check(_lib.muffin_batch_snr(self._h, cube, _dev_ptr(t, (L, N, N), "truth"), 1, ctypes.byref(out)),
+               "muffin_batch_snr")
+        return out.value
 
     def autotune(self, reps: int = 3) -> str:
         buf = ctypes.create_string_buffer(1 << 20)

@@ -1,7 +1,8 @@
 """Learned warm start for the MUFFIN iteration: training data, training loop and the
 time-to-tolerance comparison against a cold start.
 
-Training pairs are (dirty channel image / PSF main-lobe gain, plain-solver reconstruction of that channel):
+Training pairs are (the warm start's network input, i.e. each dirty channel image divided by its PSF's
+main-lobe gain as muffin_warm_input builds it, plain-solver reconstruction of that channel):
 seeded synthetic cubes are reconstructed by the library's own primal-dual iteration, and the
 network is trained by the library's own forward/backward kernels (muffin_cnn_train_step).  The
 comparison runs both starts with identical step sizes against the same reference objective f_ref
@@ -25,18 +26,6 @@ from . import muffin, synth
 MU_S, MU_L = 0.25, 3.0
 
 
-def lobe_gain(psf: np.ndarray, radius: int = 4) -> np.ndarray:
-    """Sum of each PSF over the (2r+1)^2 window at its origin (N/2, N/2): the main-lobe gain."""
-    N = psf.shape[-1]
-    c = N // 2
-    return psf[:, c - radius:c + radius + 1, c - radius:c + radius + 1].sum(axis=(1, 2))
-
-
-def normalised_input(cube) -> np.ndarray:
-    """Dirty channel images divided by their PSF main-lobe gains (the network's input)."""
-    return (cube.dirty / lobe_gain(cube.psf)[:, None, None]).astype(np.float32)
-
-
 def build_training_set(n_cubes: int, spec: synth.CubeSpec, iters: int, sigma: float, seed0: int = 10000,
                        log=print):
     """Solve n_cubes seeded cubes with the plain iteration; returns GPU tensors (inputs, targets)."""
@@ -47,9 +36,9 @@ def build_training_set(n_cubes: int, spec: synth.CubeSpec, iters: int, sigma: fl
         s = synth.CubeSpec(**{**spec.__dict__, "seed": seed0 + i})
         cube = synth.make_cube(s, dtype=np.float32, with_sky=False)
         with muffin.Muffin(cube.dirty, cube.psf, J=s.J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as m:
+            ins.append(m.warm_input())  # exactly what muffin_warm_start feeds the network
             m.step(iters)
             tgs.append(m.get_x())
-        ins.append(torch.from_numpy(normalised_input(cube)).cuda())
         if log and (i + 1) % max(1, n_cubes // 8) == 0:
             log(f"[warmstart] solved {i + 1}/{n_cubes} training cubes ({time.time() - t0:.1f}s)")
     return torch.cat(ins), torch.cat(tgs)
@@ -87,23 +76,25 @@ def train(net: muffin.Cnn, inputs, targets, epochs: int, batch: int, lr: float, 
 
 def time_to_tolerance(m: muffin.Muffin, f_ref: float, tol: float, check_every: int, max_iter: int,
                       trace: list | None = None, trace_every: int = 500):
-    """Iterate until (f - f_ref)/|f_ref| <= tol; returns (iterations, seconds, final f).
+    """Iterate until (f - f_ref)/|f_ref| <= tol with the library's own stopping rule (muffin_solve,
+    objective checked every check_every iterations); returns (iterations, seconds, final f).
     With trace, (iteration, relative gap) pairs are appended every trace_every iterations."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     it = 0
     f = m.objective()[0]
+    gap = (f - f_ref) / abs(f_ref)
     if trace is not None:
-        trace.append((0, (f - f_ref) / abs(f_ref)))
-    while (f - f_ref) / abs(f_ref) > tol and it < max_iter:
-        m.step(check_every)
-        it += check_every
-        f = m.objective()[0]
-        if trace is not None and (it % trace_every == 0 or it in (50, 100, 200, 300)):
-            trace.append((it, (f - f_ref) / abs(f_ref)))
-        if it % 20000 == 0:
-            print(f"[warmstart] {it} iterations, gap {(f - f_ref) / abs(f_ref):.3e}", file=sys.stderr, flush=True)
+        trace.append((0, gap))
+    while gap > tol and it < max_iter:
+        n, f = m.solve(min(trace_every, max_iter - it), check_every=check_every, tol=tol, f_ref=f_ref)
+        it += n
+        gap = (f - f_ref) / abs(f_ref)
+        if trace is not None:
+            trace.append((it, gap))
+        if it % 20000 < trace_every:
+            print(f"[warmstart] {it} iterations, gap {gap:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     return it, time.perf_counter() - t0, f
 
@@ -120,16 +111,22 @@ def reference_objective(cube, J: int, sigma: float, iters: int, check_every: int
     return best
 
 
-def compare(net: muffin.Cnn, cube, J: int, sigma: float, tol: float, f_ref: float, check_every: int,
-            max_iter: int) -> dict:
-    """Cold start (X = 0) against the warm start (X = max(CNN, 0)) on the same cube."""
-    import torch
+def compare_cold(cube, J: int, sigma: float, tol: float, f_ref: float, check_every: int, max_iter: int) -> dict:
+    """The cold start (X = 0) to the tolerance."""
     out = {"tol": tol, "f_ref": f_ref, "sigma": sigma}
     with muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as m:
         out["f0_cold"] = float(m.objective()[0])
         tr = []
         it, sec, f = time_to_tolerance(m, f_ref, tol, check_every, max_iter, tr)
         out.update(cold_iters=it, cold_s=sec, cold_f=f, cold_trace=tr)
+    return out
+
+
+def compare_warm(net: muffin.Cnn, cube, J: int, sigma: float, tol: float, f_ref: float, check_every: int,
+                 max_iter: int) -> dict:
+    """The warm start (X = max(CNN, 0)) to the tolerance; seconds include the network's inference."""
+    import torch
+    out = {}
     with muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as m:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -138,13 +135,45 @@ def compare(net: muffin.Cnn, cube, J: int, sigma: float, tol: float, f_ref: floa
         infer = time.perf_counter() - t0
         out["f0_warm"] = float(m.objective()[0])
         if cube.sky is not None:
-            x0 = m.get_x().double().cpu().numpy()
-            out["snr0_warm_db"] = float(10 * np.log10(np.sum(cube.sky ** 2) / np.sum((x0 - cube.sky) ** 2)))
-            out["snr_dirty_norm_db"] = float(10 * np.log10(np.sum(cube.sky ** 2) / np.sum(
-                (np.maximum(normalised_input(cube), 0) - cube.sky) ** 2)))
+            out["snr0_warm_db"] = m.snr(cube.sky)
+            inp = np.maximum(m.warm_input().double().cpu().numpy(), 0)
+            out["snr_dirty_norm_db"] = float(10 * np.log10(np.sum(cube.sky ** 2) / np.sum((inp - cube.sky) ** 2)))
         tr = []
         it, sec, f = time_to_tolerance(m, f_ref, tol, check_every, max_iter, tr)
         out.update(warm_iters=it, warm_s=sec + infer, warm_infer_s=infer, warm_f=f, warm_trace=tr)
+    return out
+
+
+def compare(net: muffin.Cnn, cube, J: int, sigma: float, tol: float, f_ref: float, check_every: int,
+            max_iter: int) -> dict:
+    """Cold start (X = 0) against the warm start (X = max(CNN, 0)) on the same cube."""
+    out = compare_cold(cube, J, sigma, tol, f_ref, check_every, max_iter)
+    out.update(compare_warm(net, cube, J, sigma, tol, f_ref, check_every, max_iter))
+    return out
+
+
+def compare_two_step(cube, J: int, sigma: float, tol: float, f_ref: float, n1: int, check_every: int,
+                     max_iter: int) -> dict:
+    """The paper's own warm start, its two-step calibration protocol (Sec. 4): n1 iterations with
+    mu_lambda = 0 (each channel on its own; the spectral step is skipped), then the full method from
+    that X with U = V = 0 until (f - f_ref)/|f_ref| <= tol.  Seconds include both steps."""
+    import torch
+    out = {"two_step_n1": n1}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=MU_S, mu_lambda=0.0, sigma=sigma) as m1:
+        m1.step(n1)
+        x1 = m1.get_x()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter() - t0
+    with muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as m:
+        m.set_x(x1)
+        out["f0_two_step"] = float(m.objective()[0])
+        if cube.sky is not None:
+            out["snr0_two_step_db"] = m.snr(cube.sky)
+        tr = []
+        it, sec, f = time_to_tolerance(m, f_ref, tol, check_every, max_iter, tr)
+    out.update(two_step_iters=it, two_step_s=sec + t1, two_step_step1_s=t1, two_step_f=f, two_step_trace=tr)
     return out
 
 
@@ -208,52 +237,79 @@ def main(argv=None):
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--out", default=None)
     ap.add_argument("--load-params", default=None, help="skip training: load a parameter vector (.npy)")
+    ap.add_argument("--net-seeds", default="1",
+                    help="comma-separated seeds: one network per seed (initial weights and batch order), each "
+                         "trained on the same data and compared against the same cold run")
+    ap.add_argument("--two-step", type=int, default=0,
+                    help="also run the paper's two-step protocol with this many mu_lambda = 0 iterations first")
     ap.add_argument("--budget", type=int, default=0,
                     help="instead of the 1e-4 gap: iterations of the cold run whose final objective the warm "
                          "start must reach")
     a = ap.parse_args(argv)
     log = lambda s: print(s, file=sys.stderr, flush=True)
     spec = synth.CubeSpec(N=a.train_N, L=a.train_L, J=a.train_J, n_sources=20, n_baselines=2000)
-    net = muffin.Cnn(seed=1)
-    t_data = t_train = 0.0
-    hist = []
-    if a.load_params:
-        net.set_params(np.load(a.load_params))
-    else:
+    seeds = [int(v) for v in a.net_seeds.split(",")]
+    t_data = 0.0
+    inputs = targets = None
+    if not a.load_params:
         t0 = time.time()
         inputs, targets = build_training_set(a.train_cubes, spec, a.train_iters, a.sigma, log=log)
         t_data = time.time() - t0
-        t0 = time.time()
-        hist = train(net, inputs, targets, a.epochs, a.batch, a.lr, log=log)
-        t_train = time.time() - t0
-        del inputs, targets
+    nets = []
+    for sd in seeds:
+        net = muffin.Cnn(seed=sd)
+        info = {"net_seed": sd, "loss_hist": [], "t_train_s": 0.0}
+        if a.load_params:
+            net.set_params(np.load(a.load_params))
+        else:
+            t0 = time.time()
+            info["loss_hist"] = train(net, inputs, targets, a.epochs, a.batch, a.lr, seed=sd, log=log)
+            info["t_train_s"] = time.time() - t0
+        nets.append((net, info))
+    del inputs, targets
     tspec = synth.WORKLOADS[a.test]
     tspec = synth.CubeSpec(**{**tspec.__dict__, "seed": a.test_seed})
     cube = synth.make_cube(tspec, dtype=np.float32, with_sky=not a.budget)
+    common = dict(train_cubes=a.train_cubes, train_iters=a.train_iters, epochs=a.epochs, t_data_s=t_data,
+                  test=a.test, test_seed=a.test_seed)
     if a.budget:
-        res = compare_budget(net, cube, tspec.J, a.sigma, a.budget, a.check_every)
-        res.update(train_cubes=a.train_cubes, train_iters=a.train_iters, epochs=a.epochs, loss_hist=hist,
-                   t_data_s=t_data, t_train_s=t_train, test=a.test)
-        _emit(res, a.out, net)
+        runs = []
+        for net, info in nets:
+            res = compare_budget(net, cube, tspec.J, a.sigma, a.budget, a.check_every)
+            res.update(info)
+            runs.append(res)
+        _emit({**common, "runs": runs}, a.out, nets)
         return
     t0 = time.time()
     f_ref = reference_objective(cube, tspec.J, a.sigma, a.ref_iters, log=log)
     t_ref = time.time() - t0
     log(f"[warmstart] f_ref {f_ref:.8e} from {a.ref_iters} iterations ({t_ref:.1f}s)")
-    res = compare(net, cube, tspec.J, a.sigma, a.tol, f_ref, a.check_every, a.max_iter)
-    res.update(train_cubes=a.train_cubes, train_iters=a.train_iters, epochs=a.epochs, loss_hist=hist,
-               t_data_s=t_data, t_train_s=t_train, t_ref_s=t_ref, test=a.test, ref_iters=a.ref_iters)
-    _emit(res, a.out, net)
+    res = {**common, "t_ref_s": t_ref, "ref_iters": a.ref_iters}
+    res.update(compare_cold(cube, tspec.J, a.sigma, a.tol, f_ref, a.check_every, a.max_iter))
+    log(f"[warmstart] cold: {res['cold_iters']} iterations, {res['cold_s']:.2f}s")
+    if a.two_step:
+        res.update(compare_two_step(cube, tspec.J, a.sigma, a.tol, f_ref, a.two_step, a.check_every, a.max_iter))
+        log(f"[warmstart] two-step: {res['two_step_iters']} + {a.two_step} iterations, {res['two_step_s']:.2f}s")
+    runs = []
+    for net, info in nets:
+        w = compare_warm(net, cube, tspec.J, a.sigma, a.tol, f_ref, a.check_every, a.max_iter)
+        w.update(info)
+        log(f"[warmstart] warm (net seed {info['net_seed']}): {w['warm_iters']} iterations, {w['warm_s']:.2f}s")
+        runs.append(w)
+    res["runs"] = runs
+    _emit(res, a.out, nets)
 
 
-def _emit(res: dict, out: str | None, net: muffin.Cnn):
+def _emit(res: dict, out: str | None, nets):
     line = json.dumps(res)
     print(line, flush=True)
     if out:
         with open(out, "w") as f:
             f.write(line + "\n")
-        np.save(out.replace(".json", "_params.npy"), net.get_params())
-    net.close()
+        for net, info in nets:
+            np.save(out.replace(".json", f"_params_seed{info['net_seed']}.npy"), net.get_params())
+    for net, _ in nets:
+        net.close()
 
 
 if __name__ == "__main__":

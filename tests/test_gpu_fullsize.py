@@ -4,7 +4,8 @@
 * the single cube (1024 x 1024 pixels, 256 channels, J = 5, mu_s = 0.25, mu_lambda = 3,
   sigma = rho = 1), with either generation of the IUWT: two iterations from a seeded positive X0,
   X1 and V1 compared in full, U1, X2 and U2 on three channels;
-* the batch of 32 uneven cubes: two iterations from zero, X1 and X2 on four sampled cubes.
+* the batch of 32 uneven cubes: two iterations, the four sampled cubes from seeded positive X0 (the
+  others from zero), X1 and X2 on those four cubes.
 
 X2 is the first iterate whose spatial adjoint term reads the sum the previous iteration's last
 analysis launch carried over (when the autotuner picks the fused tail), and U2 the first analysis
@@ -84,10 +85,11 @@ def test_full_size_two_iterations_match_oracle(lib, gen):
 @pytest.mark.timeout(900)
 def test_full_size_uneven_batch_two_iterations_match_oracle(lib):
     """The benchmark's batch of 32 uneven cubes (sides 128-512, 20-128 channels, J = 4), autotuned
-    and advanced together by grouped graphs: two iterations from X = U = V = 0, X1 in full and X2
-    on three channels of the smallest, median and largest cube and of the one cube whose channel
-    count has an FFT plan (384 x 384 x 128: radix-3 image FFTs and the FFT spectral kernel; the
-    others take the dense cosine products)."""
+    and advanced together by grouped graphs: two iterations, X1 in full and X2 on three channels of
+    the smallest, median and largest cube and of the one cube whose channel count has an FFT plan
+    and whose side has radix-3 image FFTs (384 x 384 x 128; the others take the dense cosine
+    products).  The sampled cubes start from seeded positive X0 (set through the batch API), so the
+    positive part clips; the other cubes start from zero."""
     specs = synth.uneven_batch_specs(32, J=4)
     t0 = time.time()
     cubes = [synth.make_cube(s, dtype=np.float32, with_sky=False) for s in specs]
@@ -96,10 +98,18 @@ def test_full_size_uneven_batch_two_iterations_match_oracle(lib):
     picks += [i for i, s in enumerate(specs) if s.L == 128 and s.N == 384][:1]
     assert len(picks) == 4
     log(f"batch generated ({time.time() - t0:.1f}s); sampled cubes {[(i, specs[i].N, specs[i].L) for i in picks]}")
+    X0 = {}
+    for k, i in enumerate(picks):
+        rng = np.random.default_rng(100 + k)
+        s = specs[i]
+        X0[i] = np.abs(rng.standard_normal(size=(s.L, s.N, s.N), dtype=np.float32)) * np.float32(
+            8.0 * cubes[i].dirty.std())
     got = {}
     with lib.Batch([(c.dirty, c.psf) for c in cubes], J=4, mu_s=0.25, mu_lambda=3.0) as b:
         b.autotune(reps=3)
         taus = {i: b.info(i)["tau"] for i in picks}
+        for i in picks:
+            b.set_x(i, X0[i])
         b.step(1)
         X1 = {i: b.get_x(i).cpu().numpy() for i in picks}
         b.step(1)
@@ -113,12 +123,13 @@ def test_full_size_uneven_batch_two_iterations_match_oracle(lib):
         p = om.Problem(dirty=dirty, psf=psf, J=4, mu_s=0.25, mu_l=3.0)
         tau = om.step_sizes(p)[0]
         assert abs(taus[i] - tau) / tau < 1e-5, (i, taus[i], tau)
-        ref = two_passes_sampled(dirty, psf, np.zeros(dirty.shape), 4, 0.25, 3.0, tau, [0, L // 2, L - 1],
+        ref = two_passes_sampled(dirty, psf, X0[i].astype(np.float64), 4, 0.25, 3.0, tau, [0, L // 2, L - 1],
                                  workers=16)
-        # from zero, the gradient of these positive-pedestal cubes is negative everywhere in the first
-        # two iterations, so the positive part never clips here; the single-cube test covers both branches
+        # both branches of the positive part are taken in each sampled cube
+        assert 0 < np.mean(ref["X1"] == 0) < 1 and 0 < np.mean(ref["X2"] == 0) < 1, i
         e1, e2 = rel(got[i][0], ref["X1"]), rel(got[i][1], ref["X2"])
-        log(f"cube {i} ({specs[i].N}x{specs[i].N}x{L}): relative errors X1 {e1:.2e}, X2 {e2:.2e}")
+        log(f"cube {i} ({specs[i].N}x{specs[i].N}x{L}): relative errors X1 {e1:.2e}, X2 {e2:.2e}, "
+            f"clipped X2 {np.mean(ref['X2'] == 0):.2f}")
         assert e1 < 1e-5 and e2 < 1e-5, (i, e1, e2)
         for g, r in ((got[i][0], ref["X1"]), (got[i][1], ref["X2"])):
             assert np.max(np.abs(g - r)) <= 1e-4 * np.max(np.abs(r)), i

@@ -76,6 +76,32 @@ def test_iuwt_ops(lib, ctxs, N, L, J, gen):
     assert rel(m.apply_op(lib.OP_IUWT_ADJ, u).cpu().numpy(), ref) < TOL
 
 
+def check_iuwt_sched(lib, m, N, L, J, gen, seed):
+    x = f32(0.05 * np.random.default_rng(seed).normal(size=(L, N, N)))
+    ref = np.stack([om.iuwt(x[l], J, gen) for l in range(L)])
+    assert np.max(np.abs(ref)) < 1.0  # the dual step's saturation stays inactive
+    got = m.apply_op(lib.OP_IUWT_SCHED, x).cpu().numpy()
+    assert rel(got, ref) < TOL
+    assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("N,L,J,gen", SHAPES)
+def test_iuwt_through_the_iteration_kernels(lib, ctxs, N, L, J, gen):
+    """W_s through the analysis launches the iteration itself runs (scale triples and pairs with the
+    dual step on zero planes), not the operator-only smoothing kernels."""
+    c, m = ctxs(N, L, J, gen)
+    check_iuwt_sched(lib, m, N, L, J, gen, 12)
+
+
+@pytest.mark.parametrize("N,L,J", [(64, 8, 4), (128, 17, 4), (64, 5, 5), (256, 64, 4), (32, 3, 2)])
+def test_iuwt_through_the_fused_tail(lib, N, L, J):
+    """The same with the fused tail forced on: the last two scales and the coarse plane come from the
+    fused analysis + next-adjoint launch."""
+    c = make(N, L, J, seed=5)
+    with lib.Muffin(f32(c.dirty), f32(c.psf), J=J, mu_s=0.25, mu_lambda=3.0, flags=lib.FLAG_FUSED_TAIL) as m:
+        check_iuwt_sched(lib, m, N, L, J, 2, 13)
+
+
 @pytest.mark.parametrize("N,L,J,gen", SHAPES)
 def test_dct_ops(lib, ctxs, N, L, J, gen):
     c, m = ctxs(N, L, J, gen)
