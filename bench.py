@@ -5,7 +5,9 @@ python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube1024_L256_J5
 One step is one full iteration of Algorithm 1 over the whole cube (spatial adjoint, gradient,
 fused spectral step, spatial dual step).  Inputs are synthetic (seeded generator), uploaded to HBM
 before timing.  Prints one JSON line.  Other workloads: --workload batch32 (32 uneven cubes
-advanced together), --workload cnn (the warm-start network's inference and training step).
+advanced together), --workload cnn (the warm-start network's inference and training step),
+--workload calib (the mu_lambda = 0 first step of the calibration protocol of Sec. 4, beside the
+learned warm start's inference time on the same cube).
 """
 import argparse
 import hashlib
@@ -23,14 +25,35 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def alg_bytes_per_voxel(N, J):
+def alg_bytes_per_voxel(N, J, spectral=True):
     """Compulsory HBM bytes per voxel-iteration of the two-phase iteration (FP32 state):
-    U read+write 8(J+1), X 12, V 8, b 4, |H|^2 2(N+2)/N, q write+read 8, d write+read 8."""
-    return 42.0 + 8.0 * (J + 1) + 2.0 * (N + 2) / N
+    U read+write 8(J+1), X 12 (read in the gradient, read and written in the primal step), V read+write
+    8, b 4, |H|^2 2(N+2)/N (half spectrum, FP32), q write+read 8, d write+read 8: 40 + 8(J+1) + 2(N+2)/N.
+    Without the spectral step (mu_lambda = 0) V and the q exchange drop out: 24 + 8(J+1) + 2(N+2)/N."""
+    return (40.0 if spectral else 24.0) + 8.0 * (J + 1) + 2.0 * (N + 2) / N
 
 
-# Algorithmic HBM bytes per voxel of one launch of each hot kernel, and its slot k in the
-# library's profile (mean launch time at 8 + 2k, launches per iteration at 9 + 2k)
+# Algorithmic bytes per voxel that each hot kernel moves, counting only the terms of the iteration's
+# bytes model above, each charged to the launch that moves it first (re-reads of U and intermediate
+# planes count nothing), at J = 5 with the fused tail: the gradient's passes x 4, |H|^2 2(N+2)/N,
+# b + q 8; the spectral step X 8, V 8, q 4, d 4; the analysis triple d 4 and u_0..u_2 24; the fused
+# tail u_3, u_4 and the coarse plane 24; the adjoint triple 0.  They sum to the bytes model.
+def kernel_alg_bytes(name, N):
+    table = {
+        "k_spectral_fft (fused spectral step)": 24.0,
+        "k_triple_an<RS, false> (three scales of analysis + spatial dual steps)": 28.0,
+        "k_fused<RS> (last analysis pair + next iteration's first adjoint pair)": 24.0,
+        "k_triple_adj<RS> (three adjoint Horner steps)": 0.0,
+        "k_rows_r2c": 4.0,
+        "k_cols<REAL>": 2.0 * (N + 2) / N,
+        "k_rows_c2r<GRAD>": 8.0,
+    }
+    return table.get(name)
+
+
+# Bytes per voxel of one launch of each hot kernel as scheduled (what it reads and writes, including
+# re-reads and intermediate planes), and its slot k in the library's profile (mean launch time at
+# 8 + 2k, launches per iteration at 9 + 2k)
 KERNEL_BYTES = {
     # reads x, q, V and writes x, d, V
     "k_spectral_fft (fused spectral step)": 24.0,
@@ -130,23 +153,30 @@ def measured_traffic(kernel, workload):
     return m["fetch_kib"] * 1024 * m["fetch_factor"] + m["write_kib"] * 1024 * m["write_factor"]
 
 
-def cpu_baseline(N, L_sample, J, iters, seed=0):
-    """Time the FP64 oracle on a channel subset of the workload in a single-threaded subprocess."""
+def cpu_baseline(spec, L_sample, iters, out_npz):
+    """Time the FP64 oracle on a channel sample of the workload (same generator and image side, the
+    first L_sample channels of a cube of that many channels) in a single-threaded subprocess, from a
+    seeded positive X0 so that the positive part clips; its final state and step size go to out_npz
+    for the parity check of the same sample on the GPU."""
     code = f"""
 import time, sys
 sys.path.insert(0, {ROOT!r})
 import numpy as np
 from oracle import muffin as om
 from paper_1602_08847_amd import synth
-spec = synth.CubeSpec(N={N}, L={L_sample}, J={J}, n_sources=200, n_baselines=20000, seed={seed})
-c = synth.make_cube(spec, with_sky=False)
-p = om.Problem(dirty=c.dirty, psf=c.psf, J={J}, mu_s=0.25, mu_l=3.0)
+spec = synth.CubeSpec(N={spec.N}, L={L_sample}, J={spec.J}, n_sources={spec.n_sources},
+                      n_baselines={spec.n_baselines}, seed={spec.seed})
+c = synth.make_cube(spec, dtype=np.float32, with_sky=False)
+rng = np.random.default_rng(7)
+X0 = np.abs(rng.standard_normal(size=c.dirty.shape, dtype=np.float32)) * np.float32(8.0 * c.dirty.std())
+p = om.Problem(dirty=c.dirty.astype(np.float64), psf=c.psf.astype(np.float64), J={spec.J}, mu_s=0.25, mu_l=3.0)
 tau = om.step_sizes(p)[0]
-st = om.init_state(p)
+st = om.init_state(p, X0.astype(np.float64))
 t0 = time.perf_counter()
 for _ in range({iters}):
     st = om.iterate(p, st, tau)
 dt = time.perf_counter() - t0
+np.savez({out_npz!r}, X=st.X, U=st.U, V=st.V, X0=X0, tau=tau, f=om.objective(p, st.X))
 print(dt)
 """
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
@@ -154,7 +184,29 @@ print(dt)
     if out.returncode != 0:
         raise RuntimeError(out.stderr[-2000:])
     dt = float(out.stdout.strip().splitlines()[-1])
-    return N * N * L_sample * iters / dt, dt
+    return spec.N * spec.N * L_sample * iters / dt, dt
+
+
+def sample_parity(muffin, spec, L_sample, iters, npz, flags):
+    """The same channel sample on the GPU, in the timed launch configuration (the autotuned band rows
+    of this process, the fused tail forced on), from the oracle's X0 with its tau: relative L2 errors
+    of X, U, V and the relative objective error after the same iterations."""
+    from paper_1602_08847_amd import synth
+    ref = np.load(npz)
+    c = synth.make_cube(synth.CubeSpec(N=spec.N, L=L_sample, J=spec.J, n_sources=spec.n_sources,
+                                       n_baselines=spec.n_baselines, seed=spec.seed), dtype=np.float32, with_sky=False)
+    with muffin.Muffin(c.dirty, c.psf, J=spec.J, mu_s=0.25, mu_lambda=3.0, tau=float(ref["tau"]), flags=flags) as m:
+        m.set_x(ref["X0"])
+        m.step(iters)
+        got = {"X": m.get_x(), "U": m.get_u(), "V": m.get_v()}
+        f = m.objective()[0]
+    err = {}
+    for k, t in got.items():
+        a = t.double().cpu().numpy()
+        err[k] = float(np.linalg.norm(a - ref[k]) / np.linalg.norm(ref[k]))
+    err["objective"] = float(abs(f - ref["f"][0]) / abs(ref["f"][0]))
+    err["clipped_fraction_X"] = float(np.mean(ref["X"] == 0))
+    return err
 
 
 def main():
@@ -183,6 +235,8 @@ def main():
         return bench_batch(args)
     if args.workload == "cnn":
         return bench_cnn(args)
+    if args.workload == "calib":
+        return bench_calib(args)
     spec = synth.WORKLOADS[args.workload]
     N, L, J = spec.N, spec.L, spec.J
     t0 = time.time()
@@ -200,6 +254,9 @@ def main():
     if tune:
         print(f"[bench] autotuned band rows: {[(s['j'], s['kernel'], s['rows']) for s in json.loads(tune)['scales']]}",
               file=sys.stderr, flush=True)
+    # the parity sample runs the timed kernels: the fused tail as the timed context has it
+    fused = json.loads(tune).get("fused_tail") if tune else None
+    sample_flags = args.flags if fused is None else (args.flags & ~6) | (4 if fused else 2)
 
     if args.calib_copy:
         # an elementwise kernel (not a DMA copy) that reads 1 GiB and writes 1 GiB
@@ -229,7 +286,9 @@ def main():
             fams[name] = (ph[8 + 2 * k], ph[9 + 2 * k])
     dom = max(fams, key=lambda k: fams[k][0] * fams[k][1])
     k_ms = fams[dom][0]
-    k_gbs = KERNEL_BYTES[dom] * vox / (k_ms * 1e-3) / 1e9
+    b_k = kernel_alg_bytes(dom, N)
+    sched_k = KERNEL_BYTES[dom]
+    k_gbs = b_k * vox / (k_ms * 1e-3) / 1e9
     b_alg = alg_bytes_per_voxel(N, J)
     traffic = measured_traffic(dom, args.workload)
     roof = {
@@ -241,23 +300,33 @@ def main():
         "frac": round(k_gbs / HBM_PEAK_GBS, 4),
         "traffic": traffic,
         "traffic_unit": "HBM bytes per launch (fetch + write, rocprofv3 counters, calibrated)",
-        "kernel_alg_bytes_per_launch": KERNEL_BYTES[dom] * vox,
-        "kernel_alg_bytes_per_voxel": KERNEL_BYTES[dom],
+        "kernel_alg_bytes_per_voxel": b_k,
+        "kernel_alg_bytes_per_launch": b_k * vox,
         "kernel_avg_ms": round(k_ms, 4),
+        "kernel_schedule_bytes_per_voxel": sched_k,
+        "kernel_schedule_gbs": round(sched_k * vox / (k_ms * 1e-3) / 1e9, 1),
         "iteration_alg_bytes_per_voxel": round(b_alg, 3),
         "iteration_alg_frac": round(b_alg * vox / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_ms": {"adjoint": round(ph[1], 3), "gradient": round(ph[2], 3),
                      "spectral": round(ph[3], 3), "analysis_dual": round(ph[4], 3)},
         "launch_ms": {name: [round(v[0], 4), v[1]] for name, v in fams.items()},
     }
+    m.close()
     cpu = None
     if not args.no_cpu:
-        L_s = min(L, 8)
-        its = 2
-        v, dt = cpu_baseline(N, L_s, J, its)
+        import tempfile
+        L_s, its = min(L, 12), 2
+        with tempfile.TemporaryDirectory() as td:
+            npz = os.path.join(td, "oracle_sample.npz")
+            v, dt = cpu_baseline(spec, L_s, its, npz)
+            err = sample_parity(muffin, spec, L_s, its, npz, flags=sample_flags)
+        print(f"[bench] oracle sample {dt:.1f}s; FP32 vs FP64 errors {err}", file=sys.stderr, flush=True)
         cpu = {"value": v, "unit": "voxel-iter/s", "cores": 1, "kind": "oracle",
                "sample": f"FP64 oracle, {N}x{N}x{L_s} channels of the same generator, J={J}, "
-                         f"{its} iteration(s), {dt:.1f}s single-threaded"}
+                         f"{its} iterations from a seeded positive X0, {dt:.1f}s single-threaded",
+               "fp64_error": {**err, "what": f"relative L2 of the GPU's FP32 X, U, V after the same {its} "
+                                             f"iterations of the same sample, autotuned band rows and fused "
+                                             f"tail as timed, and the relative objective error"}}
     line = {
         "metric": "voxel-iterations/s on 1024^2x256 cube (MUFFIN primal-dual iteration)",
         "value": value,
@@ -277,7 +346,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
-    m.close()
 
 
 def bench_batch(args):
@@ -317,6 +385,68 @@ def bench_batch(args):
     }
     print(json.dumps(line), flush=True)
     b.close()
+
+
+def bench_calib(args):
+    """The first step of the paper's calibration protocol (Sec. 4) on the 1024^2 x 256, J = 5 cube:
+    mu_lambda = 0, so every channel iterates on its own (the primal step runs in the gradient's last
+    pass and the spectral step is skipped), timed like the main workload; beside it, the time of the
+    learned warm start (network inference) on the same cube, the other way to produce a starting
+    point for the full method."""
+    import torch
+    from paper_1602_08847_amd import muffin, synth
+
+    spec = synth.WORKLOADS["cube1024_L256_J5"]
+    N, L, J = spec.N, spec.L, spec.J
+    cube = synth.make_cube(spec, dtype=np.float32, with_sky=False)
+    m = muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=0.25, mu_lambda=0.0, flags=args.flags)
+    net = muffin.Cnn(seed=1)
+    m2 = muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=0.25, mu_lambda=3.0)
+    del cube
+    if args.autotune:
+        m.autotune(reps=3)
+    ph = m.profile(args.profile_steps)
+    m.step(args.warmup)
+    torch.cuda.synchronize()
+    dev_ms = m.step_timed(args.steps)
+    torch.cuda.synchronize()
+    ms_per_step = dev_ms / args.steps
+    vox = N * N * L
+    b_alg = alg_bytes_per_voxel(N, J, spectral=False)
+    m.close()
+    for _ in range(2):
+        m2.warm_start(net)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        m2.warm_start(net)
+    torch.cuda.synchronize()
+    ws_ms = (time.perf_counter() - t0) * 1e3 / reps
+    m2.close()
+    net.close()
+    line = {
+        "metric": "voxel-iterations/s of the mu_lambda = 0 calibration step on the 1024^2x256 cube",
+        "value": vox * args.steps / (dev_ms / 1e3),
+        "unit": "voxel-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "calib_step1_cube1024_L256_J5", "N": N, "L": L, "J": J, "mu_lambda": 0.0},
+        "iteration_alg_bytes_per_voxel": round(b_alg, 3),
+        "iteration_alg_frac": round(b_alg * vox / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "phase_ms": {"adjoint": round(ph[1], 3), "gradient_and_primal_step": round(ph[2], 3),
+                     "analysis_dual": round(ph[4], 3)},
+        "step1_2000_iterations_s": round(2000 * ms_per_step / 1e3, 2),
+        "cnn_warm_start_ms": round(ws_ms, 2),
+    }
+    print(json.dumps(line), flush=True)
 
 
 def bench_cnn(args):
