@@ -281,6 +281,8 @@ int muffin_batch_get_x(muffin_batch* batch, int32_t cube, float* x, int on_devic
 /* Initial point of one cube of the batch (Algorithm 1, "Initialize"), as muffin_set_x: its X becomes
  * max(x0, 0) and its U and V zero; the other cubes are unchanged. */
 int muffin_batch_set_x(muffin_batch* batch, int32_t cube, const float* x0, int on_device);
+/* The warm start's network input of one cube of the batch [L][N][N], as muffin_warm_input. */
+int muffin_batch_warm_input(muffin_batch* batch, int32_t cube, float* out, int on_device);
 /* SNR of one cube of the batch against its truth [L][N][N], as muffin_snr. */
 int muffin_batch_snr(muffin_batch* batch, int32_t cube, const float* truth, int on_device, double* snr_db);
 int muffin_batch_info(muffin_batch* batch, int32_t cube, double out[8]);

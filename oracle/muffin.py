@@ -29,6 +29,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from . import uob as _uob
+
 B3_TAPS = np.array([1.0, 4.0, 6.0, 4.0, 1.0]) / 16.0
 
 
@@ -215,6 +217,7 @@ class Problem:
     tau: float = 0.0
     sigma: float = 1.0
     rho: float = 1.0
+    prior: str = "iuwt"  # spatial transform W_s: "iuwt", or "uob" (union of the first 8 Daubechies bases)
 
     @property
     def L(self):
@@ -225,8 +228,10 @@ class Problem:
         return self.dirty.shape[1]
 
 
-def spatial_l1(X, J, gen=2, omega=None) -> float:
+def spatial_l1(X, J, gen=2, omega=None, prior="iuwt") -> float:
     """sum_l ||W_s x_l||_1 with plane weights omega (eq. (RegAll), second term without mu_s)."""
+    if prior == "uob":
+        return float(sum(np.sum(np.abs(_uob.uob(X[l], J))) for l in range(X.shape[0])))
     om = plane_weights(J, omega)
     tot = 0.0
     for l in range(X.shape[0]):
@@ -242,7 +247,7 @@ def spectral_l1(X) -> float:
 def objective(p: Problem, X: np.ndarray) -> np.ndarray:
     """[total, data, spatial, spectral] of eq. (reg) + eq. (RegAll) at X (inf if X has a negative entry)."""
     data = data_term(p.psf, X, p.dirty, p.w)
-    spat = p.mu_s * spatial_l1(X, p.J, p.gen, p.omega)
+    spat = p.mu_s * spatial_l1(X, p.J, p.gen, p.omega, p.prior)
     spec = p.mu_l * spectral_l1(X)
     total = data + spat + spec
     if np.any(X < 0):
@@ -261,7 +266,8 @@ def op_norm_sq(p: Problem) -> float:
 
     W_lambda is orthonormal, so K^dagger K = mu_s^2 (W_s^dagger W_s per channel) + mu_lambda^2 I.
     """
-    ws2 = float(np.max(frame_symbol(p.N, p.J, p.gen, p.omega)))
+    # the union of orthonormal bases scaled by 1/sqrt(8) is a tight frame: W_s^dagger W_s = I
+    ws2 = 1.0 if p.prior == "uob" else float(np.max(frame_symbol(p.N, p.J, p.gen, p.omega)))
     return p.mu_s ** 2 * ws2 + p.mu_l ** 2
 
 
@@ -328,13 +334,18 @@ class AnalysisOperator:
     mu_s: float
     mu_l: float
     omega: np.ndarray  # (J+1,)
+    prior: str = "iuwt"
 
     def spatial(self, x):
-        """mu_s omega W_s x for one channel image (N, N) -> (J+1, N, N)."""
+        """mu_s omega W_s x for one channel image (N, N) -> (J+1, N, N) (union of bases: (8, N, N))."""
+        if self.prior == "uob":
+            return self.mu_s * _uob.uob(x, self.J)
         return self.mu_s * self.omega[:, None, None] * iuwt(x, self.J, self.gen)
 
     def spatial_adjoint(self, u):
-        """mu_s W_s^dagger (omega u) for one channel's decomposition (J+1, N, N) -> (N, N)."""
+        """mu_s W_s^dagger (omega u) for one channel's decomposition -> (N, N)."""
+        if self.prior == "uob":
+            return self.mu_s * _uob.uob_adjoint(u, self.J)
         return self.mu_s * iuwt_adjoint(self.omega[:, None, None] * u, self.J, self.gen)
 
     def apply(self, X):
@@ -345,7 +356,8 @@ class AnalysisOperator:
 
 
 def analysis_operator(p: Problem) -> AnalysisOperator:
-    return AnalysisOperator(J=p.J, gen=p.gen, mu_s=p.mu_s, mu_l=p.mu_l, omega=plane_weights(p.J, p.omega))
+    return AnalysisOperator(J=p.J, gen=p.gen, mu_s=p.mu_s, mu_l=p.mu_l, omega=plane_weights(p.J, p.omega),
+                            prior=p.prior)
 
 
 @dataclass
@@ -360,7 +372,8 @@ def init_state(p: Problem, X0=None) -> State:
     """Initial point (Algorithm 1, "Initialize"): X = max(X0, 0) or 0, U = V = 0."""
     L, N = p.L, p.N
     X = np.zeros((L, N, N)) if X0 is None else positive(np.asarray(X0, dtype=np.float64))
-    return State(X=X, U=np.zeros((L, p.J + 1, N, N)), V=np.zeros((L, N, N)))
+    planes = _uob.N_BASES if p.prior == "uob" else p.J + 1
+    return State(X=X, U=np.zeros((L, planes, N, N)), V=np.zeros((L, N, N)))
 
 
 def iterate(p: Problem, st: State, tau: float) -> State:

@@ -1163,6 +1163,17 @@ int muffin_batch_set_x(muffin_batch* b, int32_t cube, const float* x0, int on_de
   return MUFFIN_OK;
 }
 
+int muffin_batch_warm_input(muffin_batch* b, int32_t cube, float* out, int on_device) {
+  muffin_ctx* g;
+  int si;
+  MF_TRY(batch_cube(b, cube, &g, &si));
+  if (!out) return set_error("bad arguments"), MUFFIN_EINVAL;
+  StreamScope scope(g);
+  const Seg& s = g->segs[si];
+  MF_TRY(cnn_warm_input(g->Y + (long long)s.ch0 * g->cs, g->cs, g->psf_lobe + s.ch0, g->cA, g->N, s.L, g->st));
+  return copy_out(out, g->cA, (size_t)(g->npix * s.L), on_device, g->st);
+}
+
 int muffin_batch_snr(muffin_batch* b, int32_t cube, const float* truth, int on_device, double* snr_db) {
   muffin_ctx* g;
   int si;

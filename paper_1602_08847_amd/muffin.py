@@ -36,7 +36,7 @@ EXPORTS = [
     "muffin_cnn_free", "muffin_warm_start", "muffin_autotune", "muffin_batch_init", "muffin_batch_step",
     "muffin_batch_step_timed", "muffin_batch_objective", "muffin_batch_get_x", "muffin_batch_info",
     "muffin_batch_autotune", "muffin_batch_free", "muffin_step_monitored", "muffin_snr", "muffin_batch_snr",
-    "muffin_warm_input", "muffin_batch_set_x",
+    "muffin_warm_input", "muffin_batch_set_x", "muffin_batch_warm_input",
 ]
 
 
@@ -60,6 +60,7 @@ _lib.muffin_snr.argtypes = [_vp, _vp, ctypes.c_int, ctypes.POINTER(_dbl)]
 _lib.muffin_batch_snr.argtypes = [_vp, _i32, _vp, ctypes.c_int, ctypes.POINTER(_dbl)]
 _lib.muffin_warm_input.argtypes = [_vp, _vp, ctypes.c_int]
 _lib.muffin_batch_set_x.argtypes = [_vp, _i32, _vp, ctypes.c_int]
+_lib.muffin_batch_warm_input.argtypes = [_vp, _i32, _vp, ctypes.c_int]
 _lib.muffin_objective.argtypes = [_vp, ctypes.POINTER(_dbl)]
 _lib.muffin_info.argtypes = [_vp, ctypes.POINTER(_dbl)]
 for _n in ("muffin_set_x", "muffin_get_x", "muffin_get_u", "muffin_get_v"):
@@ -400,10 +401,11 @@ class Batch:
 
     def __init__(self, cubes, J: int, mu_s: float, mu_lambda, iuwt_gen: int = 2, sigma: float = 1.0,
                  rho: float = 1.0, tau=0.0, flags: int = 0):
-        """cubes: list of (dirty, psf) pairs of [L_i][N_i][N_i] arrays; mu_lambda and tau may be
-        scalars or per-cube sequences."""
+        """cubes: list of (dirty, psf) pairs of [L_i][N_i][N_i] arrays; mu_s, mu_lambda and tau may be
+        scalars or per-cube sequences (cubes of different mu_s fall into different groups)."""
         torch = _torch()
         n = len(cubes)
+        mss = list(mu_s) if np.ndim(mu_s) else [mu_s] * n
         mls = list(mu_lambda) if np.ndim(mu_lambda) else [mu_lambda] * n
         taus = list(tau) if np.ndim(tau) else [tau] * n
         self._keep = []
@@ -417,7 +419,7 @@ class Batch:
             L, N, _ = d.shape
             self.shapes.append((L, N))
             self._keep += [d, f]
-            ps[i] = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=1, flags=flags, mu_s=mu_s,
+            ps[i] = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=1, flags=flags, mu_s=mss[i],
                            mu_lambda=mls[i], tau=taus[i], sigma=sigma, rho=rho)
             dptr[i] = d.data_ptr()
             fptr[i] = f.data_ptr()
@@ -475,6 +477,14 @@ class Batch:
         x0 = torch.as_tensor(x0, dtype=torch.float32).cuda().contiguous()
         _check(_lib.muffin_batch_set_x(self._h, cube, _dev_ptr(x0, (L, N, N), "x0"), 1), "muffin_batch_set_x")
         torch.cuda.current_stream().synchronize()
+
+    def warm_input(self, cube: int):
+        torch = _torch()
+        L, N = self.shapes[cube]
+        out = torch.empty((L, N, N), dtype=torch.float32, device="cuda")
+        _check(_lib.muffin_batch_warm_input(self._h, cube, ctypes.c_void_p(out.data_ptr()), 1),
+               "muffin_batch_warm_input")
+        return out
 
     def snr(self, cube: int, truth) -> float:
         torch = _torch()

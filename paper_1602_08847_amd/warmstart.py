@@ -44,6 +44,28 @@ def build_training_set(n_cubes: int, spec: synth.CubeSpec, iters: int, sigma: fl
     return torch.cat(ins), torch.cat(tgs)
 
 
+def build_training_set_batched(n_cubes: int, spec: synth.CubeSpec, iters: int, sigma: float, seed0: int = 10000,
+                               group: int = 32, log=print):
+    """As build_training_set, with ``group`` cubes solved together by the batch API (one graph over
+    all their channels); each cube keeps its own step size, so its iterates are those of its own
+    context.  Returns GPU tensors (inputs, targets) in seed order."""
+    import torch
+    ins, tgs = [], []
+    t0 = time.time()
+    for g0 in range(0, n_cubes, group):
+        specs = [synth.CubeSpec(**{**spec.__dict__, "seed": seed0 + i}) for i in range(g0, min(n_cubes, g0 + group))]
+        cubes = [synth.make_cube(s, dtype=np.float32, with_sky=False) for s in specs]
+        with muffin.Batch([(c.dirty, c.psf) for c in cubes], J=spec.J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as b:
+            for i in range(len(cubes)):
+                ins.append(b.warm_input(i))
+            b.step(iters)
+            for i in range(len(cubes)):
+                tgs.append(b.get_x(i))
+        if log:
+            log(f"[warmstart] solved {min(n_cubes, g0 + group)}/{n_cubes} training cubes ({time.time() - t0:.1f}s)")
+    return torch.cat(ins), torch.cat(tgs)
+
+
 def train(net: muffin.Cnn, inputs, targets, epochs: int, batch: int, lr: float, seed: int = 0, log=print):
     """Adam on shuffled batches of channel images; returns the per-epoch mean loss.
 
@@ -242,6 +264,9 @@ def main(argv=None):
                          "trained on the same data and compared against the same cold run")
     ap.add_argument("--two-step", type=int, default=0,
                     help="also run the paper's two-step protocol with this many mu_lambda = 0 iterations first")
+    ap.add_argument("--learning-curve", default="",
+                    help="comma-separated training-set sizes (cubes): one network per size, trained on the first "
+                         "cubes of one batch-solved set, each compared against the same cold run")
     ap.add_argument("--budget", type=int, default=0,
                     help="instead of the 1e-4 gap: iterations of the cold run whose final objective the warm "
                          "start must reach")
@@ -249,23 +274,36 @@ def main(argv=None):
     log = lambda s: print(s, file=sys.stderr, flush=True)
     spec = synth.CubeSpec(N=a.train_N, L=a.train_L, J=a.train_J, n_sources=20, n_baselines=2000)
     seeds = [int(v) for v in a.net_seeds.split(",")]
+    sizes = [int(v) for v in a.learning_curve.split(",")] if a.learning_curve else []
     t_data = 0.0
     inputs = targets = None
     if not a.load_params:
         t0 = time.time()
-        inputs, targets = build_training_set(a.train_cubes, spec, a.train_iters, a.sigma, log=log)
+        n_data = max(sizes) if sizes else a.train_cubes
+        if sizes:
+            inputs, targets = build_training_set_batched(n_data, spec, a.train_iters, a.sigma, log=log)
+        else:
+            inputs, targets = build_training_set(n_data, spec, a.train_iters, a.sigma, log=log)
         t_data = time.time() - t0
     nets = []
-    for sd in seeds:
-        net = muffin.Cnn(seed=sd)
-        info = {"net_seed": sd, "loss_hist": [], "t_train_s": 0.0}
-        if a.load_params:
-            net.set_params(np.load(a.load_params))
-        else:
-            t0 = time.time()
-            info["loss_hist"] = train(net, inputs, targets, a.epochs, a.batch, a.lr, seed=sd, log=log)
-            info["t_train_s"] = time.time() - t0
-        nets.append((net, info))
+    for size in (sizes or [a.train_cubes]):
+        for sd in seeds:
+            net = muffin.Cnn(seed=sd)
+            info = {"net_seed": sd, "train_cubes": size, "loss_hist": [], "t_train_s": 0.0}
+            if a.load_params:
+                net.set_params(np.load(a.load_params))
+            else:
+                n_img = size * a.train_L
+                # the same number of Adam steps for every size: smaller sets take more epochs
+                epochs = a.epochs if not sizes else max(1, round(a.epochs * max(sizes) / size))
+                if sizes:
+                    epochs = min(epochs, a.epochs * 8)
+                info["epochs"] = epochs
+                t0 = time.time()
+                info["loss_hist"] = train(net, inputs[:n_img], targets[:n_img], epochs, a.batch, a.lr, seed=sd,
+                                          log=log)
+                info["t_train_s"] = time.time() - t0
+            nets.append((net, info))
     del inputs, targets
     tspec = synth.WORKLOADS[a.test]
     tspec = synth.CubeSpec(**{**tspec.__dict__, "seed": a.test_seed})
@@ -294,7 +332,8 @@ def main(argv=None):
     for net, info in nets:
         w = compare_warm(net, cube, tspec.J, a.sigma, a.tol, f_ref, a.check_every, a.max_iter)
         w.update(info)
-        log(f"[warmstart] warm (net seed {info['net_seed']}): {w['warm_iters']} iterations, {w['warm_s']:.2f}s")
+        log(f"[warmstart] warm (net seed {info['net_seed']}, {info['train_cubes']} training cubes): "
+            f"{w['warm_iters']} iterations, {w['warm_s']:.2f}s")
         runs.append(w)
     res["runs"] = runs
     _emit(res, a.out, nets)
@@ -307,7 +346,8 @@ def _emit(res: dict, out: str | None, nets):
         with open(out, "w") as f:
             f.write(line + "\n")
         for net, info in nets:
-            np.save(out.replace(".json", f"_params_seed{info['net_seed']}.npy"), net.get_params())
+            np.save(out.replace(".json", f"_params_n{info['train_cubes']}_seed{info['net_seed']}.npy"),
+                    net.get_params())
     for net, _ in nets:
         net.close()
 
