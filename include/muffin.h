@@ -16,7 +16,8 @@
  *    muffin_last_error() gives a message for the last failure on the calling thread.
  *  - Arrays are FP32, C-contiguous, channel-major:
  *      cube    [L][N][N]           (X, dirty image, PSF, V, gradients)
- *      U       [L][J+1][N][N]      (planes w_1..w_J, then the coarse plane c_J, of each channel)
+ *      U       [L][J+1][N][N]      (planes w_1..w_J, then the coarse plane c_J, of each channel;
+ *                                   with the union-of-bases prior [L][8][N][N], one plane per basis)
  *    V holds the cosine coefficients of each pixel spectrum, coefficient index first.
  *  - "on_device" arguments: nonzero means the pointer is device memory on the context's device,
  *    zero means host memory.  The library never takes ownership of caller memory: it copies
@@ -62,14 +63,26 @@ typedef struct muffin_ctx muffin_ctx;
 #define MUFFIN_FLAG_NO_FUSED_TAIL 2
 #define MUFFIN_FLAG_FUSED_TAIL 4
 
+/* Spatial prior W_s (eq. (RegAll)): the isotropic undecimated wavelet transform MUFFIN uses (Sec. 3,
+ * Sec. 4), or the union of the first eight orthonormal Daubechies wavelet bases it is compared with
+ * (Sec. 3, Sec. 4 Fig. 3): W_s x = (Psi_1 x, ..., Psi_8 x) / sqrt(8), Psi_n the J-level periodic 2-D
+ * DWT with n vanishing moments, each basis's coefficients in the pyramid layout of an N x N plane
+ * (after level l the approximation is the top-left (N/2^l)^2 block, the level's horizontal,
+ * vertical and diagonal details to its right, below it and diagonally).  With the union of bases,
+ * U holds 8 planes per channel, iuwt_gen and penalize_coarse are ignored (every coefficient is
+ * penalised), ||W_s||^2 = 1, and N must be divisible by 2^J. */
+#define MUFFIN_PRIOR_IUWT 0
+#define MUFFIN_PRIOR_UOB 1
+
 /* Problem and algorithm parameters (Sec. 2 eqs. (reg), (RegAll); Sec. 3, Algorithm 1). */
 typedef struct {
   int32_t N;                /* image side; N = 2^a or 3 * 2^a with 8 <= N <= 1024 */
   int32_t L;                /* channels, 1 <= L <= 512 */
-  int32_t J;                /* IUWT detail scales, 1 <= J <= 6; W_s yields J+1 planes */
+  int32_t J;                /* wavelet scales, 1 <= J <= 6; the IUWT yields J+1 planes */
   int32_t iuwt_gen;         /* 1 or 2: first or second generation IUWT (the paper uses 2, Sec. 4) */
   int32_t penalize_coarse;  /* 1: the coarse plane is part of W_s's l1 term; 0: it is not */
   int32_t flags;            /* MUFFIN_FLAG_* bits, 0 by default */
+  int32_t prior;            /* MUFFIN_PRIOR_IUWT (0, default) or MUFFIN_PRIOR_UOB */
   double mu_s;              /* spatial weight mu_s >= 0 (eq. (RegAll)) */
   double mu_lambda;         /* spectral weight mu_lambda >= 0 (eq. (RegAll)) */
   double tau;               /* primal step; <= 0 selects 0.99 / (beta/2 + sigma ||K||^2) */
@@ -127,17 +140,19 @@ int muffin_snr(muffin_ctx* ctx, const float* truth, int on_device, double* snr_d
  * out[3] mu_lambda-weighted spectral l1.  Synchronises. */
 int muffin_objective(muffin_ctx* ctx, double out[4]);
 
-/* Scalars of the context: out[0] tau, [1] sigma, [2] rho, [3] beta, [4] ||K||^2, [5] ||W_s||^2,
- * [6] delta (rho must lie in (0, delta)), [7] iterations done. */
+/* Scalars of the context (Sec. 3: the step sizes are fixed by the convergence condition of the
+ * primal-dual method it cites): out[0] tau, [1] sigma, [2] rho, [3] beta (Lipschitz constant of the
+ * data term's gradient), [4] ||K||^2, [5] ||W_s||^2, [6] delta (rho must lie in (0, delta)),
+ * [7] iterations done.  Host values, no device work. */
 int muffin_info(muffin_ctx* ctx, double out[8]);
 
 /* Initial point (Algorithm 1, "Initialize"; Sec. 4, calibration step 2 starts the full method from
  * step 1's X): X = max(x0, 0), which keeps X inside the positivity constraint, and U = V = 0.
  * x0 is [L][N][N] on the host or the device; the caller keeps it. */
 int muffin_set_x(muffin_ctx* ctx, const float* x0, int on_device);
-/* Copy out the primal variable X [L][N][N] and the dual variables U [L][J+1][N][N] (one IUWT
- * decomposition per channel, eq. (anaylsespat)) and V [L][N][N] (cosine coefficients of each pixel
- * spectrum) of Algorithm 1, into caller memory (host or device). */
+/* Copy out the primal variable X [L][N][N] and the dual variables U (one decomposition per channel,
+ * eq. (anaylsespat): [L][J+1][N][N] for the IUWT, [L][8][N][N] for the union of bases) and V [L][N][N]
+ * (cosine coefficients of each pixel spectrum) of Algorithm 1, into caller memory (host or device). */
 int muffin_get_x(muffin_ctx* ctx, float* x, int on_device);
 int muffin_get_u(muffin_ctx* ctx, float* u, int on_device);
 int muffin_get_v(muffin_ctx* ctx, float* v, int on_device);
@@ -178,8 +193,8 @@ int muffin_set_state(muffin_ctx* ctx, const void* blob, size_t bytes);
 #define MUFFIN_OP_IUWT_SCHED 8
 int muffin_apply_op(muffin_ctx* ctx, int op, const float* in, float* out);
 
-/* Time n_iter iterations with HIP events on the library's stream, without graph replay, and
- * report average device milliseconds:
+/* Measurement, not part of the paper's method: time n_iter iterations of Algorithm 1 with HIP
+ * events on the library's stream, without graph replay, and report average device milliseconds:
  *   ms[0] whole iteration, [1] spatial adjoint (IUWT^dagger), [2] gradient FFT passes,
  *   [3] fused spectral kernel, [4] spatial analysis and dual update; [5..7] are 0;
  *   ms[8 + 2k] mean duration of one launch of kind k and ms[9 + 2k] launches of kind k per
@@ -195,8 +210,9 @@ int muffin_apply_op(muffin_ctx* ctx, int op, const float* in, float* out);
  * The iterations advance the state like muffin_step. */
 int muffin_profile(muffin_ctx* ctx, int32_t n_iter, double ms[32]);
 
-/* Time n_iter iterations (graph replay) with HIP events on the library's stream: *ms is the
- * total device time.  Advances the state like muffin_step. */
+/* Measurement, not part of the paper's method: time n_iter iterations of Algorithm 1 (graph
+ * replay) with HIP events on the library's stream: *ms is the total device time.  Advances the
+ * state like muffin_step. */
 int muffin_step_timed(muffin_ctx* ctx, int32_t n_iter, double* ms);
 
 /* ---------------------------------------------------------------------------------------------
@@ -214,6 +230,7 @@ typedef struct muffin_cnn muffin_cnn;
 /* Create with He-normal weights drawn from a counter-based generator seeded by seed; features
  * must be 32. */
 int muffin_cnn_create(muffin_cnn** out, int32_t features, uint64_t seed, void* hip_stream);
+/* Number of FP32 parameters of the network (19105). */
 int muffin_cnn_param_count(muffin_cnn* net, int32_t* n);
 /* Copy the FP32 parameter vector to or from host memory (n must equal the count); set_params
  * also resets the Adam moments. */
@@ -244,6 +261,7 @@ int muffin_cnn_layer(muffin_cnn* net, int32_t layer, int32_t op, const float* x,
  * on one GPU shares that GPU's workspace: calls that overlap in time on one GPU (two networks, two
  * streams, two threads) race and must be ordered by the caller. */
 int muffin_cnn_predict_noalloc(muffin_cnn* net, const float* in, float* out, int32_t B, int32_t N);
+/* Release a network and its device buffers (NULL is accepted). */
 void muffin_cnn_free(muffin_cnn* net);
 /* Warm start: X = max(CNN(y_l / g_l), 0) channel by channel, U = V = 0, where g_l is the sum of
  * psf_l over the 9 x 9 window centred on its origin.  N must be a multiple of 32.  The network's
@@ -254,9 +272,10 @@ int muffin_warm_start(muffin_ctx* ctx, muffin_cnn* net);
  * device), so that a caller can train on or check exactly what muffin_warm_start feeds the network. */
 int muffin_warm_input(muffin_ctx* ctx, float* out, int on_device);
 
+/* Release a context and every device buffer it owns (NULL is accepted); waits for its stream. */
 void muffin_free(muffin_ctx* ctx);
 
-/* Autotuner: times every band height (rows per workgroup) of the IUWT band kernels, for each scale
+/* Launch tuning, not part of the paper's method.  Autotuner: times every band height (rows per workgroup) of the IUWT band kernels, for each scale
  * of this context's sizes, keeps the fastest (process-wide, per image side, scale and kernel) and
  * recaptures the iteration.  Only scratch planes are written: the state is unchanged.  report (may
  * be NULL) receives a JSON description of the candidates and choices, truncated to report_len. */
@@ -273,9 +292,11 @@ int muffin_autotune(muffin_ctx* ctx, int32_t reps, char* report, size_t report_l
 typedef struct muffin_batch muffin_batch;
 int muffin_batch_init(muffin_batch** out, int32_t n_cubes, const muffin_params* p, const float* const* dirty,
                       const float* const* psf, int inputs_on_device, void* hip_stream);
+/* n_iter iterations of Algorithm 1 for every cube of the batch (graph replay, groups concurrent). */
 int muffin_batch_step(muffin_batch* batch, int32_t n_iter);
 /* n_iter iterations of every cube; *ms is the device time between two events of the caller's stream. */
 int muffin_batch_step_timed(muffin_batch* batch, int32_t n_iter, double* ms);
+/* Per cube, as muffin_objective (eq. (reg) + eq. (RegAll)) and muffin_get_x. */
 int muffin_batch_objective(muffin_batch* batch, int32_t cube, double out[4]);
 int muffin_batch_get_x(muffin_batch* batch, int32_t cube, float* x, int on_device);
 /* Initial point of one cube of the batch (Algorithm 1, "Initialize"), as muffin_set_x: its X becomes
@@ -285,10 +306,19 @@ int muffin_batch_set_x(muffin_batch* batch, int32_t cube, const float* x0, int o
 int muffin_batch_warm_input(muffin_batch* batch, int32_t cube, float* out, int on_device);
 /* SNR of one cube of the batch against its truth [L][N][N], as muffin_snr. */
 int muffin_batch_snr(muffin_batch* batch, int32_t cube, const float* truth, int on_device, double* snr_db);
+/* Per cube, as muffin_info; the autotuner over every group, as muffin_autotune; release. */
 int muffin_batch_info(muffin_batch* batch, int32_t cube, double out[8]);
 int muffin_batch_autotune(muffin_batch* batch, int32_t reps, char* report, size_t report_len);
 void muffin_batch_free(muffin_batch* batch);
 
+/* The scaling filter of Daubechies' orthonormal wavelet with n vanishing moments (1 <= n <= 8; 2n
+ * taps into h[0..2n), len >= 2n) as the library builds it for the union-of-bases prior, in FP64
+ * (host only: Daubechies' spectral factorisation, minimum phase, largest taps first).  EINVAL for
+ * other n or a short buffer. */
+int muffin_uob_filter(int32_t n, double* h, int32_t len);
+
+/* Error reporting: a fixed text for each MUFFIN_E* code, and the message of the last failure on the
+ * calling thread (valid until the next failing call on that thread). */
 const char* muffin_strerror(int code);
 const char* muffin_last_error(void);
 

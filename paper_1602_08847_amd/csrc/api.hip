@@ -49,6 +49,12 @@ struct muffin_ctx {
   std::vector<Seg> segs;
   std::vector<float> chan_w_host;
   int N = 0, L = 0, J = 0, gen = 2;
+  // spatial prior: the IUWT (np_u = J + 1 dual planes per channel) or the union of Daubechies
+  // bases (np_u = kUobBases planes, each one basis's pyramid of coefficients)
+  bool uob = false;
+  int np_u = 0;
+  UobFilters uf{};
+  float *uobA = nullptr, *uobB = nullptr;  // approximations between levels: (N/2)^2 and (N/4)^2 per (channel, basis)
   // Every N x N plane of the cube buffers sits in a slot of cs floats: N^2 plus one row, rounded up
   // to 32 floats, plus 32 more (128 bytes).  The spectral step walks each pixel across all the
   // channels; with planes a power of two apart those accesses fall on few HBM channels, and the
@@ -139,6 +145,10 @@ int validate(const muffin_params* p) {
   if ((p->flags & MUFFIN_FLAG_NO_FUSED_TAIL) && (p->flags & MUFFIN_FLAG_FUSED_TAIL))
     return set_error("FUSED_TAIL and NO_FUSED_TAIL exclude each other"), MUFFIN_EINVAL;
   if (p->iuwt_gen != 1 && p->iuwt_gen != 2) return set_error("iuwt_gen must be 1 or 2"), MUFFIN_EINVAL;
+  if (p->prior != MUFFIN_PRIOR_IUWT && p->prior != MUFFIN_PRIOR_UOB)
+    return set_error("prior must be MUFFIN_PRIOR_IUWT or MUFFIN_PRIOR_UOB"), MUFFIN_EINVAL;
+  if (p->prior == MUFFIN_PRIOR_UOB && p->N % (1 << p->J) != 0)
+    return set_error("the union of bases needs N divisible by 2^J"), MUFFIN_EINVAL;
   if (p->penalize_coarse != 0 && p->penalize_coarse != 1)
     return set_error("penalize_coarse must be 0 or 1"), MUFFIN_EINVAL;
   if (!(p->mu_s >= 0) || !(p->mu_lambda >= 0) || !std::isfinite(p->mu_s) || !std::isfinite(p->mu_lambda))
@@ -177,7 +187,7 @@ static bool use_pairs(const muffin_ctx* c) { return c->gen == 2 && !(c->p.flags 
 // Plane k of U in the buffers of parity par (see muffin_ctx::upar): pointer and channel stride.
 static PlaneOut uplane(const muffin_ctx* c, int k, int par) {
   if (c->fused && par && k >= c->jf) return PlaneOut{c->U2 + (long long)(k - c->jf) * c->us, 3 * c->us};
-  return PlaneOut{c->U + (long long)k * c->us, (long long)(c->J + 1) * c->us};
+  return PlaneOut{c->U + (long long)k * c->us, (long long)c->np_u * c->us};
 }
 static PlaneRef uref(const muffin_ctx* c, int k, int par) {
   const PlaneOut o = uplane(c, k, par);
@@ -243,6 +253,99 @@ static std::vector<IuwtStep> adjoint_schedule(const muffin_ctx* c) {
   return v;
 }
 
+// ---------------------------------------------------------------- union of bases
+// Approximation planes between levels: LL_l of every (channel, basis) sits in uobA when l is odd
+// ((N/2)^2 floats each) and in uobB when l is even ((N/4)^2 floats each).
+static long long uob_cap(const muffin_ctx* c, int level) {
+  const long long h = c->N >> ((level & 1) ? 1 : 2);
+  return h * h > 0 ? h * h : 1;
+}
+static float* uob_ll(const muffin_ctx* c, int level, int ch0) {
+  return ((level & 1) ? c->uobA : c->uobB) + (long long)ch0 * kUobBases * uob_cap(c, level);
+}
+
+// W_s of nch channel images (in, channel stride in_cs; channel ch0 of the context) through the J
+// levels of every basis: UOB_DUAL updates the dual planes U (strides u_cs, u_bs) with
+// u <- rho sat(u + coef w) + (1 - rho) u, UOB_STORE writes scale * w to out, UOB_ABS adds
+// sum |scale * w| (FP64) to *dst_abs.
+int enqueue_uob_analysis(muffin_ctx* c, int mode, const float* in, long long in_cs, int ch0, int nch, float* U,
+                         long long u_cs, long long u_bs, float* out, long long out_cs, long long out_bs, float coef,
+                         float rho, float scale, double* dst_abs) {
+  for (int lev = 1; lev <= c->J; ++lev) {
+    UobLevelArgs a;
+    a.f = c->uf;
+    a.n = c->N >> (lev - 1);
+    a.N = c->N;
+    if (lev == 1) {
+      a.in = in;
+      a.in_cs = in_cs;
+      a.in_bs = 0;
+      a.in_ld = c->N;
+      a.shared_input = 1;
+    } else {
+      a.in = uob_ll(c, lev - 1, ch0);
+      a.in_cs = kUobBases * uob_cap(c, lev - 1);
+      a.in_bs = uob_cap(c, lev - 1);
+      a.in_ld = a.n;
+    }
+    a.last = lev == c->J;
+    if (!a.last) {
+      a.llout = uob_ll(c, lev, ch0);
+      a.ll_cs = kUobBases * uob_cap(c, lev);
+      a.ll_bs = uob_cap(c, lev);
+    }
+    a.U = U;
+    a.u_cs = u_cs;
+    a.u_bs = u_bs;
+    a.out = out;
+    a.out_cs = out_cs;
+    a.out_bs = out_bs;
+    a.coef = coef;
+    a.rho = rho;
+    a.scale = scale;
+    int nb = 0;
+    MF_TRY(launch_uob_an(mode, a, nch, c->partial, &nb, c->st));
+    if (mode == UOB_ABS) MF_TRY(launch_reduce_sum(c->partial, nb, dst_abs, 1, c->st));
+  }
+  return MUFFIN_OK;
+}
+
+// dst = W_s^dagger u = sum_n Psi_n^T u_n / sqrt(8) for every channel (dst channel stride dst_cs).
+int enqueue_uob_adjoint(muffin_ctx* c, const float* U, long long u_cs, long long u_bs, float* dst, long long dst_cs) {
+  for (int lev = c->J; lev >= 1; --lev) {
+    UobLevelArgs a;
+    a.f = c->uf;
+    a.n = c->N >> (lev - 1);
+    a.N = c->N;
+    if (lev == c->J) {
+      a.in = U;
+      a.in_cs = u_cs;
+      a.in_bs = u_bs;
+      a.in_ld = c->N;
+    } else {
+      a.in = uob_ll(c, lev, 0);
+      a.in_cs = kUobBases * uob_cap(c, lev);
+      a.in_bs = uob_cap(c, lev);
+      a.in_ld = c->N >> lev;
+    }
+    a.U = const_cast<float*>(U);
+    a.u_cs = u_cs;
+    a.u_bs = u_bs;
+    if (lev == 1) {
+      a.out = dst;
+      a.out_cs = dst_cs;
+      a.scale = (float)(1.0 / std::sqrt((double)kUobBases));
+      MF_TRY(launch_uob_adj(true, a, c->L, c->st));
+    } else {
+      a.llout = uob_ll(c, lev - 1, 0);
+      a.ll_cs = kUobBases * uob_cap(c, lev - 1);
+      a.ll_bs = uob_cap(c, lev - 1);
+      MF_TRY(launch_uob_adj(false, a, c->L, c->st));
+    }
+  }
+  return MUFFIN_OK;
+}
+
 // Spatial adjoint of omega-weighted U; returns the buffer holding a = W_s^dagger (omega u).
 // Second generation: Horner steps a <- u_j + H_j (a - H_j u_j) from the coarsest scale down, two
 // scales per launch where possible.
@@ -251,6 +354,11 @@ static std::vector<IuwtStep> adjoint_schedule(const muffin_ctx* c) {
 // (channel stride cs): the fused tail of the last iteration has already run them.
 int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ups, long long ucs, float omega_c,
                     const float** result, bool timed = false, const float* carried = nullptr) {
+  if (c->uob) {
+    MF_TRY(enqueue_uob_adjoint(c, Ubase, ucs, ups, c->cA, c->cs));
+    *result = c->cA;
+    return MUFFIN_OK;
+  }
   const int J = c->J;
   const long long np = c->cs;
   const float* a = Ubase + (long long)J * ups;  // coarse plane
@@ -307,8 +415,12 @@ int enqueue_adjoint(muffin_ctx* c, const float* Ubase, long long ups, long long 
 // Analysis of the channel images in (stride cs) fused with the spatial dual step on U; second
 // generation: two scales per launch where possible, the last one feeding the coarse plane's step.
 int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false, int par = 0) {
+  if (c->uob)
+    return enqueue_uob_analysis(c, UOB_DUAL, in, c->cs, 0, c->L, c->U, (long long)c->np_u * c->us, c->us, nullptr, 0,
+                                0, (float)(c->sigma * c->p.mu_s / std::sqrt((double)kUobBases)), (float)c->rho, 1.f,
+                                nullptr);
   const int J = c->J;
-  const long long np = c->cs, us = c->us, ucs = (long long)(J + 1) * us;
+  const long long np = c->cs, us = c->us, ucs = (long long)c->np_u * us;
   const float coef = (float)(c->sigma * c->p.mu_s);
   const float rho = (float)c->rho;
   const float coefc = coef * c->omega_c;
@@ -430,7 +542,7 @@ int enqueue_spectral(muffin_ctx* c) {
 // transform, each scale's fused adjoint (marks pass 1) or analysis launch is bracketed in kev.
 // par: parity of the fused tail's planes at the start of the iteration (it flips at the end).
 int enqueue_iteration(muffin_ctx* c, hipEvent_t* marks, int timed_family = 0, int par = 0) {
-  const long long ucs = (long long)(c->J + 1) * c->us;
+  const long long ucs = (long long)c->np_u * c->us;
   if (marks) MF_HIP(hipEventRecord(marks[0], c->st));
   const float* s = nullptr;
   MF_TRY(enqueue_adjoint(c, c->U, c->us, ucs, c->omega_c, &s, timed_family == 1, c->fused ? c->Acar : nullptr));
@@ -463,6 +575,12 @@ int enqueue_objective(muffin_ctx* c, int si) {
   MF_TRY(launch_rows_c2r(c->S, nch, c->g, c->tw, EPI_RESID, nullptr, np, nullptr, nullptr, 0.f, c->Y + off,
                          c->chan_w ? c->chan_w + s.ch0 : nullptr, c->partial, &nb, c->st));
   MF_TRY(launch_reduce_sum(c->partial, nb, c->dres + 1, 0, c->st));
+  if (c->uob) {
+    MF_TRY(enqueue_uob_analysis(c, UOB_ABS, X, np, s.ch0, nch, nullptr, 0, 0, nullptr, 0, 0, 0.f, 1.f,
+                                (float)(1.0 / std::sqrt((double)kUobBases)), c->dres + 2));
+    MF_TRY(launch_dct_abs(X, s.WT, c->npix, np, nch, c->partial, &nb, c->st));
+    return launch_reduce_sum(c->partial, nb, c->dres + 3, 0, c->st);
+  }
   const float* cur = X;
   float* bufs[2] = {c->cA, c->cB};
   for (int j = 0; j < c->J; ++j) {
@@ -496,7 +614,7 @@ void destroy(muffin_ctx* c) {
     if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
   }
   void* bufs[] = {c->X, c->U, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT, c->S, c->Hhat_T, c->P_T,
-                  c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres, c->U2, c->Acar, c->tau_ch, c->Xs, c->Us, c->Vs};
+                  c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres, c->U2, c->Acar, c->tau_ch, c->Xs, c->Us, c->Vs, c->uobA, c->uobB};
   for (Seg& s : c->segs) {
     void* sb[] = {s.W, s.WT, s.twL, s.csL};
     for (void* b : sb)
@@ -560,6 +678,9 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   c->us = c->npix;
   c->g = fft_geom(p->N);
   c->omega_c = p->penalize_coarse ? 1.f : 0.f;
+  c->uob = p->prior == MUFFIN_PRIOR_UOB;
+  c->np_u = c->uob ? kUobBases : c->J + 1;
+  if (c->uob) c->uf = uob_filters();
   c->sigma = p->sigma;
   c->rho = p->rho;
   int total = 0;
@@ -575,8 +696,8 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   }
   c->L = total;
   c->cube = c->cs * total;
-  c->ucube = c->us * total * (c->J + 1);
-  c->fused_ok = !(p->flags & MUFFIN_FLAG_NO_FUSED_TAIL) && use_pairs(c) && c->omega_c == 1.f &&
+  c->ucube = c->us * total * c->np_u;
+  c->fused_ok = !c->uob && !(p->flags & MUFFIN_FLAG_NO_FUSED_TAIL) && use_pairs(c) && c->omega_c == 1.f &&
                 !iuwt_groups(c).empty() && iuwt_groups(c).back() == 2;
   c->jf = c->J - 2;
   if (c->fused_ok) {
@@ -631,6 +752,10 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   MF_TRY(dalloc(&c->partial, kMaxPartials));
   MF_TRY(dalloc(&c->dres, 16));
   MF_TRY(dalloc(&c->psf_lobe, c->L));
+  if (c->uob) {
+    MF_TRY(dalloc(&c->uobA, (long long)c->L * kUobBases * uob_cap(c, 1)));
+    MF_TRY(dalloc(&c->uobB, (long long)c->L * kUobBases * uob_cap(c, 2)));
+  }
   if (!c->chan_w_host.empty()) MF_TRY(dalloc(&c->chan_w, c->L));
 
   StreamScope scope(c);
@@ -700,8 +825,13 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
                          nullptr, nullptr, st));
   if (c->chan_w) MF_TRY(launch_scale_channels(c->B, c->chan_w, c->npix, c->cs, c->L, st));
   // ||W_s||^2 (FP64, shared by the group) and, per cube, beta = max_l w_l max_k |H_l(k)|^2
-  MF_TRY(launch_frame_bound(c->N, c->J, c->gen, c->omega_c, c->partial, c->dres + 5, st));
-  MF_HIP(hipMemcpyAsync(&c->Ws2, c->dres + 5, sizeof(double), hipMemcpyDeviceToHost, st));
+  // (the union of orthonormal bases divided by sqrt(8) is a tight frame: W_s^dagger W_s = I)
+  if (c->uob) {
+    c->Ws2 = 1.0;
+  } else {
+    MF_TRY(launch_frame_bound(c->N, c->J, c->gen, c->omega_c, c->partial, c->dres + 5, st));
+    MF_HIP(hipMemcpyAsync(&c->Ws2, c->dres + 5, sizeof(double), hipMemcpyDeviceToHost, st));
+  }
   const long long per_ch = (long long)c->g.pitch * c->N;
   for (size_t i = 0; i < c->segs.size(); ++i) {
     Seg& s = c->segs[i];
@@ -741,13 +871,13 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
 // Before a monitored iteration: X, U (the planes of the current parity, into dense planes) and V
 // are copied aside (the copies are allocated on first use).
 int snapshot_state(muffin_ctx* c) {
-  const long long np = c->npix, J1 = c->J + 1;
+  const long long np = c->npix, J1 = c->np_u;
   if (!c->Xs) MF_TRY(dalloc(&c->Xs, c->cube));
   if (!c->Vs) MF_TRY(dalloc(&c->Vs, c->cube));
   if (!c->Us) MF_TRY(dalloc(&c->Us, (long long)c->L * J1 * np));
   MF_HIP(hipMemcpyAsync(c->Xs, c->X, sizeof(float) * c->cube, hipMemcpyDeviceToDevice, c->st));
   MF_HIP(hipMemcpyAsync(c->Vs, c->V, sizeof(float) * c->cube, hipMemcpyDeviceToDevice, c->st));
-  for (int k = 0; k <= c->J; ++k) {
+  for (int k = 0; k < c->np_u; ++k) {
     const PlaneOut u = uplane(c, k, c->upar);
     MF_TRY(copy_planes(c->Us + k * np, J1 * np, u.p, u.cs, c->L, np, hipMemcpyDeviceToDevice, c->st));
   }
@@ -756,9 +886,9 @@ int snapshot_state(muffin_ctx* c) {
 
 // After it: out = {||X - Xs||, ||X||, ||U - Us||, ||U||, ||V - Vs||, ||V||} (FP64, L2 over the cube).
 int state_change(muffin_ctx* c, double out[6]) {
-  const long long np = c->npix, J1 = c->J + 1;
+  const long long np = c->npix, J1 = c->np_u;
   MF_TRY(launch_diff_norms(c->X, c->cs, c->Xs, c->cs, np, c->L, c->partial, c->dres + 6, c->dres + 7, 0, c->st));
-  for (int k = 0; k <= c->J; ++k) {
+  for (int k = 0; k < c->np_u; ++k) {
     const PlaneOut u = uplane(c, k, c->upar);
     MF_TRY(launch_diff_norms(u.p, u.cs, c->Us + k * np, J1 * np, np, c->L, c->partial, c->dres + 8, c->dres + 9,
                              k > 0, c->st));
@@ -822,7 +952,7 @@ int set_fused(muffin_ctx* c, bool on) {
   if (on && !c->fused_ok) return set_error("fused tail not available for this context"), MUFFIN_EINVAL;
   if (!on && c->upar) {
     const long long np = c->npix;
-    MF_TRY(copy_planes(c->U + (long long)c->jf * c->us, (c->J + 1) * c->us, c->U2, 3 * c->us, c->L, 3 * np,
+    MF_TRY(copy_planes(c->U + (long long)c->jf * c->us, c->np_u * c->us, c->U2, 3 * c->us, c->L, 3 * np,
                        hipMemcpyDeviceToDevice, c->st));
     c->upar = 0;
   }
@@ -856,7 +986,12 @@ int replay(muffin_ctx* c, int n) {
 // Autotuner: for every band or pair launch of the iteration, time each band height that divides N
 // on the context's own sizes (reading state, writing only scratch planes) and keep the fastest.
 int autotune(muffin_ctx* c, int reps, std::string& rep) {
-  const long long np = c->cs, us = c->us, ucs = (long long)(c->J + 1) * us;
+  if (c->uob) {
+    rep += "{\"N\": " + std::to_string(c->N) + ", \"channels\": " + std::to_string(c->L) +
+           ", \"prior\": \"union of bases\", \"scales\": []}";
+    return MUFFIN_OK;
+  }
+  const long long np = c->cs, us = c->us, ucs = (long long)c->np_u * us;
   // the schedule without the fused tail, plus the fused launch when it is available; the faster
   // of the fused launch and the two it replaces is kept
   const bool was_fused = c->fused;
@@ -973,6 +1108,8 @@ extern "C" {
 
 const char* muffin_last_error(void) { return g_err.c_str(); }
 
+int muffin_uob_filter(int32_t n, double* h, int32_t len) { return uob_lowpass(n, h, len); }
+
 const char* muffin_strerror(int code) {
   switch (code) {
     case MUFFIN_OK: return "ok";
@@ -1052,6 +1189,7 @@ int muffin_batch_init(muffin_batch** out, int32_t n_cubes, const muffin_params* 
   // group cubes that can share the per-channel phases
   auto same = [&](const muffin_params& a, const muffin_params& c) {
     return a.N == c.N && a.J == c.J && a.iuwt_gen == c.iuwt_gen && a.penalize_coarse == c.penalize_coarse &&
+           a.prior == c.prior &&
            a.mu_s == c.mu_s && a.sigma == c.sigma && a.rho == c.rho && a.flags == c.flags;
   };
   std::vector<char> done(n_cubes, 0);
@@ -1151,7 +1289,7 @@ int muffin_batch_set_x(muffin_batch* b, int32_t cube, const float* x0, int on_de
   if (!x0) return set_error("bad arguments"), MUFFIN_EINVAL;
   StreamScope scope(g);
   const Seg& s = g->segs[si];
-  const long long off = (long long)s.ch0 * g->cs, J1 = g->J + 1;
+  const long long off = (long long)s.ch0 * g->cs, J1 = g->np_u;
   MF_TRY(planes_in(g, g->X + off, x0, s.L, on_device));
   MF_TRY(launch_clamp_pos(g->X + off, (long long)s.L * g->cs, g->st));
   // this cube's duals: U (both buffers of the fused tail's planes) and V; the carried adjoint sum
@@ -1387,16 +1525,16 @@ static int zero_dual(muffin_ctx* c) {
 // U to or from the caller's dense [L][J+1][N][N] array.  With the fused tail's current planes
 // in U2, its three planes of every channel are copied on their own.
 static int u_out(muffin_ctx* c, float* dst, int on_device) {
-  MF_TRY(planes_out(c, dst, c->U, (long long)c->L * (c->J + 1), on_device, c->us));
+  MF_TRY(planes_out(c, dst, c->U, (long long)c->L * c->np_u, on_device, c->us));
   if (c->fused && c->upar) {
     const long long np = c->npix;
-    MF_TRY(copy_planes(dst + (long long)c->jf * np, (c->J + 1) * np, c->U2, 3 * c->us, c->L, 3 * np,
+    MF_TRY(copy_planes(dst + (long long)c->jf * np, c->np_u * np, c->U2, 3 * c->us, c->L, 3 * np,
                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st));
   }
   return MUFFIN_OK;
 }
 static int u_in(muffin_ctx* c, const float* src, int on_device) {
-  MF_TRY(planes_in(c, c->U, src, (long long)c->L * (c->J + 1), on_device, c->us));
+  MF_TRY(planes_in(c, c->U, src, (long long)c->L * c->np_u, on_device, c->us));
   if (c->fused) {
     c->upar = 0;
     c->acar_ok = false;  // recomputed before the next iteration
@@ -1444,7 +1582,7 @@ int muffin_get_v(muffin_ctx* c, float* v, int on_device) {
 
 int muffin_state_size(muffin_ctx* c, size_t* bytes) {
   if (!c || !bytes) return set_error("bad arguments"), MUFFIN_EINVAL;
-  *bytes = sizeof(BlobHeader) + sizeof(float) * (size_t)c->npix * c->L * (c->J + 3);
+  *bytes = sizeof(BlobHeader) + sizeof(float) * (size_t)c->npix * c->L * (c->np_u + 2);
   return MUFFIN_OK;
 }
 
@@ -1459,6 +1597,7 @@ int muffin_get_state(muffin_ctx* c, void* blob, size_t bytes) {
   h.J = c->J;
   h.gen = c->gen;
   h.pc = c->p.penalize_coarse;
+  h.pad = c->p.prior;
   h.mu_s = c->p.mu_s;
   h.mu_l = c->segs[0].mu_l;
   h.tau = c->segs[0].tau;
@@ -1471,7 +1610,7 @@ int muffin_get_state(muffin_ctx* c, void* blob, size_t bytes) {
   const long long dense = c->npix * c->L;  // the blob holds X, U, V in the dense layout
   MF_TRY(planes_out(c, f, c->X, c->L, 0));
   MF_TRY(u_out(c, f + dense, 0));
-  MF_TRY(planes_out(c, f + dense * (c->J + 2), c->V, c->L, 0));
+  MF_TRY(planes_out(c, f + dense * (c->np_u + 1), c->V, c->L, 0));
   return MUFFIN_OK;
 }
 
@@ -1482,7 +1621,7 @@ int muffin_set_state(muffin_ctx* c, const void* blob, size_t bytes) {
   BlobHeader h;
   std::memcpy(&h, blob, sizeof(h));
   if (h.magic != kMagic || h.N != c->N || h.L != c->L || h.J != c->J || h.gen != c->gen ||
-      h.pc != c->p.penalize_coarse || h.mu_s != c->p.mu_s || h.mu_l != c->segs[0].mu_l || h.tau != c->segs[0].tau ||
+      h.pc != c->p.penalize_coarse || h.pad != c->p.prior || h.mu_s != c->p.mu_s || h.mu_l != c->segs[0].mu_l || h.tau != c->segs[0].tau ||
       h.sigma != c->sigma || h.rho != c->rho)
     return set_error("checkpoint sizes or parameters differ from the context"), MUFFIN_ESTATE;
   const float* f = (const float*)((const char*)blob + sizeof(h));
@@ -1490,7 +1629,7 @@ int muffin_set_state(muffin_ctx* c, const void* blob, size_t bytes) {
   const long long dense = c->npix * c->L;
   MF_TRY(planes_in(c, c->X, f, c->L, 0));
   MF_TRY(u_in(c, f + dense, 0));
-  MF_TRY(planes_in(c, c->V, f + dense * (c->J + 2), c->L, 0));
+  MF_TRY(planes_in(c, c->V, f + dense * (c->np_u + 1), c->L, 0));
   c->iter = h.iter;
   return MUFFIN_OK;
 }
@@ -1535,7 +1674,10 @@ int muffin_apply_op(muffin_ctx* c, int op, const float* in, float* out) {
       MF_TRY(enqueue_gradient(c, c->cT, c->cA, nullptr, 0.f));
       return planes_out(c, out, c->cA, c->L, 1);
     case MUFFIN_OP_IUWT: {
-      const long long ucs = (long long)(c->J + 1) * np;
+      const long long ucs = (long long)c->np_u * np;
+      if (c->uob)
+        return enqueue_uob_analysis(c, UOB_STORE, in, np, 0, c->L, nullptr, 0, 0, out, ucs, np, 0.f, 1.f,
+                                    (float)(1.0 / std::sqrt((double)kUobBases)), nullptr);
       const float* cur = in;
       float* bufs[2] = {c->cA, c->cB};
       for (int j = 0; j < c->J; ++j) {
@@ -1561,14 +1703,14 @@ int muffin_apply_op(muffin_ctx* c, int op, const float* in, float* out) {
     }
     case MUFFIN_OP_IUWT_ADJ: {
       const float* a = nullptr;
-      MF_TRY(enqueue_adjoint(c, in, np, (long long)(c->J + 1) * np, 1.f, &a));
+      MF_TRY(enqueue_adjoint(c, in, np, (long long)c->np_u * np, 1.f, &a));
       return launch_pointwise(PT_COPY, c->N, c->L, pref(a, cs), PlaneRef{}, pout(out, np), 1.f, 1.f, nullptr,
                               nullptr, c->st);
     }
     case MUFFIN_OP_IUWT_SCHED: {
       // the iteration's own analysis launches (triples, pairs, the fused tail when the context uses
       // it) on zero dual planes with sigma mu_s = rho = 1: each dual plane becomes sat(w) = w
-      const long long J1 = c->J + 1, us = c->us;
+      const long long J1 = c->np_u, us = c->us;
       if (!c->Us) MF_TRY(dalloc(&c->Us, (long long)c->L * J1 * np));
       float *U2s = nullptr, *Acs = nullptr;
       if (c->fused) {

@@ -207,6 +207,43 @@ int launch_dct(const float* in, float* out, const float* Wmat, long long npix, l
 int launch_dct_abs(const float* in, const float* WT, long long npix, long long cs, int L, double* partial,
                    int* nblocks_out, hipStream_t st);
 
+// ------------------------------------------------------------------ union of wavelet bases
+// The spatial prior as a union of the first kUobBases orthonormal Daubechies bases (scaled by
+// 1/sqrt(kUobBases)), each a J-level periodic 2-D DWT in pyramid layout; see uob.hip.
+constexpr int kUobBases = 8;
+struct UobFilters {
+  float h[kUobBases][2 * kUobBases];  // scaling filters (basis b has 2 (b + 1) taps)
+  float g[kUobBases][2 * kUobBases];  // wavelet filters g_k = (-1)^k h_{F-1-k}
+  int len[kUobBases];
+};
+UobFilters uob_filters();
+// Daubechies scaling filter with n vanishing moments (2n taps) in FP64, from the library's own
+// construction (for host-side checks)
+int uob_lowpass(int n, double* h, int len);
+enum UobMode { UOB_DUAL = 0, UOB_STORE = 1, UOB_ABS = 2 };
+// One level of the analysis (input side n -> four m x m subbands, m = n / 2) or of the adjoint
+// (coefficient side m -> output side n), over nch channels.
+struct UobLevelArgs {
+  UobFilters f;
+  const float* in = nullptr;  // analysis: level input (d, or the previous approximation); adjoint: approximation
+  long long in_cs = 0, in_bs = 0;  // channel and basis strides of in (in_bs = 0: one input for all bases)
+  int in_ld = 0;                   // row stride of in
+  int n = 0;                       // analysis: input side; adjoint: output side
+  int N = 0;                       // side (and row stride) of the dual planes and of out
+  int shared_input = 0;            // analysis: one input tile for all bases (level 1)
+  int last = 0;                    // analysis: the coarsest level (its approximation is a coefficient too)
+  float* U = nullptr;              // dual planes [channel][basis][N][N]
+  long long u_cs = 0, u_bs = 0;
+  float* llout = nullptr;          // next approximation of each (channel, basis), dense rows
+  long long ll_cs = 0, ll_bs = 0;
+  float* out = nullptr;            // UOB_STORE: coefficients (strides out_cs, out_bs); adjoint: the image
+  long long out_cs = 0, out_bs = 0;
+  float coef = 0.f, rho = 1.f, scale = 1.f;
+  double* partial = nullptr;
+};
+int launch_uob_an(int mode, const UobLevelArgs& a, int nch, double* partial, int* nblocks_out, hipStream_t st);
+int launch_uob_adj(bool accum, const UobLevelArgs& a, int nch, hipStream_t st);
+
 // ------------------------------------------------------------------ reductions (FP64)
 // dst[slot] (+)= sum(partial[0..n)) in a fixed order.
 int launch_reduce_sum(const double* partial, int n, double* dst, int accumulate, hipStream_t st);

@@ -1,0 +1,353 @@
+// Union of orthonormal wavelet bases as the spatial prior: W_s x = (Psi_1 x, ..., Psi_8 x) / sqrt(8),
+// Psi_n the J-level periodic 2-D discrete wavelet transform with Daubechies' filter of n vanishing
+// moments (the prior MUFFIN's IUWT replaces and is compared with, Sec. 3 and Sec. 4, Fig. 3).
+//
+// Coefficients of basis n sit in the pyramid layout of an N x N plane: after level l the
+// approximation LL_l is the top-left (N / 2^l)^2 block, and the level's HL, LH and HH blocks sit to
+// its right, below it and diagonally.  A level filters along the columns index first (lo/hi),
+// then along the rows index (LL, LH from lo; HL, HH from hi):
+//   lo[r][c] = sum_k h_k x[r][(2c + k) mod n],   hi with g_k = (-1)^k h_{F-1-k}
+//   LL[r][c] = sum_k h_k lo[(2r + k) mod n][c], LH with g, HL and HH likewise from hi.
+// The adjoint (= inverse, each basis being orthonormal) runs the transposes coarse to fine:
+//   x[p] = sum over k with p - k even of h_k a[(p - k) / 2 mod m] + g_k d[(p - k) / 2 mod m].
+//
+// One launch per level.  The analysis launch of level 1 loads a tile of d once and runs all eight
+// bases on it; later levels read each basis's approximation from scratch.  The dual step of
+// eq. (anaylsespat) is fused into the analysis epilogue: u <- rho sat(u + coef w) + (1 - rho) u with
+// coef = sigma mu_s / sqrt(8).  The adjoint's finest level sums the eight bases in registers and
+// writes W_s^dagger u once.
+//
+// Filters are built on the host from Daubechies' construction: the roots y_k of
+// P_n(y) = sum_{k<n} C(n-1+k, k) y^k (Durand-Kerner iteration in long double), each mapped to the
+// root z inside the unit circle of z^2 - (2 - 4y) z + 1 = 0, and h proportional to
+// (1 + z)^n prod_k (z - z_k), scaled to sum sqrt(2) and ordered largest taps first.
+#include "common.h"
+
+#include <cmath>
+#include <complex>
+#include <vector>
+
+namespace mf {
+
+namespace {
+
+constexpr int TO = 32;                      // output coefficients (analysis) or pixels (adjoint) per tile side
+constexpr int FMAX = 2 * kUobBases;         // longest filter (8 vanishing moments: 16 taps)
+constexpr int SA = 2 * TO + FMAX - 2;       // input rows / columns of an analysis tile
+constexpr int CWS = TO / 2 + FMAX / 2 + 1;  // coefficient rows / columns of an adjoint tile
+
+__device__ __forceinline__ float satf_u(float u) { return fminf(1.f, fmaxf(-1.f, u)); }
+__device__ __forceinline__ int wrapm(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// ------------------------------------------------------------------ analysis (one level)
+// Grid: x = tiles of the level's m x m output, y = channel, z = basis (1 when the input is shared
+// by all bases, level 1).  MODE: UOB_DUAL (dual step into U), UOB_STORE (coefficients times scale
+// into out), UOB_ABS (FP64 sum of |coefficient| times scale into partial).
+template <int MODE>
+__global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
+  __shared__ float tin[SA][SA + 1];
+  __shared__ float lo[SA][TO + 1], hi[SA][TO + 1];
+  const int n = a.n, m = n >> 1;
+  const int to = m < TO ? m : TO;
+  const int tiles_x = (m + to - 1) / to;
+  const int R0 = (blockIdx.x / tiles_x) * to, C0 = (blockIdx.x % tiles_x) * to;
+  const int l = blockIdx.y;
+  const bool shared = a.shared_input != 0;
+  const int b_first = shared ? 0 : blockIdx.z, b_last = shared ? kUobBases : blockIdx.z + 1;
+  // input tile: rows 2R0 .. 2R0 + 2to + F - 3 (mod n), same for columns; with a shared input the
+  // longest filter sets the extent, otherwise the basis's own
+  const int Fl = shared ? FMAX : a.f.len[b_first];
+  const int S = 2 * to + Fl - 2;
+  double acc = 0.0;
+  auto load_tile = [&](const float* base) {
+    for (int i = threadIdx.x; i < S * S; i += 256) {
+      const int r = i / S, c = i - (i / S) * S;
+      tin[r][c] = base[(long long)wrapm(2 * R0 + r, n) * a.in_ld + wrapm(2 * C0 + c, n)];
+    }
+  };
+  if (shared) load_tile(a.in + (long long)l * a.in_cs);
+  for (int b = b_first; b < b_last; ++b) {
+    if (!shared) load_tile(a.in + (long long)l * a.in_cs + (long long)b * a.in_bs);
+    __syncthreads();
+    const int F = a.f.len[b];
+    const int Sr = 2 * to + F - 2;
+    // along the columns index: lo / hi for every loaded row
+    for (int i = threadIdx.x; i < Sr * to; i += 256) {
+      const int r = i / to, c = i - (i / to) * to;
+      float sl = 0.f, sh = 0.f;
+      for (int k = 0; k < F; ++k) {
+        const float v = tin[r][2 * c + k];
+        sl = fmaf(a.f.h[b][k], v, sl);
+        sh = fmaf(a.f.g[b][k], v, sh);
+      }
+      lo[r][c] = sl;
+      hi[r][c] = sh;
+    }
+    __syncthreads();
+    // along the rows index: the four subbands of each output coefficient of the tile
+    for (int i = threadIdx.x; i < to * to; i += 256) {
+      const int r = i / to, c = i - (i / to) * to;
+      const int gr = R0 + r, gc = C0 + c;
+      if (gr >= m || gc >= m) continue;
+      float ll = 0.f, lh = 0.f, hl = 0.f, hh = 0.f;
+      for (int k = 0; k < F; ++k) {
+        const float hk = a.f.h[b][k], gk = a.f.g[b][k];
+        const float vl = lo[2 * r + k][c], vh = hi[2 * r + k][c];
+        ll = fmaf(hk, vl, ll);
+        lh = fmaf(gk, vl, lh);
+        hl = fmaf(hk, vh, hl);
+        hh = fmaf(gk, vh, hh);
+      }
+      // pyramid positions in the N x N plane of basis b: HL (gr, m + gc), LH (m + gr, gc), HH (m + gr, m + gc)
+      const long long pb = (long long)l * a.u_cs + (long long)b * a.u_bs;
+      const long long pos[3] = {(long long)gr * a.N + m + gc, (long long)(m + gr) * a.N + gc,
+                                (long long)(m + gr) * a.N + m + gc};
+      const float w[3] = {hl, lh, hh};
+      const long long lpos = (long long)gr * a.N + gc;
+      if constexpr (MODE == UOB_DUAL) {
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+          float* up = a.U + pb + pos[s];
+          const float u = *up;
+          *up = a.rho * satf_u(u + a.coef * w[s]) + (1.f - a.rho) * u;
+        }
+        if (a.last) {
+          float* up = a.U + pb + lpos;
+          const float u = *up;
+          *up = a.rho * satf_u(u + a.coef * ll) + (1.f - a.rho) * u;
+        }
+      } else if constexpr (MODE == UOB_STORE) {
+        float* op = a.out + (long long)l * a.out_cs + (long long)b * a.out_bs;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) op[pos[s]] = a.scale * w[s];
+        if (a.last) op[lpos] = a.scale * ll;
+      } else {
+#pragma unroll
+        for (int s = 0; s < 3; ++s) acc += fabs((double)(a.scale * w[s]));
+        if (a.last) acc += fabs((double)(a.scale * ll));
+      }
+      if (!a.last)
+        a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)gr * m + gc] = ll;
+    }
+    __syncthreads();  // lo / hi (and an unshared input tile) are rewritten for the next basis
+  }
+  if constexpr (MODE == UOB_ABS) {
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0)
+      a.partial[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+  }
+}
+
+// ------------------------------------------------------------------ adjoint (one level)
+// Level with coefficient side m and output side n = 2m.  The approximation comes from in (row
+// stride in_ld; at the coarsest level, the LL block of the dual planes), the details from the
+// dual planes' level blocks.  ACCUM: the output level is the image; the eight bases are summed and
+// written once, times scale.  Otherwise the output is the next finer approximation of each basis
+// (grid z = basis).
+template <bool ACCUM>
+__global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
+  __shared__ float cf[4][CWS][CWS + 1];  // LL, LH, HL, HH coefficient tiles
+  __shared__ float lo[TO][CWS + 1], hi[TO][CWS + 1];
+  const int m = a.n >> 1, n = a.n;
+  const int to = n < TO ? n : TO;
+  const int tiles_x = (n + to - 1) / to;
+  const int R0 = (blockIdx.x / tiles_x) * to, C0 = (blockIdx.x % tiles_x) * to;
+  const int l = blockIdx.y;
+  // coefficient index range of the tile along each axis: i0 .. i0 + CWS - 1 (mod m)
+  const int i0 = (R0 - FMAX) / 2, j0 = (C0 - FMAX) / 2;
+  const int b_first = ACCUM ? 0 : blockIdx.z, b_last = ACCUM ? kUobBases : blockIdx.z + 1;
+  float accv[(TO * TO + 255) / 256];
+#pragma unroll
+  for (int q = 0; q < (TO * TO + 255) / 256; ++q) accv[q] = 0.f;
+  for (int b = b_first; b < b_last; ++b) {
+    const int F = a.f.len[b];
+    const float* U = a.U + (long long)l * a.u_cs + (long long)b * a.u_bs;
+    const float* LLs = a.in + (long long)l * a.in_cs + (long long)b * a.in_bs;
+    for (int i = threadIdx.x; i < 4 * CWS * CWS; i += 256) {
+      const int s = i / (CWS * CWS), rc = i - s * (CWS * CWS);
+      const int r = rc / CWS, c = rc - (rc / CWS) * CWS;
+      const int gr = wrapm(i0 + r, m), gc = wrapm(j0 + c, m);
+      float v;
+      if (s == 0) v = LLs[(long long)gr * a.in_ld + gc];
+      else if (s == 1) v = U[(long long)(m + gr) * a.N + gc];  // LH
+      else if (s == 2) v = U[(long long)gr * a.N + m + gc];    // HL
+      else v = U[(long long)(m + gr) * a.N + m + gc];          // HH
+      cf[s][r][c] = v;
+    }
+    __syncthreads();
+    // along the rows index: lo[r][c] from (LL, LH), hi[r][c] from (HL, HH), output rows R0 + r
+    for (int i = threadIdx.x; i < to * CWS; i += 256) {
+      const int r = i / CWS, c = i - (i / CWS) * CWS;
+      const int p = R0 + r;
+      float sl = 0.f, sh = 0.f;
+      for (int k = (p & 1); k < F; k += 2) {
+        const int ii = ((p - k) >> 1) - i0;  // in range: p - k >= R0 - FMAX + 1
+        const float hk = a.f.h[b][k], gk = a.f.g[b][k];
+        sl = fmaf(hk, cf[0][ii][c], fmaf(gk, cf[1][ii][c], sl));
+        sh = fmaf(hk, cf[2][ii][c], fmaf(gk, cf[3][ii][c], sh));
+      }
+      lo[r][c] = sl;
+      hi[r][c] = sh;
+    }
+    __syncthreads();
+    // along the columns index: the output pixels of the tile
+#pragma unroll
+    for (int q = 0; q < (TO * TO + 255) / 256; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i >= to * to) continue;
+      const int r = i / to, c = i - (i / to) * to;
+      const int p = C0 + c;
+      float x = 0.f;
+      for (int k = (p & 1); k < F; k += 2) {
+        const int jj = ((p - k) >> 1) - j0;
+        x = fmaf(a.f.h[b][k], lo[r][jj], fmaf(a.f.g[b][k], hi[r][jj], x));
+      }
+      if (ACCUM) {
+        accv[q] += x;
+      } else if (R0 + r < n && p < n) {
+        a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)(R0 + r) * n + p] = x;
+      }
+    }
+    __syncthreads();
+  }
+  if (ACCUM) {
+#pragma unroll
+    for (int q = 0; q < (TO * TO + 255) / 256; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i >= to * to) continue;
+      const int r = i / to, c = i - (i / to) * to;
+      if (R0 + r < n && C0 + c < n) a.out[(long long)l * a.out_cs + (long long)(R0 + r) * a.N + C0 + c] = a.scale * accv[q];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ filters (host)
+// Roots of sum_k c_k y^k (c_{deg} != 0) by Durand-Kerner iteration.
+std::vector<std::complex<long double>> poly_roots(const std::vector<long double>& c) {
+  using cd = std::complex<long double>;
+  const int deg = (int)c.size() - 1;
+  std::vector<cd> r(deg);
+  if (deg <= 0) return r;
+  for (int i = 0; i < deg; ++i) r[i] = std::pow(cd(0.4L, 0.9L), i);
+  auto eval = [&](cd y) {
+    cd s = 0;
+    for (int k = deg; k >= 0; --k) s = s * y + c[k];
+    return s / c[deg];
+  };
+  for (int it = 0; it < 2000; ++it) {
+    long double delta = 0;
+    for (int i = 0; i < deg; ++i) {
+      cd den = 1;
+      for (int j = 0; j < deg; ++j)
+        if (j != i) den *= (r[i] - r[j]);
+      const cd step = eval(r[i]) / den;
+      r[i] -= step;
+      delta = std::max(delta, std::abs(step));
+    }
+    if (delta < 1e-18L) break;
+  }
+  return r;
+}
+
+std::vector<double> daubechies_lowpass(int n) {
+  using cd = std::complex<long double>;
+  std::vector<long double> coef(n);
+  for (int k = 0; k < n; ++k) {
+    long double bin = 1;  // C(n - 1 + k, k)
+    for (int i = 1; i <= k; ++i) bin = bin * (n - 1 + i) / i;
+    coef[k] = bin;
+  }
+  std::vector<cd> poly{cd(1)};
+  auto mul = [&](cd c0, cd c1) {  // poly *= (c0 + c1 z)
+    std::vector<cd> out(poly.size() + 1, cd(0));
+    for (size_t i = 0; i < poly.size(); ++i) {
+      out[i] += poly[i] * c0;
+      out[i + 1] += poly[i] * c1;
+    }
+    poly.swap(out);
+  };
+  for (int i = 0; i < n; ++i) mul(cd(1), cd(1));
+  for (const cd& y : poly_roots(coef)) {
+    // z^2 - (2 - 4y) z + 1 = 0: the two roots are reciprocal; keep the one inside the unit circle
+    const cd bq = -(cd(2) - cd(4) * y);
+    const cd disc = std::sqrt(bq * bq - cd(4));
+    cd z1 = (-bq + disc) / cd(2), z2 = (-bq - disc) / cd(2);
+    const cd z = std::abs(z1) < std::abs(z2) ? z1 : z2;
+    mul(-z, cd(1));
+  }
+  std::vector<long double> h(poly.size());
+  long double sum = 0;
+  for (size_t i = 0; i < poly.size(); ++i) {
+    h[i] = poly[i].real();
+    sum += h[i];
+  }
+  std::vector<double> out(h.size());
+  for (size_t i = 0; i < h.size(); ++i) out[i] = (double)(h[i] * std::sqrt(2.0L) / sum);
+  if (std::fabs(out.front()) < std::fabs(out.back())) std::reverse(out.begin(), out.end());
+  return out;
+}
+
+}  // namespace
+
+UobFilters uob_filters() {
+  UobFilters f{};
+  for (int b = 0; b < kUobBases; ++b) {
+    const std::vector<double> h = daubechies_lowpass(b + 1);
+    const int F = (int)h.size();
+    f.len[b] = F;
+    for (int k = 0; k < F; ++k) {
+      f.h[b][k] = (float)h[k];
+      f.g[b][k] = (float)((k & 1) ? -h[F - 1 - k] : h[F - 1 - k]);
+    }
+  }
+  return f;
+}
+
+int uob_lowpass(int n, double* h, int len) {
+  if (n < 1 || n > kUobBases || !h || len < 2 * n) return set_error("uob_lowpass: bad arguments"), MUFFIN_EINVAL;
+  const std::vector<double> v = daubechies_lowpass(n);
+  for (int k = 0; k < 2 * n; ++k) h[k] = v[k];
+  return MUFFIN_OK;
+}
+
+int launch_uob_an(int mode, const UobLevelArgs& a, int nch, double* partial, int* nblocks_out, hipStream_t st) {
+  const int m = a.n >> 1;
+  const int to = m < TO ? m : TO;
+  const int tiles = ((m + to - 1) / to) * ((m + to - 1) / to);
+  const dim3 grid((unsigned)tiles, (unsigned)nch, a.shared_input ? 1u : (unsigned)kUobBases);
+  if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y * grid.z);
+  if (mode == UOB_ABS && (long long)grid.x * grid.y * grid.z > kMaxPartials)
+    return set_error("uob: too many blocks for the partial sums"), MUFFIN_EINVAL;
+  UobLevelArgs b = a;
+  b.partial = partial;
+  switch (mode) {
+    case UOB_DUAL: hipLaunchKernelGGL(k_uob_an<UOB_DUAL>, grid, dim3(256), 0, st, b); break;
+    case UOB_STORE: hipLaunchKernelGGL(k_uob_an<UOB_STORE>, grid, dim3(256), 0, st, b); break;
+    case UOB_ABS: hipLaunchKernelGGL(k_uob_an<UOB_ABS>, grid, dim3(256), 0, st, b); break;
+    default: return set_error("uob: bad mode"), MUFFIN_EINVAL;
+  }
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+int launch_uob_adj(bool accum, const UobLevelArgs& a, int nch, hipStream_t st) {
+  const int n = a.n;
+  const int to = n < TO ? n : TO;
+  const int tiles = ((n + to - 1) / to) * ((n + to - 1) / to);
+  const dim3 grid((unsigned)tiles, (unsigned)nch, accum ? 1u : (unsigned)kUobBases);
+  if (accum) hipLaunchKernelGGL(k_uob_adj<true>, grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_uob_adj<false>, grid, dim3(256), 0, st, a);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+}  // namespace mf

@@ -36,7 +36,7 @@ EXPORTS = [
     "muffin_cnn_free", "muffin_warm_start", "muffin_autotune", "muffin_batch_init", "muffin_batch_step",
     "muffin_batch_step_timed", "muffin_batch_objective", "muffin_batch_get_x", "muffin_batch_info",
     "muffin_batch_autotune", "muffin_batch_free", "muffin_step_monitored", "muffin_snr", "muffin_batch_snr",
-    "muffin_warm_input", "muffin_batch_set_x", "muffin_batch_warm_input",
+    "muffin_warm_input", "muffin_batch_set_x", "muffin_batch_warm_input", "muffin_uob_filter",
 ]
 
 
@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
     _fields_ = [
         ("N", ctypes.c_int32), ("L", ctypes.c_int32), ("J", ctypes.c_int32),
         ("iuwt_gen", ctypes.c_int32), ("penalize_coarse", ctypes.c_int32),
-        ("flags", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("prior", ctypes.c_int32),
         ("mu_s", ctypes.c_double), ("mu_lambda", ctypes.c_double),
         ("tau", ctypes.c_double), ("sigma", ctypes.c_double), ("rho", ctypes.c_double),
         ("chan_weight", ctypes.POINTER(ctypes.c_float)),
@@ -61,6 +61,7 @@ _lib.muffin_batch_snr.argtypes = [_vp, _i32, _vp, ctypes.c_int, ctypes.POINTER(_
 _lib.muffin_warm_input.argtypes = [_vp, _vp, ctypes.c_int]
 _lib.muffin_batch_set_x.argtypes = [_vp, _i32, _vp, ctypes.c_int]
 _lib.muffin_batch_warm_input.argtypes = [_vp, _i32, _vp, ctypes.c_int]
+_lib.muffin_uob_filter.argtypes = [_i32, ctypes.POINTER(_dbl), _i32]
 _lib.muffin_objective.argtypes = [_vp, ctypes.POINTER(_dbl)]
 _lib.muffin_info.argtypes = [_vp, ctypes.POINTER(_dbl)]
 for _n in ("muffin_set_x", "muffin_get_x", "muffin_get_u", "muffin_get_v"):
@@ -106,6 +107,8 @@ FLAG_SINGLE_SCALE = 1  # one IUWT launch per scale (same results as the fused pa
 FLAG_NO_FUSED_TAIL = 2  # last analysis pair and the next first adjoint pair as two launches (same results)
 FLAG_FUSED_TAIL = 4  # always fuse them (by default: when the cube is large enough, or as autotuned)
 STOP_OBJECTIVE, STOP_CHANGE = 0, 1  # stopping rules of muffin_solve
+PRIOR_IUWT, PRIOR_UOB = 0, 1  # spatial prior: the IUWT, or the union of the first 8 Daubechies bases
+UOB_BASES = 8
 
 
 class MuffinError(RuntimeError):
@@ -146,7 +149,7 @@ class Muffin:
 
     def __init__(self, dirty, psf, J: int, mu_s: float, mu_lambda: float, iuwt_gen: int = 2,
                  penalize_coarse: bool = True, tau: float = 0.0, sigma: float = 1.0,
-                 rho: float = 1.0, chan_weight=None, flags: int = 0):
+                 rho: float = 1.0, chan_weight=None, flags: int = 0, prior: int = PRIOR_IUWT):
         torch = _torch()
         dirty = torch.as_tensor(dirty, dtype=torch.float32).cuda().contiguous()
         psf = torch.as_tensor(psf, dtype=torch.float32).cuda().contiguous()
@@ -154,9 +157,10 @@ class Muffin:
         if N != N2 or tuple(psf.shape) != (L, N, N):
             raise ValueError("dirty and psf must both be [L][N][N]")
         self.N, self.L, self.J = N, L, J
+        self.planes = UOB_BASES if prior == PRIOR_UOB else J + 1  # dual planes per channel
         self._cw = None
         p = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=int(bool(penalize_coarse)),
-                   flags=flags, mu_s=mu_s, mu_lambda=mu_lambda, tau=tau, sigma=sigma, rho=rho)
+                   flags=flags, prior=prior, mu_s=mu_s, mu_lambda=mu_lambda, tau=tau, sigma=sigma, rho=rho)
         if chan_weight is not None:
             self._cw = np.ascontiguousarray(chan_weight, dtype=np.float32)
             if self._cw.shape != (L,):
@@ -251,7 +255,7 @@ class Muffin:
         return self._get(_lib.muffin_get_x, (self.L, self.N, self.N))
 
     def get_u(self):
-        return self._get(_lib.muffin_get_u, (self.L, self.J + 1, self.N, self.N))
+        return self._get(_lib.muffin_get_u, (self.L, self.planes, self.N, self.N))
 
     def get_v(self):
         return self._get(_lib.muffin_get_v, (self.L, self.N, self.N))
@@ -279,8 +283,8 @@ class Muffin:
     # ------------------------------------------------------------------ single operators
     def apply_op(self, op: int, x):
         torch = _torch()
-        L, N, J = self.L, self.N, self.J
-        cube, ucube = (L, N, N), (L, J + 1, N, N)
+        L, N = self.L, self.N
+        cube, ucube = (L, N, N), (L, self.planes, N, N)
         in_shape = ucube if op == OP_IUWT_ADJ else cube
         out_shape = ucube if op in (OP_IUWT, OP_IUWT_SCHED) else cube
         x = torch.as_tensor(x, dtype=torch.float32).cuda().contiguous()
@@ -400,7 +404,7 @@ class Batch:
     """Independent cubes of uneven sizes advanced together (muffin_batch_*)."""
 
     def __init__(self, cubes, J: int, mu_s: float, mu_lambda, iuwt_gen: int = 2, sigma: float = 1.0,
-                 rho: float = 1.0, tau=0.0, flags: int = 0):
+                 rho: float = 1.0, tau=0.0, flags: int = 0, prior: int = PRIOR_IUWT):
         """cubes: list of (dirty, psf) pairs of [L_i][N_i][N_i] arrays; mu_s, mu_lambda and tau may be
         scalars or per-cube sequences (cubes of different mu_s fall into different groups)."""
         torch = _torch()
@@ -419,7 +423,7 @@ class Batch:
             L, N, _ = d.shape
             self.shapes.append((L, N))
             self._keep += [d, f]
-            ps[i] = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=1, flags=flags, mu_s=mss[i],
+            ps[i] = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=1, flags=flags, prior=prior, mu_s=mss[i],
                            mu_lambda=mls[i], tau=taus[i], sigma=sigma, rho=rho)
             dptr[i] = d.data_ptr()
             fptr[i] = f.data_ptr()
@@ -517,6 +521,13 @@ def cnn_params_to_oracle(p: np.ndarray):
 
 def cnn_params_from_oracle(params) -> np.ndarray:
     return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
+
+
+def uob_filter(n: int) -> np.ndarray:
+    """The library's Daubechies scaling filter with n vanishing moments (host computation)."""
+    out = (_dbl * (2 * n))()
+    _check(_lib.muffin_uob_filter(n, out, 2 * n), "muffin_uob_filter")
+    return np.array(out[:])
 
 
 def last_error() -> str:

@@ -59,3 +59,21 @@ def test_null_arguments_are_rejected_without_a_gpu():
     assert lib.muffin_get_x(None, None, 0) == muffin.EINVAL
     assert lib.muffin_apply_op(None, 1, None, None) == muffin.EINVAL
     lib.muffin_free(None)
+
+
+def test_library_daubechies_filters_match_the_oracle_and_closed_forms():
+    """The library builds its union-of-bases filters on the host (Durand-Kerner roots in long double),
+    independently of the oracle (numpy companion-matrix roots): both agree, and with the published
+    Haar and db2 filters."""
+    import numpy as np
+    from oracle import uob
+    from paper_1602_08847_amd import muffin
+    for n in range(1, 9):
+        np.testing.assert_allclose(muffin.uob_filter(n), uob.daubechies_lowpass(n), atol=1e-12)
+    s3 = np.sqrt(3.0)
+    np.testing.assert_allclose(muffin.uob_filter(2), np.array([1 + s3, 3 + s3, 3 - s3, 1 - s3]) / (4 * np.sqrt(2.0)),
+                               atol=1e-15)
+    np.testing.assert_allclose(muffin.uob_filter(1), [2 ** -0.5, 2 ** -0.5], atol=1e-16)
+    h = (ctypes.c_double * 4)()
+    assert muffin._lib.muffin_uob_filter(9, h, 4) == muffin.EINVAL
+    assert muffin._lib.muffin_uob_filter(3, h, 4) == muffin.EINVAL  # buffer shorter than 6 taps

@@ -1,0 +1,103 @@
+"""The union-of-bases spatial prior (the first eight Daubechies bases, Sec. 3 and Sec. 4's comparison)
+on the GPU against the FP64 oracle (oracle/uob.py): W_s, its adjoint and W_s through the dual-step
+launches per operator, one iteration and 30-iteration trajectories, the objective, the step-size
+constants, the mu_lambda = 0 path and checkpoint/resume."""
+import numpy as np
+import pytest
+
+from oracle import muffin as om
+from oracle import uob
+from paper_1602_08847_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make(N, L, J, seed=0):
+    c = synth.make_cube(synth.CubeSpec(N=N, L=L, J=J, n_sources=max(2, N // 16), n_baselines=max(8, 2 * N), seed=seed))
+    return f32(c.dirty), f32(c.psf), c
+
+
+SHAPES = [(64, 8, 3), (32, 3, 5), (96, 5, 3), (128, 17, 4), (16, 2, 4), (256, 4, 5)]
+
+
+@pytest.mark.parametrize("N,L,J", SHAPES)
+def test_uob_operators(lib, N, L, J):
+    dirty, psf, _ = make(N, L, J)
+    with lib.Muffin(dirty, psf, J=J, mu_s=0.25, mu_lambda=3.0, prior=lib.PRIOR_UOB) as m:
+        r = np.random.default_rng(N + L)
+        x = f32(r.normal(size=(L, N, N)))
+        ref = np.stack([uob.uob(x[l], J) for l in range(L)])
+        got = m.apply_op(lib.OP_IUWT, x).cpu().numpy()
+        assert got.shape == (L, 8, N, N)
+        assert rel(got, ref) < TOL
+        assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+        u = f32(r.normal(size=(L, 8, N, N)))
+        ref = np.stack([uob.uob_adjoint(u[l], J) for l in range(L)])
+        assert rel(m.apply_op(lib.OP_IUWT_ADJ, u).cpu().numpy(), ref) < TOL
+        # W_s through the iteration's own dual-step launches on zero planes (saturation inactive)
+        xs = f32(0.05 * r.normal(size=(L, N, N)))
+        ref = np.stack([uob.uob(xs[l], J) for l in range(L)])
+        assert np.max(np.abs(ref)) < 1.0
+        assert rel(m.apply_op(lib.OP_IUWT_SCHED, xs).cpu().numpy(), ref) < TOL
+        info = m.info()
+        assert info["Ws2"] == 1.0
+        p = om.Problem(dirty=dirty, psf=psf, J=J, mu_s=0.25, mu_l=3.0, prior="uob")
+        assert info["tau"] == pytest.approx(om.step_sizes(p)[0], rel=1e-6)
+        # objective at a fixed positive X
+        xp = f32(np.abs(r.normal(size=(L, N, N))))
+        m.set_x(xp)
+        np.testing.assert_allclose(m.objective(), om.objective(p, xp), rtol=1e-6)
+
+
+@pytest.mark.parametrize("mu_l,rho", [(3.0, 1.0), (0.0, 1.0), (3.0, 0.7)])
+def test_uob_iterations_match_oracle(lib, mu_l, rho):
+    c = synth.make_cube(synth.WORKLOADS["cube64_L8_J3"])
+    dirty, psf = f32(c.dirty), f32(c.psf)
+    p = om.Problem(dirty=dirty, psf=psf, J=3, mu_s=0.25, mu_l=mu_l, prior="uob", rho=rho, sigma=4.0)
+    tau = om.step_sizes(p)[0]
+    x0 = f32(np.abs(np.random.default_rng(9).normal(size=dirty.shape)))
+    one = om.iterate(p, om.init_state(p, x0), tau)
+    st, _ = om.solve(p, 30, tau=tau)
+    with lib.Muffin(dirty, psf, J=3, mu_s=0.25, mu_lambda=mu_l, prior=lib.PRIOR_UOB, rho=rho, sigma=4.0,
+                    tau=tau) as m:
+        m.set_x(x0)
+        m.step(1)
+        assert rel(m.get_x().double().cpu().numpy(), one.X) < TOL
+        assert rel(m.get_u().double().cpu().numpy(), one.U) < TOL
+        if mu_l:
+            assert rel(m.get_v().double().cpu().numpy(), one.V) < TOL
+        m.set_x(np.zeros(dirty.shape))
+        m.step(30)
+        X, U = m.get_x().double().cpu().numpy(), m.get_u().double().cpu().numpy()
+        f = m.objective()[0]
+        assert rel(X, st.X) < 1e-4 and rel(U, st.U) < 1e-4
+        assert f == pytest.approx(om.objective(p, st.X)[0], rel=1e-4)
+        if rho == 1.0:  # the saturation is active in the dual step
+            assert 0 < np.mean(np.abs(st.U) >= 1.0 - 1e-12) < 1
+
+
+def test_uob_checkpoint_resume_is_bit_exact(lib):
+    dirty, psf, _ = make(64, 4, 3, seed=2)
+    with lib.Muffin(dirty, psf, J=3, mu_s=0.25, mu_lambda=3.0, prior=lib.PRIOR_UOB) as a, \
+            lib.Muffin(dirty, psf, J=3, mu_s=0.25, mu_lambda=3.0, prior=lib.PRIOR_UOB) as b:
+        a.step(7)
+        blob = a.get_state()
+        assert len(blob) > 4 * 64 * 64 * 4 * 10
+        a.step(5)
+        b.set_state(blob)
+        b.step(5)
+        np.testing.assert_array_equal(a.get_x().cpu().numpy(), b.get_x().cpu().numpy())
+        np.testing.assert_array_equal(a.get_u().cpu().numpy(), b.get_u().cpu().numpy())
+    with lib.Muffin(dirty, psf, J=3, mu_s=0.25, mu_lambda=3.0) as c:
+        with pytest.raises(lib.MuffinError):
+            c.set_state(blob)  # written by the other prior
