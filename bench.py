@@ -94,43 +94,89 @@ PROFILE_SLOT = {
 
 
 # HBM bytes per launch of the hot kernels, from two rocprofv3 --pmc runs of this script (FETCH_SIZE,
-# then WRITE_SIZE, KiB per dispatch) on the named workload: the mean over the launches of one
-# iteration, times the factor a 1 GiB elementwise copy (--calib-copy) gives for the same counter.
-# An entry holds only for the kernel sources it was taken on (hash below); otherwise traffic is null.
+# then WRITE_SIZE, KiB per dispatch) on the named workload: the mean over the kernel's launches,
+# times the factor a 1 GiB elementwise copy (--calib-copy) gives for the same counter.  An entry
+# holds only for the source files that define the kernel as they were when it was taken (hash
+# below); otherwise traffic is null.
 MEASURED_TRAFFIC = {
     "k_triple_an<RS, false> (three scales of analysis + spatial dual steps)": {
         "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "a12d85cecaee1fee",
-        "fetch_kib": 2201708.6,
+        "sources": [
+            "paper_1602_08847_amd/csrc/iuwt.hip"
+        ],
+        "sha256": "d726fcad644f2251",
+        "fetch_kib": 2201709.2,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     },
     "k_fused<RS> (last analysis pair + next iteration's first adjoint pair)": {
         "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "a12d85cecaee1fee",
-        "fetch_kib": 2857076.1,
+        "sources": [
+            "paper_1602_08847_amd/csrc/iuwt.hip"
+        ],
+        "sha256": "d726fcad644f2251",
+        "fetch_kib": 2857079.4,
         "write_kib": 4194304.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     },
     "k_triple_adj<RS> (three adjoint Horner steps)": {
         "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/iuwt.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "a12d85cecaee1fee",
-        "fetch_kib": 2191529.2,
+        "sources": [
+            "paper_1602_08847_amd/csrc/iuwt.hip"
+        ],
+        "sha256": "d726fcad644f2251",
+        "fetch_kib": 2191459.3,
         "write_kib": 1048576.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     },
     "k_spectral_fft (fused spectral step)": {
         "workload": "cube1024_L256_J5",
-        "sources": ["paper_1602_08847_amd/csrc/spectral.hip", "paper_1602_08847_amd/csrc/common.h", "paper_1602_08847_amd/csrc/fft_core.h", "paper_1602_08847_amd/csrc/api.hip"],
-        "sha256": "019ba098b55c9d08",
-        "fetch_kib": 1573067.9,
-        "write_kib": 3145835.8,
+        "sources": [
+            "paper_1602_08847_amd/csrc/spectral.hip",
+            "paper_1602_08847_amd/csrc/fft_core.h"
+        ],
+        "sha256": "f86660084828d359",
+        "fetch_kib": 1573105.4,
+        "write_kib": 3145823.8,
+        "fetch_factor": 2.0,
+        "write_factor": 1.0
+    },
+    "k_rows_r2c": {
+        "workload": "cube1024_L256_J5",
+        "sources": [
+            "paper_1602_08847_amd/csrc/fft.hip",
+            "paper_1602_08847_amd/csrc/fft_core.h"
+        ],
+        "sha256": "3870dae3d2d209d9",
+        "fetch_kib": 524380.0,
+        "write_kib": 1056768.4,
+        "fetch_factor": 2.0,
+        "write_factor": 1.0
+    },
+    "k_cols<REAL>": {
+        "workload": "cube1024_L256_J5",
+        "sources": [
+            "paper_1602_08847_amd/csrc/fft.hip",
+            "paper_1602_08847_amd/csrc/fft_core.h"
+        ],
+        "sha256": "3870dae3d2d209d9",
+        "fetch_kib": 831829.1,
+        "write_kib": 1131520.0,
+        "fetch_factor": 2.0,
+        "write_factor": 1.0
+    },
+    "k_rows_c2r<GRAD>": {
+        "workload": "cube1024_L256_J5",
+        "sources": [
+            "paper_1602_08847_amd/csrc/fft.hip",
+            "paper_1602_08847_amd/csrc/fft_core.h"
+        ],
+        "sha256": "3870dae3d2d209d9",
+        "fetch_kib": 1588457.4,
+        "write_kib": 1048576.0,
         "fetch_factor": 2.0,
         "write_factor": 1.0
     }
