@@ -25,113 +25,202 @@
 
 #include <cmath>
 #include <complex>
+#include <type_traits>
 #include <vector>
 
 namespace mf {
 
 namespace {
 
-constexpr int TO = 32;                      // output coefficients (analysis) or pixels (adjoint) per tile side
+constexpr int TO = 32;                      // output coefficients per analysis tile side
 constexpr int FMAX = 2 * kUobBases;         // longest filter (8 vanishing moments: 16 taps)
 constexpr int SA = 2 * TO + FMAX - 2;       // input rows / columns of an analysis tile
-constexpr int CWS = TO / 2 + FMAX / 2 + 1;  // coefficient rows / columns of an adjoint tile
+constexpr int TA = 64;                      // output pixels per adjoint tile side
+constexpr int CWA = TA / 2 + FMAX / 2 + 1;  // coefficient rows / columns of an adjoint tile
+constexpr int NOUT = (TO * TO + 255) / 256; // analysis outputs per thread
+constexpr int NPX = (TA * TA + 255) / 256;  // adjoint output pixels per thread
+constexpr int LB = 8;                       // global loads a thread keeps in flight while staging a tile
 
 __device__ __forceinline__ float satf_u(float u) { return fminf(1.f, fmaxf(-1.f, u)); }
-__device__ __forceinline__ int wrapm(int v, int n) {
+// v mod n in [0, n) for any v
+__device__ __forceinline__ int wrap_any(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
+}
+// v mod n for v in [-n, 2n): two selects, no branch
+__device__ __forceinline__ int wrap_once(int v, int n) {
+  v += v < 0 ? n : 0;
+  return v >= n ? v - n : v;
+}
+// i / d for 0 <= i < 2^20 and 1 <= d <= 2^10 through the float reciprocal of d: the quotient's
+// error stays below 0.5 / d, so rounding i + 1/2 down gives the exact floor
+__device__ __forceinline__ int div_small(int i, float inv_d) { return (int)(((float)i + 0.5f) * inv_d); }
+
+// Stage `total` floats into LDS, LB loads in flight per thread: addr(i) gives the global address
+// of entry i, put(i, v) stores it.  Lanes past the end load entry total - 1 and discard it.
+template <class Addr, class Put>
+__device__ __forceinline__ void stage(int tid, int total, Addr addr, Put put) {
+  for (int base = tid; base < total; base += 256 * LB) {
+    float v[LB];
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int i = base + 256 * q;
+      v[q] = *addr(i < total ? i : total - 1);
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int i = base + 256 * q;
+      if (i < total) put(i, v[q]);
+    }
+  }
+}
+
+// Calls fn with the filter length F (2, 4, ..., 16) as a compile-time constant, so that the tap
+// loops unroll and the taps of the block's basis sit in scalar registers.
+template <class Fn>
+__device__ __forceinline__ void with_len(int F, Fn&& fn) {
+  switch (F) {
+    case 2: fn(std::integral_constant<int, 2>{}); break;
+    case 4: fn(std::integral_constant<int, 4>{}); break;
+    case 6: fn(std::integral_constant<int, 6>{}); break;
+    case 8: fn(std::integral_constant<int, 8>{}); break;
+    case 10: fn(std::integral_constant<int, 10>{}); break;
+    case 12: fn(std::integral_constant<int, 12>{}); break;
+    case 14: fn(std::integral_constant<int, 14>{}); break;
+    default: fn(std::integral_constant<int, 16>{}); break;
+  }
 }
 
 // ------------------------------------------------------------------ analysis (one level)
 // Grid: x = tiles of the level's m x m output, y = channel, z = basis (1 when the input is shared
 // by all bases, level 1).  MODE: UOB_DUAL (dual step into U), UOB_STORE (coefficients times scale
-// into out), UOB_ABS (FP64 sum of |coefficient| times scale into partial).
+// into out), UOB_ABS (FP64 sum of |coefficient| times scale into partial).  The dual-plane entries
+// a thread updates are fetched before the basis's filtering starts.
 template <int MODE>
 __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
   __shared__ float tin[SA][SA + 1];
   __shared__ float lo[SA][TO + 1], hi[SA][TO + 1];
   const int n = a.n, m = n >> 1;
   const int to = m < TO ? m : TO;
+  const float inv_to = 1.f / (float)to;
   const int tiles_x = (m + to - 1) / to;
   const int R0 = (blockIdx.x / tiles_x) * to, C0 = (blockIdx.x % tiles_x) * to;
   const int l = blockIdx.y;
   const bool shared = a.shared_input != 0;
   const int b_first = shared ? 0 : blockIdx.z, b_last = shared ? kUobBases : blockIdx.z + 1;
   // input tile: rows 2R0 .. 2R0 + 2to + F - 3 (mod n), same for columns; with a shared input the
-  // longest filter sets the extent, otherwise the basis's own
+  // longest filter sets the extent, otherwise the basis's own.  2R0 + S - 1 < 2n once n >= SA.
   const int Fl = shared ? FMAX : a.f.len[b_first];
   const int S = 2 * to + Fl - 2;
+  const float inv_S = 1.f / (float)S;
+  const bool one_wrap = n >= SA;
   double acc = 0.0;
   auto load_tile = [&](const float* base) {
-    for (int i = threadIdx.x; i < S * S; i += 256) {
-      const int r = i / S, c = i - (i / S) * S;
-      tin[r][c] = base[(long long)wrapm(2 * R0 + r, n) * a.in_ld + wrapm(2 * C0 + c, n)];
-    }
+    auto put = [&](int i, float v) {
+      const int r = div_small(i, inv_S);
+      tin[r][i - r * S] = v;
+    };
+    if (one_wrap)
+      stage(threadIdx.x, S * S, [&](int i) {
+        const int r = div_small(i, inv_S);
+        return base + (long long)wrap_once(2 * R0 + r, n) * a.in_ld + wrap_once(2 * C0 + i - r * S, n);
+      }, put);
+    else
+      stage(threadIdx.x, S * S, [&](int i) {
+        const int r = div_small(i, inv_S);
+        return base + (long long)wrap_any(2 * R0 + r, n) * a.in_ld + wrap_any(2 * C0 + i - r * S, n);
+      }, put);
   };
   if (shared) load_tile(a.in + (long long)l * a.in_cs);
+#pragma unroll 1
   for (int b = b_first; b < b_last; ++b) {
+    // the thread index, opaque to the compiler inside the basis loop: the addresses are
+    // recomputed per basis instead of being hoisted out of the loop into registers
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     if (!shared) load_tile(a.in + (long long)l * a.in_cs + (long long)b * a.in_bs);
-    __syncthreads();
-    const int F = a.f.len[b];
-    const int Sr = 2 * to + F - 2;
-    // along the columns index: lo / hi for every loaded row
-    for (int i = threadIdx.x; i < Sr * to; i += 256) {
-      const int r = i / to, c = i - (i / to) * to;
-      float sl = 0.f, sh = 0.f;
-      for (int k = 0; k < F; ++k) {
-        const float v = tin[r][2 * c + k];
-        sl = fmaf(a.f.h[b][k], v, sl);
-        sh = fmaf(a.f.g[b][k], v, sh);
+    const long long pb = (long long)l * a.u_cs + (long long)b * a.u_bs;
+    float uold[NOUT][4];
+    if constexpr (MODE == UOB_DUAL) {
+#pragma unroll
+      for (int q = 0; q < NOUT; ++q) {
+        const int i = tid + 256 * q;
+        const int r = div_small(i, inv_to), c = i - r * to;
+        const bool ok = i < to * to && R0 + r < m && C0 + c < m;
+        const int gr = ok ? R0 + r : 0, gc = ok ? C0 + c : 0;
+        const float* U = a.U + pb;
+        uold[q][0] = U[(long long)gr * a.N + m + gc];        // HL
+        uold[q][1] = U[(long long)(m + gr) * a.N + gc];      // LH
+        uold[q][2] = U[(long long)(m + gr) * a.N + m + gc];  // HH
+        uold[q][3] = a.last ? U[(long long)gr * a.N + gc] : 0.f;  // LL at the coarsest level
       }
-      lo[r][c] = sl;
-      hi[r][c] = sh;
     }
     __syncthreads();
-    // along the rows index: the four subbands of each output coefficient of the tile
-    for (int i = threadIdx.x; i < to * to; i += 256) {
-      const int r = i / to, c = i - (i / to) * to;
-      const int gr = R0 + r, gc = C0 + c;
-      if (gr >= m || gc >= m) continue;
-      float ll = 0.f, lh = 0.f, hl = 0.f, hh = 0.f;
-      for (int k = 0; k < F; ++k) {
-        const float hk = a.f.h[b][k], gk = a.f.g[b][k];
-        const float vl = lo[2 * r + k][c], vh = hi[2 * r + k][c];
-        ll = fmaf(hk, vl, ll);
-        lh = fmaf(gk, vl, lh);
-        hl = fmaf(hk, vh, hl);
-        hh = fmaf(gk, vh, hh);
-      }
-      // pyramid positions in the N x N plane of basis b: HL (gr, m + gc), LH (m + gr, gc), HH (m + gr, m + gc)
-      const long long pb = (long long)l * a.u_cs + (long long)b * a.u_bs;
-      const long long pos[3] = {(long long)gr * a.N + m + gc, (long long)(m + gr) * a.N + gc,
-                                (long long)(m + gr) * a.N + m + gc};
-      const float w[3] = {hl, lh, hh};
-      const long long lpos = (long long)gr * a.N + gc;
-      if constexpr (MODE == UOB_DUAL) {
+    with_len(a.f.len[b], [&](auto Fc) {
+      constexpr int F = decltype(Fc)::value;
+      float hk[F], gk[F];
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
-          float* up = a.U + pb + pos[s];
-          const float u = *up;
-          *up = a.rho * satf_u(u + a.coef * w[s]) + (1.f - a.rho) * u;
+      for (int k = 0; k < F; ++k) hk[k] = a.f.h[b][k], gk[k] = a.f.g[b][k];
+      const int Sr = 2 * to + F - 2;
+      // along the columns index: lo / hi for every loaded row
+      for (int i = tid; i < Sr * to; i += 256) {
+        const int r = div_small(i, inv_to), c = i - r * to;
+        float sl = 0.f, sh = 0.f;
+#pragma unroll
+        for (int k = 0; k < F; ++k) {
+          const float v = tin[r][2 * c + k];
+          sl = fmaf(hk[k], v, sl);
+          sh = fmaf(gk[k], v, sh);
         }
-        if (a.last) {
-          float* up = a.U + pb + lpos;
-          const float u = *up;
-          *up = a.rho * satf_u(u + a.coef * ll) + (1.f - a.rho) * u;
-        }
-      } else if constexpr (MODE == UOB_STORE) {
-        float* op = a.out + (long long)l * a.out_cs + (long long)b * a.out_bs;
-#pragma unroll
-        for (int s = 0; s < 3; ++s) op[pos[s]] = a.scale * w[s];
-        if (a.last) op[lpos] = a.scale * ll;
-      } else {
-#pragma unroll
-        for (int s = 0; s < 3; ++s) acc += fabs((double)(a.scale * w[s]));
-        if (a.last) acc += fabs((double)(a.scale * ll));
+        lo[r][c] = sl;
+        hi[r][c] = sh;
       }
-      if (!a.last)
-        a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)gr * m + gc] = ll;
-    }
+      __syncthreads();
+      // along the rows index: the four subbands of each output coefficient of the tile
+#pragma unroll
+      for (int q = 0; q < NOUT; ++q) {
+        const int i = tid + 256 * q;
+        const int r = div_small(i, inv_to), c = i - r * to;
+        const int gr = R0 + r, gc = C0 + c;
+        if (i >= to * to || gr >= m || gc >= m) continue;
+        float ll = 0.f, lh = 0.f, hl = 0.f, hh = 0.f;
+#pragma unroll
+        for (int k = 0; k < F; ++k) {
+          const float vl = lo[2 * r + k][c], vh = hi[2 * r + k][c];
+          ll = fmaf(hk[k], vl, ll);
+          lh = fmaf(gk[k], vl, lh);
+          hl = fmaf(hk[k], vh, hl);
+          hh = fmaf(gk[k], vh, hh);
+        }
+        // pyramid positions in the N x N plane of basis b: HL (gr, m + gc), LH (m + gr, gc), HH (m + gr, m + gc)
+        const long long pos[3] = {(long long)gr * a.N + m + gc, (long long)(m + gr) * a.N + gc,
+                                  (long long)(m + gr) * a.N + m + gc};
+        const float w[3] = {hl, lh, hh};
+        const long long lpos = (long long)gr * a.N + gc;
+        if constexpr (MODE == UOB_DUAL) {
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            const float u = uold[q][t];
+            a.U[pb + pos[t]] = a.rho * satf_u(u + a.coef * w[t]) + (1.f - a.rho) * u;
+          }
+          if (a.last) {
+            const float u = uold[q][3];
+            a.U[pb + lpos] = a.rho * satf_u(u + a.coef * ll) + (1.f - a.rho) * u;
+          }
+        } else if constexpr (MODE == UOB_STORE) {
+          float* op = a.out + (long long)l * a.out_cs + (long long)b * a.out_bs;
+#pragma unroll
+          for (int t = 0; t < 3; ++t) op[pos[t]] = a.scale * w[t];
+          if (a.last) op[lpos] = a.scale * ll;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 3; ++t) acc += fabs((double)(a.scale * w[t]));
+          if (a.last) acc += fabs((double)(a.scale * ll));
+        }
+        if (!a.last)
+          a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)gr * m + gc] = ll;
+      }
+    });
     __syncthreads();  // lo / hi (and an unshared input tile) are rewritten for the next basis
   }
   if constexpr (MODE == UOB_ABS) {
@@ -148,83 +237,116 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
 }
 
 // ------------------------------------------------------------------ adjoint (one level)
-// Level with coefficient side m and output side n = 2m.  The approximation comes from in (row
-// stride in_ld; at the coarsest level, the LL block of the dual planes), the details from the
-// dual planes' level blocks.  ACCUM: the output level is the image; the eight bases are summed and
-// written once, times scale.  Otherwise the output is the next finer approximation of each basis
-// (grid z = basis).
+// Level with coefficient side m and output side n = 2m, tiles of TA x TA output pixels.  The
+// approximation comes from in (row stride in_ld; at the coarsest level, the LL block of the dual
+// planes), the details from the dual planes' level blocks.  ACCUM: the output level is the image;
+// the eight bases are summed in registers and written once, times scale.  Otherwise the output is
+// the next finer approximation of each basis (grid z = basis).
+//
+// Output pixel p takes the taps k of its own parity: coefficient (p - k) / 2 = (p - par) / 2 - kk
+// for k = 2 kk + par, par = p mod 2.
 template <bool ACCUM>
 __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
-  __shared__ float cf[4][CWS][CWS + 1];  // LL, LH, HL, HH coefficient tiles
-  __shared__ float lo[TO][CWS + 1], hi[TO][CWS + 1];
+  __shared__ float cf[4][CWA][CWA + 1];  // LL, LH, HL, HH coefficient tiles
+  __shared__ float lo[TA][CWA + 1], hi[TA][CWA + 1];
   const int m = a.n >> 1, n = a.n;
-  const int to = n < TO ? n : TO;
+  const int to = n < TA ? n : TA;
+  const float inv_to = 1.f / (float)to;
   const int tiles_x = (n + to - 1) / to;
   const int R0 = (blockIdx.x / tiles_x) * to, C0 = (blockIdx.x % tiles_x) * to;
   const int l = blockIdx.y;
-  // coefficient index range of the tile along each axis: i0 .. i0 + CWS - 1 (mod m)
-  const int i0 = (R0 - FMAX) / 2, j0 = (C0 - FMAX) / 2;
+  // coefficient index range of the tile along each axis: i0 .. i0 + CWA - 1 (mod m), with
+  // i0 >= -FMAX / 2 and i0 + CWA - 1 <= m once m >= CWA
+  const int i0t = (R0 - FMAX) / 2, j0t = (C0 - FMAX) / 2;
+  const bool one_wrap = m >= CWA;
   const int b_first = ACCUM ? 0 : blockIdx.z, b_last = ACCUM ? kUobBases : blockIdx.z + 1;
-  float accv[(TO * TO + 255) / 256];
+  float accv[NPX];
 #pragma unroll
-  for (int q = 0; q < (TO * TO + 255) / 256; ++q) accv[q] = 0.f;
+  for (int q = 0; q < NPX; ++q) accv[q] = 0.f;
+#pragma unroll 1
   for (int b = b_first; b < b_last; ++b) {
-    const int F = a.f.len[b];
     const float* U = a.U + (long long)l * a.u_cs + (long long)b * a.u_bs;
     const float* LLs = a.in + (long long)l * a.in_cs + (long long)b * a.in_bs;
-    for (int i = threadIdx.x; i < 4 * CWS * CWS; i += 256) {
-      const int s = i / (CWS * CWS), rc = i - s * (CWS * CWS);
-      const int r = rc / CWS, c = rc - (rc / CWS) * CWS;
-      const int gr = wrapm(i0 + r, m), gc = wrapm(j0 + c, m);
-      float v;
-      if (s == 0) v = LLs[(long long)gr * a.in_ld + gc];
-      else if (s == 1) v = U[(long long)(m + gr) * a.N + gc];  // LH
-      else if (s == 2) v = U[(long long)gr * a.N + m + gc];    // HL
-      else v = U[(long long)(m + gr) * a.N + m + gc];          // HH
-      cf[s][r][c] = v;
-    }
+    // the tile origin and the thread index, opaque to the compiler inside the basis loop: the
+    // addresses are recomputed per basis instead of being hoisted out of the loop into registers
+    int i0 = i0t, j0 = j0t, tid = threadIdx.x;
+    asm volatile("" : "+s"(i0), "+s"(j0), "+v"(tid));
+    auto put = [&](int i, float v) {
+      const int s = i / (CWA * CWA), rc = i - s * (CWA * CWA);
+      const int r = rc / CWA;
+      cf[s][r][rc - r * CWA] = v;
+    };
+    auto src = [&](int i, int gr, int gc) {
+      const int s = i / (CWA * CWA);
+      return s == 0 ? LLs + (long long)gr * a.in_ld + gc
+           : s == 1 ? U + (long long)(m + gr) * a.N + gc         // LH
+           : s == 2 ? U + (long long)gr * a.N + m + gc           // HL
+                    : U + (long long)(m + gr) * a.N + m + gc;    // HH
+    };
+    if (one_wrap)
+      stage(tid, 4 * CWA * CWA, [&](int i) {
+        const int rc = i % (CWA * CWA), r = rc / CWA;
+        return src(i, wrap_once(i0 + r, m), wrap_once(j0 + rc - r * CWA, m));
+      }, put);
+    else
+      stage(tid, 4 * CWA * CWA, [&](int i) {
+        const int rc = i % (CWA * CWA), r = rc / CWA;
+        return src(i, wrap_any(i0 + r, m), wrap_any(j0 + rc - r * CWA, m));
+      }, put);
     __syncthreads();
-    // along the rows index: lo[r][c] from (LL, LH), hi[r][c] from (HL, HH), output rows R0 + r
-    for (int i = threadIdx.x; i < to * CWS; i += 256) {
-      const int r = i / CWS, c = i - (i / CWS) * CWS;
-      const int p = R0 + r;
-      float sl = 0.f, sh = 0.f;
-      for (int k = (p & 1); k < F; k += 2) {
-        const int ii = ((p - k) >> 1) - i0;  // in range: p - k >= R0 - FMAX + 1
-        const float hk = a.f.h[b][k], gk = a.f.g[b][k];
-        sl = fmaf(hk, cf[0][ii][c], fmaf(gk, cf[1][ii][c], sl));
-        sh = fmaf(hk, cf[2][ii][c], fmaf(gk, cf[3][ii][c], sh));
-      }
-      lo[r][c] = sl;
-      hi[r][c] = sh;
-    }
-    __syncthreads();
-    // along the columns index: the output pixels of the tile
+    with_len(a.f.len[b], [&](auto Fc) {
+      constexpr int H = decltype(Fc)::value / 2;
+      float he[H], ho[H], ge[H], go[H];  // taps of even and odd index
 #pragma unroll
-    for (int q = 0; q < (TO * TO + 255) / 256; ++q) {
-      const int i = threadIdx.x + 256 * q;
-      if (i >= to * to) continue;
-      const int r = i / to, c = i - (i / to) * to;
-      const int p = C0 + c;
-      float x = 0.f;
-      for (int k = (p & 1); k < F; k += 2) {
-        const int jj = ((p - k) >> 1) - j0;
-        x = fmaf(a.f.h[b][k], lo[r][jj], fmaf(a.f.g[b][k], hi[r][jj], x));
+      for (int kk = 0; kk < H; ++kk) {
+        he[kk] = a.f.h[b][2 * kk], ho[kk] = a.f.h[b][2 * kk + 1];
+        ge[kk] = a.f.g[b][2 * kk], go[kk] = a.f.g[b][2 * kk + 1];
       }
-      if (ACCUM) {
-        accv[q] += x;
-      } else if (R0 + r < n && p < n) {
-        a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)(R0 + r) * n + p] = x;
+      // along the rows index: lo[r][c] from (LL, LH), hi[r][c] from (HL, HH), output rows R0 + r
+      for (int i = tid; i < to * CWA; i += 256) {
+        const int r = i / CWA, c = i - (i / CWA) * CWA;
+        const int p = R0 + r, par = p & 1;
+        const int ib = ((p - par) >> 1) - i0;  // coefficient row of kk = 0; ib - H + 1 >= 0
+        float sl = 0.f, sh = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < H; ++kk) {
+          const float h = par ? ho[kk] : he[kk], g = par ? go[kk] : ge[kk];
+          sl = fmaf(h, cf[0][ib - kk][c], fmaf(g, cf[1][ib - kk][c], sl));
+          sh = fmaf(h, cf[2][ib - kk][c], fmaf(g, cf[3][ib - kk][c], sh));
+        }
+        lo[r][c] = sl;
+        hi[r][c] = sh;
       }
-    }
+      __syncthreads();
+      // along the columns index: the output pixels of the tile
+#pragma unroll
+      for (int q = 0; q < NPX; ++q) {
+        const int i = tid + 256 * q;
+        if (i >= to * to) continue;
+        const int r = div_small(i, inv_to), c = i - r * to;
+        const int p = C0 + c, par = p & 1;
+        const int jb = ((p - par) >> 1) - j0;
+        float x = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < H; ++kk) {
+          const float h = par ? ho[kk] : he[kk], g = par ? go[kk] : ge[kk];
+          x = fmaf(h, lo[r][jb - kk], fmaf(g, hi[r][jb - kk], x));
+        }
+        if (ACCUM) {
+          accv[q] += x;
+        } else if (R0 + r < n && p < n) {
+          a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)(R0 + r) * n + p] = x;
+        }
+      }
+    });
     __syncthreads();
   }
   if (ACCUM) {
 #pragma unroll
-    for (int q = 0; q < (TO * TO + 255) / 256; ++q) {
+    for (int q = 0; q < NPX; ++q) {
       const int i = threadIdx.x + 256 * q;
       if (i >= to * to) continue;
-      const int r = i / to, c = i - (i / to) * to;
+      const int r = div_small(i, inv_to), c = i - r * to;
       if (R0 + r < n && C0 + c < n) a.out[(long long)l * a.out_cs + (long long)(R0 + r) * a.N + C0 + c] = a.scale * accv[q];
     }
   }
@@ -341,7 +463,7 @@ int launch_uob_an(int mode, const UobLevelArgs& a, int nch, double* partial, int
 
 int launch_uob_adj(bool accum, const UobLevelArgs& a, int nch, hipStream_t st) {
   const int n = a.n;
-  const int to = n < TO ? n : TO;
+  const int to = n < TA ? n : TA;
   const int tiles = ((n + to - 1) / to) * ((n + to - 1) / to);
   const dim3 grid((unsigned)tiles, (unsigned)nch, accum ? 1u : (unsigned)kUobBases);
   if (accum) hipLaunchKernelGGL(k_uob_adj<true>, grid, dim3(256), 0, st, a);
