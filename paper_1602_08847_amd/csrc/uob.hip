@@ -38,8 +38,12 @@ constexpr int SA = 2 * TO + FMAX - 2;       // input rows / columns of an analys
 constexpr int TA = 64;                      // output pixels per adjoint tile side
 constexpr int CWA = TA / 2 + FMAX / 2 + 1;  // coefficient rows / columns of an adjoint tile
 constexpr int NOUT = (TO * TO + 255) / 256; // analysis outputs per thread
-constexpr int NPX = (TA * TA + 255) / 256;  // adjoint output pixels per thread
+constexpr int NPP = (TA * TA / 2 + 255) / 256;  // adjoint output pixel pairs per thread
 constexpr int LB = 8;                       // global loads a thread keeps in flight while staging a tile
+
+// Workgroup barrier for LDS traffic: waits for this wave's LDS operations only, so that global loads
+// issued ahead (the next basis's data) stay in flight across it.
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 __device__ __forceinline__ float satf_u(float u) { return fminf(1.f, fmaxf(-1.f, u)); }
 // v mod n in [0, n) for any v
@@ -94,8 +98,7 @@ __device__ __forceinline__ void with_len(int F, Fn&& fn) {
 // ------------------------------------------------------------------ analysis (one level)
 // Grid: x = tiles of the level's m x m output, y = channel, z = basis (1 when the input is shared
 // by all bases, level 1).  MODE: UOB_DUAL (dual step into U), UOB_STORE (coefficients times scale
-// into out), UOB_ABS (FP64 sum of |coefficient| times scale into partial).  The dual-plane entries
-// a thread updates are fetched before the basis's filtering starts.
+// into out), UOB_ABS (FP64 sum of |coefficient| times scale into partial).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
   __shared__ float tin[SA][SA + 1];
@@ -131,6 +134,24 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
         return base + (long long)wrap_any(2 * R0 + r, n) * a.in_ld + wrap_any(2 * C0 + i - r * S, n);
       }, put);
   };
+  // the dual-plane entries a thread updates (HL, LH, HH, and LL at the coarsest level), one basis
+  // ahead of the filtering
+  float unext[NOUT][4];
+  auto fetch_u = [&](int b, int tid) {
+    const float* U = a.U + (long long)l * a.u_cs + (long long)b * a.u_bs;
+#pragma unroll
+    for (int q = 0; q < NOUT; ++q) {
+      const int i = tid + 256 * q;
+      const int r = div_small(i, inv_to), c = i - r * to;
+      const bool ok = i < to * to && R0 + r < m && C0 + c < m;
+      const int gr = ok ? R0 + r : 0, gc = ok ? C0 + c : 0;
+      unext[q][0] = U[(long long)gr * a.N + m + gc];
+      unext[q][1] = U[(long long)(m + gr) * a.N + gc];
+      unext[q][2] = U[(long long)(m + gr) * a.N + m + gc];
+      unext[q][3] = a.last ? U[(long long)gr * a.N + gc] : 0.f;
+    }
+  };
+  if constexpr (MODE == UOB_DUAL) fetch_u(b_first, threadIdx.x);  // in flight with the input tile
   if (shared) load_tile(a.in + (long long)l * a.in_cs);
 #pragma unroll 1
   for (int b = b_first; b < b_last; ++b) {
@@ -140,22 +161,15 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
     asm volatile("" : "+v"(tid));
     if (!shared) load_tile(a.in + (long long)l * a.in_cs + (long long)b * a.in_bs);
     const long long pb = (long long)l * a.u_cs + (long long)b * a.u_bs;
-    float uold[NOUT][4];
+    float uold[NOUT][4];  // this basis's dual entries; the next basis's are fetched into unext
     if constexpr (MODE == UOB_DUAL) {
 #pragma unroll
-      for (int q = 0; q < NOUT; ++q) {
-        const int i = tid + 256 * q;
-        const int r = div_small(i, inv_to), c = i - r * to;
-        const bool ok = i < to * to && R0 + r < m && C0 + c < m;
-        const int gr = ok ? R0 + r : 0, gc = ok ? C0 + c : 0;
-        const float* U = a.U + pb;
-        uold[q][0] = U[(long long)gr * a.N + m + gc];        // HL
-        uold[q][1] = U[(long long)(m + gr) * a.N + gc];      // LH
-        uold[q][2] = U[(long long)(m + gr) * a.N + m + gc];  // HH
-        uold[q][3] = a.last ? U[(long long)gr * a.N + gc] : 0.f;  // LL at the coarsest level
-      }
+      for (int q = 0; q < NOUT; ++q)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) uold[q][t] = unext[q][t];
+      if (b + 1 < b_last) fetch_u(b + 1, tid);
     }
-    __syncthreads();
+    lds_sync();
     with_len(a.f.len[b], [&](auto Fc) {
       constexpr int F = decltype(Fc)::value;
       float hk[F], gk[F];
@@ -175,7 +189,7 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
         lo[r][c] = sl;
         hi[r][c] = sh;
       }
-      __syncthreads();
+      lds_sync();
       // along the rows index: the four subbands of each output coefficient of the tile
 #pragma unroll
       for (int q = 0; q < NOUT; ++q) {
@@ -221,7 +235,8 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
           a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)gr * m + gc] = ll;
       }
     });
-    __syncthreads();  // lo / hi (and an unshared input tile) are rewritten for the next basis
+    // with a shared input, lo / hi are next written after the barrier ahead of the next filtering;
+    // an unshared input has one basis per block
   }
   if constexpr (MODE == UOB_ABS) {
     __shared__ double red[256];
@@ -244,14 +259,15 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
 // the next finer approximation of each basis (grid z = basis).
 //
 // Output pixel p takes the taps k of its own parity: coefficient (p - k) / 2 = (p - par) / 2 - kk
-// for k = 2 kk + par, par = p mod 2.
+// for k = 2 kk + par, par = p mod 2.  The two pixels 2j and 2j + 1 read the same coefficients, so
+// a thread computes them together: every LDS read feeds two FMAs, taps stay in scalar registers.
 template <bool ACCUM>
 __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
   __shared__ float cf[4][CWA][CWA + 1];  // LL, LH, HL, HH coefficient tiles
   __shared__ float lo[TA][CWA + 1], hi[TA][CWA + 1];
   const int m = a.n >> 1, n = a.n;
   const int to = n < TA ? n : TA;
-  const float inv_to = 1.f / (float)to;
+  const float inv_hto = 1.f / (float)(to >> 1);
   const int tiles_x = (n + to - 1) / to;
   const int R0 = (blockIdx.x / tiles_x) * to, C0 = (blockIdx.x % tiles_x) * to;
   const int l = blockIdx.y;
@@ -260,40 +276,47 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
   const int i0t = (R0 - FMAX) / 2, j0t = (C0 - FMAX) / 2;
   const bool one_wrap = m >= CWA;
   const int b_first = ACCUM ? 0 : blockIdx.z, b_last = ACCUM ? kUobBases : blockIdx.z + 1;
-  float accv[NPX];
+  float accv[NPP][2];
 #pragma unroll
-  for (int q = 0; q < NPX; ++q) accv[q] = 0.f;
+  for (int q = 0; q < NPP; ++q) accv[q][0] = accv[q][1] = 0.f;
+  // Staging of the four coefficient tiles of a basis: wave w loads subband w (LL, LH, HL, HH), one
+  // tile row per load, one column per lane (lanes past CWA load column CWA - 1 and discard it).
+  // A row's source address is wave-uniform; a lane's column is fixed.
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cl = lane < CWA ? lane : CWA - 1;
+  const int gc = one_wrap ? wrap_once(j0t + cl, m) : wrap_any(j0t + cl, m);
+  // the subband's rows within its plane: the LL block of in (row stride in_ld), or the level's
+  // LH (rows m.., columns 0..), HL (rows 0.., columns m..) or HH block of the dual planes
+  const long long sub_off = wave == 1 ? (long long)m * a.N : wave == 2 ? (long long)m : (long long)m * a.N + m;
+  const long long sub_ld = wave == 0 ? (long long)a.in_ld : (long long)a.N;
+  // one basis's tile rows of this lane, in registers: the next basis's are loaded while the
+  // current one is filtered (the barriers below wait for LDS traffic only)
+  float creg[CWA];
+  auto fetch = [&](int b, int i0) __attribute__((always_inline)) {
+    const float* base = wave == 0 ? a.in + (long long)l * a.in_cs + (long long)b * a.in_bs
+                                  : a.U + (long long)l * a.u_cs + (long long)b * a.u_bs + sub_off;
+    int gr = wrap_any(i0, m);  // coefficient row of tile row 0, then advanced one row per load
+#pragma unroll
+    for (int t = 0; t < CWA; ++t) {
+      creg[t] = base[(long long)gr * sub_ld + gc];
+      gr = gr + 1 == m ? 0 : gr + 1;
+    }
+  };
+  fetch(b_first, i0t);
 #pragma unroll 1
   for (int b = b_first; b < b_last; ++b) {
-    const float* U = a.U + (long long)l * a.u_cs + (long long)b * a.u_bs;
-    const float* LLs = a.in + (long long)l * a.in_cs + (long long)b * a.in_bs;
     // the tile origin and the thread index, opaque to the compiler inside the basis loop: the
     // addresses are recomputed per basis instead of being hoisted out of the loop into registers
-    int i0 = i0t, j0 = j0t, tid = threadIdx.x;
-    asm volatile("" : "+s"(i0), "+s"(j0), "+v"(tid));
-    auto put = [&](int i, float v) {
-      const int s = i / (CWA * CWA), rc = i - s * (CWA * CWA);
-      const int r = rc / CWA;
-      cf[s][r][rc - r * CWA] = v;
-    };
-    auto src = [&](int i, int gr, int gc) {
-      const int s = i / (CWA * CWA);
-      return s == 0 ? LLs + (long long)gr * a.in_ld + gc
-           : s == 1 ? U + (long long)(m + gr) * a.N + gc         // LH
-           : s == 2 ? U + (long long)gr * a.N + m + gc           // HL
-                    : U + (long long)(m + gr) * a.N + m + gc;    // HH
-    };
-    if (one_wrap)
-      stage(tid, 4 * CWA * CWA, [&](int i) {
-        const int rc = i % (CWA * CWA), r = rc / CWA;
-        return src(i, wrap_once(i0 + r, m), wrap_once(j0 + rc - r * CWA, m));
-      }, put);
-    else
-      stage(tid, 4 * CWA * CWA, [&](int i) {
-        const int rc = i % (CWA * CWA), r = rc / CWA;
-        return src(i, wrap_any(i0 + r, m), wrap_any(j0 + rc - r * CWA, m));
-      }, put);
-    __syncthreads();
+    int i0 = i0t, tid = threadIdx.x;
+    asm volatile("" : "+s"(i0), "+v"(tid));
+    // cf is read by the row pass only, which every wave has left (barrier before the column pass)
+    if (lane < CWA) {
+#pragma unroll
+      for (int t = 0; t < CWA; ++t) cf[wave][t][lane] = creg[t];
+    }
+    lds_sync();
+    if (b + 1 < b_last) fetch(b + 1, i0);
     with_len(a.f.len[b], [&](auto Fc) {
       constexpr int H = decltype(Fc)::value / 2;
       float he[H], ho[H], ge[H], go[H];  // taps of even and odd index
@@ -302,52 +325,65 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
         he[kk] = a.f.h[b][2 * kk], ho[kk] = a.f.h[b][2 * kk + 1];
         ge[kk] = a.f.g[b][2 * kk], go[kk] = a.f.g[b][2 * kk + 1];
       }
-      // along the rows index: lo[r][c] from (LL, LH), hi[r][c] from (HL, HH), output rows R0 + r
-      for (int i = tid; i < to * CWA; i += 256) {
-        const int r = i / CWA, c = i - (i / CWA) * CWA;
-        const int p = R0 + r, par = p & 1;
-        const int ib = ((p - par) >> 1) - i0;  // coefficient row of kk = 0; ib - H + 1 >= 0
-        float sl = 0.f, sh = 0.f;
+      // along the rows index, output rows R0 + 2 rp and R0 + 2 rp + 1 together (same coefficient
+      // rows ib - kk, ib = rp + FMAX / 2): lo from (LL, LH), hi from (HL, HH)
+      for (int i = tid; i < (to >> 1) * CWA; i += 256) {
+        const int rp = i / CWA, c = i - rp * CWA;
+        const int ib = rp + FMAX / 2;
+        float le = 0.f, lodd = 0.f, hev = 0.f, hodd = 0.f;
 #pragma unroll
         for (int kk = 0; kk < H; ++kk) {
-          const float h = par ? ho[kk] : he[kk], g = par ? go[kk] : ge[kk];
-          sl = fmaf(h, cf[0][ib - kk][c], fmaf(g, cf[1][ib - kk][c], sl));
-          sh = fmaf(h, cf[2][ib - kk][c], fmaf(g, cf[3][ib - kk][c], sh));
+          const float vll = cf[0][ib - kk][c], vlh = cf[1][ib - kk][c];
+          const float vhl = cf[2][ib - kk][c], vhh = cf[3][ib - kk][c];
+          le = fmaf(he[kk], vll, fmaf(ge[kk], vlh, le));
+          lodd = fmaf(ho[kk], vll, fmaf(go[kk], vlh, lodd));
+          hev = fmaf(he[kk], vhl, fmaf(ge[kk], vhh, hev));
+          hodd = fmaf(ho[kk], vhl, fmaf(go[kk], vhh, hodd));
         }
-        lo[r][c] = sl;
-        hi[r][c] = sh;
+        lo[2 * rp][c] = le;
+        lo[2 * rp + 1][c] = lodd;
+        hi[2 * rp][c] = hev;
+        hi[2 * rp + 1][c] = hodd;
       }
-      __syncthreads();
-      // along the columns index: the output pixels of the tile
+      lds_sync();
+      // along the columns index, output pixels C0 + 2 cp and C0 + 2 cp + 1 of row r together
+      // (same columns jb - kk of lo and hi, jb = cp + FMAX / 2)
 #pragma unroll
-      for (int q = 0; q < NPX; ++q) {
+      for (int q = 0; q < NPP; ++q) {
         const int i = tid + 256 * q;
-        if (i >= to * to) continue;
-        const int r = div_small(i, inv_to), c = i - r * to;
-        const int p = C0 + c, par = p & 1;
-        const int jb = ((p - par) >> 1) - j0;
-        float x = 0.f;
+        if (i >= to * (to >> 1)) continue;
+        const int r = div_small(i, inv_hto), cp = i - r * (to >> 1);
+        const int jb = cp + FMAX / 2;
+        float xe = 0.f, xo = 0.f;
 #pragma unroll
         for (int kk = 0; kk < H; ++kk) {
-          const float h = par ? ho[kk] : he[kk], g = par ? go[kk] : ge[kk];
-          x = fmaf(h, lo[r][jb - kk], fmaf(g, hi[r][jb - kk], x));
+          const float vl = lo[r][jb - kk], vh = hi[r][jb - kk];
+          xe = fmaf(he[kk], vl, fmaf(ge[kk], vh, xe));
+          xo = fmaf(ho[kk], vl, fmaf(go[kk], vh, xo));
         }
         if (ACCUM) {
-          accv[q] += x;
-        } else if (R0 + r < n && p < n) {
-          a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)(R0 + r) * n + p] = x;
+          accv[q][0] += xe;
+          accv[q][1] += xo;
+        } else if (R0 + r < n && C0 + 2 * cp < n) {
+          float* o = a.llout + (long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)(R0 + r) * n + C0 + 2 * cp;
+          o[0] = xe;
+          o[1] = xo;
         }
       }
     });
-    __syncthreads();
+    // lo and hi are next written after the barrier that follows the next basis's tile store
   }
   if (ACCUM) {
 #pragma unroll
-    for (int q = 0; q < NPX; ++q) {
+    for (int q = 0; q < NPP; ++q) {
       const int i = threadIdx.x + 256 * q;
-      if (i >= to * to) continue;
-      const int r = div_small(i, inv_to), c = i - r * to;
-      if (R0 + r < n && C0 + c < n) a.out[(long long)l * a.out_cs + (long long)(R0 + r) * a.N + C0 + c] = a.scale * accv[q];
+      if (i >= to * (to >> 1)) continue;
+      const int r = div_small(i, inv_hto), cp = i - r * (to >> 1);
+      if (R0 + r < n && C0 + 2 * cp < n) {
+        float* o = a.out + (long long)l * a.out_cs + (long long)(R0 + r) * a.N + C0 + 2 * cp;
+        o[0] = a.scale * accv[q][0];
+        o[1] = a.scale * accv[q][1];
+      }
     }
   }
 }
