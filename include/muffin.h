@@ -62,6 +62,13 @@ typedef struct muffin_ctx muffin_ctx;
  * NO_FUSED_TAIL always runs the two launches separately, FUSED_TAIL always fuses them. */
 #define MUFFIN_FLAG_NO_FUSED_TAIL 2
 #define MUFFIN_FLAG_FUSED_TAIL 4
+/* Union-of-bases prior: on the levels after the first, one workgroup per (tile, channel) runs all
+ * eight bases (loading the next basis's input while it filters the current one) when the level has
+ * enough tiles and channels to fill the GPU that way, else one workgroup per basis.  UOB_ALL_BASES
+ * and UOB_PER_BASIS force either form on every level; the results are the same bit for bit (the
+ * objective's FP64 partial sums aside, which are grouped by workgroup). */
+#define MUFFIN_FLAG_UOB_ALL_BASES 8
+#define MUFFIN_FLAG_UOB_PER_BASIS 16
 
 /* Spatial prior W_s (eq. (RegAll)): the isotropic undecimated wavelet transform MUFFIN uses (Sec. 3,
  * Sec. 4), or the union of the first eight orthonormal Daubechies wavelet bases it is compared with

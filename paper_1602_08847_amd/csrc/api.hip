@@ -140,10 +140,13 @@ int validate(const muffin_params* p) {
   if (!fft_supported(p->N)) return set_error("N must be 2^a or 3*2^a with 8 <= N <= 1024"), MUFFIN_EINVAL;
   if (p->L < 1 || p->L > 512) return set_error("L must be in [1, 512]"), MUFFIN_EINVAL;
   if (p->J < 1 || p->J > 6) return set_error("J must be in [1, 6]"), MUFFIN_EINVAL;
-  if (p->flags & ~(MUFFIN_FLAG_SINGLE_SCALE | MUFFIN_FLAG_NO_FUSED_TAIL | MUFFIN_FLAG_FUSED_TAIL))
+  if (p->flags & ~(MUFFIN_FLAG_SINGLE_SCALE | MUFFIN_FLAG_NO_FUSED_TAIL | MUFFIN_FLAG_FUSED_TAIL |
+                   MUFFIN_FLAG_UOB_ALL_BASES | MUFFIN_FLAG_UOB_PER_BASIS))
     return set_error("unknown flags"), MUFFIN_EINVAL;
   if ((p->flags & MUFFIN_FLAG_NO_FUSED_TAIL) && (p->flags & MUFFIN_FLAG_FUSED_TAIL))
     return set_error("FUSED_TAIL and NO_FUSED_TAIL exclude each other"), MUFFIN_EINVAL;
+  if ((p->flags & MUFFIN_FLAG_UOB_ALL_BASES) && (p->flags & MUFFIN_FLAG_UOB_PER_BASIS))
+    return set_error("UOB_ALL_BASES and UOB_PER_BASIS exclude each other"), MUFFIN_EINVAL;
   if (p->iuwt_gen != 1 && p->iuwt_gen != 2) return set_error("iuwt_gen must be 1 or 2"), MUFFIN_EINVAL;
   if (p->prior != MUFFIN_PRIOR_IUWT && p->prior != MUFFIN_PRIOR_UOB)
     return set_error("prior must be MUFFIN_PRIOR_IUWT or MUFFIN_PRIOR_UOB"), MUFFIN_EINVAL;
@@ -264,6 +267,13 @@ static float* uob_ll(const muffin_ctx* c, int level, int ch0) {
   return ((level & 1) ? c->uobA : c->uobB) + (long long)ch0 * kUobBases * uob_cap(c, level);
 }
 
+// Workgroup layout of the union-of-bases levels after the first (flags; -1: by the level's size).
+static int uob_all_bases(const muffin_ctx* c) {
+  if (c->p.flags & MUFFIN_FLAG_UOB_ALL_BASES) return 1;
+  if (c->p.flags & MUFFIN_FLAG_UOB_PER_BASIS) return 0;
+  return -1;
+}
+
 // W_s of nch channel images (in, channel stride in_cs; channel ch0 of the context) through the J
 // levels of every basis: UOB_DUAL updates the dual planes U (strides u_cs, u_bs) with
 // u <- rho sat(u + coef w) + (1 - rho) u, UOB_STORE writes scale * w to out, UOB_ABS adds
@@ -274,6 +284,7 @@ int enqueue_uob_analysis(muffin_ctx* c, int mode, const float* in, long long in_
   for (int lev = 1; lev <= c->J; ++lev) {
     UobLevelArgs a;
     a.f = c->uf;
+    a.all_bases = uob_all_bases(c);
     a.n = c->N >> (lev - 1);
     a.N = c->N;
     if (lev == 1) {
@@ -315,6 +326,7 @@ int enqueue_uob_adjoint(muffin_ctx* c, const float* U, long long u_cs, long long
   for (int lev = c->J; lev >= 1; --lev) {
     UobLevelArgs a;
     a.f = c->uf;
+    a.all_bases = uob_all_bases(c);
     a.n = c->N >> (lev - 1);
     a.N = c->N;
     if (lev == c->J) {

@@ -232,6 +232,7 @@ struct UobLevelArgs {
   int N = 0;                       // side (and row stride) of the dual planes and of out
   int shared_input = 0;            // analysis: one input tile for all bases (level 1)
   int last = 0;                    // analysis: the coarsest level (its approximation is a coefficient too)
+  int all_bases = -1;              // after level 1: one block runs every basis (1), one per basis (0), by size (-1)
   float* U = nullptr;              // dual planes [channel][basis][N][N]
   long long u_cs = 0, u_bs = 0;
   float* llout = nullptr;          // next approximation of each (channel, basis), dense rows

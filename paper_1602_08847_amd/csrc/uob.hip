@@ -38,8 +38,9 @@ constexpr int SA = 2 * TO + FMAX - 2;       // input rows / columns of an analys
 constexpr int TA = 64;                      // output pixels per adjoint tile side
 constexpr int CWA = TA / 2 + FMAX / 2 + 1;  // coefficient rows / columns of an adjoint tile
 constexpr int NOUT = (TO * TO + 255) / 256; // analysis outputs per thread
+constexpr int NLD = (SA * SA + 255) / 256;  // analysis tile entries per thread
 constexpr int NPP = (TA * TA / 2 + 255) / 256;  // adjoint output pixel pairs per thread
-constexpr int LB = 8;                       // global loads a thread keeps in flight while staging a tile
+constexpr int kUobAllBasesBlocks = 2048;  // blocks a level needs before one block runs all bases
 
 // Workgroup barrier for LDS traffic: waits for this wave's LDS operations only, so that global loads
 // issued ahead (the next basis's data) stay in flight across it.
@@ -60,25 +61,6 @@ __device__ __forceinline__ int wrap_once(int v, int n) {
 // error stays below 0.5 / d, so rounding i + 1/2 down gives the exact floor
 __device__ __forceinline__ int div_small(int i, float inv_d) { return (int)(((float)i + 0.5f) * inv_d); }
 
-// Stage `total` floats into LDS, LB loads in flight per thread: addr(i) gives the global address
-// of entry i, put(i, v) stores it.  Lanes past the end load entry total - 1 and discard it.
-template <class Addr, class Put>
-__device__ __forceinline__ void stage(int tid, int total, Addr addr, Put put) {
-  for (int base = tid; base < total; base += 256 * LB) {
-    float v[LB];
-#pragma unroll
-    for (int q = 0; q < LB; ++q) {
-      const int i = base + 256 * q;
-      v[q] = *addr(i < total ? i : total - 1);
-    }
-#pragma unroll
-    for (int q = 0; q < LB; ++q) {
-      const int i = base + 256 * q;
-      if (i < total) put(i, v[q]);
-    }
-  }
-}
-
 // Calls fn with the filter length F (2, 4, ..., 16) as a compile-time constant, so that the tap
 // loops unroll and the taps of the block's basis sit in scalar registers.
 template <class Fn>
@@ -96,9 +78,11 @@ __device__ __forceinline__ void with_len(int F, Fn&& fn) {
 }
 
 // ------------------------------------------------------------------ analysis (one level)
-// Grid: x = tiles of the level's m x m output, y = channel, z = basis (1 when the input is shared
-// by all bases, level 1).  MODE: UOB_DUAL (dual step into U), UOB_STORE (coefficients times scale
-// into out), UOB_ABS (FP64 sum of |coefficient| times scale into partial).
+// Grid: x = tiles of the level's m x m output, y = channel, z = basis, or z = 1 for a block that
+// runs all bases on its tile (the level's input then either is shared by all bases, level 1, or
+// is each basis's own approximation, whose next tile is loaded while the current basis is
+// filtered).  MODE: UOB_DUAL (dual step into U), UOB_STORE (coefficients times scale into out),
+// UOB_ABS (FP64 sum of |coefficient| times scale into partial).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
   __shared__ float tin[SA][SA + 1];
@@ -110,34 +94,44 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
   const int R0 = (blockIdx.x / tiles_x) * to, C0 = (blockIdx.x % tiles_x) * to;
   const int l = blockIdx.y;
   const bool shared = a.shared_input != 0;
-  const int b_first = shared ? 0 : blockIdx.z, b_last = shared ? kUobBases : blockIdx.z + 1;
-  // input tile: rows 2R0 .. 2R0 + 2to + F - 3 (mod n), same for columns; with a shared input the
-  // longest filter sets the extent, otherwise the basis's own.  2R0 + S - 1 < 2n once n >= SA.
-  const int Fl = shared ? FMAX : a.f.len[b_first];
-  const int S = 2 * to + Fl - 2;
+  const bool all_bases = gridDim.z == 1;
+  const int b_first = all_bases ? 0 : blockIdx.z, b_last = all_bases ? kUobBases : blockIdx.z + 1;
+  // input tile: rows 2R0 .. 2R0 + S - 1 (mod n), same for columns, S set by the longest filter;
+  // 2R0 + S - 1 < 2n once n >= SA.  Entry i = tid + 256 q of the tile (row i / S, column i mod S)
+  // is the same plane offset for every basis: computed once.
+  const int S = 2 * to + FMAX - 2;
   const float inv_S = 1.f / (float)S;
   const bool one_wrap = n >= SA;
-  double acc = 0.0;
-  auto load_tile = [&](const float* base) {
-    auto put = [&](int i, float v) {
-      const int r = div_small(i, inv_S);
-      tin[r][i - r * S] = v;
-    };
-    if (one_wrap)
-      stage(threadIdx.x, S * S, [&](int i) {
-        const int r = div_small(i, inv_S);
-        return base + (long long)wrap_once(2 * R0 + r, n) * a.in_ld + wrap_once(2 * C0 + i - r * S, n);
-      }, put);
-    else
-      stage(threadIdx.x, S * S, [&](int i) {
-        const int r = div_small(i, inv_S);
-        return base + (long long)wrap_any(2 * R0 + r, n) * a.in_ld + wrap_any(2 * C0 + i - r * S, n);
-      }, put);
+  int toff[NLD];
+#pragma unroll
+  for (int q = 0; q < NLD; ++q) {
+    int i = threadIdx.x + 256 * q;
+    i = i < S * S ? i : S * S - 1;
+    const int r = div_small(i, inv_S), c = i - r * S;
+    toff[q] = one_wrap ? wrap_once(2 * R0 + r, n) * a.in_ld + wrap_once(2 * C0 + c, n)
+                       : wrap_any(2 * R0 + r, n) * a.in_ld + wrap_any(2 * C0 + c, n);
+  }
+  float treg[NLD];  // a tile in registers, on its way to LDS
+  auto fetch_tile = [&](int b) __attribute__((always_inline)) {
+    const float* base = a.in + (long long)l * a.in_cs + (long long)b * a.in_bs;
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) treg[q] = base[toff[q]];
   };
+  auto put_tile = [&](int tid) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int i = tid + 256 * q;
+      if (i < S * S) {
+        const int r = div_small(i, inv_S);
+        tin[r][i - r * S] = treg[q];
+      }
+    }
+  };
+  double acc = 0.0;
   // the dual-plane entries a thread updates (HL, LH, HH, and LL at the coarsest level), one basis
   // ahead of the filtering
   float unext[NOUT][4];
-  auto fetch_u = [&](int b, int tid) {
+  auto fetch_u = [&](int b, int tid) __attribute__((always_inline)) {
     const float* U = a.U + (long long)l * a.u_cs + (long long)b * a.u_bs;
 #pragma unroll
     for (int q = 0; q < NOUT; ++q) {
@@ -151,15 +145,17 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
       unext[q][3] = a.last ? U[(long long)gr * a.N + gc] : 0.f;
     }
   };
-  if constexpr (MODE == UOB_DUAL) fetch_u(b_first, threadIdx.x);  // in flight with the input tile
-  if (shared) load_tile(a.in + (long long)l * a.in_cs);
+  if constexpr (MODE == UOB_DUAL) fetch_u(b_first, threadIdx.x);
+  fetch_tile(b_first);
 #pragma unroll 1
   for (int b = b_first; b < b_last; ++b) {
     // the thread index, opaque to the compiler inside the basis loop: the addresses are
     // recomputed per basis instead of being hoisted out of the loop into registers
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    if (!shared) load_tile(a.in + (long long)l * a.in_cs + (long long)b * a.in_bs);
+    // tin is read by the row pass only, which every wave has left (barrier before the column pass)
+    if (b == b_first || !shared) put_tile(tid);
+    if (!shared && b + 1 < b_last) fetch_tile(b + 1);
     const long long pb = (long long)l * a.u_cs + (long long)b * a.u_bs;
     float uold[NOUT][4];  // this basis's dual entries; the next basis's are fetched into unext
     if constexpr (MODE == UOB_DUAL) {
@@ -235,8 +231,8 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
           a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)gr * m + gc] = ll;
       }
     });
-    // with a shared input, lo / hi are next written after the barrier ahead of the next filtering;
-    // an unshared input has one basis per block
+    // lo / hi (and an unshared tin) are next written after this wave has passed the barrier
+    // between the row and column passes, and read after the next barrier
   }
   if constexpr (MODE == UOB_ABS) {
     __shared__ double red[256];
@@ -256,7 +252,7 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
 // approximation comes from in (row stride in_ld; at the coarsest level, the LL block of the dual
 // planes), the details from the dual planes' level blocks.  ACCUM: the output level is the image;
 // the eight bases are summed in registers and written once, times scale.  Otherwise the output is
-// the next finer approximation of each basis (grid z = basis).
+// the next finer approximation of each basis, for one basis (grid z = basis) or all of them.
 //
 // Output pixel p takes the taps k of its own parity: coefficient (p - k) / 2 = (p - par) / 2 - kk
 // for k = 2 kk + par, par = p mod 2.  The two pixels 2j and 2j + 1 read the same coefficients, so
@@ -275,7 +271,8 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
   // i0 >= -FMAX / 2 and i0 + CWA - 1 <= m once m >= CWA
   const int i0t = (R0 - FMAX) / 2, j0t = (C0 - FMAX) / 2;
   const bool one_wrap = m >= CWA;
-  const int b_first = ACCUM ? 0 : blockIdx.z, b_last = ACCUM ? kUobBases : blockIdx.z + 1;
+  const bool all_bases = gridDim.z == 1;  // always with ACCUM
+  const int b_first = all_bases ? 0 : blockIdx.z, b_last = all_bases ? kUobBases : blockIdx.z + 1;
   float accv[NPP][2];
 #pragma unroll
   for (int q = 0; q < NPP; ++q) accv[q][0] = accv[q][1] = 0.f;
@@ -481,7 +478,10 @@ int launch_uob_an(int mode, const UobLevelArgs& a, int nch, double* partial, int
   const int m = a.n >> 1;
   const int to = m < TO ? m : TO;
   const int tiles = ((m + to - 1) / to) * ((m + to - 1) / to);
-  const dim3 grid((unsigned)tiles, (unsigned)nch, a.shared_input ? 1u : (unsigned)kUobBases);
+  // one block per (tile, channel) runs all bases when that still gives the chip several blocks per
+  // slot; otherwise one block per basis
+  const bool all_bases = a.shared_input || (a.all_bases < 0 ? (long long)tiles * nch >= kUobAllBasesBlocks : a.all_bases != 0);
+  const dim3 grid((unsigned)tiles, (unsigned)nch, all_bases ? 1u : (unsigned)kUobBases);
   if (nblocks_out) *nblocks_out = (int)(grid.x * grid.y * grid.z);
   if (mode == UOB_ABS && (long long)grid.x * grid.y * grid.z > kMaxPartials)
     return set_error("uob: too many blocks for the partial sums"), MUFFIN_EINVAL;
@@ -501,7 +501,8 @@ int launch_uob_adj(bool accum, const UobLevelArgs& a, int nch, hipStream_t st) {
   const int n = a.n;
   const int to = n < TA ? n : TA;
   const int tiles = ((n + to - 1) / to) * ((n + to - 1) / to);
-  const dim3 grid((unsigned)tiles, (unsigned)nch, accum ? 1u : (unsigned)kUobBases);
+  const bool all_bases = accum || (a.all_bases < 0 ? (long long)tiles * nch >= kUobAllBasesBlocks : a.all_bases != 0);
+  const dim3 grid((unsigned)tiles, (unsigned)nch, all_bases ? 1u : (unsigned)kUobBases);
   if (accum) hipLaunchKernelGGL(k_uob_adj<true>, grid, dim3(256), 0, st, a);
   else hipLaunchKernelGGL(k_uob_adj<false>, grid, dim3(256), 0, st, a);
   MF_HIP(hipGetLastError());

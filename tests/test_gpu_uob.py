@@ -30,10 +30,16 @@ def make(N, L, J, seed=0):
 SHAPES = [(64, 8, 3), (32, 3, 5), (96, 5, 3), (128, 17, 4), (16, 2, 4), (256, 4, 5)]
 
 
+# workgroup layouts of the levels after the first: by size (small cubes: one workgroup per basis),
+# and one workgroup running all bases of a tile, forced
+LAYOUTS = [0, 8]
+
+
+@pytest.mark.parametrize("flags", LAYOUTS)
 @pytest.mark.parametrize("N,L,J", SHAPES)
-def test_uob_operators(lib, N, L, J):
+def test_uob_operators(lib, N, L, J, flags):
     dirty, psf, _ = make(N, L, J)
-    with lib.Muffin(dirty, psf, J=J, mu_s=0.25, mu_lambda=3.0, prior=lib.PRIOR_UOB) as m:
+    with lib.Muffin(dirty, psf, J=J, mu_s=0.25, mu_lambda=3.0, prior=lib.PRIOR_UOB, flags=flags) as m:
         r = np.random.default_rng(N + L)
         x = f32(r.normal(size=(L, N, N)))
         ref = np.stack([uob.uob(x[l], J) for l in range(L)])
@@ -59,8 +65,8 @@ def test_uob_operators(lib, N, L, J):
         np.testing.assert_allclose(m.objective(), om.objective(p, xp), rtol=1e-6)
 
 
-@pytest.mark.parametrize("mu_l,rho", [(3.0, 1.0), (0.0, 1.0), (3.0, 0.7)])
-def test_uob_iterations_match_oracle(lib, mu_l, rho):
+@pytest.mark.parametrize("mu_l,rho,flags", [(3.0, 1.0, 0), (0.0, 1.0, 0), (3.0, 0.7, 0), (3.0, 1.0, 8)])
+def test_uob_iterations_match_oracle(lib, mu_l, rho, flags):
     c = synth.make_cube(synth.WORKLOADS["cube64_L8_J3"])
     dirty, psf = f32(c.dirty), f32(c.psf)
     p = om.Problem(dirty=dirty, psf=psf, J=3, mu_s=0.25, mu_l=mu_l, prior="uob", rho=rho, sigma=4.0)
@@ -69,7 +75,7 @@ def test_uob_iterations_match_oracle(lib, mu_l, rho):
     one = om.iterate(p, om.init_state(p, x0), tau)
     st, _ = om.solve(p, 30, tau=tau)
     with lib.Muffin(dirty, psf, J=3, mu_s=0.25, mu_lambda=mu_l, prior=lib.PRIOR_UOB, rho=rho, sigma=4.0,
-                    tau=tau) as m:
+                    tau=tau, flags=flags) as m:
         m.set_x(x0)
         m.step(1)
         assert rel(m.get_x().double().cpu().numpy(), one.X) < TOL
@@ -101,3 +107,20 @@ def test_uob_checkpoint_resume_is_bit_exact(lib):
     with lib.Muffin(dirty, psf, J=3, mu_s=0.25, mu_lambda=3.0) as c:
         with pytest.raises(lib.MuffinError):
             c.set_state(blob)  # written by the other prior
+
+
+def test_uob_workgroup_layouts_agree_bit_for_bit(lib):
+    """All bases per workgroup, one workgroup per basis, and the size rule give the same iterates."""
+    dirty, psf, _ = make(128, 6, 4, seed=3)
+    xs, us = [], []
+    for flags in (lib.FLAG_UOB_ALL_BASES, lib.FLAG_UOB_PER_BASIS, 0):
+        with lib.Muffin(dirty, psf, J=4, mu_s=0.25, mu_lambda=3.0, prior=lib.PRIOR_UOB, flags=flags) as m:
+            m.step(6)
+            xs.append(m.get_x().cpu().numpy())
+            us.append(m.get_u().cpu().numpy())
+    for x, u in zip(xs[1:], us[1:]):
+        np.testing.assert_array_equal(x, xs[0])
+        np.testing.assert_array_equal(u, us[0])
+    with pytest.raises(lib.MuffinError):
+        lib.Muffin(dirty, psf, J=4, mu_s=0.25, mu_lambda=3.0, prior=lib.PRIOR_UOB,
+                   flags=lib.FLAG_UOB_ALL_BASES | lib.FLAG_UOB_PER_BASIS)
