@@ -69,6 +69,13 @@ typedef struct muffin_ctx muffin_ctx;
  * objective's FP64 partial sums aside, which are grouped by workgroup). */
 #define MUFFIN_FLAG_UOB_ALL_BASES 8
 #define MUFFIN_FLAG_UOB_PER_BASIS 16
+/* Channel counts L without a radix-2/3 FFT plan (16 < L <= 512): the two cosine transforms of the
+ * spectral step (Sec. 2) run either as dense products with a cosine table, or through L-point DFTs
+ * in Bluestein's form (a chirp convolution through FFTs of a length M >= 2L - 1 that has a plan).
+ * Both agree to FP32 rounding.  By default each L takes the form measured faster (Bluestein for
+ * 110 <= L <= 128 and L >= 216); SPECTRAL_DENSE and SPECTRAL_BLUESTEIN force one form. */
+#define MUFFIN_FLAG_SPECTRAL_DENSE 32
+#define MUFFIN_FLAG_SPECTRAL_BLUESTEIN 64
 
 /* Spatial prior W_s (eq. (RegAll)): the isotropic undecimated wavelet transform MUFFIN uses (Sec. 3,
  * Sec. 4), or the union of the first eight orthonormal Daubechies wavelet bases it is compared with

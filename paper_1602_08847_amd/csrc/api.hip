@@ -42,6 +42,7 @@ struct Seg {
   double mu_l = 0, tau = 0, beta = 0, K2 = 0, delta = 0;
   float *W = nullptr, *WT = nullptr;
   float2 *twL = nullptr, *csL = nullptr;
+  float2* blu = nullptr;  // Bluestein table when L has no FFT plan (spectral_blu_table)
 };
 
 struct muffin_ctx {
@@ -141,12 +142,15 @@ int validate(const muffin_params* p) {
   if (p->L < 1 || p->L > 512) return set_error("L must be in [1, 512]"), MUFFIN_EINVAL;
   if (p->J < 1 || p->J > 6) return set_error("J must be in [1, 6]"), MUFFIN_EINVAL;
   if (p->flags & ~(MUFFIN_FLAG_SINGLE_SCALE | MUFFIN_FLAG_NO_FUSED_TAIL | MUFFIN_FLAG_FUSED_TAIL |
-                   MUFFIN_FLAG_UOB_ALL_BASES | MUFFIN_FLAG_UOB_PER_BASIS))
+                   MUFFIN_FLAG_UOB_ALL_BASES | MUFFIN_FLAG_UOB_PER_BASIS | MUFFIN_FLAG_SPECTRAL_DENSE |
+                   MUFFIN_FLAG_SPECTRAL_BLUESTEIN))
     return set_error("unknown flags"), MUFFIN_EINVAL;
   if ((p->flags & MUFFIN_FLAG_NO_FUSED_TAIL) && (p->flags & MUFFIN_FLAG_FUSED_TAIL))
     return set_error("FUSED_TAIL and NO_FUSED_TAIL exclude each other"), MUFFIN_EINVAL;
   if ((p->flags & MUFFIN_FLAG_UOB_ALL_BASES) && (p->flags & MUFFIN_FLAG_UOB_PER_BASIS))
     return set_error("UOB_ALL_BASES and UOB_PER_BASIS exclude each other"), MUFFIN_EINVAL;
+  if ((p->flags & MUFFIN_FLAG_SPECTRAL_DENSE) && (p->flags & MUFFIN_FLAG_SPECTRAL_BLUESTEIN))
+    return set_error("SPECTRAL_DENSE and SPECTRAL_BLUESTEIN exclude each other"), MUFFIN_EINVAL;
   if (p->iuwt_gen != 1 && p->iuwt_gen != 2) return set_error("iuwt_gen must be 1 or 2"), MUFFIN_EINVAL;
   if (p->prior != MUFFIN_PRIOR_IUWT && p->prior != MUFFIN_PRIOR_UOB)
     return set_error("prior must be MUFFIN_PRIOR_IUWT or MUFFIN_PRIOR_UOB"), MUFFIN_EINVAL;
@@ -541,6 +545,9 @@ int enqueue_spectral(muffin_ctx* c) {
     a.cs = c->cs;
     a.L = s.L;
     a.use_fft = spectral_has_fft(s.L) ? 1 : 0;
+    const bool blu = (c->p.flags & MUFFIN_FLAG_SPECTRAL_BLUESTEIN) ||
+                     (!(c->p.flags & MUFFIN_FLAG_SPECTRAL_DENSE) && spectral_blu_default(s.L));
+    a.blu = blu ? s.blu : nullptr;
     a.tau = (float)s.tau;
     a.mu_l = (float)s.mu_l;
     a.smu_l = (float)(c->sigma * s.mu_l);
@@ -628,7 +635,7 @@ void destroy(muffin_ctx* c) {
   void* bufs[] = {c->X, c->U, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT, c->S, c->Hhat_T, c->P_T,
                   c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres, c->U2, c->Acar, c->tau_ch, c->Xs, c->Us, c->Vs, c->uobA, c->uobB};
   for (Seg& s : c->segs) {
-    void* sb[] = {s.W, s.WT, s.twL, s.csL};
+    void* sb[] = {s.W, s.WT, s.twL, s.csL, s.blu};
     for (void* b : sb)
       if (b) (void)hipFree(b);
   }
@@ -760,6 +767,7 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
     MF_TRY(dalloc(&s.csL, s.L));
     MF_TRY(dalloc(&s.W, (long long)s.L * s.L));
     MF_TRY(dalloc(&s.WT, (long long)s.L * s.L));
+    if (const int M = spectral_blu_m(s.L)) MF_TRY(dalloc(&s.blu, 2LL * M + s.L));
   }
   MF_TRY(dalloc(&c->partial, kMaxPartials));
   MF_TRY(dalloc(&c->dres, 16));
@@ -813,6 +821,8 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
       MF_HIP(hipMemcpyAsync(s.csL, cs.data(), sizeof(float2) * L, hipMemcpyHostToDevice, st));
       MF_HIP(hipMemcpyAsync(s.W, W.data(), sizeof(float) * W.size(), hipMemcpyHostToDevice, st));
       MF_HIP(hipMemcpyAsync(s.WT, WT.data(), sizeof(float) * WT.size(), hipMemcpyHostToDevice, st));
+      const std::vector<float2> blu = spectral_blu_table(L);
+      if (s.blu) MF_HIP(hipMemcpyAsync(s.blu, blu.data(), sizeof(float2) * blu.size(), hipMemcpyHostToDevice, st));
       MF_HIP(hipStreamSynchronize(st));
     }
   }

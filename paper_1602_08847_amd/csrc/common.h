@@ -196,8 +196,17 @@ struct SpectralArgs {
   int L;
   int use_fft;        // 1: FFT-based cosine transforms (L has an FFT plan), 0: cosine table
   float tau, mu_l, smu_l, rho;
+  const float2* blu = nullptr;  // Bluestein table of L (spectral_blu_table), or null: cosine table
 };
 bool spectral_has_fft(int L);
+// Bluestein length M (the shortest FFT plan of even thread count with M >= 2L - 1) for L without
+// an FFT plan, kBluMinL <= L <= 512; else 0.
+constexpr int kBluMinL = 16;
+int spectral_blu_m(int L);
+// Whether the spectral step of L channels takes the Bluestein form by default (else cosine tables).
+bool spectral_blu_default(int L);
+// exp(-2 pi i m / M) (m < M), FFT_M of the chirp conj(c_j), and c_n = exp(-i pi n^2 / L) (n < L).
+std::vector<float2> spectral_blu_table(int L);
 int launch_spectral_step(const SpectralArgs& a, hipStream_t st);
 // out = X W_lambda (inverse = false) or X W_lambda^dagger (inverse = true), per pixel; in and out
 // hold L planes of npix pixels with channel stride cs floats.

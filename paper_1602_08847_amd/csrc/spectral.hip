@@ -12,6 +12,10 @@
 // four outputs so every LDS read feeds four FMAs.
 #include "fft_core.h"
 
+#include <cmath>
+#include <complex>
+#include <vector>
+
 namespace mf {
 
 constexpr int PX = 32;  // pixels per workgroup
@@ -334,6 +338,285 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ Bluestein form of the same step
+// For L without an FFT plan the L-point DFTs of the step above run as circular convolutions of a
+// length M >= 2L - 1 with an FFT plan (Bluestein's chirp-z identity nk = (n^2 + k^2 - (k - n)^2) / 2):
+//   DFT_L(z)_k = c_k sum_{n<L} (z_n c_n) conj(c_{k-n}),   c_n = exp(-i pi n^2 / L),
+// i.e. a = z c zero-padded to M, the chirp b_j = conj(c_j) (|j| < L, stored at j mod M), and
+// DFT_L(z)_k = c_k IFFT_M(FFT_M(a) FFT_M(b))_k / M for k < L.  The unnormalised inverse DFT is
+// conj(DFT_L(conj z)).  The table a.blu holds exp(-2 pi i m / M) (m < M), B = FFT_M(b) and c_n
+// (n < L), all from FP64 on the host.
+template <int M>
+struct BluGeom {
+  static constexpr int T = Plan<M>::T;
+  static constexpr int NF = (256 / T) > 0 ? (256 / T) : 1;  // transforms (pixel pairs) per block
+  static constexpr int PXB = 2 * NF;                        // pixels per block
+  static constexpr int LS = lstride<M>();
+  static constexpr int NT = NF * T;                          // threads per block (256)
+  static constexpr int LMAX = M / 2;                         // largest L served: 2L - 1 <= M (M even)
+  static constexpr int PER = (LMAX * PXB + NT - 1) / NT;     // (channel, pixel) elements per thread, at most
+  static constexpr size_t shm = sizeof(float2) * (NF * LS + 2 * M + LMAX);
+  static_assert(NT % PXB == 0, "a thread keeps one pixel");
+};
+
+// The Stockham transform of fft_core.h with the pointwise steps around it folded into its first
+// loads and last stores: pre(n, v) is applied to input n as the first stage reads it, post(k, v)
+// to output k as the last stage writes it.  Same stages, twiddles and barriers as fft_lds.
+template <int N, bool INV, int S = 0, class Pre, class Post>
+__device__ __forceinline__ void fft_io(float2* buf, int t, const float2* __restrict__ tw, const Pre& pre,
+                                       const Post& post) {
+  if constexpr (S == 0) {
+    int zero = 0;  // keeps the two transforms' twiddle loads apart (as in fft_lds)
+    asm volatile("" : "+s"(zero));
+    tw += zero;
+  }
+  if constexpr (S < Plan<N>::nst) {
+    constexpr int T = Plan<N>::T;
+    constexpr int R = Plan<N>::rad[S];
+    constexpr int Ns = span_before<N>(S);
+    constexpr int NB = N / R;
+    constexpr int PER = (NB + T - 1) / T;
+    constexpr int TWS = N / (Ns * R);
+    constexpr bool LAST = S + 1 == Plan<N>::nst;
+    float2 v[PER][R];
+    float2 w[PER][R];
+    if constexpr (Ns > 1) {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int k = (t + i * T) % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[i][r] = tw[r * k * TWS];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = t + i * T;
+      if (PER * T == NB || b < NB) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          v[i][r] = buf[lpad(b + r * NB)];
+          if constexpr (S == 0) v[i][r] = pre(b + r * NB, v[i][r]);
+        }
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = t + i * T;
+      if (PER * T == NB || b < NB) {
+        const int k = b % Ns;
+        if constexpr (Ns > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            float2 wr = w[i][r];
+            if (INV) wr.y = -wr.y;
+            v[i][r] = cmul(v[i][r], wr);
+          }
+        }
+        dftR<R, INV>(v[i]);
+        const int base = (b / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int pos = base + r * Ns;
+          buf[lpad(pos)] = LAST ? post(pos, v[i][r]) : v[i][r];
+        }
+      }
+    }
+    lds_barrier();
+    fft_io<N, INV, S + 1>(buf, t, tw, pre, post);
+  }
+}
+
+// One L-point DFT (INV: unnormalised inverse) of slots [0, L) of the transform at fb by its T
+// threads, through the length-M convolution; slots [L, M) are ignored on entry and left
+// unspecified.  The caller has synchronised the workgroup since fb was last written.
+template <int M, bool INV>
+__device__ __forceinline__ void blu_dft(float2* fb, int t, int L, const float2* twm, const float2* bh,
+                                        const float2* ch) {
+  const float inv_m = 1.f / (float)M;
+  // FFT_M of a = z c (n < L; INV: conj z), zero beyond, times B
+  fft_io<M, false>(
+      fb, t, twm,
+      [&](int n, float2 z) {
+        const float2 c = ch[n < L ? n : 0];
+        return n < L ? cmul(INV ? cconj(z) : z, c) : make_float2(0.f, 0.f);
+      },
+      [&](int k, float2 z) { return cmul(z, bh[k]); });
+  // inverse FFT_M, then c_k / M on k < L (INV: conjugated)
+  fft_io<M, true>(
+      fb, t, twm, [](int, float2 z) { return z; },
+      [&](int k, float2 z) {
+        const float2 c = ch[k < L ? k : 0];
+        const float2 y = cmul(z, c);
+        return k < L ? make_float2(y.x * inv_m, (INV ? -y.y : y.y) * inv_m) : z;
+      });
+}
+
+template <int M>
+__global__ void __launch_bounds__(256) k_spectral_blu(SpectralArgs a) {
+  using G = BluGeom<M>;
+  constexpr int T = G::T, NF = G::NF, PXB = G::PXB, LS = G::LS, NT = G::NT, PER = G::PER;
+  const int L = a.L;
+  extern __shared__ float2 buf[];  // [NF][LS] transforms, then twiddles [M], B [M], chirp [L]
+  float2* twm = buf + NF * LS;
+  float2* bh = twm + M;
+  float2* ch = bh + M;
+  for (int i = threadIdx.x; i < 2 * M + L; i += NT) twm[i] = a.blu[i];
+  const long long npix = a.npix, cs = a.cs;
+  const long long pix0 = (long long)blockIdx.x * PXB;
+  // element i of a thread: channel l0 + i LSTEP of pixel p0 (valid while the channel is < L)
+  constexpr int LSTEP = NT / PXB;
+  const int l0 = threadIdx.x / PXB, p0 = threadIdx.x - l0 * PXB;
+  const bool pok = pix0 + p0 < npix;
+  const long long pbase = l0 * cs + pix0 + p0;
+  const long long cstep = (long long)LSTEP * cs;
+  const int f = threadIdx.x / T, t = threadIdx.x - f * T;
+  float2* fb = buf + f * LS;
+  float* my = reinterpret_cast<float*>(buf + (p0 >> 1) * LS) + (p0 & 1);  // part p0 & 1 of its transform
+  float vreg[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int l = l0 + i * LSTEP;
+    vreg[i] = (l < L && pok) ? ld_stream(a.V + pbase + i * cstep) : 0.f;
+    if (l < L) my[2 * lpad(l)] = vreg[i];
+  }
+  lds_barrier();
+  {
+    // t = mu_l * DCT-III(V): slot k becomes exp(i pi k / 2L) (Y_k - i Y_{L-k}), Y = s h mu_l V
+    // (Y_L = 0), for both packed pixels; one thread owns slots k and L - k
+    const float c0 = a.mu_l * sqrtf(1.f / L), c1 = a.mu_l * rsqrtf(2.f * L);
+    auto twiddled = [&](float2 yk, float2 ym, int k) -> float2 {
+      const float2 e = a.csL[k];
+      const float2 Va = make_float2(yk.x * e.x + ym.x * e.y, yk.x * e.y - ym.x * e.x);
+      const float2 Vb = make_float2(yk.y * e.x + ym.y * e.y, yk.y * e.y - ym.y * e.x);
+      return make_float2(Va.x - Vb.y, Va.y + Vb.x);
+    };
+    for (int k = t; 2 * k <= L; k += T) {
+      const float2 zk = fb[lpad(k)];
+      if (k == 0) {
+        fb[lpad(0)] = twiddled(make_float2(zk.x * c0, zk.y * c0), make_float2(0.f, 0.f), 0);
+      } else {
+        const float2 zm = fb[lpad(L - k)];
+        const float2 yk = make_float2(zk.x * c1, zk.y * c1), ym = make_float2(zm.x * c1, zm.y * c1);
+        fb[lpad(k)] = twiddled(yk, ym, k);
+        if (2 * k != L) fb[lpad(L - k)] = twiddled(ym, yk, L - k);
+      }
+    }
+  }
+  lds_barrier();
+  blu_dft<M, true>(fb, t, L, twm, bh, ch);
+  // primal step per (channel, pixel); d goes back into the same slot for the forward transform
+  float xreg[PER], qreg[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const bool ok = l0 + i * LSTEP < L && pok;
+    xreg[i] = ok ? ld_stream(a.X + pbase + i * cstep) : 0.f;
+    qreg[i] = ok ? ld_stream(a.Q + pbase + i * cstep) : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int l = l0 + i * LSTEP;
+    if (l >= L) continue;
+    float* slot = my + 2 * lpad(dct_slot(l, L));
+    const float tv = *slot;
+    float d = 0.f;
+    if (pok) {
+      const float x = xreg[i];
+      const float xt = fmaxf(x - a.tau * (qreg[i] + tv), 0.f);
+      d = 2.f * xt - x;
+      st_stream(a.D + pbase + i * cstep, d);
+      st_stream(a.X + pbase + i * cstep, a.rho * xt + (1.f - a.rho) * x);
+    }
+    *slot = d;
+  }
+  lds_barrier();
+  blu_dft<M, false>(fb, t, L, twm, bh, ch);
+  // spectral dual step per (coefficient, pixel): element i now stands for coefficient k
+  const float s0 = a.smu_l * sqrtf(1.f / L), s1 = a.smu_l * sqrtf(2.f / L);
+  const float2* fp = buf + (p0 >> 1) * LS;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int k = l0 + i * LSTEP;
+    if (k >= L) continue;
+    const float2 zk = fp[lpad(k)];
+    const float2 zm = cconj(fp[lpad(k ? L - k : 0)]);
+    float2 v;
+    if ((p0 & 1) == 0) {
+      v = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+    } else {
+      v = make_float2(0.5f * (zk.y - zm.y), -0.5f * (zk.x - zm.x));
+    }
+    const float2 e = a.csL[k];
+    const float c = (v.x * e.x + v.y * e.y) * (k ? s1 : s0);
+    if (pok) {
+      const float vo = vreg[i];
+      st_stream(a.V + pbase + i * cstep, a.rho * satf_s(vo + c) + (1.f - a.rho) * vo);
+    }
+  }
+}
+
+template <int M>
+static int spectral_blu_n(const SpectralArgs& a, hipStream_t st) {
+  using G = BluGeom<M>;
+  const long long nblk = (a.npix + G::PXB - 1) / G::PXB;
+  hipLaunchKernelGGL(k_spectral_blu<M>, dim3((unsigned)nblk), dim3(G::NT), G::shm, st, a);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
+template <int M>
+static int spectral_blu_attr() {
+  MF_HIP(hipFuncSetAttribute((const void*)k_spectral_blu<M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)BluGeom<M>::shm));
+  return MUFFIN_OK;
+}
+
+// Default choice between the Bluestein step and the cosine-table products, from their measured
+// times on a 512 x 512 image (the products cost L^2 per pixel and transform, the Bluestein step
+// grows with M): the products are faster below 110 channels and from 129 to 215 channels (M = 384
+// and 512); beyond 256 channels only the direct kernel is left, which the Bluestein step beats.
+bool spectral_blu_default(int L) {
+  if (!spectral_blu_m(L)) return false;
+  return (L >= 110 && L <= 128) || L >= 216;
+}
+
+int spectral_blu_m(int L) {
+  if (L < kBluMinL || L > 512 || spectral_has_fft(L)) return 0;
+  for (int M : {64, 96, 128, 192, 256, 384, 512, 768, 1024})  // the FFT plans of even thread count
+    if (M >= 2 * L - 1) return M;
+  return 0;
+}
+
+std::vector<float2> spectral_blu_table(int L) {
+  const int M = spectral_blu_m(L);
+  std::vector<float2> out;
+  if (!M) return out;
+  out.resize((size_t)2 * M + L);
+  std::vector<std::complex<double>> b(M, 0.0), chirp(L);
+  for (int n = 0; n < L; ++n) {
+    const long long r = ((long long)n * n) % (2LL * L);  // exp(-i pi n^2 / L) has period 2L in n^2
+    chirp[n] = std::polar(1.0, -M_PI * (double)r / L);
+  }
+  for (int j = 0; j < L; ++j) {
+    b[j] = std::conj(chirp[j]);
+    if (j) b[M - j] = std::conj(chirp[j]);
+  }
+  for (int m = 0; m < M; ++m) {
+    const double th = -2.0 * M_PI * m / M;
+    out[m] = make_float2((float)std::cos(th), (float)std::sin(th));
+  }
+  for (int k = 0; k < M; ++k) {  // B = FFT_M(b), directly in FP64 (M <= 1024, once per context)
+    std::complex<double> acc = 0.0;
+    for (int j = 0; j < M; ++j) {
+      if (b[j] == 0.0) continue;
+      acc += b[j] * std::polar(1.0, -2.0 * M_PI * (double)(((long long)j * k) % M) / M);
+    }
+    out[M + k] = make_float2((float)acc.real(), (float)acc.imag());
+  }
+  for (int n = 0; n < L; ++n) out[2 * M + n] = make_float2((float)chirp[n].real(), (float)chirp[n].imag());
+  return out;
+}
+
 template <int L>
 static int spectral_fft_n(const SpectralArgs& a, hipStream_t st) {
   using G = SpecGeom<L>;
@@ -381,6 +664,20 @@ bool spectral_has_fft(int L) {
 int launch_spectral_step(const SpectralArgs& a, hipStream_t st) {
   if (a.use_fft) {
     MF_SPEC_DISPATCH(a.L, spectral_fft_n, a, st)
+  }
+  if (a.blu) {
+    switch (spectral_blu_m(a.L)) {
+      case 64: return spectral_blu_n<64>(a, st);
+      case 96: return spectral_blu_n<96>(a, st);
+      case 128: return spectral_blu_n<128>(a, st);
+      case 192: return spectral_blu_n<192>(a, st);
+      case 256: return spectral_blu_n<256>(a, st);
+      case 384: return spectral_blu_n<384>(a, st);
+      case 512: return spectral_blu_n<512>(a, st);
+      case 768: return spectral_blu_n<768>(a, st);
+      case 1024: return spectral_blu_n<1024>(a, st);
+      default: return set_error("spectral: no Bluestein length for L"), MUFFIN_EINVAL;
+    }
   }
   if (a.L <= kMatMaxL) {
     // one LDS array of L x PXM; each wave keeps the d of up to MAXM chunks of 8 channels
@@ -488,6 +785,18 @@ int spectral_init_attrs(int L) {
   MF_TRY(spectral_direct_attrs(L));
   if (spectral_has_fft(L)) {
     MF_SPEC_DISPATCH(L, spectral_fft_attr)
+  }
+  switch (spectral_blu_m(L)) {
+    case 64: MF_TRY(spectral_blu_attr<64>()); break;
+    case 96: MF_TRY(spectral_blu_attr<96>()); break;
+    case 128: MF_TRY(spectral_blu_attr<128>()); break;
+    case 192: MF_TRY(spectral_blu_attr<192>()); break;
+    case 256: MF_TRY(spectral_blu_attr<256>()); break;
+    case 384: MF_TRY(spectral_blu_attr<384>()); break;
+    case 512: MF_TRY(spectral_blu_attr<512>()); break;
+    case 768: MF_TRY(spectral_blu_attr<768>()); break;
+    case 1024: MF_TRY(spectral_blu_attr<1024>()); break;
+    default: break;
   }
   return MUFFIN_OK;
 }

@@ -108,6 +108,8 @@ FLAG_NO_FUSED_TAIL = 2  # last analysis pair and the next first adjoint pair as 
 FLAG_FUSED_TAIL = 4  # always fuse them (by default: when the cube is large enough, or as autotuned)
 FLAG_UOB_ALL_BASES = 8  # union of bases: one workgroup runs all bases of a tile on every level (same results)
 FLAG_UOB_PER_BASIS = 16  # union of bases: one workgroup per basis after the first level (same results)
+FLAG_SPECTRAL_DENSE = 32  # L without an FFT plan: cosine-table products for the spectral step
+FLAG_SPECTRAL_BLUESTEIN = 64  # L without an FFT plan: Bluestein DFTs for the spectral step
 STOP_OBJECTIVE, STOP_CHANGE = 0, 1  # stopping rules of muffin_solve
 PRIOR_IUWT, PRIOR_UOB = 0, 1  # spatial prior: the IUWT, or the union of the first 8 Daubechies bases
 UOB_BASES = 8

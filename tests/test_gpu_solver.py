@@ -83,11 +83,23 @@ def test_single_iteration_matches_oracle_tightly(lib, small):
         assert rel(m.get_v().double().cpu().numpy(), st.V) < 1e-5
 
 
-@pytest.mark.parametrize("N,L", [(16, 100), (16, 200), (16, 260), (16, 384)])
-def test_single_iteration_spectral_paths(lib, N, L):
-    """One iteration with the spectral step on each of its paths: dense cosine products (L <= 256
-    without an FFT plan; 100 and 200 channels take the kernels for up to 128 and 256), the direct
-    kernel (larger L without a plan), an FFT with a radix-3 plan."""
+SPECTRAL_PATHS = [
+    # Bluestein DFTs (flag 64) through FFTs of length M = 64, 96, 128, 192, 256, 384, 512, 768, 1024
+    (16, 17, 64), (16, 37, 64), (16, 50, 64), (16, 70, 64), (16, 100, 64), (16, 150, 64), (16, 200, 64),
+    (16, 300, 64), (8, 511, 64),
+    # the cosine-table paths (flag 32): dense products for L <= 256 (kernels for up to 128 and 256
+    # channels), the direct kernel beyond
+    (16, 100, 32), (16, 200, 32), (16, 260, 32),
+    # by default: dense products (L = 11, 100), Bluestein (L = 120, 260), an FFT with a radix-3 plan
+    (16, 11, 0), (16, 100, 0), (16, 120, 0), (16, 260, 0), (16, 384, 0),
+]
+
+
+@pytest.mark.parametrize("N,L,flags", SPECTRAL_PATHS)
+def test_single_iteration_spectral_paths(lib, N, L, flags):
+    """Two iterations with the spectral step on each of its paths against the oracle: flags 64
+    (FLAG_SPECTRAL_BLUESTEIN) and 32 (FLAG_SPECTRAL_DENSE) force the form of the cosine transforms
+    for channel counts without an FFT plan; 0 takes the default choice."""
     c = synth.make_cube(synth.CubeSpec(N=N, L=L, J=2, n_sources=3, n_baselines=40, seed=L))
     dirty, psf = f32(c.dirty), f32(c.psf)
     p = om.Problem(dirty=dirty, psf=psf, J=2, mu_s=0.25, mu_l=3.0)
@@ -96,7 +108,7 @@ def test_single_iteration_spectral_paths(lib, N, L):
     x0 = f32(np.abs(r.normal(size=dirty.shape)))
     st = om.iterate(p, om.init_state(p, x0), tau)
     st = om.iterate(p, st, tau)
-    with lib.Muffin(dirty, psf, J=2, mu_s=0.25, mu_lambda=3.0, tau=tau) as m:
+    with lib.Muffin(dirty, psf, J=2, mu_s=0.25, mu_lambda=3.0, tau=tau, flags=flags) as m:
         m.set_x(x0)
         m.step(2)
         assert rel(m.get_x().double().cpu().numpy(), st.X) < 1e-5
