@@ -49,6 +49,50 @@ def build(verbose: bool = True, jobs: int = 8) -> str:
     return LIB
 
 
+# Host code under AddressSanitizer and UndefinedBehaviorSanitizer (device code is not
+# instrumented: each sanitizer flag applies to the host compilation only).
+HOST_SANITIZERS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                   "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """libmuffin with its host code built with ASan and UBSan (device code as usual, at -O1), and
+    the host check driver tests/host_sanitizer_driver.cpp linked against it; returns the driver."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    outdir = os.path.join(HERE, "_build", "hostsan")
+    os.makedirs(outdir, exist_ok=True)
+    base = ["-O1", "-g", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
+            "-packed-fp32-ops", "-Wno-unused-result", *HOST_SANITIZERS]
+    procs, objs = [], []
+    for s in SOURCES:
+        obj = os.path.join(outdir, s.replace(".hip", ".o"))
+        cmd = [hipcc, *base, "-c", "-I", os.path.join(ROOT, "include"), "-I", CSRC, os.path.join(CSRC, s), "-o", obj]
+        procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        objs.append(obj)
+    for s, pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            raise RuntimeError(f"hipcc (host sanitizers) failed for {s}:\n" + out.decode(errors="replace")[-4000:])
+    lib = os.path.join(outdir, "libmuffin_hostsan.so")
+    r = subprocess.run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *HOST_SANITIZERS, *objs, "-o", lib],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        raise RuntimeError("link (host sanitizers) failed:\n" + r.stdout.decode(errors="replace")[-4000:])
+    exe = os.path.join(outdir, "host_sanitizer_driver")
+    drv = os.path.join(ROOT, "tests", "host_sanitizer_driver.cpp")
+    dobj = os.path.join(outdir, "host_sanitizer_driver.o")
+    r = subprocess.run([hipcc, *base, "-I", os.path.join(ROOT, "include"), "-c", drv, "-o", dobj],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode == 0:
+        r = subprocess.run([hipcc, *HOST_SANITIZERS, dobj, lib, "-Wl,-rpath," + outdir, "-o", exe],
+                           stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        raise RuntimeError("driver build failed:\n" + r.stdout.decode(errors="replace")[-4000:])
+    if verbose:
+        print(exe)
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
     sys.exit(0)
