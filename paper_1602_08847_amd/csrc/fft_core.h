@@ -29,7 +29,7 @@ MF_PLAN(512, 3, 8, 8, 8, 8)
 MF_PLAN(1024, 3, 16, 16, 4, 16)
 MF_PLAN(12, 2, 4, 3, 1, 4)
 MF_PLAN(24, 2, 8, 3, 1, 8)
-MF_PLAN(48, 2, 16, 3, 1, 16)
+MF_PLAN(48, 3, 4, 4, 3, 4)  // not (16, 3): an even thread count per transform (12, not 3)
 MF_PLAN(96, 3, 8, 4, 3, 8)
 MF_PLAN(192, 3, 8, 8, 3, 8)
 MF_PLAN(384, 3, 16, 8, 3, 16)

@@ -203,10 +203,16 @@ __global__ void __launch_bounds__(256) k_spectral_mat(SpectralArgs a) {
 // X_k = s_k Re(exp(-i pi k / 2L) FFT(v)_k).  Its inverse: Y_k = s_k h_k X_k (h_0 = 1, h_k = 1/2),
 // V_k = exp(i pi k / 2L) (Y_k - i Y_{L-k}) (Y_L = 0), v = unnormalised inverse FFT of V, and x is
 // read back from v with the same reordering.
+// the largest power of two <= v (v >= 1)
+constexpr int pow2_floor(int v) { return v < 2 ? 1 : 2 * pow2_floor(v / 2); }
+
 template <int L>
 struct SpecGeom {
   static constexpr int T = Plan<L>::T;
-  static constexpr int NF = (256 / T) > 0 ? (256 / T) : 1;  // transforms (pixel pairs) per block
+  // transforms (pixel pairs) per block: a power of two, so that a block's pixels span whole
+  // 128-byte lines of every channel plane (T = 12 or 24 with L = 3 * 2^a would otherwise give 42
+  // or 20 pixels per block)
+  static constexpr int NF = pow2_floor(256 / T);
   static constexpr int PXB = 2 * NF;                        // pixels per block
   // odd transform stride: the per-pixel steps read one entry of each of 16 transforms at once
   static constexpr int LS = lstride<L>();

@@ -26,7 +26,7 @@ SHAPES = [
     # (N, L, J, gen): the small parity cube, ragged and degenerate cases, radix-3 sizes,
     # scales whose taps wrap around the image
     (64, 8, 3, 2), (64, 8, 3, 1), (8, 1, 3, 2), (8, 3, 1, 1), (12, 5, 2, 2), (16, 2, 3, 2),
-    (96, 7, 3, 2), (128, 17, 4, 2), (384, 3, 4, 2), (256, 64, 4, 2), (32, 33, 2, 1),
+    (96, 7, 3, 2), (128, 17, 4, 2), (384, 3, 4, 2), (256, 64, 4, 2), (32, 33, 2, 1), (48, 48, 3, 2),
     # channel counts above 256 without an FFT plan, and a radix-3 plan
     (8, 260, 2, 2), (8, 384, 2, 2),
 ]
