@@ -331,6 +331,12 @@ void muffin_batch_free(muffin_batch* batch);
  * other n or a short buffer. */
 int muffin_uob_filter(int32_t n, double* h, int32_t len);
 
+/* Checked builds (test infrastructure, not part of the paper's method): in a library built with
+ * MF_CHECKED every instrumented kernel index outside its bound is counted, and replaced by an index
+ * in bounds so that the kernel completes.  *count = the number caught since the last call, then
+ * zero.  The normal build returns EINVAL (count 0). */
+int muffin_debug_oob(uint64_t* count);
+
 /* Error reporting: a fixed text for each MUFFIN_E* code, and the message of the last failure on the
  * calling thread (valid until the next failing call on that thread). */
 const char* muffin_strerror(int code);

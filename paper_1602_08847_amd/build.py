@@ -17,14 +17,13 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = True, jobs: int = 8) -> str:
+def _compile_and_link(extra: list, objdir: str, lib: str, verbose: bool) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs, procs = [], []
     for s in SOURCES:
         obj = os.path.join(objdir, s.replace(".hip", ".o"))
-        cmd = [hipcc, *FLAGS, "-c", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+        cmd = [hipcc, *FLAGS, *extra, "-c", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                os.path.join(CSRC, s), "-o", obj]
         cmd.remove("-shared")
         procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -40,13 +39,27 @@ def build(verbose: bool = True, jobs: int = 8) -> str:
             failed.append(s)
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, *objs, "-o", tmp]
+    tmp = lib + ".tmp"
+    cmd = [hipcc, *FLAGS, *extra, *objs, "-o", tmp]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout.decode(errors="replace"))
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = True, jobs: int = 8) -> str:
+    return _compile_and_link([], os.path.join(HERE, "_build"), LIB, verbose)
+
+
+CHECKED_LIB = os.path.join(HERE, "libmuffin_checked.so")  # in-tree: it ships with the package
+
+
+def build_checked(verbose: bool = True) -> str:
+    """The same library with MF_CHECKED: instrumented kernel indices are bounds-checked on the
+    device (a miss is counted and replaced by an index in bounds; muffin_debug_oob reads the count).
+    Test infrastructure: the GPU tests load it through MUFFIN_LIBRARY."""
+    return _compile_and_link(["-DMF_CHECKED"], os.path.join(HERE, "_build", "checked"), CHECKED_LIB, verbose)
 
 
 # Host code under AddressSanitizer and UndefinedBehaviorSanitizer (device code is not

@@ -1132,6 +1132,23 @@ const char* muffin_last_error(void) { return g_err.c_str(); }
 
 int muffin_uob_filter(int32_t n, double* h, int32_t len) { return uob_lowpass(n, h, len); }
 
+int muffin_debug_oob(uint64_t* count) {
+  if (!count) return mf::set_error("debug_oob: count is NULL"), MUFFIN_EINVAL;
+#ifdef MF_CHECKED
+  unsigned long long total = 0, n = 0;
+  for (int (*take)(unsigned long long*) : {mf::oob_take_fft, mf::oob_take_iuwt, mf::oob_take_spectral,
+                                           mf::oob_take_uob}) {
+    MF_TRY(take(&n));
+    total += n;
+  }
+  *count = total;
+  return MUFFIN_OK;
+#else
+  *count = 0;
+  return mf::set_error("debug_oob: not a checked build (MF_CHECKED)"), MUFFIN_EINVAL;
+#endif
+}
+
 const char* muffin_strerror(int code) {
   switch (code) {
     case MUFFIN_OK: return "ok";

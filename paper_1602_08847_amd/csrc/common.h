@@ -38,6 +38,37 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// ------------------------------------------------------------------ checked build
+// Built with -DMF_CHECKED (build.build_checked), MF_CHK(i, n) counts an index i outside [0, n) in
+// this translation unit's device counter and yields 0 in its place, so the access stays in bounds
+// and the kernel runs on; in the normal build it is i itself.  muffin_debug_oob sums and clears the
+// counters of every translation unit.
+#ifdef MF_CHECKED
+static __device__ unsigned long long mf_oob_count;  // one per translation unit
+__device__ __forceinline__ long long mf_chk(long long i, long long n) {
+  if (i < 0 || i >= n) {
+    atomicAdd(&mf_oob_count, 1ull);
+    return 0;
+  }
+  return i;
+}
+#define MF_CHK(i, n) (static_cast<decltype(i)>(::mf::mf_chk((long long)(i), (long long)(n))))
+// This translation unit's count since the last call, then zero.
+static inline int oob_take_here(unsigned long long* n) {
+  MF_HIP(hipMemcpyFromSymbol(n, HIP_SYMBOL(mf_oob_count), sizeof(*n)));
+  const unsigned long long zero = 0;
+  MF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(mf_oob_count), &zero, sizeof(zero)));
+  return MUFFIN_OK;
+}
+#else
+#define MF_CHK(i, n) (i)
+#endif
+// Per translation unit (checked build): its count since the last call, then zero.
+int oob_take_fft(unsigned long long* n);
+int oob_take_iuwt(unsigned long long* n);
+int oob_take_spectral(unsigned long long* n);
+int oob_take_uob(unsigned long long* n);
+
 // XCD-aware block order.  Consecutive workgroup ids are dealt round-robin to the 8 XCDs, each
 // with its own L2; this maps id b to logical block xcd_remap(b) so that XCD x (ids b = x, x + 8,
 // ...) walks one contiguous range of logical blocks, and neighbouring blocks that share cache

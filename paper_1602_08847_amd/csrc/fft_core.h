@@ -189,7 +189,7 @@ __device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const f
         if constexpr (R >= 8) {
           // w^r from the table's w, w^2, w^4 (and w^8): at most three products per twiddle
 #pragma unroll
-          for (int r = 1; r < R; r *= 2) w[i][r] = tw[r * k * TWS];
+          for (int r = 1; r < R; r *= 2) w[i][r] = tw[MF_CHK(r * k * TWS, N)];
 #pragma unroll
           for (int r = 3; r < R; ++r) {
             if ((r & (r - 1)) == 0) continue;
@@ -198,7 +198,7 @@ __device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const f
           }
         } else {
 #pragma unroll
-          for (int r = 1; r < R; ++r) w[i][r] = tw[r * k * TWS];
+          for (int r = 1; r < R; ++r) w[i][r] = tw[MF_CHK(r * k * TWS, N)];
         }
       }
     }
@@ -207,7 +207,7 @@ __device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const f
       const int b = t + i * T;
       if (active && (PER * T == NB || b < NB)) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[i][r] = buf[lpad(b + r * NB)];
+        for (int r = 0; r < R; ++r) v[i][r] = buf[lpad(MF_CHK(b + r * NB, N))];
       }
     }
     lds_barrier();
@@ -227,7 +227,7 @@ __device__ __forceinline__ void fft_lds(float2* buf, int t, bool active, const f
         dftR<R, INV>(v[i]);
         const int base = (b / Ns) * Ns * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[lpad(base + r * Ns)] = v[i][r];
+        for (int r = 0; r < R; ++r) buf[lpad(MF_CHK(base + r * Ns, N))] = v[i][r];
       }
     }
     lds_barrier();

@@ -108,10 +108,10 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
   const int rowb = N * 4, planeb = N * N * 4, stepb = (s % N) * rowb;
   const unsigned xb = (unsigned)x * 4u;
   auto at = [&](const char* base, int off) -> float {
-    return *reinterpret_cast<const float*>(base + off + xb);
+    return *reinterpret_cast<const float*>(base + MF_CHK(off, planeb) + xb);
   };
   auto put = [&](float* base, int y, float v) {  // row y of the band
-    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + MF_CHK(y, N) * rowb + xb) = v;
   };
   // class r: stage-1 outputs at rows first(r) + m s, m < M1(r); steps t = m + 4, padded to rounds
   auto nsteps = [&](int r) -> int {
@@ -351,10 +351,10 @@ __device__ __forceinline__ void pair_body(const AtrousArgs& a) {
   const int rowb = N * 4, planeb = N * N * 4, stepb = (s % N) * rowb;
   const unsigned xb = (unsigned)x * 4u;
   auto at = [&](const char* base, int off) -> float {
-    return *reinterpret_cast<const float*>(base + off + xb);
+    return *reinterpret_cast<const float*>(base + MF_CHK(off, planeb) + xb);
   };
   auto put = [&](float* base, int y, float v) {
-    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + MF_CHK(y, N) * rowb + xb) = v;
   };
   auto upd = [&](float u, float w, float coef) { return dual_upd(u, w, coef, a.rho); };
   auto nsteps = [&](int r) -> int {
@@ -695,10 +695,10 @@ __device__ __forceinline__ void triple_an_body(const AtrousArgs& a) {
   const unsigned xb = (unsigned)x * 4u;
   auto at = [&](const char* base, int off) -> float {
     // streaming loads (the stores stay cached: the next launch reads c_{j+3})
-    return ld_stream(reinterpret_cast<const float*>(base + off + xb));
+    return ld_stream(reinterpret_cast<const float*>(base + MF_CHK(off, planeb) + xb));
   };
   auto put = [&](float* base, int y, float v) {
-    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + MF_CHK(y, N) * rowb + xb) = v;
   };
   auto upd = [&](float u, float w, float coef) { return dual_upd(u, w, coef, a.rho); };
   auto nsteps = [&](int r) -> int {
@@ -906,10 +906,10 @@ __device__ __forceinline__ void triple_adj_body(const AtrousArgs& a) {
   const unsigned xb = (unsigned)x * 4u;
   auto at = [&](const char* base, int off) -> float {
     // streaming: every row is read once, and the new sum is next read two launches later
-    return ld_stream(reinterpret_cast<const float*>(base + off + xb));
+    return ld_stream(reinterpret_cast<const float*>(base + MF_CHK(off, planeb) + xb));
   };
   auto put = [&](float* base, int y, float v) {
-    st_stream(reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb), v);
+    st_stream(reinterpret_cast<float*>(reinterpret_cast<char*>(base) + MF_CHK(y, N) * rowb + xb), v);
   };
   auto nsteps = [&](int r) -> int {
     const int v = TY - r;
@@ -1168,10 +1168,10 @@ __device__ __forceinline__ void fused_body(const AtrousArgs& a) {
   const int rowb = N * 4, planeb = N * N * 4, stepb = (s % N) * rowb;
   const unsigned xb = (unsigned)x * 4u;
   auto at = [&](const char* base, int off) -> float {
-    return *reinterpret_cast<const float*>(base + off + xb);
+    return *reinterpret_cast<const float*>(base + MF_CHK(off, planeb) + xb);
   };
   auto put = [&](float* base, int y, float v) {
-    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + y * rowb + xb) = v;
+    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + MF_CHK(y, N) * rowb + xb) = v;
   };
   auto upd = [&](float u, float w, float coef) { return dual_upd(u, w, coef, a.rho); };
   auto nsteps = [&](int r) -> int {
@@ -1840,5 +1840,9 @@ int launch_scale_channels(float* x, const float* chan_w, long long npix, long lo
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }
+
+#ifdef MF_CHECKED
+int oob_take_iuwt(unsigned long long* n) { return oob_take_here(n); }
+#endif
 
 }  // namespace mf

@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   for (int i = 0; i < PER; ++i) {
     if (FIXP || threadIdx.x + i * NT < L * PXB) {
       const int p = el_p(i);
-      reinterpret_cast<float*>(buf + (p >> 1) * LS + lpad(el_l(i)))[p & 1] = vreg[i];
+      reinterpret_cast<float*>(buf + MF_CHK(p >> 1, NF) * LS + lpad(MF_CHK(el_l(i), L)))[p & 1] = vreg[i];
     }
   }
   lds_barrier();
@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
       if (k == 0) {
         fb[lpad(0)] = twiddled(make_float2(zk.x * c0, zk.y * c0), make_float2(0.f, 0.f), 0);
       } else {
-        const float2 zm = fb[lpad(L - k)];
+        const float2 zm = fb[lpad(MF_CHK(L - k, L))];
         const float2 yk = make_float2(zk.x * c1, zk.y * c1), ym = make_float2(zm.x * c1, zm.y * c1);
         fb[lpad(k)] = twiddled(yk, ym, k);
         if (2 * k != L) fb[lpad(L - k)] = twiddled(ym, yk, L - k);
@@ -306,7 +306,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
   for (int i = 0; i < PER; ++i) {
     if (!FIXP && threadIdx.x + i * NT >= L * PXB) continue;
     const int l = el_l(i), p = el_p(i);
-    float* slot = reinterpret_cast<float*>(buf + (p >> 1) * LS + lpad(dct_slot(l, L))) + (p & 1);
+    float* slot = reinterpret_cast<float*>(buf + MF_CHK(p >> 1, NF) * LS + lpad(MF_CHK(dct_slot(l, L), L))) + (p & 1);
     const float tv = *slot;
     float d = 0.f;
     if (el_ok(i)) {
@@ -328,7 +328,7 @@ __global__ void __launch_bounds__(256) k_spectral_fft(SpectralArgs a) {
     const int k = el_l(i), p = el_p(i);
     const float2* fp = buf + (p >> 1) * LS;
     const float2 zk = fp[lpad(k)];
-    const float2 zm = cconj(fp[lpad(k ? L - k : 0)]);
+    const float2 zm = cconj(fp[lpad(MF_CHK(k ? L - k : 0, L))]);
     float2 v;
     if ((p & 1) == 0) {
       v = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
@@ -391,7 +391,7 @@ __device__ __forceinline__ void fft_io(float2* buf, int t, const float2* __restr
       for (int i = 0; i < PER; ++i) {
         const int k = (t + i * T) % Ns;
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[i][r] = tw[r * k * TWS];
+        for (int r = 1; r < R; ++r) w[i][r] = tw[MF_CHK(r * k * TWS, N)];
       }
     }
 #pragma unroll
@@ -400,7 +400,7 @@ __device__ __forceinline__ void fft_io(float2* buf, int t, const float2* __restr
       if (PER * T == NB || b < NB) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          v[i][r] = buf[lpad(b + r * NB)];
+          v[i][r] = buf[lpad(MF_CHK(b + r * NB, N))];
           if constexpr (S == 0) v[i][r] = pre(b + r * NB, v[i][r]);
         }
       }
@@ -423,7 +423,7 @@ __device__ __forceinline__ void fft_io(float2* buf, int t, const float2* __restr
         const int base = (b / Ns) * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const int pos = base + r * Ns;
+          const int pos = MF_CHK(base + r * Ns, N);
           buf[lpad(pos)] = LAST ? post(pos, v[i][r]) : v[i][r];
         }
       }
@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(256) k_spectral_blu(SpectralArgs a) {
   float2* twm = buf + NF * LS;
   float2* bh = twm + M;
   float2* ch = bh + M;
-  for (int i = threadIdx.x; i < 2 * M + L; i += NT) twm[i] = a.blu[i];
+  for (int i = threadIdx.x; i < 2 * M + L; i += NT) twm[MF_CHK(i, 2 * M + G::LMAX)] = a.blu[i];
   const long long npix = a.npix, cs = a.cs;
   const long long pix0 = (long long)blockIdx.x * PXB;
   // element i of a thread: channel l0 + i LSTEP of pixel p0 (valid while the channel is < L)
@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(256) k_spectral_blu(SpectralArgs a) {
   for (int i = 0; i < PER; ++i) {
     const int l = l0 + i * LSTEP;
     vreg[i] = (l < L && pok) ? ld_stream(a.V + pbase + i * cstep) : 0.f;
-    if (l < L) my[2 * lpad(l)] = vreg[i];
+    if (l < L) my[2 * lpad(MF_CHK(l, L))] = vreg[i];
   }
   lds_barrier();
   {
@@ -502,7 +502,7 @@ __global__ void __launch_bounds__(256) k_spectral_blu(SpectralArgs a) {
       if (k == 0) {
         fb[lpad(0)] = twiddled(make_float2(zk.x * c0, zk.y * c0), make_float2(0.f, 0.f), 0);
       } else {
-        const float2 zm = fb[lpad(L - k)];
+        const float2 zm = fb[lpad(MF_CHK(L - k, L))];
         const float2 yk = make_float2(zk.x * c1, zk.y * c1), ym = make_float2(zm.x * c1, zm.y * c1);
         fb[lpad(k)] = twiddled(yk, ym, k);
         if (2 * k != L) fb[lpad(L - k)] = twiddled(ym, yk, L - k);
@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(256) k_spectral_blu(SpectralArgs a) {
   for (int i = 0; i < PER; ++i) {
     const int l = l0 + i * LSTEP;
     if (l >= L) continue;
-    float* slot = my + 2 * lpad(dct_slot(l, L));
+    float* slot = my + 2 * lpad(MF_CHK(dct_slot(l, L), L));
     const float tv = *slot;
     float d = 0.f;
     if (pok) {
@@ -545,7 +545,7 @@ __global__ void __launch_bounds__(256) k_spectral_blu(SpectralArgs a) {
     const int k = l0 + i * LSTEP;
     if (k >= L) continue;
     const float2 zk = fp[lpad(k)];
-    const float2 zm = cconj(fp[lpad(k ? L - k : 0)]);
+    const float2 zm = cconj(fp[lpad(MF_CHK(k ? L - k : 0, L))]);
     float2 v;
     if ((p0 & 1) == 0) {
       v = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
@@ -806,5 +806,9 @@ int spectral_init_attrs(int L) {
   }
   return MUFFIN_OK;
 }
+
+#ifdef MF_CHECKED
+int oob_take_spectral(unsigned long long* n) { return oob_take_here(n); }
+#endif
 
 }  // namespace mf

@@ -42,10 +42,6 @@ constexpr int NLD = (SA * SA + 255) / 256;  // analysis tile entries per thread
 constexpr int NPP = (TA * TA / 2 + 255) / 256;  // adjoint output pixel pairs per thread
 constexpr int kUobAllBasesBlocks = 2048;  // blocks a level needs before one block runs all bases
 
-// Workgroup barrier for LDS traffic: waits for this wave's LDS operations only, so that global loads
-// issued ahead (the next basis's data) stay in flight across it.
-__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
 __device__ __forceinline__ float satf_u(float u) { return fminf(1.f, fmaxf(-1.f, u)); }
 // v mod n in [0, n) for any v
 __device__ __forceinline__ int wrap_any(int v, int n) {
@@ -108,8 +104,9 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
     int i = threadIdx.x + 256 * q;
     i = i < S * S ? i : S * S - 1;
     const int r = div_small(i, inv_S), c = i - r * S;
-    toff[q] = one_wrap ? wrap_once(2 * R0 + r, n) * a.in_ld + wrap_once(2 * C0 + c, n)
-                       : wrap_any(2 * R0 + r, n) * a.in_ld + wrap_any(2 * C0 + c, n);
+    const int gy = one_wrap ? wrap_once(2 * R0 + r, n) : wrap_any(2 * R0 + r, n);
+    const int gx = one_wrap ? wrap_once(2 * C0 + c, n) : wrap_any(2 * C0 + c, n);
+    toff[q] = MF_CHK(gy, n) * a.in_ld + MF_CHK(gx, n);
   }
   float treg[NLD];  // a tile in registers, on its way to LDS
   auto fetch_tile = [&](int b) __attribute__((always_inline)) {
@@ -123,7 +120,7 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
       const int i = tid + 256 * q;
       if (i < S * S) {
         const int r = div_small(i, inv_S);
-        tin[r][i - r * S] = treg[q];
+        tin[MF_CHK(r, S)][MF_CHK(i - r * S, S)] = treg[q];
       }
     }
   };
@@ -138,7 +135,7 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
       const int i = tid + 256 * q;
       const int r = div_small(i, inv_to), c = i - r * to;
       const bool ok = i < to * to && R0 + r < m && C0 + c < m;
-      const int gr = ok ? R0 + r : 0, gc = ok ? C0 + c : 0;
+      const int gr = MF_CHK(ok ? R0 + r : 0, m), gc = MF_CHK(ok ? C0 + c : 0, m);
       unext[q][0] = U[(long long)gr * a.N + m + gc];
       unext[q][1] = U[(long long)(m + gr) * a.N + gc];
       unext[q][2] = U[(long long)(m + gr) * a.N + m + gc];
@@ -165,7 +162,7 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
         for (int t = 0; t < 4; ++t) uold[q][t] = unext[q][t];
       if (b + 1 < b_last) fetch_u(b + 1, tid);
     }
-    lds_sync();
+    lds_barrier();
     with_len(a.f.len[b], [&](auto Fc) {
       constexpr int F = decltype(Fc)::value;
       float hk[F], gk[F];
@@ -178,14 +175,14 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
         float sl = 0.f, sh = 0.f;
 #pragma unroll
         for (int k = 0; k < F; ++k) {
-          const float v = tin[r][2 * c + k];
+          const float v = tin[MF_CHK(r, S)][MF_CHK(2 * c + k, S)];
           sl = fmaf(hk[k], v, sl);
           sh = fmaf(gk[k], v, sh);
         }
-        lo[r][c] = sl;
+        lo[MF_CHK(r, SA)][MF_CHK(c, to)] = sl;
         hi[r][c] = sh;
       }
-      lds_sync();
+      lds_barrier();
       // along the rows index: the four subbands of each output coefficient of the tile
 #pragma unroll
       for (int q = 0; q < NOUT; ++q) {
@@ -196,7 +193,7 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
         float ll = 0.f, lh = 0.f, hl = 0.f, hh = 0.f;
 #pragma unroll
         for (int k = 0; k < F; ++k) {
-          const float vl = lo[2 * r + k][c], vh = hi[2 * r + k][c];
+          const float vl = lo[MF_CHK(2 * r + k, Sr)][MF_CHK(c, to)], vh = hi[2 * r + k][c];
           ll = fmaf(hk[k], vl, ll);
           lh = fmaf(gk[k], vl, lh);
           hl = fmaf(hk[k], vh, hl);
@@ -207,6 +204,9 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
                                   (long long)(m + gr) * a.N + m + gc};
         const float w[3] = {hl, lh, hh};
         const long long lpos = (long long)gr * a.N + gc;
+#ifdef MF_CHECKED
+        for (int t = 0; t < 3; ++t) (void)MF_CHK(pos[t], (long long)a.N * a.N);
+#endif
         if constexpr (MODE == UOB_DUAL) {
 #pragma unroll
           for (int t = 0; t < 3; ++t) {
@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
           if (a.last) acc += fabs((double)(a.scale * ll));
         }
         if (!a.last)
-          a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)gr * m + gc] = ll;
+          a.llout[(long long)l * a.ll_cs + (long long)b * a.ll_bs + MF_CHK((long long)gr * m + gc, (long long)m * m)] = ll;
       }
     });
     // lo / hi (and an unshared tin) are next written after this wave has passed the barrier
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int cl = lane < CWA ? lane : CWA - 1;
-  const int gc = one_wrap ? wrap_once(j0t + cl, m) : wrap_any(j0t + cl, m);
+  const int gc = MF_CHK(one_wrap ? wrap_once(j0t + cl, m) : wrap_any(j0t + cl, m), m);
   // the subband's rows within its plane: the LL block of in (row stride in_ld), or the level's
   // LH (rows m.., columns 0..), HL (rows 0.., columns m..) or HH block of the dual planes
   const long long sub_off = wave == 1 ? (long long)m * a.N : wave == 2 ? (long long)m : (long long)m * a.N + m;
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
     int gr = wrap_any(i0, m);  // coefficient row of tile row 0, then advanced one row per load
 #pragma unroll
     for (int t = 0; t < CWA; ++t) {
-      creg[t] = base[(long long)gr * sub_ld + gc];
+      creg[t] = base[(long long)MF_CHK(gr, m) * sub_ld + gc];
       gr = gr + 1 == m ? 0 : gr + 1;
     }
   };
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
 #pragma unroll
       for (int t = 0; t < CWA; ++t) cf[wave][t][lane] = creg[t];
     }
-    lds_sync();
+    lds_barrier();
     if (b + 1 < b_last) fetch(b + 1, i0);
     with_len(a.f.len[b], [&](auto Fc) {
       constexpr int H = decltype(Fc)::value / 2;
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
         float le = 0.f, lodd = 0.f, hev = 0.f, hodd = 0.f;
 #pragma unroll
         for (int kk = 0; kk < H; ++kk) {
-          const float vll = cf[0][ib - kk][c], vlh = cf[1][ib - kk][c];
+          const float vll = cf[0][MF_CHK(ib - kk, CWA)][MF_CHK(c, CWA)], vlh = cf[1][ib - kk][c];
           const float vhl = cf[2][ib - kk][c], vhh = cf[3][ib - kk][c];
           le = fmaf(he[kk], vll, fmaf(ge[kk], vlh, le));
           lodd = fmaf(ho[kk], vll, fmaf(go[kk], vlh, lodd));
@@ -338,11 +338,11 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
           hodd = fmaf(ho[kk], vhl, fmaf(go[kk], vhh, hodd));
         }
         lo[2 * rp][c] = le;
-        lo[2 * rp + 1][c] = lodd;
+        lo[MF_CHK(2 * rp + 1, to)][c] = lodd;
         hi[2 * rp][c] = hev;
         hi[2 * rp + 1][c] = hodd;
       }
-      lds_sync();
+      lds_barrier();
       // along the columns index, output pixels C0 + 2 cp and C0 + 2 cp + 1 of row r together
       // (same columns jb - kk of lo and hi, jb = cp + FMAX / 2)
 #pragma unroll
@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
         float xe = 0.f, xo = 0.f;
 #pragma unroll
         for (int kk = 0; kk < H; ++kk) {
-          const float vl = lo[r][jb - kk], vh = hi[r][jb - kk];
+          const float vl = lo[MF_CHK(r, to)][MF_CHK(jb - kk, CWA)], vh = hi[r][jb - kk];
           xe = fmaf(he[kk], vl, fmaf(ge[kk], vh, xe));
           xo = fmaf(ho[kk], vl, fmaf(go[kk], vh, xo));
         }
@@ -362,7 +362,8 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
           accv[q][0] += xe;
           accv[q][1] += xo;
         } else if (R0 + r < n && C0 + 2 * cp < n) {
-          float* o = a.llout + (long long)l * a.ll_cs + (long long)b * a.ll_bs + (long long)(R0 + r) * n + C0 + 2 * cp;
+          float* o = a.llout + (long long)l * a.ll_cs + (long long)b * a.ll_bs +
+                     MF_CHK((long long)(R0 + r) * n + C0 + 2 * cp, (long long)n * n - 1);
           o[0] = xe;
           o[1] = xo;
         }
@@ -377,7 +378,7 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
       if (i >= to * (to >> 1)) continue;
       const int r = div_small(i, inv_hto), cp = i - r * (to >> 1);
       if (R0 + r < n && C0 + 2 * cp < n) {
-        float* o = a.out + (long long)l * a.out_cs + (long long)(R0 + r) * a.N + C0 + 2 * cp;
+        float* o = a.out + (long long)l * a.out_cs + MF_CHK((long long)(R0 + r) * a.N + C0 + 2 * cp, (long long)a.N * a.N - 1);
         o[0] = a.scale * accv[q][0];
         o[1] = a.scale * accv[q][1];
       }
@@ -508,5 +509,9 @@ int launch_uob_adj(bool accum, const UobLevelArgs& a, int nch, hipStream_t st) {
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }
+
+#ifdef MF_CHECKED
+int oob_take_uob(unsigned long long* n) { return oob_take_here(n); }
+#endif
 
 }  // namespace mf

@@ -13,10 +13,11 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmuffin.so")
+# MUFFIN_LIBRARY selects another build of the same library (the checked build of the tests)
+LIB_PATH = os.environ.get("MUFFIN_LIBRARY") or os.path.join(_HERE, "libmuffin.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"libmuffin.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    raise ImportError(f"libmuffin not built at {LIB_PATH}; run __graft_entry__.build()")
 # torch is loaded first so that libmuffin binds to the HIP runtime torch already uses (both carry
 # the same soname): device pointers and streams are shared with torch.
 import torch  # noqa: E402,F401
@@ -37,6 +38,7 @@ EXPORTS = [
     "muffin_batch_step_timed", "muffin_batch_objective", "muffin_batch_get_x", "muffin_batch_info",
     "muffin_batch_autotune", "muffin_batch_free", "muffin_step_monitored", "muffin_snr", "muffin_batch_snr",
     "muffin_warm_input", "muffin_batch_set_x", "muffin_batch_warm_input", "muffin_uob_filter",
+    "muffin_debug_oob",
 ]
 
 
@@ -62,6 +64,7 @@ _lib.muffin_warm_input.argtypes = [_vp, _vp, ctypes.c_int]
 _lib.muffin_batch_set_x.argtypes = [_vp, _i32, _vp, ctypes.c_int]
 _lib.muffin_batch_warm_input.argtypes = [_vp, _i32, _vp, ctypes.c_int]
 _lib.muffin_uob_filter.argtypes = [_i32, ctypes.POINTER(_dbl), _i32]
+_lib.muffin_debug_oob.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
 _lib.muffin_objective.argtypes = [_vp, ctypes.POINTER(_dbl)]
 _lib.muffin_info.argtypes = [_vp, ctypes.POINTER(_dbl)]
 for _n in ("muffin_set_x", "muffin_get_x", "muffin_get_u", "muffin_get_v"):
@@ -536,3 +539,10 @@ def uob_filter(n: int) -> np.ndarray:
 
 def last_error() -> str:
     return _lib.muffin_last_error().decode(errors="replace")
+
+
+def debug_oob() -> int:
+    """Kernel indices caught out of bounds since the last call (checked builds only)."""
+    n = ctypes.c_uint64()
+    _check(_lib.muffin_debug_oob(ctypes.byref(n)), "muffin_debug_oob")
+    return int(n.value)
