@@ -8,6 +8,8 @@
 //   data     dx[p][c] = sum_{tap, o} W[o][c][tap] dz[p - tap][o]         the forward kernel with taps
 //                                                                          mirrored and W transposed
 //   weight   dW[tap][o][c] = sum_p dz[p][o] a[p + tap][c]                M = 32 o, N = 32 c, K = pixels
+// The forward edge layers use the same product: layer 1 with its nine taps as K (padded to 16),
+// layer 4 with its nine taps as the output columns (padded to 32) followed by a nine-point sum.
 // Operand lane layout of the 32x32x16 BF16 MFMA (checked on the device): A[i][k] sits in lane
 // i + 32 (k / 8), element k % 8; B[k][j] in lane j + 32 (k / 8), element k % 8; D[i][j] in lane
 // j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8).
@@ -35,43 +37,6 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 __device__ __forceinline__ float bfround(float f) { return bf2f(f2bf(f)); }
 __device__ __forceinline__ bool bf_pos(uint16_t h) { return h != 0 && (h & 0x8000u) == 0; }
 __device__ __forceinline__ int wrapn(int v, int N) { return v < 0 ? v + N : (v >= N ? v - N : v); }
-
-// ------------------------------------------------------------------ layer 1 (1 -> 32), VALU
-// z[o] = b[o] + sum_tap W1[tap][o] x[p + tap] with x rounded to BF16.
-// mode 0: a1 = bf16(relu(z)) NHWC; mode 1: z FP32 [B][32][N][N].
-__global__ void __launch_bounds__(256) k_conv1_fwd(const float* __restrict__ x, const float* __restrict__ w1b,
-                                                   const float* __restrict__ b1, uint16_t* __restrict__ a1,
-                                                   float* __restrict__ zout, int N, long long P, int mode) {
-  __shared__ float sw[9 * FC + FC];
-  for (int i = threadIdx.x; i < 9 * FC + FC; i += 256) sw[i] = i < 9 * FC ? w1b[i] : b1[i - 9 * FC];
-  __syncthreads();
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (p >= P) return;
-  const long long n2 = (long long)N * N;
-  const long long b = p / n2;
-  const int yx = (int)(p - b * n2), y = yx / N, xx = yx - y * N;
-  const float* xb = x + b * n2;
-  float v[9];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int yy = wrapn(y + t / 3 - 1, N), xq = wrapn(xx + t % 3 - 1, N);
-    v[t] = bfround(xb[(long long)yy * N + xq]);
-  }
-  u16x8 out[4];
-#pragma unroll
-  for (int o = 0; o < FC; ++o) {
-    float z = sw[9 * FC + o];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) z = fmaf(sw[t * FC + o], v[t], z);
-    if (mode == 0) out[o / 8][o % 8] = f2bf(fmaxf(z, 0.f));
-    else zout[((b * FC + o) * N + y) * (long long)N + xx] = z;
-  }
-  if (mode == 0) {
-    u16x8* dst = reinterpret_cast<u16x8*>(a1 + p * FC);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dst[q] = out[q];
-  }
-}
 
 // ------------------------------------------------------------------ 32 -> 32 layers, MFMA
 enum MmaMode { MM_ACT = 0, MM_Z = 1, MM_DMASK = 2, MM_DRAW = 3 };
@@ -171,11 +136,15 @@ __global__ void __launch_bounds__(256) k_conv_mma(const uint16_t* __restrict__ i
 
 // Forward activations, persistent: each workgroup stages the weights once and walks the tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's input loads are in flight while the
-// MFMAs of the current one run, into the other half of a double-buffered LDS tile.  (The other
+// MFMAs of the current one run, into the other half of a double-buffered LDS tile.  Its barriers
+// (and those of the persistent edge-layer kernels) order LDS only: a tile's output stores and the
+// next tile's loads stay in flight across them.  (The other
 // modes keep one tile per workgroup: there the double buffer and the prefetch registers would cut
 // the workgroups per CU from three to two.)
 constexpr int kConvBlocks = 512;  // two resident workgroups per CU
-unsigned conv_grid(long long tiles) { return (unsigned)(tiles < kConvBlocks ? tiles : kConvBlocks); }
+unsigned conv_grid(long long tiles, int blocks = kConvBlocks) { return (unsigned)(tiles < blocks ? tiles : blocks); }
+// the edge layers' persistent grids: as many workgroups as fit on a CU (LDS 21 KB and 39 KB)
+constexpr int kConv1Blocks = 256 * 6, kConv4Blocks = 256 * 4;
 
 __global__ void __launch_bounds__(256) k_conv_act(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wg,
                                                   const float* __restrict__ bias, uint16_t* __restrict__ out16, int N,
@@ -190,7 +159,7 @@ __global__ void __launch_bounds__(256) k_conv_act(const uint16_t* __restrict__ i
       *reinterpret_cast<u16x8*>(tin[0] + (k >> 2) * PSTR + (k & 3) * 8) = *tile_chunk(in, t, k, N);
   int cur = 0;
   for (; t < ntiles; t += gridDim.x) {
-    __syncthreads();  // the current tile is in place, and every wave is done with the other buffer
+    lds_barrier();  // the current tile is in place, and every wave is done with the other buffer
     const long long nt = t + gridDim.x;
     u16x8 pre[kTileLoads];
     if (nt < ntiles) {
@@ -209,6 +178,169 @@ __global__ void __launch_bounds__(256) k_conv_act(const uint16_t* __restrict__ i
       }
     }
     cur ^= 1;
+  }
+}
+
+// ------------------------------------------------------------------ edge layers on the MFMA
+// Tile t of the image batch: 8 rows x 32 pixels at (x0, y0) of image b.
+struct TileAt {
+  long long b;
+  int x0, y0;
+};
+__device__ __forceinline__ TileAt tile_at(long long t, int N) {
+  const int tiles_x = N / TPX, tiles_y = N / TROWS;
+  const long long rest = t / tiles_x;
+  return TileAt{rest / tiles_y, (int)(t % tiles_x) * TPX, (int)(rest % tiles_y) * TROWS};
+}
+
+// Layer 1 (1 -> 32): z[p][o] = b[o] + sum_tap W1[o][tap] bf16(x[p + tap]) as one 32x32x16 product
+// per 32-pixel row segment, A[i][k] = bf16(x[pixel i + offset of tap k]) (k < 9; zero for k >= 9),
+// B[k][j] = W1[j][tap k].  Persistent workgroups walk the 8-row x 32-pixel tiles (wave w: rows 2w,
+// 2w + 1); the next tile's haloed x is loaded while the current one is multiplied.
+// mode 0: a1 = bf16(relu(z)) NHWC, staged per wave in LDS so that every store is 16 bytes of one
+// pixel; mode 1: z FP32 [B][32][N][N].
+constexpr int kX1 = (TROWS + 2) * (TPX + 2);     // haloed x tile
+constexpr int kX1Loads = (kX1 + 255) / 256;
+__global__ void __launch_bounds__(256) k_conv1_mma(const float* __restrict__ x, const float* __restrict__ w1b,
+                                                   const float* __restrict__ b1, uint16_t* __restrict__ a1,
+                                                   float* __restrict__ zout, int N, int nimg, int mode) {
+  constexpr int TW = TPX + 2;
+  __shared__ uint16_t xs[kX1];
+  __shared__ __attribute__((aligned(16))) uint16_t os[4][2 * TPX * PSTR];  // per wave: 2 rows x 32 pixels
+  const long long ntiles = (long long)nimg * (N / TPX) * (N / TROWS);
+  const long long n2 = (long long)N * N;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 31, kb = (lane >> 5) * 8;  // this lane's k = kb .. kb + 7
+  u16x8 bv;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) bv[e] = kb + e < 9 ? f2bf(w1b[(kb + e) * FC + li]) : (uint16_t)0;
+  const float bias = b1[li];
+  float pre[kX1Loads];
+  auto fetch = [&](long long t) {
+    const TileAt ta = tile_at(t, N);
+    const float* xb = x + ta.b * n2;
+#pragma unroll
+    for (int m = 0; m < kX1Loads; ++m) {
+      int i = threadIdx.x + 256 * m;
+      i = i < kX1 ? i : kX1 - 1;
+      const int r = i / TW, c = i - r * TW;
+      pre[m] = xb[(long long)wrapn(ta.y0 + r - 1, N) * N + wrapn(ta.x0 + c - 1, N)];
+    }
+  };
+  long long t = blockIdx.x;
+  if (t < ntiles) fetch(t);
+  for (; t < ntiles; t += gridDim.x) {
+#pragma unroll
+    for (int m = 0; m < kX1Loads; ++m) {
+      const int i = threadIdx.x + 256 * m;
+      if (i < kX1) xs[i] = f2bf(pre[m]);
+    }
+    lds_barrier();
+    if (t + gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the products
+    const TileAt ta = tile_at(t, N);
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+      const int r = 2 * w + tt;  // output row within the tile
+      u16x8 av;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kb + e;  // tap k reads tile row r + k / 3, column li + k % 3 (halo offset +1)
+        av[e] = k < 9 ? xs[(r + k / 3) * TW + li + k % 3] : (uint16_t)0;
+      }
+      f32x16 acc = {};
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                    acc, 0, 0, 0);
+      const int y = ta.y0 + r;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int i = (e & 3) + 4 * (lane >> 5) + 8 * (e >> 2);  // pixel within the segment; channel li
+        const float v = acc[e] + bias;
+        if (mode == 0) os[w][(tt * TPX + i) * PSTR + li] = f2bf(fmaxf(v, 0.f));
+        else zout[((ta.b * FC + li) * N + y) * (long long)N + ta.x0 + i] = v;
+      }
+    }
+    if (mode == 0) {
+      // this wave's two rows: 64 pixels x four 16-byte chunks, read back across lanes
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ch = lane + 64 * q;  // chunk: pixel ch / 4 of the two rows, channels 8 (ch % 4) ..
+        const int px = ch >> 2, part = ch & 3;
+        const int y = ta.y0 + 2 * w + px / TPX;
+        const u16x8 v = *reinterpret_cast<const u16x8*>(&os[w][px * PSTR + part * 8]);
+        *reinterpret_cast<u16x8*>(a1 + (ta.b * n2 + (long long)y * N + ta.x0 + px % TPX) * FC + part * 8) = v;
+      }
+    }
+    lds_barrier();  // xs and os are rewritten for the next tile
+  }
+}
+
+// Layer 4 (32 -> 1): z[p] = b4 + sum_tap Y[p + offset(tap)][tap] with Y[q][tap] = sum_c W4[tap][c] a3[q][c].
+// Y of the tile's haloed 10 x 34 pixels comes from 32x32x16 products (A[i][k] = a3[pixel i][k] over
+// two halves of the 32 channels, B[k][j] = W4[tap j][k] for j < 9, zero beyond) into LDS; each
+// row of 34 takes two overlapping segments (columns 0..31 and 2..33, the second keeping 32 and 33).
+// Then one thread per output pixel adds the bias and its nine Y terms in tap order.  Persistent
+// workgroups; the next tile's activations are loaded while the current one is multiplied.
+__global__ void __launch_bounds__(256) k_conv4_mma(const uint16_t* __restrict__ a3, const float* __restrict__ w4b,
+                                                   const float* __restrict__ b4, float* __restrict__ z, int N,
+                                                   int nimg) {
+  constexpr int TW = TPX + 2, YS = 9;
+  __shared__ __attribute__((aligned(16))) uint16_t tin[(TROWS + 2) * TW * PSTR];
+  __shared__ float ys[(TROWS + 2) * TW * YS];
+  const long long ntiles = (long long)nimg * (N / TPX) * (N / TROWS);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 31, kh8 = (lane >> 5) * 8;
+  u16x8 bv[2];
+#pragma unroll
+  for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bv[kh][e] = li < 9 ? f2bf(w4b[li * FC + kh * 16 + kh8 + e]) : (uint16_t)0;
+  const float bias = b4[0];
+  u16x8 pre[kTileLoads];
+  auto fetch = [&](long long t) {
+#pragma unroll
+    for (int m = 0; m < kTileLoads; ++m) {
+      const int k = threadIdx.x + 256 * m;
+      pre[m] = *tile_chunk(a3, t, k < kTileChunks ? k : kTileChunks - 1, N);
+    }
+  };
+  long long t = blockIdx.x;
+  if (t < ntiles) fetch(t);
+  for (; t < ntiles; t += gridDim.x) {
+#pragma unroll
+    for (int m = 0; m < kTileLoads; ++m) {
+      const int k = threadIdx.x + 256 * m;
+      if (k < kTileChunks) *reinterpret_cast<u16x8*>(tin + (k >> 2) * PSTR + (k & 3) * 8) = pre[m];
+    }
+    lds_barrier();
+    if (t + gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the products
+    // (row, segment) items 0 .. 19, wave w takes w, w + 4, ...
+    for (int it = w; it < 2 * (TROWS + 2); it += 4) {
+      const int r = it >> 1, c0 = (it & 1) ? 2 : 0;
+      f32x16 acc = {};
+#pragma unroll
+      for (int kh = 0; kh < 2; ++kh) {
+        const u16x8 av = *reinterpret_cast<const u16x8*>(tin + (r * TW + c0 + li) * PSTR + kh * 16 + kh8);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                      __builtin_bit_cast(bf16x8, bv[kh]), acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int i = (e & 3) + 4 * (lane >> 5) + 8 * (e >> 2);  // pixel within the segment; tap li
+        if (li < 9 && (c0 == 0 || c0 + i >= TPX)) ys[(r * TW + c0 + i) * YS + li] = acc[e];
+      }
+    }
+    lds_barrier();
+    const TileAt ta = tile_at(t, N);
+    const int r = threadIdx.x / TPX, c = threadIdx.x % TPX;
+    float acc = bias;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) acc += ys[((r + tap / 3) * TW + c + tap % 3) * YS + tap];
+    z[ta.b * (long long)N * N + (long long)(ta.y0 + r) * N + ta.x0 + c] = acc;
+    // tin is rewritten next only after every wave has passed the barrier above (its products are
+    // done), ys only after the barrier that follows the next tile's store
   }
 }
 
@@ -287,33 +419,6 @@ __global__ void __launch_bounds__(192) k_wgrad_mma(const uint16_t* __restrict__ 
     }
   }
   if (w == 1 && lane < 32) pb[9 * FC * FC + lane] = dbacc;
-}
-
-// ------------------------------------------------------------------ layer 4 (32 -> 1), VALU
-// z[p] = b4 + sum_{tap, c} W4[tap][c] a3[p + tap][c]
-__global__ void __launch_bounds__(256) k_conv4_fwd(const uint16_t* __restrict__ a3, const float* __restrict__ w4b,
-                                                   const float* __restrict__ b4, float* __restrict__ z, int N,
-                                                   long long P) {
-  __shared__ float sw[9 * FC];
-  for (int i = threadIdx.x; i < 9 * FC; i += 256) sw[i] = w4b[i];
-  __syncthreads();
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (p >= P) return;
-  const long long n2 = (long long)N * N;
-  const long long b = p / n2;
-  const int yx = (int)(p - b * n2), y = yx / N, xx = yx - y * N;
-  float acc = b4[0];
-  for (int t = 0; t < 9; ++t) {
-    const int yy = wrapn(y + t / 3 - 1, N), xq = wrapn(xx + t % 3 - 1, N);
-    const u16x8* src = reinterpret_cast<const u16x8*>(a3 + (b * n2 + (long long)yy * N + xq) * FC);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const u16x8 v = src[q];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) acc = fmaf(sw[t * FC + q * 8 + e], bf2f(v[e]), acc);
-    }
-  }
-  z[p] = acc;
 }
 
 // dz4 = bf16(2 (z - t) / M); partial[block] = sum (z - t)^2 (FP64)
@@ -587,15 +692,15 @@ unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
 // forward of P pixels (B images) from FP32 input planes into the activation planes a1, a2, a3
 // (BF16, 32 features per pixel; a3 may be a1, which layer 3 no longer reads) and the output z
 int forward_into(muffin_cnn* c, const float* x, int B, int N, uint16_t* a1, uint16_t* a2, uint16_t* a3, float* z) {
-  const long long P = (long long)B * N * N;
   const unsigned tiles = (unsigned)((long long)B * (N / TPX) * (N / TROWS));
-  hipLaunchKernelGGL(k_conv1_fwd, dim3(nb256(P)), dim3(256), 0, c->st, x, c->w1b, c->prm + CnnOffsets::b1, a1,
-                     (float*)nullptr, N, P, 0);
+  hipLaunchKernelGGL(k_conv1_mma, dim3(conv_grid(tiles, kConv1Blocks)), dim3(256), 0, c->st, x, c->w1b, c->prm + CnnOffsets::b1,
+                     a1, (float*)nullptr, N, B, 0);
   hipLaunchKernelGGL(k_conv_act, dim3(conv_grid(tiles)), dim3(256), 0, c->st, a1, c->w2f, c->prm + CnnOffsets::b2, a2,
                      N, B);
   hipLaunchKernelGGL(k_conv_act, dim3(conv_grid(tiles)), dim3(256), 0, c->st, a2, c->w3f, c->prm + CnnOffsets::b3, a3,
                      N, B);
-  hipLaunchKernelGGL(k_conv4_fwd, dim3(nb256(P)), dim3(256), 0, c->st, a3, c->w4b, c->prm + CnnOffsets::b4, z, N, P);
+  hipLaunchKernelGGL(k_conv4_mma, dim3(conv_grid(tiles, kConv4Blocks)), dim3(256), 0, c->st, a3, c->w4b, c->prm + CnnOffsets::b4,
+                     z, N, B);
   MF_HIP(hipGetLastError());
   return MUFFIN_OK;
 }
@@ -889,11 +994,11 @@ int muffin_cnn_layer(muffin_cnn* c, int32_t layer, int32_t op, const float* x, c
   }
   if (op == 0) {
     if (layer == 1)
-      hipLaunchKernelGGL(k_conv1_fwd, dim3(nb256(P)), dim3(256), 0, c->st, c->xin, c->w1b, c->prm + CnnOffsets::b1,
-                         (uint16_t*)nullptr, out, N, P, 1);
+      hipLaunchKernelGGL(k_conv1_mma, dim3(conv_grid(tiles, kConv1Blocks)), dim3(256), 0, c->st, c->xin, c->w1b,
+                         c->prm + CnnOffsets::b1, (uint16_t*)nullptr, out, N, B, 1);
     else if (layer == 4)
-      hipLaunchKernelGGL(k_conv4_fwd, dim3(nb256(P)), dim3(256), 0, c->st, c->a2, c->w4b, c->prm + CnnOffsets::b4, out,
-                         N, P);
+      hipLaunchKernelGGL(k_conv4_mma, dim3(conv_grid(tiles, kConv4Blocks)), dim3(256), 0, c->st, c->a2, c->w4b,
+                         c->prm + CnnOffsets::b4, out, N, B);
     else
       hipLaunchKernelGGL((k_conv_mma<MM_Z>), dim3(tiles), dim3(256), 0, c->st, c->a2, layer == 2 ? c->w2f : c->w3f,
                          c->prm + (layer == 2 ? CnnOffsets::b2 : CnnOffsets::b3), (const uint16_t*)nullptr,
