@@ -68,8 +68,51 @@ __device__ __forceinline__ void stage_weights(uint16_t* tw, const uint16_t* wg) 
   }
 }
 
-// The MFMA sums of tile t (8 rows of 32 pixels x 32 outputs: wave w owns rows 2w, 2w + 1) from
-// its haloed input tile tc and the weights tw, both in LDS, and the epilogue of MODE.
+// The MFMA sums of output row r of a tile (32 pixels x 32 outputs) from its haloed input tile tc
+// and the weights tw, both in LDS.
+__device__ __forceinline__ f32x16 conv_row(const uint16_t* tc, const uint16_t* tw, int r) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 31, kh8 = (lane >> 5) * 8;
+  f32x16 acc = {};
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3, dx = tap % 3;  // input offset +1 (halo)
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+      const u16x8 av = *reinterpret_cast<const u16x8*>(tc + ((r + dy) * (TPX + 2) + li + dx) * PSTR + kh * 16 + kh8);
+      const u16x8 bv = *reinterpret_cast<const u16x8*>(tw + (tap * FC + li) * PSTR + kh * 16 + kh8);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                    acc, 0, 0, 0);
+    }
+  }
+  return acc;
+}
+
+// The same for the two output rows r0 and r0 + 1 together: each weight operand read feeds both rows.
+__device__ __forceinline__ void conv_rows2(const uint16_t* tc, const uint16_t* tw, int r0, f32x16 (&acc)[2]) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 31, kh8 = (lane >> 5) * 8;
+  acc[0] = f32x16{};
+  acc[1] = f32x16{};
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3, dx = tap % 3;  // input offset +1 (halo)
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+      const u16x8 bv = *reinterpret_cast<const u16x8*>(tw + (tap * FC + li) * PSTR + kh * 16 + kh8);
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) {
+        const u16x8 av =
+            *reinterpret_cast<const u16x8*>(tc + ((r0 + tt + dy) * (TPX + 2) + li + dx) * PSTR + kh * 16 + kh8);
+        acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                          __builtin_bit_cast(bf16x8, bv), acc[tt], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// The MFMA sums of tile t (8 rows of 32 pixels x 32 outputs: wave w owns rows 2w, 2w + 1) and the
+// epilogue of MODE.
 template <int MODE>
 __device__ __forceinline__ void conv_tile(const uint16_t* tc, const uint16_t* tw, long long t,
                                           const float* __restrict__ bias, const uint16_t* __restrict__ mask,
@@ -82,22 +125,11 @@ __device__ __forceinline__ void conv_tile(const uint16_t* tc, const uint16_t* tw
   const int x0 = tx * TPX, y0 = ty * TROWS;
   const long long n2 = (long long)N * N;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int li = lane & 31, kh8 = (lane >> 5) * 8;
+  const int li = lane & 31;
 #pragma unroll
   for (int tt = 0; tt < 2; ++tt) {
     const int r = 2 * w + tt;  // output row within the tile
-    f32x16 acc = {};
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const int dy = tap / 3, dx = tap % 3;  // input offset +1 (halo)
-#pragma unroll
-      for (int kh = 0; kh < 2; ++kh) {
-        const u16x8 av = *reinterpret_cast<const u16x8*>(tc + ((r + dy) * (TPX + 2) + li + dx) * PSTR + kh * 16 + kh8);
-        const u16x8 bv = *reinterpret_cast<const u16x8*>(tw + (tap * FC + li) * PSTR + kh * 16 + kh8);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
-                                                      acc, 0, 0, 0);
-      }
-    }
+    const f32x16 acc = conv_row(tc, tw, r);
     const int y = y0 + r;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -118,6 +150,17 @@ __device__ __forceinline__ void conv_tile(const uint16_t* tc, const uint16_t* tw
   }
 }
 
+// Tile t of the image batch: 8 rows x 32 pixels at (x0, y0) of image b.
+struct TileAt {
+  long long b;
+  int x0, y0;
+};
+__device__ __forceinline__ TileAt tile_at(long long t, int N) {
+  const int tiles_x = N / TPX, tiles_y = N / TROWS;
+  const long long rest = t / tiles_x;
+  return TileAt{rest / tiles_y, (int)(t % tiles_x) * TPX, (int)(rest % tiles_y) * TROWS};
+}
+
 // One tile per workgroup (the backward and single-layer modes).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_conv_mma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wg,
@@ -136,63 +179,73 @@ __global__ void __launch_bounds__(256) k_conv_mma(const uint16_t* __restrict__ i
 
 // Forward activations, persistent: each workgroup stages the weights once and walks the tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's input loads are in flight while the
-// MFMAs of the current one run, into the other half of a double-buffered LDS tile.  Its barriers
-// (and those of the persistent edge-layer kernels) order LDS only: a tile's output stores and the
-// next tile's loads stay in flight across them.  (The other
-// modes keep one tile per workgroup: there the double buffer and the prefetch registers would cut
-// the workgroups per CU from three to two.)
-constexpr int kConvBlocks = 512;  // two resident workgroups per CU
+// MFMAs of the current one run, in registers.  Its barriers (and those of the persistent edge-layer
+// kernels) order LDS only: a tile's output stores and the next tile's loads stay in flight across
+// them.  (The other modes keep one tile per workgroup.)
+constexpr int kConvBlocks = 768;  // three resident workgroups per CU
 unsigned conv_grid(long long tiles, int blocks = kConvBlocks) { return (unsigned)(tiles < blocks ? tiles : blocks); }
 // the edge layers' persistent grids: as many workgroups as fit on a CU (LDS 21 KB and 39 KB)
 constexpr int kConv1Blocks = 256 * 6, kConv4Blocks = 256 * 4;
 
-__global__ void __launch_bounds__(256) k_conv_act(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wg,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_conv_act(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wg,
                                                   const float* __restrict__ bias, uint16_t* __restrict__ out16, int N,
                                                   int nimg) {
-  __shared__ __attribute__((aligned(16))) uint16_t tin[2][(TROWS + 2) * (TPX + 2) * PSTR];
+  // one tile buffer (50 KB of LDS with the weights: three workgroups per CU); the next tile waits
+  // in registers until every wave is done with the current one
+  __shared__ __attribute__((aligned(16))) uint16_t tin[(TROWS + 2) * (TPX + 2) * PSTR];
   __shared__ __attribute__((aligned(16))) uint16_t tw[9 * FC * PSTR];
   const long long ntiles = (long long)nimg * (N / TPX) * (N / TROWS);
   stage_weights(tw, wg);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 31;
+  const float bj = bias[li];
+  u16x8 pre[kTileLoads];
+  auto fetch = [&](long long tt) {
+#pragma unroll
+    for (int m = 0; m < kTileLoads; ++m) {
+      const int k = threadIdx.x + 256 * m;
+      pre[m] = *tile_chunk(in, tt, k < kTileChunks ? k : kTileChunks - 1, N);
+    }
+  };
   long long t = blockIdx.x;
-  if (t < ntiles)
-    for (int k = threadIdx.x; k < kTileChunks; k += 256)
-      *reinterpret_cast<u16x8*>(tin[0] + (k >> 2) * PSTR + (k & 3) * 8) = *tile_chunk(in, t, k, N);
-  int cur = 0;
+  if (t < ntiles) fetch(t);
   for (; t < ntiles; t += gridDim.x) {
-    lds_barrier();  // the current tile is in place, and every wave is done with the other buffer
-    const long long nt = t + gridDim.x;
-    u16x8 pre[kTileLoads];
-    if (nt < ntiles) {
 #pragma unroll
-      for (int m = 0; m < kTileLoads; ++m) {
-        const int k = threadIdx.x + 256 * m;
-        if (k < kTileChunks) pre[m] = *tile_chunk(in, nt, k, N);
-      }
+    for (int m = 0; m < kTileLoads; ++m) {
+      const int k = threadIdx.x + 256 * m;
+      if (k < kTileChunks) *reinterpret_cast<u16x8*>(tin + (k >> 2) * PSTR + (k & 3) * 8) = pre[m];
     }
-    conv_tile<MM_ACT>(tin[cur], tw, t, bias, nullptr, out16, nullptr, N);
-    if (nt < ntiles) {
+    lds_barrier();  // the tile is in place
+    if (t + gridDim.x < ntiles) fetch(t + gridDim.x);  // in flight during the products
+    f32x16 acc[2];
+    conv_rows2(tin, tw, 2 * w, acc);
+    lds_barrier();  // every wave is done reading the tile: it now stages the outputs
+    // this wave's two rows, 64 pixels x 32 channels (BF16, pixel stride PSTR), then 16-byte stores
+    // of one pixel's 8 channels
+    uint16_t* os = tin + w * 2 * TPX * PSTR;
 #pragma unroll
-      for (int m = 0; m < kTileLoads; ++m) {
-        const int k = threadIdx.x + 256 * m;
-        if (k < kTileChunks) *reinterpret_cast<u16x8*>(tin[cur ^ 1] + (k >> 2) * PSTR + (k & 3) * 8) = pre[m];
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int i = (e & 3) + 4 * (lane >> 5) + 8 * (e >> 2);  // pixel within the segment; channel li
+        os[(tt * TPX + i) * PSTR + li] = f2bf(fmaxf(acc[tt][e] + bj, 0.f));
       }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    const TileAt ta = tile_at(t, N);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = lane + 64 * q;  // pixel ch / 4 of the two rows, channels 8 (ch % 4) ..
+      const int px = ch >> 2, part = ch & 3;
+      const int y = ta.y0 + 2 * w + px / TPX;
+      *reinterpret_cast<u16x8*>(out16 + (ta.b * (long long)N * N + (long long)y * N + ta.x0 + px % TPX) * FC +
+                                part * 8) = *reinterpret_cast<const u16x8*>(os + px * PSTR + part * 8);
     }
-    cur ^= 1;
+    lds_barrier();  // every wave is done with its staged outputs before the next tile overwrites them
   }
 }
 
 // ------------------------------------------------------------------ edge layers on the MFMA
-// Tile t of the image batch: 8 rows x 32 pixels at (x0, y0) of image b.
-struct TileAt {
-  long long b;
-  int x0, y0;
-};
-__device__ __forceinline__ TileAt tile_at(long long t, int N) {
-  const int tiles_x = N / TPX, tiles_y = N / TROWS;
-  const long long rest = t / tiles_x;
-  return TileAt{rest / tiles_y, (int)(t % tiles_x) * TPX, (int)(rest % tiles_y) * TROWS};
-}
-
 // Layer 1 (1 -> 32): z[p][o] = b[o] + sum_tap W1[o][tap] bf16(x[p + tap]) as one 32x32x16 product
 // per 32-pixel row segment, A[i][k] = bf16(x[pixel i + offset of tap k]) (k < 9; zero for k >= 9),
 // B[k][j] = W1[j][tap k].  Persistent workgroups walk the 8-row x 32-pixel tiles (wave w: rows 2w,
