@@ -245,6 +245,96 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   }
 }
 
+// Inference, layers 1 and 2 in one pass: layer 1 is computed on the haloed 10 x 34 tile of a1 from a
+// 12 x 36 tile of x (MFMA as in k_conv1_mma, two overlapping 32-pixel segments per row) straight
+// into LDS, and layer 2 reads it there as k_conv_act reads its input tile; a1 never reaches
+// memory.  Every product and rounding is the one of the separate kernels, so a2 is the same bit for
+// bit.  Persistent, with the next tile's x in registers.
+constexpr int kX12 = (TROWS + 4) * (TPX + 4);  // haloed x tile of the fused pass
+constexpr int kX12Loads = (kX12 + 255) / 256;
+__global__ void __launch_bounds__(256) k_conv12_act(const float* __restrict__ x, const float* __restrict__ w1b,
+                                                    const float* __restrict__ b1, const uint16_t* __restrict__ wg,
+                                                    const float* __restrict__ b2, uint16_t* __restrict__ out16, int N,
+                                                    int nimg) {
+  constexpr int XW = TPX + 4, TW = TPX + 2;
+  __shared__ uint16_t xs[kX12];
+  __shared__ __attribute__((aligned(16))) uint16_t tin[(TROWS + 2) * TW * PSTR];
+  __shared__ __attribute__((aligned(16))) uint16_t tw[9 * FC * PSTR];
+  const long long ntiles = (long long)nimg * (N / TPX) * (N / TROWS);
+  const long long n2 = (long long)N * N;
+  stage_weights(tw, wg);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 31, kb = (lane >> 5) * 8;
+  u16x8 bv1;  // layer 1: B[k][j] = W1[j][tap k]
+#pragma unroll
+  for (int e = 0; e < 8; ++e) bv1[e] = kb + e < 9 ? f2bf(w1b[(kb + e) * FC + li]) : (uint16_t)0;
+  const float bias1 = b1[li], bias2 = b2[li];
+  float pre[kX12Loads];
+  auto fetch = [&](long long tt) {
+    const TileAt ta = tile_at(tt, N);
+    const float* xb = x + ta.b * n2;
+#pragma unroll
+    for (int m = 0; m < kX12Loads; ++m) {
+      int i = threadIdx.x + 256 * m;
+      i = i < kX12 ? i : kX12 - 1;
+      const int r = i / XW, c = i - r * XW;
+      pre[m] = xb[(long long)wrapn(ta.y0 + r - 2, N) * N + wrapn(ta.x0 + c - 2, N)];
+    }
+  };
+  long long t = blockIdx.x;
+  if (t < ntiles) fetch(t);
+  for (; t < ntiles; t += gridDim.x) {
+#pragma unroll
+    for (int m = 0; m < kX12Loads; ++m) {
+      const int i = threadIdx.x + 256 * m;
+      if (i < kX12) xs[i] = f2bf(pre[m]);
+    }
+    lds_barrier();  // x is in place, and every wave is done with the previous tile's outputs
+    if (t + gridDim.x < ntiles) fetch(t + gridDim.x);
+    // layer 1 on a1 rows 0..9 (image rows y0 - 1 ..), columns 0..33, items (row, segment)
+    for (int it = w; it < 2 * (TROWS + 2); it += 4) {
+      const int r = it >> 1, c0 = (it & 1) ? 2 : 0;
+      u16x8 av;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kb + e;  // a1 (r, c0 + li) reads x tile row r + k / 3, column c0 + li + k % 3
+        av[e] = k < 9 ? xs[(r + k / 3) * XW + c0 + li + k % 3] : (uint16_t)0;
+      }
+      f32x16 a = {};
+      a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv1), a,
+                                                  0, 0, 0);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int i = (e & 3) + 4 * (lane >> 5) + 8 * (e >> 2);  // pixel c0 + i of the row; channel li
+        if (c0 == 0 || c0 + i >= TPX) tin[(r * TW + c0 + i) * PSTR + li] = f2bf(fmaxf(a[e] + bias1, 0.f));
+      }
+    }
+    lds_barrier();  // a1 is in place
+    f32x16 acc[2];
+    conv_rows2(tin, tw, 2 * w, acc);
+    lds_barrier();  // every wave is done reading a1: the tile now stages the outputs
+    uint16_t* os = tin + w * 2 * TPX * PSTR;
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int i = (e & 3) + 4 * (lane >> 5) + 8 * (e >> 2);
+        os[(tt * TPX + i) * PSTR + li] = f2bf(fmaxf(acc[tt][e] + bias2, 0.f));
+      }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    const TileAt ta = tile_at(t, N);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ch = lane + 64 * q;
+      const int px = ch >> 2, part = ch & 3;
+      const int y = ta.y0 + 2 * w + px / TPX;
+      *reinterpret_cast<u16x8*>(out16 + (ta.b * n2 + (long long)y * N + ta.x0 + px % TPX) * FC + part * 8) =
+          *reinterpret_cast<const u16x8*>(os + px * PSTR + part * 8);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ edge layers on the MFMA
 // Layer 1 (1 -> 32): z[p][o] = b[o] + sum_tap W1[o][tap] bf16(x[p + tap]) as one 32x32x16 product
 // per 32-pixel row segment, A[i][k] = bf16(x[pixel i + offset of tap k]) (k < 9; zero for k >= 9),
@@ -758,6 +848,20 @@ int forward_into(muffin_cnn* c, const float* x, int B, int N, uint16_t* a1, uint
   return MUFFIN_OK;
 }
 
+// inference of B images: layers 1 and 2 in one pass into a2, layer 3 into a3 (may alias nothing
+// else the pass reads), layer 4 into z; a1 is never formed
+int forward_infer(muffin_cnn* c, const float* x, int B, int N, uint16_t* a2, uint16_t* a3, float* z) {
+  const unsigned tiles = (unsigned)((long long)B * (N / TPX) * (N / TROWS));
+  hipLaunchKernelGGL(k_conv12_act, dim3(conv_grid(tiles)), dim3(256), 0, c->st, x, c->w1b, c->prm + CnnOffsets::b1,
+                     c->w2f, c->prm + CnnOffsets::b2, a2, N, B);
+  hipLaunchKernelGGL(k_conv_act, dim3(conv_grid(tiles)), dim3(256), 0, c->st, a2, c->w3f, c->prm + CnnOffsets::b3, a3,
+                     N, B);
+  hipLaunchKernelGGL(k_conv4_mma, dim3(conv_grid(tiles, kConv4Blocks)), dim3(256), 0, c->st, a3, c->w4b,
+                     c->prm + CnnOffsets::b4, z, N, B);
+  MF_HIP(hipGetLastError());
+  return MUFFIN_OK;
+}
+
 // forward with the network's own workspaces; activations kept for training
 int forward(muffin_cnn* c, const float* x, int B, int N) { return forward_into(c, x, B, N, c->a1, c->a2, c->a3, c->z4); }
 
@@ -950,8 +1054,7 @@ int muffin_cnn_predict(muffin_cnn* c, const float* in, float* out, int32_t B, in
   MF_TRY(ensure_ws(c, chunk * n2));
   for (long long b0 = 0; b0 < B; b0 += chunk) {
     const int nb = (int)((B - b0) < chunk ? (B - b0) : chunk);
-    MF_TRY(forward(c, in + b0 * n2, nb, N));
-    MF_HIP(hipMemcpyAsync(out + b0 * n2, c->z4, sizeof(float) * nb * n2, hipMemcpyDeviceToDevice, c->st));
+    MF_TRY(forward_infer(c, in + b0 * n2, nb, N, c->a2, c->a1, out + b0 * n2));
   }
   return MUFFIN_OK;
 }
@@ -971,7 +1074,7 @@ int muffin_cnn_predict_noalloc(muffin_cnn* c, const float* in, float* out, int32
   const long long chunk = (kNoAllocPixels / n2) < B ? (kNoAllocPixels / n2) : B;
   for (long long b0 = 0; b0 < B; b0 += chunk) {
     const int nb = (int)((B - b0) < chunk ? (B - b0) : chunk);
-    MF_TRY(forward_into(c, in + b0 * n2, nb, N, a1, a2, a1, out + b0 * n2));
+    MF_TRY(forward_infer(c, in + b0 * n2, nb, N, a2, a1, out + b0 * n2));
   }
   return MUFFIN_OK;
 }

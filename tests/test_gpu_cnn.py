@@ -64,6 +64,27 @@ def test_network_loss_and_gradient(lib, net):
     assert rel(pred, out[:, 0]) < 2e-3
 
 
+def bf16_round(a):
+    """FP32 -> nearest BF16 (ties to even), returned as FP32."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32)
+
+
+def test_inference_equals_the_layer_chain_bitwise(lib, net):
+    """predict runs layers 1 and 2 in one pass (a1 stays in LDS); chaining the single-layer launches
+    on the host, with the same ReLU and BF16 rounding between them, must give the same bits."""
+    B, N = 2, 64
+    x = np.abs(rnd((B, N, N), 41)).astype(np.float32)
+    pred = net.predict(x).cpu().numpy()
+    a = x[:, None]
+    for layer in (1, 2, 3):
+        z = net.layer(layer, 0, a).cpu().numpy()
+        a = bf16_round(np.maximum(z, 0.0))
+    z4 = net.layer(4, 0, a).cpu().numpy()[:, 0]
+    np.testing.assert_array_equal(pred, z4)
+
+
 def test_adam_steps_match_oracle(lib):
     """Four Adam steps (Kingma and Ba's recursion with bias correction, beta 0.9 / 0.999): the
     parameters after each step against the oracle's update chained from the same gradients, with
