@@ -386,7 +386,7 @@ def main():
                                              f"iterations of the same sample, autotuned band rows and fused "
                                              f"tail as timed, and the relative objective error"}}
     line = {
-        "metric": "voxel-iterations/s on 1024^2x256 cube (MUFFIN primal-dual iteration)",
+        "metric": f"voxel-iterations/s on {N}^2x{L} cube (MUFFIN primal-dual iteration)",
         "value": value,
         "unit": "voxel-iter/s",
         "n_gpus": 1,
@@ -422,7 +422,7 @@ def bench_uob(args, m, spec):
     b_alg = 40.0 + 8.0 * 8 + 2.0 * (N + 2) / N
     m.close()
     line = {
-        "metric": "voxel-iterations/s on 1024^2x256 cube, union-of-bases prior (8 Daubechies bases)",
+        "metric": f"voxel-iterations/s on {N}^2x{L} cube, union-of-bases prior (8 Daubechies bases)",
         "value": vox * args.steps / (dev_ms / 1e3),
         "unit": "voxel-iter/s",
         "n_gpus": 1,
