@@ -12,10 +12,10 @@
 //   x[p] = sum over k with p - k even of h_k a[(p - k) / 2 mod m] + g_k d[(p - k) / 2 mod m].
 //
 // One launch per level.  The analysis launch of level 1 loads a tile of d once and runs all eight
-// bases on it; later levels read each basis's approximation from scratch.  The dual step of
-// eq. (anaylsespat) is fused into the analysis epilogue: u <- rho sat(u + coef w) + (1 - rho) u with
-// coef = sigma mu_s / sqrt(8).  The adjoint's finest level sums the eight bases in registers and
-// writes W_s^dagger u once.
+// bases on it; later levels read each basis's approximation, which the previous level wrote to a
+// work buffer.  The dual step of eq. (anaylsespat) is fused into the analysis epilogue:
+// u <- rho sat(u + coef w) + (1 - rho) u with coef = sigma mu_s / sqrt(8).  The adjoint's finest
+// level sums the eight bases in registers and writes W_s^dagger u once.
 //
 // Filters are built on the host from Daubechies' construction: the roots y_k of
 // P_n(y) = sum_{k<n} C(n-1+k, k) y^k (Durand-Kerner iteration in long double), each mapped to the
