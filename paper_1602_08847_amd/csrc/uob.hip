@@ -39,7 +39,8 @@ constexpr int TA = 64;                      // output pixels per adjoint tile si
 constexpr int CWA = TA / 2 + FMAX / 2 + 1;  // coefficient rows / columns of an adjoint tile
 constexpr int NOUT = (TO * TO + 255) / 256; // analysis outputs per thread
 constexpr int NLD = (SA * SA + 255) / 256;  // analysis tile entries per thread
-constexpr int NPP = (TA * TA / 2 + 255) / 256;  // adjoint output pixel pairs per thread
+constexpr int NPPH = (TA / 2 * TA / 2 + 255) / 256;  // adjoint output pixel pairs per thread and half tile
+constexpr int NPP = 2 * NPPH;                          // ... and per tile
 constexpr int kUobAllBasesBlocks = 2048;  // blocks a level needs before one block runs all bases
 
 __device__ __forceinline__ float satf_u(float u) { return fminf(1.f, fmaxf(-1.f, u)); }
@@ -260,9 +261,10 @@ __global__ void __launch_bounds__(256) k_uob_an(UobLevelArgs a) {
 template <bool ACCUM>
 __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
   __shared__ float cf[4][CWA][CWA + 1];  // LL, LH, HL, HH coefficient tiles
-  __shared__ float lo[TA][CWA + 1], hi[TA][CWA + 1];
+  __shared__ float lo[TA / 2][CWA + 1], hi[TA / 2][CWA + 1];  // one half of the tile's rows
   const int m = a.n >> 1, n = a.n;
   const int to = n < TA ? n : TA;
+  const int HR = ((to >> 1) + 1) & ~1;  // output rows per half (even; TA / 2 for full tiles)
   const float inv_hto = 1.f / (float)(to >> 1);
   const int tiles_x = (n + to - 1) / to;
   const int R0 = (blockIdx.x / tiles_x) * to, C0 = (blockIdx.x % tiles_x) * to;
@@ -322,51 +324,59 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
         he[kk] = a.f.h[b][2 * kk], ho[kk] = a.f.h[b][2 * kk + 1];
         ge[kk] = a.f.g[b][2 * kk], go[kk] = a.f.g[b][2 * kk + 1];
       }
-      // along the rows index, output rows R0 + 2 rp and R0 + 2 rp + 1 together (same coefficient
-      // rows ib - kk, ib = rp + FMAX / 2): lo from (LL, LH), hi from (HL, HH)
-      for (int i = tid; i < (to >> 1) * CWA; i += 256) {
-        const int rp = i / CWA, c = i - rp * CWA;
-        const int ib = rp + FMAX / 2;
-        float le = 0.f, lodd = 0.f, hev = 0.f, hodd = 0.f;
+      // two halves of HR output rows each, so that lo and hi hold HR rows (a quarter of the LDS)
 #pragma unroll
-        for (int kk = 0; kk < H; ++kk) {
-          const float vll = cf[0][MF_CHK(ib - kk, CWA)][MF_CHK(c, CWA)], vlh = cf[1][ib - kk][c];
-          const float vhl = cf[2][ib - kk][c], vhh = cf[3][ib - kk][c];
-          le = fmaf(he[kk], vll, fmaf(ge[kk], vlh, le));
-          lodd = fmaf(ho[kk], vll, fmaf(go[kk], vlh, lodd));
-          hev = fmaf(he[kk], vhl, fmaf(ge[kk], vhh, hev));
-          hodd = fmaf(ho[kk], vhl, fmaf(go[kk], vhh, hodd));
-        }
-        lo[2 * rp][c] = le;
-        lo[MF_CHK(2 * rp + 1, to)][c] = lodd;
-        hi[2 * rp][c] = hev;
-        hi[2 * rp + 1][c] = hodd;
-      }
-      lds_barrier();
-      // along the columns index, output pixels C0 + 2 cp and C0 + 2 cp + 1 of row r together
-      // (same columns jb - kk of lo and hi, jb = cp + FMAX / 2)
+      for (int h = 0; h < 2; ++h) {
+        // along the rows index, output rows R0 + 2 rp and R0 + 2 rp + 1 together (same coefficient
+        // rows ib - kk, ib = rp + FMAX / 2): lo from (LL, LH), hi from (HL, HH)
+        for (int i = tid; i < (HR >> 1) * CWA; i += 256) {
+          const int rl = i / CWA, c = i - rl * CWA;  // row pair within the half
+          const int rp = h * (HR >> 1) + rl;
+          if (2 * rp >= to) break;
+          const int ib = rp + FMAX / 2;
+          float le = 0.f, lodd = 0.f, hev = 0.f, hodd = 0.f;
 #pragma unroll
-      for (int q = 0; q < NPP; ++q) {
-        const int i = tid + 256 * q;
-        if (i >= to * (to >> 1)) continue;
-        const int r = div_small(i, inv_hto), cp = i - r * (to >> 1);
-        const int jb = cp + FMAX / 2;
-        float xe = 0.f, xo = 0.f;
+          for (int kk = 0; kk < H; ++kk) {
+            const float vll = cf[0][MF_CHK(ib - kk, CWA)][MF_CHK(c, CWA)], vlh = cf[1][ib - kk][c];
+            const float vhl = cf[2][ib - kk][c], vhh = cf[3][ib - kk][c];
+            le = fmaf(he[kk], vll, fmaf(ge[kk], vlh, le));
+            lodd = fmaf(ho[kk], vll, fmaf(go[kk], vlh, lodd));
+            hev = fmaf(he[kk], vhl, fmaf(ge[kk], vhh, hev));
+            hodd = fmaf(ho[kk], vhl, fmaf(go[kk], vhh, hodd));
+          }
+          lo[2 * rl][c] = le;
+          lo[MF_CHK(2 * rl + 1, HR)][c] = lodd;
+          hi[2 * rl][c] = hev;
+          hi[2 * rl + 1][c] = hodd;
+        }
+        lds_barrier();
+        // along the columns index, output pixels C0 + 2 cp and C0 + 2 cp + 1 of row r together
+        // (same columns jb - kk of lo and hi, jb = cp + FMAX / 2)
 #pragma unroll
-        for (int kk = 0; kk < H; ++kk) {
-          const float vl = lo[MF_CHK(r, to)][MF_CHK(jb - kk, CWA)], vh = hi[r][jb - kk];
-          xe = fmaf(he[kk], vl, fmaf(ge[kk], vh, xe));
-          xo = fmaf(ho[kk], vl, fmaf(go[kk], vh, xo));
+        for (int q = 0; q < NPPH; ++q) {
+          const int i = tid + 256 * q;
+          const int rl = div_small(i, inv_hto), cp = i - rl * (to >> 1);
+          const int r = h * HR + rl;
+          if (rl >= HR || r >= to) continue;
+          const int jb = cp + FMAX / 2;
+          float xe = 0.f, xo = 0.f;
+#pragma unroll
+          for (int kk = 0; kk < H; ++kk) {
+            const float vl = lo[MF_CHK(rl, HR)][MF_CHK(jb - kk, CWA)], vh = hi[rl][jb - kk];
+            xe = fmaf(he[kk], vl, fmaf(ge[kk], vh, xe));
+            xo = fmaf(ho[kk], vl, fmaf(go[kk], vh, xo));
+          }
+          if (ACCUM) {
+            accv[h * NPPH + q][0] += xe;
+            accv[h * NPPH + q][1] += xo;
+          } else if (R0 + r < n && C0 + 2 * cp < n) {
+            float* o = a.llout + (long long)l * a.ll_cs + (long long)b * a.ll_bs +
+                       MF_CHK((long long)(R0 + r) * n + C0 + 2 * cp, (long long)n * n - 1);
+            o[0] = xe;
+            o[1] = xo;
+          }
         }
-        if (ACCUM) {
-          accv[q][0] += xe;
-          accv[q][1] += xo;
-        } else if (R0 + r < n && C0 + 2 * cp < n) {
-          float* o = a.llout + (long long)l * a.ll_cs + (long long)b * a.ll_bs +
-                     MF_CHK((long long)(R0 + r) * n + C0 + 2 * cp, (long long)n * n - 1);
-          o[0] = xe;
-          o[1] = xo;
-        }
+        if (h == 0) lds_barrier();  // the second half rewrites lo and hi
       }
     });
     // lo and hi are next written after the barrier that follows the next basis's tile store
@@ -374,9 +384,10 @@ __global__ void __launch_bounds__(256) k_uob_adj(UobLevelArgs a) {
   if (ACCUM) {
 #pragma unroll
     for (int q = 0; q < NPP; ++q) {
-      const int i = threadIdx.x + 256 * q;
-      if (i >= to * (to >> 1)) continue;
-      const int r = div_small(i, inv_hto), cp = i - r * (to >> 1);
+      const int i = threadIdx.x + 256 * (q % NPPH);
+      const int rl = div_small(i, inv_hto), cp = i - rl * (to >> 1);
+      const int r = (q / NPPH) * HR + rl;
+      if (rl >= HR || r >= to) continue;
       if (R0 + r < n && C0 + 2 * cp < n) {
         float* o = a.out + (long long)l * a.out_cs + MF_CHK((long long)(R0 + r) * a.N + C0 + 2 * cp, (long long)a.N * a.N - 1);
         o[0] = a.scale * accv[q][0];
