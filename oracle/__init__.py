@@ -7,4 +7,4 @@ test suite, the smoke check and the benchmark's CPU-baseline leg may import it;
 the library and its Python binding never do.  It shares no code with the HIP
 path.
 """
-from . import muffin, cnn, uob  # noqa: F401
+from . import muffin, cnn, uob, visibility  # noqa: F401

@@ -30,6 +30,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import uob as _uob
+from . import visibility as _vis
 
 B3_TAPS = np.array([1.0, 4.0, 6.0, 4.0, 1.0]) / 16.0
 
@@ -218,14 +219,29 @@ class Problem:
     sigma: float = 1.0
     rho: float = 1.0
     prior: str = "iuwt"  # spatial transform W_s: "iuwt", or "uob" (union of the first 8 Daubechies bases)
+    # visibility-domain data term (Sec. 2, eq. (viseq)) in place of H: then dirty and psf are unused
+    vis: _vis.VisData | None = None
 
     @property
     def L(self):
-        return self.dirty.shape[0]
+        return self.vis.vis.shape[0] if self.vis is not None else self.dirty.shape[0]
 
     @property
     def N(self):
-        return self.dirty.shape[1]
+        return self.vis.N if self.vis is not None else self.dirty.shape[1]
+
+
+def problem_gradient(p: Problem, X: np.ndarray) -> np.ndarray:
+    """Gradient of the problem's data term at X (image plane, or visibilities when p.vis is set)."""
+    if p.vis is not None:
+        return _vis.vis_gradient(X, p.vis)
+    return data_gradient(p.psf, X, p.dirty, p.w)
+
+
+def problem_data_term(p: Problem, X: np.ndarray) -> float:
+    if p.vis is not None:
+        return _vis.vis_data_term(X, p.vis)
+    return data_term(p.psf, X, p.dirty, p.w)
 
 
 def spatial_l1(X, J, gen=2, omega=None, prior="iuwt") -> float:
@@ -246,7 +262,7 @@ def spectral_l1(X) -> float:
 
 def objective(p: Problem, X: np.ndarray) -> np.ndarray:
     """[total, data, spatial, spectral] of eq. (reg) + eq. (RegAll) at X (inf if X has a negative entry)."""
-    data = data_term(p.psf, X, p.dirty, p.w)
+    data = problem_data_term(p, X)
     spat = p.mu_s * spatial_l1(X, p.J, p.gen, p.omega, p.prior)
     spec = p.mu_l * spectral_l1(X)
     total = data + spat + spec
@@ -278,7 +294,7 @@ def step_sizes(p: Problem):
     delta = 2 - (beta / 2) / (1/tau - sigma ||K||^2).  If tau <= 0 it is set to
     0.99 / (beta / 2 + sigma ||K||^2).
     """
-    beta = lipschitz(p.psf, p.w)
+    beta = _vis.vis_lipschitz(p.vis) if p.vis is not None else lipschitz(p.psf, p.w)
     k2 = op_norm_sq(p)
     tau = p.tau if p.tau > 0 else 0.99 / (beta / 2.0 + p.sigma * k2)
     margin = 1.0 / tau - p.sigma * k2
@@ -380,7 +396,7 @@ def iterate(p: Problem, st: State, tau: float) -> State:
     """One MUFFIN iteration (Algorithm 1): the primal-dual step with f the data term, g the
     positivity indicator, h = ||.||_1 and K the stacked analysis operator."""
     K = analysis_operator(p)
-    X, (U, V) = primal_dual_step(st.X, (st.U, st.V), lambda x: data_gradient(p.psf, x, p.dirty, p.w),
+    X, (U, V) = primal_dual_step(st.X, (st.U, st.V), lambda x: problem_gradient(p, x),
                                  K.apply, K.adjoint, positive, l1_conj_prox, tau, p.sigma, p.rho)
     return State(X=X, U=U, V=V, k=st.k + 1)
 

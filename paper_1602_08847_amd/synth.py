@@ -125,3 +125,69 @@ def make_cube(spec: CubeSpec, dtype=np.float64, with_sky: bool = True) -> Cube:
         if with_sky:
             sky[l] = x
     return Cube(spec=spec, sky=sky, psf=psf, dirty=dirty, nu=nu)
+
+
+# ------------------------------------------------------------------ visibility-domain inputs
+@dataclass(frozen=True)
+class VisSpec:
+    """Inputs of the visibility-domain data term: a sky cube, K baselines and the channels'
+    wavelengths (Sec. 2, eq. (viseq)).
+
+    * wavelengths ``lambda_l = lambda_0 nu_0 / nu_l`` with the channel frequencies of the image
+      cubes (``nu`` from ``nu_min`` to ``nu_max``, ``lambda_0 = 1`` metre at ``nu_0 = nu_min``);
+    * baselines in metres: ``u, v ~ U[-b_max, b_max)`` and ``w ~ U[-w_frac b_max, w_frac b_max)``
+      (``b_max`` in units of ``lambda_0``);
+    * pixel size ``cell = lambda_min / (4 b_max)`` (direction cosines), so that the longest
+      baseline at the highest frequency spans N/4 cycles across the image, as the uv masks of the
+      image-plane cubes do;
+    * sky: the Gaussian sources of ``make_cube`` with this spec's own draws;
+    * noise: complex, i.i.d. ``N(0, noise_sigma^2)`` in each part, one value per visibility.
+
+    Draw order from ``numpy.random.default_rng(seed)``: source centres (2S), widths (S), peaks
+    (S), indices (S), baselines (3K), then the noise (real parts, imaginary parts).
+    """
+
+    N: int
+    L: int
+    K: int
+    n_sources: int
+    seed: int = 0
+    b_max: float = 0.0  # 0: 2 N
+    w_frac: float = 0.5
+    noise_sigma: float = 0.01
+    nu_min: float = 1.0
+    nu_max: float = 1.5
+
+
+@dataclass
+class VisInputs:
+    spec: VisSpec
+    sky: np.ndarray  # (L, N, N)
+    uvw: np.ndarray  # (K, 3) metres
+    lam: np.ndarray  # (L,) metres
+    cell: float
+    noise: np.ndarray  # (L, K) complex
+
+
+def make_vis_inputs(spec: VisSpec) -> VisInputs:
+    N, L, S, K = spec.N, spec.L, spec.n_sources, spec.K
+    rng = np.random.default_rng(spec.seed)
+    centres = rng.uniform(0.0, N, size=(2, S))
+    widths = rng.uniform(1.0, 4.0, size=S)
+    peaks = rng.uniform(0.5, 1.0, size=S)
+    index = rng.uniform(-1.0, 0.0, size=S)
+    b_max = spec.b_max if spec.b_max > 0 else 2.0 * N
+    uvw = np.empty((K, 3))
+    uvw[:, 0:2] = rng.uniform(-b_max, b_max, size=(K, 2))
+    uvw[:, 2] = rng.uniform(-spec.w_frac * b_max, spec.w_frac * b_max, size=K)
+    nu = channel_freqs(L, spec.nu_min, spec.nu_max)
+    lam = spec.nu_min / nu
+    cell = float(lam.min() / (4.0 * b_max))
+    g0 = _gauss_1d(N, centres[0], widths)
+    g1 = _gauss_1d(N, centres[1], widths)
+    sky = np.empty((L, N, N))
+    for l in range(L):
+        amp = peaks * (nu[l] / spec.nu_min) ** index
+        sky[l] = (g0.T * amp[None, :]) @ g1
+    noise = spec.noise_sigma * (rng.normal(size=(L, K)) + 1j * rng.normal(size=(L, K)))
+    return VisInputs(spec=spec, sky=sky, uvw=uvw, lam=lam, cell=cell, noise=noise)
