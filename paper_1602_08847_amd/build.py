@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "fft.hip", "iuwt.hip", "spectral.hip", "reduce.hip", "cnn.hip", "uob.hip"]
+SOURCES = ["api.hip", "fft.hip", "iuwt.hip", "spectral.hip", "reduce.hip", "cnn.hip", "uob.hip", "vis.hip"]
 LIB = os.path.join(HERE, "libmuffin.so")
 
 FLAGS = [

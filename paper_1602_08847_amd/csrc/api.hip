@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace mf {
@@ -106,6 +107,25 @@ struct muffin_ctx {
   float *U2 = nullptr, *Acar = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};  // one iteration per parity of upar
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // Visibility-domain data term (Sec. 2, eq. (viseq)) in place of H: K visibilities per channel,
+  // each with its baseline in wavelengths of the channel and the residual the forward pass leaves
+  // (vp, [L][K]); the data (vdata, [L][K] complex); the forward pass's band sums (vpart,
+  // [vC][L][K]); l = m of each column or row (vlt, FP64 [N]); n (vnt, FP64 [N][N]) and 1/n
+  // (vinvn, FP32) of each pixel; x / n of the cube (XN, dense [L][N][N]).  The image-plane
+  // buffers (Y, B, S, Hhat_T, P_T, psf_lobe) are then not allocated.
+  bool vis = false;
+  int K = 0, vC = 0;
+  VisPt* vp = nullptr;
+  float2 *vdata = nullptr, *vpart = nullptr;
+  double *vlt = nullptr, *vnt = nullptr;
+  float *vinvn = nullptr, *XN = nullptr;
+};
+
+// Visibility inputs of muffin_init_vis.
+struct VisInit {
+  const muffin_vis_desc* d;
+  const float* vis;
+  int on_device;
 };
 
 namespace {
@@ -507,7 +527,21 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false, int 
   return MUFFIN_OK;
 }
 
+// Phi_l (x_l) (x in slots of cs floats) into the band sums, then the residual Phi x + vsign vis
+// (vis NULL: Phi x) into c->vp, with 1/2 |r|^2 block sums in partial when it is not NULL.
+int enqueue_vis_forward(muffin_ctx* c, const float* x, long long xcs, const float2* vis, float vsign, double* partial,
+                        int* nb, float2* rout = nullptr) {
+  MF_TRY(launch_vis_xn(x, xcs, c->vinvn, c->XN, c->N, c->L, c->st));
+  MF_TRY(launch_vis_fwd(c->vp, c->XN, c->vlt, c->vnt, c->vpart, c->N, c->K, c->L, c->vC, c->st));
+  return launch_vis_resid(c->vpart, c->vC, c->L, c->K, vis, vsign, c->vp, partial, nb, rout, c->st);
+}
+
 int enqueue_gradient(muffin_ctx* c, const float* x, float* out, const float* s, float s_scale) {
+  if (c->vis) {
+    // Re Phi^H (Phi x - v) + s_scale s
+    MF_TRY(enqueue_vis_forward(c, x, c->cs, c->vdata, -1.f, nullptr, nullptr));
+    return launch_vis_adj(c->vp, c->K, c->L, c->vlt, c->vnt, c->vinvn, c->N, out, c->cs, s, c->cs, s_scale, c->st);
+  }
   MF_TRY(launch_rows_r2c(x, c->cs, c->S, c->L, c->g, c->tw, false, c->st));
   MF_TRY(launch_cols(c->S, c->L, c->g, c->tw, COL_REAL, c->P_T, nullptr, 1.f, nullptr, c->st));
   MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_GRAD, out, c->cs, c->B, s, s_scale, nullptr, nullptr, nullptr,
@@ -588,11 +622,16 @@ int enqueue_objective(muffin_ctx* c, int si) {
   float* X = c->X + off;
   MF_HIP(hipMemsetAsync(c->dres, 0, sizeof(double) * 4, c->st));
   int nb = 0;
-  MF_TRY(launch_rows_r2c(X, np, c->S, nch, c->g, c->tw, false, c->st));
-  MF_TRY(launch_cols(c->S, nch, c->g, c->tw, COL_CPLX, nullptr, c->Hhat_T + (long long)s.ch0 * c->g.pitch * c->N,
-                     1.f / ((float)c->N * c->N), nullptr, c->st));
-  MF_TRY(launch_rows_c2r(c->S, nch, c->g, c->tw, EPI_RESID, nullptr, np, nullptr, nullptr, 0.f, c->Y + off,
-                         c->chan_w ? c->chan_w + s.ch0 : nullptr, c->partial, &nb, c->st));
+  if (c->vis) {
+    // 1/2 ||Phi x - v||^2 (one segment)
+    MF_TRY(enqueue_vis_forward(c, X, np, c->vdata, -1.f, c->partial, &nb));
+  } else {
+    MF_TRY(launch_rows_r2c(X, np, c->S, nch, c->g, c->tw, false, c->st));
+    MF_TRY(launch_cols(c->S, nch, c->g, c->tw, COL_CPLX, nullptr, c->Hhat_T + (long long)s.ch0 * c->g.pitch * c->N,
+                       1.f / ((float)c->N * c->N), nullptr, c->st));
+    MF_TRY(launch_rows_c2r(c->S, nch, c->g, c->tw, EPI_RESID, nullptr, np, nullptr, nullptr, 0.f, c->Y + off,
+                           c->chan_w ? c->chan_w + s.ch0 : nullptr, c->partial, &nb, c->st));
+  }
   MF_TRY(launch_reduce_sum(c->partial, nb, c->dres + 1, 0, c->st));
   if (c->uob) {
     MF_TRY(enqueue_uob_analysis(c, UOB_ABS, X, np, s.ch0, nch, nullptr, 0, 0, nullptr, 0, 0, 0.f, 1.f,
@@ -633,7 +672,8 @@ void destroy(muffin_ctx* c) {
     if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
   }
   void* bufs[] = {c->X, c->U, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT, c->S, c->Hhat_T, c->P_T,
-                  c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres, c->U2, c->Acar, c->tau_ch, c->Xs, c->Us, c->Vs, c->uobA, c->uobB};
+                  c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres, c->U2, c->Acar, c->tau_ch, c->Xs, c->Us, c->Vs, c->uobA, c->uobB,
+                  c->vp, c->vdata, c->vpart, c->vlt, c->vnt, c->vinvn, c->XN};
   for (Seg& s : c->segs) {
     void* sb[] = {s.W, s.WT, s.twL, s.csL, s.blu};
     for (void* b : sb)
@@ -682,12 +722,23 @@ int planes_out(muffin_ctx* c, float* dst, const float* src, long long n, int on_
                      on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->st);
 }
 
+// Power iterations and safety factor of beta for the visibility data term: beta is the largest
+// eigenvalue of Re Phi^H Phi over all channels, estimated by power iteration from the all-ones cube
+// (its estimate approaches the eigenvalue from below, hence the factor).
+constexpr int kVisPowerIters = 40;
+constexpr double kVisBetaMargin = 1.01;
+
+int init_vis_data(muffin_ctx* c, const VisInit* vi);
+int vis_power_beta(muffin_ctx* c, int iters, double* beta);
+
 // Build a context over n cubes that share N, J, generation, coarse weighting, mu_s, sigma and rho
-// (checked by the caller); their channels are packed one cube after the other.
+// (checked by the caller); their channels are packed one cube after the other.  With vi (one cube),
+// the data term is the visibility-domain one of Sec. 2, eq. (viseq), and dirty and psf are unused.
 int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float* const* dirty,
-               const float* const* psf, int on_device) {
+               const float* const* psf, int on_device, const VisInit* vi = nullptr) {
   const muffin_params* p = ps[0];
   c->p = *p;
+  c->vis = vi != nullptr;
   c->p.chan_weight = nullptr;
   c->N = p->N;
   c->J = p->J;
@@ -753,14 +804,18 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   MF_TRY(dalloc(&c->V, cube));
   MF_TRY(dalloc(&c->D, cube));
   MF_TRY(dalloc(&c->Q, cube));
-  MF_TRY(dalloc(&c->B, cube));
-  MF_TRY(dalloc(&c->Y, cube));
+  if (!c->vis) {
+    MF_TRY(dalloc(&c->B, cube));
+    MF_TRY(dalloc(&c->Y, cube));
+  }
   MF_TRY(dalloc(&c->cA, cube));
   MF_TRY(dalloc(&c->cB, cube));
   MF_TRY(dalloc(&c->cT, cube));
-  MF_TRY(dalloc(&c->S, spec));
-  MF_TRY(dalloc(&c->Hhat_T, spec));
-  MF_TRY(dalloc(&c->P_T, spec));
+  if (!c->vis) {
+    MF_TRY(dalloc(&c->S, spec));
+    MF_TRY(dalloc(&c->Hhat_T, spec));
+    MF_TRY(dalloc(&c->P_T, spec));
+  }
   MF_TRY(dalloc(&c->tw, c->N));
   for (Seg& s : c->segs) {
     MF_TRY(dalloc(&s.twL, s.L));
@@ -771,7 +826,7 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   }
   MF_TRY(dalloc(&c->partial, kMaxPartials));
   MF_TRY(dalloc(&c->dres, 16));
-  MF_TRY(dalloc(&c->psf_lobe, c->L));
+  if (!c->vis) MF_TRY(dalloc(&c->psf_lobe, c->L));
   if (c->uob) {
     MF_TRY(dalloc(&c->uobA, (long long)c->L * kUobBases * uob_cap(c, 1)));
     MF_TRY(dalloc(&c->uobB, (long long)c->L * kUobBases * uob_cap(c, 2)));
@@ -781,18 +836,18 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   StreamScope scope(c);
   if (!scope.ok) return set_error("stream ordering failed"), MUFFIN_EHIP;
   hipStream_t st = c->st;
-  MF_HIP(hipMemsetAsync(c->S, 0, sizeof(float2) * spec, st));
+  if (c->S) MF_HIP(hipMemsetAsync(c->S, 0, sizeof(float2) * spec, st));
   MF_HIP(hipMemsetAsync(c->dres, 0, sizeof(double) * 16, st));
   // the slot padding of every cube buffer stays zero
   for (float* b : {c->X, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT})
-    MF_HIP(hipMemsetAsync(b, 0, sizeof(float) * cube, st));
+    if (b) MF_HIP(hipMemsetAsync(b, 0, sizeof(float) * cube, st));
   MF_HIP(hipMemsetAsync(c->U, 0, sizeof(float) * c->ucube, st));
   if (c->fused_ok) {
     // U = 0: the carried adjoint sum of zero planes is exactly zero
     MF_HIP(hipMemsetAsync(c->U2, 0, sizeof(float) * c->us * total * 3, st));
     MF_HIP(hipMemsetAsync(c->Acar, 0, sizeof(float) * cube, st));
   }
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < n && !c->vis; ++i) {
     const long long off = (long long)c->segs[i].ch0 * c->cs;
     MF_TRY(planes_in(c, c->Y + off, dirty[i], c->segs[i].L, on_device));
     MF_TRY(planes_in(c, c->cT + off, psf[i], c->segs[i].L, on_device));
@@ -826,6 +881,9 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
       MF_HIP(hipStreamSynchronize(st));
     }
   }
+  if (c->vis) {
+    MF_TRY(init_vis_data(c, vi));
+  } else {
   // non-finite inputs
   MF_TRY(launch_count_nonfinite(c->Y, cube, c->partial, c->dres + 0, st));
   MF_TRY(launch_count_nonfinite(c->cT, cube, c->partial, c->dres + 0, st));
@@ -846,6 +904,7 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   MF_TRY(launch_rows_c2r(c->S, c->L, c->g, c->tw, EPI_STORE, c->B, c->cs, nullptr, nullptr, 0.f, nullptr, nullptr,
                          nullptr, nullptr, st));
   if (c->chan_w) MF_TRY(launch_scale_channels(c->B, c->chan_w, c->npix, c->cs, c->L, st));
+  }
   // ||W_s||^2 (FP64, shared by the group) and, per cube, beta = max_l w_l max_k |H_l(k)|^2
   // (the union of orthonormal bases divided by sqrt(8) is a tight frame: W_s^dagger W_s = I)
   if (c->uob) {
@@ -857,10 +916,14 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   const long long per_ch = (long long)c->g.pitch * c->N;
   for (size_t i = 0; i < c->segs.size(); ++i) {
     Seg& s = c->segs[i];
-    MF_TRY(launch_reduce_max(c->P_T + s.ch0 * per_ch, s.L * per_ch, (double)c->N * (double)c->N, c->partial,
-                             c->dres + 4, st));
-    MF_HIP(hipMemcpyAsync(&s.beta, c->dres + 4, sizeof(double), hipMemcpyDeviceToHost, st));
-    MF_HIP(hipStreamSynchronize(st));
+    if (c->vis) {
+      MF_TRY(vis_power_beta(c, vi->d->power_iters > 0 ? vi->d->power_iters : kVisPowerIters, &s.beta));
+    } else {
+      MF_TRY(launch_reduce_max(c->P_T + s.ch0 * per_ch, s.L * per_ch, (double)c->N * (double)c->N, c->partial,
+                               c->dres + 4, st));
+      MF_HIP(hipMemcpyAsync(&s.beta, c->dres + 4, sizeof(double), hipMemcpyDeviceToHost, st));
+      MF_HIP(hipStreamSynchronize(st));
+    }
     s.K2 = c->p.mu_s * c->p.mu_s * c->Ws2 + s.mu_l * s.mu_l;
     s.tau = ps[i]->tau > 0 ? ps[i]->tau : 0.99 / (s.beta / 2.0 + c->sigma * s.K2);
     const double margin = 1.0 / s.tau - c->sigma * s.K2;
@@ -871,7 +934,8 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
     if (!(c->rho < s.delta)) return set_error("rho must lie in (0, delta)"), MUFFIN_ESTEP;
   }
 
-  c->local_primal = true;
+  // the mu_lambda = 0 pass runs the primal step in the image-plane gradient's last FFT pass
+  c->local_primal = !c->vis;
   for (const Seg& s : c->segs) c->local_primal = c->local_primal && s.mu_l == 0.0;
   {
     std::vector<float> tch(c->L);
@@ -887,6 +951,84 @@ int init_group(muffin_ctx* c, int n, const muffin_params* const* ps, const float
   MF_HIP(hipMemsetAsync(c->V, 0, sizeof(float) * cube, st));
   MF_HIP(hipMemsetAsync(c->D, 0, sizeof(float) * cube, st));
   MF_HIP(hipStreamSynchronize(st));
+  return MUFFIN_OK;
+}
+
+// Tables and data of the visibility data term (Sec. 2, eq. (viseq)): pixel (i, j) sits at
+// l = (j - N/2) cell, m = (i - N/2) cell, n = sqrt(1 - l^2 - m^2) (FP64 on the host); each channel's
+// baselines are divided by its wavelength in FP64.
+int init_vis_data(muffin_ctx* c, const VisInit* vi) {
+  const muffin_vis_desc* d = vi->d;
+  const int N = c->N, L = c->L, K = d->K;
+  const long long LK = (long long)L * K, np = c->npix;
+  c->K = K;
+  c->vC = vis_chunks(N, K, L);
+  MF_TRY(dalloc(&c->vp, LK));
+  MF_TRY(dalloc(&c->vdata, LK));
+  MF_TRY(dalloc(&c->vpart, (long long)c->vC * LK));
+  MF_TRY(dalloc(&c->vlt, N));
+  MF_TRY(dalloc(&c->vnt, np));
+  MF_TRY(dalloc(&c->vinvn, np));
+  MF_TRY(dalloc(&c->XN, np * L));
+  std::vector<double> lt(N), nt(np);
+  std::vector<float> invn(np);
+  for (int j = 0; j < N; ++j) lt[j] = (j - N / 2) * d->cell;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const double n = std::sqrt(1.0 - lt[j] * lt[j] - lt[i] * lt[i]);
+      nt[(size_t)i * N + j] = n;
+      invn[(size_t)i * N + j] = (float)(1.0 / n);
+    }
+  std::vector<VisPt> vp(LK);
+  for (int l = 0; l < L; ++l)
+    for (int k = 0; k < K; ++k) {
+      VisPt& q = vp[(size_t)l * K + k];
+      q.u = d->uvw[3 * k] / d->lambda[l];
+      q.v = d->uvw[3 * k + 1] / d->lambda[l];
+      q.w = d->uvw[3 * k + 2] / d->lambda[l];
+      q.rre = q.rim = 0.f;
+    }
+  hipStream_t st = c->st;
+  MF_HIP(hipMemcpyAsync(c->vlt, lt.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+  MF_HIP(hipMemcpyAsync(c->vnt, nt.data(), sizeof(double) * np, hipMemcpyHostToDevice, st));
+  MF_HIP(hipMemcpyAsync(c->vinvn, invn.data(), sizeof(float) * np, hipMemcpyHostToDevice, st));
+  MF_HIP(hipMemcpyAsync(c->vp, vp.data(), sizeof(VisPt) * LK, hipMemcpyHostToDevice, st));
+  MF_TRY(copy_in((float*)c->vdata, vi->vis, (size_t)(2 * LK), vi->on_device, st));
+  MF_HIP(hipMemsetAsync(c->dres, 0, sizeof(double), st));
+  MF_TRY(launch_count_nonfinite((const float*)c->vdata, 2 * LK, c->partial, c->dres + 0, st));
+  double bad = 0;
+  MF_HIP(hipMemcpyAsync(&bad, c->dres, sizeof(double), hipMemcpyDeviceToHost, st));
+  MF_HIP(hipStreamSynchronize(st));  // also keeps the host tables alive until their copies are done
+  if (bad != 0) return set_error("NaN or Inf in the visibilities"), MUFFIN_ENONFINITE;
+  return MUFFIN_OK;
+}
+
+// beta = kVisBetaMargin ||A x_T|| after `iters` steps x <- A x / ||A x|| from the all-ones cube,
+// A = Re Phi^H Phi over every channel (norms in FP64).  Uses the scratch planes cT and cA.
+int vis_power_beta(muffin_ctx* c, int iters, double* beta) {
+  hipStream_t st = c->st;
+  const long long np = c->npix;
+  float* x = c->cT;
+  float* y = c->cA;
+  {
+    std::vector<float> ones((size_t)(np * c->L), 1.f);
+    MF_TRY(planes_in(c, x, ones.data(), c->L, 0));
+  }
+  MF_TRY(launch_vis_scale(x, c->cs, c->N, c->L, (float)(1.0 / std::sqrt((double)np * c->L)), st));
+  double est = 0.0;
+  for (int t = 0; t < iters; ++t) {
+    MF_TRY(enqueue_vis_forward(c, x, c->cs, nullptr, 0.f, nullptr, nullptr));
+    MF_TRY(launch_vis_adj(c->vp, c->K, c->L, c->vlt, c->vnt, c->vinvn, c->N, y, c->cs, nullptr, 0, 0.f, st));
+    MF_TRY(launch_diff_norms(y, c->cs, nullptr, 0, np, c->L, c->partial, c->dres + 6, c->dres + 7, 0, st));
+    double ss = 0.0;
+    MF_HIP(hipMemcpyAsync(&ss, c->dres + 7, sizeof(double), hipMemcpyDeviceToHost, st));
+    MF_HIP(hipStreamSynchronize(st));
+    if (!(ss > 0.0) || !std::isfinite(ss)) return set_error("beta: the power iteration broke down"), MUFFIN_ENONFINITE;
+    est = std::sqrt(ss);
+    MF_TRY(launch_vis_scale(y, c->cs, c->N, c->L, (float)(1.0 / est), st));
+    std::swap(x, y);
+  }
+  *beta = kVisBetaMargin * est;
   return MUFFIN_OK;
 }
 
@@ -1137,7 +1279,7 @@ int muffin_debug_oob(uint64_t* count) {
 #ifdef MF_CHECKED
   unsigned long long total = 0, n = 0;
   for (int (*take)(unsigned long long*) : {mf::oob_take_fft, mf::oob_take_iuwt, mf::oob_take_spectral,
-                                           mf::oob_take_uob}) {
+                                           mf::oob_take_uob, mf::oob_take_vis}) {
     MF_TRY(take(&n));
     total += n;
   }
@@ -1178,6 +1320,45 @@ int muffin_init(muffin_ctx** out, const muffin_params* p, const float* dirty, co
   }
   *out = c;
   return MUFFIN_OK;
+}
+
+int muffin_init_vis(muffin_ctx** out, const muffin_params* p, const muffin_vis_desc* d, const float* vis,
+                    int vis_on_device, void* hip_stream) {
+  if (!out) return set_error("out is NULL"), MUFFIN_EINVAL;
+  *out = nullptr;
+  MF_TRY(validate(p));
+  if (!d || !vis || !d->uvw || !d->lambda) return set_error("desc, vis, uvw or lambda is NULL"), MUFFIN_EINVAL;
+  if (p->N % 8) return set_error("the visibility data term needs N to be a multiple of 8"), MUFFIN_EINVAL;
+  if (p->chan_weight) return set_error("channel weights are not supported with visibilities"), MUFFIN_EINVAL;
+  if (d->K < 1 || d->K > (1 << 22)) return set_error("K must be in [1, 2^22]"), MUFFIN_EINVAL;
+  if (d->power_iters < 0 || d->power_iters > 100000) return set_error("power_iters must be in [0, 1e5]"), MUFFIN_EINVAL;
+  const double half = 0.5 * p->N * d->cell;
+  if (!(d->cell > 0) || !std::isfinite(d->cell) || !(2.0 * half * half < 1.0))
+    return set_error("cell must be > 0 with every pixel inside the unit disc (l^2 + m^2 < 1)"), MUFFIN_EINVAL;
+  for (int l = 0; l < p->L; ++l)
+    if (!(d->lambda[l] > 0) || !std::isfinite(d->lambda[l]))
+      return set_error("every wavelength must be finite and > 0"), MUFFIN_EINVAL;
+  for (long long i = 0; i < 3LL * d->K; ++i)
+    if (!std::isfinite(d->uvw[i])) return set_error("NaN or Inf in uvw"), MUFFIN_ENONFINITE;
+  muffin_ctx* c = new (std::nothrow) muffin_ctx();
+  if (!c) return set_error("host allocation failed"), MUFFIN_ENOMEM;
+  c->user = (hipStream_t)hip_stream;
+  const VisInit vi{d, vis, vis_on_device};
+  const int rc = init_group(c, 1, &p, nullptr, nullptr, 0, &vi);
+  if (rc != MUFFIN_OK) {
+    destroy(c);
+    return rc;
+  }
+  *out = c;
+  return MUFFIN_OK;
+}
+
+int muffin_vis_residual(muffin_ctx* c, float* r, int on_device) {
+  if (!c || !r) return set_error("bad arguments"), MUFFIN_EINVAL;
+  if (!c->vis) return set_error("not a visibility context"), MUFFIN_EINVAL;
+  StreamScope scope(c);
+  MF_TRY(enqueue_vis_forward(c, c->X, c->cs, c->vdata, -1.f, nullptr, nullptr, (float2*)c->cA));
+  return copy_out(r, c->cA, (size_t)(2LL * c->L * c->K), on_device, c->st);
 }
 
 void muffin_free(muffin_ctx* c) { destroy(c); }
@@ -1675,6 +1856,7 @@ int muffin_set_state(muffin_ctx* c, const void* blob, size_t bytes) {
 
 int muffin_warm_input(muffin_ctx* c, float* out, int on_device) {
   if (!c || !out) return set_error("bad arguments"), MUFFIN_EINVAL;
+  if (c->vis) return set_error("the warm start needs dirty images (image-plane context)"), MUFFIN_EINVAL;
   StreamScope scope(c);
   MF_TRY(cnn_warm_input(c->Y, c->cs, c->psf_lobe, c->cA, c->N, c->L, c->st));  // dense planes
   return copy_out(out, c->cA, (size_t)(c->npix * c->L), on_device, c->st);
@@ -1682,6 +1864,7 @@ int muffin_warm_input(muffin_ctx* c, float* out, int on_device) {
 
 int muffin_warm_start(muffin_ctx* c, muffin_cnn* net) {
   if (!c || !net) return set_error("bad arguments"), MUFFIN_EINVAL;
+  if (c->vis) return set_error("the warm start needs dirty images (image-plane context)"), MUFFIN_EINVAL;
   if (c->N % 32) return set_error("warm start needs N to be a multiple of 32"), MUFFIN_EINVAL;
   StreamScope scope(c);
   MF_TRY(cnn_warm_input(c->Y, c->cs, c->psf_lobe, c->cA, c->N, c->L, c->st));  // dense planes
@@ -1698,7 +1881,19 @@ int muffin_apply_op(muffin_ctx* c, int op, const float* in, float* out) {
   // in and out are dense (planes np floats apart); the scratch planes use the library's slots
   const long long np = c->npix, cs = c->cs;
   const float inv_n2 = 1.f / ((float)c->N * c->N);
+  const bool vis_op = op == MUFFIN_OP_PHI || op == MUFFIN_OP_PHI_ADJ;
+  if (vis_op && !c->vis) return set_error("PHI operators need a visibility context"), MUFFIN_EINVAL;
+  if ((op == MUFFIN_OP_H || op == MUFFIN_OP_HT) && c->vis)
+    return set_error("H operators need an image-plane context"), MUFFIN_EINVAL;
   switch (op) {
+    case MUFFIN_OP_PHI:
+      // the residual with no data is Phi x; it also lands in out
+      return enqueue_vis_forward(c, in, np, nullptr, 0.f, nullptr, nullptr, (float2*)out);
+    case MUFFIN_OP_PHI_ADJ:
+      // no bands: the residual is the operand itself
+      MF_TRY(launch_vis_resid(nullptr, 0, c->L, c->K, (const float2*)in, 1.f, c->vp, nullptr, nullptr, nullptr,
+                              c->st));
+      return launch_vis_adj(c->vp, c->K, c->L, c->vlt, c->vnt, c->vinvn, c->N, out, np, nullptr, 0, 0.f, c->st);
     case MUFFIN_OP_H:
     case MUFFIN_OP_HT:
       MF_TRY(launch_rows_r2c(in, np, c->S, c->L, c->g, c->tw, false, c->st));

@@ -68,6 +68,7 @@ int oob_take_fft(unsigned long long* n);
 int oob_take_iuwt(unsigned long long* n);
 int oob_take_spectral(unsigned long long* n);
 int oob_take_uob(unsigned long long* n);
+int oob_take_vis(unsigned long long* n);
 
 // XCD-aware block order.  Consecutive workgroup ids are dealt round-robin to the 8 XCDs, each
 // with its own L2; this maps id b to logical block xcd_remap(b) so that XCD x (ids b = x, x + 8,
@@ -302,5 +303,31 @@ int launch_count_nonfinite(const float* x, long long n, double* partial, double*
 int launch_diff_norms(const float* a, long long acs, const float* b, long long bcs, long long npix, int nplanes,
                       double* partial, double* dst_diff, double* dst_a, int accumulate, hipStream_t st);
 constexpr int kMaxPartials = 1 << 20;
+
+// ------------------------------------------------------------------ visibility-domain data term
+// One visibility of one channel (Sec. 2, eq. (viseq)): the baseline in wavelengths of the channel,
+// and the residual (Phi x - v) that the forward pass leaves for the adjoint.  32 bytes, so that a
+// wave-uniform visibility is one scalar load.
+struct VisPt {
+  double u, v, w;
+  float rre, rim;
+};
+static_assert(sizeof(VisPt) == 32, "VisPt must stay 32 bytes");
+// Row bands of the forward pass for N x N images, K visibilities and L channels.
+int vis_chunks(int N, int K, int L);
+// XN = X / n per pixel (X in slots of cs floats, XN dense planes).
+int launch_vis_xn(const float* X, long long cs, const float* invn, float* XN, int N, int L, hipStream_t st);
+// part[c][l][k]: band c's share of Phi_l (XN n)_k, C = vis_chunks(N, K, L) bands.
+int launch_vis_fwd(const VisPt* vp, const float* XN, const double* lt, const double* nt, float2* part, int N, int K,
+                   int L, int C, hipStream_t st);
+// r = sum of the C bands + vsign vis (vis NULL: 0) into vp (and rout unless NULL); with partial,
+// 1/2 |r|^2 block sums (*nblocks of them).
+int launch_vis_resid(const float2* part, int C, int L, int K, const float2* vis, float vsign, VisPt* vp,
+                     double* partial, int* nblocks, float2* rout, hipStream_t st);
+// out = Re Phi^H r (+ s_scale sadd), planes out_cs (sadd: s_cs) floats apart.
+int launch_vis_adj(const VisPt* vp, int K, int L, const double* lt, const double* nt, const float* invn, int N,
+                   float* out, long long out_cs, const float* sadd, long long s_cs, float s_scale, hipStream_t st);
+// x *= f over the N x N planes of L channels in slots of cs floats.
+int launch_vis_scale(float* x, long long cs, int N, int L, float f, hipStream_t st);
 
 }  // namespace mf

@@ -26,6 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ESTEP, ESTATE = 0, -1, -2, -3, -4, -5, -6
 OP_H, OP_HT, OP_GRAD, OP_IUWT, OP_IUWT_ADJ, OP_DCT, OP_IDCT, OP_IUWT_SCHED = 1, 2, 3, 4, 5, 6, 7, 8
+OP_PHI, OP_PHI_ADJ = 9, 10  # visibility contexts: image -> visibilities, visibilities -> image
 
 EXPORTS = [
     "muffin_init", "muffin_step", "muffin_solve", "muffin_objective", "muffin_info",
@@ -38,7 +39,7 @@ EXPORTS = [
     "muffin_batch_step_timed", "muffin_batch_objective", "muffin_batch_get_x", "muffin_batch_info",
     "muffin_batch_autotune", "muffin_batch_free", "muffin_step_monitored", "muffin_snr", "muffin_batch_snr",
     "muffin_warm_input", "muffin_batch_set_x", "muffin_batch_warm_input", "muffin_uob_filter",
-    "muffin_debug_oob",
+    "muffin_debug_oob", "muffin_init_vis", "muffin_vis_residual",
 ]
 
 
@@ -54,7 +55,18 @@ class Params(ctypes.Structure):
 
 
 _vp, _i32, _dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+
+
+class VisDesc(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int32), ("cell", ctypes.c_double),
+        ("uvw", ctypes.POINTER(ctypes.c_double)), ("lam", ctypes.POINTER(ctypes.c_double)),
+        ("power_iters", ctypes.c_int32),
+    ]
 _lib.muffin_init.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(Params), _vp, _vp, ctypes.c_int, _vp]
+_lib.muffin_init_vis.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(Params), ctypes.POINTER(VisDesc), _vp,
+                                 ctypes.c_int, _vp]
+_lib.muffin_vis_residual.argtypes = [_vp, _vp, ctypes.c_int]
 _lib.muffin_step.argtypes = [_vp, _i32]
 _lib.muffin_solve.argtypes = [_vp, _i32, _i32, _i32, _dbl, _dbl, ctypes.POINTER(_i32), ctypes.POINTER(_dbl)]
 _lib.muffin_step_monitored.argtypes = [_vp, _i32, ctypes.POINTER(_dbl)]
@@ -163,7 +175,7 @@ class Muffin:
         L, N, N2 = dirty.shape
         if N != N2 or tuple(psf.shape) != (L, N, N):
             raise ValueError("dirty and psf must both be [L][N][N]")
-        self.N, self.L, self.J = N, L, J
+        self.N, self.L, self.J, self.K = N, L, J, 0
         self.planes = UOB_BASES if prior == PRIOR_UOB else J + 1  # dual planes per channel
         self._cw = None
         p = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=int(bool(penalize_coarse)),
@@ -177,6 +189,42 @@ class Muffin:
         _check(_lib.muffin_init(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(dirty.data_ptr()),
                                 ctypes.c_void_p(psf.data_ptr()), 1, _stream_handle()), "muffin_init")
         self._h = h
+
+    @classmethod
+    def from_visibilities(cls, vis, uvw, lam, cell: float, N: int, J: int, mu_s: float, mu_lambda: float,
+                          iuwt_gen: int = 2, penalize_coarse: bool = True, tau: float = 0.0, sigma: float = 1.0,
+                          rho: float = 1.0, flags: int = 0, prior: int = PRIOR_IUWT, power_iters: int = 0):
+        """A context with the visibility-domain data term: vis (L, K) complex (or (L, K, 2) float),
+        uvw (K, 3) baselines in metres, lam (L,) wavelengths in metres, cell the pixel size."""
+        torch = _torch()
+        v = np.asarray(vis)
+        if np.iscomplexobj(v):
+            v = np.stack([v.real, v.imag], axis=-1)
+        vt = torch.as_tensor(np.ascontiguousarray(v, dtype=np.float32)).cuda().contiguous()
+        if vt.dim() != 3 or vt.shape[2] != 2:
+            raise ValueError("vis must be (L, K) complex or (L, K, 2) float")
+        L, K = int(vt.shape[0]), int(vt.shape[1])
+        self = cls.__new__(cls)
+        self.N, self.L, self.J, self.K = N, L, J, K
+        self.planes = UOB_BASES if prior == PRIOR_UOB else J + 1
+        self._cw = None
+        self._uvw = np.ascontiguousarray(uvw, dtype=np.float64)
+        self._lam = np.ascontiguousarray(lam, dtype=np.float64)
+        if self._uvw.shape != (K, 3) or self._lam.shape != (L,):
+            raise ValueError("uvw must be (K, 3) and lam (L,)")
+        d = VisDesc(K=K, cell=cell, uvw=self._uvw.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                    lam=self._lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), power_iters=power_iters)
+        p = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=int(bool(penalize_coarse)),
+                   flags=flags, prior=prior, mu_s=mu_s, mu_lambda=mu_lambda, tau=tau, sigma=sigma, rho=rho)
+        h = ctypes.c_void_p()
+        _check(_lib.muffin_init_vis(ctypes.byref(h), ctypes.byref(p), ctypes.byref(d),
+                                    ctypes.c_void_p(vt.data_ptr()), 1, _stream_handle()), "muffin_init_vis")
+        self._h = h
+        return self
+
+    def vis_residual(self):
+        """Phi x - v of the current X, (L, K, 2) float32 on the GPU."""
+        return self._get(_lib.muffin_vis_residual, (self.L, self.K, 2))
 
     # ------------------------------------------------------------------ lifecycle
     def close(self):
@@ -291,9 +339,9 @@ class Muffin:
     def apply_op(self, op: int, x):
         torch = _torch()
         L, N = self.L, self.N
-        cube, ucube = (L, N, N), (L, self.planes, N, N)
-        in_shape = ucube if op == OP_IUWT_ADJ else cube
-        out_shape = ucube if op in (OP_IUWT, OP_IUWT_SCHED) else cube
+        cube, ucube, vshape = (L, N, N), (L, self.planes, N, N), (L, self.K, 2)
+        in_shape = ucube if op == OP_IUWT_ADJ else vshape if op == OP_PHI_ADJ else cube
+        out_shape = ucube if op in (OP_IUWT, OP_IUWT_SCHED) else vshape if op == OP_PHI else cube
         x = torch.as_tensor(x, dtype=torch.float32).cuda().contiguous()
         out = torch.empty(out_shape, dtype=torch.float32, device="cuda")
         _check(_lib.muffin_apply_op(self._h, op, _dev_ptr(x, in_shape, "in"),

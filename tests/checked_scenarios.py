@@ -4,7 +4,7 @@ Run as a child process by tests/test_gpu_checked.py with MUFFIN_LIBRARY set to
 paper_1602_08847_amd/libmuffin_checked.so.  It drives every instrumented kernel family (the IUWT
 band, pair, triple and fused-tail kernels of both generations, the FFT passes, the spectral step in
 its planned, Bluestein and cosine-table forms, the union-of-bases kernels in both workgroup
-layouts, an uneven batch) over ragged and wrapping shapes, then prints one JSON line with the
+layouts, the visibility data term's kernels, an uneven batch) over ragged and wrapping shapes, then prints one JSON line with the
 number of out-of-bounds indices the device caught.
 """
 import json
@@ -61,6 +61,23 @@ def main():
                            (256, 4, 5, 8), (256, 4, 5, 16)]:
         run(N, L, J, prior=muffin.PRIOR_UOB, flags=flags)
         cases.append(f"uob N={N} L={L} J={J} flags={flags}")
+    # the visibility data term: ragged visibility counts, one visibility, image sides 3 * 2^a
+    for N, L, K in [(16, 3, 50), (24, 2, 65), (64, 2, 1), (48, 3, 130)]:
+        rng = np.random.default_rng(N + K)
+        uvw = np.column_stack([rng.uniform(-2 * N, 2 * N, K), rng.uniform(-2 * N, 2 * N, K), rng.uniform(-N, N, K)])
+        lam = np.linspace(1.0, 0.7, L)
+        vis = (rng.normal(size=(L, K)) + 1j * rng.normal(size=(L, K))).astype(np.complex64)
+        with muffin.Muffin.from_visibilities(vis, uvw, lam, 1.0 / (12 * N), N=N, J=2, mu_s=0.5, mu_lambda=1.0,
+                                             power_iters=3) as m:
+            m.set_x(np.abs(rng.normal(size=(L, N, N))).astype(np.float32))
+            m.step(2)
+            m.objective()
+            x = rng.normal(size=(L, N, N)).astype(np.float32)
+            m.apply_op(muffin.OP_PHI, x)
+            m.apply_op(muffin.OP_PHI_ADJ, rng.normal(size=(L, K, 2)).astype(np.float32))
+            m.apply_op(muffin.OP_GRAD, x)
+            m.vis_residual()
+        cases.append(f"vis N={N} L={L} K={K}")
     # an uneven batch (groups by image side)
     specs = [(64, 9), (128, 20), (64, 33), (96, 7)]
     data = [cube(N, L, 3, seed=i) for i, (N, L) in enumerate(specs)]

@@ -1,0 +1,202 @@
+"""The visibility-domain data term (Sec. 2, eq. (viseq)) on the GPU against the FP64 oracle: Phi, its
+adjoint and the gradient per operator, beta, the residual and the objective, iterations of Algorithm 1
+with both priors, sampled entries at the benchmark's size, and the error paths.
+
+Tolerance: each entry of Phi x is a sum of N^2 terms whose phase the kernels form in FP64 and whose
+cosine and sine come from the FP32 hardware instructions (absolute error of order 1e-7 on a unit
+value); products and sums are FP32.  The relative L2 error of a whole operator output is then a few
+1e-7 at these sizes; the tests use 1e-5 per operator and 1e-4 for iterations (as for the image plane)."""
+import numpy as np
+import pytest
+
+from oracle import muffin as om
+from oracle import visibility as ov
+from paper_1602_08847_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    a = a.astype(np.complex128) if np.iscomplexobj(a) else a.astype(np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cplx(t):
+    a = t.double().cpu().numpy()
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def inputs(N, L, K, seed=0, w_frac=0.5):
+    vi = synth.make_vis_inputs(synth.VisSpec(N=N, L=L, K=K, n_sources=max(2, N // 8), seed=seed, w_frac=w_frac))
+    # the library takes FP32 visibilities: the oracle sees the same rounded values
+    vis = ov.phi(vi.sky, vi.uvw, vi.lam, vi.cell) + vi.noise
+    vis = f32(vis.real) + 1j * f32(vis.imag)
+    return vi, vis
+
+
+SHAPES = [(16, 3, 50), (32, 5, 130), (8, 1, 64), (64, 2, 1), (48, 4, 200), (24, 2, 65)]
+
+
+@pytest.mark.parametrize("N,L,K", SHAPES)
+def test_operators_match_oracle(lib, N, L, K):
+    vi, vis = inputs(N, L, K, seed=N + K)
+    rng = np.random.default_rng(N * K)
+    x = f32(rng.normal(size=(L, N, N)))
+    r = f32(rng.normal(size=(L, K))) + 1j * f32(rng.normal(size=(L, K)))
+    with lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, N=N, J=2, mu_s=0.1, mu_lambda=0.1) as m:
+        phi = cplx(m.apply_op(lib.OP_PHI, x))
+        adj = m.apply_op(lib.OP_PHI_ADJ, np.stack([r.real, r.imag], axis=-1)).double().cpu().numpy()
+        grad = m.apply_op(lib.OP_GRAD, x).double().cpu().numpy()
+    d = ov.VisData(uvw=vi.uvw, lam=vi.lam, cell=vi.cell, vis=vis, N=N)
+    assert rel(phi, ov.phi(x, vi.uvw, vi.lam, vi.cell)) < 1e-5
+    assert rel(adj, ov.phi_adjoint(r, vi.uvw, vi.lam, vi.cell, N)) < 1e-5
+    assert rel(grad, ov.vis_gradient(x, d)) < 1e-5
+
+
+def test_wide_field_w_term_is_applied(lib):
+    """A field wide enough that w n spans many turns across the image: the GPU follows the oracle's
+    phases, and dropping the w term (the oracle with w = 0) would be far off."""
+    N, L, K = 32, 2, 96
+    rng = np.random.default_rng(4)
+    uvw = np.column_stack([rng.uniform(-300, 300, K), rng.uniform(-300, 300, K), rng.uniform(-2000, 2000, K)])
+    lam = np.array([1.0, 0.8])
+    cell = 0.02  # corner at l = m = 0.32
+    x = f32(np.abs(rng.normal(size=(L, N, N))))
+    vis = np.zeros((L, K), complex)
+    with lib.Muffin.from_visibilities(vis, uvw, lam, cell, N=N, J=2, mu_s=0.1, mu_lambda=0.1) as m:
+        phi = cplx(m.apply_op(lib.OP_PHI, x))
+    want = ov.phi(x, uvw, lam, cell)
+    flat = uvw.copy()
+    flat[:, 2] = 0.0
+    assert rel(phi, want) < 1e-5
+    assert rel(ov.phi(x, flat, lam, cell), want) > 0.5
+
+
+def test_beta_residual_and_objective(lib):
+    N, L, K = 32, 4, 150
+    vi, vis = inputs(N, L, K, seed=3)
+    d = ov.VisData(uvw=vi.uvw, lam=vi.lam, cell=vi.cell, vis=vis, N=N)
+    x0 = f32(vi.sky * 0.7)
+    with lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, N=N, J=2, mu_s=0.5, mu_lambda=1.0) as m:
+        beta = m.info()["beta"]
+        m.set_x(x0)
+        res = cplx(m.vis_residual())
+        obj = m.objective()
+    assert abs(beta - ov.vis_lipschitz(d)) / beta < 1e-5
+    assert rel(res, ov.phi(x0, vi.uvw, vi.lam, vi.cell) - vis) < 1e-5
+    assert abs(obj[1] - ov.vis_data_term(x0, d)) / ov.vis_data_term(x0, d) < 1e-5
+
+
+@pytest.mark.parametrize("prior,mu_l", [(0, 1.0), (1, 1.0), (0, 0.0)])
+def test_iterations_match_oracle(lib, prior, mu_l):
+    """Iterations of Algorithm 1 with the visibility data term from a clipping X0, both priors, and
+    mu_lambda = 0 (the spectral kernel then only takes the primal step)."""
+    N, L, K, J = 32, 6, 160, 2
+    vi, vis = inputs(N, L, K, seed=9)
+    d = ov.VisData(uvw=vi.uvw, lam=vi.lam, cell=vi.cell, vis=vis, N=N)
+    pr = "uob" if prior == 1 else "iuwt"
+    p = om.Problem(dirty=None, psf=None, J=J, mu_s=2.0, mu_l=mu_l, vis=d, prior=pr)
+    tau = om.step_sizes(p)[0]
+    x0 = f32(np.random.default_rng(2).normal(size=(L, N, N)) + 0.2)
+    st = om.init_state(p, x0)
+    for _ in range(5):
+        st = om.iterate(p, st, tau)
+    with lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, N=N, J=J, mu_s=2.0, mu_lambda=mu_l, tau=tau,
+                                      prior=prior) as m:
+        m.set_x(x0)
+        m.step(5)
+        X = m.get_x().double().cpu().numpy()
+        U = m.get_u().double().cpu().numpy()
+        V = m.get_v().double().cpu().numpy()
+        f = m.objective()[0]
+    assert np.mean(X == 0) > 0.2  # the positivity step clips
+    assert rel(X, st.X) < 1e-4
+    assert rel(U, st.U) < 1e-4
+    if mu_l > 0:
+        assert rel(V, st.V) < 1e-4
+    f_ref = om.objective(p, st.X)[0]
+    assert abs(f - f_ref) / abs(f_ref) < 1e-4
+
+
+def test_solve_reaches_the_oracle_objective(lib):
+    """50 iterations from zero, then the objective against the oracle's after the same iterations."""
+    N, L, K, J = 16, 4, 120, 2
+    vi, vis = inputs(N, L, K, seed=1)
+    d = ov.VisData(uvw=vi.uvw, lam=vi.lam, cell=vi.cell, vis=vis, N=N)
+    p = om.Problem(dirty=None, psf=None, J=J, mu_s=1.0, mu_l=2.0, vis=d)
+    tau = om.step_sizes(p)[0]
+    st, _ = om.solve(p, 50, tau=tau)
+    with lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, N=N, J=J, mu_s=1.0, mu_lambda=2.0, tau=tau) as m:
+        it, f = m.solve(50, check_every=10, tol=0.0)
+        snr = m.snr(vi.sky)
+    f_ref = om.objective(p, st.X)[0]
+    assert it == 50
+    assert abs(f - f_ref) / abs(f_ref) < 1e-4
+    assert abs(snr - om.snr_db(st.X, vi.sky)) < 1e-3
+
+
+def test_benchmark_size_sampled(lib):
+    """256^2 x 64 channels, 2000 baselines (the visibility benchmark's configuration, same launch
+    path): sampled visibilities of Phi x and sampled pixels of the gradient against the oracle
+    evaluated entry by entry."""
+    N, L, K = 256, 64, 2000
+    vi = synth.make_vis_inputs(synth.VisSpec(N=N, L=L, K=K, n_sources=20, seed=0))
+    rng = np.random.default_rng(0)
+    vis = f32(rng.normal(size=(L, K))) + 1j * f32(rng.normal(size=(L, K)))
+    x = f32(vi.sky)
+    chans = [0, 37, 63]
+    with lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, N=N, J=4, mu_s=0.1, mu_lambda=0.1,
+                                      power_iters=2) as m:
+        phi = cplx(m.apply_op(lib.OP_PHI, x))
+        grad = m.apply_op(lib.OP_GRAD, x).double().cpu().numpy()
+    ks = np.sort(rng.choice(K, size=40, replace=False))
+    pix = rng.choice(N * N, size=48, replace=False)
+    for l in chans:
+        # one pass over the channel's visibilities in chunks: each chunk's rows of Phi give its
+        # visibilities (some of them sampled) and its share of the gradient at the sampled pixels
+        want_phi = np.zeros(K, complex)
+        g = np.zeros(len(pix))
+        for k0 in range(0, K, 250):
+            A = ov.phase_matrix(N, vi.cell, vi.uvw[k0:k0 + 250], vi.lam[l])
+            v = A @ x[l].ravel()
+            want_phi[k0:k0 + 250] = v
+            g += np.real(A[:, pix].conj().T @ (v - vis[l, k0:k0 + 250]))
+        assert rel(phi[l, ks], want_phi[ks]) < 1e-5
+        assert rel(grad[l].ravel()[pix], g) < 1e-5
+
+
+def test_error_paths(lib):
+    N, L, K = 16, 2, 10
+    vi, vis = inputs(N, L, K)
+    with pytest.raises(lib.MuffinError) as e:
+        lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, 0.2, N=N, J=2, mu_s=0.1, mu_lambda=0.1)
+    assert e.value.code == lib.EINVAL  # the corner pixel leaves the unit disc
+    vi12, vis12 = inputs(12, L, K)
+    with pytest.raises(lib.MuffinError) as e:
+        lib.Muffin.from_visibilities(vis12, vi12.uvw, vi12.lam, vi12.cell, N=12, J=2, mu_s=0.1, mu_lambda=0.1)
+    assert e.value.code == lib.EINVAL  # N not a multiple of 8
+    bad = vis.copy()
+    bad[1, 3] = np.nan
+    with pytest.raises(lib.MuffinError) as e:
+        lib.Muffin.from_visibilities(bad, vi.uvw, vi.lam, vi.cell, N=N, J=2, mu_s=0.1, mu_lambda=0.1)
+    assert e.value.code == lib.ENONFINITE
+    with pytest.raises(lib.MuffinError) as e:
+        lib.Muffin.from_visibilities(vis, vi.uvw, -vi.lam, vi.cell, N=N, J=2, mu_s=0.1, mu_lambda=0.1)
+    assert e.value.code == lib.EINVAL
+    with lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, N=N, J=2, mu_s=0.1, mu_lambda=0.1) as m:
+        for op in (lib.OP_H, lib.OP_HT):
+            with pytest.raises(lib.MuffinError) as e:
+                m.apply_op(op, np.zeros((L, N, N), np.float32))
+            assert e.value.code == lib.EINVAL
+        with pytest.raises(lib.MuffinError):
+            m.warm_input()
+    c = synth.make_cube(synth.CubeSpec(N=16, L=2, J=2, n_sources=2, n_baselines=20))
+    with lib.Muffin(c.dirty, c.psf, J=2, mu_s=0.1, mu_lambda=0.1) as m:
+        with pytest.raises(lib.MuffinError) as e:
+            m.apply_op(lib.OP_PHI, np.zeros((2, 16, 16), np.float32))
+        assert e.value.code == lib.EINVAL
