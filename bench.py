@@ -7,7 +7,8 @@ fused spectral step, spatial dual step).  Inputs are synthetic (seeded generator
 before timing.  Prints one JSON line.  Other workloads: --workload batch32 (32 uneven cubes
 advanced together), --workload cnn (the warm-start network's inference and training step),
 --workload calib (the mu_lambda = 0 first step of the calibration protocol of Sec. 4, beside the
-learned warm start's inference time on the same cube).
+learned warm start's inference time on the same cube), --workload vis (the iteration with the
+visibility-domain data term of Sec. 2, eq. (viseq), on 256^2 x 64 channels and 2000 baselines).
 """
 import argparse
 import hashlib
@@ -285,6 +286,8 @@ def main():
         return bench_cnn(args)
     if args.workload == "calib":
         return bench_calib(args)
+    if args.workload.startswith("vis"):
+        return bench_vis(args)
     spec = synth.WORKLOADS[args.workload]
     N, L, J = spec.N, spec.L, spec.J
     t0 = time.time()
@@ -540,6 +543,156 @@ def bench_calib(args):
                      "analysis_dual": round(ph[4], 3)},
         "step1_2000_iterations_s": round(2000 * ms_per_step / 1e3, 2),
         "cnn_warm_start_ms": round(ws_ms, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
+# Visibility workload: the medium cube's shape (256^2 x 64 channels, J = 4, 2000 baselines) with the
+# data term of eq. (viseq).  Each (visibility, pixel) pair needs at least two FP64 FMAs for the phase,
+# one v_fract_f64, one conversion to FP32, one v_sin_f32, one v_cos_f32 and two FP32 FMAs: eight VALU
+# instructions.  A SIMD issues one wave64 VALU instruction per four cycles (16 lanes a cycle), the
+# sine and cosine included: their longer latency overlaps independent work (an issue-rate probe of
+# this mix reached 9.3 lane slots per pair with its extra conversion).  256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz = 3.93e13 lane slots per second, so 4.92e12 pairs per second bounds the direct sum.
+VIS_SPEC = dict(N=256, L=64, K=2000, J=4, n_sources=20, seed=0)
+VIS_SLOTS_PER_PAIR = 8.0
+VIS_PAIR_PEAK = 256 * 4 * 16 * 2.4e9 / VIS_SLOTS_PER_PAIR
+VIS_SAMPLE_TAU = 1e-6  # step of the FP64 sample (fixed, so that the oracle computes no beta)
+
+
+def vis_regularisation(K):
+    # the image-plane workloads' weights (mu_s 0.25, mu_lambda 3 for PSFs of peak 1) scaled by the
+    # peak K of Phi^H Phi's point response; sigma keeps sigma ||K||^2 of the order of beta / 2
+    return dict(mu_s=0.25 * K, mu_lambda=3.0 * K, sigma=1.0 / (4.0 * K))
+
+
+def cpu_baseline_vis(L_sample, out_npz):
+    """The FP64 oracle on the first L_sample channels of the visibility workload (single-threaded
+    subprocess): visibilities simulated by the oracle's Phi plus the generator's noise, then one
+    iteration from a seeded positive X0 with a fixed tau; its inputs and final state go to out_npz
+    for the same sample on the GPU."""
+    sp = VIS_SPEC
+    code = f"""
+import time, sys
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+from oracle import muffin as om, visibility as ov
+from paper_1602_08847_amd import synth
+vi = synth.make_vis_inputs(synth.VisSpec(N={sp['N']}, L={sp['L']}, K={sp['K']}, n_sources={sp['n_sources']},
+                                         seed={sp['seed']}))
+Ls = {L_sample}
+lam = vi.lam[:Ls]
+vis = np.stack([ov.phi(vi.sky[l:l + 1], vi.uvw, lam[l:l + 1], vi.cell)[0] for l in range(Ls)]) + vi.noise[:Ls]
+vis = vis.astype(np.complex64).astype(np.complex128)
+d = ov.VisData(uvw=vi.uvw, lam=lam, cell=vi.cell, vis=vis, N={sp['N']})
+reg = {vis_regularisation(sp['K'])!r}
+p = om.Problem(dirty=None, psf=None, J={sp['J']}, mu_s=reg['mu_s'], mu_l=reg['mu_lambda'], sigma=reg['sigma'], vis=d)
+rng = np.random.default_rng(7)
+X0 = np.abs(rng.standard_normal(size=(Ls, {sp['N']}, {sp['N']}), dtype=np.float32))
+st = om.init_state(p, X0.astype(np.float64))
+t0 = time.perf_counter()
+st = om.iterate(p, st, {VIS_SAMPLE_TAU!r})
+dt = time.perf_counter() - t0
+np.savez({out_npz!r}, X=st.X, U=st.U, V=st.V, X0=X0, vis=vis, lam=lam)
+print(dt)
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    dt = float(out.stdout.strip().splitlines()[-1])
+    return sp["N"] * sp["N"] * L_sample / dt, dt
+
+
+def bench_vis(args):
+    """The iteration of Algorithm 1 with the visibility-domain data term (Sec. 2, eq. (viseq)):
+    exact Phi and Phi^H by direct sums on the GPU.  The timed workload's visibilities are the
+    library's own Phi of the synthetic sky plus the generator's noise (their values do not change
+    the work); the FP64 sample's come from the oracle."""
+    import torch
+    from paper_1602_08847_amd import muffin, synth
+    sp = VIS_SPEC
+    N, L, K, J = sp["N"], sp["L"], sp["K"], sp["J"]
+    vi = synth.make_vis_inputs(synth.VisSpec(N=N, L=L, K=K, n_sources=sp["n_sources"], seed=sp["seed"]))
+    reg = vis_regularisation(K)
+    with muffin.Muffin.from_visibilities(np.zeros((L, K), np.complex64), vi.uvw, vi.lam, vi.cell, N=N, J=J,
+                                         power_iters=1, **reg) as m0:
+        v = m0.apply_op(muffin.OP_PHI, vi.sky.astype(np.float32)).double().cpu().numpy()
+    vis = v[..., 0] + 1j * v[..., 1] + vi.noise
+    m = muffin.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, N=N, J=J, **reg)
+    info = m.info()
+    print(f"[bench] visibility context ready: beta={info['beta']:.4e} tau={info['tau']:.3e}", file=sys.stderr,
+          flush=True)
+    if args.autotune:
+        m.autotune(reps=3)
+    ph = m.profile(args.profile_steps)
+    m.step(args.warmup)
+    torch.cuda.synchronize()
+    dev_ms = m.step_timed(args.steps)
+    torch.cuda.synchronize()
+    ms_per_step = dev_ms / args.steps
+    obj = m.objective()
+    m.close()
+    vox = N * N * L
+    pairs = float(L) * K * N * N  # (visibility, pixel) pairs of one direction
+    grad_ms = ph[2]
+    achieved = 2 * pairs / (grad_ms * 1e-3)
+    print(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms per iteration; phases ms {np.round(ph[:5], 3).tolist()}; "
+          f"objective {obj[0]:.6e}", file=sys.stderr, flush=True)
+    roof = {
+        "bound": "alu",
+        "kernel": "visibility gradient (k_vis_fwd + k_vis_adj, with k_vis_xn and k_vis_resid)",
+        "achieved": achieved,
+        "peak": VIS_PAIR_PEAK,
+        "unit": "pairs/s",
+        "frac": round(achieved / VIS_PAIR_PEAK, 4),
+        "traffic": None,
+        "pairs_per_launch": pairs,
+        "kernel_avg_ms": round(grad_ms, 4),
+        "slots_per_pair": VIS_SLOTS_PER_PAIR,
+        "phase_ms": {"adjoint": round(ph[1], 3), "gradient": round(grad_ms, 3), "spectral": round(ph[3], 3),
+                     "analysis_dual": round(ph[4], 3)},
+    }
+    cpu = None
+    if not args.no_cpu:
+        import tempfile
+        Ls = 2
+        with tempfile.TemporaryDirectory() as td:
+            npz = os.path.join(td, "oracle_vis.npz")
+            cv, dt = cpu_baseline_vis(Ls, npz)
+            ref = np.load(npz)
+            with muffin.Muffin.from_visibilities(ref["vis"], vi.uvw, ref["lam"], vi.cell, N=N, J=J,
+                                                 tau=VIS_SAMPLE_TAU, power_iters=2, **reg) as ms:
+                ms.set_x(ref["X0"])
+                ms.step(1)
+                got = {"X": ms.get_x(), "U": ms.get_u(), "V": ms.get_v()}
+            err = {k: float(np.linalg.norm(t.double().cpu().numpy() - ref[k]) / np.linalg.norm(ref[k]))
+                   for k, t in got.items()}
+            err["clipped_fraction_X"] = float(np.mean(ref["X"] == 0))
+        print(f"[bench] oracle sample {dt:.1f}s; FP32 vs FP64 errors {err}", file=sys.stderr, flush=True)
+        cpu = {"value": cv, "unit": "voxel-iter/s", "cores": 1, "kind": "oracle",
+               "sample": f"FP64 oracle, the first {Ls} channels of the same inputs ({N}^2, {K} baselines), "
+                         f"one iteration from a seeded positive X0 with tau {VIS_SAMPLE_TAU}, {dt:.1f}s "
+                         f"single-threaded",
+               "fp64_error": {**err, "what": "relative L2 of the GPU's FP32 X, U, V after the same iteration "
+                                             "of the same sample"}}
+    line = {
+        "metric": f"voxel-iterations/s on {N}^2x{L} cube with {K} visibilities per channel "
+                  f"(visibility-domain data term, eq. (viseq))",
+        "value": vox * args.steps / (dev_ms / 1e3),
+        "unit": "voxel-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"vis{N}_L{L}_K{K}_J{J}", "N": N, "L": L, "K": K, "J": J},
+        "roofline": roof,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
