@@ -1,6 +1,6 @@
 // Host-side checks of libmuffin built with AddressSanitizer and UndefinedBehaviorSanitizer on its
 // host code (test infrastructure; no GPU needed).  It runs the library's host logic: argument
-// validation of every constructor, error reporting, the Daubechies filter construction, the FFT
+// validation of every constructor (the visibility one included), error reporting, the Daubechies filter construction, the FFT
 // twiddle tables and the Bluestein tables of the spectral step, and context creation without a
 // usable device (the error path that tears a half-built context down).  Each table is checked
 // against its definition, recomputed here in FP64.  Prints "host checks passed" and exits 0 when
@@ -88,6 +88,54 @@ static void check_validation() {
   CHECK(muffin_batch_init(&batch, 2, ps, d, d, 0, nullptr) == MUFFIN_EINVAL);
   CHECK(muffin_batch_init(&batch, 0, ps, d, d, 0, nullptr) == MUFFIN_EINVAL);
   CHECK(muffin_batch_init(nullptr, 2, ps, d, d, 0, nullptr) == MUFFIN_EINVAL);
+  // the visibility constructor: its descriptor, geometry, wavelengths and baselines
+  {
+    std::vector<double> uvw(3 * 5, 1.0), lam(4, 1.0);
+    std::vector<float> vis(2 * 5 * 4, 0.f);
+    muffin_vis_desc d{};
+    d.K = 5;
+    d.cell = 1e-3;
+    d.uvw = uvw.data();
+    d.lambda = lam.data();
+    muffin_params p = base_params();
+    CHECK(muffin_init_vis(&ctx, &p, nullptr, vis.data(), 0, nullptr) == MUFFIN_EINVAL);
+    CHECK(muffin_init_vis(&ctx, &p, &d, nullptr, 0, nullptr) == MUFFIN_EINVAL);
+    struct BadVis {
+      void (*edit)(muffin_params&, muffin_vis_desc&, std::vector<double>&, std::vector<double>&);
+      int code;
+    };
+    const BadVis badv[] = {
+        {[](muffin_params&, muffin_vis_desc& dd, std::vector<double>&, std::vector<double>&) { dd.K = 0; },
+         MUFFIN_EINVAL},
+        {[](muffin_params&, muffin_vis_desc& dd, std::vector<double>&, std::vector<double>&) { dd.cell = 0.03; },
+         MUFFIN_EINVAL},  // the corner pixel leaves the unit disc
+        {[](muffin_params&, muffin_vis_desc& dd, std::vector<double>&, std::vector<double>&) { dd.cell = NAN; },
+         MUFFIN_EINVAL},
+        {[](muffin_params& pp, muffin_vis_desc&, std::vector<double>&, std::vector<double>&) { pp.N = 12; },
+         MUFFIN_EINVAL},  // not a multiple of 8
+        {[](muffin_params&, muffin_vis_desc&, std::vector<double>&, std::vector<double>& ll) { ll[2] = -1.0; },
+         MUFFIN_EINVAL},
+        {[](muffin_params&, muffin_vis_desc&, std::vector<double>& uu, std::vector<double>&) { uu[7] = INFINITY; },
+         MUFFIN_ENONFINITE},
+        {[](muffin_params&, muffin_vis_desc& dd, std::vector<double>&, std::vector<double>&) { dd.power_iters = -1; },
+         MUFFIN_EINVAL},
+    };
+    for (const BadVis& b : badv) {
+      muffin_params pp = base_params();
+      muffin_vis_desc dd = d;
+      std::vector<double> uu = uvw, ll = lam;
+      b.edit(pp, dd, uu, ll);
+      dd.uvw = uu.data();
+      dd.lambda = ll.data();
+      ctx = reinterpret_cast<muffin_ctx*>(&pp);  // must be reset to NULL on error
+      CHECK(muffin_init_vis(&ctx, &pp, &dd, vis.data(), 0, nullptr) == b.code);
+      CHECK(ctx == nullptr);
+    }
+    float cw[4] = {1.f, 1.f, 1.f, 1.f};
+    p.chan_weight = cw;
+    CHECK(muffin_init_vis(&ctx, &p, &d, vis.data(), 0, nullptr) == MUFFIN_EINVAL);
+    CHECK(muffin_vis_residual(nullptr, vis.data(), 0) == MUFFIN_EINVAL);
+  }
   // calls on NULL handles
   double out[8];
   CHECK(muffin_step(nullptr, 1) == MUFFIN_EINVAL);
