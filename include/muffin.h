@@ -118,18 +118,19 @@ int muffin_init(muffin_ctx** out, const muffin_params* p, const float* dirty, co
  * Visibility-domain data term (Sec. 2, eq. (viseq)): instead of dirty images and PSFs, the context
  * holds K complex visibilities per channel and minimises
  *
- *   sum_l 1/2 ||v_l - Phi_l x_l||^2 + 1_{R+}(X) + mu_s sum_l ||W_s x_l||_1 + mu_lambda sum_n ||W_lambda x^n||_1
+ *   sum_l w_l/2 ||v_l - Phi_l x_l||^2 + 1_{R+}(X) + mu_s sum_l ||W_s x_l||_1 + mu_lambda sum_n ||W_lambda x^n||_1
  *
  * with (Phi_l x)_k = sum over pixels (i, j) of x_ij / n_ij exp(-2 pi i (u_k l_j + v_k m_i + w_k n_ij) / lambda_l):
  * l_j = (j - N/2) cell, m_i = (i - N/2) cell, n_ij = sqrt(1 - l_j^2 - m_i^2); the w n term is the
  * direction-dependent effect that the image-plane model leaves out.  Phi is evaluated exactly (a
  * direct sum over every visibility and pixel, FP64 phases, FP32 products and sums), so a step costs
- * about 2 L K N^2 complex exponentials.  The gradient of the data term is Re Phi_l^H (Phi_l x_l - v_l);
- * beta is 1.01 times a power-iteration estimate (FP64 norms, power_iters steps from the all-ones
- * cube) of the largest eigenvalue of Re Phi^H Phi over all channels.  The rest of Algorithm 1 (both
- * priors, the spectral term, relaxation, muffin_step / solve / objective / state calls, the
- * autotuner) is unchanged; out[1] of muffin_objective is sum_l 1/2 ||v_l - Phi_l x_l||^2.  Not
- * available with visibilities: channel weights, the warm start, MUFFIN_OP_H / HT, batches.
+ * about 2 L K N^2 complex exponentials.  w_l are the channel weights of eq. (reg) (chan_weight, 1 by
+ * default).  The gradient of the data term is w_l Re Phi_l^H (Phi_l x_l - v_l); beta is 1.01 times a
+ * power-iteration estimate (FP64 norms, power_iters steps from the all-ones cube) of the largest
+ * eigenvalue of w_l Re Phi_l^H Phi_l over all channels.  The rest of Algorithm 1 (both priors, the
+ * spectral term, relaxation, muffin_step / solve / objective / state calls, the autotuner) is
+ * unchanged; out[1] of muffin_objective is sum_l w_l/2 ||v_l - Phi_l x_l||^2.  Not available with
+ * visibilities: the warm start, MUFFIN_OP_H / HT, batches.
  * --------------------------------------------------------------------------------------------- */
 typedef struct {
   int32_t K;            /* visibilities (baselines) per channel, 1 <= K <= 2^22 */
@@ -139,15 +140,15 @@ typedef struct {
   int32_t power_iters;  /* power iterations for beta, 0 for the default 40 */
 } muffin_vis_desc;
 
-/* Create a context with the visibility data term: p as for muffin_init (N a multiple of 8,
- * chan_weight NULL), vis [L][K] complex as interleaved FP32 (re, im) on the host or the device.
+/* Create a context with the visibility data term: p as for muffin_init (N a multiple of 8), vis
+ * [L][K] complex as interleaved FP32 (re, im) on the host or the device.
  * Initialises X = U = V = 0 (Algorithm 1, "Initialize").  Errors: EINVAL (sizes, NULL pointers,
  * parameters, a pixel outside the unit disc), ENONFINITE (NaN/Inf in uvw or vis, or a power
  * iteration that breaks down), ESTEP, ENOMEM, EHIP.  *out is NULL on error. */
 int muffin_init_vis(muffin_ctx** out, const muffin_params* p, const muffin_vis_desc* desc, const float* vis,
                     int vis_on_device, void* hip_stream);
-/* Residual Phi_l x_l - v_l of the current X for every channel, [L][K] complex as interleaved FP32,
- * into host or device memory.  EINVAL for an image-plane context. */
+/* Residual Phi_l x_l - v_l of the current X for every channel (not weighted), [L][K] complex as
+ * interleaved FP32, into host or device memory.  EINVAL for an image-plane context. */
 int muffin_vis_residual(muffin_ctx* ctx, float* r, int on_device);
 
 /* Run n_iter >= 0 iterations of Algorithm 1 (gradient, primal proximal step, spatial and spectral
@@ -234,7 +235,7 @@ int muffin_set_state(muffin_ctx* ctx, const void* blob, size_t bytes);
  *                                         the coarse plane only when it is penalised (else 0)
  *   MUFFIN_OP_PHI      cube -> [L][K] complex (interleaved FP32)   Phi_l x_l (Sec. 2, eq. (viseq))
  *   MUFFIN_OP_PHI_ADJ  [L][K] complex -> cube                     Re Phi_l^H r_l
- * With visibilities, MUFFIN_OP_GRAD is Re Phi_l^H (Phi_l x_l - v_l); the PHI operators need a
+ * With visibilities, MUFFIN_OP_GRAD is w_l Re Phi_l^H (Phi_l x_l - v_l); the PHI operators need a
  * visibility context and H / HT an image-plane one (EINVAL otherwise).
  * The context's state is not changed.  EINVAL for an unknown op. */
 #define MUFFIN_OP_H 1

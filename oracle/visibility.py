@@ -17,10 +17,11 @@ Discretisation read here (the paper fixes none of it):
   were simulated with the same operator);
 * channel l observes every baseline at its own wavelength lambda_l, so one set of K baselines
   gives K visibilities per channel;
-* the data term is 1/2 sum_l ||v_l - Phi_l x_l||^2 (eq. (reg) with Phi_l in place of H_l); x is
-  real, so its gradient is Re Phi_l^H (Phi_l x_l - v_l);
-* beta, the Lipschitz constant of that gradient, is the largest eigenvalue of Re Phi^H Phi over
-  all channels. It has no closed form here: it is estimated by power iteration in FP64 from the
+* the data term is sum_l w_l/2 ||v_l - Phi_l x_l||^2 (eq. (reg) with Phi_l in place of H_l and
+  its channel weights w_l = 1/sigma_l^2, 1 by default); x is real, so its gradient is
+  w_l Re Phi_l^H (Phi_l x_l - v_l);
+* beta, the Lipschitz constant of that gradient, is the largest eigenvalue of w_l Re Phi_l^H Phi_l
+  over all channels. It has no closed form here: it is estimated by power iteration in FP64 from the
   all-ones cube (``power_iters`` steps), and the step sizes use ``BETA_MARGIN`` times the estimate.
 
 Everything is plain numpy on dense phase matrices: sizes are kept small.
@@ -42,6 +43,7 @@ class VisData:
     cell: float  # pixel size in direction-cosine units
     vis: np.ndarray  # (L, K) complex visibilities
     N: int  # image side
+    w: np.ndarray | None = None  # (L,) channel weights 1/sigma_l^2, or None for 1
 
 
 def direction_cosines(N: int, cell: float):
@@ -78,26 +80,35 @@ def phi_adjoint(r: np.ndarray, uvw: np.ndarray, lam: np.ndarray, cell: float, N:
                      for l in range(L)])
 
 
+def _weights(L: int, w) -> np.ndarray:
+    return np.ones(L) if w is None else np.asarray(w, dtype=np.float64)
+
+
 def vis_gradient(x: np.ndarray, d: VisData) -> np.ndarray:
-    """Gradient of 1/2 sum_l ||v_l - Phi_l x_l||^2 at the real cube x."""
-    return phi_adjoint(phi(x, d.uvw, d.lam, d.cell) - d.vis, d.uvw, d.lam, d.cell, d.N)
+    """Gradient of sum_l w_l/2 ||v_l - Phi_l x_l||^2 at the real cube x."""
+    wl = _weights(x.shape[0], d.w)
+    r = wl[:, None] * (phi(x, d.uvw, d.lam, d.cell) - d.vis)
+    return phi_adjoint(r, d.uvw, d.lam, d.cell, d.N)
 
 
 def vis_data_term(x: np.ndarray, d: VisData) -> float:
-    """1/2 sum_l ||v_l - Phi_l x_l||^2."""
+    """sum_l w_l/2 ||v_l - Phi_l x_l||^2."""
+    wl = _weights(x.shape[0], d.w)
     r = phi(x, d.uvw, d.lam, d.cell) - d.vis
-    return float(0.5 * np.sum(np.abs(r) ** 2))
+    return float(0.5 * np.sum(wl * np.sum(np.abs(r) ** 2, axis=1)))
 
 
-def power_estimate(uvw: np.ndarray, lam: np.ndarray, cell: float, N: int, iters: int = POWER_ITERS) -> float:
-    """Largest eigenvalue of Re Phi^H Phi over all channels, by power iteration from the all-ones
-    cube: x <- A x / ||A x||; the estimate is ||A x|| of the last step."""
+def power_estimate(uvw: np.ndarray, lam: np.ndarray, cell: float, N: int, iters: int = POWER_ITERS,
+                   w=None) -> float:
+    """Largest eigenvalue of w_l Re Phi_l^H Phi_l over all channels, by power iteration from the
+    all-ones cube: x <- A x / ||A x||; the estimate is ||A x|| of the last step."""
     L = len(lam)
+    wl = _weights(L, w)
     x = np.ones((L, N, N))
     x /= np.linalg.norm(x)
     est = 0.0
     for _ in range(iters):
-        y = phi_adjoint(phi(x, uvw, lam, cell), uvw, lam, cell, N)
+        y = phi_adjoint(wl[:, None] * phi(x, uvw, lam, cell), uvw, lam, cell, N)
         est = float(np.linalg.norm(y))
         x = y / est
     return est
@@ -105,4 +116,4 @@ def power_estimate(uvw: np.ndarray, lam: np.ndarray, cell: float, N: int, iters:
 
 def vis_lipschitz(d: VisData, iters: int = POWER_ITERS) -> float:
     """beta of the visibility data term: BETA_MARGIN times the power-iteration estimate."""
-    return BETA_MARGIN * power_estimate(d.uvw, d.lam, d.cell, d.N, iters)
+    return BETA_MARGIN * power_estimate(d.uvw, d.lam, d.cell, d.N, iters, d.w)

@@ -527,13 +527,15 @@ int enqueue_dual_update(muffin_ctx* c, const float* in, bool timed = false, int 
   return MUFFIN_OK;
 }
 
-// Phi_l (x_l) (x in slots of cs floats) into the band sums, then the residual Phi x + vsign vis
-// (vis NULL: Phi x) into c->vp, with 1/2 |r|^2 block sums in partial when it is not NULL.
+// Phi_l (x_l) (x in slots of cs floats) into the band sums, then the residual r = Phi x + vsign vis
+// (vis NULL: Phi x): w_l r into c->vp for the adjoint (weighted: the channel weights of eq. (reg),
+// else 1), r itself into rout unless NULL, and 1/2 w_l |r|^2 block sums in partial unless NULL.
 int enqueue_vis_forward(muffin_ctx* c, const float* x, long long xcs, const float2* vis, float vsign, double* partial,
-                        int* nb, float2* rout = nullptr) {
+                        int* nb, float2* rout = nullptr, bool weighted = true) {
   MF_TRY(launch_vis_xn(x, xcs, c->vinvn, c->XN, c->N, c->L, c->st));
   MF_TRY(launch_vis_fwd(c->vp, c->XN, c->vlt, c->vnt, c->vpart, c->N, c->K, c->L, c->vC, c->st));
-  return launch_vis_resid(c->vpart, c->vC, c->L, c->K, vis, vsign, c->vp, partial, nb, rout, c->st);
+  return launch_vis_resid(c->vpart, c->vC, c->L, c->K, vis, vsign, weighted ? c->chan_w : nullptr, c->vp, partial,
+                          nb, rout, c->st);
 }
 
 int enqueue_gradient(muffin_ctx* c, const float* x, float* out, const float* s, float s_scale) {
@@ -1329,7 +1331,6 @@ int muffin_init_vis(muffin_ctx** out, const muffin_params* p, const muffin_vis_d
   MF_TRY(validate(p));
   if (!d || !vis || !d->uvw || !d->lambda) return set_error("desc, vis, uvw or lambda is NULL"), MUFFIN_EINVAL;
   if (p->N % 8) return set_error("the visibility data term needs N to be a multiple of 8"), MUFFIN_EINVAL;
-  if (p->chan_weight) return set_error("channel weights are not supported with visibilities"), MUFFIN_EINVAL;
   if (d->K < 1 || d->K > (1 << 22)) return set_error("K must be in [1, 2^22]"), MUFFIN_EINVAL;
   if (d->power_iters < 0 || d->power_iters > 100000) return set_error("power_iters must be in [0, 1e5]"), MUFFIN_EINVAL;
   const double half = 0.5 * p->N * d->cell;
@@ -1888,11 +1889,11 @@ int muffin_apply_op(muffin_ctx* c, int op, const float* in, float* out) {
   switch (op) {
     case MUFFIN_OP_PHI:
       // the residual with no data is Phi x; it also lands in out
-      return enqueue_vis_forward(c, in, np, nullptr, 0.f, nullptr, nullptr, (float2*)out);
+      return enqueue_vis_forward(c, in, np, nullptr, 0.f, nullptr, nullptr, (float2*)out, false);
     case MUFFIN_OP_PHI_ADJ:
       // no bands: the residual is the operand itself
-      MF_TRY(launch_vis_resid(nullptr, 0, c->L, c->K, (const float2*)in, 1.f, c->vp, nullptr, nullptr, nullptr,
-                              c->st));
+      MF_TRY(launch_vis_resid(nullptr, 0, c->L, c->K, (const float2*)in, 1.f, nullptr, c->vp, nullptr, nullptr,
+                              nullptr, c->st));
       return launch_vis_adj(c->vp, c->K, c->L, c->vlt, c->vnt, c->vinvn, c->N, out, np, nullptr, 0, 0.f, c->st);
     case MUFFIN_OP_H:
     case MUFFIN_OP_HT:

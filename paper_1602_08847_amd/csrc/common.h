@@ -320,10 +320,10 @@ int launch_vis_xn(const float* X, long long cs, const float* invn, float* XN, in
 // part[c][l][k]: band c's share of Phi_l (XN n)_k, C = vis_chunks(N, K, L) bands.
 int launch_vis_fwd(const VisPt* vp, const float* XN, const double* lt, const double* nt, float2* part, int N, int K,
                    int L, int C, hipStream_t st);
-// r = sum of the C bands + vsign vis (vis NULL: 0) into vp (and rout unless NULL); with partial,
-// 1/2 |r|^2 block sums (*nblocks of them).
-int launch_vis_resid(const float2* part, int C, int L, int K, const float2* vis, float vsign, VisPt* vp,
-                     double* partial, int* nblocks, float2* rout, hipStream_t st);
+// r = sum of the C bands + vsign vis (vis NULL: 0); vp receives w_l r (channel weights cw, NULL for 1)
+// and rout (unless NULL) r; with partial, 1/2 w_l |r|^2 block sums (*nblocks of them).
+int launch_vis_resid(const float2* part, int C, int L, int K, const float2* vis, float vsign, const float* cw,
+                     VisPt* vp, double* partial, int* nblocks, float2* rout, hipStream_t st);
 // out = Re Phi^H r (+ s_scale sadd), planes out_cs (sadd: s_cs) floats apart.
 int launch_vis_adj(const VisPt* vp, int K, int L, const double* lt, const double* nt, const float* invn, int N,
                    float* out, long long out_cs, const float* sadd, long long s_cs, float s_scale, hipStream_t st);

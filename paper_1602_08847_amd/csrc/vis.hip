@@ -170,12 +170,13 @@ int launch_vis_fwd(const VisPt* vp, const float* XN, const double* lt, const dou
   return MUFFIN_OK;
 }
 
-// r = sum_c part[c] + vsign vis (vis may be NULL), stored in vp (and in rout when it is not NULL);
-// partial[block] = 1/2 sum |r|^2 in FP64 when partial is not NULL.
-__global__ void __launch_bounds__(256) k_vis_resid(const float2* __restrict__ part, int C, long long LK,
+// r = sum_c part[c] + vsign vis (vis may be NULL); vp receives w_l r (w_l = cw[l], or 1 when cw is
+// NULL) and rout, when it is not NULL, r itself; partial[block] = 1/2 sum w_l |r|^2 in FP64 when
+// partial is not NULL.
+__global__ void __launch_bounds__(256) k_vis_resid(const float2* __restrict__ part, int C, long long LK, int K,
                                                    const float2* __restrict__ vis, float vsign,
-                                                   VisPt* __restrict__ vp, double* __restrict__ partial,
-                                                   float2* __restrict__ rout) {
+                                                   const float* __restrict__ cw, VisPt* __restrict__ vp,
+                                                   double* __restrict__ partial, float2* __restrict__ rout) {
   __shared__ double red[256];
   const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
   double e = 0.0;
@@ -190,10 +191,11 @@ __global__ void __launch_bounds__(256) k_vis_resid(const float2* __restrict__ pa
       re = fmaf(vsign, vis[t].x, re);
       im = fmaf(vsign, vis[t].y, im);
     }
-    vp[MF_CHK(t, LK)].rre = re;
-    vp[t].rim = im;
+    const float wl = cw ? cw[t / K] : 1.f;
+    vp[MF_CHK(t, LK)].rre = wl * re;
+    vp[t].rim = wl * im;
     if (rout) rout[t] = make_float2(re, im);
-    e = (double)re * re + (double)im * im;
+    e = (double)wl * ((double)re * re + (double)im * im);
   }
   if (!partial) return;
   red[threadIdx.x] = e;
@@ -205,12 +207,13 @@ __global__ void __launch_bounds__(256) k_vis_resid(const float2* __restrict__ pa
   if (threadIdx.x == 0) partial[blockIdx.x] = 0.5 * red[0];
 }
 
-int launch_vis_resid(const float2* part, int C, int L, int K, const float2* vis, float vsign, VisPt* vp,
-                     double* partial, int* nblocks, float2* rout, hipStream_t st) {
+int launch_vis_resid(const float2* part, int C, int L, int K, const float2* vis, float vsign, const float* cw,
+                     VisPt* vp, double* partial, int* nblocks, float2* rout, hipStream_t st) {
   const long long LK = (long long)L * K;
   const long long nb = (LK + 255) / 256;
   if (partial && nb > kMaxPartials) return set_error("visibility residual: too many blocks"), MUFFIN_EINVAL;
-  hipLaunchKernelGGL(k_vis_resid, dim3((unsigned)nb), dim3(256), 0, st, part, C, LK, vis, vsign, vp, partial, rout);
+  hipLaunchKernelGGL(k_vis_resid, dim3((unsigned)nb), dim3(256), 0, st, part, C, LK, K, vis, vsign, cw, vp, partial,
+                     rout);
   MF_HIP(hipGetLastError());
   if (nblocks) *nblocks = (int)nb;
   return MUFFIN_OK;

@@ -193,9 +193,11 @@ class Muffin:
     @classmethod
     def from_visibilities(cls, vis, uvw, lam, cell: float, N: int, J: int, mu_s: float, mu_lambda: float,
                           iuwt_gen: int = 2, penalize_coarse: bool = True, tau: float = 0.0, sigma: float = 1.0,
-                          rho: float = 1.0, flags: int = 0, prior: int = PRIOR_IUWT, power_iters: int = 0):
+                          rho: float = 1.0, flags: int = 0, prior: int = PRIOR_IUWT, power_iters: int = 0,
+                          chan_weight=None):
         """A context with the visibility-domain data term: vis (L, K) complex (or (L, K, 2) float),
-        uvw (K, 3) baselines in metres, lam (L,) wavelengths in metres, cell the pixel size."""
+        uvw (K, 3) baselines in metres, lam (L,) wavelengths in metres, cell the pixel size, optional
+        channel weights (L,)."""
         torch = _torch()
         v = np.asarray(vis)
         if np.iscomplexobj(v):
@@ -216,6 +218,11 @@ class Muffin:
                     lam=self._lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), power_iters=power_iters)
         p = Params(N=N, L=L, J=J, iuwt_gen=iuwt_gen, penalize_coarse=int(bool(penalize_coarse)),
                    flags=flags, prior=prior, mu_s=mu_s, mu_lambda=mu_lambda, tau=tau, sigma=sigma, rho=rho)
+        if chan_weight is not None:
+            self._cw = np.ascontiguousarray(chan_weight, dtype=np.float32)
+            if self._cw.shape != (L,):
+                raise ValueError("chan_weight must have shape (L,)")
+            p.chan_weight = self._cw.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         h = ctypes.c_void_p()
         _check(_lib.muffin_init_vis(ctypes.byref(h), ctypes.byref(p), ctypes.byref(d),
                                     ctypes.c_void_p(vt.data_ptr()), 1, _stream_handle()), "muffin_init_vis")

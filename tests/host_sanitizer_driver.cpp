@@ -131,7 +131,7 @@ static void check_validation() {
       CHECK(muffin_init_vis(&ctx, &pp, &dd, vis.data(), 0, nullptr) == b.code);
       CHECK(ctx == nullptr);
     }
-    float cw[4] = {1.f, 1.f, 1.f, 1.f};
+    float cw[4] = {1.f, 0.f, 1.f, 1.f};  // a channel weight must be > 0
     p.chan_weight = cw;
     CHECK(muffin_init_vis(&ctx, &p, &d, vis.data(), 0, nullptr) == MUFFIN_EINVAL);
     CHECK(muffin_vis_residual(nullptr, vis.data(), 0) == MUFFIN_EINVAL);

@@ -92,6 +92,36 @@ def test_beta_residual_and_objective(lib):
     assert abs(obj[1] - ov.vis_data_term(x0, d)) / ov.vis_data_term(x0, d) < 1e-5
 
 
+def test_channel_weights(lib):
+    """Channel weights of eq. (reg) with visibilities: the gradient, the data term, beta and five
+    iterations against the oracle with the same weights."""
+    N, L, K, J = 32, 4, 120, 2
+    vi, vis = inputs(N, L, K, seed=5)
+    w = np.array([0.5, 2.0, 1.0, 3.0])
+    wf = f32(w)
+    d = ov.VisData(uvw=vi.uvw, lam=vi.lam, cell=vi.cell, vis=vis, N=N, w=wf)
+    p = om.Problem(dirty=None, psf=None, J=J, mu_s=2.0, mu_l=1.0, vis=d)
+    tau = om.step_sizes(p)[0]
+    x0 = f32(np.abs(np.random.default_rng(3).normal(size=(L, N, N))))
+    st = om.init_state(p, x0)
+    for _ in range(5):
+        st = om.iterate(p, st, tau)
+    with lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, N=N, J=J, mu_s=2.0, mu_lambda=1.0, tau=tau,
+                                      chan_weight=w) as m:
+        grad = m.apply_op(lib.OP_GRAD, x0).double().cpu().numpy()
+        beta = m.info()["beta"]
+        m.set_x(x0)
+        obj = m.objective()
+        res = cplx(m.vis_residual())
+        m.step(5)
+        X = m.get_x().double().cpu().numpy()
+    assert rel(grad, ov.vis_gradient(x0, d)) < 1e-5
+    assert abs(beta - ov.vis_lipschitz(d)) / beta < 1e-5
+    assert abs(obj[1] - ov.vis_data_term(x0, d)) / obj[1] < 1e-5
+    assert rel(res, ov.phi(x0, vi.uvw, vi.lam, vi.cell) - vis) < 1e-5  # the residual is not weighted
+    assert rel(X, st.X) < 1e-4
+
+
 @pytest.mark.parametrize("prior,mu_l", [(0, 1.0), (1, 1.0), (0, 0.0)])
 def test_iterations_match_oracle(lib, prior, mu_l):
     """Iterations of Algorithm 1 with the visibility data term from a clipping X0, both priors, and

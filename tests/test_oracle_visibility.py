@@ -74,12 +74,13 @@ def test_adjoint_and_hermitian_symmetry():
     assert np.allclose(ov.phi(x, -uvw, lam, cell), np.conj(ov.phi(x, uvw, lam, cell)), rtol=1e-12, atol=1e-10)
 
 
-def test_gradient_matches_finite_differences():
+@pytest.mark.parametrize("w", [None, (0.5, 3.0)])
+def test_gradient_matches_finite_differences(w):
     N, L, K = 8, 2, 30
     rng = np.random.default_rng(2)
     uvw = rng_uvw(rng, K, 40.0)
     d = ov.VisData(uvw=uvw, lam=np.array([1.0, 0.75]), cell=0.02,
-                   vis=rng.normal(size=(L, K)) + 1j * rng.normal(size=(L, K)), N=N)
+                   vis=rng.normal(size=(L, K)) + 1j * rng.normal(size=(L, K)), N=N, w=w)
     x = rng.normal(size=(L, N, N))
     e = rng.normal(size=(L, N, N))
     h = 1e-5
@@ -88,18 +89,35 @@ def test_gradient_matches_finite_differences():
     assert abs(fd - an) <= 1e-6 * abs(an)
 
 
+def test_channel_weights_scale_each_channel_alone():
+    # a channel's weight scales its own data term and gradient and leaves the other channel alone
+    N, L, K = 8, 2, 20
+    rng = np.random.default_rng(6)
+    uvw = rng_uvw(rng, K, 40.0)
+    vis = rng.normal(size=(L, K)) + 1j * rng.normal(size=(L, K))
+    x = rng.normal(size=(L, N, N))
+    d1 = ov.VisData(uvw=uvw, lam=np.array([1.0, 0.75]), cell=0.02, vis=vis, N=N)
+    d2 = ov.VisData(uvw=uvw, lam=np.array([1.0, 0.75]), cell=0.02, vis=vis, N=N, w=np.array([1.0, 4.0]))
+    g1, g2 = ov.vis_gradient(x, d1), ov.vis_gradient(x, d2)
+    assert np.allclose(g2[0], g1[0], rtol=1e-13, atol=1e-13) and np.allclose(g2[1], 4.0 * g1[1], rtol=1e-13)
+    one = ov.VisData(uvw=uvw, lam=np.array([0.75]), cell=0.02, vis=vis[1:], N=N)
+    assert np.isclose(ov.vis_data_term(x, d2) - ov.vis_data_term(x, d1), 3.0 * ov.vis_data_term(x[1:], one),
+                      rtol=1e-12)
+
+
 def test_power_estimate_against_dense_eigensolver():
     N, K = 6, 25
     rng = np.random.default_rng(8)
     uvw = rng_uvw(rng, K, 30.0)
     lam = np.array([1.0, 0.7, 0.55])
     cell = 0.03
-    top = 0.0
+    tops = []
     for l in lam:
         # Re Phi^H Phi, its columns from unit images
         cols = [ov.phi_adjoint(ov.phi(np.eye(N * N)[p].reshape(1, N, N), uvw, np.array([l]), cell), uvw,
                                np.array([l]), cell, N).ravel() for p in range(N * N)]
-        top = max(top, float(np.max(np.linalg.eigvalsh(np.array(cols)))))
+        tops.append(float(np.max(np.linalg.eigvalsh(np.array(cols)))))
+    top = max(tops)
     # the three channels' top eigenvalues lie close together, which slows the iteration down
     est = ov.power_estimate(uvw, lam, cell, N, iters=200)
     assert est <= top * (1 + 1e-12)
@@ -107,6 +125,11 @@ def test_power_estimate_against_dense_eigensolver():
     assert ov.power_estimate(uvw, lam, cell, N) >= top * (1 - 1e-2)
     d = ov.VisData(uvw=uvw, lam=lam, cell=cell, vis=np.zeros((3, K), complex), N=N)
     assert ov.vis_lipschitz(d) >= top
+    # channel weights: the weighted eigenvalues, the dense way
+    w = np.array([0.2, 1.0, 2.5])
+    topw = max(w[c] * tops[c] for c in range(3))
+    estw = ov.power_estimate(uvw, lam, cell, N, iters=200, w=w)
+    assert topw * (1 - 1e-4) <= estw <= topw * (1 + 1e-12)
 
 
 def test_pixel_outside_the_unit_disc_is_rejected():
