@@ -252,7 +252,8 @@ int muffin_apply_op(muffin_ctx* ctx, int op, const float* in, float* out);
 
 /* Measurement, not part of the paper's method: time n_iter iterations of Algorithm 1 with HIP
  * events on the library's stream, without graph replay, and report average device milliseconds:
- *   ms[0] whole iteration, [1] spatial adjoint (IUWT^dagger), [2] gradient FFT passes,
+ *   ms[0] whole iteration, [1] spatial adjoint (IUWT^dagger), [2] gradient (FFT passes, or the
+ *   visibility kernels),
  *   [3] fused spectral kernel, [4] spatial analysis and dual update; [5..7] are 0;
  *   ms[8 + 2k] mean duration of one launch of kind k and ms[9 + 2k] launches of kind k per
  *   iteration, for the second-generation band kernels: k = 0 one analysis scale with its dual

@@ -133,6 +133,35 @@ def reference_objective(cube, J: int, sigma: float, iters: int, check_every: int
     return best
 
 
+def reference_run(cube, J: int, sigma: float, iters: int, every: int, tol: float, out_path: str | None = None,
+                  log=None) -> dict:
+    """A plain run from X = 0 recorded every ``every`` iterations: f_ref is its minimum objective, and
+    the same run is the cold start, whose iterations to tol are read from the record (to within
+    ``every``).  With out_path the record is rewritten there after every point, so that a run cut
+    short keeps what it measured."""
+    import torch
+    tr = []
+    with muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as m:
+        tr.append((0, float(m.objective()[0])))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(every, iters + 1, every):
+            m.step(every)
+            tr.append((it, float(m.objective()[0])))
+            if out_path:
+                with open(out_path, "w") as f:
+                    json.dump({"every": every, "sigma": sigma, "trace": tr, "s": time.perf_counter() - t0}, f)
+            if log and it % 10000 == 0:
+                log(f"[warmstart] reference run {it} iterations, f {tr[-1][1]:.10e}")
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+    f_ref = min(f for _, f in tr)
+    cross = next((it for it, f in tr if (f - f_ref) / abs(f_ref) <= tol), None)
+    return {"f_ref": f_ref, "ref_iters": iters, "ref_every": every, "ref_s": sec, "cold_iters_from_ref": cross,
+            "cold_s_from_ref": None if cross is None else sec * cross / iters, "ref_trace": tr, "tol": tol,
+            "sigma": sigma, "f0_cold": tr[0][1]}
+
+
 def compare_cold(cube, J: int, sigma: float, tol: float, f_ref: float, check_every: int, max_iter: int) -> dict:
     """The cold start (X = 0) to the tolerance."""
     out = {"tol": tol, "f_ref": f_ref, "sigma": sigma}
@@ -267,11 +296,31 @@ def main(argv=None):
     ap.add_argument("--learning-curve", default="",
                     help="comma-separated training-set sizes (cubes): one network per size, trained on the first "
                          "cubes of one batch-solved set, each compared against the same cold run")
+    ap.add_argument("--ref-only", action="store_true",
+                    help="only the reference run (the cold start, recorded every --ref-every iterations): f_ref and "
+                         "the cold start's iterations to --tol, written to --out as it goes")
+    ap.add_argument("--ref-every", type=int, default=100)
+    ap.add_argument("--f-ref", type=float, default=None,
+                    help="f_ref of an earlier reference run: skip the reference and cold runs, run the warm starts")
+    ap.add_argument("--autotune", action="store_true", help="tune the band kernels on the test cube first")
     ap.add_argument("--budget", type=int, default=0,
                     help="instead of the 1e-4 gap: iterations of the cold run whose final objective the warm "
                          "start must reach")
     a = ap.parse_args(argv)
     log = lambda s: print(s, file=sys.stderr, flush=True)
+    if a.ref_only:
+        tspec = synth.WORKLOADS[a.test]
+        tspec = synth.CubeSpec(**{**tspec.__dict__, "seed": a.test_seed})
+        cube = synth.make_cube(tspec, dtype=np.float32, with_sky=False)
+        if a.autotune:
+            _tune(cube, tspec.J, a.sigma, log)
+        res = reference_run(cube, tspec.J, a.sigma, a.ref_iters, a.ref_every, a.tol,
+                            a.out.replace(".json", "_trace.json") if a.out else None, log)
+        res.update(test=a.test, test_seed=a.test_seed)
+        log(f"[warmstart] f_ref {res['f_ref']:.10e}; cold start within {a.tol} after {res['cold_iters_from_ref']} "
+            f"iterations")
+        _emit(res, a.out, [])
+        return
     spec = synth.CubeSpec(N=a.train_N, L=a.train_L, J=a.train_J, n_sources=20, n_baselines=2000)
     seeds = [int(v) for v in a.net_seeds.split(",")]
     sizes = [int(v) for v in a.learning_curve.split(",")] if a.learning_curve else []
@@ -308,8 +357,20 @@ def main(argv=None):
     tspec = synth.WORKLOADS[a.test]
     tspec = synth.CubeSpec(**{**tspec.__dict__, "seed": a.test_seed})
     cube = synth.make_cube(tspec, dtype=np.float32, with_sky=not a.budget)
+    if a.autotune:
+        _tune(cube, tspec.J, a.sigma, log)
     common = dict(train_cubes=a.train_cubes, train_iters=a.train_iters, epochs=a.epochs, t_data_s=t_data,
                   test=a.test, test_seed=a.test_seed)
+    if a.f_ref is not None:
+        res = {**common, "f_ref": a.f_ref, "tol": a.tol, "sigma": a.sigma, "runs": []}
+        for net, info in nets:
+            w = compare_warm(net, cube, tspec.J, a.sigma, a.tol, a.f_ref, a.check_every, a.max_iter)
+            w.update(info)
+            log(f"[warmstart] warm (net seed {info['net_seed']}, {info['train_cubes']} training cubes): "
+                f"{w['warm_iters']} iterations, {w['warm_s']:.2f}s")
+            res["runs"].append(w)
+        _emit(res, a.out, nets)
+        return
     if a.budget:
         runs = []
         for net, info in nets:
@@ -337,6 +398,14 @@ def main(argv=None):
         runs.append(w)
     res["runs"] = runs
     _emit(res, a.out, nets)
+
+
+def _tune(cube, J: int, sigma: float, log):
+    """The band-height autotuner on the test cube's sizes (its choices hold for the whole process)."""
+    with muffin.Muffin(cube.dirty, cube.psf, J=J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as m:
+        rep = json.loads(m.autotune(reps=3))
+    log(f"[warmstart] autotuned: {[(s['j'], s['kernel'], s['rows']) for s in rep['scales']]}, "
+        f"fused tail {rep.get('fused_tail')}")
 
 
 def _emit(res: dict, out: str | None, nets):
