@@ -2,8 +2,8 @@
 // visibilities, v_k = sum_p x_p / n_p exp(-2 pi i (u_k l_p + v_k m_p + w_k n_p)), with (u, v, w) the
 // baseline in wavelengths of the channel and (l, m, n) the direction cosines of pixel p
 // (n = sqrt(1 - l^2 - m^2)); the w n term is the direction-dependent effect that keeps Phi from
-// being a Fourier transform.  The data term 1/2 ||v - Phi x||^2 has the gradient
-// Re Phi^H (Phi x - v).
+// being a Fourier transform.  The data term w_l/2 ||v - Phi x||^2 (w_l the channel's weight) has
+// the gradient w_l Re Phi^H (Phi x - v).
 //
 // Both directions are direct sums over all (visibility, pixel) pairs, evaluated exactly rather
 // than through a gridded approximation.  Each pair costs one phase and one complex exponential,
@@ -172,15 +172,15 @@ int launch_vis_fwd(const VisPt* vp, const float* XN, const double* lt, const dou
 
 // r = sum_c part[c] + vsign vis (vis may be NULL); vp receives w_l r (w_l = cw[l], or 1 when cw is
 // NULL) and rout, when it is not NULL, r itself; partial[block] = 1/2 sum w_l |r|^2 in FP64 when
-// partial is not NULL.
+// partial is not NULL.  Grid-stride over the L K visibilities, so that the number of partial sums
+// stays bounded.
 __global__ void __launch_bounds__(256) k_vis_resid(const float2* __restrict__ part, int C, long long LK, int K,
                                                    const float2* __restrict__ vis, float vsign,
                                                    const float* __restrict__ cw, VisPt* __restrict__ vp,
                                                    double* __restrict__ partial, float2* __restrict__ rout) {
   __shared__ double red[256];
-  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
   double e = 0.0;
-  if (t < LK) {
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < LK; t += (long long)gridDim.x * 256) {
     float re = 0.f, im = 0.f;
     for (int c = 0; c < C; ++c) {
       const float2 q = part[(long long)c * LK + t];
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) k_vis_resid(const float2* __restrict__ pa
     vp[MF_CHK(t, LK)].rre = wl * re;
     vp[t].rim = wl * im;
     if (rout) rout[t] = make_float2(re, im);
-    e = (double)wl * ((double)re * re + (double)im * im);
+    e += (double)wl * ((double)re * re + (double)im * im);
   }
   if (!partial) return;
   red[threadIdx.x] = e;
@@ -210,8 +210,8 @@ __global__ void __launch_bounds__(256) k_vis_resid(const float2* __restrict__ pa
 int launch_vis_resid(const float2* part, int C, int L, int K, const float2* vis, float vsign, const float* cw,
                      VisPt* vp, double* partial, int* nblocks, float2* rout, hipStream_t st) {
   const long long LK = (long long)L * K;
-  const long long nb = (LK + 255) / 256;
-  if (partial && nb > kMaxPartials) return set_error("visibility residual: too many blocks"), MUFFIN_EINVAL;
+  long long nb = (LK + 255) / 256;
+  if (nb > 16384) nb = 16384;
   hipLaunchKernelGGL(k_vis_resid, dim3((unsigned)nb), dim3(256), 0, st, part, C, LK, K, vis, vsign, cw, vp, partial,
                      rout);
   MF_HIP(hipGetLastError());
