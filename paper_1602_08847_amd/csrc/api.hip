@@ -1260,6 +1260,9 @@ int write_report(const std::string& rep, char* out, size_t len) {
 }
 
 constexpr uint64_t kMagic = 0x4d5546464e434b31ull;  // "MUFFNCK1"
+// The header's kind field: the spatial prior, plus 0x100 for a context with the visibility data term
+// (a state written by one kind of context is rejected by the other).
+static int32_t blob_kind(const muffin_ctx* c) { return c->p.prior | (c->vis ? 0x100 : 0); }
 struct BlobHeader {
   uint64_t magic;
   int32_t N, L, J, gen, pc, pad;
@@ -1818,7 +1821,7 @@ int muffin_get_state(muffin_ctx* c, void* blob, size_t bytes) {
   h.J = c->J;
   h.gen = c->gen;
   h.pc = c->p.penalize_coarse;
-  h.pad = c->p.prior;
+  h.pad = blob_kind(c);
   h.mu_s = c->p.mu_s;
   h.mu_l = c->segs[0].mu_l;
   h.tau = c->segs[0].tau;
@@ -1842,7 +1845,7 @@ int muffin_set_state(muffin_ctx* c, const void* blob, size_t bytes) {
   BlobHeader h;
   std::memcpy(&h, blob, sizeof(h));
   if (h.magic != kMagic || h.N != c->N || h.L != c->L || h.J != c->J || h.gen != c->gen ||
-      h.pc != c->p.penalize_coarse || h.pad != c->p.prior || h.mu_s != c->p.mu_s || h.mu_l != c->segs[0].mu_l || h.tau != c->segs[0].tau ||
+      h.pc != c->p.penalize_coarse || h.pad != blob_kind(c) || h.mu_s != c->p.mu_s || h.mu_l != c->segs[0].mu_l || h.tau != c->segs[0].tau ||
       h.sigma != c->sigma || h.rho != c->rho)
     return set_error("checkpoint sizes or parameters differ from the context"), MUFFIN_ESTATE;
   const float* f = (const float*)((const char*)blob + sizeof(h));

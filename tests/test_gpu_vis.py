@@ -170,6 +170,29 @@ def test_solve_reaches_the_oracle_objective(lib):
     assert abs(snr - om.snr_db(st.X, vi.sky)) < 1e-3
 
 
+def test_checkpoint_resume_and_kind(lib):
+    """A visibility context's state resumes bit for bit; an image-plane context's state of the same
+    sizes and parameters is rejected."""
+    N, L, K, J = 16, 3, 60, 2
+    vi, vis = inputs(N, L, K, seed=2)
+    kw = dict(N=N, J=J, mu_s=1.0, mu_lambda=1.0, tau=1e-4)
+    with lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, **kw) as a:
+        a.step(7)
+        blob = a.get_state()
+        a.step(5)
+        xa = a.get_x().cpu().numpy()
+    with lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, **kw) as b:
+        b.set_state(blob)
+        b.step(5)
+        np.testing.assert_array_equal(b.get_x().cpu().numpy(), xa)
+        c = synth.make_cube(synth.CubeSpec(N=N, L=L, J=J, n_sources=2, n_baselines=40))
+        with lib.Muffin(c.dirty, c.psf, J=J, mu_s=1.0, mu_lambda=1.0, tau=1e-4) as m:
+            other = m.get_state()
+        with pytest.raises(lib.MuffinError) as e:
+            b.set_state(other)
+        assert e.value.code == lib.ESTATE
+
+
 def test_benchmark_size_sampled(lib):
     """256^2 x 64 channels, 2000 baselines (the visibility benchmark's configuration, same launch
     path): sampled visibilities of Phi x and sampled pixels of the gradient against the oracle
