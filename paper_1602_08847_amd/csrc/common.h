@@ -195,6 +195,9 @@ int launch_triple(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
 // band height (rows per workgroup) of the band kernels, default or autotuned; set_band_rows records
 // an autotuned choice for (N, j, kernel class of mode)
 int atrous_band_rows(int N, int j, int mode);
+// The band height a launch over nch channels uses: the tuned one, else the default made small
+// enough for the launch to fill the GPU.
+int atrous_band_rows(int N, int j, int mode, int nch);
 int atrous_set_band_rows(int N, int j, int mode, int TY);
 // true if the double-smoothing kernels fit in LDS at scale j for image side N
 bool atrous_double_fits(int N, int j, int* TX, int* TY);

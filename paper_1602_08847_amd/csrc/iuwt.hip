@@ -1450,6 +1450,23 @@ int atrous_band_rows(int N, int j, int mode) {
   return is_pair(mode) ? pair_rows_default(N, j) : band_rows_default(N, j);
 }
 
+// For a launch over nch channels: without a tuned value, the default band height is halved (down
+// to 16 rows, as long as it divides N) while the launch would have fewer than kMinBandWaves waves
+// (N / 64 waves per band), so that few channels of a small image still fill the GPU; the
+// autotuner's measurements on such sizes pick heights of that order.
+constexpr long long kMinBandWaves = 2048;
+int atrous_band_rows(int N, int j, int mode, int nch) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(N, j, atrous_class(mode)));
+    if (it != g_tune.end()) return it->second;
+  }
+  int TY = atrous_band_rows(N, j, mode);
+  const long long wpb = (N + 63) / 64;
+  while (TY > 16 && N % (TY / 2) == 0 && (long long)nch * (N / TY) * wpb < kMinBandWaves) TY /= 2;
+  return TY;
+}
+
 int atrous_set_band_rows(int N, int j, int mode, int TY) {
   if (TY != 0 && (TY < 1 || TY > N || N % TY)) return set_error("band rows must divide N"), MUFFIN_EINVAL;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1482,7 +1499,7 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   const bool dbl = (mode == DB_ANALYSIS || mode == DB_ADJOINT || mode == DB_ANALYSIS_C);
   if (N > 1024) return set_error("atrous: N > 1024"), MUFFIN_EINVAL;
   a.TX = N;
-  a.TY = atrous_band_rows(N, j, mode);
+  a.TY = atrous_band_rows(N, j, mode, nch);
   a.tiles_x = 1;
   a.tiles_per_ch = N / a.TY;
   const long long nb = (long long)a.tiles_per_ch * nch;
@@ -1542,7 +1559,7 @@ int launch_pair(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRe
   a.rho = rho;
   a.coef2 = coef2;
   a.TX = N;
-  a.TY = atrous_band_rows(N, j, mode);
+  a.TY = atrous_band_rows(N, j, mode, nch);
   a.tiles_x = 1;
   a.tiles_per_ch = N / a.TY;
   const long long nb = (long long)a.tiles_per_ch * nch;
@@ -1600,7 +1617,7 @@ int launch_triple(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   a.rho = rho;
   a.coef2 = coef2;
   a.TX = N;
-  a.TY = atrous_band_rows(N, j, mode);
+  a.TY = atrous_band_rows(N, j, mode, nch);
   a.tiles_x = 1;
   a.tiles_per_ch = N / a.TY;
   const long long nb = (long long)a.tiles_per_ch * nch;
@@ -1666,7 +1683,7 @@ int launch_fused_pair(int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E,
   a.rho = rho;
   a.coef2 = coef2;
   a.TX = N;
-  a.TY = atrous_band_rows(N, j, PR_FUSED);
+  a.TY = atrous_band_rows(N, j, PR_FUSED, nch);
   a.tiles_x = 1;
   a.tiles_per_ch = N / a.TY;
   const long long nb = (long long)a.tiles_per_ch * nch;
