@@ -45,16 +45,29 @@ def build_training_set(n_cubes: int, spec: synth.CubeSpec, iters: int, sigma: fl
 
 
 def build_training_set_batched(n_cubes: int, spec: synth.CubeSpec, iters: int, sigma: float, seed0: int = 10000,
-                               group: int = 32, log=print):
+                               group: int = 32, log=print, pool=None, ahead: int = 4):
     """As build_training_set, with ``group`` cubes solved together by the batch API (one graph over
     all their channels); each cube keeps its own step size, so its iterates are those of its own
-    context.  Returns GPU tensors (inputs, targets) in seed order."""
+    context.  Returns GPU tensors (inputs, targets) in seed order.
+
+    ``pool`` (a multiprocessing pool, or None) draws the cubes of the next ``ahead`` groups on the
+    host while the GPU solves the current one; the cubes are the same either way."""
     import torch
     ins, tgs = [], []
     t0 = time.time()
+
+    def specs_of(g0):
+        return [synth.CubeSpec(**{**spec.__dict__, "seed": seed0 + i}) for i in range(g0, min(n_cubes, g0 + group))]
+
+    pending = {}
     for g0 in range(0, n_cubes, group):
-        specs = [synth.CubeSpec(**{**spec.__dict__, "seed": seed0 + i}) for i in range(g0, min(n_cubes, g0 + group))]
-        cubes = [synth.make_cube(s, dtype=np.float32, with_sky=False) for s in specs]
+        if pool is not None:
+            for g in range(g0, min(n_cubes, g0 + ahead * group), group):
+                if g not in pending:
+                    pending[g] = [pool.apply_async(synth.make_cube, (s, np.float32, False)) for s in specs_of(g)]
+            cubes = [r.get() for r in pending.pop(g0)]
+        else:
+            cubes = [synth.make_cube(s, dtype=np.float32, with_sky=False) for s in specs_of(g0)]
         with muffin.Batch([(c.dirty, c.psf) for c in cubes], J=spec.J, mu_s=MU_S, mu_lambda=MU_L, sigma=sigma) as b:
             for i in range(len(cubes)):
                 ins.append(b.warm_input(i))
@@ -303,6 +316,8 @@ def main(argv=None):
     ap.add_argument("--f-ref", type=float, default=None,
                     help="f_ref of an earlier reference run: skip the reference and cold runs, run the warm starts")
     ap.add_argument("--autotune", action="store_true", help="tune the band kernels on the test cube first")
+    ap.add_argument("--gen-workers", type=int, default=0,
+                    help="host processes that draw the training cubes while the GPU solves (batch-solved sets)")
     ap.add_argument("--budget", type=int, default=0,
                     help="instead of the 1e-4 gap: iterations of the cold run whose final objective the warm "
                          "start must reach")
@@ -330,7 +345,18 @@ def main(argv=None):
         t0 = time.time()
         n_data = max(sizes) if sizes else a.train_cubes
         if sizes:
-            inputs, targets = build_training_set_batched(n_data, spec, a.train_iters, a.sigma, log=log)
+            pool = None
+            if a.gen_workers > 0:
+                import multiprocessing as mp
+                # forked before this process first touches the GPU; the workers only run numpy
+                pool = mp.get_context("fork").Pool(a.gen_workers)
+            try:
+                inputs, targets = build_training_set_batched(n_data, spec, a.train_iters, a.sigma, log=log,
+                                                             pool=pool)
+            finally:
+                if pool is not None:
+                    pool.terminate()
+                    pool.join()
         else:
             inputs, targets = build_training_set(n_data, spec, a.train_iters, a.sigma, log=log)
         t_data = time.time() - t0
