@@ -306,8 +306,8 @@ def main():
     print(f"[bench] context ready, tau={m.info()['tau']:.3e}", file=sys.stderr, flush=True)
     tune = m.autotune(reps=3) if args.autotune else None
     if tune:
-        print(f"[bench] autotuned band rows: {[(s['j'], s['kernel'], s['rows']) for s in json.loads(tune)['scales']]}",
-              file=sys.stderr, flush=True)
+        tiles = [(s['j'], s['kernel'], s['rows'], s['class_groups']) for s in json.loads(tune)['scales']]
+        print(f"[bench] autotuned (scale, kernel, band rows, class groups): {tiles}", file=sys.stderr, flush=True)
     # the parity sample runs the timed kernels: the fused tail as the timed context has it
     fused = json.loads(tune).get("fused_tail") if tune else None
     sample_flags = args.flags if fused is None else (args.flags & ~6) | (4 if fused else 2)

@@ -333,11 +333,35 @@ int muffin_warm_input(muffin_ctx* ctx, float* out, int on_device);
 /* Release a context and every device buffer it owns (NULL is accepted); waits for its stream. */
 void muffin_free(muffin_ctx* ctx);
 
-/* Launch tuning, not part of the paper's method.  Autotuner: times every band height (rows per workgroup) of the IUWT band kernels, for each scale
- * of this context's sizes, keeps the fastest (process-wide, per image side, scale and kernel) and
- * recaptures the iteration.  Only scratch planes are written: the state is unchanged.  report (may
- * be NULL) receives a JSON description of the candidates and choices, truncated to report_len. */
+/* Launch tuning, not part of the paper's method.  Autotuner: times every band height (rows per
+ * workgroup) of the IUWT band kernels, and for the pair kernels every split of a band's residue
+ * classes mod 2^j over 1, 2, 4 or 8 workgroups ("class groups"), for each scale of this context's
+ * sizes, keeps the fastest (process-wide, per image side, scale and kernel family) and recaptures
+ * the iteration.  Only scratch planes are written: the state is unchanged.  report (may be NULL)
+ * receives a JSON description of the candidates and choices (each with its kernel family, rows
+ * and class groups), truncated to report_len.  None of these choices changes a result bit. */
 int muffin_autotune(muffin_ctx* ctx, int32_t reps, char* report, size_t report_len);
+
+/* Kernel families of the IUWT launches, as the autotuner's report names them. */
+#define MUFFIN_FAMILY_ANALYSIS 0          /* one scale, second generation: analysis + dual step */
+#define MUFFIN_FAMILY_ADJOINT 1           /* one scale, second generation: adjoint Horner step */
+#define MUFFIN_FAMILY_ANALYSIS_G1 2       /* one scale, first generation: analysis + dual step */
+#define MUFFIN_FAMILY_ADJOINT_G1 3        /* one scale, first generation: adjoint step */
+#define MUFFIN_FAMILY_PAIR_ANALYSIS 5     /* two scales: analysis + dual steps */
+#define MUFFIN_FAMILY_PAIR_ADJOINT 6      /* two adjoint Horner steps */
+#define MUFFIN_FAMILY_TRIPLE_ANALYSIS 7   /* three scales: analysis + dual steps */
+#define MUFFIN_FAMILY_TRIPLE_ADJOINT 8    /* three adjoint Horner steps */
+#define MUFFIN_FAMILY_FUSED_PAIR 9        /* last analysis pair + next iteration's first adjoint pair */
+#define MUFFIN_FAMILY_PAIR_ANALYSIS_G1 10 /* first generation: two scales of analysis */
+#define MUFFIN_FAMILY_PAIR_ADJOINT_G1 11  /* first generation: two adjoint steps */
+
+/* Launch tuning: record band rows (0: back to the default) and class groups (pair families only;
+ * 0 or 1: one workgroup per band) for the launches of image side N at scale j of one family, as
+ * the autotuner would, e.g. to restore an earlier report's choices without timing again.  rows must
+ * divide N; class_groups must be a power of two up to 2^j.  Process-wide; applies to iterations
+ * captured afterwards (a context captures its iteration on its first step after creation or after
+ * muffin_autotune).  EINVAL for a value out of range. */
+int muffin_set_band_tiles(int32_t N, int32_t j, int32_t family, int32_t rows, int32_t class_groups);
 
 /* ---------------------------------------------------------------------------------------------
  * Batches of independent cubes of uneven sizes (not part of the paper's method).  Cubes that share

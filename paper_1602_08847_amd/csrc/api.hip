@@ -11,6 +11,7 @@
 // from a captured HIP graph.
 #include "common.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -1150,7 +1151,8 @@ int replay(muffin_ctx* c, int n) {
 }
 
 // Autotuner: for every band or pair launch of the iteration, time each band height that divides N
-// on the context's own sizes (reading state, writing only scratch planes) and keep the fastest.
+// (and, for the pairs, each split of a band's residue classes over 1, 2, 4 or 8 workgroups) on the
+// context's own sizes (reading state, writing only scratch planes) and keep the fastest.
 int autotune(muffin_ctx* c, int reps, std::string& rep) {
   if (c->uob) {
     rep += "{\"N\": " + std::to_string(c->N) + ", \"channels\": " + std::to_string(c->L) +
@@ -1172,11 +1174,18 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
   for (const IuwtStep& L : sched) {
     const int mode = L.mode, j = L.j;
     double best = 1e30;
-    int best_ty = atrous_band_rows(c->N, j, mode);
+    int best_ty = atrous_band_rows(c->N, j, mode, c->L), best_cg = atrous_class_groups(c->N, j, mode, c->L);
+    const bool pairk = mode == PR_ANALYSIS || mode == PR_ANALYSIS_C || mode == PR_ADJOINT || mode == P1_ANALYSIS ||
+                       mode == P1_ANALYSIS_C || mode == P1_ADJOINT;
+    const int max_cg = pairk ? std::min(1 << j, 8) : 1;
+    std::vector<std::pair<int, int>> tiles;  // (band rows, class groups)
+    for (int TY = 16; TY <= c->N; TY *= 2)
+      if (c->N % TY == 0)
+        for (int cg = 1; cg <= max_cg; cg *= 2) tiles.push_back({TY, cg});
     std::string cand;
-    for (int TY = 16; TY <= c->N; TY *= 2) {
-      if (c->N % TY) continue;
+    for (const auto& [TY, cg] : tiles) {
       MF_TRY(atrous_set_band_rows(c->N, j, mode, TY));
+      if (pairk) MF_TRY(atrous_set_class_groups(c->N, j, mode, cg));
       auto launch = [&]() -> int {
         switch (mode) {
           case PR_FUSED:
@@ -1224,20 +1233,24 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
       MF_HIP(hipEventElapsedTime(&tm, c->e0, c->e1));
       const double ms = tm / reps;
       if (!cand.empty()) cand += ", ";
-      cand += "\"" + std::to_string(TY) + "\": " + std::to_string(ms);
+      cand += "\"" + std::to_string(TY) + (pairk ? "x" + std::to_string(cg) : std::string()) +
+              "\": " + std::to_string(ms);
       if (ms < best) {
         best = ms;
         best_ty = TY;
+        best_cg = cg;
       }
     }
     MF_TRY(atrous_set_band_rows(c->N, j, mode, best_ty));
+    if (pairk) MF_TRY(atrous_set_class_groups(c->N, j, mode, best_cg));
     if (mode == PR_FUSED) t_fused = best;
     if (mode == PR_ANALYSIS_C && j == c->jf) t_an = best;
     if (mode == PR_ADJOINT && j == c->jf) t_adj = best;
     if (!firstrep) rep += ", ";
     firstrep = false;
-    rep += "{\"j\": " + std::to_string(j) + ", \"kernel\": \"" + L.name + "\", \"rows\": " +
-           std::to_string(best_ty) + ", \"ms\": " + std::to_string(best) + ", \"candidates_ms\": {" + cand + "}}";
+    rep += "{\"j\": " + std::to_string(j) + ", \"kernel\": \"" + L.name + "\", \"family\": " +
+           std::to_string(atrous_class(mode)) + ", \"rows\": " +
+           std::to_string(best_ty) + ", \"class_groups\": " + std::to_string(pairk ? best_cg : 1) + ", \"ms\": " + std::to_string(best) + ", \"candidates_ms\": {" + cand + "}}";
   }
   rep += "]";
   if (c->fused_ok) {
@@ -1366,6 +1379,11 @@ int muffin_vis_residual(muffin_ctx* c, float* r, int on_device) {
 }
 
 void muffin_free(muffin_ctx* c) { destroy(c); }
+
+int muffin_set_band_tiles(int32_t N, int32_t j, int32_t family, int32_t rows, int32_t class_groups) {
+  if (N < 1 || N > 1024 || j < 0 || j > 10) return mf::set_error("set_band_tiles: N or j out of range"), MUFFIN_EINVAL;
+  return mf::atrous_set_tiles(N, j, family, rows, class_groups);
+}
 
 int muffin_autotune(muffin_ctx* c, int32_t reps, char* report, size_t report_len) {
   if (!c || reps < 1) return set_error("bad arguments"), MUFFIN_EINVAL;

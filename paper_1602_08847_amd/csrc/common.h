@@ -199,6 +199,13 @@ int atrous_band_rows(int N, int j, int mode);
 // enough for the launch to fill the GPU.
 int atrous_band_rows(int N, int j, int mode, int nch);
 int atrous_set_band_rows(int N, int j, int mode, int TY);
+// residue-class groups per band of the pair kernels (each group its own workgroup) for a launch
+// over nch channels: the tuned value with the tuned band rows, else the default with the default rows
+int atrous_class_groups(int N, int j, int mode, int nch);
+int atrous_set_class_groups(int N, int j, int mode, int ncg);
+// band rows (0: default) and class groups (0 or 1: none) of one kernel class at once
+int atrous_set_tiles(int N, int j, int cls, int TY, int ncg);
+int atrous_class(int mode);
 // true if the double-smoothing kernels fit in LDS at scale j for image side N
 bool atrous_double_fits(int N, int j, int* TX, int* TY);
 int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E, PlaneOut out,

@@ -15,6 +15,7 @@
 // bands, keeping neighbouring bands' edge rows in its own L2.
 #include "common.h"
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <type_traits>
@@ -44,6 +45,9 @@ struct AtrousArgs {
   int tiles_x, tiles_per_ch, nblocks;
   float coef, rho, coef2;
   double* partial;
+  // pair kernels: the residue classes of a band are split over ncg workgroups (0 or 1: one
+  // workgroup per band); tiles_per_ch counts (band, class group) tiles
+  int ncg;
 };
 
 // The rounding of the filter and of the dual update is written out (the power-of-two weights scale
@@ -335,8 +339,12 @@ __device__ __forceinline__ void pair_body(const AtrousArgs& a) {
   float* bC = sm + 2 * KR * N;
   float* bD = sm + 3 * KR * N;
   const int b = xcd_remap(blockIdx.x, a.nblocks);
-  const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
+  const int ch = b / a.tiles_per_ch, tile = b - ch * a.tiles_per_ch;
+  // tile = (band, class group): the workgroup runs classes [r_lo, r_hi) of rows [y0, y0 + TY)
+  const int ncg = a.ncg > 1 ? a.ncg : 1;
+  const int band = tile / ncg, cgi = tile - band * ncg;
   const int y0 = band * TY;
+  const int r_lo = cgi * (s / ncg), r_hi = r_lo + s / ncg;
   const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
   const char* __restrict__ Bp = ADJ ? reinterpret_cast<const char*>(a.B.p + ch * a.B.cs) : nullptr;
   const char* __restrict__ Ep = ADJ ? reinterpret_cast<const char*>(a.E.p + ch * a.E.cs) : nullptr;
@@ -407,8 +415,8 @@ __device__ __forceinline__ void pair_body(const AtrousArgs& a) {
       lt = 0;
       do {
         ++lr;
-      } while (lr < s && nsteps(lr) == 0);
-      if (lr < s) start_class(lr);
+      } while (lr < r_hi && nsteps(lr) == 0);
+      if (lr < r_hi) start_class(lr);
     }
   };
   // windows, oldest first
@@ -598,9 +606,9 @@ __device__ __forceinline__ void pair_body(const AtrousArgs& a) {
       }
     }
   };
-  int r = 0;
-  while (r < s && nsteps(r) == 0) ++r;
-  if (r < s) {
+  int r = r_lo;
+  while (r < r_hi && nsteps(r) == 0) ++r;
+  if (r < r_hi) {
     lr = r;
     start_class(lr);
     int pt = 0, pns = nsteps(r), pfirst = y0 + r - HALO * s;
@@ -615,8 +623,8 @@ __device__ __forceinline__ void pair_body(const AtrousArgs& a) {
       if (pt >= padded(pns)) {
         do {
           ++r;
-        } while (r < s && nsteps(r) == 0);
-        if (r >= s) break;
+        } while (r < r_hi && nsteps(r) == 0);
+        if (r >= r_hi) break;
         pt = 0;
         pns = nsteps(r);
         pfirst = y0 + r - HALO * s;
@@ -1454,16 +1462,30 @@ int atrous_band_rows(int N, int j, int mode) {
 // to 16 rows, as long as it divides N) while the launch would have fewer than kMinBandWaves waves
 // (N / 64 waves per band), so that few channels of a small image still fill the GPU; the
 // autotuner's measurements on such sizes pick heights of that order.
+// A pair launch first splits each band's residue classes mod 2^j over more workgroups (class groups,
+// up to 8): that adds no halo rows, where a lower band adds a halo per class.
 constexpr long long kMinBandWaves = 2048;
+constexpr int kMaxClassGroups = 8;
+static void default_tiles(int N, int j, int mode, int nch, int& TY, int& ncg) {
+  TY = atrous_band_rows(N, j, mode);
+  ncg = 1;
+  const int maxg = is_pair(mode) ? std::min(1 << j, kMaxClassGroups) : 1;
+  const long long wpb = (N + 63) / 64;
+  while ((long long)nch * (N / TY) * ncg * wpb < kMinBandWaves) {
+    if (ncg < maxg) ncg *= 2;
+    else if (TY > 16 && N % (TY / 2) == 0) TY /= 2;
+    else break;
+  }
+}
+
 int atrous_band_rows(int N, int j, int mode, int nch) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(N, j, atrous_class(mode)));
     if (it != g_tune.end()) return it->second;
   }
-  int TY = atrous_band_rows(N, j, mode);
-  const long long wpb = (N + 63) / 64;
-  while (TY > 16 && N % (TY / 2) == 0 && (long long)nch * (N / TY) * wpb < kMinBandWaves) TY /= 2;
+  int TY, ncg;
+  default_tiles(N, j, mode, nch, TY, ncg);
   return TY;
 }
 
@@ -1472,6 +1494,52 @@ int atrous_set_band_rows(int N, int j, int mode, int TY) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (TY == 0) g_tune.erase(tune_key(N, j, atrous_class(mode)));
   else g_tune[tune_key(N, j, atrous_class(mode))] = TY;
+  return MUFFIN_OK;
+}
+
+// Class groups of the pair kernels (the residue classes mod 2^j of a band split over that many
+// workgroups): with tuned band rows, the tuned groups (1 if none were recorded); else the default.
+static std::map<long long, int> g_tune_cg;
+
+// Both choices for one kernel class (the codes of atrous_class) at once, as a caller restores them.
+int atrous_set_tiles(int N, int j, int cls, int TY, int ncg) {
+  const bool pair = cls == 5 || cls == 6 || cls == 10 || cls == 11;
+  if (cls < 0 || cls > 11 || cls == 4) return set_error("band tiles: unknown kernel family"), MUFFIN_EINVAL;
+  if (TY != 0 && (TY < 1 || TY > N || N % TY)) return set_error("band rows must divide N"), MUFFIN_EINVAL;
+  if (ncg != 0 && (ncg < 1 || ncg > (1 << j) || (ncg & (ncg - 1))))
+    return set_error("class groups must be a power of two up to 2^j"), MUFFIN_EINVAL;
+  if (!pair && ncg > 1) return set_error("class groups: pair kernels only"), MUFFIN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const long long k = tune_key(N, j, cls);
+  if (TY == 0) g_tune.erase(k);
+  else g_tune[k] = TY;
+  if (ncg <= 1) g_tune_cg.erase(k);
+  else g_tune_cg[k] = ncg;
+  return MUFFIN_OK;
+}
+
+int atrous_class_groups(int N, int j, int mode, int nch) {
+  if (!is_pair(mode)) return 1;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const long long k = tune_key(N, j, atrous_class(mode));
+    if (g_tune.count(k)) {
+      auto it = g_tune_cg.find(k);
+      return it != g_tune_cg.end() ? it->second : 1;
+    }
+  }
+  int TY, ncg;
+  default_tiles(N, j, mode, nch, TY, ncg);
+  return ncg;
+}
+
+int atrous_set_class_groups(int N, int j, int mode, int ncg) {
+  if (!is_pair(mode) && ncg > 1) return set_error("class groups: pair kernels only"), MUFFIN_EINVAL;
+  if (ncg != 0 && (ncg < 1 || ncg > (1 << j) || (ncg & (ncg - 1))))
+    return set_error("class groups must be a power of two up to 2^j"), MUFFIN_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (ncg <= 1) g_tune_cg.erase(tune_key(N, j, atrous_class(mode)));
+  else g_tune_cg[tune_key(N, j, atrous_class(mode))] = ncg;
   return MUFFIN_OK;
 }
 
@@ -1496,6 +1564,7 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   a.rho = rho;
   a.coef2 = coef2;
   a.partial = partial;
+  a.ncg = 1;
   const bool dbl = (mode == DB_ANALYSIS || mode == DB_ADJOINT || mode == DB_ANALYSIS_C);
   if (N > 1024) return set_error("atrous: N > 1024"), MUFFIN_EINVAL;
   a.TX = N;
@@ -1560,8 +1629,10 @@ int launch_pair(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRe
   a.coef2 = coef2;
   a.TX = N;
   a.TY = atrous_band_rows(N, j, mode, nch);
+  a.ncg = atrous_class_groups(N, j, mode, nch);
+  if (a.ncg < 1 || a.ncg > (1 << j)) return set_error("pair: bad class groups"), MUFFIN_EINVAL;
   a.tiles_x = 1;
-  a.tiles_per_ch = N / a.TY;
+  a.tiles_per_ch = N / a.TY * a.ncg;
   const long long nb = (long long)a.tiles_per_ch * nch;
   if (nb > 0x7fffffffLL) return set_error("pair: grid too large"), MUFFIN_EINVAL;
   a.nblocks = (int)nb;

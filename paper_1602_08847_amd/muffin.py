@@ -39,7 +39,7 @@ EXPORTS = [
     "muffin_batch_step_timed", "muffin_batch_objective", "muffin_batch_get_x", "muffin_batch_info",
     "muffin_batch_autotune", "muffin_batch_free", "muffin_step_monitored", "muffin_snr", "muffin_batch_snr",
     "muffin_warm_input", "muffin_batch_set_x", "muffin_batch_warm_input", "muffin_uob_filter",
-    "muffin_debug_oob", "muffin_init_vis", "muffin_vis_residual",
+    "muffin_debug_oob", "muffin_init_vis", "muffin_vis_residual", "muffin_set_band_tiles",
 ]
 
 
@@ -77,6 +77,7 @@ _lib.muffin_batch_set_x.argtypes = [_vp, _i32, _vp, ctypes.c_int]
 _lib.muffin_batch_warm_input.argtypes = [_vp, _i32, _vp, ctypes.c_int]
 _lib.muffin_uob_filter.argtypes = [_i32, ctypes.POINTER(_dbl), _i32]
 _lib.muffin_debug_oob.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
+_lib.muffin_set_band_tiles.argtypes = [_i32, _i32, _i32, _i32, _i32]
 _lib.muffin_objective.argtypes = [_vp, ctypes.POINTER(_dbl)]
 _lib.muffin_info.argtypes = [_vp, ctypes.POINTER(_dbl)]
 for _n in ("muffin_set_x", "muffin_get_x", "muffin_get_u", "muffin_get_v"):
@@ -125,6 +126,10 @@ FLAG_UOB_ALL_BASES = 8  # union of bases: one workgroup runs all bases of a tile
 FLAG_UOB_PER_BASIS = 16  # union of bases: one workgroup per basis after the first level (same results)
 FLAG_SPECTRAL_DENSE = 32  # L without an FFT plan: cosine-table products for the spectral step
 FLAG_SPECTRAL_BLUESTEIN = 64  # L without an FFT plan: Bluestein DFTs for the spectral step
+# kernel families of the IUWT launches (the autotuner report's "family")
+FAMILY_ANALYSIS, FAMILY_ADJOINT, FAMILY_ANALYSIS_G1, FAMILY_ADJOINT_G1 = 0, 1, 2, 3
+FAMILY_PAIR_ANALYSIS, FAMILY_PAIR_ADJOINT, FAMILY_TRIPLE_ANALYSIS, FAMILY_TRIPLE_ADJOINT = 5, 6, 7, 8
+FAMILY_FUSED_PAIR, FAMILY_PAIR_ANALYSIS_G1, FAMILY_PAIR_ADJOINT_G1 = 9, 10, 11
 STOP_OBJECTIVE, STOP_CHANGE = 0, 1  # stopping rules of muffin_solve
 PRIOR_IUWT, PRIOR_UOB = 0, 1  # spatial prior: the IUWT, or the union of the first 8 Daubechies bases
 UOB_BASES = 8
@@ -590,6 +595,11 @@ def uob_filter(n: int) -> np.ndarray:
     out = (_dbl * (2 * n))()
     _check(_lib.muffin_uob_filter(n, out, 2 * n), "muffin_uob_filter")
     return np.array(out[:])
+
+
+def set_band_tiles(N: int, j: int, family: int, rows: int, class_groups: int = 1):
+    """Record band rows (0: default) and class groups of one IUWT kernel family, process-wide."""
+    _check(_lib.muffin_set_band_tiles(N, j, family, rows, class_groups), "muffin_set_band_tiles")
 
 
 def last_error() -> str:

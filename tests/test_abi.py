@@ -77,3 +77,19 @@ def test_library_daubechies_filters_match_the_oracle_and_closed_forms():
     h = (ctypes.c_double * 4)()
     assert muffin._lib.muffin_uob_filter(9, h, 4) == muffin.EINVAL
     assert muffin._lib.muffin_uob_filter(3, h, 4) == muffin.EINVAL  # buffer shorter than 6 taps
+
+
+def test_band_tiles_setter_validates_without_a_gpu():
+    """muffin_set_band_tiles only records launch choices: it is checked on the host."""
+    from paper_1602_08847_amd import muffin
+    bad = [(64, 2, muffin.FAMILY_PAIR_ANALYSIS, 24, 1),   # rows must divide N
+           (64, 2, muffin.FAMILY_PAIR_ANALYSIS, 16, 8),   # more groups than classes (2^2)
+           (64, 3, muffin.FAMILY_PAIR_ADJOINT, 16, 3),    # not a power of two
+           (64, 3, muffin.FAMILY_TRIPLE_ANALYSIS, 16, 2),  # class groups: pair families only
+           (64, 3, 4, 16, 1),                             # no such family
+           (2048, 3, muffin.FAMILY_PAIR_ANALYSIS, 16, 1)]  # N beyond the kernels' limit
+    for args in bad:
+        assert muffin._lib.muffin_set_band_tiles(*args) == -1, args
+    # accepted, then back to the defaults
+    muffin.set_band_tiles(64, 3, muffin.FAMILY_PAIR_ADJOINT, 32, 8)
+    muffin.set_band_tiles(64, 3, muffin.FAMILY_PAIR_ADJOINT, 0, 0)
