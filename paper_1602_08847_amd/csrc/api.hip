@@ -1150,9 +1150,9 @@ int replay(muffin_ctx* c, int n) {
   return MUFFIN_OK;
 }
 
-// Autotuner: for every band or pair launch of the iteration, time each band height that divides N
-// (and, for the pairs, each split of a band's residue classes over 1, 2, 4 or 8 workgroups) on the
-// context's own sizes (reading state, writing only scratch planes) and keep the fastest.
+// Autotuner: for every band, pair, triple or fused launch of the iteration, time each band height
+// that divides N with each split of a band's residue classes over 1, 2, 4 or 8 workgroups (up to
+// 2^j) on the context's own sizes (reading state, writing only scratch planes) and keep the fastest.
 int autotune(muffin_ctx* c, int reps, std::string& rep) {
   if (c->uob) {
     rep += "{\"N\": " + std::to_string(c->N) + ", \"channels\": " + std::to_string(c->L) +
@@ -1175,9 +1175,7 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
     const int mode = L.mode, j = L.j;
     double best = 1e30;
     int best_ty = atrous_band_rows(c->N, j, mode, c->L), best_cg = atrous_class_groups(c->N, j, mode, c->L);
-    const bool pairk = mode == PR_ANALYSIS || mode == PR_ANALYSIS_C || mode == PR_ADJOINT || mode == P1_ANALYSIS ||
-                       mode == P1_ANALYSIS_C || mode == P1_ADJOINT;
-    const int max_cg = pairk ? std::min(1 << j, 8) : 1;
+    const int max_cg = std::min(1 << j, 8);
     std::vector<std::pair<int, int>> tiles;  // (band rows, class groups)
     for (int TY = 16; TY <= c->N; TY *= 2)
       if (c->N % TY == 0)
@@ -1185,7 +1183,7 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
     std::string cand;
     for (const auto& [TY, cg] : tiles) {
       MF_TRY(atrous_set_band_rows(c->N, j, mode, TY));
-      if (pairk) MF_TRY(atrous_set_class_groups(c->N, j, mode, cg));
+      MF_TRY(atrous_set_class_groups(c->N, j, mode, cg));
       auto launch = [&]() -> int {
         switch (mode) {
           case PR_FUSED:
@@ -1233,8 +1231,7 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
       MF_HIP(hipEventElapsedTime(&tm, c->e0, c->e1));
       const double ms = tm / reps;
       if (!cand.empty()) cand += ", ";
-      cand += "\"" + std::to_string(TY) + (pairk ? "x" + std::to_string(cg) : std::string()) +
-              "\": " + std::to_string(ms);
+      cand += "\"" + std::to_string(TY) + "x" + std::to_string(cg) + "\": " + std::to_string(ms);
       if (ms < best) {
         best = ms;
         best_ty = TY;
@@ -1242,7 +1239,7 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
       }
     }
     MF_TRY(atrous_set_band_rows(c->N, j, mode, best_ty));
-    if (pairk) MF_TRY(atrous_set_class_groups(c->N, j, mode, best_cg));
+    MF_TRY(atrous_set_class_groups(c->N, j, mode, best_cg));
     if (mode == PR_FUSED) t_fused = best;
     if (mode == PR_ANALYSIS_C && j == c->jf) t_an = best;
     if (mode == PR_ADJOINT && j == c->jf) t_adj = best;
@@ -1250,7 +1247,7 @@ int autotune(muffin_ctx* c, int reps, std::string& rep) {
     firstrep = false;
     rep += "{\"j\": " + std::to_string(j) + ", \"kernel\": \"" + L.name + "\", \"family\": " +
            std::to_string(atrous_class(mode)) + ", \"rows\": " +
-           std::to_string(best_ty) + ", \"class_groups\": " + std::to_string(pairk ? best_cg : 1) + ", \"ms\": " + std::to_string(best) + ", \"candidates_ms\": {" + cand + "}}";
+           std::to_string(best_ty) + ", \"class_groups\": " + std::to_string(best_cg) + ", \"ms\": " + std::to_string(best) + ", \"candidates_ms\": {" + cand + "}}";
   }
   rep += "]";
   if (c->fused_ok) {

@@ -95,7 +95,10 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
   float* buf1 = sm;                            // [2][KR][N] single stage, [KR][N] double
   float* buf2 = sm + (DBL ? KR : 2 * KR) * N;  // [KR][N]
   const int b = xcd_remap(blockIdx.x, a.nblocks);
-  const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
+  const int ch = b / a.tiles_per_ch, tile = b - ch * a.tiles_per_ch;
+  // tile = (band, class group): the workgroup runs classes [r_lo, r_hi) of its band's rows
+  const int ncg = a.ncg > 1 ? a.ncg : 1;
+  const int band = tile / ncg, r_lo = (tile - band * ncg) * (s / ncg), r_hi = r_lo + s / ncg;
   const int y0 = band * TY, y1 = y0 + TY;
   const int E1 = DBL ? 2 * s : 0;
   const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
@@ -159,8 +162,8 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
       lt = 0;
       do {
         ++lr;
-      } while (lr < s && nsteps(lr) == 0);
-      if (lr < s) start_class(lr);
+      } while (lr < r_hi && nsteps(lr) == 0);
+      if (lr < r_hi) start_class(lr);
     }
   };
   double acc = 0.0;
@@ -258,9 +261,9 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
     }
     ++round;
   };
-  int r = 0;
-  while (r < s && nsteps(r) == 0) ++r;
-  if (r < s) {
+  int r = r_lo;
+  while (r < r_hi && nsteps(r) == 0) ++r;
+  if (r < r_hi) {
     lr = r;
     start_class(lr);
     int pt = 0, pns = nsteps(r), pfirst = y0 + r - E1;
@@ -276,8 +279,8 @@ __device__ __forceinline__ void band_body(const AtrousArgs& a) {
       if (pt >= padded(pns)) {
         do {
           ++r;
-        } while (r < s && nsteps(r) == 0);
-        if (r >= s) break;
+        } while (r < r_hi && nsteps(r) == 0);
+        if (r >= r_hi) break;
         pt = 0;
         pns = nsteps(r);
         pfirst = y0 + r - E1;
@@ -686,7 +689,10 @@ __device__ __forceinline__ void triple_an_body(const AtrousArgs& a) {
   extern __shared__ float sm[];
   const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
   const int b = xcd_remap(blockIdx.x, a.nblocks);
-  const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
+  const int ch = b / a.tiles_per_ch, tile = b - ch * a.tiles_per_ch;
+  // tile = (band, class group): the workgroup runs classes [r_lo, r_hi) of its band's rows
+  const int ncg = a.ncg > 1 ? a.ncg : 1;
+  const int band = tile / ncg, r_lo = (tile - band * ncg) * (s / ncg), r_hi = r_lo + s / ncg;
   const int y0 = band * TY;
   const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
   float* __restrict__ O = a.out.p + ch * a.out.cs;
@@ -751,8 +757,8 @@ __device__ __forceinline__ void triple_an_body(const AtrousArgs& a) {
       lt = 0;
       do {
         ++lr;
-      } while (lr < s && nsteps(lr) == 0);
-      if (lr < s) start_class(lr);
+      } while (lr < r_hi && nsteps(lr) == 0);
+      if (lr < r_hi) start_class(lr);
     }
   };
   // windows, oldest first: c (S1), c1 by residue mod 2 (S2), c2 and c3 by residue mod 4 (S3, S4)
@@ -831,9 +837,9 @@ __device__ __forceinline__ void triple_an_body(const AtrousArgs& a) {
     wr[x] = v5(wc);
     lds_barrier();
   };
-  int r = 0;
-  while (r < s && nsteps(r) == 0) ++r;
-  if (r < s) {
+  int r = r_lo;
+  while (r < r_hi && nsteps(r) == 0) ++r;
+  if (r < r_hi) {
     lr = r;
     start_class(lr);
     int pt = 0, pns = nsteps(r), pfirst = y0 + r - HALO * s;
@@ -841,8 +847,8 @@ __device__ __forceinline__ void triple_an_body(const AtrousArgs& a) {
       if (++pt >= pns) {
         do {
           ++r;
-        } while (r < s && nsteps(r) == 0);
-        if (r >= s) return false;
+        } while (r < r_hi && nsteps(r) == 0);
+        if (r >= r_hi) return false;
         pt = 0;
         pns = nsteps(r);
         pfirst = y0 + r - HALO * s;
@@ -897,7 +903,10 @@ __device__ __forceinline__ void triple_adj_body(const AtrousArgs& a) {
   extern __shared__ float sm[];
   const int N = a.N, jj = a.j, s = 1 << jj, x = threadIdx.x, TY = a.TY;
   const int b = xcd_remap(blockIdx.x, a.nblocks);
-  const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
+  const int ch = b / a.tiles_per_ch, tile = b - ch * a.tiles_per_ch;
+  // tile = (band, class group): the workgroup runs classes [r_lo, r_hi) of its band's rows
+  const int ncg = a.ncg > 1 ? a.ncg : 1;
+  const int band = tile / ncg, r_lo = (tile - band * ncg) * (s / ncg), r_hi = r_lo + s / ncg;
   const int y0 = band * TY;
   const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
   const char* __restrict__ Bp = reinterpret_cast<const char*>(a.B.p + ch * a.B.cs);
@@ -957,8 +966,8 @@ __device__ __forceinline__ void triple_adj_body(const AtrousArgs& a) {
       lt = 0;
       do {
         ++lr;
-      } while (lr < s && nsteps(lr) == 0);
-      if (lr < s) start_class(lr);
+      } while (lr < r_hi && nsteps(lr) == 0);
+      if (lr < r_hi) start_class(lr);
     }
   };
   // windows, oldest first: u_{j+2} and a - H_{j+2} u_{j+2} by residue mod 4, u_{j+1} and
@@ -1043,9 +1052,9 @@ __device__ __forceinline__ void triple_adj_body(const AtrousArgs& a) {
     if (to >= 2 * HALO && to < ns - SKEW) put(O, first + (to - HALO) * s, out);
     lds_barrier();
   };
-  int r = 0;
-  while (r < s && nsteps(r) == 0) ++r;
-  if (r < s) {
+  int r = r_lo;
+  while (r < r_hi && nsteps(r) == 0) ++r;
+  if (r < r_hi) {
     lr = r;
     start_class(lr);
     int pt = 0, pns = nsteps(r), pfirst = y0 + r - HALO * s;
@@ -1053,8 +1062,8 @@ __device__ __forceinline__ void triple_adj_body(const AtrousArgs& a) {
       if (++pt >= pns) {
         do {
           ++r;
-        } while (r < s && nsteps(r) == 0);
-        if (r >= s) return false;
+        } while (r < r_hi && nsteps(r) == 0);
+        if (r >= r_hi) return false;
         pt = 0;
         pns = nsteps(r);
         pfirst = y0 + r - HALO * s;
@@ -1158,7 +1167,10 @@ __device__ __forceinline__ void fused_body(const AtrousArgs& a) {
   float* ringJ = sm + 16 * RS;
   float* ringC = sm + (16 + kFusedDJ) * RS;
   const int b = xcd_remap(blockIdx.x, a.nblocks);
-  const int ch = b / a.tiles_per_ch, band = b - ch * a.tiles_per_ch;
+  const int ch = b / a.tiles_per_ch, tile = b - ch * a.tiles_per_ch;
+  // tile = (band, class group): the workgroup runs classes [r_lo, r_hi) of its band's rows
+  const int ncg = a.ncg > 1 ? a.ncg : 1;
+  const int band = tile / ncg, r_lo = (tile - band * ncg) * (s / ncg), r_hi = r_lo + s / ncg;
   const int y0 = band * TY;
   const char* __restrict__ A = reinterpret_cast<const char*>(a.A.p + ch * a.A.cs);
   const char* __restrict__ Bp = reinterpret_cast<const char*>(a.B.p + ch * a.B.cs);
@@ -1221,8 +1233,8 @@ __device__ __forceinline__ void fused_body(const AtrousArgs& a) {
       lt = 0;
       do {
         ++lr;
-      } while (lr < s && nsteps(lr) == 0);
-      if (lr < s) start_class(lr);
+      } while (lr < r_hi && nsteps(lr) == 0);
+      if (lr < r_hi) start_class(lr);
     }
   };
   // windows, oldest first (9-entry windows with taps two steps apart as two phase windows):
@@ -1323,9 +1335,9 @@ __device__ __forceinline__ void fused_body(const AtrousArgs& a) {
     rc = rc + 1 == kFusedDC ? 0 : rc + 1;
     lds_barrier();
   };
-  int r = 0;
-  while (r < s && nsteps(r) == 0) ++r;
-  if (r < s) {
+  int r = r_lo;
+  while (r < r_hi && nsteps(r) == 0) ++r;
+  if (r < r_hi) {
     lr = r;
     start_class(lr);
     int pt = 0, pns = nsteps(r), pfirst = y0 + r - HALO * s;
@@ -1333,8 +1345,8 @@ __device__ __forceinline__ void fused_body(const AtrousArgs& a) {
       if (++pt >= pns) {
         do {
           ++r;
-        } while (r < s && nsteps(r) == 0);
-        if (r >= s) return false;
+        } while (r < r_hi && nsteps(r) == 0);
+        if (r >= r_hi) return false;
         pt = 0;
         pns = nsteps(r);
         pfirst = y0 + r - HALO * s;
@@ -1462,14 +1474,15 @@ int atrous_band_rows(int N, int j, int mode) {
 // to 16 rows, as long as it divides N) while the launch would have fewer than kMinBandWaves waves
 // (N / 64 waves per band), so that few channels of a small image still fill the GPU; the
 // autotuner's measurements on such sizes pick heights of that order.
-// A pair launch first splits each band's residue classes mod 2^j over more workgroups (class groups,
-// up to 8): that adds no halo rows, where a lower band adds a halo per class.
+// A launch first splits each band's residue classes mod 2^j over more workgroups (class groups, up
+// to 8): that adds no halo rows, where a lower band adds a halo per class.  The objective's
+// reduction (one partial sum per workgroup) keeps one workgroup per band.
 constexpr long long kMinBandWaves = 2048;
 constexpr int kMaxClassGroups = 8;
 static void default_tiles(int N, int j, int mode, int nch, int& TY, int& ncg) {
   TY = atrous_band_rows(N, j, mode);
   ncg = 1;
-  const int maxg = is_pair(mode) ? std::min(1 << j, kMaxClassGroups) : 1;
+  const int maxg = mode != SM_DETAIL_ABS ? std::min(1 << j, kMaxClassGroups) : 1;
   const long long wpb = (N + 63) / 64;
   while ((long long)nch * (N / TY) * ncg * wpb < kMinBandWaves) {
     if (ncg < maxg) ncg *= 2;
@@ -1497,18 +1510,16 @@ int atrous_set_band_rows(int N, int j, int mode, int TY) {
   return MUFFIN_OK;
 }
 
-// Class groups of the pair kernels (the residue classes mod 2^j of a band split over that many
-// workgroups): with tuned band rows, the tuned groups (1 if none were recorded); else the default.
+// Class groups (the residue classes mod 2^j of a band split over that many workgroups): with tuned
+// band rows, the tuned groups (1 if none were recorded); else the default.
 static std::map<long long, int> g_tune_cg;
 
 // Both choices for one kernel class (the codes of atrous_class) at once, as a caller restores them.
 int atrous_set_tiles(int N, int j, int cls, int TY, int ncg) {
-  const bool pair = cls == 5 || cls == 6 || cls == 10 || cls == 11;
   if (cls < 0 || cls > 11 || cls == 4) return set_error("band tiles: unknown kernel family"), MUFFIN_EINVAL;
   if (TY != 0 && (TY < 1 || TY > N || N % TY)) return set_error("band rows must divide N"), MUFFIN_EINVAL;
-  if (ncg != 0 && (ncg < 1 || ncg > (1 << j) || (ncg & (ncg - 1))))
-    return set_error("class groups must be a power of two up to 2^j"), MUFFIN_EINVAL;
-  if (!pair && ncg > 1) return set_error("class groups: pair kernels only"), MUFFIN_EINVAL;
+  if (ncg != 0 && (ncg < 1 || ncg > std::min(1 << j, kMaxClassGroups) || (ncg & (ncg - 1))))
+    return set_error("class groups must be a power of two up to min(2^j, 8)"), MUFFIN_EINVAL;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   const long long k = tune_key(N, j, cls);
   if (TY == 0) g_tune.erase(k);
@@ -1519,7 +1530,7 @@ int atrous_set_tiles(int N, int j, int cls, int TY, int ncg) {
 }
 
 int atrous_class_groups(int N, int j, int mode, int nch) {
-  if (!is_pair(mode)) return 1;
+  if (mode == SM_DETAIL_ABS) return 1;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     const long long k = tune_key(N, j, atrous_class(mode));
@@ -1534,9 +1545,9 @@ int atrous_class_groups(int N, int j, int mode, int nch) {
 }
 
 int atrous_set_class_groups(int N, int j, int mode, int ncg) {
-  if (!is_pair(mode) && ncg > 1) return set_error("class groups: pair kernels only"), MUFFIN_EINVAL;
-  if (ncg != 0 && (ncg < 1 || ncg > (1 << j) || (ncg & (ncg - 1))))
-    return set_error("class groups must be a power of two up to 2^j"), MUFFIN_EINVAL;
+  if (mode == SM_DETAIL_ABS && ncg > 1) return set_error("class groups: not for the reduction"), MUFFIN_EINVAL;
+  if (ncg != 0 && (ncg < 1 || ncg > std::min(1 << j, kMaxClassGroups) || (ncg & (ncg - 1))))
+    return set_error("class groups must be a power of two up to min(2^j, 8)"), MUFFIN_EINVAL;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (ncg <= 1) g_tune_cg.erase(tune_key(N, j, atrous_class(mode)));
   else g_tune_cg[tune_key(N, j, atrous_class(mode))] = ncg;
@@ -1564,13 +1575,14 @@ int launch_atrous(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   a.rho = rho;
   a.coef2 = coef2;
   a.partial = partial;
-  a.ncg = 1;
   const bool dbl = (mode == DB_ANALYSIS || mode == DB_ADJOINT || mode == DB_ANALYSIS_C);
   if (N > 1024) return set_error("atrous: N > 1024"), MUFFIN_EINVAL;
   a.TX = N;
   a.TY = atrous_band_rows(N, j, mode, nch);
+  a.ncg = atrous_class_groups(N, j, mode, nch);
+  if (a.ncg < 1 || a.ncg > (1 << j)) return set_error("atrous: bad class groups"), MUFFIN_EINVAL;
   a.tiles_x = 1;
-  a.tiles_per_ch = N / a.TY;
+  a.tiles_per_ch = N / a.TY * a.ncg;
   const long long nb = (long long)a.tiles_per_ch * nch;
   if (nb > 0x7fffffffLL) return set_error("atrous: grid too large"), MUFFIN_EINVAL;
   if (nblocks_out) *nblocks_out = (int)nb;
@@ -1689,8 +1701,10 @@ int launch_triple(int mode, int N, int nch, int j, PlaneRef A, PlaneRef B, Plane
   a.coef2 = coef2;
   a.TX = N;
   a.TY = atrous_band_rows(N, j, mode, nch);
+  a.ncg = atrous_class_groups(N, j, mode, nch);
+  if (a.ncg < 1 || a.ncg > (1 << j)) return set_error("triple: bad class groups"), MUFFIN_EINVAL;
   a.tiles_x = 1;
-  a.tiles_per_ch = N / a.TY;
+  a.tiles_per_ch = N / a.TY * a.ncg;
   const long long nb = (long long)a.tiles_per_ch * nch;
   if (nb > 0x7fffffffLL) return set_error("triple: grid too large"), MUFFIN_EINVAL;
   a.nblocks = (int)nb;
@@ -1755,8 +1769,10 @@ int launch_fused_pair(int N, int nch, int j, PlaneRef A, PlaneRef B, PlaneRef E,
   a.coef2 = coef2;
   a.TX = N;
   a.TY = atrous_band_rows(N, j, PR_FUSED, nch);
+  a.ncg = atrous_class_groups(N, j, PR_FUSED, nch);
+  if (a.ncg < 1 || a.ncg > (1 << j)) return set_error("fused pair: bad class groups"), MUFFIN_EINVAL;
   a.tiles_x = 1;
-  a.tiles_per_ch = N / a.TY;
+  a.tiles_per_ch = N / a.TY * a.ncg;
   const long long nb = (long long)a.tiles_per_ch * nch;
   if (nb > 0x7fffffffLL) return set_error("fused pair: grid too large"), MUFFIN_EINVAL;
   a.nblocks = (int)nb;

@@ -85,11 +85,13 @@ def test_band_tiles_setter_validates_without_a_gpu():
     bad = [(64, 2, muffin.FAMILY_PAIR_ANALYSIS, 24, 1),   # rows must divide N
            (64, 2, muffin.FAMILY_PAIR_ANALYSIS, 16, 8),   # more groups than classes (2^2)
            (64, 3, muffin.FAMILY_PAIR_ADJOINT, 16, 3),    # not a power of two
-           (64, 3, muffin.FAMILY_TRIPLE_ANALYSIS, 16, 2),  # class groups: pair families only
+           (64, 4, muffin.FAMILY_TRIPLE_ANALYSIS, 16, 16),  # more than 8 groups
            (64, 3, 4, 16, 1),                             # no such family
            (2048, 3, muffin.FAMILY_PAIR_ANALYSIS, 16, 1)]  # N beyond the kernels' limit
     for args in bad:
         assert muffin._lib.muffin_set_band_tiles(*args) == -1, args
     # accepted, then back to the defaults
     muffin.set_band_tiles(64, 3, muffin.FAMILY_PAIR_ADJOINT, 32, 8)
-    muffin.set_band_tiles(64, 3, muffin.FAMILY_PAIR_ADJOINT, 0, 0)
+    muffin.set_band_tiles(64, 3, muffin.FAMILY_FUSED_PAIR, 64, 4)
+    for f in (muffin.FAMILY_PAIR_ADJOINT, muffin.FAMILY_FUSED_PAIR):
+        muffin.set_band_tiles(64, 3, f, 0, 0)

@@ -57,7 +57,8 @@ def test_autotune_keeps_results_and_reports_choices(lib, cubes):
         assert rep["N"] == 128 and len(rep["scales"]) == 2
         assert [(s["j"], s["kernel"]) for s in rep["scales"]] == [(0, "analysis triple"), (0, "adjoint triple")]
         for s in rep["scales"]:
-            assert 128 % s["rows"] == 0 and str(s["rows"]) in s["candidates_ms"]
+            assert 128 % s["rows"] == 0 and f'{s["rows"]}x{s["class_groups"]}' in s["candidates_ms"]
+            # the triples start at scale 0: one residue class, so one group
             assert s["class_groups"] == 1 and s["family"] in (lib.FAMILY_TRIPLE_ANALYSIS, lib.FAMILY_TRIPLE_ADJOINT)
         t.step(6)
         np.testing.assert_array_equal(t.get_x().cpu().numpy(), xa)
@@ -83,10 +84,9 @@ def test_autotune_chooses_the_fused_tail(lib, cubes, shape, flags):
         kernels = [s["kernel"] for s in rep["scales"]]
         assert "analysis pair + next adjoint pair" in kernels and "adjoint pair" in kernels
         for s in rep["scales"]:
-            if s["family"] in (lib.FAMILY_PAIR_ANALYSIS, lib.FAMILY_PAIR_ADJOINT):
-                # pairs: every band height with 1, 2, 4 or 8 class groups (up to 2^j)
-                g = s["class_groups"]
-                assert f'{s["rows"]}x{g}' in s["candidates_ms"] and 1 <= g <= min(8, 1 << s["j"])
+            # every band height with 1, 2, 4 or 8 class groups (up to 2^j)
+            g = s["class_groups"]
+            assert f'{s["rows"]}x{g}' in s["candidates_ms"] and 1 <= g <= min(8, 1 << s["j"])
         assert isinstance(rep["fused_tail"], bool)
         assert rep["fused_tail"] == (flags == 4 or rep["fused_ms"] < rep["separate_ms"])
         t.step(2)

@@ -73,35 +73,46 @@ def test_first_generation_pairs_match_single_scale_bitwise(lib, N, L, J, pc, rho
         np.testing.assert_array_equal(a, b)
 
 
-# Class groups: a pair launch may split a band's residue classes mod 2^j over several workgroups.
-# Each class still runs through the same steps, so the iterates agree bit for bit with one scale
-# per launch, for both generations, with whole-channel and short bands, with and without relaxation.
+# Class groups: a launch may split a band's residue classes mod 2^j over several workgroups. Each
+# class still runs through the same steps, so the iterates agree bit for bit with one workgroup per
+# band, for every kernel family (one scale, pairs, triples, the fused tail), both generations, whole-
+# channel and short bands, with and without relaxation.
+FAMILIES = {2: (0, 1, 5, 6, 7, 8, 9), 1: (2, 3, 10, 11)}
+
+
+def _set_tiles(lib, N, J, gen, rows, groups):
+    for j in range(J):
+        for f in FAMILIES[gen]:
+            lib.set_band_tiles(N, j, f, rows, min(groups, 1 << j, 8) if groups else 0)
+
+
 @pytest.mark.parametrize("N,L,J,gen,pc,rho,rows,groups", [
     (64, 6, 4, 2, True, 1.0, 16, 4), (64, 6, 4, 2, False, 0.8, 64, 2), (64, 6, 4, 1, True, 1.0, 32, 4),
     (96, 4, 5, 2, True, 0.9, 96, 8), (96, 4, 5, 1, True, 1.0, 32, 8), (128, 3, 5, 2, True, 1.0, 128, 8),
-    (16, 3, 4, 2, True, 1.0, 16, 4), (8, 2, 5, 1, True, 1.0, 8, 8)])
-def test_pair_class_groups_match_single_scale_bitwise(lib, N, L, J, gen, pc, rho, rows, groups):
+    (128, 3, 6, 2, True, 1.0, 64, 8), (64, 4, 3, 2, True, 1.0, 64, 4), (64, 4, 2, 2, True, 1.0, 32, 2),
+    (16, 3, 4, 2, True, 1.0, 16, 4), (8, 2, 5, 1, True, 1.0, 8, 8), (8, 2, 5, 2, True, 0.9, 8, 8)])
+def test_class_groups_match_one_workgroup_per_band_bitwise(lib, N, L, J, gen, pc, rho, rows, groups):
     c = synth.make_cube(synth.CubeSpec(N=N, L=L, J=J, n_sources=max(2, N // 16), n_baselines=max(8, N * 2),
                                        seed=N + J + 200))
-    fams = (lib.FAMILY_PAIR_ANALYSIS, lib.FAMILY_PAIR_ADJOINT) if gen == 2 else \
-        (lib.FAMILY_PAIR_ANALYSIS_G1, lib.FAMILY_PAIR_ADJOINT_G1)
     kw = dict(J=J, mu_s=0.25, mu_lambda=3.0, iuwt_gen=gen, penalize_coarse=pc, sigma=10.0, rho=rho)
-    with lib.Muffin(c.dirty, c.psf, flags=lib.FLAG_SINGLE_SCALE, **kw) as m:
-        m.step(7)
-        ref = (m.get_x().cpu().numpy(), m.get_u().cpu().numpy(), m.get_v().cpu().numpy())
+    flag_sets = (lib.FLAG_FUSED_TAIL, lib.FLAG_NO_FUSED_TAIL, lib.FLAG_SINGLE_SCALE) if gen == 2 else \
+        (0, lib.FLAG_SINGLE_SCALE)
+
+    def run(flags):
+        with lib.Muffin(c.dirty, c.psf, flags=flags, **kw) as m:
+            m.step(7)  # odd: the fused tail's planes end in its second buffer
+            return m.get_x().cpu().numpy(), m.get_u().cpu().numpy(), m.get_v().cpu().numpy()
+
     try:
-        for j in range(J):
-            for f in fams:
-                lib.set_band_tiles(N, j, f, rows, min(groups, 1 << j))
-        with lib.Muffin(c.dirty, c.psf, flags=lib.FLAG_NO_FUSED_TAIL, **kw) as m:
-            m.step(7)
-            got = (m.get_x().cpu().numpy(), m.get_u().cpu().numpy(), m.get_v().cpu().numpy())
+        _set_tiles(lib, N, J, gen, rows, 1)
+        ref = run(lib.FLAG_SINGLE_SCALE)
+        _set_tiles(lib, N, J, gen, rows, groups)
+        got = {f: run(f) for f in flag_sets}
     finally:
-        for j in range(J):
-            for f in fams:
-                lib.set_band_tiles(N, j, f, 0, 0)
-    for a, b in zip(got, ref):
-        np.testing.assert_array_equal(a, b)
+        _set_tiles(lib, N, J, gen, 0, 0)
+    for f in flag_sets:
+        for a, b in zip(got[f], ref):
+            np.testing.assert_array_equal(a, b)
 
 
 @pytest.mark.parametrize("flags,gen", [(0, 2), (2, 2), (4, 2), (0, 1)])
