@@ -105,8 +105,8 @@ MEASURED_TRAFFIC = {
         "sources": [
             "paper_1602_08847_amd/csrc/iuwt.hip"
         ],
-        "sha256": "08421b0403b69cee",
-        "fetch_kib": 2857079.6,
+        "sha256": "276e16f068989e35",
+        "fetch_kib": 2900091.0,
         "write_kib": 4194304.0,
         "fetch_factor": 1.9999,
         "write_factor": 1.0
@@ -116,8 +116,8 @@ MEASURED_TRAFFIC = {
         "sources": [
             "paper_1602_08847_amd/csrc/iuwt.hip"
         ],
-        "sha256": "08421b0403b69cee",
-        "fetch_kib": 2201709.3,
+        "sha256": "276e16f068989e35",
+        "fetch_kib": 2201709.1,
         "write_kib": 4194304.0,
         "fetch_factor": 1.9999,
         "write_factor": 1.0
@@ -127,8 +127,8 @@ MEASURED_TRAFFIC = {
         "sources": [
             "paper_1602_08847_amd/csrc/iuwt.hip"
         ],
-        "sha256": "08421b0403b69cee",
-        "fetch_kib": 2191346.4,
+        "sha256": "276e16f068989e35",
+        "fetch_kib": 2191451.5,
         "write_kib": 1048576.0,
         "fetch_factor": 1.9999,
         "write_factor": 1.0
@@ -140,8 +140,8 @@ MEASURED_TRAFFIC = {
             "paper_1602_08847_amd/csrc/fft_core.h"
         ],
         "sha256": "7dd811dd6ba2ef20",
-        "fetch_kib": 1573105.6,
-        "write_kib": 3145793.6,
+        "fetch_kib": 1573104.7,
+        "write_kib": 3145812.9,
         "fetch_factor": 1.9999,
         "write_factor": 1.0
     },
@@ -152,7 +152,7 @@ MEASURED_TRAFFIC = {
             "paper_1602_08847_amd/csrc/fft_core.h"
         ],
         "sha256": "7deb0bda57c04e0f",
-        "fetch_kib": 524380.0,
+        "fetch_kib": 524379.9,
         "write_kib": 1056768.3,
         "fetch_factor": 1.9999,
         "write_factor": 1.0
@@ -164,7 +164,7 @@ MEASURED_TRAFFIC = {
             "paper_1602_08847_amd/csrc/fft_core.h"
         ],
         "sha256": "7deb0bda57c04e0f",
-        "fetch_kib": 831847.7,
+        "fetch_kib": 831820.8,
         "write_kib": 1131519.9,
         "fetch_factor": 1.9999,
         "write_factor": 1.0
@@ -176,7 +176,7 @@ MEASURED_TRAFFIC = {
             "paper_1602_08847_amd/csrc/fft_core.h"
         ],
         "sha256": "7deb0bda57c04e0f",
-        "fetch_kib": 1588079.9,
+        "fetch_kib": 1588558.7,
         "write_kib": 1048576.0,
         "fetch_factor": 1.9999,
         "write_factor": 1.0
