@@ -105,7 +105,7 @@ MEASURED_TRAFFIC = {
         "sources": [
             "paper_1602_08847_amd/csrc/iuwt.hip"
         ],
-        "sha256": "276e16f068989e35",
+        "sha256": "689ff4a1d518f22a",
         "fetch_kib": 2900091.0,
         "write_kib": 4194304.0,
         "fetch_factor": 1.9999,
@@ -116,7 +116,7 @@ MEASURED_TRAFFIC = {
         "sources": [
             "paper_1602_08847_amd/csrc/iuwt.hip"
         ],
-        "sha256": "276e16f068989e35",
+        "sha256": "689ff4a1d518f22a",
         "fetch_kib": 2201709.1,
         "write_kib": 4194304.0,
         "fetch_factor": 1.9999,
@@ -127,7 +127,7 @@ MEASURED_TRAFFIC = {
         "sources": [
             "paper_1602_08847_amd/csrc/iuwt.hip"
         ],
-        "sha256": "276e16f068989e35",
+        "sha256": "689ff4a1d518f22a",
         "fetch_kib": 2191451.5,
         "write_kib": 1048576.0,
         "fetch_factor": 1.9999,

@@ -45,8 +45,8 @@ struct AtrousArgs {
   int tiles_x, tiles_per_ch, nblocks;
   float coef, rho, coef2;
   double* partial;
-  // pair kernels: the residue classes of a band are split over ncg workgroups (0 or 1: one
-  // workgroup per band); tiles_per_ch counts (band, class group) tiles
+  // the residue classes mod 2^j of a band are split over ncg workgroups (0 or 1: one workgroup
+  // per band); tiles_per_ch counts (band, class group) tiles
   int ncg;
 };
 
