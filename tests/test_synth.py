@@ -39,3 +39,17 @@ def test_paper_step_sizes_satisfy_convergence_condition_on_synthetic_cube():
                    rho=g["rho"]["value"])
     tau, sigma, rho, beta, k2 = om.step_sizes(p)
     assert tau == 1e-5 and 1 / tau - sigma * k2 > beta / 2
+
+
+def test_cubes_drawn_by_worker_processes_match_the_serial_draw():
+    """The warm-start training set may be drawn by forked host processes (--gen-workers): the cubes
+    depend only on their spec and seed, so they equal the serial draw bit for bit."""
+    import multiprocessing as mp
+    spec = synth.CubeSpec(N=32, L=4, J=2, n_sources=3, n_baselines=40)
+    specs = [synth.CubeSpec(**{**spec.__dict__, "seed": 10000 + i}) for i in range(4)]
+    with mp.get_context("fork").Pool(2) as pool:
+        got = [r.get() for r in [pool.apply_async(synth.make_cube, (s, np.float32, False)) for s in specs]]
+    for g, s in zip(got, specs):
+        ref = synth.make_cube(s, dtype=np.float32, with_sky=False)
+        np.testing.assert_array_equal(g.dirty, ref.dirty)
+        np.testing.assert_array_equal(g.psf, ref.psf)
