@@ -148,7 +148,9 @@ typedef struct {
 int muffin_init_vis(muffin_ctx** out, const muffin_params* p, const muffin_vis_desc* desc, const float* vis,
                     int vis_on_device, void* hip_stream);
 /* Residual Phi_l x_l - v_l of the current X for every channel (not weighted), [L][K] complex as
- * interleaved FP32, into host or device memory.  EINVAL for an image-plane context. */
+ * interleaved FP32, into host or device memory (device output is written in place on the
+ * context's stream; host output is staged through a device buffer of L K complex values that the
+ * context allocates on its first such call and keeps).  EINVAL for an image-plane context. */
 int muffin_vis_residual(muffin_ctx* ctx, float* r, int on_device);
 
 /* Run n_iter >= 0 iterations of Algorithm 1 (gradient, primal proximal step, spatial and spectral

@@ -112,12 +112,13 @@ struct muffin_ctx {
   // each with its baseline in wavelengths of the channel and the residual the forward pass leaves
   // (vp, [L][K]); the data (vdata, [L][K] complex); the forward pass's band sums (vpart,
   // [vC][L][K]); l = m of each column or row (vlt, FP64 [N]); n (vnt, FP64 [N][N]) and 1/n
-  // (vinvn, FP32) of each pixel; x / n of the cube (XN, dense [L][N][N]).  The image-plane
-  // buffers (Y, B, S, Hhat_T, P_T, psf_lobe) are then not allocated.
+  // (vinvn, FP32) of each pixel; x / n of the cube (XN, dense [L][N][N]); the staging buffer of
+  // muffin_vis_residual for host output (vres, [L][K] complex, allocated on its first such call).
+  // The image-plane buffers (Y, B, S, Hhat_T, P_T, psf_lobe) are then not allocated.
   bool vis = false;
   int K = 0, vC = 0;
   VisPt* vp = nullptr;
-  float2 *vdata = nullptr, *vpart = nullptr;
+  float2 *vdata = nullptr, *vpart = nullptr, *vres = nullptr;
   double *vlt = nullptr, *vnt = nullptr;
   float *vinvn = nullptr, *XN = nullptr;
 };
@@ -676,7 +677,7 @@ void destroy(muffin_ctx* c) {
   }
   void* bufs[] = {c->X, c->U, c->V, c->D, c->Q, c->B, c->Y, c->cA, c->cB, c->cT, c->S, c->Hhat_T, c->P_T,
                   c->tw, c->chan_w, c->psf_lobe, c->partial, c->dres, c->U2, c->Acar, c->tau_ch, c->Xs, c->Us, c->Vs, c->uobA, c->uobB,
-                  c->vp, c->vdata, c->vpart, c->vlt, c->vnt, c->vinvn, c->XN};
+                  c->vp, c->vdata, c->vpart, c->vlt, c->vnt, c->vinvn, c->XN, c->vres};
   for (Seg& s : c->segs) {
     void* sb[] = {s.W, s.WT, s.twL, s.csL, s.blu};
     for (void* b : sb)
@@ -1371,8 +1372,16 @@ int muffin_vis_residual(muffin_ctx* c, float* r, int on_device) {
   if (!c || !r) return set_error("bad arguments"), MUFFIN_EINVAL;
   if (!c->vis) return set_error("not a visibility context"), MUFFIN_EINVAL;
   StreamScope scope(c);
-  MF_TRY(enqueue_vis_forward(c, c->X, c->cs, c->vdata, -1.f, nullptr, nullptr, (float2*)c->cA));
-  return copy_out(r, c->cA, (size_t)(2LL * c->L * c->K), on_device, c->st);
+  // L K complex values: written straight into a device buffer, or staged for a host one (the
+  // scratch planes hold L (N^2 + N + 32) floats, too few for K above about N^2 / 2)
+  float2* dst = reinterpret_cast<float2*>(r);
+  if (!on_device) {
+    if (!c->vres) MF_TRY(dalloc(&c->vres, (size_t)c->L * c->K));
+    dst = c->vres;
+  }
+  MF_TRY(enqueue_vis_forward(c, c->X, c->cs, c->vdata, -1.f, nullptr, nullptr, dst));
+  if (on_device) return MUFFIN_OK;
+  return copy_out(r, reinterpret_cast<const float*>(c->vres), (size_t)(2LL * c->L * c->K), 0, c->st);
 }
 
 void muffin_free(muffin_ctx* c) { destroy(c); }

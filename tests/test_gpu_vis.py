@@ -92,6 +92,26 @@ def test_beta_residual_and_objective(lib):
     assert abs(obj[1] - ov.vis_data_term(x0, d)) / ov.vis_data_term(x0, d) < 1e-5
 
 
+@pytest.mark.parametrize("N,L,K", [(8, 3, 120), (16, 2, 700)])
+def test_residual_with_more_visibilities_than_pixels(lib, N, L, K):
+    """K well above N^2 / 2: the residual (L K complex values) is larger than a scratch plane of the
+    cube; it goes straight into device output, and through the context's own staging buffer into
+    host output, twice in a row."""
+    import ctypes
+    vi, vis = inputs(N, L, K, seed=11)
+    x0 = f32(vi.sky * 0.9)
+    want = ov.phi(x0, vi.uvw, vi.lam, vi.cell) - vis
+    with lib.Muffin.from_visibilities(vis, vi.uvw, vi.lam, vi.cell, N=N, J=2, mu_s=0.5, mu_lambda=1.0) as m:
+        m.set_x(x0)
+        dev = cplx(m.vis_residual())
+        for _ in range(2):
+            host = np.zeros((L, K, 2), np.float32)
+            rc = lib._lib.muffin_vis_residual(m._h, ctypes.c_void_p(host.ctypes.data), 0)
+            assert rc == 0, lib.last_error()
+            assert rel(host[..., 0] + 1j * host[..., 1], want) < 1e-5
+    assert rel(dev, want) < 1e-5
+
+
 def test_channel_weights(lib):
     """Channel weights of eq. (reg) with visibilities: the gradient, the data term, beta and five
     iterations against the oracle with the same weights."""
