@@ -136,6 +136,17 @@ static void check_validation() {
     CHECK(muffin_init_vis(&ctx, &p, &d, vis.data(), 0, nullptr) == MUFFIN_EINVAL);
     CHECK(muffin_vis_residual(nullptr, vis.data(), 0) == MUFFIN_EINVAL);
   }
+  // launch tiles: rows must divide N, class groups a power of two up to min(2^j, 8), known families
+  CHECK(muffin_set_band_tiles(64, 2, MUFFIN_FAMILY_PAIR_ANALYSIS, 24, 1) == MUFFIN_EINVAL);
+  CHECK(muffin_set_band_tiles(64, 2, MUFFIN_FAMILY_PAIR_ANALYSIS, 16, 8) == MUFFIN_EINVAL);
+  CHECK(muffin_set_band_tiles(64, 4, MUFFIN_FAMILY_TRIPLE_ADJOINT, 16, 16) == MUFFIN_EINVAL);
+  CHECK(muffin_set_band_tiles(64, 3, MUFFIN_FAMILY_FUSED_PAIR, 16, 3) == MUFFIN_EINVAL);
+  CHECK(muffin_set_band_tiles(64, 3, 4, 16, 1) == MUFFIN_EINVAL);
+  CHECK(muffin_set_band_tiles(64, 3, 12, 16, 1) == MUFFIN_EINVAL);
+  CHECK(muffin_set_band_tiles(0, 3, MUFFIN_FAMILY_ANALYSIS, 0, 0) == MUFFIN_EINVAL);
+  CHECK(muffin_set_band_tiles(64, -1, MUFFIN_FAMILY_ANALYSIS, 0, 0) == MUFFIN_EINVAL);
+  CHECK(muffin_set_band_tiles(64, 3, MUFFIN_FAMILY_FUSED_PAIR, 32, 8) == MUFFIN_OK);
+  CHECK(muffin_set_band_tiles(64, 3, MUFFIN_FAMILY_FUSED_PAIR, 0, 0) == MUFFIN_OK);
   // calls on NULL handles
   double out[8];
   CHECK(muffin_step(nullptr, 1) == MUFFIN_EINVAL);
