@@ -29,6 +29,8 @@ SHAPES = [
     (96, 7, 3, 2), (128, 17, 4, 2), (384, 3, 4, 2), (256, 64, 4, 2), (32, 33, 2, 1), (48, 48, 3, 2),
     # channel counts above 256 without an FFT plan, and a radix-3 plan
     (8, 260, 2, 2), (8, 384, 2, 2),
+    # the largest image sides: 512, the radix-3 768 and 1024 (at J = 6: scale triples 0-2 and 3-5)
+    (512, 2, 5, 2), (768, 2, 4, 1), (1024, 2, 6, 2),
 ]
 
 

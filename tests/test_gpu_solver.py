@@ -92,8 +92,8 @@ SPECTRAL_PATHS = [
     (16, 100, 32), (16, 200, 32), (16, 260, 32),
     # by default: dense products (L = 11, 100), Bluestein (L = 120, 260), an FFT with a radix-3 plan
     (16, 11, 0), (16, 100, 0), (16, 120, 0), (16, 260, 0), (16, 384, 0),
-    # radix-3 plans with 16 and 8 transforms per block
-    (16, 48, 0), (16, 96, 0), (16, 192, 0),
+    # radix-3 plans with 16 and 8 transforms per block; the largest power-of-two plan
+    (16, 48, 0), (16, 96, 0), (16, 192, 0), (8, 512, 0),
 ]
 
 
