@@ -336,12 +336,13 @@ int muffin_warm_input(muffin_ctx* ctx, float* out, int on_device);
 void muffin_free(muffin_ctx* ctx);
 
 /* Launch tuning, not part of the paper's method.  Autotuner: times every band height (rows per
- * workgroup) of the IUWT band kernels, and for the pair kernels every split of a band's residue
- * classes mod 2^j over 1, 2, 4 or 8 workgroups ("class groups"), for each scale of this context's
- * sizes, keeps the fastest (process-wide, per image side, scale and kernel family) and recaptures
- * the iteration.  Only scratch planes are written: the state is unchanged.  report (may be NULL)
- * receives a JSON description of the candidates and choices (each with its kernel family, rows
- * and class groups), truncated to report_len.  None of these choices changes a result bit. */
+ * workgroup) of the IUWT band kernels with every split of a band's residue classes mod 2^j over
+ * 1, 2, 4 or 8 workgroups ("class groups", up to 2^j), for each scale of this context's sizes,
+ * keeps the fastest (process-wide, per image side, scale and kernel family) and recaptures the
+ * iteration.  Only scratch planes are written: the state is unchanged.  report (may be NULL)
+ * receives a JSON description of the candidates ("rows x groups") and choices (each with its
+ * kernel family, rows and class groups), truncated to report_len.  None of these choices changes
+ * a result bit. */
 int muffin_autotune(muffin_ctx* ctx, int32_t reps, char* report, size_t report_len);
 
 /* Kernel families of the IUWT launches, as the autotuner's report names them. */
@@ -357,10 +358,10 @@ int muffin_autotune(muffin_ctx* ctx, int32_t reps, char* report, size_t report_l
 #define MUFFIN_FAMILY_PAIR_ANALYSIS_G1 10 /* first generation: two scales of analysis */
 #define MUFFIN_FAMILY_PAIR_ADJOINT_G1 11  /* first generation: two adjoint steps */
 
-/* Launch tuning: record band rows (0: back to the default) and class groups (pair families only;
- * 0 or 1: one workgroup per band) for the launches of image side N at scale j of one family, as
- * the autotuner would, e.g. to restore an earlier report's choices without timing again.  rows must
- * divide N; class_groups must be a power of two up to 2^j.  Process-wide; applies to iterations
+/* Launch tuning: record band rows (0: back to the default) and class groups (0 or 1: one
+ * workgroup per band) for the launches of image side N at scale j of one family, as the autotuner
+ * would, e.g. to restore an earlier report's choices without timing again.  rows must divide N;
+ * class_groups must be a power of two up to min(2^j, 8).  Process-wide; applies to iterations
  * captured afterwards (a context captures its iteration on its first step after creation or after
  * muffin_autotune).  EINVAL for a value out of range. */
 int muffin_set_band_tiles(int32_t N, int32_t j, int32_t family, int32_t rows, int32_t class_groups);
