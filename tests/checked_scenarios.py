@@ -2,10 +2,11 @@
 
 Run as a child process by tests/test_gpu_checked.py with MUFFIN_LIBRARY set to
 paper_1602_08847_amd/libmuffin_checked.so.  It drives every instrumented kernel family (the IUWT
-band, pair, triple and fused-tail kernels of both generations, the FFT passes, the spectral step in
-its planned, Bluestein and cosine-table forms, the union-of-bases kernels in both workgroup
-layouts, the visibility data term's kernels, an uneven batch) over ragged and wrapping shapes, then prints one JSON line with the
-number of out-of-bounds indices the device caught.
+band, pair, triple and fused-tail kernels of both generations, also with class groups forced, the
+FFT passes, the spectral step in its planned, Bluestein and cosine-table forms, the union-of-bases
+kernels in both workgroup layouts, the visibility data term's kernels, an uneven batch) over ragged
+and wrapping shapes, then prints one JSON line with the number of out-of-bounds indices the device
+caught.
 """
 import json
 import os
@@ -51,6 +52,19 @@ def main():
                                 (256, 64, 4, 1, 0), (64, 5, 5, 2, 1), (384, 3, 4, 2, 0), (48, 48, 3, 2, 0)]:
         run(N, L, J, iuwt_gen=gen, flags=flags)
         cases.append(f"iuwt N={N} L={L} J={J} gen={gen} flags={flags}")
+    # class groups forced on every IUWT family, with bands no taller than the coarsest residue step
+    fams = {2: (0, 1, 5, 6, 7, 8, 9), 1: (2, 3, 10, 11)}
+    for N, L, J, gen, flags in [(64, 4, 5, 2, 4), (64, 4, 5, 2, 2), (64, 4, 5, 2, 1), (64, 4, 5, 1, 0)]:
+        try:
+            for j in range(J):
+                for f in fams[gen]:
+                    muffin.set_band_tiles(N, j, f, 16, min(8, 1 << j))
+            run(N, L, J, iuwt_gen=gen, flags=flags)
+        finally:
+            for j in range(J):
+                for f in fams[gen]:
+                    muffin.set_band_tiles(N, j, f, 0, 0)
+        cases.append(f"iuwt class groups N={N} L={L} J={J} gen={gen} flags={flags}")
     # the spectral step: Bluestein (64), cosine tables (32), default choice; planned radix-3 sizes
     for L, flags in [(17, 64), (37, 64), (70, 64), (100, 64), (150, 64), (300, 64), (100, 32), (260, 32),
                      (120, 0), (96, 0), (192, 0)]:
@@ -62,7 +76,7 @@ def main():
         run(N, L, J, prior=muffin.PRIOR_UOB, flags=flags)
         cases.append(f"uob N={N} L={L} J={J} flags={flags}")
     # the visibility data term: ragged visibility counts, one visibility, image sides 3 * 2^a
-    for N, L, K in [(16, 3, 50), (24, 2, 65), (64, 2, 1), (48, 3, 130)]:
+    for N, L, K in [(16, 3, 50), (24, 2, 65), (64, 2, 1), (48, 3, 130), (8, 2, 200)]:
         rng = np.random.default_rng(N + K)
         uvw = np.column_stack([rng.uniform(-2 * N, 2 * N, K), rng.uniform(-2 * N, 2 * N, K), rng.uniform(-N, N, K)])
         lam = np.linspace(1.0, 0.7, L)
